@@ -1,0 +1,275 @@
+"""Python access to the FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+Only tests/, __graft_entry__.smoke() and the CPU-baseline leg of bench.py may
+import this package.  The product path (paper_1006_0720_amd) never touches it.
+
+The arithmetic lives in pdf_oracle.c; this module only marshals numpy arrays.
+The neural-network part of the oracle is in oracle/mlp.py (NumPy, FP64).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "liboracle.so")
+NSTAT = 25
+CNT_NAMES = ["walk_steps", "fallback", "brute", "lost", "reflect", "periodic", "noslip_b",
+             "omega_clamp", "gamma_fail", "empty_node"]
+
+
+def build(force=False):
+    """Compile the oracle with plain IEEE binary64 arithmetic (no contraction)."""
+    src = os.path.join(_HERE, "pdf_oracle.c")
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(src):
+        return _LIB
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared",
+           "-o", _LIB + ".tmp", src, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int32)
+        up = C.POINTER(C.c_uint32)
+        u64p = C.POINTER(C.c_uint64)
+        L.or_philox4x32_10.argtypes = [up, up, up]
+        L.or_uniform.argtypes = [C.c_uint32]
+        L.or_uniform.restype = C.c_double
+        L.or_box_muller.argtypes = [C.c_double, C.c_double, dp, dp]
+        L.or_gamma.argtypes = [C.c_double, C.c_double, C.c_uint64, C.c_uint32, C.c_uint32,
+                               C.c_uint32, ip]
+        L.or_gamma.restype = C.c_double
+        L.or_mesh_new.argtypes = [C.c_int32, C.c_int32, C.c_int32, dp, ip, ip, ip, ip, ip, ip, dp, ip]
+        L.or_mesh_new.restype = C.c_void_p
+        L.or_mesh_free.argtypes = [C.c_void_p]
+        L.or_locate_brute.argtypes = [C.c_void_p, C.c_double, C.c_double]
+        L.or_locate_brute.restype = C.c_int32
+        L.or_lambdas.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_double, dp]
+        L.or_seed.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, dp, ip, up]
+        L.or_estimate.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, dp, ip, dp, dp, dp, u64p]
+        L.or_local_wp.argtypes = [C.c_void_p, C.c_void_p, dp, dp]
+        L.or_derivatives.argtypes = [C.c_void_p, dp]
+        L.or_step.argtypes = [C.c_void_p, C.c_void_p, dp, dp, dp, C.c_int64, dp, ip, up,
+                              C.c_uint64, C.c_uint32, C.c_double, C.POINTER(C.c_uint8), u64p]
+        L.or_step.restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+class _Params(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("model", "wp_source", "omega_source", "tm_mode", "frozen",
+                                         "wall_b", "store_fp32", "pad")] + \
+               [(n, C.c_double) for n in ("C0", "C1", "C2", "C3", "C4", "CT", "CL", "Ceta", "Cv",
+                                          "gamma5", "Cw1", "Cw2", "Cphi", "nu", "k_floor",
+                                          "src_x", "src_y", "src_r")]
+
+
+class _Seed(C.Structure):
+    _fields_ = [("ppe", C.c_int32), ("psi_mode", C.c_int32), ("seed", C.c_uint64),
+                ("a", C.c_double), ("b", C.c_double), ("c", C.c_double),
+                ("U0", C.POINTER(C.c_double)), ("R0", C.POINTER(C.c_double)),
+                ("Om0", C.POINTER(C.c_double))]
+
+
+def _p(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def _params(params: dict, store_fp32: bool):
+    p = _Params()
+    for name, _ in _Params._fields_:
+        if name == "store_fp32":
+            p.store_fp32 = int(store_fp32)
+        elif name == "pad":
+            p.pad = 0
+        else:
+            setattr(p, name, params[name])
+    return p
+
+
+# ----------------------------------------------------------------------------
+# random numbers
+# ----------------------------------------------------------------------------
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().or_philox4x32_10(_p(c, C.c_uint32), _p(k, C.c_uint32), _p(out, C.c_uint32))
+    return out
+
+
+def uniform(r):
+    return lib().or_uniform(int(r))
+
+
+def box_muller(u1, u2):
+    a, b = C.c_double(), C.c_double()
+    lib().or_box_muller(u1, u2, C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def gamma(shape, scale, seed, pid, step, subbase):
+    fail = C.c_int32(0)
+    v = lib().or_gamma(shape, scale, seed, pid, step, subbase, C.byref(fail))
+    return v, bool(fail.value)
+
+
+# ----------------------------------------------------------------------------
+# mesh, seeding, estimator, step
+# ----------------------------------------------------------------------------
+
+class OracleMesh:
+    def __init__(self, mesh):
+        self.mesh = mesh
+        self._arr = dict(
+            xy=np.ascontiguousarray(mesh.node_xy, np.float64),
+            en=np.ascontiguousarray(mesh.elem_nodes, np.int32),
+            nbr=np.ascontiguousarray(mesh.elem_nbr, np.int32),
+            be=np.ascontiguousarray(mesh.bedge_elem, np.int32),
+            bl=np.ascontiguousarray(mesh.bedge_local, np.int32),
+            bt=np.ascontiguousarray(mesh.bedge_type, np.int32),
+            bp=np.ascontiguousarray(mesh.bedge_partner, np.int32),
+            bs=np.ascontiguousarray(mesh.bedge_shift, np.float64),
+            master=np.ascontiguousarray(mesh.node_master, np.int32))
+        a = self._arr
+        dp, ip = C.c_double, C.c_int32
+        self.h = lib().or_mesh_new(mesh.n_nodes, mesh.n_elems, mesh.n_bedges, _p(a["xy"], dp),
+                                   _p(a["en"], ip), _p(a["nbr"], ip), _p(a["be"], ip),
+                                   _p(a["bl"], ip), _p(a["bt"], ip), _p(a["bp"], ip),
+                                   _p(a["bs"], dp), _p(a["master"], ip))
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().or_mesh_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def locate_brute(self, x, y):
+        return lib().or_locate_brute(self.h, float(x), float(y))
+
+    def derivatives(self, stats):
+        """Recompute nodal fields 15-23 (gradients, Laplacians) from fields 0-2."""
+        st = np.ascontiguousarray(stats, np.float64).copy()
+        lib().or_derivatives(self.h, _p(st, C.c_double))
+        return st
+
+    def lambdas(self, e, x, y):
+        out = np.zeros(3)
+        lib().or_lambdas(self.h, int(e), float(x), float(y), _p(out, C.c_double))
+        return out
+
+
+class Oracle:
+    """State holder around the C oracle.  Particle state is kept in id order as
+    a (7, Np) float64 array (x, y, u, v, w, omega, psi) plus host elements."""
+
+    def __init__(self, mesh, params: dict, store_fp32=False, gradp=None, wp=None):
+        self.om = OracleMesh(mesh)
+        self.mesh = mesh
+        self.params = dict(params)
+        self.store_fp32 = bool(store_fp32)
+        self.cp = _params(self.params, self.store_fp32)
+        nn = mesh.n_nodes
+        self.gradp = None if gradp is None else np.ascontiguousarray(gradp, np.float64).reshape(2, nn)
+        self.wp_input = None if wp is None else np.ascontiguousarray(wp, np.float64).reshape(9, nn)
+        self.stats = np.zeros((NSTAT, nn))
+        self.elem_stats = None
+        self.counters = np.zeros(len(CNT_NAMES), np.uint64)
+        self.step_index = 0
+
+    # -- seeding (initial conditions) --------------------------------------
+    def seed(self, spec: dict):
+        m = self.mesh
+        ppe = int(spec["ppe"])
+        np_ = m.n_elems * ppe
+        self.U0 = np.ascontiguousarray(spec["U0"], np.float64).reshape(3, m.n_nodes)
+        self.R0 = np.ascontiguousarray(spec["R0"], np.float64).reshape(6, m.n_nodes)
+        self.Om0 = np.ascontiguousarray(spec["Om0"], np.float64).reshape(m.n_nodes)
+        s = _Seed(ppe=ppe, psi_mode=int(spec.get("psi_mode", 0)), seed=int(spec["seed"]),
+                  a=float(spec.get("a", 0.0)), b=float(spec.get("b", 0.0)),
+                  c=float(spec.get("c", 0.0)), U0=_p(self.U0, C.c_double),
+                  R0=_p(self.R0, C.c_double), Om0=_p(self.Om0, C.c_double))
+        self.state = np.zeros((7, np_))
+        self.elem = np.zeros(np_, np.int32)
+        self.id = np.zeros(np_, np.uint32)
+        self.seed_value = int(spec["seed"])
+        lib().or_seed(self.om.h, C.byref(self.cp), C.byref(s), _p(self.state, C.c_double),
+                      _p(self.elem, C.c_int32), _p(self.id, C.c_uint32))
+        self.step_index = 0
+        self.stats = np.zeros((NSTAT, m.n_nodes))
+        self.estimate()
+        return self
+
+    def estimate(self, into_stats=True):
+        m = self.mesh
+        out = np.zeros((NSTAT, m.n_nodes))
+        el = np.zeros((16, m.n_elems))
+        prev = np.ascontiguousarray(self.stats)
+        lib().or_estimate(self.om.h, C.byref(self.cp), self.state.shape[1],
+                          _p(self.state, C.c_double), _p(self.elem, C.c_int32),
+                          _p(prev, C.c_double), _p(out, C.c_double), _p(el, C.c_double),
+                          _p(self.counters, C.c_uint64))
+        self.elem_stats = el
+        self.est = out
+        if into_stats:
+            self.stats = out
+        return out
+
+    def local_wp(self, stats=None):
+        m = self.mesh
+        st = np.ascontiguousarray(self.stats if stats is None else stats, np.float64)
+        wp = np.zeros((9, m.n_nodes))
+        lib().or_local_wp(self.om.h, C.byref(self.cp), _p(st, C.c_double), _p(wp, C.c_double))
+        return wp
+
+    def set_stats(self, stats):
+        self.stats = np.ascontiguousarray(stats, np.float64).reshape(NSTAT, self.mesh.n_nodes).copy()
+
+    def step(self, dt, mask=None):
+        """One step: element records from the current nodal statistics, advance,
+        then re-estimate (fed back unless params['frozen'])."""
+        m = self.mesh
+        st = np.ascontiguousarray(self.stats)
+        if self.params["model"] == 1:
+            wp = self.local_wp(st) if self.params["wp_source"] == 1 else self.wp_input
+            wp = np.ascontiguousarray(wp)
+            wpp = _p(wp, C.c_double)
+        else:
+            wpp = None
+        gp = None if self.gradp is None else _p(self.gradp, C.c_double)
+        mk = None if mask is None else _p(np.ascontiguousarray(mask, np.uint8), C.c_uint8)
+        if mask is not None:
+            self._mask_keep = np.ascontiguousarray(mask, np.uint8)
+            mk = _p(self._mask_keep, C.c_uint8)
+        lost = lib().or_step(self.om.h, C.byref(self.cp), _p(st, C.c_double), wpp, gp,
+                             self.state.shape[1], _p(self.state, C.c_double),
+                             _p(self.elem, C.c_int32), _p(self.id, C.c_uint32),
+                             self.seed_value, self.step_index, float(dt), mk,
+                             _p(self.counters, C.c_uint64))
+        self.step_index += 1
+        self.estimate(into_stats=not self.params["frozen"])
+        return lost
+
+    def run(self, dt, nsteps):
+        for _ in range(nsteps):
+            self.step(dt)
+        return self
+
+    def counter_dict(self):
+        return {n: int(v) for n, v in zip(CNT_NAMES, self.counters)}
