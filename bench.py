@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the particle hot path on one MI355X.
+
+One step = one pass of the whole hot path over the synthetic workload:
+element records, the fused particle kernel (noise, SDEs, tracking and
+boundary conditions, element sums) and the two-pass nodal estimator with its
+derivatives (plus the periodic reorder).  Inputs are resident in HBM before the
+timed region; the timed region is exactly K calls' worth of steps bracketed by
+device synchronisation.
+
+Prints one JSON line (see the design doc for the roofline accounting).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s + %HBM peak; learned-vs-plain cost at equal stat error"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (constructor, description)
+    "channel_block": ("channel_block", "graded channel with a floor block, ~1M triangles, "
+                      "100 particles/element (~100M), FP32, GLM + gamma frequency + IEM"),
+    "canyon": ("canyon", "street-canyon box with two blocks, ~200k triangles, 50 particles/element "
+               "(~10M), FP32, GLM + gamma frequency + IEM, disc source"),
+    "channel": ("channel", "plane channel, 20k triangles, 100 particles/element (2M), FP32, GLM"),
+    "periodic_square": ("periodic_square", "periodic unit square, 2048 triangles, 50 particles/"
+                        "element (102400), FP64, simplified Langevin"),
+}
+
+
+def kernel_bytes(w, tsize):
+    """Algorithmic HBM bytes of one launch of the fused particle kernel:
+    per particle the state is read (7 values + element + id) and written
+    (7 values + element); per element its record is read once and its 16
+    FP64 sums are read and written once."""
+    n_p, n_e = w.n_particles, w.mesh.n_elems
+    per_particle = (7 * tsize + 4 + 4) + (7 * tsize + 4)
+    per_element = 32 * tsize + 2 * 16 * 8
+    return n_p * per_particle + n_e * per_element, per_particle, per_element
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("k_particles.hip", "rng.h", "pdf_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1006_0720_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload, bytes_alg):
+    """HBM traffic of the particle kernel from committed rocprofv3 counter
+    summaries, or None when none exists or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", f"k_advance_{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(wname, w):
+    """The FP64 oracle (single thread) on a bounded sample of the workload:
+    the full mesh at a reduced particle count, a few steps."""
+    import numpy as np
+
+    import oracle as O
+
+    target = 10_000_000
+    ppe = max(10, min(int(w.seed["ppe"]), target // w.mesh.n_elems))
+    steps = 2 if w.mesh.n_elems * ppe > 4_000_000 else 5
+    seed = dict(w.seed, ppe=ppe)
+    o = O.Oracle(w.mesh, w.params, store_fp32=(w.precision == "f32"), gradp=w.gradp, wp=w.wp)
+    o.seed(seed)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        o.step(w.dt)
+    dt = time.perf_counter() - t0
+    n = w.mesh.n_elems * ppe
+    return {"value": n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"same mesh ({w.mesh.n_elems} elements) at {ppe} particles/element "
+                      f"({n} particles), {steps} steps, FP64 oracle, 1 thread, includes the "
+                      f"statistics estimate of each step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="channel_block", choices=sorted(WORKLOADS))
+    ap.add_argument("--reorder-every", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the particle hot path is built and measured on a "
+              "single MI355X; multi-GPU sharding (spatial domain decomposition) is described in "
+              "DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1006_0720_amd.runner import workload_context
+    from synth import configs as CF
+
+    ctor, desc = WORKLOADS[args.workload]
+    w = getattr(CF, ctor)()
+    tsize = 4 if w.precision == "f32" else 8
+    ctx = workload_context(w, device=0, reorder_every=args.reorder_every)
+    stream = torch.cuda.current_stream()
+
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    ctx.advance(args.warmup, w.dt)
+    torch.cuda.synchronize()
+    ctx.counters(reset=True)
+    ctx.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.advance(args.steps, w.dt)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    tm = ctx.timing()
+    cnt = ctx.counters()
+    n_p = w.n_particles
+    value = n_p * args.steps / wall
+
+    bytes_alg, per_p, per_e = kernel_bytes(w, tsize)
+    adv_ms = tm["advance"] / args.steps
+    achieved = bytes_alg / (adv_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(args.workload, bytes_alg)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_advance", "kernel_ms": round(adv_ms, 4),
+            "bytes_per_launch": bytes_alg, "bytes_per_particle": per_p,
+            "bytes_per_element": per_e}
+    step_ms = wall * 1e3 / args.steps
+    out = {
+        "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if w.precision == "f32" else "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "n_particles": n_p,
+                   "n_elements": w.mesh.n_elems, "n_nodes": w.mesh.n_nodes,
+                   "particles_per_element": int(w.seed["ppe"]), "dt": w.dt,
+                   "reorder_every": args.reorder_every},
+        "roofline": roof,
+        "phase_ms_per_step": {k: round(v / args.steps, 4) for k, v in tm.items()},
+        "counters": {k: cnt[k] for k in ("lost", "brute", "fallback", "nonfinite", "empty_node")},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload, w)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * pdf.h -- C ABI of the MI355X (gfx950) particle hot path of the stand-alone
+ * PDF method for turbulent velocity, frequency and passive-scalar transport on
+ * unstructured triangle grids (J. Bakosi, "PDF modeling of turbulent flows on
+ * unstructured grids", 2008).
+ *
+ * The problem, as the dissertation states it (Ch.3, Introduction):
+ *   given an unstructured triangle grid, model constants, the nodal Eulerian
+ *   inputs of the particle equations and an initial particle population,
+ *   advance the particle SDEs by explicit Euler-Maruyama steps while tracking
+ *   every particle through the grid, and estimate Eulerian statistics at the
+ *   grid nodes from the particles.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns pdf_status; PDF_OK == 0.  No C++ exception and no
+ *     abort crosses this interface.  pdf_last_error() returns the context's
+ *     last message.
+ *   - Host arrays passed in are borrowed for the duration of the call and
+ *     copied; the library never keeps a caller pointer.
+ *   - All device work is enqueued on the hipStream_t given to pdf_init_mesh().
+ *     Calls that return data into host memory synchronize that stream; all
+ *     others are asynchronous.  A context belongs to one host thread.
+ *   - Arrays are field-major ("structure of arrays"): field f of item i is at
+ *     [f * n_items + i].
+ *   - Particle identifiers are id = e * ppe + j for the j-th particle seeded in
+ *     element e (caller numbering); the counter-based random numbers are a pure
+ *     function of (seed, id, step), so results do not depend on launch shape or
+ *     particle storage order.
+ */
+#ifndef PDF_H
+#define PDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pdf_ctx pdf_ctx;
+
+typedef enum pdf_status {
+  PDF_OK = 0,
+  PDF_E_INVALID_ARG = 1,   /* a pointer, size or enum is out of range */
+  PDF_E_BAD_MESH = 2,      /* the mesh fails a consistency check (orientation, neighbours, periodic pairs) */
+  PDF_E_OOM = 3,           /* a device allocation failed */
+  PDF_E_DEVICE = 4,        /* a HIP call failed (message in pdf_last_error) */
+  PDF_E_STATE = 5,         /* wrong call order (e.g. advance before seeding) */
+  PDF_E_LOST_PARTICLE = 6, /* a particle was found by neither the walk, the fall-back nor brute force */
+  PDF_E_NUMERIC = 7        /* non-finite particle state detected */
+} pdf_status;
+
+enum { PDF_FP64 = 0, PDF_FP32 = 1 };                          /* particle-state precision */
+enum { PDF_BC_PERIODIC = 1, PDF_BC_SLIP = 2, PDF_BC_NOSLIP = 3 }; /* boundary-edge types */
+enum { PDF_MODEL_SLM = 0, PDF_MODEL_GLM = 1 };                /* eq:wall-GandC / eq:GandC */
+enum { PDF_WP_INPUT = 0, PDF_WP_LOCAL = 1 };                  /* source of the tensor wp_ij (GLM) */
+enum { PDF_TM_CPHI = 0, PDF_TM_KEPS = 1 };                    /* micromixing time scale */
+enum { PDF_PSI_ZERO = 0, PDF_PSI_STEP_X = 1, PDF_PSI_GAUSS_X = 2, PDF_PSI_BERNOULLI = 3,
+       PDF_PSI_DISC = 4 };                                    /* scalar initial conditions */
+enum { PDF_FIELD_STATS = 0, PDF_FIELD_WP = 1, PDF_FIELD_GRADP = 2 }; /* pdf_set_nodal_field ids */
+
+#define PDF_NSTAT 25     /* nodal statistics per node, see pdf_estimate_stats */
+#define PDF_NELEMSTAT 16 /* element statistics per element */
+#define PDF_NCOUNTERS 16
+
+/* counter indices (pdf_get_counters) */
+enum {
+  PDF_CNT_WALK_STEPS = 0, PDF_CNT_FALLBACK = 1, PDF_CNT_BRUTE = 2, PDF_CNT_LOST = 3,
+  PDF_CNT_REFLECT = 4, PDF_CNT_PERIODIC = 5, PDF_CNT_NOSLIP_B = 6, PDF_CNT_OMEGA_CLAMP = 7,
+  PDF_CNT_GAMMA_FAIL = 8, PDF_CNT_EMPTY_NODE = 9, PDF_CNT_NONFINITE = 10, PDF_CNT_STEPS = 11
+};
+
+/* Device allocator hook.  alloc returns device memory of at least `bytes`
+ * bytes (256-byte aligned) or NULL; free releases it.  Passing NULL to
+ * pdf_init_mesh selects hipMalloc/hipFree. */
+typedef struct pdf_allocator {
+  void *(*alloc)(size_t bytes, void *user);
+  void (*free)(void *ptr, void *user);
+  void *user;
+} pdf_allocator;
+
+/* Unstructured triangle grid (Ch.3, Sec. Particle tracking and Sec. Estimation
+ * of Eulerian statistics: elements, the elements surrounding each element with
+ * tagged boundary neighbours, and the grid nodes).  Host pointers.
+ *   node_xy       2*n_nodes doubles, interleaved (x0,y0,x1,y1,...)
+ *   elem_nodes    3*n_elems node indices per element, counter-clockwise
+ *   elem_nbr      3*n_elems: element across the edge opposite local node k, or
+ *                 -(b+1) for boundary edge b
+ *   bedge_elem/local  element and local edge index of boundary edge b
+ *   bedge_type    PDF_BC_* per boundary edge
+ *   bedge_partner periodic partner edge, or -1
+ *   bedge_shift   2*n_bedges: translation added to a particle crossing edge b
+ *                 (periodic edges only)
+ *   node_master   periodic identification: statistics of node n are those of
+ *                 node node_master[n] (n itself when not periodic)
+ * Errors: PDF_E_BAD_MESH if an element has non-positive area, elem_nbr is not
+ * symmetric, a periodic partner is not mutual or a master is not its own master. */
+typedef struct pdf_mesh_desc {
+  int32_t n_nodes, n_elems, n_bedges, pad;
+  const double *node_xy;
+  const int32_t *elem_nodes;
+  const int32_t *elem_nbr;
+  const int32_t *bedge_elem;
+  const int32_t *bedge_local;
+  const int32_t *bedge_type;
+  const int32_t *bedge_partner;
+  const double *bedge_shift;
+  const int32_t *node_master;
+} pdf_mesh_desc;
+
+/* Model constants and switches.  Constants as in the paper's tables
+ * (Ch.4 tab:fd-constants, Ch.5 tab:constants); nu is the kinematic viscosity
+ * (nu = 0 selects the inviscid position equation eq:Lagrangian-position-wf).
+ *   model        PDF_MODEL_SLM: G_ij = -(1/2 + 3/4 C0)<omega> delta_ij, C0 constant
+ *                PDF_MODEL_GLM: G_ij and C0 from wp_ij by eq:GandC
+ *   wp_source    GLM only: PDF_WP_INPUT (nodal field set by pdf_set_nodal_field)
+ *                or PDF_WP_LOCAL (right-hand side of eq:elliptic-relaxation-Lagrangian
+ *                evaluated at the nodes from the estimated statistics)
+ *   omega_source 1: S_omega of eq:frequency-source; 0: S_omega = 0
+ *   tm_mode      PDF_TM_CPHI: 1/t_m = C_phi <omega>/2; PDF_TM_KEPS: t_m = max(k/eps, C_T sqrt(nu/eps))
+ *   frozen       1: element records always come from the PDF_FIELD_STATS field;
+ *                the estimator still runs but is not fed back
+ *   wall_b       1: apply the no-slip trajectory (b) condition of eq:fw (nu > 0)
+ *   reorder_every  particles are re-sorted by host element every R steps (0: never)
+ *   src_x,src_y,src_r  continuous scalar source disc: psi = 1 inside (r <= 0: none) */
+typedef struct pdf_model_params {
+  int32_t model, wp_source, omega_source, tm_mode, frozen, wall_b, reorder_every, pad;
+  double C0, C1, C2, C3, C4, CT, CL, Ceta, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
+  double src_x, src_y, src_r;
+} pdf_model_params;
+
+/* Initial particle population (Ch.3, Sec. Particle-number control): ppe
+ * particles uniformly distributed in every element; velocity Gaussian with the
+ * nodal mean U0 and Reynolds stress R0 interpolated linearly at the particle;
+ * frequency Gamma(1/C4, C4*Om0); scalar by psi_mode with parameters a, b, c
+ * (STEP_X: psi = [x < a]; GAUSS_X: exp(-(x-a)^2/(2 b^2)); BERNOULLI: 0/1 with
+ * probability 1/2; DISC: psi = [|x-(a,b)| <= c]).  Host pointers:
+ *   U0 [3][n_nodes], R0 [6][n_nodes] (11,22,33,12,13,23), Om0 [n_nodes]. */
+typedef struct pdf_seed_desc {
+  int32_t ppe, psi_mode;
+  uint64_t seed;
+  double a, b, c;
+  const double *U0, *R0, *Om0;
+} pdf_seed_desc;
+
+/* Create a context: validate and upload the mesh, derive the linked lists
+ * (elements surrounding nodes, wall edges near each element) and shape-function
+ * derivatives (Ch.3, Sec. Derivatives).  precision is PDF_FP64 or PDF_FP32;
+ * hip_stream is a hipStream_t (NULL: the null stream); alloc may be NULL.
+ * On success *out owns all device memory until pdf_destroy. */
+pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *params,
+                         int32_t precision, const pdf_allocator *alloc, void *hip_stream,
+                         pdf_ctx **out);
+
+/* Set a nodal input field from host (on_device = 0) or device (1) memory:
+ *   PDF_FIELD_STATS [PDF_NSTAT][n_nodes]  nodal statistics (frozen mode, restart)
+ *   PDF_FIELD_WP    [9][n_nodes]          wp_ij row-major (GLM with PDF_WP_INPUT)
+ *   PDF_FIELD_GRADP [2][n_nodes]          mean-pressure gradient / rho
+ *                                         (eq:velocity-prediction; default 0) */
+pdf_status pdf_set_nodal_field(pdf_ctx *ctx, int32_t field, const double *data, int32_t on_device);
+
+/* Seed n_elems*ppe particles (ids e*ppe+j) and estimate the initial statistics. */
+pdf_status pdf_seed_particles(pdf_ctx *ctx, const pdf_seed_desc *seed);
+
+/* Advance nsteps explicit Euler-Maruyama steps of size dt (Ch.3, Sec.
+ * Timestepping).  Each step: element-average statistics from the nodal fields
+ * (loop (ii) of Table tab:loops), one fused particle kernel (noise, SDEs
+ * eq:Lagrangian-position-exact/-wf, eq:Lagrangian-model, eq:frequency-model,
+ * eq:IEM, tracking eq:element-test with boundary conditions, accumulation of
+ * element sums), then the two-pass nodal estimator and its derivatives.
+ * Asynchronous; lost particles are reported through the counters. */
+pdf_status pdf_advance(pdf_ctx *ctx, int32_t nsteps, double dt);
+
+/* Copy the latest nodal statistics (and optionally element statistics) out.
+ * nodal [PDF_NSTAT][n_nodes]: 0-2 <U>,<V>,<W>; 3 <omega>; 4 <phi>; 5-10 <u_i u_j>
+ * (11,22,33,12,13,23); 11 <phi'^2>; 12-14 <u_i phi'>; 15-20 d<U_i>/dx, d<U_i>/dy
+ * for i = U,V,W; 21-23 Laplacian of <U_i>; 24 particles in the non-empty
+ * surrounding elements.
+ * elem [PDF_NELEMSTAT][n_elems] or NULL: count, 5 means (u,v,w,omega,psi),
+ * 10 central moments (uu,vv,ww,uv,uw,vw,psipsi,upsi,vpsi,wpsi), 1/N normalised.
+ * on_device = 0: host buffers (synchronizes); 1: device buffers (asynchronous). */
+pdf_status pdf_estimate_stats(pdf_ctx *ctx, double *nodal, double *elem, int32_t on_device);
+
+/* Number of particles currently held. */
+pdf_status pdf_num_particles(pdf_ctx *ctx, int64_t *n);
+
+/* Copy the particle state to host memory in storage order:
+ * state [7][n] = x, y, u, v, w, omega, psi (as double), elem [n], id [n]. */
+pdf_status pdf_get_particles(pdf_ctx *ctx, double *state, int32_t *elem, uint32_t *id);
+
+/* Replace the particle state from host memory (same layout; n particles).
+ * Values are rounded to the context precision.  Statistics are re-estimated. */
+pdf_status pdf_set_particles(pdf_ctx *ctx, int64_t n, const double *state, const int32_t *elem,
+                             const uint32_t *id);
+
+/* Read (and optionally reset) the device counters PDF_CNT_*; synchronizes. */
+pdf_status pdf_get_counters(pdf_ctx *ctx, uint64_t *out, int32_t n, int32_t reset);
+
+/* Per-kernel timing of the last pdf_advance call, measured with HIP events on
+ * the context stream: out[0] element records, out[1] particle kernel,
+ * out[2] estimator, out[3] reorder (milliseconds, summed over its steps).
+ * Timing is recorded only while enabled (pdf_enable_timing). */
+pdf_status pdf_enable_timing(pdf_ctx *ctx, int32_t on);
+pdf_status pdf_get_timing(pdf_ctx *ctx, double *out_ms, int32_t n);
+
+const char *pdf_last_error(const pdf_ctx *ctx);
+void pdf_destroy(pdf_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

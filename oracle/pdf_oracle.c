@@ -114,6 +114,7 @@ struct or_mesh {
   int32_t *n2e_off, *n2e; /* node -> elements */
   int32_t *m2e_off, *m2e; /* master node -> elements touching any node identified with it */
   int32_t *w_off, *w_list; /* element -> no-slip wall edges sharing a node with it */
+  int32_t *nwall_off, *nwall; /* node -> wall (slip or no-slip) edges ending at it */
 };
 
 static void *dup(const void *p, size_t n) {
@@ -240,6 +241,24 @@ or_mesh *or_mesh_new(int32_t nn, int32_t ne, int32_t nb, const double *xy, const
   }
   free(nw_off);
   free(nw);
+  /* node -> wall edges (slip and no-slip) ending at the node, ascending */
+  m->nwall_off = (int32_t *)calloc((size_t)nn + 1, sizeof(int32_t));
+  for (int32_t b = 0; b < nb; ++b) {
+    if (bt[b] == OR_BC_PERIODIC) continue;
+    int32_t e = be[b], k = bl[b];
+    m->nwall_off[en[3 * e + (k + 1) % 3] + 1]++;
+    m->nwall_off[en[3 * e + (k + 2) % 3] + 1]++;
+  }
+  for (int32_t n = 0; n < nn; ++n) m->nwall_off[n + 1] += m->nwall_off[n];
+  m->nwall = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m->nwall_off[nn] + 1));
+  fill = (int32_t *)dup(m->nwall_off, sizeof(int32_t) * (size_t)nn);
+  for (int32_t b = 0; b < nb; ++b) {
+    if (bt[b] == OR_BC_PERIODIC) continue;
+    int32_t e = be[b], k = bl[b];
+    m->nwall[fill[en[3 * e + (k + 1) % 3]]++] = b;
+    m->nwall[fill[en[3 * e + (k + 2) % 3]]++] = b;
+  }
+  free(fill);
   return m;
 }
 
@@ -248,6 +267,7 @@ void or_mesh_free(or_mesh *m) {
   free(m->xy); free(m->en); free(m->nbr); free(m->be); free(m->bl); free(m->bt); free(m->bp);
   free(m->bs); free(m->master); free(m->area); free(m->dNdx); free(m->dNdy);
   free(m->n2e_off); free(m->n2e); free(m->m2e_off); free(m->m2e); free(m->w_off); free(m->w_list);
+  free(m->nwall_off); free(m->nwall);
   free(m);
 }
 
@@ -696,7 +716,9 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
     /* tracking: next best element walk with boundary conditions */
     int32_t e = e0, found = -1, nrefl = 0;
     double shx = 0.0, shy = 0.0;
-    for (int it = 0; it < 64 && found < 0; ++it) {
+    /* a non-finite position cannot be located: the particle is lost at once */
+    int finite_pos = isfinite(x) && isfinite(y);
+    for (int it = 0; it < 64 && found < 0 && finite_pos; ++it) {
       if (cnt) cnt[OR_CNT_WALK_STEPS]++;
       double lam[3];
       or_lambdas(m, e, x, y, lam);
@@ -728,7 +750,27 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
       double t = ((x - xa) * dx + (y - ya) * dy) / (dx * dx + dy * dy);
       int reflect = (t >= 0.0 && t <= 1.0);
       if (!reflect) {
-        /* beyond the end of this wall segment: concave corner fall-back */
+        /* past an end of this wall segment: the point is outside the domain if
+         * it lies directly behind another wall edge ending at that node */
+        int32_t c = m->en[3 * e + (t < 0.0 ? (k + 1) % 3 : (k + 2) % 3)];
+        for (int32_t j = m->nwall_off[c]; j < m->nwall_off[c + 1] && !reflect; ++j) {
+          int32_t w = m->nwall[j];
+          if (w == b) continue;
+          double wa, wya, wb, wyb;
+          edge_geom(m, m->be[w], m->bl[w], &wa, &wya, &wb, &wyb);
+          double wdx = wb - wa, wdy = wyb - wya;
+          double tw = ((x - wa) * wdx + (y - wya) * wdy) / (wdx * wdx + wdy * wdy);
+          double out = (x - wa) * wdy - (y - wya) * wdx; /* > 0 behind the wall line */
+          if (tw >= 0.0 && tw <= 1.0 && out > 0.0) {
+            reflect = 1;
+            b = w;
+            xa = wa; ya = wya; xb = wb; yb = wyb;
+            dx = wdx; dy = wdy;
+          }
+        }
+      }
+      if (!reflect) {
+        /* in the domain beyond a concave corner: fall-back of Fig. corner */
         int32_t f = search_patch(m, e0, x, y);
         if (f < 0) f = search_patch(m, e, x, y);
         if (f >= 0) {
@@ -762,8 +804,8 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
       nrefl++;
     }
     if (found < 0) {
-      int32_t f = search_patch(m, e0, x, y);
-      if (f < 0) f = or_locate_brute(m, x, y);
+      int32_t f = finite_pos ? search_patch(m, e0, x, y) : -1;
+      if (f < 0 && finite_pos) f = or_locate_brute(m, x, y);
       if (f >= 0) {
         if (cnt) cnt[OR_CNT_BRUTE]++;
         found = f;

@@ -1,0 +1,252 @@
+"""ctypes binding of libpdf.so (the C ABI in include/pdf.h).
+
+Argument marshalling only: every step of the particle method runs in the HIP
+kernels of libpdf.so.  PyTorch supplies the device memory (through the
+caching allocator hook of pdf_init_mesh) and the HIP stream.  If the library
+has not been built this module raises at import: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdf.so")
+
+PDF_OK = 0
+PDF_FP64, PDF_FP32 = 0, 1
+FIELD_STATS, FIELD_WP, FIELD_GRADP = 0, 1, 2
+NSTAT = 25
+NELEMSTAT = 16
+NCOUNTERS = 16
+COUNTER_NAMES = ["walk_steps", "fallback", "brute", "lost", "reflect", "periodic", "noslip_b",
+                 "omega_clamp", "gamma_fail", "empty_node", "nonfinite", "steps"]
+STATUS = {0: "PDF_OK", 1: "PDF_E_INVALID_ARG", 2: "PDF_E_BAD_MESH", 3: "PDF_E_OOM",
+          4: "PDF_E_DEVICE", 5: "PDF_E_STATE", 6: "PDF_E_LOST_PARTICLE", 7: "PDF_E_NUMERIC"}
+
+
+class PdfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_elems", C.c_int32), ("n_bedges", C.c_int32),
+                ("pad", C.c_int32), ("node_xy", C.c_void_p), ("elem_nodes", C.c_void_p),
+                ("elem_nbr", C.c_void_p), ("bedge_elem", C.c_void_p), ("bedge_local", C.c_void_p),
+                ("bedge_type", C.c_void_p), ("bedge_partner", C.c_void_p),
+                ("bedge_shift", C.c_void_p), ("node_master", C.c_void_p)]
+
+
+class ModelParams(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("model", "wp_source", "omega_source", "tm_mode", "frozen",
+                                         "wall_b", "reorder_every", "pad")] + \
+               [(n, C.c_double) for n in ("C0", "C1", "C2", "C3", "C4", "CT", "CL", "Ceta", "Cv",
+                                          "gamma5", "Cw1", "Cw2", "Cphi", "nu", "k_floor",
+                                          "src_x", "src_y", "src_r")]
+
+
+class SeedDesc(C.Structure):
+    _fields_ = [("ppe", C.c_int32), ("psi_mode", C.c_int32), ("seed", C.c_uint64),
+                ("a", C.c_double), ("b", C.c_double), ("c", C.c_double),
+                ("U0", C.c_void_p), ("R0", C.c_void_p), ("Om0", C.c_void_p)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
+                          "(run __graft_entry__.build() or python -m paper_1006_0720_amd.build)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "pdf_init_mesh": ([vp, vp, i32, vp, vp, C.POINTER(vp)], i32),
+        "pdf_set_nodal_field": ([vp, i32, vp, i32], i32),
+        "pdf_seed_particles": ([vp, vp], i32),
+        "pdf_advance": ([vp, i32, dbl], i32),
+        "pdf_estimate_stats": ([vp, vp, vp, i32], i32),
+        "pdf_num_particles": ([vp, C.POINTER(i64)], i32),
+        "pdf_get_particles": ([vp, vp, vp, vp], i32),
+        "pdf_set_particles": ([vp, i64, vp, vp, vp], i32),
+        "pdf_get_counters": ([vp, vp, i32, i32], i32),
+        "pdf_enable_timing": ([vp, i32], i32),
+        "pdf_get_timing": ([vp, vp, i32], i32),
+        "pdf_last_error": ([vp], C.c_char_p),
+        "pdf_destroy": ([vp], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    return L
+
+
+lib = _load()
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Context:
+    """One pdf_ctx on one GPU.  mesh: synth.meshes.Mesh-like object with the
+    arrays of pdf_mesh_desc; params: dict of pdf_model_params fields."""
+
+    def __init__(self, mesh, params: dict, precision="f64", device=0, stream=None,
+                 use_torch_allocator=True, reorder_every=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        if self.device.type != "cuda" or not torch.cuda.is_available():
+            raise RuntimeError("a ROCm GPU is required (torch.cuda is not available)")
+        torch.cuda.set_device(self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.prec = PDF_FP32 if precision == "f32" else PDF_FP64
+        self.n_nodes = mesh.n_nodes
+        self.n_elems = mesh.n_elems
+        self._arrays = [np.ascontiguousarray(mesh.node_xy, np.float64),
+                        np.ascontiguousarray(mesh.elem_nodes, np.int32),
+                        np.ascontiguousarray(mesh.elem_nbr, np.int32),
+                        np.ascontiguousarray(mesh.bedge_elem, np.int32),
+                        np.ascontiguousarray(mesh.bedge_local, np.int32),
+                        np.ascontiguousarray(mesh.bedge_type, np.int32),
+                        np.ascontiguousarray(mesh.bedge_partner, np.int32),
+                        np.ascontiguousarray(mesh.bedge_shift, np.float64),
+                        np.ascontiguousarray(mesh.node_master, np.int32)]
+        a = self._arrays
+        md = MeshDesc(mesh.n_nodes, mesh.n_elems, mesh.n_bedges, 0, *[_ptr(x) for x in a])
+        mp = ModelParams()
+        for name, _ in ModelParams._fields_:
+            if name == "pad":
+                continue
+            if name == "reorder_every":
+                mp.reorder_every = int(params.get("reorder_every", 0) if reorder_every is None
+                                       else reorder_every)
+                continue
+            setattr(mp, name, params[name])
+        self.params = mp
+        self._alloc = None
+        if use_torch_allocator:
+            dev = self.device.index
+            strm = self.stream
+
+            def _a(nbytes, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, strm)
+                except Exception:
+                    return None
+
+            def _f(ptr, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._alloc_fns = (ALLOC_FN(_a), FREE_FN(_f))
+            self._alloc = Allocator(self._alloc_fns[0], self._alloc_fns[1], None)
+        h = C.c_void_p()
+        st = lib.pdf_init_mesh(C.byref(md), C.byref(mp), self.prec,
+                               C.byref(self._alloc) if self._alloc is not None else None,
+                               C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        self.h = h
+        if st != PDF_OK:
+            msg = lib.pdf_last_error(h).decode() if h.value else ""
+            if h.value:
+                lib.pdf_destroy(h)
+            self.h = None
+            raise PdfError(st, msg)
+
+    def _chk(self, st):
+        if st != PDF_OK:
+            raise PdfError(st, lib.pdf_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.pdf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- inputs --------------------------------------------------------
+    def set_nodal_field(self, field, data):
+        if hasattr(data, "data_ptr"):
+            t = data.contiguous().to(self.torch.float64)
+            self._chk(lib.pdf_set_nodal_field(self.h, field, C.c_void_p(t.data_ptr()), 1))
+            self._keep = t
+        else:
+            arr = np.ascontiguousarray(data, np.float64)
+            self._chk(lib.pdf_set_nodal_field(self.h, field, _ptr(arr), 0))
+
+    def seed(self, spec: dict):
+        nn = self.n_nodes
+        U0 = np.ascontiguousarray(spec["U0"], np.float64).reshape(3, nn)
+        R0 = np.ascontiguousarray(spec["R0"], np.float64).reshape(6, nn)
+        Om0 = np.ascontiguousarray(spec["Om0"], np.float64).reshape(nn)
+        sd = SeedDesc(int(spec["ppe"]), int(spec.get("psi_mode", 0)), int(spec["seed"]),
+                      float(spec.get("a", 0.0)), float(spec.get("b", 0.0)), float(spec.get("c", 0.0)),
+                      _ptr(U0), _ptr(R0), _ptr(Om0))
+        self._chk(lib.pdf_seed_particles(self.h, C.byref(sd)))
+
+    # ---- stepping ------------------------------------------------------
+    def advance(self, nsteps, dt):
+        self._chk(lib.pdf_advance(self.h, int(nsteps), float(dt)))
+
+    # ---- outputs -------------------------------------------------------
+    def stats(self, elem=False):
+        nodal = np.empty((NSTAT, self.n_nodes))
+        el = np.empty((NELEMSTAT, self.n_elems)) if elem else None
+        self._chk(lib.pdf_estimate_stats(self.h, _ptr(nodal), _ptr(el), 0))
+        return (nodal, el) if elem else nodal
+
+    def stats_device(self):
+        """Nodal statistics copied into a new torch tensor on the context's device."""
+        t = self.torch.empty((NSTAT, self.n_nodes), dtype=self.torch.float64, device=self.device)
+        self._chk(lib.pdf_estimate_stats(self.h, C.c_void_p(t.data_ptr()), None, 1))
+        return t
+
+    def num_particles(self):
+        n = C.c_int64()
+        self._chk(lib.pdf_num_particles(self.h, C.byref(n)))
+        return n.value
+
+    def particles(self, sort_by_id=True):
+        n = self.num_particles()
+        state = np.empty((7, n))
+        elem = np.empty(n, np.int32)
+        pid = np.empty(n, np.uint32)
+        self._chk(lib.pdf_get_particles(self.h, _ptr(state), _ptr(elem), _ptr(pid)))
+        if sort_by_id:
+            o = np.argsort(pid, kind="stable")
+            return state[:, o], elem[o], pid[o]
+        return state, elem, pid
+
+    def set_particles(self, state, elem, pid):
+        state = np.ascontiguousarray(state, np.float64)
+        elem = np.ascontiguousarray(elem, np.int32)
+        pid = np.ascontiguousarray(pid, np.uint32)
+        self._chk(lib.pdf_set_particles(self.h, state.shape[1], _ptr(state), _ptr(elem), _ptr(pid)))
+
+    def counters(self, reset=False):
+        out = np.zeros(NCOUNTERS, np.uint64)
+        self._chk(lib.pdf_get_counters(self.h, _ptr(out), NCOUNTERS, int(reset)))
+        return {n: int(v) for n, v in zip(COUNTER_NAMES, out)}
+
+    def enable_timing(self, on=True):
+        self._chk(lib.pdf_enable_timing(self.h, int(on)))
+
+    def timing(self):
+        out = np.zeros(4)
+        self._chk(lib.pdf_get_timing(self.h, _ptr(out), 4))
+        return dict(elem_prep=out[0], advance=out[1], estimator=out[2], reorder=out[3])

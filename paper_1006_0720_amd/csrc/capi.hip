@@ -1,0 +1,670 @@
+// Host side of the C ABI declared in include/pdf.h.
+//
+// Owns the device memory of a context, validates and uploads the mesh, builds
+// the linked lists the method needs (Ch.3, Sec. Estimation of Eulerian
+// statistics and Sec. Particle tracking: elements surrounding elements,
+// elements surrounding nodes) and enqueues the per-step kernel pipeline on the
+// caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pdf_internal.h"
+
+using namespace pdfk;
+
+struct pdf_ctx {
+  int32_t prec = PDF_FP64;
+  hipStream_t stream = nullptr;
+  pdf_allocator alloc{};
+  bool has_alloc = false;
+  std::string err;
+  pdf_model_params params{};
+  MeshDev md{};
+  ModelDev model{};
+  std::vector<void *> owned;
+  // nodal fields
+  double *stats_a = nullptr, *stats_b = nullptr, *stats_cur = nullptr, *stats_est = nullptr,
+         *latest = nullptr;
+  double *wp = nullptr, *gradp = nullptr;
+  bool wp_set = false, gradp_set = false;
+  // element data
+  void *rec = nullptr;
+  double *sums = nullptr, *emom = nullptr;
+  int32_t *offs = nullptr, *cursor = nullptr, *blocksums = nullptr;
+  // particles (two buffers for the reorder)
+  void *pbuf[2] = {nullptr, nullptr};
+  int cur = 0;
+  int64_t np = 0;
+  int32_t ppe = 0;
+  uint64_t seed = 0;
+  uint32_t step = 0;
+  bool seeded = false;
+  unsigned long long *cnt = nullptr;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_phase;
+  double phase_ms[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+pdf_status fail(pdf_ctx *c, pdf_status s, const std::string &msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                                       \
+  do {                                                                                          \
+    hipError_t _e = (call);                                                                     \
+    if (_e != hipSuccess)                                                                       \
+      return fail(ctx, PDF_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(_e));        \
+  } while (0)
+
+void *dalloc(pdf_ctx *c, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~(size_t)255;
+  void *p = nullptr;
+  if (c->has_alloc) {
+    p = c->alloc.alloc(bytes, c->alloc.user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) c->owned.push_back(p);
+  return p;
+}
+
+void dfree(pdf_ctx *c, void *p) {
+  if (!p) return;
+  auto it = std::find(c->owned.begin(), c->owned.end(), p);
+  if (it != c->owned.end()) c->owned.erase(it);
+  if (c->has_alloc)
+    c->alloc.free(p, c->alloc.user);
+  else
+    (void)hipFree(p);
+}
+
+template <typename V>
+bool upload(pdf_ctx *c, const std::vector<V> &h, const V **out) {
+  V *d = (V *)dalloc(c, h.size() * sizeof(V));
+  if (!d) return false;
+  if (!h.empty() && hipMemcpyAsync(d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return false;
+  *out = d;
+  return true;
+}
+
+size_t tsize(const pdf_ctx *c) { return c->prec == PDF_FP32 ? 4 : 8; }
+
+template <typename T>
+PartDev<T> part_view(pdf_ctx *c, int which) {
+  char *b = (char *)c->pbuf[which];
+  const int64_t n = c->np;
+  PartDev<T> p;
+  T *t = (T *)b;
+  p.x = t;
+  p.y = t + n;
+  p.u = t + 2 * n;
+  p.v = t + 3 * n;
+  p.w = t + 4 * n;
+  p.om = t + 5 * n;
+  p.psi = t + 6 * n;
+  char *ip = b + ((7 * n * sizeof(T) + 255) & ~(size_t)255);
+  p.e = (int32_t *)ip;
+  p.id = (uint32_t *)(ip + ((n * 4 + 255) & ~(size_t)255));
+  return p;
+}
+
+size_t part_bytes(size_t tsz, int64_t n) {
+  return ((7 * n * tsz + 255) & ~(size_t)255) + 2 * ((n * 4 + 255) & ~(size_t)255);
+}
+
+void mark(pdf_ctx *c, int phase) {
+  if (!c->timing) return;
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  (void)hipEventRecord(e, c->stream);
+  c->ev.push_back(e);
+  c->ev_phase.push_back(phase);
+}
+
+// estimate the statistics of the current particle state from scratch:
+// a first pass with zero references gives the element means, which become the
+// references of a second, shifted pass (prev = nodal values kept for empty nodes)
+template <typename T>
+pdf_status estimate_from_scratch(pdf_ctx *c, const double *prev) {
+  const int32_t ne = c->md.ne;
+  T *rec = (T *)c->rec;
+  HIPCHK(c, hipMemsetAsync(rec, 0, (size_t)ne * NREC * sizeof(T), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->sums, 0, (size_t)ne * NSUM * sizeof(double), c->stream));
+  launch_accumulate<T>(c->stream, part_view<T>(c, c->cur), c->np, rec, c->sums);
+  launch_ref_from_sums<T>(c->stream, ne, c->sums, rec);
+  HIPCHK(c, hipMemsetAsync(c->sums, 0, (size_t)ne * NSUM * sizeof(double), c->stream));
+  launch_accumulate<T>(c->stream, part_view<T>(c, c->cur), c->np, rec, c->sums);
+  launch_elem_moments<T>(c->stream, ne, c->sums, rec, c->emom);
+  launch_node_stats(c->stream, c->md, c->emom, prev, c->stats_est, c->cnt);
+  launch_node_derivs(c->stream, c->md, c->stats_est);
+  HIPCHK(c, hipGetLastError());
+  // the estimate becomes the current statistics
+  std::swap(c->stats_cur, c->stats_est);
+  c->latest = c->stats_cur;
+  return PDF_OK;
+}
+
+template <typename T>
+pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt) {
+  const int32_t ne = c->md.ne;
+  T *rec = (T *)c->rec;
+  for (int32_t s = 0; s < nsteps; ++s) {
+    mark(c, 0);
+    if (c->params.model == PDF_MODEL_GLM && c->params.wp_source == PDF_WP_LOCAL)
+      launch_local_wp(c->stream, c->md, c->model, c->stats_cur, c->wp);
+    launch_elem_prep<T>(c->stream, c->md, c->model, c->stats_cur,
+                        c->params.model == PDF_MODEL_GLM ? c->wp : nullptr,
+                        c->gradp_set ? c->gradp : nullptr, dt, rec);
+    HIPCHK(c, hipMemsetAsync(c->sums, 0, (size_t)ne * NSUM * sizeof(double), c->stream));
+    mark(c, 1);
+    launch_advance<T>(c->stream, c->md, c->model, part_view<T>(c, c->cur), c->np, rec, c->sums,
+                      c->seed, c->step, dt, c->cnt);
+    mark(c, 2);
+    launch_elem_moments<T>(c->stream, ne, c->sums, rec, c->emom);
+    launch_node_stats(c->stream, c->md, c->emom, c->stats_cur, c->stats_est, c->cnt);
+    launch_node_derivs(c->stream, c->md, c->stats_est);
+    if (!c->params.frozen) {
+      std::swap(c->stats_cur, c->stats_est);
+      c->latest = c->stats_cur;
+    } else {
+      c->latest = c->stats_est;
+    }
+    c->step++;
+    mark(c, 3);
+    if (c->params.reorder_every > 0 && (c->step % (uint32_t)c->params.reorder_every) == 0) {
+      launch_reorder<T>(c->stream, ne, c->np, c->sums, c->offs, c->cursor, c->blocksums,
+                        part_view<T>(c, c->cur), part_view<T>(c, 1 - c->cur));
+      c->cur = 1 - c->cur;
+    }
+    mark(c, 4);
+    HIPCHK(c, hipGetLastError());
+  }
+  return PDF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pdf_last_error(const pdf_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void pdf_destroy(pdf_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto e : ctx->ev) (void)hipEventDestroy(e);
+  std::vector<void *> own = ctx->owned;
+  for (void *p : own) dfree(ctx, p);
+  delete ctx;
+}
+
+pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *params, int32_t precision,
+                         const pdf_allocator *alloc, void *hip_stream, pdf_ctx **out) {
+  if (!out) return PDF_E_INVALID_ARG;
+  *out = nullptr;
+  if (!mesh || !params || (precision != PDF_FP32 && precision != PDF_FP64)) return PDF_E_INVALID_ARG;
+  if (mesh->n_nodes <= 0 || mesh->n_elems <= 0 || mesh->n_bedges < 0 || !mesh->node_xy ||
+      !mesh->elem_nodes || !mesh->elem_nbr || !mesh->node_master ||
+      (mesh->n_bedges > 0 && (!mesh->bedge_elem || !mesh->bedge_local || !mesh->bedge_type ||
+                              !mesh->bedge_partner || !mesh->bedge_shift)))
+    return PDF_E_INVALID_ARG;
+  if (params->model != PDF_MODEL_SLM && params->model != PDF_MODEL_GLM) return PDF_E_INVALID_ARG;
+  if (!(params->C4 > 0.0 && params->C4 <= 1.0) || params->nu < 0.0 || params->reorder_every < 0)
+    return PDF_E_INVALID_ARG;
+  pdf_ctx *c = new pdf_ctx();
+  c->prec = precision;
+  c->stream = (hipStream_t)hip_stream;
+  c->params = *params;
+  if (alloc && alloc->alloc && alloc->free) {
+    c->alloc = *alloc;
+    c->has_alloc = true;
+  }
+  const int32_t nn = mesh->n_nodes, ne = mesh->n_elems, nb = mesh->n_bedges;
+  const double *xy = mesh->node_xy;
+  const int32_t *en = mesh->elem_nodes, *nbr = mesh->elem_nbr, *master = mesh->node_master;
+  // ---- validation ----
+  auto bad = [&](const std::string &m) {
+    c->err = m;
+    *out = c;  // the caller can read the message, then destroy
+    return PDF_E_BAD_MESH;
+  };
+  for (int32_t n = 0; n < nn; ++n) {
+    if (master[n] < 0 || master[n] >= nn || master[master[n]] != master[n])
+      return bad("node_master is not a projection at node " + std::to_string(n));
+  }
+  std::vector<ElemGeo> geo(ne);
+  std::vector<double> dN(6 * (size_t)ne);
+  std::vector<int32_t> mnode(3 * (size_t)ne);
+  for (int32_t e = 0; e < ne; ++e) {
+    ElemGeo &g = geo[e];
+    for (int k = 0; k < 3; ++k) {
+      const int32_t n = en[3 * e + k];
+      if (n < 0 || n >= nn) return bad("element node out of range in element " + std::to_string(e));
+      g.n[k] = n;
+      g.x[k] = xy[2 * n];
+      g.y[k] = xy[2 * n + 1];
+      g.nb[k] = nbr[3 * e + k];
+      mnode[3 * e + k] = master[n];
+    }
+    // shape-function derivatives of the linear triangle (Ch.3, Sec. Derivatives)
+    const double xBA = g.x[1] - g.x[0], yBA = g.y[1] - g.y[0];
+    const double xCA = g.x[2] - g.x[0], yCA = g.y[2] - g.y[0];
+    const double twoA = xBA * yCA - xCA * yBA;
+    if (!(twoA > 0.0)) return bad("non-positive area or clockwise element " + std::to_string(e));
+    dN[6 * e + 0] = (yBA - yCA) / twoA;
+    dN[6 * e + 1] = yCA / twoA;
+    dN[6 * e + 2] = -yBA / twoA;
+    dN[6 * e + 3] = (xCA - xBA) / twoA;
+    dN[6 * e + 4] = -xCA / twoA;
+    dN[6 * e + 5] = xBA / twoA;
+  }
+  for (int32_t e = 0; e < ne; ++e)
+    for (int k = 0; k < 3; ++k) {
+      const int32_t o = nbr[3 * e + k];
+      if (o >= 0) {
+        if (o >= ne) return bad("neighbour out of range in element " + std::to_string(e));
+        const int32_t a = en[3 * e + (k + 1) % 3], b = en[3 * e + (k + 2) % 3];
+        bool ok = false;
+        for (int j = 0; j < 3; ++j)
+          if (nbr[3 * o + j] == e && en[3 * o + (j + 1) % 3] == b && en[3 * o + (j + 2) % 3] == a) ok = true;
+        if (!ok) return bad("neighbour table not symmetric at element " + std::to_string(e));
+      } else {
+        const int32_t b = -(o + 1);
+        if (b >= nb || mesh->bedge_elem[b] != e || mesh->bedge_local[b] != k)
+          return bad("boundary edge table inconsistent at element " + std::to_string(e));
+      }
+    }
+  for (int32_t b = 0; b < nb; ++b) {
+    const int32_t t = mesh->bedge_type[b];
+    if (t != PDF_BC_PERIODIC && t != PDF_BC_SLIP && t != PDF_BC_NOSLIP)
+      return bad("unknown boundary type at edge " + std::to_string(b));
+    const int32_t e = mesh->bedge_elem[b], k = mesh->bedge_local[b];
+    if (e < 0 || e >= ne || k < 0 || k > 2 || nbr[3 * e + k] != -(b + 1))
+      return bad("boundary edge " + std::to_string(b) + " does not match elem_nbr");
+    if (t == PDF_BC_PERIODIC) {
+      const int32_t p = mesh->bedge_partner[b];
+      if (p < 0 || p >= nb || mesh->bedge_partner[p] != b || mesh->bedge_type[p] != PDF_BC_PERIODIC)
+        return bad("periodic partner not mutual at edge " + std::to_string(b));
+    }
+  }
+  // ---- linked lists ----
+  // elements surrounding nodes (ascending element index)
+  std::vector<int32_t> n2e_off(nn + 1, 0), n2e(3 * (size_t)ne);
+  for (int32_t i = 0; i < 3 * ne; ++i) n2e_off[en[i] + 1]++;
+  for (int32_t n = 0; n < nn; ++n) n2e_off[n + 1] += n2e_off[n];
+  {
+    std::vector<int32_t> fill(n2e_off.begin(), n2e_off.end() - 1);
+    for (int32_t e = 0; e < ne; ++e)
+      for (int k = 0; k < 3; ++k) n2e[fill[en[3 * e + k]]++] = e;
+  }
+  // elements surrounding each master node (an element once per distinct master)
+  std::vector<int32_t> m2e_off(nn + 1, 0);
+  std::vector<int32_t> m2e;
+  {
+    std::vector<std::vector<int32_t>> lists(nn);
+    for (int32_t e = 0; e < ne; ++e) {
+      const int32_t q[3] = {mnode[3 * e], mnode[3 * e + 1], mnode[3 * e + 2]};
+      for (int k = 0; k < 3; ++k) {
+        bool dup = false;
+        for (int j = 0; j < k; ++j) dup |= (q[j] == q[k]);
+        if (!dup) lists[q[k]].push_back(e);
+      }
+    }
+    for (int32_t n = 0; n < nn; ++n) m2e_off[n + 1] = m2e_off[n] + (int32_t)lists[n].size();
+    m2e.reserve(m2e_off[nn]);
+    for (int32_t n = 0; n < nn; ++n) m2e.insert(m2e.end(), lists[n].begin(), lists[n].end());
+  }
+  // element -> no-slip wall edges sharing a node with the element (ascending)
+  std::vector<int32_t> w_off(ne + 1, 0), w_list;
+  {
+    std::vector<std::vector<int32_t>> nw(nn);
+    for (int32_t b = 0; b < nb; ++b) {
+      if (mesh->bedge_type[b] != PDF_BC_NOSLIP) continue;
+      const int32_t e = mesh->bedge_elem[b], k = mesh->bedge_local[b];
+      nw[en[3 * e + (k + 1) % 3]].push_back(b);
+      nw[en[3 * e + (k + 2) % 3]].push_back(b);
+    }
+    for (int32_t e = 0; e < ne; ++e) {
+      std::vector<int32_t> l;
+      for (int k = 0; k < 3; ++k)
+        for (int32_t b : nw[en[3 * e + k]])
+          if (std::find(l.begin(), l.end(), b) == l.end()) l.push_back(b);
+      std::sort(l.begin(), l.end());
+      w_list.insert(w_list.end(), l.begin(), l.end());
+      w_off[e + 1] = (int32_t)w_list.size();
+    }
+  }
+  // node -> wall edges (slip and no-slip) ending at the node (ascending)
+  std::vector<int32_t> nwall_off(nn + 1, 0), nwall;
+  {
+    std::vector<std::vector<int32_t>> l(nn);
+    for (int32_t b = 0; b < nb; ++b) {
+      if (mesh->bedge_type[b] == PDF_BC_PERIODIC) continue;
+      const int32_t e = mesh->bedge_elem[b], k = mesh->bedge_local[b];
+      l[en[3 * e + (k + 1) % 3]].push_back(b);
+      l[en[3 * e + (k + 2) % 3]].push_back(b);
+    }
+    for (int32_t n = 0; n < nn; ++n) {
+      nwall.insert(nwall.end(), l[n].begin(), l[n].end());
+      nwall_off[n + 1] = (int32_t)nwall.size();
+    }
+  }
+  std::vector<int32_t> masters, slaves, slave_master;
+  for (int32_t n = 0; n < nn; ++n) {
+    if (master[n] == n)
+      masters.push_back(n);
+    else {
+      slaves.push_back(n);
+      slave_master.push_back(master[n]);
+    }
+  }
+  std::vector<int32_t> btype(mesh->bedge_type, mesh->bedge_type + nb);
+  std::vector<int32_t> bpart(mesh->bedge_partner, mesh->bedge_partner + nb);
+  std::vector<int32_t> belem(mesh->bedge_elem, mesh->bedge_elem + nb);
+  std::vector<int32_t> blocal(mesh->bedge_local, mesh->bedge_local + nb);
+  std::vector<double> bshift(mesh->bedge_shift, mesh->bedge_shift + 2 * (size_t)nb);
+  std::vector<int32_t> vmaster(master, master + nn);
+  // ---- upload ----
+  MeshDev &m = c->md;
+  m.ne = ne;
+  m.nn = nn;
+  m.nb = nb;
+  m.n_masters = (int32_t)masters.size();
+  m.n_slaves = (int32_t)slaves.size();
+  bool ok = upload(c, geo, &m.geo) && upload(c, mnode, &m.mnode) && upload(c, dN, &m.dN) &&
+            upload(c, btype, &m.btype) && upload(c, bpart, &m.bpart) && upload(c, belem, &m.belem) &&
+            upload(c, blocal, &m.blocal) && upload(c, bshift, &m.bshift) &&
+            upload(c, n2e_off, &m.n2e_off) && upload(c, n2e, &m.n2e) &&
+            upload(c, m2e_off, &m.m2e_off) && upload(c, m2e, &m.m2e) && upload(c, w_off, &m.w_off) &&
+            upload(c, w_list, &m.w_list) && upload(c, vmaster, &m.master) &&
+            upload(c, nwall_off, &m.nwall_off) && upload(c, nwall, &m.nwall) &&
+            upload(c, masters, &m.masters) && upload(c, slaves, &m.slaves) &&
+            upload(c, slave_master, &m.slave_master);
+  const size_t ts = tsize(c);
+  c->stats_a = (double *)dalloc(c, (size_t)PDF_NSTAT * nn * sizeof(double));
+  c->stats_b = (double *)dalloc(c, (size_t)PDF_NSTAT * nn * sizeof(double));
+  c->wp = (double *)dalloc(c, 9 * (size_t)nn * sizeof(double));
+  c->gradp = (double *)dalloc(c, 2 * (size_t)nn * sizeof(double));
+  c->rec = dalloc(c, (size_t)ne * NREC * ts);
+  c->sums = (double *)dalloc(c, (size_t)ne * NSUM * sizeof(double));
+  c->emom = (double *)dalloc(c, (size_t)ne * 16 * sizeof(double));
+  c->offs = (int32_t *)dalloc(c, ((size_t)ne + 1) * sizeof(int32_t));
+  c->cursor = (int32_t *)dalloc(c, ((size_t)ne + 1) * sizeof(int32_t));
+  c->blocksums = (int32_t *)dalloc(c, ((size_t)ne / 1024 + 2) * sizeof(int32_t));
+  c->cnt = (unsigned long long *)dalloc(c, PDF_NCOUNTERS * sizeof(unsigned long long));
+  if (!ok || !c->stats_a || !c->stats_b || !c->wp || !c->gradp || !c->rec || !c->sums || !c->emom ||
+      !c->offs || !c->cursor || !c->blocksums || !c->cnt) {
+    c->err = "device allocation or upload failed";
+    pdf_destroy(c);
+    return PDF_E_OOM;
+  }
+  c->stats_cur = c->stats_a;
+  c->stats_est = c->stats_b;
+  c->latest = c->stats_cur;
+  hipStream_t s = c->stream;
+  if (hipMemsetAsync(c->stats_a, 0, (size_t)PDF_NSTAT * nn * sizeof(double), s) != hipSuccess ||
+      hipMemsetAsync(c->stats_b, 0, (size_t)PDF_NSTAT * nn * sizeof(double), s) != hipSuccess ||
+      hipMemsetAsync(c->wp, 0, 9 * (size_t)nn * sizeof(double), s) != hipSuccess ||
+      hipMemsetAsync(c->gradp, 0, 2 * (size_t)nn * sizeof(double), s) != hipSuccess ||
+      hipMemsetAsync(c->rec, 0, (size_t)ne * NREC * ts, s) != hipSuccess ||
+      hipMemsetAsync(c->emom, 0, (size_t)ne * 16 * sizeof(double), s) != hipSuccess ||
+      hipMemsetAsync(c->cnt, 0, PDF_NCOUNTERS * sizeof(unsigned long long), s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    c->err = "device initialisation failed";
+    pdf_destroy(c);
+    return PDF_E_DEVICE;
+  }
+  ModelDev &md = c->model;
+  md.model = params->model;
+  md.wp_source = params->wp_source;
+  md.omega_source = params->omega_source;
+  md.tm_mode = params->tm_mode;
+  md.wall_b = params->wall_b;
+  md.C0 = params->C0;
+  md.C1 = params->C1;
+  md.C2 = params->C2;
+  md.C3 = params->C3;
+  md.C4 = params->C4;
+  md.CT = params->CT;
+  md.Cv = params->Cv;
+  md.gamma5 = params->gamma5;
+  md.Cw1 = params->Cw1;
+  md.Cw2 = params->Cw2;
+  md.Cphi = params->Cphi;
+  md.nu = params->nu;
+  md.k_floor = params->k_floor;
+  md.src_x = params->src_x;
+  md.src_y = params->src_y;
+  md.src_r = params->src_r;
+  *out = c;
+  return PDF_OK;
+}
+
+pdf_status pdf_set_nodal_field(pdf_ctx *c, int32_t field, const double *data, int32_t on_device) {
+  if (!c || !data) return PDF_E_INVALID_ARG;
+  const size_t nn = (size_t)c->md.nn;
+  double *dst;
+  size_t nf;
+  if (field == PDF_FIELD_STATS) {
+    dst = c->stats_cur;
+    nf = PDF_NSTAT;
+  } else if (field == PDF_FIELD_WP) {
+    dst = c->wp;
+    nf = 9;
+    c->wp_set = true;
+  } else if (field == PDF_FIELD_GRADP) {
+    dst = c->gradp;
+    nf = 2;
+    c->gradp_set = true;
+  } else {
+    return fail(c, PDF_E_INVALID_ARG, "unknown field id");
+  }
+  HIPCHK(c, hipMemcpyAsync(dst, data, nf * nn * sizeof(double),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  if (!on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (field == PDF_FIELD_STATS) c->latest = c->stats_cur;
+  return PDF_OK;
+}
+
+pdf_status pdf_seed_particles(pdf_ctx *c, const pdf_seed_desc *sd) {
+  if (!c || !sd || sd->ppe <= 0 || !sd->U0 || !sd->R0 || !sd->Om0) return PDF_E_INVALID_ARG;
+  if (sd->psi_mode < PDF_PSI_ZERO || sd->psi_mode > PDF_PSI_DISC) return PDF_E_INVALID_ARG;
+  const int64_t np = (int64_t)c->md.ne * sd->ppe;
+  if (np > (int64_t)0x7FFFFFFF) return fail(c, PDF_E_INVALID_ARG, "too many particles for 32-bit ids");
+  const size_t nn = (size_t)c->md.nn;
+  for (int i = 0; i < 2; ++i) {
+    dfree(c, c->pbuf[i]);
+    c->pbuf[i] = nullptr;
+  }
+  c->np = np;
+  c->ppe = sd->ppe;
+  c->seed = sd->seed;
+  c->step = 0;
+  c->cur = 0;
+  const size_t pb = part_bytes(tsize(c), np);
+  c->pbuf[0] = dalloc(c, pb);
+  if (c->params.reorder_every > 0) c->pbuf[1] = dalloc(c, pb);
+  double *tmp = (double *)dalloc(c, 10 * nn * sizeof(double));
+  if (!c->pbuf[0] || (c->params.reorder_every > 0 && !c->pbuf[1]) || !tmp)
+    return fail(c, PDF_E_OOM, "particle allocation failed");
+  HIPCHK(c, hipMemcpyAsync(tmp, sd->U0, 3 * nn * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(tmp + 3 * nn, sd->R0, 6 * nn * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(tmp + 9 * nn, sd->Om0, nn * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->stats_cur, 0, PDF_NSTAT * nn * sizeof(double), c->stream));
+  pdf_status st;
+  if (c->prec == PDF_FP32) {
+    launch_seed<float>(c->stream, c->md, c->model, part_view<float>(c, 0), sd->ppe, sd->seed,
+                       sd->psi_mode, sd->a, sd->b, sd->c, tmp, tmp + 3 * nn, tmp + 9 * nn, c->cnt);
+    st = estimate_from_scratch<float>(c, c->stats_cur);
+  } else {
+    launch_seed<double>(c->stream, c->md, c->model, part_view<double>(c, 0), sd->ppe, sd->seed,
+                        sd->psi_mode, sd->a, sd->b, sd->c, tmp, tmp + 3 * nn, tmp + 9 * nn, c->cnt);
+    st = estimate_from_scratch<double>(c, c->stats_cur);
+  }
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  dfree(c, tmp);
+  if (st != PDF_OK) return st;
+  c->seeded = true;
+  return PDF_OK;
+}
+
+pdf_status pdf_advance(pdf_ctx *c, int32_t nsteps, double dt) {
+  if (!c || nsteps < 0 || !(dt > 0.0)) return PDF_E_INVALID_ARG;
+  if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_advance before pdf_seed_particles");
+  if (c->params.model == PDF_MODEL_GLM && c->params.wp_source == PDF_WP_INPUT && !c->wp_set)
+    return fail(c, PDF_E_STATE, "GLM with PDF_WP_INPUT needs the PDF_FIELD_WP field");
+  if (c->timing) {
+    for (auto e : c->ev) (void)hipEventDestroy(e);
+    c->ev.clear();
+    c->ev_phase.clear();
+  }
+  return c->prec == PDF_FP32 ? advance_impl<float>(c, nsteps, dt) : advance_impl<double>(c, nsteps, dt);
+}
+
+pdf_status pdf_estimate_stats(pdf_ctx *c, double *nodal, double *elem, int32_t on_device) {
+  if (!c || (!nodal && !elem)) return PDF_E_INVALID_ARG;
+  if (!c->seeded) return fail(c, PDF_E_STATE, "no particles");
+  const size_t nn = (size_t)c->md.nn, ne = (size_t)c->md.ne;
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (nodal) HIPCHK(c, hipMemcpyAsync(nodal, c->latest, PDF_NSTAT * nn * sizeof(double), kind, c->stream));
+  if (elem) {
+    double *tmp = on_device ? elem : (double *)dalloc(c, 16 * ne * sizeof(double));
+    if (!tmp) return fail(c, PDF_E_OOM, "temporary allocation failed");
+    launch_export_elem(c->stream, (int32_t)ne, c->emom, tmp);
+    HIPCHK(c, hipGetLastError());
+    if (!on_device) {
+      HIPCHK(c, hipMemcpyAsync(elem, tmp, 16 * ne * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      dfree(c, tmp);
+    }
+  }
+  if (!on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PDF_OK;
+}
+
+pdf_status pdf_num_particles(pdf_ctx *c, int64_t *n) {
+  if (!c || !n) return PDF_E_INVALID_ARG;
+  *n = c->np;
+  return PDF_OK;
+}
+
+pdf_status pdf_get_particles(pdf_ctx *c, double *state, int32_t *elem, uint32_t *id) {
+  if (!c) return PDF_E_INVALID_ARG;
+  if (!c->seeded) return fail(c, PDF_E_STATE, "no particles");
+  const int64_t np = c->np;
+  if (state) {
+    double *tmp = (double *)dalloc(c, 7 * (size_t)np * sizeof(double));
+    if (!tmp) return fail(c, PDF_E_OOM, "temporary allocation failed");
+    if (c->prec == PDF_FP32)
+      launch_pack_state<float>(c->stream, part_view<float>(c, c->cur), np, tmp);
+    else
+      launch_pack_state<double>(c->stream, part_view<double>(c, c->cur), np, tmp);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(state, tmp, 7 * (size_t)np * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    dfree(c, tmp);
+  }
+  if (elem) {
+    int32_t *e = c->prec == PDF_FP32 ? part_view<float>(c, c->cur).e : part_view<double>(c, c->cur).e;
+    HIPCHK(c, hipMemcpyAsync(elem, e, (size_t)np * 4, hipMemcpyDeviceToHost, c->stream));
+  }
+  if (id) {
+    uint32_t *d = c->prec == PDF_FP32 ? part_view<float>(c, c->cur).id : part_view<double>(c, c->cur).id;
+    HIPCHK(c, hipMemcpyAsync(id, d, (size_t)np * 4, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PDF_OK;
+}
+
+pdf_status pdf_set_particles(pdf_ctx *c, int64_t n, const double *state, const int32_t *elem,
+                             const uint32_t *id) {
+  if (!c || n <= 0 || !state || !elem || !id) return PDF_E_INVALID_ARG;
+  const int32_t ne = c->md.ne;
+  for (int64_t i = 0; i < n; ++i)
+    if (elem[i] < 0 || elem[i] >= ne) return fail(c, PDF_E_INVALID_ARG, "element index out of range");
+  if (n != c->np || !c->pbuf[0]) {
+    for (int i = 0; i < 2; ++i) {
+      dfree(c, c->pbuf[i]);
+      c->pbuf[i] = nullptr;
+    }
+    c->np = n;
+    c->cur = 0;
+    const size_t pb = part_bytes(tsize(c), n);
+    c->pbuf[0] = dalloc(c, pb);
+    if (c->params.reorder_every > 0) c->pbuf[1] = dalloc(c, pb);
+    if (!c->pbuf[0] || (c->params.reorder_every > 0 && !c->pbuf[1]))
+      return fail(c, PDF_E_OOM, "particle allocation failed");
+  }
+  double *tmp = (double *)dalloc(c, 7 * (size_t)n * sizeof(double));
+  if (!tmp) return fail(c, PDF_E_OOM, "temporary allocation failed");
+  HIPCHK(c, hipMemcpyAsync(tmp, state, 7 * (size_t)n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  pdf_status st;
+  if (c->prec == PDF_FP32) {
+    PartDev<float> p = part_view<float>(c, c->cur);
+    launch_unpack_state<float>(c->stream, p, n, tmp);
+    HIPCHK(c, hipMemcpyAsync(p.e, elem, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(p.id, id, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+    st = estimate_from_scratch<float>(c, c->stats_cur);
+  } else {
+    PartDev<double> p = part_view<double>(c, c->cur);
+    launch_unpack_state<double>(c->stream, p, n, tmp);
+    HIPCHK(c, hipMemcpyAsync(p.e, elem, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(p.id, id, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+    st = estimate_from_scratch<double>(c, c->stats_cur);
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  dfree(c, tmp);
+  if (st != PDF_OK) return st;
+  c->seeded = true;
+  return PDF_OK;
+}
+
+pdf_status pdf_get_counters(pdf_ctx *c, uint64_t *out, int32_t n, int32_t reset) {
+  if (!c || !out || n < 0 || n > PDF_NCOUNTERS) return PDF_E_INVALID_ARG;
+  unsigned long long h[PDF_NCOUNTERS];
+  HIPCHK(c, hipMemcpyAsync(h, c->cnt, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  h[PDF_CNT_STEPS] = c->step;
+  for (int i = 0; i < n; ++i) out[i] = h[i];
+  if (reset) {
+    HIPCHK(c, hipMemsetAsync(c->cnt, 0, sizeof(h), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return PDF_OK;
+}
+
+pdf_status pdf_enable_timing(pdf_ctx *c, int32_t on) {
+  if (!c) return PDF_E_INVALID_ARG;
+  c->timing = on != 0;
+  return PDF_OK;
+}
+
+pdf_status pdf_get_timing(pdf_ctx *c, double *out_ms, int32_t n) {
+  if (!c || !out_ms || n < 0) return PDF_E_INVALID_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double acc[4] = {0, 0, 0, 0};
+  for (size_t i = 0; i + 1 < c->ev.size(); ++i) {
+    const int ph = c->ev_phase[i];
+    if (ph > 3) continue;  // phase 4 marks the end of a step
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+    acc[ph] += ms;
+  }
+  for (int i = 0; i < n && i < 4; ++i) out_ms[i] = acc[i];
+  return PDF_OK;
+}
+
+}  // extern "C"

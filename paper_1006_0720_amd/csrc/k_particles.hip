@@ -1,0 +1,638 @@
+// Particle kernels for gfx950: seeding, element records and the fused
+// Euler-Maruyama step with tracking, boundary conditions and accumulation.
+//
+// Method: J. Bakosi, "PDF modeling of turbulent flows on unstructured grids"
+// (2008).  Equations are cited by their labels; "Ch.3 ..." names a section.
+//
+// Precision: particle state in T (float or double).  Positions are advanced,
+// reflected and located in binary64 and stored rounded to T, so the element
+// decision is taken on the stored position.  The library is compiled with
+// floating-point contraction off; fused multiply-adds are written explicitly
+// only where the element decision does not depend on them.
+#include <hip/hip_runtime.h>
+
+#include "pdf_internal.h"
+#include "rng.h"
+
+namespace pdfk {
+
+template <typename T>
+__device__ __forceinline__ double stor(double v) {
+  return (double)(T)v;
+}
+
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// ---------------------------------------------------------------------------
+// Element test (eq:element-test): signed areas of the sub-triangles formed by
+// the point and each edge, each edge evaluated from its lower to its higher
+// global node number so that the two elements sharing an edge get the same
+// magnitude with opposite signs.  lam[k] belongs to the edge opposite local
+// node k.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void edge_lambdas(const ElemGeo &g, double px, double py, double lam[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int a = (k + 1) % 3, b = (k + 2) % 3;
+    const bool fwd = g.n[a] < g.n[b];
+    const double xp = fwd ? g.x[a] : g.x[b], yp = fwd ? g.y[a] : g.y[b];
+    const double xq = fwd ? g.x[b] : g.x[a], yq = fwd ? g.y[b] : g.y[a];
+    const double cr = (xq - xp) * (py - yp) - (yq - yp) * (px - xp);
+    lam[k] = fwd ? cr : -cr;
+  }
+}
+
+__device__ __forceinline__ bool contains(const ElemGeo &g, double px, double py) {
+  double l[3];
+  edge_lambdas(g, px, py, l);
+  return l[0] >= 0.0 && l[1] >= 0.0 && l[2] >= 0.0;
+}
+
+// fall-back for concave corners (Fig. corner): elements surrounding the nodes of e
+__device__ int32_t search_patch(const MeshDev &m, int32_t e, double px, double py) {
+  const ElemGeo g = m.geo[e];
+  for (int k = 0; k < 3; ++k) {
+    const int32_t n = g.n[k];
+    for (int32_t i = m.n2e_off[n]; i < m.n2e_off[n + 1]; ++i) {
+      const int32_t c = m.n2e[i];
+      if (contains(m.geo[c], px, py)) return c;
+    }
+  }
+  return -1;
+}
+
+__device__ int32_t locate_brute(const MeshDev &m, double px, double py) {
+  for (int32_t e = 0; e < m.ne; ++e)
+    if (contains(m.geo[e], px, py)) return e;
+  return -1;
+}
+
+// wave-wide sum of a per-lane count followed by one atomic per wave
+__device__ __forceinline__ void wave_count(unsigned long long *dst, int v) {
+  if (__ballot(v != 0) == 0) return;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(dst, (unsigned long long)v);
+}
+
+// ---------------------------------------------------------------------------
+// Seeding (Ch.3, Sec. Particle-number control)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_seed(MeshDev m, ModelDev md, PartDev<T> p, int32_t ppe,
+                                              uint32_t k0, uint32_t k1, int32_t psi_mode, double pa,
+                                              double pb, double pc, const double *U0,
+                                              const double *R0, const double *Om0, int64_t np,
+                                              unsigned long long *cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int gfail = 0;
+  if (i < np) {
+    const int32_t e = (int32_t)(i / ppe);
+    const uint32_t id = (uint32_t)i;
+    const ElemGeo g = m.geo[e];
+    const int nn = m.nn;
+    const u32x4 r = philox10(id, 0xFFFFFFFFu, 0u, 0u, k0, k1);
+    const u32x4 r2 = philox10(id, 0xFFFFFFFFu, 1u, 0u, k0, k1);
+    double b1 = unif_d(r.a), b2 = unif_d(r.b);
+    if (b1 + b2 > 1.0) {
+      b1 = 1.0 - b1;
+      b2 = 1.0 - b2;
+    }
+    double x = g.x[0] + b1 * (g.x[1] - g.x[0]) + b2 * (g.x[2] - g.x[0]);
+    double y = g.y[0] + b1 * (g.y[1] - g.y[0]) + b2 * (g.y[2] - g.y[0]);
+    const double wA = 1.0 - b1 - b2, wB = b1, wC = b2;
+    double z0, z1, z2, z3;
+    box_muller_d(r.c, r.d, z0, z1);
+    box_muller_d(r2.a, r2.b, z2, z3);
+    const int nA = g.n[0], nB = g.n[1], nC = g.n[2];
+    double U[3], R[6];
+    for (int f = 0; f < 3; ++f)
+      U[f] = wA * U0[f * nn + nA] + wB * U0[f * nn + nB] + wC * U0[f * nn + nC];
+    for (int f = 0; f < 6; ++f)
+      R[f] = wA * R0[f * nn + nA] + wB * R0[f * nn + nB] + wC * R0[f * nn + nC];
+    const double Om = wA * Om0[nA] + wB * Om0[nB] + wC * Om0[nC];
+    // velocity = U + L z with L the Cholesky factor of the Reynolds stress
+    const double L11 = sqrt(R[0] > 0.0 ? R[0] : 0.0);
+    const double L21 = L11 > 0.0 ? R[3] / L11 : 0.0, L31 = L11 > 0.0 ? R[4] / L11 : 0.0;
+    const double t22 = R[1] - L21 * L21;
+    const double L22 = sqrt(t22 > 0.0 ? t22 : 0.0);
+    const double L32 = L22 > 0.0 ? (R[5] - L31 * L21) / L22 : 0.0;
+    const double t33 = R[2] - L31 * L31 - L32 * L32;
+    const double L33 = sqrt(t33 > 0.0 ? t33 : 0.0);
+    const double u = U[0] + L11 * z0;
+    const double v = U[1] + L21 * z0 + L22 * z1;
+    const double w = U[2] + L31 * z0 + L32 * z1 + L33 * z2;
+    int fail = 0;
+    const double om =
+        (Om > 0.0) ? gamma_mt(1.0 / md.C4, md.C4 * Om, k0, k1, id, 0xFFFFFFFFu, 16u, &fail) : 0.0;
+    gfail = fail;
+    x = stor<T>(x);
+    y = stor<T>(y);
+    double psi = 0.0;
+    if (psi_mode == PDF_PSI_STEP_X) psi = (x < pa) ? 1.0 : 0.0;
+    else if (psi_mode == PDF_PSI_GAUSS_X) psi = exp(-(x - pa) * (x - pa) / (2.0 * pb * pb));
+    else if (psi_mode == PDF_PSI_BERNOULLI) psi = (unif_d(r2.c) < 0.5) ? 1.0 : 0.0;
+    else if (psi_mode == PDF_PSI_DISC) psi = ((x - pa) * (x - pa) + (y - pb) * (y - pb) <= pc * pc) ? 1.0 : 0.0;
+    p.x[i] = (T)x;
+    p.y[i] = (T)y;
+    p.u[i] = (T)u;
+    p.v[i] = (T)v;
+    p.w[i] = (T)w;
+    p.om[i] = (T)om;
+    p.psi[i] = (T)psi;
+    p.e[i] = e;
+    p.id[i] = id;
+  }
+  wave_count(&cnt[PDF_CNT_GAMMA_FAIL], gfail);
+}
+
+template <typename T>
+void launch_seed(hipStream_t s, const MeshDev &m, const ModelDev &md, PartDev<T> p, int32_t ppe,
+                 uint64_t seed, int32_t psi_mode, double a, double b, double c, const double *U0,
+                 const double *R0, const double *Om0, unsigned long long *cnt) {
+  const int64_t np = (int64_t)m.ne * ppe;
+  const unsigned grid = (unsigned)((np + 255) / 256);
+  hipLaunchKernelGGL(k_seed<T>, dim3(grid), dim3(256), 0, s, m, md, p, ppe, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), psi_mode, a, b, c, U0, R0, Om0, np, cnt);
+}
+
+// ---------------------------------------------------------------------------
+// Element records (loop (ii) of Table tab:loops): element average of the nodal
+// statistics, the element's FEM gradient of the mean velocity (eq:gradient),
+// k, eps (eq:dissipation-from-frequency_wall), G_ij and C0 (eq:wall-GandC or
+// eq:GandC), production, S_omega (eq:frequency-source) and t_m.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_elem_prep(MeshDev m, ModelDev md, const double *S,
+                                                   const double *wp, const double *gradp, double dt,
+                                                   T *rec) {
+  const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.ne) return;
+  const int nn = m.nn;
+  const int q0 = m.mnode[3 * e], q1 = m.mnode[3 * e + 1], q2 = m.mnode[3 * e + 2];
+  const int qk[3] = {q0, q1, q2};
+#define AVG(arr, f) ((arr[(f) * nn + q0] + arr[(f) * nn + q1] + arr[(f) * nn + q2]) / 3.0)
+  double U[3] = {AVG(S, 0), AVG(S, 1), AVG(S, 2)};
+  const double Om = AVG(S, 3), Phi = AVG(S, 4);
+  double R[6];
+  for (int i = 0; i < 6; ++i) R[i] = AVG(S, 5 + i);
+  const double lap[3] = {AVG(S, 21), AVG(S, 22), AVG(S, 23)};
+  const double gp[2] = {gradp ? AVG(gradp, 0) : 0.0, gradp ? AVG(gradp, 1) : 0.0};
+  const double *d = m.dN + 6 * (size_t)e;
+  double dU[3][2];
+  for (int i = 0; i < 3; ++i) {
+    double gx = 0.0, gy = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      gx += d[k] * S[i * nn + qk[k]];
+      gy += d[3 + k] * S[i * nn + qk[k]];
+    }
+    dU[i][0] = gx;
+    dU[i][1] = gy;
+  }
+  double gs[2] = {0.0, 0.0};
+  for (int k = 0; k < 3; ++k) {
+    const double kn = 0.5 * (S[5 * nn + qk[k]] + S[6 * nn + qk[k]] + S[7 * nn + qk[k]]);
+    const double sq = sqrt(2.0 * (kn > 0.0 ? kn : 0.0));
+    gs[0] += d[k] * sq;
+    gs[1] += d[3 + k] * sq;
+  }
+  double k = 0.5 * (R[0] + R[1] + R[2]);
+  if (!(k > md.k_floor)) k = md.k_floor;
+  const double eps = Om * (k + md.nu * md.CT * md.CT * Om);
+  double G[3][3], C0;
+  const int sidx[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+  if (md.model == PDF_MODEL_SLM) {
+    C0 = md.C0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) G[i][j] = (i == j) ? -(0.5 + 0.75 * md.C0) * Om : 0.0;
+  } else {
+    double wr = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const double W = AVG(wp, 3 * i + j);
+        G[i][j] = (W - ((i == j) ? 0.5 * eps : 0.0)) / k;
+        wr += W * R[sidx[i][j]];
+      }
+    const double c0 = -2.0 * wr / (3.0 * k * eps);
+    C0 = (c0 > 0.0) ? c0 : 0.0;
+  }
+#undef AVG
+  double prod = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 2; ++j) prod -= R[sidx[i][j]] * dU[i][j];
+  const double Sw = md.omega_source ? (md.Cw2 - md.Cw1 * prod / eps) : 0.0;
+  double inv_tm;
+  if (md.tm_mode == PDF_TM_CPHI) {
+    inv_tm = 0.5 * md.Cphi * Om;
+  } else {
+    const double ta = k / eps, tb = md.CT * sqrt(md.nu / eps);
+    inv_tm = 1.0 / (ta > tb ? ta : tb);
+  }
+  T *r = rec + (size_t)e * NREC;
+  r[R_U] = (T)U[0];
+  r[R_V] = (T)U[1];
+  r[R_W] = (T)U[2];
+  r[R_OM] = (T)Om;
+  r[R_PHI] = (T)Phi;
+  r[R_A0] = (T)((-gp[0] + 2.0 * md.nu * lap[0]) * dt);
+  r[R_A1] = (T)((-gp[1] + 2.0 * md.nu * lap[1]) * dt);
+  r[R_A2] = (T)((2.0 * md.nu * lap[2]) * dt);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) r[R_G00 + 3 * i + j] = (T)(G[i][j] * dt);
+  r[R_SC0] = (T)sqrt(C0 * eps * dt);
+  const double sv = sqrt(2.0 * md.nu * dt);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 2; ++j) r[R_B00 + 2 * i + j] = (T)(sv * dU[i][j]);
+  r[R_WA] = (T)(md.C3 * Om * dt);
+  r[R_WB] = (T)(Sw * Om * dt);
+  r[R_WC] = (T)sqrt(2.0 * md.C3 * md.C4 * Om * Om * dt);
+  r[R_MIX] = (T)(dt * inv_tm);
+  r[R_GSX] = (T)gs[0];
+  r[R_GSY] = (T)gs[1];
+  r[30] = (T)0;
+  r[31] = (T)0;
+}
+
+template <typename T>
+void launch_elem_prep(hipStream_t s, const MeshDev &m, const ModelDev &md, const double *stats,
+                      const double *wp, const double *gradp, double dt, T *rec) {
+  hipLaunchKernelGGL(k_elem_prep<T>, dim3((m.ne + 255) / 256), dim3(256), 0, s, m, md, stats, wp,
+                     gradp, dt, rec);
+}
+
+// ---------------------------------------------------------------------------
+// Accumulation of element sums about the element's reference means
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void accumulate(double *sums, const T *rec, int32_t e, T u, T v, T w, T om,
+                                           T psi) {
+  const T *r = rec + (size_t)e * NREC;
+  const double q0 = (double)u - (double)r[R_U], q1 = (double)v - (double)r[R_V],
+               q2 = (double)w - (double)r[R_W], q3 = (double)om - (double)r[R_OM],
+               q4 = (double)psi - (double)r[R_PHI];
+  double *s = sums + (size_t)e * NSUM;
+  unsafeAtomicAdd(&s[0], 1.0);
+  unsafeAtomicAdd(&s[1], q0);
+  unsafeAtomicAdd(&s[2], q1);
+  unsafeAtomicAdd(&s[3], q2);
+  unsafeAtomicAdd(&s[4], q3);
+  unsafeAtomicAdd(&s[5], q4);
+  unsafeAtomicAdd(&s[6], q0 * q0);
+  unsafeAtomicAdd(&s[7], q1 * q1);
+  unsafeAtomicAdd(&s[8], q2 * q2);
+  unsafeAtomicAdd(&s[9], q0 * q1);
+  unsafeAtomicAdd(&s[10], q0 * q2);
+  unsafeAtomicAdd(&s[11], q1 * q2);
+  unsafeAtomicAdd(&s[12], q4 * q4);
+  unsafeAtomicAdd(&s[13], q0 * q4);
+  unsafeAtomicAdd(&s[14], q1 * q4);
+  unsafeAtomicAdd(&s[15], q2 * q4);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_accumulate(PartDev<T> p, int64_t np, const T *rec, double *sums) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  accumulate<T>(sums, rec, p.e[i], p.u[i], p.v[i], p.w[i], p.om[i], p.psi[i]);
+}
+
+template <typename T>
+void launch_accumulate(hipStream_t s, PartDev<T> p, int64_t np, const T *rec, double *sums) {
+  hipLaunchKernelGGL(k_accumulate<T>, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, p, np,
+                     rec, sums);
+}
+
+// reference means from a first accumulation pass made with zero references
+template <typename T>
+__global__ void k_ref_from_sums(int32_t ne, const double *sums, T *rec) {
+  const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const double *s = sums + (size_t)e * NSUM;
+  T *r = rec + (size_t)e * NREC;
+  for (int f = 0; f < NREC; ++f) r[f] = (T)0;
+  if (s[0] > 0.0)
+    for (int f = 0; f < 5; ++f) r[f] = (T)(s[1 + f] / s[0]);
+}
+
+template <typename T>
+void launch_ref_from_sums(hipStream_t s, int32_t ne, const double *sums, T *rec) {
+  hipLaunchKernelGGL(k_ref_from_sums<T>, dim3((ne + 255) / 256), dim3(256), 0, s, ne, sums, rec);
+}
+
+// ---------------------------------------------------------------------------
+// No-slip particle condition (Ch.3, Sec. No-slip wall-boundary conditions):
+// U_i = 0 and a frequency drawn from the gamma distribution with mean
+// (1/C_T) d sqrt(2k)/dn (inward) and variance C4 <omega>^2 (eq:frequency-wallstats)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void noslip(const ModelDev &md, const T *r, double nx, double ny,
+                                       uint32_t k0, uint32_t k1, uint32_t id, uint32_t step, int hit,
+                                       T &u, T &v, T &w, T &om, int &gfail) {
+  u = (T)0;
+  v = (T)0;
+  w = (T)0;
+  double omw = -((double)r[R_GSX] * nx + (double)r[R_GSY] * ny) / md.CT;
+  if (!(omw > 0.0)) omw = (double)r[R_OM];
+  if (omw > 0.0) {
+    int fail = 0;
+    om = (T)gamma_mt(1.0 / md.C4, md.C4 * omw, k0, k1, id, step, 16u + 32u * (uint32_t)hit, &fail);
+    gfail += fail;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The fused particle step.  One thread per particle in storage order:
+//   noise (Philox) -> eq:Lagrangian-position-exact / -wf -> eq:velocity-prediction
+//   -> eq:frequency-model -> eq:IEM -> next-best-element walk with periodic,
+//   slip and no-slip conditions -> trajectory (b) of eq:fw -> source
+//   -> store -> element sums of the new host.
+// ---------------------------------------------------------------------------
+template <typename T, bool VISC, bool WALLB>
+__global__ __launch_bounds__(256) void k_advance(MeshDev m, ModelDev md, PartDev<T> p, int64_t np,
+                                                 const T *__restrict__ rec, double *sums, uint32_t k0,
+                                                 uint32_t k1, uint32_t step, double dt, double sdt,
+                                                 double s2nu, unsigned long long *cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int c_walk = 0, c_fall = 0, c_brute = 0, c_lost = 0, c_refl = 0, c_per = 0, c_b = 0, c_clamp = 0,
+      c_gfail = 0, c_nan = 0;
+  if (i < np) {
+    const int32_t e0 = p.e[i];
+    const uint32_t id = p.id[i];
+    const double x0 = (double)p.x[i], y0 = (double)p.y[i];
+    const T up0 = p.u[i], up1 = p.v[i], up2 = p.w[i], om = p.om[i], psi = p.psi[i];
+    const T *r = rec + (size_t)e0 * NREC;
+
+    // ---- noise: six standard normals and one uniform per particle-step ----
+    const u32x4 q0 = philox10(id, step, 0u, 0u, k0, k1);
+    const u32x4 q1 = philox10(id, step, 1u, 0u, k0, k1);
+    double xi0 = 0.0, xi1 = 0.0;
+    T xi2, xi3, xi4, xi5;
+    if (VISC || sizeof(T) == 8) box_muller_d(q0.a, q0.b, xi0, xi1);
+    if constexpr (sizeof(T) == 8) {
+      double a0, a1, a2, a3;
+      box_muller_d(q0.c, q0.d, a0, a1);
+      box_muller_d(q1.a, q1.b, a2, a3);
+      xi2 = a0;
+      xi3 = a1;
+      xi4 = a2;
+      xi5 = a3;
+    } else {
+      box_muller_f(q0.c, q0.d, xi2, xi3);
+      box_muller_f(q1.a, q1.b, xi4, xi5);
+    }
+    const double eta = unif_d(q1.c);
+
+    // ---- position (binary64, stored rounded to T) ----
+    double x = x0 + (double)up0 * dt;
+    double y = y0 + (double)up1 * dt;
+    if (VISC) {
+      x = x + s2nu * (sdt * xi0);
+      y = y + s2nu * (sdt * xi1);
+    }
+    x = stor<T>(x);
+    y = stor<T>(y);
+
+    // ---- velocity: eq:velocity-prediction with G_ij and C0 of the record ----
+    const T d0 = up0 - r[R_U], d1 = up1 - r[R_V], d2 = up2 - r[R_W];
+    T un0 = up0 + r[R_A0], un1 = up1 + r[R_A1], un2 = up2 + r[R_A2];
+    un0 = fmaT(r[R_G00], d0, fmaT(r[R_G01], d1, fmaT(r[R_G02], d2, un0)));
+    un1 = fmaT(r[R_G10], d0, fmaT(r[R_G11], d1, fmaT(r[R_G12], d2, un1)));
+    un2 = fmaT(r[R_G20], d0, fmaT(r[R_G21], d1, fmaT(r[R_G22], d2, un2)));
+    if (VISC) {
+      const T x0n = (T)xi0, x1n = (T)xi1;
+      un0 = fmaT(r[R_B00], x0n, fmaT(r[R_B01], x1n, un0));
+      un1 = fmaT(r[R_B10], x0n, fmaT(r[R_B11], x1n, un1));
+      un2 = fmaT(r[R_B20], x0n, fmaT(r[R_B21], x1n, un2));
+    }
+    const T sc = r[R_SC0];
+    un0 = fmaT(sc, xi2, un0);
+    un1 = fmaT(sc, xi3, un1);
+    un2 = fmaT(sc, xi4, un2);
+
+    // ---- frequency: eq:frequency-model, negative excursions folded back ----
+    const T omp = om > (T)0 ? om : (T)0;
+    T omn = om - r[R_WA] * (om - r[R_OM]) - r[R_WB] * om + r[R_WC] * sqrt(omp) * xi5;
+    if (omn < (T)0) {
+      omn = -omn;
+      c_clamp = 1;
+    }
+    // ---- scalar: eq:IEM ----
+    T psin = psi - r[R_MIX] * (psi - r[R_PHI]);
+
+    // ---- tracking: next-best-element walk (Ch.3, Sec. Particle tracking) ----
+    int32_t e = e0, found = -1, nrefl = 0;
+    double shx = 0.0, shy = 0.0;
+    // a non-finite position cannot be located: the particle is lost at once
+    const bool finite_pos = isfinite(x) && isfinite(y);
+    for (int it = 0; it < 64 && finite_pos; ++it) {
+      c_walk++;
+      const ElemGeo g = m.geo[e];
+      double lam[3];
+      edge_lambdas(g, x, y, lam);
+      if (lam[0] >= 0.0 && lam[1] >= 0.0 && lam[2] >= 0.0) {
+        found = e;
+        break;
+      }
+      int k = 0;
+      if (lam[1] < lam[k]) k = 1;
+      if (lam[2] < lam[k]) k = 2;
+      const int32_t nb = g.nb[k];
+      if (nb >= 0) {
+        e = nb;
+        continue;
+      }
+      const int32_t b = -(nb + 1);
+      const int32_t bt = m.btype[b];
+      if (bt == PDF_BC_PERIODIC) {
+        const double sx = m.bshift[2 * b], sy = m.bshift[2 * b + 1];
+        x = stor<T>(x + sx);
+        y = stor<T>(y + sy);
+        shx += sx;
+        shy += sy;
+        e = m.belem[m.bpart[b]];
+        c_per++;
+        continue;
+      }
+      const int ia = (k + 1) % 3, ib = (k + 2) % 3;
+      double xa = g.x[ia], ya = g.y[ia], xb = g.x[ib], yb = g.y[ib];
+      double dx = xb - xa, dy = yb - ya;
+      const double t = ((x - xa) * dx + (y - ya) * dy) / (dx * dx + dy * dy);
+      bool refl = (t >= 0.0 && t <= 1.0);
+      int32_t bw = b;
+      if (!refl) {
+        // past an end of this wall segment: outside the domain if the point
+        // lies directly behind another wall edge ending at that node
+        const int32_t cn = g.n[t < 0.0 ? ia : ib];
+        for (int32_t j = m.nwall_off[cn]; j < m.nwall_off[cn + 1] && !refl; ++j) {
+          const int32_t wdg = m.nwall[j];
+          if (wdg == b) continue;
+          const ElemGeo gw = m.geo[m.belem[wdg]];
+          const int kw = m.blocal[wdg];
+          const double wa = gw.x[(kw + 1) % 3], wya = gw.y[(kw + 1) % 3];
+          const double wdx = gw.x[(kw + 2) % 3] - wa, wdy = gw.y[(kw + 2) % 3] - wya;
+          const double tw = ((x - wa) * wdx + (y - wya) * wdy) / (wdx * wdx + wdy * wdy);
+          const double out = (x - wa) * wdy - (y - wya) * wdx;  // > 0 behind the wall line
+          if (tw >= 0.0 && tw <= 1.0 && out > 0.0) {
+            refl = true;
+            bw = wdg;
+            xa = wa;
+            ya = wya;
+            dx = wdx;
+            dy = wdy;
+          }
+        }
+      }
+      if (!refl) {
+        // in the domain beyond a concave corner: fall-back of Fig. corner
+        int32_t f = search_patch(m, e0, x, y);
+        if (f < 0) f = search_patch(m, e, x, y);
+        if (f >= 0) {
+          c_fall++;
+          found = f;
+          break;
+        }
+        f = locate_brute(m, x, y);
+        if (f >= 0) {
+          c_brute++;
+          found = f;
+          break;
+        }
+        refl = true;  // outside the domain beyond a convex corner
+      }
+      if (nrefl >= 8) break;
+      // perfect reflection across the wall line
+      const double len = sqrt(dx * dx + dy * dy);
+      const double nx = dy / len, ny = -dx / len;
+      const double dist = (x - xa) * nx + (y - ya) * ny;
+      x = stor<T>(x - 2.0 * dist * nx);
+      y = stor<T>(y - 2.0 * dist * ny);
+      c_refl++;
+      if (m.btype[bw] == PDF_BC_SLIP) {
+        const double vn = (double)un0 * nx + (double)un1 * ny;
+        un0 = (T)((double)un0 - 2.0 * vn * nx);
+        un1 = (T)((double)un1 - 2.0 * vn * ny);
+      } else {
+        noslip<T>(md, r, nx, ny, k0, k1, id, step, nrefl, un0, un1, un2, omn, c_gfail);
+      }
+      nrefl++;
+    }
+    if (found < 0) {
+      int32_t f = finite_pos ? search_patch(m, e0, x, y) : -1;
+      if (f < 0 && finite_pos) f = locate_brute(m, x, y);
+      if (f >= 0) {
+        c_brute++;
+        found = f;
+      } else {
+        c_lost++;
+        x = x0;
+        y = y0;
+        found = e0;
+      }
+    }
+
+    // ---- no-slip trajectory (b): eq:fw and eq:exp-wall-condition ----
+    if (WALLB && nrefl == 0) {
+      int32_t best = -1;
+      double bd = 0.0;
+      for (int32_t j = m.w_off[found]; j < m.w_off[found + 1]; ++j) {
+        const int32_t b = m.w_list[j];
+        const ElemGeo g = m.geo[m.belem[b]];
+        const int kk = m.blocal[b];
+        const double xa = g.x[(kk + 1) % 3], ya = g.y[(kk + 1) % 3];
+        const double dx = g.x[(kk + 2) % 3] - xa, dy = g.y[(kk + 2) % 3] - ya;
+        double t = ((x - xa) * dx + (y - ya) * dy) / (dx * dx + dy * dy);
+        if (t < 0.0) t = 0.0;
+        if (t > 1.0) t = 1.0;
+        const double ex = x - (xa + t * dx), ey = y - (ya + t * dy);
+        const double d2 = ex * ex + ey * ey;
+        if (best < 0 || d2 < bd) {
+          best = b;
+          bd = d2;
+        }
+      }
+      if (best >= 0) {
+        const ElemGeo g = m.geo[m.belem[best]];
+        const int kk = m.blocal[best];
+        const double xa = g.x[(kk + 1) % 3], ya = g.y[(kk + 1) % 3];
+        const double dx = g.x[(kk + 2) % 3] - xa, dy = g.y[(kk + 2) % 3] - ya;
+        const double len = sqrt(dx * dx + dy * dy);
+        const double nx = dy / len, ny = -dx / len;
+        const double d1 = -((x - xa) * nx + (y - ya) * ny);
+        const double dd0 = -((x0 + shx - xa) * nx + (y0 + shy - ya) * ny);
+        if (dd0 > 0.0 && d1 >= 0.0) {
+          const double fw = exp(-dd0 * d1 / (md.nu * dt));
+          if (eta < fw) {
+            c_b++;
+            noslip<T>(md, r, nx, ny, k0, k1, id, step, 8, un0, un1, un2, omn, c_gfail);
+          }
+        }
+      }
+    }
+    // ---- continuous scalar source ----
+    if (md.src_r > 0.0) {
+      const double ddx = x - md.src_x, ddy = y - md.src_y;
+      if (ddx * ddx + ddy * ddy <= md.src_r * md.src_r) psin = (T)1;
+    }
+    if (!(isfinite((double)un0) && isfinite((double)un1) && isfinite((double)un2) &&
+          isfinite((double)omn) && isfinite((double)psin)))
+      c_nan = 1;
+
+    p.x[i] = (T)x;
+    p.y[i] = (T)y;
+    p.u[i] = un0;
+    p.v[i] = un1;
+    p.w[i] = un2;
+    p.om[i] = omn;
+    p.psi[i] = psin;
+    p.e[i] = found;
+    accumulate<T>(sums, rec, found, un0, un1, un2, omn, psin);
+  }
+  wave_count(&cnt[PDF_CNT_WALK_STEPS], c_walk);
+  wave_count(&cnt[PDF_CNT_FALLBACK], c_fall);
+  wave_count(&cnt[PDF_CNT_BRUTE], c_brute);
+  wave_count(&cnt[PDF_CNT_LOST], c_lost);
+  wave_count(&cnt[PDF_CNT_REFLECT], c_refl);
+  wave_count(&cnt[PDF_CNT_PERIODIC], c_per);
+  wave_count(&cnt[PDF_CNT_NOSLIP_B], c_b);
+  wave_count(&cnt[PDF_CNT_OMEGA_CLAMP], c_clamp);
+  wave_count(&cnt[PDF_CNT_GAMMA_FAIL], c_gfail);
+  wave_count(&cnt[PDF_CNT_NONFINITE], c_nan);
+}
+
+template <typename T>
+void launch_advance(hipStream_t s, const MeshDev &m, const ModelDev &md, PartDev<T> p, int64_t np,
+                    const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
+                    unsigned long long *cnt) {
+  const unsigned grid = (unsigned)((np + 255) / 256);
+  const bool visc = md.nu > 0.0;
+  const bool wallb = visc && md.wall_b;
+  const double sdt = sqrt(dt), s2nu = sqrt(2.0 * md.nu);
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  if (visc && wallb)
+    hipLaunchKernelGGL((k_advance<T, true, true>), dim3(grid), dim3(256), 0, s, m, md, p, np, rec,
+                       sums, k0, k1, step, dt, sdt, s2nu, cnt);
+  else if (visc)
+    hipLaunchKernelGGL((k_advance<T, true, false>), dim3(grid), dim3(256), 0, s, m, md, p, np, rec,
+                       sums, k0, k1, step, dt, sdt, s2nu, cnt);
+  else
+    hipLaunchKernelGGL((k_advance<T, false, false>), dim3(grid), dim3(256), 0, s, m, md, p, np, rec,
+                       sums, k0, k1, step, dt, sdt, s2nu, cnt);
+}
+
+#define INST(T)                                                                                  \
+  template void launch_seed<T>(hipStream_t, const MeshDev &, const ModelDev &, PartDev<T>, int32_t, \
+                               uint64_t, int32_t, double, double, double, const double *,         \
+                               const double *, const double *, unsigned long long *);            \
+  template void launch_elem_prep<T>(hipStream_t, const MeshDev &, const ModelDev &, const double *, \
+                                    const double *, const double *, double, T *);                \
+  template void launch_advance<T>(hipStream_t, const MeshDev &, const ModelDev &, PartDev<T>,       \
+                                  int64_t, const T *, double *, uint64_t, uint32_t, double,        \
+                                  unsigned long long *);                                         \
+  template void launch_accumulate<T>(hipStream_t, PartDev<T>, int64_t, const T *, double *);        \
+  template void launch_ref_from_sums<T>(hipStream_t, int32_t, const double *, T *);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace pdfk

@@ -1,0 +1,322 @@
+// Statistics kernels for gfx950: the two-pass particle-in-cell estimator
+// (Ch.3, Sec. Estimation of Eulerian statistics), FEM derivatives (Sec.
+// Derivatives), the local elliptic-relaxation tensor, and the counting-sort
+// reorder of particles by host element.
+//
+// Every nodal kernel is a gather over the linked list "elements surrounding
+// master node" (no atomics), so nodal results do not depend on launch order.
+#include <hip/hip_runtime.h>
+
+#include "pdf_internal.h"
+
+namespace pdfk {
+
+// element means and central second moments (1/N) from the shifted sums
+template <typename T>
+__global__ __launch_bounds__(256) void k_elem_moments(int32_t ne, const double *sums, const T *rec,
+                                                      double *emom) {
+  const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const double *s = sums + (size_t)e * NSUM;
+  const T *r = rec + (size_t)e * NREC;
+  double *o = emom + (size_t)e * 16;
+  const double N = s[0];
+  o[0] = N;
+  if (!(N > 0.0)) {
+    for (int f = 1; f < 16; ++f) o[f] = 0.0;
+    return;
+  }
+  double m1[5];
+  for (int f = 0; f < 5; ++f) {
+    m1[f] = s[1 + f] / N;
+    o[1 + f] = (double)r[f] + m1[f];
+  }
+  const int ca[10] = {0, 1, 2, 0, 0, 1, 4, 0, 1, 2};
+  const int cb[10] = {0, 1, 2, 1, 2, 2, 4, 4, 4, 4};
+  for (int c = 0; c < 10; ++c) o[6 + c] = s[6 + c] / N - m1[ca[c]] * m1[cb[c]];
+}
+
+template <typename T>
+void launch_elem_moments(hipStream_t s, int32_t ne, const double *sums, const T *rec, double *emom) {
+  hipLaunchKernelGGL(k_elem_moments<T>, dim3((ne + 255) / 256), dim3(256), 0, s, ne, sums, rec, emom);
+}
+
+// pass 2: node value = average over the surrounding elements holding particles;
+// nodes with none keep their previous value
+__global__ __launch_bounds__(256) void k_node_stats(MeshDev m, const double *emom, const double *prev,
+                                                    double *out, unsigned long long *cnt) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  int empty = 0;
+  if (t < m.n_masters) {
+    const int32_t n = m.masters[t];
+    const int nn = m.nn;
+    double acc[15];
+    for (int f = 0; f < 15; ++f) acc[f] = 0.0;
+    double sup = 0.0;
+    int c = 0;
+    for (int32_t i = m.m2e_off[n]; i < m.m2e_off[n + 1]; ++i) {
+      const double *o = emom + (size_t)m.m2e[i] * 16;
+      if (!(o[0] > 0.0)) continue;
+      c++;
+      sup += o[0];
+      for (int f = 0; f < 15; ++f) acc[f] += o[1 + f];
+    }
+    if (c > 0) {
+      for (int f = 0; f < 15; ++f) out[f * nn + n] = acc[f] / (double)c;
+    } else {
+      for (int f = 0; f < 15; ++f) out[f * nn + n] = prev[f * nn + n];
+      empty = 1;
+    }
+    out[24 * nn + n] = sup;
+  }
+  if (__ballot(empty) != 0) {
+    int v = empty;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&cnt[PDF_CNT_EMPTY_NODE], (unsigned long long)v);
+  }
+}
+
+void launch_node_stats(hipStream_t s, const MeshDev &m, const double *emom, const double *prev,
+                       double *out, unsigned long long *cnt) {
+  hipLaunchKernelGGL(k_node_stats, dim3((m.n_masters + 255) / 256), dim3(256), 0, s, m, emom, prev,
+                     out, cnt);
+}
+
+// first derivatives: eq:gradient in every surrounding element, averaged
+__global__ __launch_bounds__(256) void k_node_grad(MeshDev m, double *S) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.n_masters) return;
+  const int32_t n = m.masters[t];
+  const int nn = m.nn;
+  double g[6] = {0, 0, 0, 0, 0, 0};
+  int c = 0;
+  for (int32_t i = m.m2e_off[n]; i < m.m2e_off[n + 1]; ++i) {
+    const int32_t e = m.m2e[i];
+    const double *d = m.dN + 6 * (size_t)e;
+    c++;
+    for (int f = 0; f < 3; ++f)
+      for (int k = 0; k < 3; ++k) {
+        const double q = S[f * nn + m.mnode[3 * e + k]];
+        g[2 * f] += d[k] * q;
+        g[2 * f + 1] += d[3 + k] * q;
+      }
+  }
+  for (int f = 0; f < 6; ++f) S[(15 + f) * nn + n] = c ? g[f] / (double)c : 0.0;
+}
+
+// second derivatives: eq:gradient applied to the nodal first derivatives
+__global__ __launch_bounds__(256) void k_node_lap(MeshDev m, double *S) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.n_masters) return;
+  const int32_t n = m.masters[t];
+  const int nn = m.nn;
+  double l[3] = {0, 0, 0};
+  int c = 0;
+  for (int32_t i = m.m2e_off[n]; i < m.m2e_off[n + 1]; ++i) {
+    const int32_t e = m.m2e[i];
+    const double *d = m.dN + 6 * (size_t)e;
+    c++;
+    for (int f = 0; f < 3; ++f)
+      for (int k = 0; k < 3; ++k) {
+        const int32_t q = m.mnode[3 * e + k];
+        l[f] += d[k] * S[(15 + 2 * f) * nn + q] + d[3 + k] * S[(16 + 2 * f) * nn + q];
+      }
+  }
+  for (int f = 0; f < 3; ++f) S[(21 + f) * nn + n] = c ? l[f] / (double)c : 0.0;
+}
+
+__global__ void k_copy_slaves(MeshDev m, double *S, int nf) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.n_slaves) return;
+  const int32_t n = m.slaves[t], q = m.slave_master[t];
+  for (int f = 0; f < nf; ++f) S[f * m.nn + n] = S[f * m.nn + q];
+}
+
+void launch_node_derivs(hipStream_t s, const MeshDev &m, double *stats) {
+  const unsigned g = (m.n_masters + 255) / 256;
+  hipLaunchKernelGGL(k_node_grad, dim3(g), dim3(256), 0, s, m, stats);
+  hipLaunchKernelGGL(k_node_lap, dim3(g), dim3(256), 0, s, m, stats);
+  if (m.n_slaves > 0)
+    hipLaunchKernelGGL(k_copy_slaves, dim3((m.n_slaves + 255) / 256), dim3(256), 0, s, m, stats,
+                       PDF_NSTAT);
+}
+
+// Local elliptic-relaxation tensor: the right-hand side of
+// eq:elliptic-relaxation-Lagrangian (L -> 0) with H from eq:H, A_v and b_ij
+// (eq:bij), from the nodal k, <omega>, Reynolds stress and mean-velocity gradient.
+__global__ __launch_bounds__(256) void k_local_wp(MeshDev m, ModelDev md, const double *S, double *wp) {
+  const int32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= m.nn) return;
+  const int nn = m.nn;
+  const int32_t q = m.master[n];  // identified nodes use their master's statistics
+  double R[6];
+  for (int i = 0; i < 6; ++i) R[i] = S[(5 + i) * nn + q];
+  double k = 0.5 * (R[0] + R[1] + R[2]);
+  if (!(k > md.k_floor)) k = md.k_floor;
+  const double om = S[3 * nn + q];
+  const double Sg[3][3] = {{S[15 * nn + q], S[16 * nn + q], 0.0},
+                           {S[17 * nn + q], S[18 * nn + q], 0.0},
+                           {S[19 * nn + q], S[20 * nn + q], 0.0}};
+  const double det = R[0] * (R[1] * R[2] - R[5] * R[5]) - R[3] * (R[3] * R[2] - R[5] * R[4]) +
+                     R[4] * (R[3] * R[5] - R[1] * R[4]);
+  const double k23 = 2.0 / 3.0 * k;
+  double Av = md.Cv * det / (k23 * k23 * k23);
+  if (Av > 1.0) Av = 1.0;
+  const int sidx[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+  double b[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) b[i][j] = R[sidx[i][j]] / (2.0 * k) - ((i == j) ? 1.0 / 3.0 : 0.0);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double h = (md.C2 * Av + md.gamma5 / 3.0) * Sg[i][j] - md.gamma5 / 3.0 * Sg[j][i];
+      for (int l = 0; l < 3; ++l) h += md.gamma5 * b[i][l] * Sg[l][j] - md.gamma5 * b[i][l] * Sg[j][l];
+      wp[(3 * i + j) * nn + n] = k * h + ((i == j) ? 0.5 * (1.0 - md.C1) * k * om : 0.0);
+    }
+}
+
+void launch_local_wp(hipStream_t s, const MeshDev &m, const ModelDev &md, const double *stats,
+                     double *wp) {
+  hipLaunchKernelGGL(k_local_wp, dim3((m.nn + 255) / 256), dim3(256), 0, s, m, md, stats, wp);
+}
+
+// element statistics out of the AoS buffer into [16][ne]
+__global__ void k_export_elem(int32_t ne, const double *emom, double *out) {
+  const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  for (int f = 0; f < 16; ++f) out[(size_t)f * ne + e] = emom[(size_t)e * 16 + f];
+}
+
+void launch_export_elem(hipStream_t s, int32_t ne, const double *emom, double *out) {
+  hipLaunchKernelGGL(k_export_elem, dim3((ne + 255) / 256), dim3(256), 0, s, ne, emom, out);
+}
+
+// ---------------------------------------------------------------------------
+// Reorder: counting sort of the particle SoA by host element.  Counts are the
+// element sums' particle counts of the last accumulation.
+// ---------------------------------------------------------------------------
+constexpr int SCAN_B = 1024;
+
+__global__ __launch_bounds__(SCAN_B) void k_scan_blocks(int32_t ne, const double *sums, int32_t *offs,
+                                                        int32_t *blocksums) {
+  __shared__ int32_t sh[SCAN_B];
+  const int32_t i = blockIdx.x * SCAN_B + threadIdx.x;
+  const int32_t v = (i < ne) ? (int32_t)sums[(size_t)i * NSUM] : 0;
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < SCAN_B; off <<= 1) {
+    const int32_t a = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += a;
+    __syncthreads();
+  }
+  if (i < ne) offs[i] = sh[threadIdx.x] - v;  // exclusive within the block
+  if (threadIdx.x == SCAN_B - 1) blocksums[blockIdx.x] = sh[threadIdx.x];
+}
+
+__global__ __launch_bounds__(SCAN_B) void k_scan_top(int32_t nblocks, int32_t *blocksums) {
+  __shared__ int32_t sh[SCAN_B];
+  __shared__ int32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int32_t base = 0; base < nblocks; base += SCAN_B) {
+    const int32_t i = base + threadIdx.x;
+    const int32_t v = (i < nblocks) ? blocksums[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_B; off <<= 1) {
+      const int32_t a = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += a;
+      __syncthreads();
+    }
+    if (i < nblocks) blocksums[i] = carry + sh[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == SCAN_B - 1) carry += sh[threadIdx.x];
+    __syncthreads();
+  }
+}
+
+__global__ void k_scan_add(int32_t ne, int32_t *offs, const int32_t *blocksums, int32_t *cursor) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ne) return;
+  offs[i] += blocksums[i / SCAN_B];
+  cursor[i] = 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter(int64_t np, const int32_t *offs, int32_t *cursor,
+                                                 PartDev<T> src, PartDev<T> dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const int32_t e = src.e[i];
+  const int64_t d = (int64_t)offs[e] + atomicAdd(&cursor[e], 1);
+  dst.x[d] = src.x[i];
+  dst.y[d] = src.y[i];
+  dst.u[d] = src.u[i];
+  dst.v[d] = src.v[i];
+  dst.w[d] = src.w[i];
+  dst.om[d] = src.om[i];
+  dst.psi[d] = src.psi[i];
+  dst.e[d] = e;
+  dst.id[d] = src.id[i];
+}
+
+template <typename T>
+void launch_reorder(hipStream_t s, int32_t ne, int64_t np, const double *sums, int32_t *offs,
+                    int32_t *cursor, int32_t *blocksums, PartDev<T> src, PartDev<T> dst) {
+  const int32_t nb = (ne + SCAN_B - 1) / SCAN_B;
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(SCAN_B), 0, s, ne, sums, offs, blocksums);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_B), 0, s, nb, blocksums);
+  hipLaunchKernelGGL(k_scan_add, dim3((ne + 255) / 256), dim3(256), 0, s, ne, offs, blocksums, cursor);
+  hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, np, offs,
+                     cursor, src, dst);
+}
+
+// particle state <-> double [7][n]
+template <typename T>
+__global__ void k_pack(PartDev<T> p, int64_t np, double *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  out[0 * np + i] = (double)p.x[i];
+  out[1 * np + i] = (double)p.y[i];
+  out[2 * np + i] = (double)p.u[i];
+  out[3 * np + i] = (double)p.v[i];
+  out[4 * np + i] = (double)p.w[i];
+  out[5 * np + i] = (double)p.om[i];
+  out[6 * np + i] = (double)p.psi[i];
+}
+
+template <typename T>
+__global__ void k_unpack(PartDev<T> p, int64_t np, const double *in) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  p.x[i] = (T)in[0 * np + i];
+  p.y[i] = (T)in[1 * np + i];
+  p.u[i] = (T)in[2 * np + i];
+  p.v[i] = (T)in[3 * np + i];
+  p.w[i] = (T)in[4 * np + i];
+  p.om[i] = (T)in[5 * np + i];
+  p.psi[i] = (T)in[6 * np + i];
+}
+
+template <typename T>
+void launch_pack_state(hipStream_t s, PartDev<T> p, int64_t np, double *out) {
+  hipLaunchKernelGGL(k_pack<T>, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, p, np, out);
+}
+template <typename T>
+void launch_unpack_state(hipStream_t s, PartDev<T> p, int64_t np, const double *in) {
+  hipLaunchKernelGGL(k_unpack<T>, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, p, np, in);
+}
+
+#define INST(T)                                                                                  \
+  template void launch_elem_moments<T>(hipStream_t, int32_t, const double *, const T *, double *); \
+  template void launch_reorder<T>(hipStream_t, int32_t, int64_t, const double *, int32_t *,         \
+                                  int32_t *, int32_t *, PartDev<T>, PartDev<T>);                  \
+  template void launch_pack_state<T>(hipStream_t, PartDev<T>, int64_t, double *);                  \
+  template void launch_unpack_state<T>(hipStream_t, PartDev<T>, int64_t, const double *);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace pdfk

@@ -1,0 +1,103 @@
+// Internal declarations shared by the host side of the C ABI (capi.hip) and
+// the kernel translation units (k_particles.hip, k_stats.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/pdf.h"
+
+namespace pdfk {
+
+// Element geometry for the walk: node coordinates, global node ids and
+// neighbours (>= 0 element, < 0 boundary edge -(b+1)).  72 bytes.
+struct ElemGeo {
+  double x[3], y[3];
+  int32_t n[3];
+  int32_t nb[3];
+};
+
+// Element record: element-average statistics and the pre-multiplied
+// coefficients of one Euler-Maruyama step (rebuilt every step).
+enum RecField {
+  R_U = 0, R_V, R_W, R_OM, R_PHI,       // reference means (element average of nodal means)
+  R_A0, R_A1, R_A2,                     // (-dP/dx_i/rho + 2 nu lap U_i) dt
+  R_G00, R_G01, R_G02, R_G10, R_G11, R_G12, R_G20, R_G21, R_G22,  // G_ij dt
+  R_SC0,                                // sqrt(C0 eps dt)
+  R_B00, R_B01, R_B10, R_B11, R_B20, R_B21,  // sqrt(2 nu dt) dU_i/dx_j
+  R_WA, R_WB, R_WC,                     // C3<om>dt, S_om<om>dt, sqrt(2 C3 C4 <om>^2 dt)
+  R_MIX,                                // dt / t_m
+  R_GSX, R_GSY,                         // gradient of sqrt(2k) (wall frequency)
+  R_N                                   // = 30
+};
+constexpr int NREC = 32;
+
+// Element sums: count, 5 shifted first moments, 10 shifted second moments.
+constexpr int NSUM = 16;
+
+struct MeshDev {
+  int32_t ne, nn, nb;
+  const ElemGeo *geo;
+  const int32_t *mnode;     // [3*ne] master node of each element node
+  const double *dN;         // [6*ne] dN_k/dx (k=0..2), dN_k/dy (k=0..2)
+  const int32_t *btype, *bpart, *belem, *blocal;
+  const double *bshift;     // [2*nb]
+  const int32_t *n2e_off, *n2e;  // node -> elements
+  const int32_t *m2e_off, *m2e;  // master node -> elements (statistics)
+  const int32_t *w_off, *w_list; // element -> nearby no-slip wall edges
+  const int32_t *nwall_off, *nwall; // node -> wall (slip/no-slip) edges ending at it
+  const int32_t *master;    // [nn] periodic identification
+  const int32_t *masters;   // list of master nodes
+  int32_t n_masters;
+  const int32_t *slaves;    // list of identified (non-master) nodes
+  const int32_t *slave_master;
+  int32_t n_slaves;
+};
+
+template <typename T>
+struct PartDev {
+  T *x, *y, *u, *v, *w, *om, *psi;
+  int32_t *e;
+  uint32_t *id;
+};
+
+struct ModelDev {
+  int32_t model, wp_source, omega_source, tm_mode, wall_b;
+  double C0, C1, C2, C3, C4, CT, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
+  double src_x, src_y, src_r;
+};
+
+// ---- launchers (defined in the kernel translation units) ----
+template <typename T>
+void launch_seed(hipStream_t s, const MeshDev &m, const ModelDev &md, PartDev<T> p, int32_t ppe,
+                 uint64_t seed, int32_t psi_mode, double a, double b, double c, const double *U0,
+                 const double *R0, const double *Om0, unsigned long long *cnt);
+template <typename T>
+void launch_elem_prep(hipStream_t s, const MeshDev &m, const ModelDev &md, const double *stats,
+                      const double *wp, const double *gradp, double dt, T *rec);
+template <typename T>
+void launch_advance(hipStream_t s, const MeshDev &m, const ModelDev &md, PartDev<T> p, int64_t np,
+                    const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
+                    unsigned long long *cnt);
+template <typename T>
+void launch_accumulate(hipStream_t s, PartDev<T> p, int64_t np, const T *rec, double *sums);
+template <typename T>
+void launch_ref_from_sums(hipStream_t s, int32_t ne, const double *sums, T *rec);
+template <typename T>
+void launch_elem_moments(hipStream_t s, int32_t ne, const double *sums, const T *rec, double *emom);
+void launch_node_stats(hipStream_t s, const MeshDev &m, const double *emom, const double *prev,
+                       double *out, unsigned long long *cnt);
+void launch_node_derivs(hipStream_t s, const MeshDev &m, double *stats);
+void launch_local_wp(hipStream_t s, const MeshDev &m, const ModelDev &md, const double *stats,
+                     double *wp);
+void launch_export_elem(hipStream_t s, int32_t ne, const double *emom, double *out);
+template <typename T>
+void launch_reorder(hipStream_t s, int32_t ne, int64_t np, const double *sums, int32_t *offs,
+                    int32_t *cursor, int32_t *blocksums, PartDev<T> src, PartDev<T> dst);
+template <typename T>
+void launch_pack_state(hipStream_t s, PartDev<T> p, int64_t np, double *out);
+template <typename T>
+void launch_unpack_state(hipStream_t s, PartDev<T> p, int64_t np, const double *in);
+
+}  // namespace pdfk

@@ -1,0 +1,202 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on
+the same seeded inputs.
+
+FP64 runs are compared as whole trajectories: element indices bit-exact,
+particle state and nodal statistics within 1e-12 (relative with the per-
+quantity scale of tests/parity.py).  FP32 runs are compared one step at a
+time from the common seeded state (the oracle stores the state rounded to
+binary32 exactly where the GPU does): element indices bit-exact, floats
+within 1e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import configs as CF
+from synth import meshes as M
+from tests.parity import compare_state, compare_stats
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1006_0720_amd import _lib
+    return _lib
+
+
+def _pair(L, w, reorder_every=0):
+    from paper_1006_0720_amd.runner import workload_context
+
+    print(f"[parity] {w.name} np={w.n_particles} prec={w.precision}", flush=True)
+    ctx = workload_context(w, reorder_every=reorder_every)
+    o = O.Oracle(w.mesh, w.params, store_fp32=(w.precision == "f32"), gradp=w.gradp, wp=w.wp)
+    o.seed(w.seed)
+    return ctx, o
+
+
+def _check(ctx, o, w, rtol, what, stats_rtol=None):
+    st, el, pid = ctx.particles()
+    assert np.array_equal(pid, o.id)
+    assert np.array_equal(el, o.elem), f"{what}: {(el != o.elem).sum()} element mismatches"
+    errs = compare_state(st, o.state, w.mesh, rtol, what)
+    g = ctx.stats()
+    serr = compare_stats(g, o.stats, stats_rtol or rtol, what=what)
+    return errs, serr
+
+
+def test_seed_parity_fp64(L):
+    w = CF.periodic_square()
+    ctx, o = _pair(L, w)
+    st, el, pid = ctx.particles()
+    # positions are computed with identical IEEE operations: bit-exact
+    assert np.array_equal(st[0], o.state[0]) and np.array_equal(st[1], o.state[1])
+    assert np.array_equal(st[6], o.state[6])
+    _check(ctx, o, w, 1e-12, "seed")
+    ctx.close()
+
+
+@pytest.mark.parametrize("reorder", [0, 4])
+def test_trajectory_parity_fp64_periodic_square(L, reorder):
+    """Workload 1 at full size: 2048 elements, 102400 particles, 100 steps."""
+    w = CF.periodic_square()
+    ctx, o = _pair(L, w, reorder_every=reorder)
+    for chunk in range(4):
+        ctx.advance(25, w.dt)
+        o.run(w.dt, 25)
+        _check(ctx, o, w, 1e-12, f"step {25 * (chunk + 1)}")
+    c = ctx.counters()
+    oc = o.counter_dict()
+    assert c["lost"] == 0 and oc["lost"] == 0
+    for k in ("walk_steps", "periodic", "omega_clamp"):
+        assert c[k] == oc[k], (k, c[k], oc[k])
+    ctx.close()
+
+
+def _small_channel(precision="f64", ppe=30, steps=30, nx=20, nh=8, seed=0):
+    w = CF.channel(nx=nx, n_half=nh, ppe=ppe, steps=steps, precision=precision, seed=seed)
+    return w
+
+
+def test_trajectory_parity_fp64_channel_glm_walls(L):
+    """Generalized Langevin model with the local elliptic-relaxation tensor,
+    nu > 0, no-slip walls with trajectory (b) and gamma wall frequencies."""
+    w = _small_channel("f64")
+    ctx, o = _pair(L, w)
+    for chunk in range(3):
+        ctx.advance(10, w.dt)
+        o.run(w.dt, 10)
+        _check(ctx, o, w, 1e-12, f"channel step {10 * (chunk + 1)}")
+    c, oc = ctx.counters(), o.counter_dict()
+    for k in ("walk_steps", "reflect", "noslip_b", "periodic", "gamma_fail", "lost"):
+        assert c[k] == oc[k], (k, c[k], oc[k])
+    assert oc["reflect"] > 0 and oc["noslip_b"] > 0
+    ctx.close()
+
+
+def test_trajectory_parity_fp64_canyon_corners(L):
+    """Canyon geometry: block corners (fall-back searches), slip top, no-slip
+    floor and blocks, continuous scalar source."""
+    mesh = M.canyon(3000, 0.15, 2)
+    w = CF.canyon(mesh=mesh, ppe=20, precision="f64", steps=30)
+    ctx, o = _pair(L, w)
+    for chunk in range(3):
+        ctx.advance(10, w.dt)
+        o.run(w.dt, 10)
+        _check(ctx, o, w, 1e-12, f"canyon step {10 * (chunk + 1)}")
+    c, oc = ctx.counters(), o.counter_dict()
+    for k in ("walk_steps", "reflect", "fallback", "brute", "noslip_b", "lost"):
+        assert c[k] == oc[k], (k, c[k], oc[k])
+    ctx.close()
+
+
+def test_frozen_glm_input_wp_fp64(L):
+    """Frozen statistics and an input wp field (PDF_WP_INPUT)."""
+    w = _small_channel("f64", ppe=20)
+    nn = w.mesh.n_nodes
+    rng = np.random.default_rng(0)
+    wp = np.zeros((9, nn))
+    wp[0] = wp[4] = wp[8] = -0.4 + 0.05 * rng.standard_normal(nn)
+    wp[1] = wp[3] = 0.02 * rng.standard_normal(nn)
+    w.params = dict(w.params, wp_source=CF.WP_INPUT, frozen=1)
+    w.wp = wp
+    ctx, o = _pair(L, w)
+    fz = CF.frozen_stats_for(w.mesh, U=(5.0, 0.0, 0.0), R_diag=(1.0, 0.5, 0.7), Om=3.0, Phi=0.2)
+    ctx.set_nodal_field(L.FIELD_STATS, fz)
+    o.set_stats(fz)
+    ctx.advance(10, w.dt)
+    o.run(w.dt, 10)
+    st, el, pid = ctx.particles()
+    assert np.array_equal(el, o.elem)
+    compare_state(st, o.state, w.mesh, 1e-12, "frozen GLM")
+    compare_stats(ctx.stats(), o.est, 1e-12, what="frozen GLM estimate")
+    ctx.close()
+
+
+def test_kernel_parity_fp32_channel(L):
+    """FP32 state: one step from the common seeded state."""
+    w = _small_channel("f32", ppe=60, nx=30, nh=10)
+    ctx, o = _pair(L, w)
+    st, el, pid = ctx.particles()
+    assert np.array_equal(el, o.elem)
+    compare_state(st, o.state, w.mesh, 1e-6, "fp32 seed")
+    compare_stats(ctx.stats(), o.stats, 1e-5, what="fp32 seed stats")
+    ctx.advance(1, w.dt)
+    o.step(w.dt)
+    st, el, pid = ctx.particles()
+    assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
+    compare_state(st, o.state, w.mesh, 1e-5, "fp32 step")
+    compare_stats(ctx.stats(), o.stats, 1e-5, what="fp32 step stats")
+    ctx.close()
+
+
+def test_kernel_parity_fp32_canyon_full_size_sampled(L):
+    """Street-canyon workload at full size (~200k elements, 50 per element,
+    ~10M particles): seeded state and nodal statistics compared in full, one
+    step compared on a 1% particle sample advanced by the oracle from the
+    same state and statistics."""
+    w = CF.canyon()
+    ctx, o = _pair(L, w)
+    st, el, pid = ctx.particles()
+    assert np.array_equal(el, o.elem)
+    compare_state(st, o.state, w.mesh, 1e-6, "canyon fp32 seed")
+    compare_stats(ctx.stats(), o.stats, 1e-5, what="canyon fp32 seed stats")
+    ctx.advance(1, w.dt)
+    mask = np.zeros(o.state.shape[1], np.uint8)
+    mask[np.random.default_rng(0).choice(mask.size, mask.size // 100, replace=False)] = 1
+    o.step(w.dt, mask=mask)
+    st, el, pid = ctx.particles()
+    sel = mask.astype(bool)
+    assert np.array_equal(el[sel], o.elem[sel])
+    compare_state(st[:, sel], o.state[:, sel], w.mesh, 1e-5, "canyon fp32 step (sample)")
+    c = ctx.counters()
+    assert c["lost"] == 0 and c["nonfinite"] == 0
+    # particle count conservation: element counts add up to N_p
+    _, elst = ctx.stats(elem=True)
+    assert elst[0].sum() == w.n_particles
+    ctx.close()
+
+
+def test_gpu_ou_stationary_variance(L):
+    """The closed-form OU limit on the GPU (frozen simplified Langevin model)."""
+    mesh = M.periodic_square(16)
+    w = CF.periodic_square(n=16, ppe=200, frozen=1)
+    from paper_1006_0720_amd.runner import workload_context
+    ctx = workload_context(w)
+    fz = CF.frozen_stats_for(mesh, U=(1.0, 0.0, 0.0), R_diag=(2 / 3,) * 3, Om=1.0, Phi=0.5)
+    ctx.set_nodal_field(L.FIELD_STATS, fz)
+    dt = 0.01
+    ctx.advance(200, dt)
+    v = []
+    for _ in range(5):
+        ctx.advance(50, dt)
+        st, _, _ = ctx.particles(sort_by_id=False)
+        v.append(st[2:5].var(axis=1).mean())
+    G = -(0.5 + 0.75 * 2.1)
+    expect = 2.1 / (-2 * G - G * G * dt)
+    assert abs(np.mean(v) - expect) / expect < 0.004
+    ctx.close()
