@@ -750,23 +750,28 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
       double t = ((x - xa) * dx + (y - ya) * dy) / (dx * dx + dy * dy);
       int reflect = (t >= 0.0 && t <= 1.0);
       if (!reflect) {
-        /* past an end of this wall segment: the point is outside the domain if
-         * it lies directly behind another wall edge ending at that node */
+        /* past the end node c of this wall segment.  With the boundary walked
+         * with the domain on its left, the corner at c is convex (or straight)
+         * when the boundary turns left there: the point, being behind this
+         * wall's line, is then outside the domain.  At a reflex corner it is
+         * outside only if it is also behind the other wall ending at c. */
         int32_t c = m->en[3 * e + (t < 0.0 ? (k + 1) % 3 : (k + 2) % 3)];
-        for (int32_t j = m->nwall_off[c]; j < m->nwall_off[c + 1] && !reflect; ++j) {
-          int32_t w = m->nwall[j];
-          if (w == b) continue;
+        int32_t w = -1;
+        for (int32_t j = m->nwall_off[c]; j < m->nwall_off[c + 1]; ++j)
+          if (m->nwall[j] != b) {
+            w = m->nwall[j];
+            break;
+          }
+        if (w < 0) {
+          reflect = 1; /* the wall ends at a periodic or open boundary */
+        } else {
           double wa, wya, wb, wyb;
           edge_geom(m, m->be[w], m->bl[w], &wa, &wya, &wb, &wyb);
           double wdx = wb - wa, wdy = wyb - wya;
-          double tw = ((x - wa) * wdx + (y - wya) * wdy) / (wdx * wdx + wdy * wdy);
-          double out = (x - wa) * wdy - (y - wya) * wdx; /* > 0 behind the wall line */
-          if (tw >= 0.0 && tw <= 1.0 && out > 0.0) {
-            reflect = 1;
-            b = w;
-            xa = wa; ya = wya; xb = wb; yb = wyb;
-            dx = wdx; dy = wdy;
-          }
+          /* incoming and outgoing boundary directions at c */
+          double turn = (t < 0.0) ? (wdx * dy - wdy * dx) : (dx * wdy - dy * wdx);
+          double behind_w = (x - wa) * wdy - (y - wya) * wdx;
+          if (turn >= 0.0 || behind_w > 0.0) reflect = 1;
         }
       }
       if (!reflect) {
@@ -778,13 +783,13 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
           found = f;
           break;
         }
+        if (cnt) cnt[OR_CNT_BRUTE]++;
         f = or_locate_brute(m, x, y);
         if (f >= 0) {
-          if (cnt) cnt[OR_CNT_BRUTE]++;
           found = f;
           break;
         }
-        reflect = 1; /* outside the domain beyond a convex corner */
+        reflect = 1;
       }
       if (!reflect || nrefl >= 8) break;
       /* perfect reflection across the wall line */
@@ -805,9 +810,11 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
     }
     if (found < 0) {
       int32_t f = finite_pos ? search_patch(m, e0, x, y) : -1;
-      if (f < 0 && finite_pos) f = or_locate_brute(m, x, y);
-      if (f >= 0) {
+      if (f < 0 && finite_pos) {
         if (cnt) cnt[OR_CNT_BRUTE]++;
+        f = or_locate_brute(m, x, y);
+      }
+      if (f >= 0) {
         found = f;
       } else {
         /* lost: the particle keeps its old position and host */

@@ -68,6 +68,12 @@ __device__ int32_t locate_brute(const MeshDev &m, double px, double py) {
   return -1;
 }
 
+// a[k] for k in {0,1,2} without dynamic indexing (keeps the arrays in registers)
+template <typename V>
+__device__ __forceinline__ V sel3(const V (&a)[3], int k) {
+  return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]);
+}
+
 // wave-wide sum of a per-lane count followed by one atomic per wave
 __device__ __forceinline__ void wave_count(unsigned long long *dst, int v) {
   if (__ballot(v != 0) == 0) return;
@@ -262,45 +268,99 @@ void launch_elem_prep(hipStream_t s, const MeshDev &m, const ModelDev &md, const
 }
 
 // ---------------------------------------------------------------------------
-// Accumulation of element sums about the element's reference means
+// Accumulation of element sums about the element's reference means.
+//
+// Each workgroup owns a contiguous chunk of particles (sorted by host element
+// at the last reorder) and accumulates their contributions in an LDS table
+// keyed by element (open addressing).  The table is flushed to the global
+// FP64 sums with one atomic per value per element and workgroup, so a
+// particle costs LDS atomics instead of contended global atomics.  A full
+// table (never expected at the chunk sizes used) falls back to global atomics.
 // ---------------------------------------------------------------------------
+constexpr int TAB = 256;  // LDS table slots per workgroup (power of two)
+constexpr int WG = 256;   // threads per workgroup of the particle kernels
+constexpr int PPT = 8;    // particles per thread: chunk of WG*PPT particles
+
+struct SumTable {
+  int32_t key[TAB];
+  uint32_t n[TAB];
+  double acc[15][TAB];
+};
+
+__device__ __forceinline__ void table_init(SumTable &t) {
+  for (int s = threadIdx.x; s < TAB; s += blockDim.x) {
+    t.key[s] = -1;
+    t.n[s] = 0u;
+#pragma unroll
+    for (int f = 0; f < 15; ++f) t.acc[f][s] = 0.0;
+  }
+}
+
+__device__ __forceinline__ int table_slot(SumTable &t, int32_t e) {
+  uint32_t h = ((uint32_t)e * 2654435761u) >> 24;
+  for (int probe = 0; probe < 64; ++probe) {
+    const int32_t k = __hip_atomic_load(&t.key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (k == e) return (int)h;
+    if (k == -1) {
+      const int32_t old = atomicCAS(&t.key[h], -1, e);
+      if (old == -1 || old == e) return (int)h;
+    }
+    h = (h + 1u) & (uint32_t)(TAB - 1);
+  }
+  return -1;
+}
+
 template <typename T>
-__device__ __forceinline__ void accumulate(double *sums, const T *rec, int32_t e, T u, T v, T w, T om,
-                                           T psi) {
+__device__ __forceinline__ void table_add(SumTable &t, double *sums, const T *rec, int32_t e, T u, T v,
+                                          T w, T om, T psi) {
   const T *r = rec + (size_t)e * NREC;
   const double q0 = (double)u - (double)r[R_U], q1 = (double)v - (double)r[R_V],
                q2 = (double)w - (double)r[R_W], q3 = (double)om - (double)r[R_OM],
                q4 = (double)psi - (double)r[R_PHI];
-  double *s = sums + (size_t)e * NSUM;
-  unsafeAtomicAdd(&s[0], 1.0);
-  unsafeAtomicAdd(&s[1], q0);
-  unsafeAtomicAdd(&s[2], q1);
-  unsafeAtomicAdd(&s[3], q2);
-  unsafeAtomicAdd(&s[4], q3);
-  unsafeAtomicAdd(&s[5], q4);
-  unsafeAtomicAdd(&s[6], q0 * q0);
-  unsafeAtomicAdd(&s[7], q1 * q1);
-  unsafeAtomicAdd(&s[8], q2 * q2);
-  unsafeAtomicAdd(&s[9], q0 * q1);
-  unsafeAtomicAdd(&s[10], q0 * q2);
-  unsafeAtomicAdd(&s[11], q1 * q2);
-  unsafeAtomicAdd(&s[12], q4 * q4);
-  unsafeAtomicAdd(&s[13], q0 * q4);
-  unsafeAtomicAdd(&s[14], q1 * q4);
-  unsafeAtomicAdd(&s[15], q2 * q4);
+  const double val[15] = {q0,      q1,      q2,      q3,      q4,      q0 * q0, q1 * q1, q2 * q2,
+                          q0 * q1, q0 * q2, q1 * q2, q4 * q4, q0 * q4, q1 * q4, q2 * q4};
+  const int s = table_slot(t, e);
+  if (s >= 0) {
+    atomicAdd(&t.n[s], 1u);
+#pragma unroll
+    for (int f = 0; f < 15; ++f) unsafeAtomicAdd(&t.acc[f][s], val[f]);
+  } else {
+    double *g = sums + (size_t)e * NSUM;
+    unsafeAtomicAdd(&g[0], 1.0);
+#pragma unroll
+    for (int f = 0; f < 15; ++f) unsafeAtomicAdd(&g[1 + f], val[f]);
+  }
+}
+
+__device__ __forceinline__ void table_flush(SumTable &t, double *sums) {
+  __syncthreads();
+  for (int s = threadIdx.x; s < TAB; s += blockDim.x) {
+    const int32_t e = t.key[s];
+    if (e < 0) continue;
+    double *g = sums + (size_t)e * NSUM;
+    unsafeAtomicAdd(&g[0], (double)t.n[s]);
+#pragma unroll
+    for (int f = 0; f < 15; ++f) unsafeAtomicAdd(&g[1 + f], t.acc[f][s]);
+  }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_accumulate(PartDev<T> p, int64_t np, const T *rec, double *sums) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= np) return;
-  accumulate<T>(sums, rec, p.e[i], p.u[i], p.v[i], p.w[i], p.om[i], p.psi[i]);
+__global__ __launch_bounds__(WG) void k_accumulate(PartDev<T> p, int64_t np, const T *rec, double *sums) {
+  __shared__ SumTable tab;
+  table_init(tab);
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * (WG * PPT);
+  for (int j = 0; j < PPT; ++j) {
+    const int64_t i = base + (int64_t)j * WG + threadIdx.x;
+    if (i < np) table_add<T>(tab, sums, rec, p.e[i], p.u[i], p.v[i], p.w[i], p.om[i], p.psi[i]);
+  }
+  table_flush(tab, sums);
 }
 
 template <typename T>
 void launch_accumulate(hipStream_t s, PartDev<T> p, int64_t np, const T *rec, double *sums) {
-  hipLaunchKernelGGL(k_accumulate<T>, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, p, np,
-                     rec, sums);
+  hipLaunchKernelGGL(k_accumulate<T>, dim3((unsigned)((np + WG * PPT - 1) / (WG * PPT))), dim3(WG), 0,
+                     s, p, np, rec, sums);
 }
 
 // reference means from a first accumulation pass made with zero references
@@ -349,14 +409,19 @@ __device__ __forceinline__ void noslip(const ModelDev &md, const T *r, double nx
 //   -> store -> element sums of the new host.
 // ---------------------------------------------------------------------------
 template <typename T, bool VISC, bool WALLB>
-__global__ __launch_bounds__(256) void k_advance(MeshDev m, ModelDev md, PartDev<T> p, int64_t np,
-                                                 const T *__restrict__ rec, double *sums, uint32_t k0,
-                                                 uint32_t k1, uint32_t step, double dt, double sdt,
-                                                 double s2nu, unsigned long long *cnt) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(WG) void k_advance(MeshDev m, ModelDev md, PartDev<T> p, int64_t np,
+                                                const T *__restrict__ rec, double *sums, uint32_t k0,
+                                                uint32_t k1, uint32_t step, double dt, double sdt,
+                                                double s2nu, unsigned long long *cnt) {
+  __shared__ SumTable tab;
+  table_init(tab);
+  __syncthreads();
   int c_walk = 0, c_fall = 0, c_brute = 0, c_lost = 0, c_refl = 0, c_per = 0, c_b = 0, c_clamp = 0,
       c_gfail = 0, c_nan = 0;
-  if (i < np) {
+  const int64_t base = (int64_t)blockIdx.x * (WG * PPT);
+  for (int jj = 0; jj < PPT; ++jj) {
+    const int64_t i = base + (int64_t)jj * WG + threadIdx.x;
+    if (i >= np) continue;
     const int32_t e0 = p.e[i];
     const uint32_t id = p.id[i];
     const double x0 = (double)p.x[i], y0 = (double)p.y[i];
@@ -437,7 +502,7 @@ __global__ __launch_bounds__(256) void k_advance(MeshDev m, ModelDev md, PartDev
       int k = 0;
       if (lam[1] < lam[k]) k = 1;
       if (lam[2] < lam[k]) k = 2;
-      const int32_t nb = g.nb[k];
+      const int32_t nb = sel3(g.nb, k);
       if (nb >= 0) {
         e = nb;
         continue;
@@ -455,32 +520,32 @@ __global__ __launch_bounds__(256) void k_advance(MeshDev m, ModelDev md, PartDev
         continue;
       }
       const int ia = (k + 1) % 3, ib = (k + 2) % 3;
-      double xa = g.x[ia], ya = g.y[ia], xb = g.x[ib], yb = g.y[ib];
-      double dx = xb - xa, dy = yb - ya;
+      const double xa = sel3(g.x, ia), ya = sel3(g.y, ia);
+      const double dx = sel3(g.x, ib) - xa, dy = sel3(g.y, ib) - ya;
       const double t = ((x - xa) * dx + (y - ya) * dy) / (dx * dx + dy * dy);
       bool refl = (t >= 0.0 && t <= 1.0);
-      int32_t bw = b;
       if (!refl) {
-        // past an end of this wall segment: outside the domain if the point
-        // lies directly behind another wall edge ending at that node
-        const int32_t cn = g.n[t < 0.0 ? ia : ib];
-        for (int32_t j = m.nwall_off[cn]; j < m.nwall_off[cn + 1] && !refl; ++j) {
-          const int32_t wdg = m.nwall[j];
-          if (wdg == b) continue;
+        // past the end node c of this wall segment: with the boundary walked
+        // with the domain on its left, a left turn at c (convex or straight
+        // corner) puts the point, behind this wall's line, outside the domain;
+        // at a reflex corner it is outside only if also behind the other wall
+        const int32_t cn = sel3(g.n, t < 0.0 ? ia : ib);
+        int32_t wdg = -1;
+        for (int32_t j = m.nwall_off[cn]; j < m.nwall_off[cn + 1]; ++j)
+          if (m.nwall[j] != b) {
+            wdg = m.nwall[j];
+            break;
+          }
+        if (wdg < 0) {
+          refl = true;  // the wall ends at a periodic or open boundary
+        } else {
           const ElemGeo gw = m.geo[m.belem[wdg]];
           const int kw = m.blocal[wdg];
-          const double wa = gw.x[(kw + 1) % 3], wya = gw.y[(kw + 1) % 3];
-          const double wdx = gw.x[(kw + 2) % 3] - wa, wdy = gw.y[(kw + 2) % 3] - wya;
-          const double tw = ((x - wa) * wdx + (y - wya) * wdy) / (wdx * wdx + wdy * wdy);
-          const double out = (x - wa) * wdy - (y - wya) * wdx;  // > 0 behind the wall line
-          if (tw >= 0.0 && tw <= 1.0 && out > 0.0) {
-            refl = true;
-            bw = wdg;
-            xa = wa;
-            ya = wya;
-            dx = wdx;
-            dy = wdy;
-          }
+          const double wa = sel3(gw.x, (kw + 1) % 3), wya = sel3(gw.y, (kw + 1) % 3);
+          const double wdx = sel3(gw.x, (kw + 2) % 3) - wa, wdy = sel3(gw.y, (kw + 2) % 3) - wya;
+          const double turn = (t < 0.0) ? (wdx * dy - wdy * dx) : (dx * wdy - dy * wdx);
+          const double behind_w = (x - wa) * wdy - (y - wya) * wdx;
+          if (turn >= 0.0 || behind_w > 0.0) refl = true;
         }
       }
       if (!refl) {
@@ -492,13 +557,13 @@ __global__ __launch_bounds__(256) void k_advance(MeshDev m, ModelDev md, PartDev
           found = f;
           break;
         }
+        c_brute++;
         f = locate_brute(m, x, y);
         if (f >= 0) {
-          c_brute++;
           found = f;
           break;
         }
-        refl = true;  // outside the domain beyond a convex corner
+        refl = true;
       }
       if (nrefl >= 8) break;
       // perfect reflection across the wall line
@@ -508,7 +573,7 @@ __global__ __launch_bounds__(256) void k_advance(MeshDev m, ModelDev md, PartDev
       x = stor<T>(x - 2.0 * dist * nx);
       y = stor<T>(y - 2.0 * dist * ny);
       c_refl++;
-      if (m.btype[bw] == PDF_BC_SLIP) {
+      if (bt == PDF_BC_SLIP) {
         const double vn = (double)un0 * nx + (double)un1 * ny;
         un0 = (T)((double)un0 - 2.0 * vn * nx);
         un1 = (T)((double)un1 - 2.0 * vn * ny);
@@ -519,9 +584,11 @@ __global__ __launch_bounds__(256) void k_advance(MeshDev m, ModelDev md, PartDev
     }
     if (found < 0) {
       int32_t f = finite_pos ? search_patch(m, e0, x, y) : -1;
-      if (f < 0 && finite_pos) f = locate_brute(m, x, y);
-      if (f >= 0) {
+      if (f < 0 && finite_pos) {
         c_brute++;
+        f = locate_brute(m, x, y);
+      }
+      if (f >= 0) {
         found = f;
       } else {
         c_lost++;
@@ -539,8 +606,8 @@ __global__ __launch_bounds__(256) void k_advance(MeshDev m, ModelDev md, PartDev
         const int32_t b = m.w_list[j];
         const ElemGeo g = m.geo[m.belem[b]];
         const int kk = m.blocal[b];
-        const double xa = g.x[(kk + 1) % 3], ya = g.y[(kk + 1) % 3];
-        const double dx = g.x[(kk + 2) % 3] - xa, dy = g.y[(kk + 2) % 3] - ya;
+        const double xa = sel3(g.x, (kk + 1) % 3), ya = sel3(g.y, (kk + 1) % 3);
+        const double dx = sel3(g.x, (kk + 2) % 3) - xa, dy = sel3(g.y, (kk + 2) % 3) - ya;
         double t = ((x - xa) * dx + (y - ya) * dy) / (dx * dx + dy * dy);
         if (t < 0.0) t = 0.0;
         if (t > 1.0) t = 1.0;
@@ -554,8 +621,8 @@ __global__ __launch_bounds__(256) void k_advance(MeshDev m, ModelDev md, PartDev
       if (best >= 0) {
         const ElemGeo g = m.geo[m.belem[best]];
         const int kk = m.blocal[best];
-        const double xa = g.x[(kk + 1) % 3], ya = g.y[(kk + 1) % 3];
-        const double dx = g.x[(kk + 2) % 3] - xa, dy = g.y[(kk + 2) % 3] - ya;
+        const double xa = sel3(g.x, (kk + 1) % 3), ya = sel3(g.y, (kk + 1) % 3);
+        const double dx = sel3(g.x, (kk + 2) % 3) - xa, dy = sel3(g.y, (kk + 2) % 3) - ya;
         const double len = sqrt(dx * dx + dy * dy);
         const double nx = dy / len, ny = -dx / len;
         const double d1 = -((x - xa) * nx + (y - ya) * ny);
@@ -586,8 +653,9 @@ __global__ __launch_bounds__(256) void k_advance(MeshDev m, ModelDev md, PartDev
     p.om[i] = omn;
     p.psi[i] = psin;
     p.e[i] = found;
-    accumulate<T>(sums, rec, found, un0, un1, un2, omn, psin);
+    table_add<T>(tab, sums, rec, found, un0, un1, un2, omn, psin);
   }
+  table_flush(tab, sums);
   wave_count(&cnt[PDF_CNT_WALK_STEPS], c_walk);
   wave_count(&cnt[PDF_CNT_FALLBACK], c_fall);
   wave_count(&cnt[PDF_CNT_BRUTE], c_brute);
@@ -604,19 +672,19 @@ template <typename T>
 void launch_advance(hipStream_t s, const MeshDev &m, const ModelDev &md, PartDev<T> p, int64_t np,
                     const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
                     unsigned long long *cnt) {
-  const unsigned grid = (unsigned)((np + 255) / 256);
+  const unsigned grid = (unsigned)((np + WG * PPT - 1) / (WG * PPT));
   const bool visc = md.nu > 0.0;
   const bool wallb = visc && md.wall_b;
   const double sdt = sqrt(dt), s2nu = sqrt(2.0 * md.nu);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   if (visc && wallb)
-    hipLaunchKernelGGL((k_advance<T, true, true>), dim3(grid), dim3(256), 0, s, m, md, p, np, rec,
+    hipLaunchKernelGGL((k_advance<T, true, true>), dim3(grid), dim3(WG), 0, s, m, md, p, np, rec,
                        sums, k0, k1, step, dt, sdt, s2nu, cnt);
   else if (visc)
-    hipLaunchKernelGGL((k_advance<T, true, false>), dim3(grid), dim3(256), 0, s, m, md, p, np, rec,
+    hipLaunchKernelGGL((k_advance<T, true, false>), dim3(grid), dim3(WG), 0, s, m, md, p, np, rec,
                        sums, k0, k1, step, dt, sdt, s2nu, cnt);
   else
-    hipLaunchKernelGGL((k_advance<T, false, false>), dim3(grid), dim3(256), 0, s, m, md, p, np, rec,
+    hipLaunchKernelGGL((k_advance<T, false, false>), dim3(grid), dim3(WG), 0, s, m, md, p, np, rec,
                        sums, k0, k1, step, dt, sdt, s2nu, cnt);
 }
 

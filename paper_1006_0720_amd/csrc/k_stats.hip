@@ -244,22 +244,75 @@ __global__ void k_scan_add(int32_t ne, int32_t *offs, const int32_t *blocksums, 
   cursor[i] = 0;
 }
 
+// Scatter: each workgroup ranks its chunk's particles per element in an LDS
+// table (local ranks from LDS atomics), reserves one range per element and
+// workgroup with a single global atomic, then writes every particle to
+// offs[e] + range base + local rank.  Elements that do not fit in the table
+// fall back to one global atomic per particle.
+constexpr int SC_WG = 256, SC_PPT = 8, SC_TAB = 512;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_scatter(int64_t np, const int32_t *offs, int32_t *cursor,
-                                                 PartDev<T> src, PartDev<T> dst) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= np) return;
-  const int32_t e = src.e[i];
-  const int64_t d = (int64_t)offs[e] + atomicAdd(&cursor[e], 1);
-  dst.x[d] = src.x[i];
-  dst.y[d] = src.y[i];
-  dst.u[d] = src.u[i];
-  dst.v[d] = src.v[i];
-  dst.w[d] = src.w[i];
-  dst.om[d] = src.om[i];
-  dst.psi[d] = src.psi[i];
-  dst.e[d] = e;
-  dst.id[d] = src.id[i];
+__global__ __launch_bounds__(SC_WG) void k_scatter(int64_t np, const int32_t *offs, int32_t *cursor,
+                                                   PartDev<T> src, PartDev<T> dst) {
+  __shared__ int32_t key[SC_TAB];
+  __shared__ int32_t cntl[SC_TAB];
+  __shared__ int32_t basel[SC_TAB];
+  for (int s = threadIdx.x; s < SC_TAB; s += SC_WG) {
+    key[s] = -1;
+    cntl[s] = 0;
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * (SC_WG * SC_PPT);
+  int slot[SC_PPT], rank[SC_PPT];
+  int32_t el[SC_PPT];
+  for (int j = 0; j < SC_PPT; ++j) {
+    const int64_t i = base + (int64_t)j * SC_WG + threadIdx.x;
+    slot[j] = -1;
+    rank[j] = 0;
+    el[j] = -1;
+    if (i >= np) continue;
+    const int32_t e = src.e[i];
+    el[j] = e;
+    uint32_t h = ((uint32_t)e * 2654435761u) >> 23;  // 9 bits
+    for (int probe = 0; probe < 64; ++probe) {
+      const int32_t k = __hip_atomic_load(&key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (k == e) {
+        slot[j] = (int)h;
+        break;
+      }
+      if (k == -1) {
+        const int32_t old = atomicCAS(&key[h], -1, e);
+        if (old == -1 || old == e) {
+          slot[j] = (int)h;
+          break;
+        }
+      }
+      h = (h + 1u) & (uint32_t)(SC_TAB - 1);
+    }
+    if (slot[j] >= 0)
+      rank[j] = atomicAdd(&cntl[slot[j]], 1);
+    else
+      rank[j] = atomicAdd(&cursor[e], 1);  // global rank (overflow path)
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < SC_TAB; s += SC_WG)
+    if (key[s] >= 0) basel[s] = atomicAdd(&cursor[key[s]], cntl[s]);
+  __syncthreads();
+  for (int j = 0; j < SC_PPT; ++j) {
+    const int64_t i = base + (int64_t)j * SC_WG + threadIdx.x;
+    if (i >= np) continue;
+    const int32_t e = el[j];
+    const int64_t d = (int64_t)offs[e] + (slot[j] >= 0 ? basel[slot[j]] + rank[j] : rank[j]);
+    dst.x[d] = src.x[i];
+    dst.y[d] = src.y[i];
+    dst.u[d] = src.u[i];
+    dst.v[d] = src.v[i];
+    dst.w[d] = src.w[i];
+    dst.om[d] = src.om[i];
+    dst.psi[d] = src.psi[i];
+    dst.e[d] = e;
+    dst.id[d] = src.id[i];
+  }
 }
 
 template <typename T>
@@ -269,8 +322,8 @@ void launch_reorder(hipStream_t s, int32_t ne, int64_t np, const double *sums, i
   hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(SCAN_B), 0, s, ne, sums, offs, blocksums);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_B), 0, s, nb, blocksums);
   hipLaunchKernelGGL(k_scan_add, dim3((ne + 255) / 256), dim3(256), 0, s, ne, offs, blocksums, cursor);
-  hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, np, offs,
-                     cursor, src, dst);
+  hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((np + SC_WG * SC_PPT - 1) / (SC_WG * SC_PPT))),
+                     dim3(SC_WG), 0, s, np, offs, cursor, src, dst);
 }
 
 // particle state <-> double [7][n]
