@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpdf.so")
+LIB_PATH = os.environ.get("PDF_LIBRARY") or os.path.join(HERE, "libpdf.so")
 
 PDF_OK = 0
 PDF_FP64, PDF_FP32 = 0, 1

@@ -46,6 +46,7 @@ struct pdf_ctx {
   uint32_t step = 0;
   bool seeded = false;
   unsigned long long *cnt = nullptr;
+  KArgs *dka = nullptr;  // device copy of the mesh and model parameters
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev;
@@ -170,7 +171,7 @@ pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt) {
                         c->gradp_set ? c->gradp : nullptr, dt, rec);
     HIPCHK(c, hipMemsetAsync(c->sums, 0, (size_t)ne * NSUM * sizeof(double), c->stream));
     mark(c, 1);
-    launch_advance<T>(c->stream, c->md, c->model, part_view<T>(c, c->cur), c->np, rec, c->sums,
+    launch_advance<T>(c->stream, c->dka, c->model, part_view<T>(c, c->cur), c->np, rec, c->sums,
                       c->seed, c->step, dt, c->cnt);
     mark(c, 2);
     launch_elem_moments<T>(c->stream, ne, c->sums, rec, c->emom);
@@ -448,6 +449,16 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   md.src_x = params->src_x;
   md.src_y = params->src_y;
   md.src_r = params->src_r;
+  KArgs hka;
+  hka.m = c->md;
+  hka.md = c->model;
+  c->dka = (KArgs *)dalloc(c, sizeof(KArgs));
+  if (!c->dka || hipMemcpyAsync(c->dka, &hka, sizeof(KArgs), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    c->err = "device allocation or upload failed";
+    pdf_destroy(c);
+    return PDF_E_OOM;
+  }
   *out = c;
   return PDF_OK;
 }

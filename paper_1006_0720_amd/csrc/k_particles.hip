@@ -277,28 +277,45 @@ void launch_elem_prep(hipStream_t s, const MeshDev &m, const ModelDev &md, const
 // particle costs LDS atomics instead of contended global atomics.  A full
 // table (never expected at the chunk sizes used) falls back to global atomics.
 // ---------------------------------------------------------------------------
-constexpr int TAB = 256;  // LDS table slots per workgroup (power of two)
-constexpr int WG = 256;   // threads per workgroup of the particle kernels
-constexpr int PPT = 8;    // particles per thread: chunk of WG*PPT particles
+#ifndef PDF_TAB_LOG2
+#define PDF_TAB_LOG2 7
+#endif
+#ifndef PDF_TAB_COPIES
+#define PDF_TAB_COPIES 4
+#endif
+#ifndef PDF_PPT
+#define PDF_PPT 8
+#endif
+constexpr int TAB = 1 << PDF_TAB_LOG2;  // LDS table slots per workgroup (power of two)
+constexpr int NCOPY = PDF_TAB_COPIES;    // accumulator copies (lane % NCOPY picks one)
+constexpr int WG = 256;                  // threads per workgroup of the particle kernels
+constexpr int PPT = PDF_PPT;             // particles per thread: chunk of WG*PPT particles
 
+// One key array and NCOPY copies of the accumulators: lanes of a wave that add
+// to the same element (typically the particles that stayed in their host)
+// are spread over the copies, dividing the serialisation of same-address LDS
+// atomics by NCOPY; the copies are summed when the table is flushed.
 struct SumTable {
   int32_t key[TAB];
-  uint32_t n[TAB];
-  double acc[15][TAB];
+  uint32_t n[NCOPY][TAB];
+  double acc[NCOPY][15][TAB];
 };
 
 __device__ __forceinline__ void table_init(SumTable &t) {
   for (int s = threadIdx.x; s < TAB; s += blockDim.x) {
     t.key[s] = -1;
-    t.n[s] = 0u;
 #pragma unroll
-    for (int f = 0; f < 15; ++f) t.acc[f][s] = 0.0;
+    for (int c = 0; c < NCOPY; ++c) {
+      t.n[c][s] = 0u;
+#pragma unroll
+      for (int f = 0; f < 15; ++f) t.acc[c][f][s] = 0.0;
+    }
   }
 }
 
 __device__ __forceinline__ int table_slot(SumTable &t, int32_t e) {
-  uint32_t h = ((uint32_t)e * 2654435761u) >> 24;
-  for (int probe = 0; probe < 64; ++probe) {
+  uint32_t h = ((uint32_t)e * 2654435761u) >> (32 - PDF_TAB_LOG2);
+  for (int probe = 0; probe < TAB; ++probe) {
     const int32_t k = __hip_atomic_load(&t.key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (k == e) return (int)h;
     if (k == -1) {
@@ -321,9 +338,10 @@ __device__ __forceinline__ void table_add(SumTable &t, double *sums, const T *re
                           q0 * q1, q0 * q2, q1 * q2, q4 * q4, q0 * q4, q1 * q4, q2 * q4};
   const int s = table_slot(t, e);
   if (s >= 0) {
-    atomicAdd(&t.n[s], 1u);
+    const int c = (int)(threadIdx.x % NCOPY);
+    atomicAdd(&t.n[c][s], 1u);
 #pragma unroll
-    for (int f = 0; f < 15; ++f) unsafeAtomicAdd(&t.acc[f][s], val[f]);
+    for (int f = 0; f < 15; ++f) unsafeAtomicAdd(&t.acc[c][f][s], val[f]);
   } else {
     double *g = sums + (size_t)e * NSUM;
     unsafeAtomicAdd(&g[0], 1.0);
@@ -338,9 +356,17 @@ __device__ __forceinline__ void table_flush(SumTable &t, double *sums) {
     const int32_t e = t.key[s];
     if (e < 0) continue;
     double *g = sums + (size_t)e * NSUM;
-    unsafeAtomicAdd(&g[0], (double)t.n[s]);
+    uint32_t n = 0;
 #pragma unroll
-    for (int f = 0; f < 15; ++f) unsafeAtomicAdd(&g[1 + f], t.acc[f][s]);
+    for (int c = 0; c < NCOPY; ++c) n += t.n[c][s];
+    unsafeAtomicAdd(&g[0], (double)n);
+#pragma unroll
+    for (int f = 0; f < 15; ++f) {
+      double a = 0.0;
+#pragma unroll
+      for (int c = 0; c < NCOPY; ++c) a += t.acc[c][f][s];
+      unsafeAtomicAdd(&g[1 + f], a);
+    }
   }
 }
 
@@ -408,24 +434,70 @@ __device__ __forceinline__ void noslip(const ModelDev &md, const T *r, double nx
 //   slip and no-slip conditions -> trajectory (b) of eq:fw -> source
 //   -> store -> element sums of the new host.
 // ---------------------------------------------------------------------------
+// event counters of one thread, packed 16 bits each in ca (walk steps, periodic
+// crossings, reflections, trajectory-(b) conditions) and 8 bits each in cb
+// (fall-backs, brute-force searches, lost, omega folds, gamma failures, non-finite)
+#define C_WALK(v) (ca += (uint64_t)(v))
+#define C_PER(v) (ca += (uint64_t)(v) << 16)
+#define C_REFL(v) (ca += (uint64_t)(v) << 32)
+#define C_B(v) (ca += (uint64_t)(v) << 48)
+#define C_FALL(v) (cb += (uint64_t)(v))
+#define C_BRUTE(v) (cb += (uint64_t)(v) << 8)
+#define C_LOST(v) (cb += (uint64_t)(v) << 16)
+#define C_CLAMP(v) (cb += (uint64_t)(v) << 24)
+#define C_GFAIL(v) (cb += (uint64_t)(v) << 32)
+#define C_NAN(v) (cb += (uint64_t)(v) << 40)
+
 template <typename T, bool VISC, bool WALLB>
-__global__ __launch_bounds__(WG) void k_advance(MeshDev m, ModelDev md, PartDev<T> p, int64_t np,
+__global__ __launch_bounds__(WG) void k_advance(const KArgs *__restrict__ ka, PartDev<T> p, int64_t np,
                                                 const T *__restrict__ rec, double *sums, uint32_t k0,
                                                 uint32_t k1, uint32_t step, double dt, double sdt,
                                                 double s2nu, unsigned long long *cnt) {
   __shared__ SumTable tab;
+  const MeshDev &m = ka->m;
+  const ModelDev &md = ka->md;
   table_init(tab);
   __syncthreads();
-  int c_walk = 0, c_fall = 0, c_brute = 0, c_lost = 0, c_refl = 0, c_per = 0, c_b = 0, c_clamp = 0,
-      c_gfail = 0, c_nan = 0;
+  uint64_t ca = 0, cb = 0;
   const int64_t base = (int64_t)blockIdx.x * (WG * PPT);
+  // software pipeline: the state of the thread's next particle is loaded
+  // while the current one is advanced
+  int32_t n_e = 0;
+  uint32_t n_id = 0;
+  T n_x = (T)0, n_y = (T)0, n_u = (T)0, n_v = (T)0, n_w = (T)0, n_om = (T)0, n_psi = (T)0;
+  {
+    const int64_t i0 = base + threadIdx.x;
+    if (i0 < np) {
+      n_e = p.e[i0];
+      n_id = p.id[i0];
+      n_x = p.x[i0];
+      n_y = p.y[i0];
+      n_u = p.u[i0];
+      n_v = p.v[i0];
+      n_w = p.w[i0];
+      n_om = p.om[i0];
+      n_psi = p.psi[i0];
+    }
+  }
   for (int jj = 0; jj < PPT; ++jj) {
     const int64_t i = base + (int64_t)jj * WG + threadIdx.x;
-    if (i >= np) continue;
-    const int32_t e0 = p.e[i];
-    const uint32_t id = p.id[i];
-    const double x0 = (double)p.x[i], y0 = (double)p.y[i];
-    const T up0 = p.u[i], up1 = p.v[i], up2 = p.w[i], om = p.om[i], psi = p.psi[i];
+    if (i >= np) break;
+    const int32_t e0 = n_e;
+    const uint32_t id = n_id;
+    const double x0 = (double)n_x, y0 = (double)n_y;
+    const T up0 = n_u, up1 = n_v, up2 = n_w, om = n_om, psi = n_psi;
+    const int64_t inx = i + WG;
+    if (jj + 1 < PPT && inx < np) {
+      n_e = p.e[inx];
+      n_id = p.id[inx];
+      n_x = p.x[inx];
+      n_y = p.y[inx];
+      n_u = p.u[inx];
+      n_v = p.v[inx];
+      n_w = p.w[inx];
+      n_om = p.om[inx];
+      n_psi = p.psi[inx];
+    }
     const T *r = rec + (size_t)e0 * NREC;
 
     // ---- noise: six standard normals and one uniform per particle-step ----
@@ -480,7 +552,7 @@ __global__ __launch_bounds__(WG) void k_advance(MeshDev m, ModelDev md, PartDev<
     T omn = om - r[R_WA] * (om - r[R_OM]) - r[R_WB] * om + r[R_WC] * sqrt(omp) * xi5;
     if (omn < (T)0) {
       omn = -omn;
-      c_clamp = 1;
+      C_CLAMP(1);
     }
     // ---- scalar: eq:IEM ----
     T psin = psi - r[R_MIX] * (psi - r[R_PHI]);
@@ -491,7 +563,7 @@ __global__ __launch_bounds__(WG) void k_advance(MeshDev m, ModelDev md, PartDev<
     // a non-finite position cannot be located: the particle is lost at once
     const bool finite_pos = isfinite(x) && isfinite(y);
     for (int it = 0; it < 64 && finite_pos; ++it) {
-      c_walk++;
+      C_WALK(1);
       const ElemGeo g = m.geo[e];
       double lam[3];
       edge_lambdas(g, x, y, lam);
@@ -516,7 +588,7 @@ __global__ __launch_bounds__(WG) void k_advance(MeshDev m, ModelDev md, PartDev<
         shx += sx;
         shy += sy;
         e = m.belem[m.bpart[b]];
-        c_per++;
+        C_PER(1);
         continue;
       }
       const int ia = (k + 1) % 3, ib = (k + 2) % 3;
@@ -553,11 +625,11 @@ __global__ __launch_bounds__(WG) void k_advance(MeshDev m, ModelDev md, PartDev<
         int32_t f = search_patch(m, e0, x, y);
         if (f < 0) f = search_patch(m, e, x, y);
         if (f >= 0) {
-          c_fall++;
+          C_FALL(1);
           found = f;
           break;
         }
-        c_brute++;
+        C_BRUTE(1);
         f = locate_brute(m, x, y);
         if (f >= 0) {
           found = f;
@@ -572,26 +644,26 @@ __global__ __launch_bounds__(WG) void k_advance(MeshDev m, ModelDev md, PartDev<
       const double dist = (x - xa) * nx + (y - ya) * ny;
       x = stor<T>(x - 2.0 * dist * nx);
       y = stor<T>(y - 2.0 * dist * ny);
-      c_refl++;
+      C_REFL(1);
       if (bt == PDF_BC_SLIP) {
         const double vn = (double)un0 * nx + (double)un1 * ny;
         un0 = (T)((double)un0 - 2.0 * vn * nx);
         un1 = (T)((double)un1 - 2.0 * vn * ny);
       } else {
-        noslip<T>(md, r, nx, ny, k0, k1, id, step, nrefl, un0, un1, un2, omn, c_gfail);
+        { int gf = 0; noslip<T>(md, r, nx, ny, k0, k1, id, step, nrefl, un0, un1, un2, omn, gf); C_GFAIL(gf); }
       }
       nrefl++;
     }
     if (found < 0) {
       int32_t f = finite_pos ? search_patch(m, e0, x, y) : -1;
       if (f < 0 && finite_pos) {
-        c_brute++;
+        C_BRUTE(1);
         f = locate_brute(m, x, y);
       }
       if (f >= 0) {
         found = f;
       } else {
-        c_lost++;
+        C_LOST(1);
         x = x0;
         y = y0;
         found = e0;
@@ -630,8 +702,8 @@ __global__ __launch_bounds__(WG) void k_advance(MeshDev m, ModelDev md, PartDev<
         if (dd0 > 0.0 && d1 >= 0.0) {
           const double fw = exp(-dd0 * d1 / (md.nu * dt));
           if (eta < fw) {
-            c_b++;
-            noslip<T>(md, r, nx, ny, k0, k1, id, step, 8, un0, un1, un2, omn, c_gfail);
+            C_B(1);
+            { int gf = 0; noslip<T>(md, r, nx, ny, k0, k1, id, step, 8, un0, un1, un2, omn, gf); C_GFAIL(gf); }
           }
         }
       }
@@ -643,7 +715,7 @@ __global__ __launch_bounds__(WG) void k_advance(MeshDev m, ModelDev md, PartDev<
     }
     if (!(isfinite((double)un0) && isfinite((double)un1) && isfinite((double)un2) &&
           isfinite((double)omn) && isfinite((double)psin)))
-      c_nan = 1;
+      C_NAN(1);
 
     p.x[i] = (T)x;
     p.y[i] = (T)y;
@@ -656,20 +728,20 @@ __global__ __launch_bounds__(WG) void k_advance(MeshDev m, ModelDev md, PartDev<
     table_add<T>(tab, sums, rec, found, un0, un1, un2, omn, psin);
   }
   table_flush(tab, sums);
-  wave_count(&cnt[PDF_CNT_WALK_STEPS], c_walk);
-  wave_count(&cnt[PDF_CNT_FALLBACK], c_fall);
-  wave_count(&cnt[PDF_CNT_BRUTE], c_brute);
-  wave_count(&cnt[PDF_CNT_LOST], c_lost);
-  wave_count(&cnt[PDF_CNT_REFLECT], c_refl);
-  wave_count(&cnt[PDF_CNT_PERIODIC], c_per);
-  wave_count(&cnt[PDF_CNT_NOSLIP_B], c_b);
-  wave_count(&cnt[PDF_CNT_OMEGA_CLAMP], c_clamp);
-  wave_count(&cnt[PDF_CNT_GAMMA_FAIL], c_gfail);
-  wave_count(&cnt[PDF_CNT_NONFINITE], c_nan);
+  wave_count(&cnt[PDF_CNT_WALK_STEPS], (int)(ca & 0xFFFF));
+  wave_count(&cnt[PDF_CNT_PERIODIC], (int)((ca >> 16) & 0xFFFF));
+  wave_count(&cnt[PDF_CNT_REFLECT], (int)((ca >> 32) & 0xFFFF));
+  wave_count(&cnt[PDF_CNT_NOSLIP_B], (int)((ca >> 48) & 0xFFFF));
+  wave_count(&cnt[PDF_CNT_FALLBACK], (int)(cb & 0xFF));
+  wave_count(&cnt[PDF_CNT_BRUTE], (int)((cb >> 8) & 0xFF));
+  wave_count(&cnt[PDF_CNT_LOST], (int)((cb >> 16) & 0xFF));
+  wave_count(&cnt[PDF_CNT_OMEGA_CLAMP], (int)((cb >> 24) & 0xFF));
+  wave_count(&cnt[PDF_CNT_GAMMA_FAIL], (int)((cb >> 32) & 0xFF));
+  wave_count(&cnt[PDF_CNT_NONFINITE], (int)((cb >> 40) & 0xFF));
 }
 
 template <typename T>
-void launch_advance(hipStream_t s, const MeshDev &m, const ModelDev &md, PartDev<T> p, int64_t np,
+void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
                     const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
                     unsigned long long *cnt) {
   const unsigned grid = (unsigned)((np + WG * PPT - 1) / (WG * PPT));
@@ -678,14 +750,14 @@ void launch_advance(hipStream_t s, const MeshDev &m, const ModelDev &md, PartDev
   const double sdt = sqrt(dt), s2nu = sqrt(2.0 * md.nu);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   if (visc && wallb)
-    hipLaunchKernelGGL((k_advance<T, true, true>), dim3(grid), dim3(WG), 0, s, m, md, p, np, rec,
-                       sums, k0, k1, step, dt, sdt, s2nu, cnt);
+    hipLaunchKernelGGL((k_advance<T, true, true>), dim3(grid), dim3(WG), 0, s, dka, p, np, rec, sums,
+                       k0, k1, step, dt, sdt, s2nu, cnt);
   else if (visc)
-    hipLaunchKernelGGL((k_advance<T, true, false>), dim3(grid), dim3(WG), 0, s, m, md, p, np, rec,
-                       sums, k0, k1, step, dt, sdt, s2nu, cnt);
+    hipLaunchKernelGGL((k_advance<T, true, false>), dim3(grid), dim3(WG), 0, s, dka, p, np, rec, sums,
+                       k0, k1, step, dt, sdt, s2nu, cnt);
   else
-    hipLaunchKernelGGL((k_advance<T, false, false>), dim3(grid), dim3(WG), 0, s, m, md, p, np, rec,
-                       sums, k0, k1, step, dt, sdt, s2nu, cnt);
+    hipLaunchKernelGGL((k_advance<T, false, false>), dim3(grid), dim3(WG), 0, s, dka, p, np, rec, sums,
+                       k0, k1, step, dt, sdt, s2nu, cnt);
 }
 
 #define INST(T)                                                                                  \
@@ -694,8 +766,8 @@ void launch_advance(hipStream_t s, const MeshDev &m, const ModelDev &md, PartDev
                                const double *, const double *, unsigned long long *);            \
   template void launch_elem_prep<T>(hipStream_t, const MeshDev &, const ModelDev &, const double *, \
                                     const double *, const double *, double, T *);                \
-  template void launch_advance<T>(hipStream_t, const MeshDev &, const ModelDev &, PartDev<T>,       \
-                                  int64_t, const T *, double *, uint64_t, uint32_t, double,        \
+  template void launch_advance<T>(hipStream_t, const KArgs *, const ModelDev &, PartDev<T>, int64_t, \
+                                  const T *, double *, uint64_t, uint32_t, double,                 \
                                   unsigned long long *);                                         \
   template void launch_accumulate<T>(hipStream_t, PartDev<T>, int64_t, const T *, double *);        \
   template void launch_ref_from_sums<T>(hipStream_t, int32_t, const double *, T *);

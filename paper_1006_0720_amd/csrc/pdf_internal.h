@@ -68,6 +68,14 @@ struct ModelDev {
   double src_x, src_y, src_r;
 };
 
+// Mesh and model parameters of the particle kernel, kept in device memory and
+// passed by pointer (uniform loads through the scalar cache instead of ~120
+// kernel-argument registers).
+struct KArgs {
+  MeshDev m;
+  ModelDev md;
+};
+
 // ---- launchers (defined in the kernel translation units) ----
 template <typename T>
 void launch_seed(hipStream_t s, const MeshDev &m, const ModelDev &md, PartDev<T> p, int32_t ppe,
@@ -77,7 +85,7 @@ template <typename T>
 void launch_elem_prep(hipStream_t s, const MeshDev &m, const ModelDev &md, const double *stats,
                       const double *wp, const double *gradp, double dt, T *rec);
 template <typename T>
-void launch_advance(hipStream_t s, const MeshDev &m, const ModelDev &md, PartDev<T> p, int64_t np,
+void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
                     const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
                     unsigned long long *cnt);
 template <typename T>

@@ -48,24 +48,24 @@ __device__ __forceinline__ double unif_d(uint32_t r) {
   return ((double)(r >> 9) + 0.5) * 1.1920928955078125e-07;
 }
 
-// Box-Muller pair in binary64.
+// Box-Muller pair in binary64 (the angle through sincospi: no range reduction).
 __device__ __forceinline__ void box_muller_d(uint32_t r1, uint32_t r2, double &z0, double &z1) {
-  double u1 = unif_d(r1), u2 = unif_d(r2);
-  double rad = sqrt(-2.0 * log(u1));
+  const double u1 = unif_d(r1), u2 = unif_d(r2);
+  const double rad = sqrt(-2.0 * log(u1));
   double s, c;
-  sincos(6.283185307179586 * u2, &s, &c);
+  sincospi(2.0 * u2, &s, &c);
   z0 = rad * c;
   z1 = rad * s;
 }
 
-// Box-Muller pair in binary32 (angle via sincospi: sin/cos(pi * 2u)).
+// Box-Muller pair in binary32 on the hardware transcendental units:
+// v_log_f32 is log2, v_sin_f32 / v_cos_f32 take their argument in revolutions
+// (sin(2 pi x)), so -2 ln u = -2 ln(2) log2(u) and the angle needs no scaling.
 __device__ __forceinline__ void box_muller_f(uint32_t r1, uint32_t r2, float &z0, float &z1) {
-  float u1 = unif_f(r1), u2 = unif_f(r2);
-  float rad = sqrtf(-2.0f * logf(u1));
-  float s, c;
-  sincospif(2.0f * u2, &s, &c);
-  z0 = rad * c;
-  z1 = rad * s;
+  const float u1 = unif_f(r1), u2 = unif_f(r2);
+  const float rad = __builtin_amdgcn_sqrtf(-1.38629436112f * __builtin_amdgcn_logf(u1));
+  z0 = rad * __builtin_amdgcn_cosf(u2);
+  z1 = rad * __builtin_amdgcn_sinf(u2);
 }
 
 // Gamma(shape, scale) for shape >= 1 by Marsaglia & Tsang (ACM TOMS 26, 2000),
