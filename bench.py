@@ -91,6 +91,37 @@ def cpu_baseline(wname, w):
                       f"statistics estimate of each step"}
 
 
+def denoise_study(mode, out_path=""):
+    """Learned-vs-plain cost at equal nodal-statistics error on the street-canyon
+    mesh (denoiser trained on the GPU from 10 vs 200 particles/element runs)."""
+    import numpy as np
+
+    from paper_1006_0720_amd.denoise_study import study
+    from synth import configs as CF
+    from synth import meshes as M
+
+    if mode == "quick":
+        mesh = M.canyon(20_000, 0.15, 0)
+        kw = dict(n_train=6, n_test=2, steps_spin=40, n_snap=4, every=10, train_steps=600,
+                  batch=4096, eval_ppes=(20, 40))
+    else:
+        mesh = M.canyon(200_000, 0.15, 0)
+        kw = dict(n_train=12, n_test=3, steps_spin=100, n_snap=5, every=10, train_steps=3000,
+                  batch=8192, eval_ppes=(20, 40, 80))
+
+    def make(ppe, seed, src):
+        return CF.canyon(mesh=mesh, ppe=ppe, seed=seed, src=src)
+
+    res, params, norm = study(make, log=lambda m: print(m, file=sys.stderr, flush=True), **kw)
+    res["mesh_elements"] = mesh.n_elems
+    res["mode"] = mode
+    if out_path:
+        base = os.path.splitext(out_path)[0]
+        json.dump(res, open(base + ".json", "w"), indent=1)
+        np.savez(base + ".npz", params=params, mu=norm[0], sig=norm[1], scale=norm[2])
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +132,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--denoise-study", default="",
+                    help="run the learned-vs-plain study on the canyon mesh: 'full' or 'quick'; "
+                         "the result is added as learned_vs_plain")
+    ap.add_argument("--study-out", default="", help="write the study result and weights here (.json/.npz)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -170,6 +205,8 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, w)
     ctx.close()
+    if args.denoise_study:
+        out["learned_vs_plain"] = denoise_study(args.denoise_study, args.study_out)
     print(json.dumps(out), flush=True)
 
 

@@ -206,6 +206,63 @@ pdf_status pdf_get_timing(pdf_ctx *ctx, double *out_ms, int32_t n);
 const char *pdf_last_error(const pdf_ctx *ctx);
 void pdf_destroy(pdf_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Learned denoiser of the nodal statistics (not part of the dissertation's
+ * method: it addresses the statistical noise that makes the method need 80-500
+ * particles per element, Ch.4 particle-number study).  A 4-layer perceptron
+ * 48 -> H -> H -> H -> 8 with GELU activations, BF16 weights and activations
+ * and FP32 accumulation on the matrix cores, predicts a correction of 8 nodal
+ * statistics (<U>, <V>, <phi>, <uu>, <vv>, <uv>, <phi'^2>, <omega>) from 48
+ * features of the plain estimate (for each statistic: node value, mean, std,
+ * min and max over the node and its neighbours, gradient magnitude).  The
+ * plain estimator stays as the fallback: a correction larger than tau times
+ * the plain standard error at the node is rejected.
+ *
+ * Parameter vector (float32, PDF_DN_NPARAM(H) values): W1 [48][H], b1 [H],
+ * W2 [H][H], b2 [H], W3 [H][H], b3 [H], W4 [H][8], b4 [8]; y = x W + b.
+ * ------------------------------------------------------------------------ */
+typedef struct pdf_denoiser pdf_denoiser;
+#define PDF_DN_NIN 48
+#define PDF_DN_NOUT 8
+#define PDF_DN_NPARAM(H) (48 * (H) + (H) + 2 * ((H) * (H) + (H)) + (H) * 8 + 8)
+
+/* Create a denoiser for the mesh of ctx (borrowed; must outlive the denoiser).
+ * hidden: H (multiple of 16, <= 1024); weights initialised uniform in
+ * +-1/sqrt(fan_in) from seed, biases 0; feature standardisation identity. */
+pdf_status pdf_denoiser_create(pdf_ctx *ctx, int32_t hidden, uint64_t seed, pdf_denoiser **out);
+void pdf_denoiser_destroy(pdf_denoiser *dn);
+
+/* Read (set = 0) or write (set = 1) the host parameter vector (n values). */
+pdf_status pdf_denoiser_params(pdf_denoiser *dn, float *host, int64_t n, int32_t set);
+
+/* Feature standardisation (48 means and standard deviations) and the output
+ * scales of the 8 statistics (correction = scale_q * network output q). */
+pdf_status pdf_denoiser_set_norm(pdf_denoiser *dn, const float *mu48, const float *sig48,
+                                 const float *scale8);
+
+/* Features of nodal statistics [PDF_NSTAT][n_nodes] (device pointer; NULL: the
+ * context's latest estimate) into feat [n_nodes][48] (device, float32),
+ * standardised when standardized != 0. */
+pdf_status pdf_denoiser_features(pdf_denoiser *dn, const double *nodal, float *feat, int32_t standardized);
+
+/* Network output y [n][8] (device, float32) for standardised inputs x [n][48]
+ * (device, float32). */
+pdf_status pdf_denoiser_forward(pdf_denoiser *dn, const float *x, int32_t n, float *y);
+
+/* One training step on a batch (device pointers x [B][48], target [B][8]):
+ * forward, mean-squared error, backward, Adam (lr, beta1 0.9, beta2 0.999,
+ * eps 1e-8) on the float32 master parameters.  *loss (host) receives the
+ * batch loss before the update.  With lr = 0 the parameters are unchanged and
+ * grad_host (may be NULL) receives the gradient vector. */
+pdf_status pdf_denoiser_train_step(pdf_denoiser *dn, const float *x, const float *target, int32_t B,
+                                   float lr, float *loss, float *grad_host);
+
+/* Denoised nodal statistics of the context's latest estimate into out
+ * [PDF_NSTAT][n_nodes] (host or device): the plain statistics with the 8
+ * corrected fields; *n_fallback (may be NULL) counts rejected corrections. */
+pdf_status pdf_denoise_stats(pdf_denoiser *dn, double tau, double *out, int32_t on_device,
+                             uint64_t *n_fallback);
+
 #ifdef __cplusplus
 }
 #endif

@@ -250,3 +250,112 @@ class Context:
         out = np.zeros(4)
         self._chk(lib.pdf_get_timing(self.h, _ptr(out), 4))
         return dict(elem_prep=out[0], advance=out[1], estimator=out[2], reorder=out[3])
+
+
+def _declare_denoiser():
+    vp, i32, i64, dbl, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_uint64
+    sig = {
+        "pdf_denoiser_create": ([vp, i32, u64, C.POINTER(vp)], i32),
+        "pdf_denoiser_destroy": ([vp], None),
+        "pdf_denoiser_params": ([vp, vp, i64, i32], i32),
+        "pdf_denoiser_set_norm": ([vp, vp, vp, vp], i32),
+        "pdf_denoiser_features": ([vp, vp, vp, i32], i32),
+        "pdf_denoiser_forward": ([vp, vp, i32, vp], i32),
+        "pdf_denoiser_train_step": ([vp, vp, vp, i32, C.c_float, C.POINTER(C.c_float), vp], i32),
+        "pdf_denoise_stats": ([vp, dbl, vp, i32, C.POINTER(u64)], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+
+
+_declare_denoiser()
+
+DN_NIN, DN_NOUT = 48, 8
+
+
+def dn_nparam(h):
+    return 48 * h + h + 2 * (h * h + h) + h * 8 + 8
+
+
+class Denoiser:
+    """Learned denoiser bound to a Context (its mesh and latest statistics).
+    Device arrays are torch tensors on the context's device."""
+
+    def __init__(self, ctx: Context, hidden=128, seed=0):
+        self.ctx = ctx
+        self.torch = ctx.torch
+        self.hidden = hidden
+        self.n_param = dn_nparam(hidden)
+        h = C.c_void_p()
+        ctx._chk(lib.pdf_denoiser_create(ctx.h, hidden, seed, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.pdf_denoiser_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        out = np.empty(self.n_param, np.float32)
+        self.ctx._chk(lib.pdf_denoiser_params(self.h, _ptr(out), self.n_param, 0))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        assert p.size == self.n_param
+        self.ctx._chk(lib.pdf_denoiser_params(self.h, _ptr(p), self.n_param, 1))
+
+    def set_norm(self, mu, sig, scale):
+        mu, sig, scale = (np.ascontiguousarray(a, np.float32) for a in (mu, sig, scale))
+        self.ctx._chk(lib.pdf_denoiser_set_norm(self.h, _ptr(mu), _ptr(sig), _ptr(scale)))
+        self.norm = (mu.copy(), sig.copy(), scale.copy())
+
+    def features(self, nodal=None, standardized=False):
+        """Features [n_nodes, 48] (torch, device) of nodal statistics (torch
+        device tensor [25, n_nodes] or None for the latest estimate)."""
+        t = self.torch
+        out = t.empty((self.ctx.n_nodes, DN_NIN), dtype=t.float32, device=self.ctx.device)
+        src = None if nodal is None else C.c_void_p(nodal.contiguous().data_ptr())
+        self.ctx._chk(lib.pdf_denoiser_features(self.h, src, C.c_void_p(out.data_ptr()), int(standardized)))
+        return out
+
+    def forward(self, x):
+        t = self.torch
+        x = x.contiguous().to(t.float32)
+        y = t.empty((x.shape[0], DN_NOUT), dtype=t.float32, device=self.ctx.device)
+        self.ctx._chk(lib.pdf_denoiser_forward(self.h, C.c_void_p(x.data_ptr()), x.shape[0],
+                                               C.c_void_p(y.data_ptr())))
+        return y
+
+    def train_step(self, x, target, lr, want_grad=False):
+        t = self.torch
+        x = x.contiguous().to(t.float32)
+        target = target.contiguous().to(t.float32)
+        loss = C.c_float()
+        g = np.empty(self.n_param, np.float32) if want_grad else None
+        self.ctx._chk(lib.pdf_denoiser_train_step(self.h, C.c_void_p(x.data_ptr()),
+                                                  C.c_void_p(target.data_ptr()), x.shape[0],
+                                                  float(lr), C.byref(loss), _ptr(g)))
+        return (loss.value, g) if want_grad else loss.value
+
+    def denoise(self, tau=3.0, device=False):
+        """Denoised copy of the latest nodal statistics and the number of
+        rejected corrections; a numpy array, or a torch device tensor if device."""
+        nf = C.c_uint64()
+        if device:
+            out = self.torch.empty((NSTAT, self.ctx.n_nodes), dtype=self.torch.float64,
+                                   device=self.ctx.device)
+            self.ctx._chk(lib.pdf_denoise_stats(self.h, float(tau), C.c_void_p(out.data_ptr()), 1,
+                                                C.byref(nf)))
+        else:
+            out = np.empty((NSTAT, self.ctx.n_nodes))
+            self.ctx._chk(lib.pdf_denoise_stats(self.h, float(tau), _ptr(out), 0, C.byref(nf)))
+        return out, nf.value

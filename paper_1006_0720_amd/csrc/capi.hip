@@ -679,3 +679,309 @@ pdf_status pdf_get_timing(pdf_ctx *c, double *out_ms, int32_t n) {
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Learned denoiser (host orchestration of the kernels in k_denoise.hip)
+// ===========================================================================
+struct pdf_denoiser {
+  pdf_ctx *ctx = nullptr;
+  int32_t H = 128;
+  int64_t np = 0;
+  int64_t off[8] = {0};  // W1 b1 W2 b2 W3 b3 W4 b4
+  float *P = nullptr, *G = nullptr, *Mom = nullptr, *Vel = nullptr;
+  uint16_t *Pb = nullptr;  // bf16 copy of the parameters (weights used by the GEMMs)
+  float *mu = nullptr, *sig = nullptr, *scale = nullptr;
+  bool norm_set = false;
+  int64_t adam_t = 0;
+  // point-surrounding-point lists over master nodes
+  int32_t *p2p_off = nullptr, *p2p = nullptr;
+  // batch buffers
+  int32_t cap = 0;
+  uint16_t *Xb = nullptr, *H1 = nullptr, *H2 = nullptr, *H3 = nullptr, *dYb = nullptr, *dZb = nullptr;
+  float *Z1 = nullptr, *Z2 = nullptr, *Z3 = nullptr, *Y = nullptr, *dH = nullptr, *part = nullptr;
+  float *feat = nullptr;
+  unsigned long long *nfall = nullptr;
+};
+
+namespace {
+
+bool dn_reserve(pdf_denoiser *d, int32_t B) {
+  if (B <= d->cap) return true;
+  pdf_ctx *c = d->ctx;
+  void *old[12] = {d->Xb, d->H1, d->H2, d->H3, d->dYb, d->dZb, d->Z1, d->Z2, d->Z3, d->Y, d->dH, d->part};
+  for (void *p : old) dfree(c, p);
+  const size_t H = (size_t)d->H, b = (size_t)B;
+  d->Xb = (uint16_t *)dalloc(c, b * PDF_DN_NIN * 2);
+  d->H1 = (uint16_t *)dalloc(c, b * H * 2);
+  d->H2 = (uint16_t *)dalloc(c, b * H * 2);
+  d->H3 = (uint16_t *)dalloc(c, b * H * 2);
+  d->dYb = (uint16_t *)dalloc(c, b * PDF_DN_NOUT * 2);
+  d->dZb = (uint16_t *)dalloc(c, b * H * 2);
+  d->Z1 = (float *)dalloc(c, b * H * 4);
+  d->Z2 = (float *)dalloc(c, b * H * 4);
+  d->Z3 = (float *)dalloc(c, b * H * 4);
+  d->Y = (float *)dalloc(c, b * PDF_DN_NOUT * 4);
+  d->dH = (float *)dalloc(c, b * H * 4);
+  d->part = (float *)dalloc(c, (b * PDF_DN_NOUT / 256 + 2) * 4);
+  d->cap = B;
+  return d->Xb && d->H1 && d->H2 && d->H3 && d->dYb && d->dZb && d->Z1 && d->Z2 && d->Z3 && d->Y &&
+         d->dH && d->part;
+}
+
+// forward pass of B rows of standardised features (fp32 x), keeping Z and H
+pdf_status dn_forward(pdf_denoiser *d, const float *x, int32_t B) {
+  pdf_ctx *c = d->ctx;
+  hipStream_t s = c->stream;
+  const int H = d->H;
+  const uint16_t *W1 = d->Pb + d->off[0], *W2 = d->Pb + d->off[2], *W3 = d->Pb + d->off[4],
+                 *W4 = d->Pb + d->off[6];
+  const float *b1 = d->P + d->off[1], *b2 = d->P + d->off[3], *b3 = d->P + d->off[5],
+              *b4 = d->P + d->off[7];
+  launch_to_bf16(s, (int64_t)B * PDF_DN_NIN, x, d->Xb);
+  launch_gemm_bf16(s, B, H, PDF_DN_NIN, d->Xb, PDF_DN_NIN, 0, W1, H, 0, d->Z1, H, 0.f);
+  launch_bias_act(s, B, H, d->Z1, b1, d->H1, 1);
+  launch_gemm_bf16(s, B, H, H, d->H1, H, 0, W2, H, 0, d->Z2, H, 0.f);
+  launch_bias_act(s, B, H, d->Z2, b2, d->H2, 1);
+  launch_gemm_bf16(s, B, H, H, d->H2, H, 0, W3, H, 0, d->Z3, H, 0.f);
+  launch_bias_act(s, B, H, d->Z3, b3, d->H3, 1);
+  launch_gemm_bf16(s, B, PDF_DN_NOUT, H, d->H3, H, 0, W4, PDF_DN_NOUT, 0, d->Y, PDF_DN_NOUT, 0.f);
+  launch_bias_act(s, B, PDF_DN_NOUT, d->Y, b4, nullptr, 0);
+  HIPCHK(c, hipGetLastError());
+  return PDF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pdf_status pdf_denoiser_create(pdf_ctx *c, int32_t hidden, uint64_t seed, pdf_denoiser **out) {
+  if (!c || !out || hidden < 16 || hidden > 1024 || hidden % 16) return PDF_E_INVALID_ARG;
+  pdf_denoiser *d = new pdf_denoiser();
+  d->ctx = c;
+  d->H = hidden;
+  const int64_t H = hidden;
+  const int64_t sizes[8] = {PDF_DN_NIN * H, H, H * H, H, H * H, H, H * PDF_DN_NOUT, PDF_DN_NOUT};
+  int64_t o = 0;
+  for (int i = 0; i < 8; ++i) {
+    d->off[i] = o;
+    o += sizes[i];
+  }
+  d->np = o;
+  d->P = (float *)dalloc(c, o * 4);
+  d->G = (float *)dalloc(c, o * 4);
+  d->Mom = (float *)dalloc(c, o * 4);
+  d->Vel = (float *)dalloc(c, o * 4);
+  d->Pb = (uint16_t *)dalloc(c, o * 2);
+  d->mu = (float *)dalloc(c, 64 * 4);
+  d->sig = (float *)dalloc(c, 64 * 4);
+  d->scale = (float *)dalloc(c, 16 * 4);
+  d->nfall = (unsigned long long *)dalloc(c, 8);
+  const int32_t nn = c->md.nn;
+  d->feat = (float *)dalloc(c, (size_t)nn * PDF_DN_NIN * 4);
+  // points surrounding points (masters): masters of the nodes of the elements around each master
+  std::vector<int32_t> m2e_off(nn + 1), m2e, mnode(3 * (size_t)c->md.ne), master(nn);
+  (void)hipStreamSynchronize(c->stream);
+  hipMemcpy(m2e_off.data(), c->md.m2e_off, (nn + 1) * 4, hipMemcpyDeviceToHost);
+  m2e.resize(m2e_off[nn]);
+  if (!m2e.empty()) hipMemcpy(m2e.data(), c->md.m2e, m2e.size() * 4, hipMemcpyDeviceToHost);
+  hipMemcpy(mnode.data(), c->md.mnode, mnode.size() * 4, hipMemcpyDeviceToHost);
+  hipMemcpy(master.data(), c->md.master, nn * 4, hipMemcpyDeviceToHost);
+  std::vector<int32_t> poff(nn + 1, 0), plist;
+  for (int32_t n = 0; n < nn; ++n) {
+    std::vector<int32_t> l;
+    if (master[n] == n)
+      for (int32_t i = m2e_off[n]; i < m2e_off[n + 1]; ++i)
+        for (int k = 0; k < 3; ++k) {
+          const int32_t q = mnode[3 * (size_t)m2e[i] + k];
+          if (q != n && std::find(l.begin(), l.end(), q) == l.end()) l.push_back(q);
+        }
+    std::sort(l.begin(), l.end());
+    plist.insert(plist.end(), l.begin(), l.end());
+    poff[n + 1] = (int32_t)plist.size();
+  }
+  const int32_t *cp = nullptr;
+  bool ok = d->P && d->G && d->Mom && d->Vel && d->Pb && d->mu && d->sig && d->scale && d->nfall &&
+            d->feat && upload(c, poff, &cp);
+  d->p2p_off = (int32_t *)cp;
+  ok = ok && upload(c, plist, &cp);
+  d->p2p = (int32_t *)cp;
+  if (!ok) {
+    pdf_denoiser_destroy(d);
+    return fail(c, PDF_E_OOM, "denoiser allocation failed");
+  }
+  // initial parameters: uniform in +-1/sqrt(fan_in) (splitmix64 stream), zero biases
+  std::vector<float> h(o, 0.f);
+  uint64_t st = seed ^ 0x9E3779B97F4A7C15ull;
+  auto next = [&]() {
+    uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+  };
+  const int64_t fan[4] = {PDF_DN_NIN, H, H, H};
+  for (int l = 0; l < 4; ++l) {
+    const double a = 1.0 / std::sqrt((double)fan[l]);
+    for (int64_t i = 0; i < sizes[2 * l]; ++i) h[d->off[2 * l] + i] = (float)((2.0 * next() - 1.0) * a);
+  }
+  std::vector<float> one(64, 1.f), zero(64, 0.f);
+  if (pdf_denoiser_params(d, h.data(), o, 1) != PDF_OK ||
+      hipMemcpy(d->mu, zero.data(), 64 * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(d->sig, one.data(), 64 * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(d->scale, one.data(), 16 * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    pdf_denoiser_destroy(d);
+    return fail(c, PDF_E_DEVICE, "denoiser initialisation failed");
+  }
+  *out = d;
+  return PDF_OK;
+}
+
+void pdf_denoiser_destroy(pdf_denoiser *d) {
+  if (!d) return;
+  pdf_ctx *c = d->ctx;
+  (void)hipStreamSynchronize(c->stream);
+  void *ps[] = {d->P, d->G, d->Mom, d->Vel, d->Pb, d->mu, d->sig, d->scale, d->p2p_off, d->p2p, d->Xb,
+                d->H1, d->H2, d->H3, d->dYb, d->dZb, d->Z1, d->Z2, d->Z3, d->Y, d->dH, d->part, d->feat,
+                d->nfall};
+  for (void *p : ps) dfree(c, p);
+  delete d;
+}
+
+pdf_status pdf_denoiser_params(pdf_denoiser *d, float *host, int64_t n, int32_t set) {
+  if (!d || !host || n != d->np) return PDF_E_INVALID_ARG;
+  pdf_ctx *c = d->ctx;
+  if (set) {
+    HIPCHK(c, hipMemcpyAsync(d->P, host, n * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(d->Mom, 0, n * 4, c->stream));
+    HIPCHK(c, hipMemsetAsync(d->Vel, 0, n * 4, c->stream));
+    launch_to_bf16(c->stream, n, d->P, d->Pb);
+    d->adam_t = 0;
+  } else {
+    HIPCHK(c, hipMemcpyAsync(host, d->P, n * 4, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PDF_OK;
+}
+
+pdf_status pdf_denoiser_set_norm(pdf_denoiser *d, const float *mu48, const float *sig48, const float *scale8) {
+  if (!d || !mu48 || !sig48 || !scale8) return PDF_E_INVALID_ARG;
+  for (int i = 0; i < PDF_DN_NIN; ++i)
+    if (!(sig48[i] > 0.f)) return fail(d->ctx, PDF_E_INVALID_ARG, "feature scale must be positive");
+  pdf_ctx *c = d->ctx;
+  HIPCHK(c, hipMemcpyAsync(d->mu, mu48, PDF_DN_NIN * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(d->sig, sig48, PDF_DN_NIN * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(d->scale, scale8, PDF_DN_NOUT * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  d->norm_set = true;
+  return PDF_OK;
+}
+
+pdf_status pdf_denoiser_features(pdf_denoiser *d, const double *nodal, float *feat, int32_t standardized) {
+  if (!d || !feat) return PDF_E_INVALID_ARG;
+  pdf_ctx *c = d->ctx;
+  if (!nodal && !c->seeded) return fail(c, PDF_E_STATE, "no statistics");
+  launch_features(c->stream, c->md, d->p2p_off, d->p2p, nodal ? nodal : c->latest,
+                  standardized ? d->mu : nullptr, d->sig, feat, nullptr);
+  HIPCHK(c, hipGetLastError());
+  return PDF_OK;
+}
+
+pdf_status pdf_denoiser_forward(pdf_denoiser *d, const float *x, int32_t n, float *y) {
+  if (!d || !x || !y || n < 0) return PDF_E_INVALID_ARG;
+  pdf_ctx *c = d->ctx;
+  const int32_t chunk = 65536;
+  if (!dn_reserve(d, n < chunk ? n : chunk)) return fail(c, PDF_E_OOM, "denoiser buffers");
+  for (int32_t r0 = 0; r0 < n; r0 += chunk) {
+    const int32_t b = (n - r0) < chunk ? (n - r0) : chunk;
+    pdf_status st = dn_forward(d, x + (size_t)r0 * PDF_DN_NIN, b);
+    if (st != PDF_OK) return st;
+    HIPCHK(c, hipMemcpyAsync(y + (size_t)r0 * PDF_DN_NOUT, d->Y, (size_t)b * PDF_DN_NOUT * 4,
+                             hipMemcpyDeviceToDevice, c->stream));
+  }
+  return PDF_OK;
+}
+
+pdf_status pdf_denoiser_train_step(pdf_denoiser *d, const float *x, const float *target, int32_t B,
+                                   float lr, float *loss, float *grad_host) {
+  if (!d || !x || !target || B <= 0 || lr < 0.f) return PDF_E_INVALID_ARG;
+  pdf_ctx *c = d->ctx;
+  hipStream_t s = c->stream;
+  if (!dn_reserve(d, B)) return fail(c, PDF_E_OOM, "denoiser buffers");
+  pdf_status st = dn_forward(d, x, B);
+  if (st != PDF_OK) return st;
+  const int H = d->H, O = PDF_DN_NOUT;
+  const uint16_t *W2 = d->Pb + d->off[2], *W3 = d->Pb + d->off[4], *W4 = d->Pb + d->off[6];
+  float *g = d->G;
+  // dL/dY (mean squared error) into Y (fp32) and dYb (bf16)
+  const int nb = launch_mse(s, B, O, O, d->Y, target, d->dYb, d->part);
+  // layer 4
+  launch_gemm_bf16(s, H, O, B, d->H3, H, 1, d->dYb, O, 0, g + d->off[6], O, 0.f);
+  launch_colsum(s, B, O, d->Y, g + d->off[7]);
+  launch_gemm_bf16(s, B, H, O, d->dYb, O, 0, W4, O, 1, d->dH, H, 0.f);
+  launch_dgelu(s, (int64_t)B * H, d->dH, d->Z3, d->dZb);
+  // layer 3
+  launch_gemm_bf16(s, H, H, B, d->H2, H, 1, d->dZb, H, 0, g + d->off[4], H, 0.f);
+  launch_colsum(s, B, H, d->dH, g + d->off[5]);
+  launch_gemm_bf16(s, B, H, H, d->dZb, H, 0, W3, H, 1, d->dH, H, 0.f);
+  launch_dgelu(s, (int64_t)B * H, d->dH, d->Z2, d->dZb);
+  // layer 2
+  launch_gemm_bf16(s, H, H, B, d->H1, H, 1, d->dZb, H, 0, g + d->off[2], H, 0.f);
+  launch_colsum(s, B, H, d->dH, g + d->off[3]);
+  launch_gemm_bf16(s, B, H, H, d->dZb, H, 0, W2, H, 1, d->dH, H, 0.f);
+  launch_dgelu(s, (int64_t)B * H, d->dH, d->Z1, d->dZb);
+  // layer 1
+  launch_gemm_bf16(s, PDF_DN_NIN, H, B, d->Xb, PDF_DN_NIN, 1, d->dZb, H, 0, g + d->off[0], H, 0.f);
+  launch_colsum(s, B, H, d->dH, g + d->off[1]);
+  HIPCHK(c, hipGetLastError());
+  if (lr > 0.f) {
+    d->adam_t++;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - (float)std::pow((double)b1, (double)d->adam_t);
+    const float c2 = 1.f - (float)std::pow((double)b2, (double)d->adam_t);
+    launch_adam(s, d->np, d->P, g, d->Mom, d->Vel, d->Pb, lr, b1, b2, 1e-8f, c1, c2);
+    HIPCHK(c, hipGetLastError());
+  }
+  if (loss) {
+    std::vector<float> hp(nb);
+    HIPCHK(c, hipMemcpyAsync(hp.data(), d->part, nb * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    double acc = 0.0;
+    for (float v : hp) acc += v;
+    *loss = (float)(acc / ((double)B * O));
+  }
+  if (grad_host) {
+    HIPCHK(c, hipMemcpyAsync(grad_host, g, d->np * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  return PDF_OK;
+}
+
+pdf_status pdf_denoise_stats(pdf_denoiser *d, double tau, double *out, int32_t on_device,
+                             uint64_t *n_fallback) {
+  if (!d || !out || !(tau >= 0.0)) return PDF_E_INVALID_ARG;
+  pdf_ctx *c = d->ctx;
+  if (!c->seeded) return fail(c, PDF_E_STATE, "no statistics");
+  hipStream_t s = c->stream;
+  const int32_t nn = c->md.nn;
+  launch_features(s, c->md, d->p2p_off, d->p2p, c->latest, d->mu, d->sig, d->feat, nullptr);
+  float *R = (float *)dalloc(c, (size_t)nn * PDF_DN_NOUT * 4);
+  double *res = on_device ? out : (double *)dalloc(c, (size_t)PDF_NSTAT * nn * 8);
+  if (!R || !res) return fail(c, PDF_E_OOM, "denoiser output buffers");
+  pdf_status st = pdf_denoiser_forward(d, d->feat, nn, R);
+  if (st != PDF_OK) return st;
+  HIPCHK(c, hipMemcpyAsync(res, c->latest, (size_t)PDF_NSTAT * nn * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemsetAsync(d->nfall, 0, 8, s));
+  launch_merge(s, nn, c->md.master, c->latest, R, PDF_DN_NOUT, d->scale, tau, c->params.C4, res, d->nfall);
+  HIPCHK(c, hipGetLastError());
+  unsigned long long nf = 0;
+  HIPCHK(c, hipMemcpyAsync(&nf, d->nfall, 8, hipMemcpyDeviceToHost, s));
+  if (!on_device)
+    HIPCHK(c, hipMemcpyAsync(out, res, (size_t)PDF_NSTAT * nn * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (n_fallback) *n_fallback = nf;
+  dfree(c, R);
+  if (!on_device) dfree(c, res);
+  return PDF_OK;
+}
+
+}  // extern "C"

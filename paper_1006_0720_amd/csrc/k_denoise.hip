@@ -1,0 +1,321 @@
+// Learned denoiser of nodal statistics: BF16 matrix-core (MFMA) GEMM and the
+// element-wise kernels of a 4-layer MLP (forward, backward, Adam), the nodal
+// feature kernel and the merge with the plain estimator.
+//
+// Matrix cores: v_mfma_f32_16x16x16bf16_1k computes a 16x16 FP32 tile
+// D = A(16x16) B(16x16) + C over one wave.  Operand layout per lane l:
+//   A: row l%16, columns 4*(l/16) .. +3      B: rows 4*(l/16) .. +3, column l%16
+//   C/D: rows 4*(l/16) .. +3, column l%16
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include "pdf_internal.h"
+
+namespace pdfk {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// round-to-nearest-even binary32 -> bfloat16 bits
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// ---------------------------------------------------------------------------
+// C (MxN, fp32, row-major, ldc) = op(A) op(B) + beta C;  A, B bf16 row-major.
+// op(A)(i,k) = ta ? A[k*lda+i] : A[i*lda+k];  op(B)(k,j) = tb ? B[j*ldb+k] : B[k*ldb+j]
+// Workgroup tile 64x64, four waves of 32x32 (2x2 MFMA tiles), K steps of 16.
+// ---------------------------------------------------------------------------
+constexpr int GT = 64, GK = 16;
+
+__global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const uint16_t *__restrict__ A,
+                                                   int lda, int ta, const uint16_t *__restrict__ B,
+                                                   int ldb, int tb, float *__restrict__ C, int ldc,
+                                                   float beta) {
+  __shared__ uint16_t sA[GT][GK + 4];  // [row i][k]
+  __shared__ uint16_t sB[GK][GT + 4];  // [k][col j]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i0 = blockIdx.y * GT, j0 = blockIdx.x * GT;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  f32x4 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    // stage 64x16 of op(A) and 16x64 of op(B) (four elements per thread each)
+    for (int t = tid; t < GT * GK; t += 256) {
+      const int r = t / GK, k = t % GK;
+      const int gi = i0 + r, gk = k0 + k;
+      uint16_t v = 0;
+      if (gi < M && gk < K) v = ta ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk];
+      sA[r][k] = v;
+      const int kb = t / GT, c = t % GT;
+      const int gj = j0 + c, gkb = k0 + kb;
+      uint16_t w = 0;
+      if (gj < N && gkb < K) w = tb ? B[(size_t)gj * ldb + gkb] : B[(size_t)gkb * ldb + gj];
+      sB[kb][c] = w;
+    }
+    __syncthreads();
+    const int kq = 4 * (lane >> 4), rc = lane & 15;
+    for (int a = 0; a < 2; ++a) {
+      bf16x4 fa;
+      for (int q = 0; q < 4; ++q) fa[q] = (short)sA[wi + 16 * a + rc][kq + q];
+      for (int b = 0; b < 2; ++b) {
+        bf16x4 fb;
+        for (int q = 0; q < 4; ++q) fb[q] = (short)sB[kq + q][wj + 16 * b + rc];
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa, fb, acc[a][b], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  const int rq = 4 * (lane >> 4), cc = lane & 15;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int q = 0; q < 4; ++q) {
+        const int gi = i0 + wi + 16 * a + rq + q, gj = j0 + wj + 16 * b + cc;
+        if (gi < M && gj < N) {
+          float *c = &C[(size_t)gi * ldc + gj];
+          *c = (beta != 0.f ? beta * *c : 0.f) + acc[a][b][q];
+        }
+      }
+}
+
+void launch_gemm_bf16(hipStream_t s, int M, int N, int K, const uint16_t *A, int lda, int ta,
+                      const uint16_t *B, int ldb, int tb, float *C, int ldc, float beta) {
+  dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta);
+}
+
+// ---------------------------------------------------------------------------
+// element-wise pieces of the MLP
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float dgelu(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.3989422804014327f * expf(-0.5f * x * x);
+}
+
+// Z += b (in place, fp32) and H = gelu(Z) (bf16) or H = Z (bf16) when act == 0
+__global__ void k_bias_act(int M, int N, float *Z, const float *b, uint16_t *H, int act) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)M * N) return;
+  const int j = (int)(t % N);
+  const float z = Z[t] + b[j];
+  Z[t] = z;
+  if (H) H[t] = f2bf(act ? gelu(z) : z);
+}
+
+// dZ = dH * gelu'(Z)  (fp32 in, bf16 out; fp32 copy kept in place of dH)
+__global__ void k_dgelu(int64_t n, float *dH, const float *Z, uint16_t *dZb) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const float g = dH[t] * dgelu(Z[t]);
+  dH[t] = g;
+  dZb[t] = f2bf(g);
+}
+
+// column sums of an M x N fp32 matrix (bias gradients): one block per column
+__global__ __launch_bounds__(256) void k_colsum(int M, int N, const float *G, float *out) {
+  __shared__ float red[256];
+  const int j = blockIdx.x;
+  float acc = 0.f;
+  for (int i = threadIdx.x; i < M; i += 256) acc += G[(size_t)i * N + j];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = red[0];
+}
+
+// MSE over the valid outputs: Y (M x ldy, first nout columns), targets T (M x nout)
+// dY = 2 (Y - T) / (M nout) written as fp32 (in place of Y) and bf16; per-block
+// partial losses in part[]
+__global__ __launch_bounds__(256) void k_mse(int M, int nout, int ldy, float *Y, const float *T,
+                                             uint16_t *dYb, float *part) {
+  __shared__ float red[256];
+  const int64_t n = (int64_t)M * ldy;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.f;
+  if (t < n) {
+    const int i = (int)(t / ldy), j = (int)(t % ldy);
+    float g = 0.f;
+    if (j < nout) {
+      const float d = Y[t] - T[(size_t)i * nout + j];
+      l = d * d;
+      g = 2.f * d / ((float)M * (float)nout);
+    }
+    Y[t] = g;
+    dYb[t] = f2bf(g);
+  }
+  red[threadIdx.x] = l;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Adam (Kingma & Ba 2015) on fp32 master parameters; refreshes the bf16 copy
+__global__ void k_adam(int64_t n, float *w, const float *g, float *m, float *v, uint16_t *wb, float lr,
+                       float b1, float b2, float eps, float c1, float c2) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const float gi = g[t];
+  const float mi = b1 * m[t] + (1.f - b1) * gi;
+  const float vi = b2 * v[t] + (1.f - b2) * gi * gi;
+  m[t] = mi;
+  v[t] = vi;
+  const float wi = w[t] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[t] = wi;
+  if (wb) wb[t] = f2bf(wi);
+}
+
+__global__ void k_to_bf16(int64_t n, const float *x, uint16_t *y) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) y[t] = f2bf(x[t]);
+}
+
+static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+void launch_bias_act(hipStream_t s, int M, int N, float *Z, const float *b, uint16_t *H, int act) {
+  hipLaunchKernelGGL(k_bias_act, dim3(nblk((int64_t)M * N)), dim3(256), 0, s, M, N, Z, b, H, act);
+}
+void launch_dgelu(hipStream_t s, int64_t n, float *dH, const float *Z, uint16_t *dZb) {
+  hipLaunchKernelGGL(k_dgelu, dim3(nblk(n)), dim3(256), 0, s, n, dH, Z, dZb);
+}
+void launch_colsum(hipStream_t s, int M, int N, const float *G, float *out) {
+  hipLaunchKernelGGL(k_colsum, dim3(N), dim3(256), 0, s, M, N, G, out);
+}
+int launch_mse(hipStream_t s, int M, int nout, int ldy, float *Y, const float *T, uint16_t *dYb,
+               float *part) {
+  const unsigned nb = nblk((int64_t)M * ldy);
+  hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, s, M, nout, ldy, Y, T, dYb, part);
+  return (int)nb;
+}
+void launch_adam(hipStream_t s, int64_t n, float *w, const float *g, float *m, float *v, uint16_t *wb,
+                 float lr, float b1, float b2, float eps, float c1, float c2) {
+  hipLaunchKernelGGL(k_adam, dim3(nblk(n)), dim3(256), 0, s, n, w, g, m, v, wb, lr, b1, b2, eps, c1, c2);
+}
+void launch_to_bf16(hipStream_t s, int64_t n, const float *x, uint16_t *y) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(nblk(n)), dim3(256), 0, s, n, x, y);
+}
+
+// ---------------------------------------------------------------------------
+// Nodal features for the denoiser.  For each of 8 statistics q (<U>, <V>,
+// <phi>, <uu>, <vv>, <uv>, <phi'^2>, <omega>) at node n: the value, the mean,
+// standard deviation, minimum and maximum over the node and its neighbours
+// (points surrounding points), and the magnitude of the nodal gradient
+// (eq:gradient in the surrounding elements, averaged).  Output row n: 48
+// features, standardised with (x - mu) / sigma, as bf16 and fp32.
+// ---------------------------------------------------------------------------
+__constant__ int kQuant[8] = {0, 1, 4, 5, 6, 8, 11, 3};
+
+__global__ __launch_bounds__(256) void k_features(MeshDev m, const int32_t *p2p_off, const int32_t *p2p,
+                                                  const double *S, const float *mu, const float *sig,
+                                                  float *F, uint16_t *Fb) {
+  const int32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= m.nn) return;
+  const int nn = m.nn;
+  const int32_t q = m.master[n];
+  float f[48];
+  for (int a = 0; a < 8; ++a) {
+    const int fld = kQuant[a];
+    const double v0 = S[(size_t)fld * nn + q];
+    double sum = v0, sum2 = v0 * v0, mn = v0, mx = v0;
+    int c = 1;
+    for (int32_t i = p2p_off[q]; i < p2p_off[q + 1]; ++i) {
+      const double v = S[(size_t)fld * nn + p2p[i]];
+      sum += v;
+      sum2 += v * v;
+      mn = v < mn ? v : mn;
+      mx = v > mx ? v : mx;
+      c++;
+    }
+    const double mean = sum / c;
+    double var = sum2 / c - mean * mean;
+    var = var > 0.0 ? var : 0.0;
+    double gx = 0.0, gy = 0.0;
+    int ce = 0;
+    for (int32_t i = m.m2e_off[q]; i < m.m2e_off[q + 1]; ++i) {
+      const int32_t e = m.m2e[i];
+      const double *d = m.dN + 6 * (size_t)e;
+      for (int k = 0; k < 3; ++k) {
+        const double val = S[(size_t)fld * nn + m.mnode[3 * e + k]];
+        gx += d[k] * val;
+        gy += d[3 + k] * val;
+      }
+      ce++;
+    }
+    if (ce) {
+      gx /= ce;
+      gy /= ce;
+    }
+    f[6 * a + 0] = (float)v0;
+    f[6 * a + 1] = (float)mean;
+    f[6 * a + 2] = (float)sqrt(var);
+    f[6 * a + 3] = (float)mn;
+    f[6 * a + 4] = (float)mx;
+    f[6 * a + 5] = (float)sqrt(gx * gx + gy * gy);
+  }
+  for (int k = 0; k < 48; ++k) {
+    const float z = mu ? (f[k] - mu[k]) / sig[k] : f[k];
+    F[(size_t)n * 48 + k] = z;
+    if (Fb) Fb[(size_t)n * 48 + k] = f2bf(z);
+  }
+}
+
+void launch_features(hipStream_t s, const MeshDev &m, const int32_t *p2p_off, const int32_t *p2p,
+                     const double *S, const float *mu, const float *sig, float *F, uint16_t *Fb) {
+  hipLaunchKernelGGL(k_features, dim3((m.nn + 255) / 256), dim3(256), 0, s, m, p2p_off, p2p, S, mu, sig,
+                     F, Fb);
+}
+
+// Merge: q = q_plain + scale_q * r_q, except where |scale_q r_q| exceeds tau
+// times the plain estimator's standard error at the node (then q = q_plain).
+// Standard errors from the plain second moments and the particle support N:
+// <U>: sqrt(<uu>/N), <V>: sqrt(<vv>/N), <phi>: sqrt(<phi'^2>/N), second
+// moments s: s sqrt(2/N), <uv>: sqrt((<uu><vv> + <uv>^2)/N), <omega>: <omega>
+// sqrt(C4/N).  out starts as a copy of the plain statistics.
+__global__ void k_merge(int nn, const int32_t *master, const double *S, const float *R, int ldr,
+                        const float *scale, double tau, double C4, double *out, unsigned long long *nfall) {
+  const int32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  int fb = 0;
+  if (n < nn) {
+    const int32_t q = master[n];
+    const double N = S[24 * (size_t)nn + q];
+    const double uu = S[5 * (size_t)nn + q], vv = S[6 * (size_t)nn + q], uv = S[8 * (size_t)nn + q];
+    const double pp = S[11 * (size_t)nn + q], om = S[3 * (size_t)nn + q];
+    const double iN = N > 0.0 ? 1.0 / N : 1.0;
+    double se[8];
+    se[0] = sqrt(fabs(uu) * iN);
+    se[1] = sqrt(fabs(vv) * iN);
+    se[2] = sqrt(fabs(pp) * iN);
+    se[3] = fabs(uu) * sqrt(2.0 * iN);
+    se[4] = fabs(vv) * sqrt(2.0 * iN);
+    se[5] = sqrt((fabs(uu * vv) + uv * uv) * iN);
+    se[6] = fabs(pp) * sqrt(2.0 * iN);
+    se[7] = fabs(om) * sqrt(C4 * iN);
+    for (int a = 0; a < 8; ++a) {
+      const int fld = kQuant[a];
+      const double corr = (double)scale[a] * (double)R[(size_t)n * ldr + a];
+      if (fabs(corr) <= tau * se[a])
+        out[(size_t)fld * nn + n] = S[(size_t)fld * nn + q] + corr;
+      else
+        fb++;
+    }
+  }
+  if (nfall && fb) atomicAdd(nfall, (unsigned long long)fb);
+}
+
+void launch_merge(hipStream_t s, int nn, const int32_t *master, const double *S, const float *R, int ldr,
+                  const float *scale, double tau, double C4, double *out, unsigned long long *nfall) {
+  hipLaunchKernelGGL(k_merge, dim3((nn + 255) / 256), dim3(256), 0, s, nn, master, S, R, ldr, scale, tau,
+                     C4, out, nfall);
+}
+
+}  // namespace pdfk

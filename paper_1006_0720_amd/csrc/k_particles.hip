@@ -289,7 +289,18 @@ void launch_elem_prep(hipStream_t s, const MeshDev &m, const ModelDev &md, const
 constexpr int TAB = 1 << PDF_TAB_LOG2;  // LDS table slots per workgroup (power of two)
 constexpr int NCOPY = PDF_TAB_COPIES;    // accumulator copies (lane % NCOPY picks one)
 constexpr int WG = 256;                  // threads per workgroup of the particle kernels
-constexpr int PPT = PDF_PPT;             // particles per thread: chunk of WG*PPT particles
+constexpr int PPT = PDF_PPT;             // most particles per thread: chunk of WG*ppt particles
+
+// Particles per thread for np particles: PPT when the grid still has at least
+// MIN_WGS workgroups, else halved until it does (or 1).  Small problems then
+// spread over more waves, which hides the latency of the per-particle
+// dependent loads; large ones amortise the table set-up and flush.
+constexpr int64_t MIN_WGS = 2048;
+inline int pick_ppt(int64_t np) {
+  int ppt = PPT;
+  while (ppt > 1 && (np + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt) < MIN_WGS) ppt >>= 1;
+  return ppt;
+}
 
 // One key array and NCOPY copies of the accumulators: lanes of a wave that add
 // to the same element (typically the particles that stayed in their host)
@@ -371,12 +382,13 @@ __device__ __forceinline__ void table_flush(SumTable &t, double *sums) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(WG) void k_accumulate(PartDev<T> p, int64_t np, const T *rec, double *sums) {
+__global__ __launch_bounds__(WG) void k_accumulate(PartDev<T> p, int64_t np, int ppt, const T *rec,
+                                                   double *sums) {
   __shared__ SumTable tab;
   table_init(tab);
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * (WG * PPT);
-  for (int j = 0; j < PPT; ++j) {
+  const int64_t base = (int64_t)blockIdx.x * WG * ppt;
+  for (int j = 0; j < ppt; ++j) {
     const int64_t i = base + (int64_t)j * WG + threadIdx.x;
     if (i < np) table_add<T>(tab, sums, rec, p.e[i], p.u[i], p.v[i], p.w[i], p.om[i], p.psi[i]);
   }
@@ -385,8 +397,9 @@ __global__ __launch_bounds__(WG) void k_accumulate(PartDev<T> p, int64_t np, con
 
 template <typename T>
 void launch_accumulate(hipStream_t s, PartDev<T> p, int64_t np, const T *rec, double *sums) {
-  hipLaunchKernelGGL(k_accumulate<T>, dim3((unsigned)((np + WG * PPT - 1) / (WG * PPT))), dim3(WG), 0,
-                     s, p, np, rec, sums);
+  const int ppt = pick_ppt(np);
+  hipLaunchKernelGGL(k_accumulate<T>, dim3((unsigned)((np + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt))),
+                     dim3(WG), 0, s, p, np, ppt, rec, sums);
 }
 
 // reference means from a first accumulation pass made with zero references
@@ -450,7 +463,7 @@ __device__ __forceinline__ void noslip(const ModelDev &md, const T *r, double nx
 
 template <typename T, bool VISC, bool WALLB>
 __global__ __launch_bounds__(WG) void k_advance(const KArgs *__restrict__ ka, PartDev<T> p, int64_t np,
-                                                const T *__restrict__ rec, double *sums, uint32_t k0,
+                                                int ppt, const T *__restrict__ rec, double *sums, uint32_t k0,
                                                 uint32_t k1, uint32_t step, double dt, double sdt,
                                                 double s2nu, unsigned long long *cnt) {
   __shared__ SumTable tab;
@@ -459,7 +472,7 @@ __global__ __launch_bounds__(WG) void k_advance(const KArgs *__restrict__ ka, Pa
   table_init(tab);
   __syncthreads();
   uint64_t ca = 0, cb = 0;
-  const int64_t base = (int64_t)blockIdx.x * (WG * PPT);
+  const int64_t base = (int64_t)blockIdx.x * WG * ppt;
   // software pipeline: the state of the thread's next particle is loaded
   // while the current one is advanced
   int32_t n_e = 0;
@@ -479,7 +492,7 @@ __global__ __launch_bounds__(WG) void k_advance(const KArgs *__restrict__ ka, Pa
       n_psi = p.psi[i0];
     }
   }
-  for (int jj = 0; jj < PPT; ++jj) {
+  for (int jj = 0; jj < ppt; ++jj) {
     const int64_t i = base + (int64_t)jj * WG + threadIdx.x;
     if (i >= np) break;
     const int32_t e0 = n_e;
@@ -487,7 +500,7 @@ __global__ __launch_bounds__(WG) void k_advance(const KArgs *__restrict__ ka, Pa
     const double x0 = (double)n_x, y0 = (double)n_y;
     const T up0 = n_u, up1 = n_v, up2 = n_w, om = n_om, psi = n_psi;
     const int64_t inx = i + WG;
-    if (jj + 1 < PPT && inx < np) {
+    if (jj + 1 < ppt && inx < np) {
       n_e = p.e[inx];
       n_id = p.id[inx];
       n_x = p.x[inx];
@@ -744,19 +757,20 @@ template <typename T>
 void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
                     const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
                     unsigned long long *cnt) {
-  const unsigned grid = (unsigned)((np + WG * PPT - 1) / (WG * PPT));
+  const int ppt = pick_ppt(np);
+  const unsigned grid = (unsigned)((np + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt));
   const bool visc = md.nu > 0.0;
   const bool wallb = visc && md.wall_b;
   const double sdt = sqrt(dt), s2nu = sqrt(2.0 * md.nu);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   if (visc && wallb)
-    hipLaunchKernelGGL((k_advance<T, true, true>), dim3(grid), dim3(WG), 0, s, dka, p, np, rec, sums,
+    hipLaunchKernelGGL((k_advance<T, true, true>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt, rec, sums,
                        k0, k1, step, dt, sdt, s2nu, cnt);
   else if (visc)
-    hipLaunchKernelGGL((k_advance<T, true, false>), dim3(grid), dim3(WG), 0, s, dka, p, np, rec, sums,
+    hipLaunchKernelGGL((k_advance<T, true, false>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt, rec, sums,
                        k0, k1, step, dt, sdt, s2nu, cnt);
   else
-    hipLaunchKernelGGL((k_advance<T, false, false>), dim3(grid), dim3(WG), 0, s, dka, p, np, rec, sums,
+    hipLaunchKernelGGL((k_advance<T, false, false>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt, rec, sums,
                        k0, k1, step, dt, sdt, s2nu, cnt);
 }
 

@@ -109,3 +109,21 @@ template <typename T>
 void launch_unpack_state(hipStream_t s, PartDev<T> p, int64_t np, const double *in);
 
 }  // namespace pdfk
+
+namespace pdfk {
+// ---- denoiser kernels (k_denoise.hip) ----
+void launch_gemm_bf16(hipStream_t s, int M, int N, int K, const uint16_t *A, int lda, int ta,
+                      const uint16_t *B, int ldb, int tb, float *C, int ldc, float beta);
+void launch_bias_act(hipStream_t s, int M, int N, float *Z, const float *b, uint16_t *H, int act);
+void launch_dgelu(hipStream_t s, int64_t n, float *dH, const float *Z, uint16_t *dZb);
+void launch_colsum(hipStream_t s, int M, int N, const float *G, float *out);
+int launch_mse(hipStream_t s, int M, int nout, int ldy, float *Y, const float *T, uint16_t *dYb,
+               float *part);
+void launch_adam(hipStream_t s, int64_t n, float *w, const float *g, float *m, float *v, uint16_t *wb,
+                 float lr, float b1, float b2, float eps, float c1, float c2);
+void launch_to_bf16(hipStream_t s, int64_t n, const float *x, uint16_t *y);
+void launch_features(hipStream_t s, const MeshDev &m, const int32_t *p2p_off, const int32_t *p2p,
+                     const double *S, const float *mu, const float *sig, float *F, uint16_t *Fb);
+void launch_merge(hipStream_t s, int nn, const int32_t *master, const double *S, const float *R, int ldr,
+                  const float *scale, double tau, double C4, double *out, unsigned long long *nfall);
+}  // namespace pdfk

@@ -1,0 +1,204 @@
+"""Training and evaluation of the learned denoiser, all on the GPU.
+
+Data: pairs of runs of the same workload that share the initial fields and
+the scalar source position but differ in particle seed and in particles per
+element: a low count (network input) and a high count (target).  After a
+spin-up, snapshots of the nodal statistics are taken every few steps.  The
+network learns the correction (high - low) of 8 nodal statistics from 48
+features of the low-count estimate; the plain estimator stays the fallback.
+
+With frozen=True (default) the model coefficients of every run come from one
+fixed field: the high-count estimate of the seeded initial state.  Low- and
+high-count runs then sample the same particle process, so their statistics
+differ only by estimator noise and bias.  Fed-back statistics at low counts
+need the mean-pressure projection and particle redistribution of the full
+method (elements drain to one particle, k -> 0 and the generalized Langevin
+drift, proportional to 1/k, diverges).
+
+Evaluation on held-out pairs, per statistic q normalised by the RMS error of
+the plain low-count estimate against the high-count reference:
+  E_plain(ppe) for several particle counts (fitted as E^2 = a/ppe + a/ppe_ref,
+  the second term being the reference's own noise), E_learned at the low
+  count, the particle count ppe_eq at which the plain estimator reaches
+  E_learned, and the cost ratio T_plain(ppe_eq) / (T_plain(low) + T_denoise)
+  with measured step and denoiser times.
+"""
+from __future__ import annotations
+
+import json
+import time
+
+import numpy as np
+
+from . import _lib
+from .runner import workload_context
+
+QUANT = [0, 1, 4, 5, 6, 8, 11, 3]
+
+
+def _run(make_workload, ppe, seed, src, steps_spin, n_snap, every, frozen_field=None, reorder_every=4):
+    """Advance one run; returns the snapshots of nodal statistics (torch,
+    device) and the measured time per step."""
+    import torch
+
+    w = make_workload(ppe=ppe, seed=seed, src=src)
+    if frozen_field is not None:
+        w.params = dict(w.params, frozen=1)
+    ctx = workload_context(w, reorder_every=reorder_every)
+    if frozen_field is not None:
+        ctx.set_nodal_field(_lib.FIELD_STATS, frozen_field)
+    ctx.advance(steps_spin, w.dt)
+    snaps = []
+    t_adv = 0.0
+    for _ in range(n_snap):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.advance(every, w.dt)
+        torch.cuda.synchronize()
+        t_adv += time.perf_counter() - t0
+        snaps.append(ctx.stats_device())
+    t_step = t_adv / (n_snap * every)
+    cnt = ctx.counters()
+    return ctx, w, snaps, t_step, cnt
+
+
+def _sources(rng, n, box):
+    x0, x1, y0, y1, r = box
+    return [(float(rng.uniform(x0, x1)), float(rng.uniform(y0, y1)), r) for _ in range(n)]
+
+
+def study(make_workload, n_train=12, n_test=3, ppe_low=10, ppe_high=200, eval_ppes=(20, 40, 80),
+          steps_spin=100, n_snap=5, every=10, hidden=128, train_steps=2000, batch=8192, lr=1e-3,
+          tau=3.0, seed=0, source_box=(4.0, 16.0, 3.5, 6.5, 0.3), frozen=True, log=print):
+    """make_workload(ppe=, seed=, src=(x, y, r)) -> workload (see runner);
+    source_box = (x0, x1, y0, y1, r): disc sources uniform in the box."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    srcs = _sources(rng, n_train + n_test, source_box)
+    F = None
+    if frozen:
+        w_ref = make_workload(ppe=ppe_high, seed=seed + 77, src=srcs[0])
+        c_ref = workload_context(w_ref)
+        F = c_ref.stats_device()
+        c_ref.close()
+    feats, targs, lows, highs = [], [], [], []
+    dn = None
+    ctx_keep = None
+    t_low = []
+    for r in range(n_train + n_test):
+        c_lo, w, s_lo, tl, _ = _run(make_workload, ppe_low, 1000 + r, srcs[r], steps_spin, n_snap, every, F)
+        t_low.append(tl)
+        c_hi, _, s_hi, _, _ = _run(make_workload, ppe_high, 5000 + r, srcs[r], steps_spin, n_snap, every, F)
+        c_hi.close()
+        if dn is None:
+            dn = _lib.Denoiser(c_lo, hidden=hidden, seed=seed)
+            ctx_keep = c_lo
+        for a, b in zip(s_lo, s_hi):
+            f = dn.features(a)  # raw features of the low-count estimate
+            if r < n_train:
+                feats.append(f)
+                targs.append((b[QUANT] - a[QUANT]).T.float())
+            lows.append((r, a))
+            highs.append((r, b))
+        if c_lo is not ctx_keep:
+            c_lo.close()
+        log(f"[denoise] run {r + 1}/{n_train + n_test} done (low-count step {tl * 1e3:.3f} ms)")
+    X = torch.cat(feats)
+    T = torch.cat(targs)
+    mu = X.mean(0)
+    sig = X.std(0).clamp_min(1e-12)
+    scale = T.std(0).clamp_min(1e-12)
+    dn.set_norm(mu.cpu().numpy(), sig.cpu().numpy(), scale.cpu().numpy())
+    Xs = ((X - mu) / sig).contiguous()
+    Ts = (T / scale).contiguous()
+    n = Xs.shape[0]
+    gen = torch.Generator(device=Xs.device)
+    gen.manual_seed(seed)
+    t0 = time.perf_counter()
+    losses = []
+    for it in range(train_steps):
+        idx = torch.randint(0, n, (batch,), device=Xs.device, generator=gen)
+        cur_lr = lr * (0.1 ** (it / max(1, train_steps)))
+        losses.append(dn.train_step(Xs[idx], Ts[idx], cur_lr))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"[denoise] trained {train_steps} steps in {t_train:.1f} s, loss {losses[0]:.4f} -> "
+        f"{np.mean(losses[-50:]):.4f}")
+
+    # ---- evaluation on held-out pairs ----
+    def rms_err(est, ref, valid):
+        return np.array([np.sqrt(np.mean(((est[f] - ref[f])[valid]) ** 2)) for f in QUANT])
+
+    test_runs = range(n_train, n_train + n_test)
+    e_plain10, e_learn, e_learn_nofb, rej = [], [], [], []
+    t_den, n_fall = [], []
+    for r in test_runs:
+        pairs = [(a, b) for (ra, a), (rb, b) in zip(lows, highs) if ra == r]
+        for a, b in pairs:
+            plain = a.cpu().numpy()
+            ref = b.cpu().numpy()
+            valid = plain[24] > 0
+            # denoise this snapshot through the C ABI (features of 'a')
+            ctx_keep.set_nodal_field(_lib.FIELD_STATS, a)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            den, nf = dn.denoise(tau, device=True)
+            t_den.append(time.perf_counter() - t1)
+            n_fall.append(nf)
+            den_all, _ = dn.denoise(float("inf"), device=True)
+            e_plain10.append(rms_err(plain, ref, valid))
+            e_learn.append(rms_err(den.cpu().numpy(), ref, valid))
+            e_learn_nofb.append(rms_err(den_all.cpu().numpy(), ref, valid))
+            d_np = den.cpu().numpy()
+            rej.append([float(np.mean(d_np[f] == plain[f])) for f in QUANT])
+    norm = np.mean(e_plain10, axis=0)
+    E_plain_low = 1.0
+    E_learned = float(np.mean(np.mean(e_learn, axis=0) / norm))
+    E_learned_nofb = float(np.mean(np.mean(e_learn_nofb, axis=0) / norm))
+    # plain estimator at more particles per element on the same held-out sources
+    E_plain = {ppe_low: E_plain_low}
+    T_plain = {ppe_low: float(np.mean(t_low))}
+    for ppe in eval_ppes:
+        errs, ts = [], []
+        for r in test_runs:
+            c, _, s, tstep, _ = _run(make_workload, ppe, 9000 + r, srcs[r], steps_spin, n_snap, every, F)
+            c.close()
+            ts.append(tstep)
+            hs = [b for (rb, b) in highs if rb == r]
+            for a, b in zip(s, hs):
+                A, Bn = a.cpu().numpy(), b.cpu().numpy()
+                errs.append(rms_err(A, Bn, A[24] > 0))
+        E_plain[ppe] = float(np.mean(np.mean(errs, axis=0) / norm))
+        T_plain[ppe] = float(np.mean(ts))
+        log(f"[denoise] plain error at {ppe} particles/element: {E_plain[ppe]:.4f}")
+    # fit E^2 = a (1/ppe + 1/ppe_high) (reference noise included)
+    ps = np.array(sorted(E_plain))
+    es = np.array([E_plain[p] for p in ps])
+    xfit = 1.0 / ps + 1.0 / ppe_high
+    a_fit = float(np.sum(xfit * es ** 2) / np.sum(xfit * xfit))
+    inv = E_learned ** 2 / a_fit - 1.0 / ppe_high
+    ppe_eq = float(1.0 / inv) if inv > 0 else float("inf")
+    # step time linear in particle count
+    pt = np.array(sorted(T_plain))
+    tt = np.array([T_plain[p] for p in pt])
+    slope, icpt = np.polyfit(pt, tt, 1)
+    t_eq = float(slope * ppe_eq + icpt) if np.isfinite(ppe_eq) else float("inf")
+    t_dn = float(np.median(t_den))
+    ratio = t_eq / (T_plain[ppe_low] + t_dn)
+    out = {"E_plain": E_plain, "E_learned": E_learned, "E_learned_no_fallback": E_learned_nofb, "ppe_eq": ppe_eq, "a_fit": a_fit,
+           "T_plain_s": T_plain, "T_denoise_s": t_dn, "cost_ratio": ratio,
+           "per_statistic_ratio": (np.mean(e_learn, axis=0) / norm).tolist(),
+           "per_statistic_ratio_no_fallback": (np.mean(e_learn_nofb, axis=0) / norm).tolist(),
+           "per_statistic_rejected_fraction": np.mean(rej, axis=0).tolist(),
+           "statistics": ["U", "V", "phi", "uu", "vv", "uv", "phi'^2", "omega"],
+           "train_loss_first": float(losses[0]), "train_loss_last": float(np.mean(losses[-50:])),
+           "train_seconds": t_train, "n_train_samples": int(n), "hidden": hidden,
+           "n_train_runs": n_train, "n_test_runs": n_test, "ppe_low": ppe_low, "ppe_high": ppe_high,
+           "frozen_coefficients": bool(frozen), "steps_spin": steps_spin, "n_snap": n_snap, "every": every,
+           "tau": tau, "fallback_fraction": float(np.mean(n_fall)) / (8.0 * ctx_keep.n_nodes)}
+    params = dn.params()
+    norm_arrays = dn.norm
+    dn.close()
+    ctx_keep.close()
+    return out, params, norm_arrays

@@ -1,0 +1,139 @@
+"""GPU tests of the learned denoiser through the C ABI: the BF16 matrix-core
+forward pass and gradients against the FP64 reference (same bfloat16-rounded
+weights, inputs and stored activations), training on a fixed batch, the
+nodal features, and the merge rule with the plain-estimator fallback.
+
+Tolerances: the kernels accumulate in FP32 where the reference uses FP64, so
+an activation can round to the neighbouring bfloat16 value (2^-8 relative) when
+it lies within ~1e-7 of a rounding boundary; a few such flips bound the
+norm-wise difference at ~1e-3 for outputs and ~1e-2 per gradient tensor.
+"""
+import numpy as np
+import pytest
+
+import oracle.mlp as M
+from synth import configs as CF
+from synth import meshes as MS
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1006_0720_amd import _lib
+    from paper_1006_0720_amd.runner import workload_context
+
+    w = CF.periodic_square(n=8, ppe=20)
+    ctx = workload_context(w)
+    return torch, _lib, ctx, w
+
+
+def _tensors(torch, x, t):
+    return (torch.tensor(x, dtype=torch.float32, device="cuda"),
+            torch.tensor(t, dtype=torch.float32, device="cuda"))
+
+
+def _layer_slices(h):
+    sizes = [48 * h, h, h * h, h, h * h, h, h * 8, 8]
+    o = np.cumsum([0] + sizes)
+    return [slice(o[i], o[i + 1]) for i in range(8)]
+
+
+@pytest.mark.parametrize("h,B", [(32, 100), (128, 1000)])
+def test_forward_matches_reference(env, h, B):
+    torch, L, ctx, w = env
+    dn = L.Denoiser(ctx, hidden=h, seed=3)
+    p = dn.params().astype(np.float64)
+    rng = np.random.default_rng(h)
+    x = rng.normal(size=(B, 48)).astype(np.float32)
+    y = dn.forward(torch.tensor(x, device="cuda")).cpu().numpy()
+    yr, _ = M.forward(p, h, x.astype(np.float64), bf16_storage=True)
+    assert np.linalg.norm(y - yr) <= 2e-3 * np.linalg.norm(yr)
+    assert np.abs(y - yr).max() <= 2e-2 * np.abs(yr).max()
+    dn.close()
+
+
+@pytest.mark.parametrize("h,B", [(32, 64), (128, 777)])
+def test_gradients_match_reference(env, h, B):
+    torch, L, ctx, w = env
+    dn = L.Denoiser(ctx, hidden=h, seed=5)
+    p = dn.params().astype(np.float64)
+    rng = np.random.default_rng(7)
+    x = rng.normal(size=(B, 48)).astype(np.float32)
+    t = rng.normal(size=(B, 8)).astype(np.float32)
+    xt, tt = _tensors(torch, x, t)
+    loss, g = dn.train_step(xt, tt, 0.0, want_grad=True)
+    lr_, gr = M.loss_and_grad(p, h, x.astype(np.float64), t.astype(np.float64), bf16_storage=True)
+    assert abs(loss - lr_) <= 1e-3 * lr_
+    for sl in _layer_slices(h):
+        a, b = g[sl], gr[sl]
+        assert np.linalg.norm(a - b) <= 1e-2 * np.linalg.norm(b) + 1e-7
+    assert np.array_equal(dn.params(), p.astype(np.float32))  # lr = 0: no update
+    dn.close()
+
+
+def test_training_reduces_loss_on_a_fixed_batch(env):
+    torch, L, ctx, w = env
+    dn = L.Denoiser(ctx, hidden=64, seed=1)
+    rng = np.random.default_rng(11)
+    x = rng.normal(size=(512, 48)).astype(np.float32)
+    t = np.tanh(x[:, :8] * 0.7 + 0.3 * x[:, 8:16] * x[:, 16:24]).astype(np.float32)
+    xt, tt = _tensors(torch, x, t)
+    l0 = dn.train_step(xt, tt, 0.0)
+    for _ in range(400):
+        dn.train_step(xt, tt, 3e-3)
+    l1 = dn.train_step(xt, tt, 0.0)
+    assert l1 < 0.1 * l0, (l0, l1)
+    dn.close()
+
+
+def test_features_match_reference(env):
+    torch, L, ctx, w = env
+    mesh = w.mesh
+    dn = L.Denoiser(ctx, hidden=32)
+    rng = np.random.default_rng(2)
+    st = rng.normal(size=(25, mesh.n_nodes))
+    st[:, :] = st[:, mesh.node_master]
+    F = dn.features(torch.tensor(st, device="cuda")).cpu().numpy()
+    Fr = M.features(mesh, st)
+    assert np.abs(F - Fr).max() <= 1e-5 * (np.abs(Fr).max() + 1.0)
+    dn.close()
+
+
+def test_merge_zero_network_and_fallback(env):
+    torch, L, ctx, w = env
+    dn = L.Denoiser(ctx, hidden=32)
+    plain = ctx.stats()
+    dn.set_params(np.zeros(dn.n_param, np.float32))
+    out, nf = dn.denoise(tau=3.0)
+    assert np.array_equal(out, plain) and nf == 0
+    # a constant output of 1 with a huge scale: every correction is rejected
+    p = np.zeros(dn.n_param, np.float32)
+    p[-8:] = 1.0
+    dn.set_params(p)
+    dn.set_norm(np.zeros(48), np.ones(48), np.full(8, 1e6))
+    out, nf = dn.denoise(tau=3.0)
+    assert np.array_equal(out, plain) and nf == 8 * ctx.n_nodes
+    # a small scale: a correction is accepted wherever the plain standard error
+    # is non-zero (and then equals the scale); where the plain estimate has no
+    # spread (e.g. a uniform scalar) the standard error is 0 and it is rejected
+    dn.set_norm(np.zeros(48), np.ones(48), np.full(8, 1e-9))
+    out, nf = dn.denoise(tau=3.0)
+    N = plain[24]
+    se = {0: np.sqrt(np.abs(plain[5]) / N), 1: np.sqrt(np.abs(plain[6]) / N),
+          4: np.sqrt(np.abs(plain[11]) / N), 5: np.abs(plain[5]) * np.sqrt(2 / N),
+          6: np.abs(plain[6]) * np.sqrt(2 / N), 8: np.sqrt((np.abs(plain[5] * plain[6]) + plain[8] ** 2) / N),
+          11: np.abs(plain[11]) * np.sqrt(2 / N), 3: np.abs(plain[3]) * np.sqrt(0.25 / N)}
+    rejected = 0
+    for fld in M.QUANT:
+        d = out[fld] - plain[fld]
+        acc = se[fld] * 3.0 >= 1e-9 * (1 + 1e-6)
+        assert np.allclose(d[acc], 1e-9, rtol=1e-6, atol=0)
+        assert np.all(d[se[fld] * 3.0 < 1e-9 * (1 - 1e-6)] == 0)
+        rejected += int((se[fld] * 3.0 < 1e-9 * (1 - 1e-6)).sum())
+    assert nf == rejected
+    dn.close()
