@@ -71,7 +71,7 @@ def lib():
 
 class _Params(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("model", "wp_source", "omega_source", "tm_mode", "frozen",
-                                         "wall_b", "store_fp32", "pad")] + \
+                                         "wall_b", "store_fp32", "stats_mode")] + \
                [(n, C.c_double) for n in ("C0", "C1", "C2", "C3", "C4", "CT", "CL", "Ceta", "Cv",
                                           "gamma5", "Cw1", "Cw2", "Cphi", "nu", "k_floor",
                                           "src_x", "src_y", "src_r")]
@@ -93,8 +93,8 @@ def _params(params: dict, store_fp32: bool):
     for name, _ in _Params._fields_:
         if name == "store_fp32":
             p.store_fp32 = int(store_fp32)
-        elif name == "pad":
-            p.pad = 0
+        elif name == "stats_mode":
+            p.stats_mode = int(params.get("stats_mode", 0))
         else:
             setattr(p, name, params[name])
     return p

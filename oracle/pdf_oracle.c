@@ -327,21 +327,40 @@ static double sym(const double R[6], int i, int j) {
   return R[idx[i][j]];
 }
 
+/* Value over element e of a nodal field f (values a[f*nn + node]): with w ==
+ * NULL the element average of its three nodal values (Fig. mesh-particles);
+ * otherwise the shape-function combination sum_j N^j q_j of eq:approximation
+ * with N^j = w[j]. */
+static double nodal_at(const double *a, int32_t nn, int f, const int32_t mk[3], const double *w) {
+  const double *q = a + (size_t)f * (size_t)nn;
+  if (!w) return (q[mk[0]] + q[mk[1]] + q[mk[2]]) / 3.0;
+  return w[0] * q[mk[0]] + w[1] * q[mk[1]] + w[2] * q[mk[2]];
+}
+
+/* Shape-function values N^j of point (x, y) in element e: the area
+ * coordinates, i.e. each signed area of eq:element-test over their sum. */
+static void shape_values(const or_mesh *m, int32_t e, double x, double y, double w[3]) {
+  double lam[3];
+  or_lambdas(m, e, x, y, lam);
+  double s = lam[0] + lam[1] + lam[2];
+  for (int k = 0; k < 3; ++k) w[k] = lam[k] / s;
+}
+
+/* Statistics and coefficients for the particles of element e: from the
+ * element average of the nodal values (w == NULL, the paper's reading) or
+ * from their shape-function values at one particle position (w = N^j). */
 static void elem_record(const or_mesh *m, const or_params *p, const double *stats, const double *wp,
-                        const double *gradp, int32_t e, orec *r) {
+                        const double *gradp, int32_t e, const double *w, orec *r) {
   int32_t nn = m->nn;
   int32_t mk[3];
   for (int k = 0; k < 3; ++k) mk[k] = m->master[m->en[3 * e + k]];
   memset(r, 0, sizeof(*r));
-  for (int i = 0; i < 3; ++i) r->U[i] = (S(i, mk[0]) + S(i, mk[1]) + S(i, mk[2])) / 3.0;
-  r->Om = (S(3, mk[0]) + S(3, mk[1]) + S(3, mk[2])) / 3.0;
-  r->Phi = (S(4, mk[0]) + S(4, mk[1]) + S(4, mk[2])) / 3.0;
-  for (int i = 0; i < 6; ++i) r->R[i] = (S(5 + i, mk[0]) + S(5 + i, mk[1]) + S(5 + i, mk[2])) / 3.0;
-  for (int i = 0; i < 3; ++i) r->lap[i] = (S(21 + i, mk[0]) + S(21 + i, mk[1]) + S(21 + i, mk[2])) / 3.0;
-  for (int i = 0; i < 2; ++i)
-    r->gp[i] = gradp ? (gradp[(size_t)i * nn + mk[0]] + gradp[(size_t)i * nn + mk[1]] +
-                        gradp[(size_t)i * nn + mk[2]]) / 3.0
-                     : 0.0;
+  for (int i = 0; i < 3; ++i) r->U[i] = nodal_at(stats, nn, i, mk, w);
+  r->Om = nodal_at(stats, nn, 3, mk, w);
+  r->Phi = nodal_at(stats, nn, 4, mk, w);
+  for (int i = 0; i < 6; ++i) r->R[i] = nodal_at(stats, nn, 5 + i, mk, w);
+  for (int i = 0; i < 3; ++i) r->lap[i] = nodal_at(stats, nn, 21 + i, mk, w);
+  for (int i = 0; i < 2; ++i) r->gp[i] = gradp ? nodal_at(gradp, nn, i, mk, w) : 0.0;
   /* eq:gradient with the precomputed shape-function derivatives */
   for (int i = 0; i < 3; ++i) {
     double gx = 0.0, gy = 0.0;
@@ -374,10 +393,7 @@ static void elem_record(const or_mesh *m, const or_params *p, const double *stat
     /* eq:GandC with the element average of the nodal tensor wp_ij */
     double W[3][3];
     for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) {
-        size_t f = (size_t)(3 * i + j);
-        W[i][j] = (wp[f * nn + mk[0]] + wp[f * nn + mk[1]] + wp[f * nn + mk[2]]) / 3.0;
-      }
+      for (int j = 0; j < 3; ++j) W[i][j] = nodal_at(wp, nn, 3 * i + j, mk, w);
     double wr = 0.0;
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
@@ -497,7 +513,6 @@ void or_derivatives(const or_mesh *m, double *stats) {
 void or_estimate(const or_mesh *m, const or_params *p, int64_t np, const double *state,
                  const int32_t *elem, const double *prev, double *stats, double *elem_out,
                  uint64_t *cnt) {
-  (void)p;
   int32_t ne = m->ne, nn = m->nn;
   const double *q[5] = {state + 2 * np, state + 3 * np, state + 4 * np, state + 5 * np, state + 6 * np};
   double *N = (double *)calloc((size_t)ne, sizeof(double));
@@ -527,6 +542,54 @@ void or_estimate(const or_mesh *m, const or_params *p, int64_t np, const double 
       for (int f = 0; f < 5; ++f) elem_out[(size_t)(1 + f) * ne + e] = mean[5 * e + f];
       for (int c = 0; c < 10; ++c) elem_out[(size_t)(6 + c) * ne + e] = cov[10 * e + c];
     }
+  }
+  if (p && p->stats_mode == 1) {
+    /* SHAPE: node n gathers every particle of the elements around it, each
+     * with weight N^n at the particle's position (eq:approximation used as a
+     * scatter): weighted means, then weighted central second moments. */
+    double *W = (double *)calloc((size_t)nn, sizeof(double));
+    double *M = (double *)calloc((size_t)nn * 5, sizeof(double));
+    double *CV = (double *)calloc((size_t)nn * 10, sizeof(double));
+    for (int64_t i = 0; i < np; ++i) {
+      double w[3];
+      shape_values(m, elem[i], state[i], state[np + i], w);
+      for (int k = 0; k < 3; ++k) {
+        int32_t n = m->master[m->en[3 * elem[i] + k]];
+        W[n] += w[k];
+        for (int f = 0; f < 5; ++f) M[5 * n + f] += w[k] * q[f][i];
+      }
+    }
+    for (int32_t n = 0; n < nn; ++n)
+      if (W[n] > 0.0)
+        for (int f = 0; f < 5; ++f) M[5 * n + f] /= W[n];
+    for (int64_t i = 0; i < np; ++i) {
+      double w[3];
+      shape_values(m, elem[i], state[i], state[np + i], w);
+      for (int k = 0; k < 3; ++k) {
+        int32_t n = m->master[m->en[3 * elem[i] + k]];
+        for (int c = 0; c < 10; ++c)
+          CV[10 * n + c] += w[k] * (q[ca[c]][i] - M[5 * n + ca[c]]) * (q[cb[c]][i] - M[5 * n + cb[c]]);
+      }
+    }
+    for (int32_t n = 0; n < nn; ++n) {
+      if (m->master[n] != n) continue;
+      if (W[n] > 0.0) {
+        for (int f = 0; f < 5; ++f) S(f, n) = M[5 * n + f];
+        for (int c = 0; c < 10; ++c) S(5 + c, n) = CV[10 * n + c] / W[n];
+      } else {
+        for (int f = 0; f < 15; ++f) S(f, n) = prev ? prev[(size_t)f * nn + n] : 0.0;
+        if (cnt) cnt[OR_CNT_EMPTY_NODE]++;
+      }
+      S(24, n) = W[n];
+    }
+    free(W);
+    free(M);
+    free(CV);
+    or_derivatives(m, stats);
+    free(N);
+    free(mean);
+    free(cov);
+    return;
   }
   /* pass 2: element -> node averages over non-empty surrounding elements */
   for (int32_t n = 0; n < nn; ++n) {
@@ -663,8 +726,11 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
                 const double *gradp, int64_t np, double *state, int32_t *elem, const uint32_t *id,
                 uint64_t seed, uint32_t step, double dt, const uint8_t *mask, uint64_t *cnt) {
   int32_t ne = m->ne;
+  const int shape = (p->stats_mode == 1);
   orec *rec = (orec *)malloc(sizeof(orec) * (size_t)ne);
-  for (int32_t e = 0; e < ne; ++e) elem_record(m, p, stats, wp, gradp, e, &rec[e]);
+  if (!shape)
+    for (int32_t e = 0; e < ne; ++e) elem_record(m, p, stats, wp, gradp, e, NULL, &rec[e]);
+  orec rl;
   double *X = state, *Y = state + np, *Uu = state + 2 * np, *Vv = state + 3 * np,
          *Ww = state + 4 * np, *OM = state + 5 * np, *PS = state + 6 * np;
   int32_t lost = 0;
@@ -673,6 +739,13 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
     if (mask && !mask[i]) continue;
     int32_t e0 = elem[i];
     const orec *r = &rec[e0];
+    if (shape) {
+      /* statistics at the particle's position at the start of the step */
+      double w[3];
+      shape_values(m, e0, X[i], Y[i], w);
+      elem_record(m, p, stats, wp, gradp, e0, w, &rl);
+      r = &rl;
+    }
     uint32_t pid = id[i];
     uint32_t q0[4], q1[4];
     draw(seed, pid, step, 0, q0);

@@ -30,7 +30,9 @@ typedef struct or_params {
   int32_t frozen;       /* 1: statistics are not fed back (fixed nodal fields) */
   int32_t wall_b;       /* 1: apply the no-slip trajectory (b) test of eq:fw */
   int32_t store_fp32;   /* 1: particle state is rounded to binary32 wherever the GPU stores it */
-  int32_t pad;
+  int32_t stats_mode;   /* 0 ELEM: element average of nodal values at particles, element -> node
+                           averages; 1 SHAPE: shape-function (eq:approximation) values at the
+                           particle, N_j-weighted particle sums at the nodes */
   double C0, C1, C2, C3, C4, CT, CL, Ceta, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
   double src_x, src_y, src_r;
 } or_params;

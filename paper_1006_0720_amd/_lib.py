@@ -43,7 +43,7 @@ class MeshDesc(C.Structure):
 
 class ModelParams(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("model", "wp_source", "omega_source", "tm_mode", "frozen",
-                                         "wall_b", "reorder_every", "pad")] + \
+                                         "wall_b", "reorder_every", "stats_mode")] + \
                [(n, C.c_double) for n in ("C0", "C1", "C2", "C3", "C4", "CT", "CL", "Ceta", "Cv",
                                           "gamma5", "Cw1", "Cw2", "Cphi", "nu", "k_floor",
                                           "src_x", "src_y", "src_r")]
@@ -128,7 +128,8 @@ class Context:
         md = MeshDesc(mesh.n_nodes, mesh.n_elems, mesh.n_bedges, 0, *[_ptr(x) for x in a])
         mp = ModelParams()
         for name, _ in ModelParams._fields_:
-            if name == "pad":
+            if name == "stats_mode":
+                mp.stats_mode = int(params.get("stats_mode", 0))
                 continue
             if name == "reorder_every":
                 mp.reorder_every = int(params.get("reorder_every", 0) if reorder_every is None
