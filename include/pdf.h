@@ -58,6 +58,7 @@ enum { PDF_TM_CPHI = 0, PDF_TM_KEPS = 1 };                    /* micromixing tim
 enum { PDF_PSI_ZERO = 0, PDF_PSI_STEP_X = 1, PDF_PSI_GAUSS_X = 2, PDF_PSI_BERNOULLI = 3,
        PDF_PSI_DISC = 4 };                                    /* scalar initial conditions */
 enum { PDF_FIELD_STATS = 0, PDF_FIELD_WP = 1, PDF_FIELD_GRADP = 2 }; /* pdf_set_nodal_field ids */
+enum { PDF_STATS_ELEM = 0, PDF_STATS_SHAPE = 1 };             /* statistics at particles and nodes */
 
 #define PDF_NSTAT 25     /* nodal statistics per node, see pdf_estimate_stats */
 #define PDF_NELEMSTAT 16 /* element statistics per element */
@@ -122,9 +123,16 @@ typedef struct pdf_mesh_desc {
  *                the estimator still runs but is not fed back
  *   wall_b       1: apply the no-slip trajectory (b) condition of eq:fw (nu > 0)
  *   reorder_every  particles are re-sorted by host element every R steps (0: never)
+ *   stats_mode   PDF_STATS_ELEM: a particle sees the element average of the nodal
+ *                statistics of its host, and node values are averages of element
+ *                means and central moments over the surrounding elements (Ch.3,
+ *                Fig. mesh-particles); PDF_STATS_SHAPE: a particle sees the nodal
+ *                statistics interpolated at its position by the shape functions of
+ *                eq:approximation, and node j's values are the N^j(x_p)-weighted
+ *                means and central moments of the particles in the elements around j
  *   src_x,src_y,src_r  continuous scalar source disc: psi = 1 inside (r <= 0: none) */
 typedef struct pdf_model_params {
-  int32_t model, wp_source, omega_source, tm_mode, frozen, wall_b, reorder_every, pad;
+  int32_t model, wp_source, omega_source, tm_mode, frozen, wall_b, reorder_every, stats_mode;
   double C0, C1, C2, C3, C4, CT, CL, Ceta, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
   double src_x, src_y, src_r;
 } pdf_model_params;
@@ -175,9 +183,12 @@ pdf_status pdf_advance(pdf_ctx *ctx, int32_t nsteps, double dt);
  * nodal [PDF_NSTAT][n_nodes]: 0-2 <U>,<V>,<W>; 3 <omega>; 4 <phi>; 5-10 <u_i u_j>
  * (11,22,33,12,13,23); 11 <phi'^2>; 12-14 <u_i phi'>; 15-20 d<U_i>/dx, d<U_i>/dy
  * for i = U,V,W; 21-23 Laplacian of <U_i>; 24 particles in the non-empty
- * surrounding elements.
+ * surrounding elements (PDF_STATS_SHAPE: the sum of the node's shape-function
+ * weights over those particles).
  * elem [PDF_NELEMSTAT][n_elems] or NULL: count, 5 means (u,v,w,omega,psi),
- * 10 central moments (uu,vv,ww,uv,uw,vw,psipsi,upsi,vpsi,wpsi), 1/N normalised.
+ * 10 central moments (uu,vv,ww,uv,uw,vw,psipsi,upsi,vpsi,wpsi), 1/N normalised;
+ * PDF_STATS_ELEM only (PDF_E_STATE in PDF_STATS_SHAPE, which forms no element
+ * statistics).
  * on_device = 0: host buffers (synchronizes); 1: device buffers (asynchronous). */
 pdf_status pdf_estimate_stats(pdf_ctx *ctx, double *nodal, double *elem, int32_t on_device);
 

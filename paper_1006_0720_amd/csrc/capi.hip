@@ -34,8 +34,9 @@ struct pdf_ctx {
   double *wp = nullptr, *gradp = nullptr;
   bool wp_set = false, gradp_set = false;
   // element data
-  void *rec = nullptr;
+  void *rec = nullptr;        // element records (NREC, or NRECS in the SHAPE mode, values each)
   double *sums = nullptr, *emom = nullptr;
+  double *nsums = nullptr;    // SHAPE: per-node weighted sums
   int32_t *offs = nullptr, *cursor = nullptr, *blocksums = nullptr;
   // particles (two buffers for the reorder)
   void *pbuf[2] = {nullptr, nullptr};
@@ -142,6 +143,24 @@ template <typename T>
 pdf_status estimate_from_scratch(pdf_ctx *c, const double *prev) {
   const int32_t ne = c->md.ne;
   T *rec = (T *)c->rec;
+  if (c->model.stats_mode == PDF_STATS_SHAPE) {
+    // two passes: weighted means about a zero reference, then all moments
+    // about those means; nodes without weight keep prev
+    const size_t nsb = (size_t)c->md.nn * NSUM * sizeof(double);
+    launch_elem_prep_shape<T>(c->stream, c->md, c->model, nullptr, nullptr, nullptr, rec);
+    HIPCHK(c, hipMemsetAsync(c->nsums, 0, nsb, c->stream));
+    launch_accumulate_shape<T>(c->stream, c->md, part_view<T>(c, c->cur), c->np, rec, c->nsums);
+    launch_node_stats_shape<T>(c->stream, c->md, c->nsums, nullptr, prev, c->stats_est, c->cnt);
+    launch_elem_prep_shape<T>(c->stream, c->md, c->model, c->stats_est, nullptr, nullptr, rec);
+    HIPCHK(c, hipMemsetAsync(c->nsums, 0, nsb, c->stream));
+    launch_accumulate_shape<T>(c->stream, c->md, part_view<T>(c, c->cur), c->np, rec, c->nsums);
+    launch_node_stats_shape<T>(c->stream, c->md, c->nsums, c->stats_est, prev, c->stats_est, c->cnt);
+    launch_node_derivs(c->stream, c->md, c->stats_est);
+    HIPCHK(c, hipGetLastError());
+    std::swap(c->stats_cur, c->stats_est);
+    c->latest = c->stats_cur;
+    return PDF_OK;
+  }
   HIPCHK(c, hipMemsetAsync(rec, 0, (size_t)ne * NREC * sizeof(T), c->stream));
   HIPCHK(c, hipMemsetAsync(c->sums, 0, (size_t)ne * NSUM * sizeof(double), c->stream));
   launch_accumulate<T>(c->stream, part_view<T>(c, c->cur), c->np, rec, c->sums);
@@ -166,16 +185,29 @@ pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt) {
     mark(c, 0);
     if (c->params.model == PDF_MODEL_GLM && c->params.wp_source == PDF_WP_LOCAL)
       launch_local_wp(c->stream, c->md, c->model, c->stats_cur, c->wp);
-    launch_elem_prep<T>(c->stream, c->md, c->model, c->stats_cur,
-                        c->params.model == PDF_MODEL_GLM ? c->wp : nullptr,
-                        c->gradp_set ? c->gradp : nullptr, dt, rec);
-    HIPCHK(c, hipMemsetAsync(c->sums, 0, (size_t)ne * NSUM * sizeof(double), c->stream));
+    const bool shape = c->model.stats_mode == PDF_STATS_SHAPE;
+    if (shape) {
+      launch_elem_prep_shape<T>(c->stream, c->md, c->model, c->stats_cur,
+                                c->params.model == PDF_MODEL_GLM ? c->wp : nullptr,
+                                c->gradp_set ? c->gradp : nullptr, rec);
+      HIPCHK(c, hipMemsetAsync(c->nsums, 0, (size_t)c->md.nn * NSUM * sizeof(double), c->stream));
+    } else {
+      launch_elem_prep<T>(c->stream, c->md, c->model, c->stats_cur,
+                          c->params.model == PDF_MODEL_GLM ? c->wp : nullptr,
+                          c->gradp_set ? c->gradp : nullptr, dt, rec);
+      HIPCHK(c, hipMemsetAsync(c->sums, 0, (size_t)ne * NSUM * sizeof(double), c->stream));
+    }
     mark(c, 1);
-    launch_advance<T>(c->stream, c->dka, c->model, part_view<T>(c, c->cur), c->np, rec, c->sums,
-                      c->seed, c->step, dt, c->cnt);
+    launch_advance<T>(c->stream, c->dka, c->model, part_view<T>(c, c->cur), c->np, rec,
+                      shape ? c->nsums : c->sums, c->seed, c->step, dt, c->cnt);
     mark(c, 2);
-    launch_elem_moments<T>(c->stream, ne, c->sums, rec, c->emom);
-    launch_node_stats(c->stream, c->md, c->emom, c->stats_cur, c->stats_est, c->cnt);
+    if (shape) {
+      launch_node_stats_shape<T>(c->stream, c->md, c->nsums, c->stats_cur, c->stats_cur, c->stats_est,
+                                 c->cnt);
+    } else {
+      launch_elem_moments<T>(c->stream, ne, c->sums, rec, c->emom);
+      launch_node_stats(c->stream, c->md, c->emom, c->stats_cur, c->stats_est, c->cnt);
+    }
     launch_node_derivs(c->stream, c->md, c->stats_est);
     if (!c->params.frozen) {
       std::swap(c->stats_cur, c->stats_est);
@@ -186,6 +218,10 @@ pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt) {
     c->step++;
     mark(c, 3);
     if (c->params.reorder_every > 0 && (c->step % (uint32_t)c->params.reorder_every) == 0) {
+      if (shape) {  // the sort needs the particles per element
+        HIPCHK(c, hipMemsetAsync(c->sums, 0, (size_t)ne * NSUM * sizeof(double), c->stream));
+        launch_elem_count<T>(c->stream, part_view<T>(c, c->cur), c->np, c->sums);
+      }
       launch_reorder<T>(c->stream, ne, c->np, c->sums, c->offs, c->cursor, c->blocksums,
                         part_view<T>(c, c->cur), part_view<T>(c, 1 - c->cur));
       c->cur = 1 - c->cur;
@@ -222,6 +258,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
                               !mesh->bedge_partner || !mesh->bedge_shift)))
     return PDF_E_INVALID_ARG;
   if (params->model != PDF_MODEL_SLM && params->model != PDF_MODEL_GLM) return PDF_E_INVALID_ARG;
+  if (params->stats_mode != PDF_STATS_ELEM && params->stats_mode != PDF_STATS_SHAPE) return PDF_E_INVALID_ARG;
   if (!(params->C4 > 0.0 && params->C4 <= 1.0) || params->nu < 0.0 || params->reorder_every < 0)
     return PDF_E_INVALID_ARG;
   pdf_ctx *c = new pdf_ctx();
@@ -398,7 +435,12 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   c->stats_b = (double *)dalloc(c, (size_t)PDF_NSTAT * nn * sizeof(double));
   c->wp = (double *)dalloc(c, 9 * (size_t)nn * sizeof(double));
   c->gradp = (double *)dalloc(c, 2 * (size_t)nn * sizeof(double));
-  c->rec = dalloc(c, (size_t)ne * NREC * ts);
+  const int nrec = params->stats_mode == PDF_STATS_SHAPE ? NRECS : NREC;
+  c->rec = dalloc(c, (size_t)ne * nrec * ts);
+  if (params->stats_mode == PDF_STATS_SHAPE) {
+    c->nsums = (double *)dalloc(c, (size_t)nn * NSUM * sizeof(double));
+    ok = ok && c->nsums;
+  }
   c->sums = (double *)dalloc(c, (size_t)ne * NSUM * sizeof(double));
   c->emom = (double *)dalloc(c, (size_t)ne * 16 * sizeof(double));
   c->offs = (int32_t *)dalloc(c, ((size_t)ne + 1) * sizeof(int32_t));
@@ -419,7 +461,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
       hipMemsetAsync(c->stats_b, 0, (size_t)PDF_NSTAT * nn * sizeof(double), s) != hipSuccess ||
       hipMemsetAsync(c->wp, 0, 9 * (size_t)nn * sizeof(double), s) != hipSuccess ||
       hipMemsetAsync(c->gradp, 0, 2 * (size_t)nn * sizeof(double), s) != hipSuccess ||
-      hipMemsetAsync(c->rec, 0, (size_t)ne * NREC * ts, s) != hipSuccess ||
+      hipMemsetAsync(c->rec, 0, (size_t)ne * nrec * ts, s) != hipSuccess ||
       hipMemsetAsync(c->emom, 0, (size_t)ne * 16 * sizeof(double), s) != hipSuccess ||
       hipMemsetAsync(c->cnt, 0, PDF_NCOUNTERS * sizeof(unsigned long long), s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
@@ -433,6 +475,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   md.omega_source = params->omega_source;
   md.tm_mode = params->tm_mode;
   md.wall_b = params->wall_b;
+  md.stats_mode = params->stats_mode;
   md.C0 = params->C0;
   md.C1 = params->C1;
   md.C2 = params->C2;
@@ -548,6 +591,8 @@ pdf_status pdf_advance(pdf_ctx *c, int32_t nsteps, double dt) {
 pdf_status pdf_estimate_stats(pdf_ctx *c, double *nodal, double *elem, int32_t on_device) {
   if (!c || (!nodal && !elem)) return PDF_E_INVALID_ARG;
   if (!c->seeded) return fail(c, PDF_E_STATE, "no particles");
+  if (elem && c->model.stats_mode == PDF_STATS_SHAPE)
+    return fail(c, PDF_E_STATE, "the SHAPE statistics mode forms no element statistics");
   const size_t nn = (size_t)c->md.nn, ne = (size_t)c->md.ne;
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   if (nodal) HIPCHK(c, hipMemcpyAsync(nodal, c->latest, PDF_NSTAT * nn * sizeof(double), kind, c->stream));

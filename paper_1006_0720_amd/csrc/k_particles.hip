@@ -14,6 +14,8 @@
 #include "pdf_internal.h"
 #include "rng.h"
 
+#include <type_traits>
+
 namespace pdfk {
 
 template <typename T>
@@ -164,45 +166,16 @@ void launch_seed(hipStream_t s, const MeshDev &m, const ModelDev &md, PartDev<T>
 }
 
 // ---------------------------------------------------------------------------
-// Element records (loop (ii) of Table tab:loops): element average of the nodal
-// statistics, the element's FEM gradient of the mean velocity (eq:gradient),
-// k, eps (eq:dissipation-from-frequency_wall), G_ij and C0 (eq:wall-GandC or
-// eq:GandC), production, S_omega (eq:frequency-source) and t_m.
+// Step coefficients from the statistics seen by a particle (loop (ii) of
+// Table tab:loops): k, eps (eq:dissipation-from-frequency_wall), G_ij and C0
+// (eq:wall-GandC or eq:GandC with the tensor W = wp_ij), production, S_omega
+// (eq:frequency-source) and t_m, pre-multiplied by dt where the step uses them.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_elem_prep(MeshDev m, ModelDev md, const double *S,
-                                                   const double *wp, const double *gradp, double dt,
-                                                   T *rec) {
-  const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m.ne) return;
-  const int nn = m.nn;
-  const int q0 = m.mnode[3 * e], q1 = m.mnode[3 * e + 1], q2 = m.mnode[3 * e + 2];
-  const int qk[3] = {q0, q1, q2};
-#define AVG(arr, f) ((arr[(f) * nn + q0] + arr[(f) * nn + q1] + arr[(f) * nn + q2]) / 3.0)
-  double U[3] = {AVG(S, 0), AVG(S, 1), AVG(S, 2)};
-  const double Om = AVG(S, 3), Phi = AVG(S, 4);
-  double R[6];
-  for (int i = 0; i < 6; ++i) R[i] = AVG(S, 5 + i);
-  const double lap[3] = {AVG(S, 21), AVG(S, 22), AVG(S, 23)};
-  const double gp[2] = {gradp ? AVG(gradp, 0) : 0.0, gradp ? AVG(gradp, 1) : 0.0};
-  const double *d = m.dN + 6 * (size_t)e;
-  double dU[3][2];
-  for (int i = 0; i < 3; ++i) {
-    double gx = 0.0, gy = 0.0;
-    for (int k = 0; k < 3; ++k) {
-      gx += d[k] * S[i * nn + qk[k]];
-      gy += d[3 + k] * S[i * nn + qk[k]];
-    }
-    dU[i][0] = gx;
-    dU[i][1] = gy;
-  }
-  double gs[2] = {0.0, 0.0};
-  for (int k = 0; k < 3; ++k) {
-    const double kn = 0.5 * (S[5 * nn + qk[k]] + S[6 * nn + qk[k]] + S[7 * nn + qk[k]]);
-    const double sq = sqrt(2.0 * (kn > 0.0 ? kn : 0.0));
-    gs[0] += d[k] * sq;
-    gs[1] += d[3 + k] * sq;
-  }
+__device__ __forceinline__ void record_from(const ModelDev &md, const double U[3], double Om, double Phi,
+                                            const double R[6], const double lap[3], const double gp[2],
+                                            const double *W, const double dU[3][2], const double gs[2],
+                                            double dt, T *r) {
   double k = 0.5 * (R[0] + R[1] + R[2]);
   if (!(k > md.k_floor)) k = md.k_floor;
   const double eps = Om * (k + md.nu * md.CT * md.CT * Om);
@@ -216,14 +189,13 @@ __global__ __launch_bounds__(256) void k_elem_prep(MeshDev m, ModelDev md, const
     double wr = 0.0;
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
-        const double W = AVG(wp, 3 * i + j);
-        G[i][j] = (W - ((i == j) ? 0.5 * eps : 0.0)) / k;
-        wr += W * R[sidx[i][j]];
+        const double Wij = W[3 * i + j];
+        G[i][j] = (Wij - ((i == j) ? 0.5 * eps : 0.0)) / k;
+        wr += Wij * R[sidx[i][j]];
       }
     const double c0 = -2.0 * wr / (3.0 * k * eps);
     C0 = (c0 > 0.0) ? c0 : 0.0;
   }
-#undef AVG
   double prod = 0.0;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 2; ++j) prod -= R[sidx[i][j]] * dU[i][j];
@@ -235,7 +207,6 @@ __global__ __launch_bounds__(256) void k_elem_prep(MeshDev m, ModelDev md, const
     const double ta = k / eps, tb = md.CT * sqrt(md.nu / eps);
     inv_tm = 1.0 / (ta > tb ? ta : tb);
   }
-  T *r = rec + (size_t)e * NREC;
   r[R_U] = (T)U[0];
   r[R_V] = (T)U[1];
   r[R_W] = (T)U[2];
@@ -256,8 +227,127 @@ __global__ __launch_bounds__(256) void k_elem_prep(MeshDev m, ModelDev md, const
   r[R_MIX] = (T)(dt * inv_tm);
   r[R_GSX] = (T)gs[0];
   r[R_GSY] = (T)gs[1];
+}
+
+// element FEM gradients (eq:gradient) of the nodal <U_i> and of sqrt(2k)
+__device__ __forceinline__ void elem_gradients(const MeshDev &m, const double *S, int32_t e,
+                                               const int qk[3], double dU[3][2], double gs[2]) {
+  const int nn = m.nn;
+  const double *d = m.dN + 6 * (size_t)e;
+  for (int i = 0; i < 3; ++i) {
+    double gx = 0.0, gy = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      gx += d[k] * S[i * nn + qk[k]];
+      gy += d[3 + k] * S[i * nn + qk[k]];
+    }
+    dU[i][0] = gx;
+    dU[i][1] = gy;
+  }
+  gs[0] = gs[1] = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double kn = 0.5 * (S[5 * nn + qk[k]] + S[6 * nn + qk[k]] + S[7 * nn + qk[k]]);
+    const double sq = sqrt(2.0 * (kn > 0.0 ? kn : 0.0));
+    gs[0] += d[k] * sq;
+    gs[1] += d[3 + k] * sq;
+  }
+}
+
+// ELEM records: the statistics of the element's particles are the element
+// average of its three nodal values (Fig. mesh-particles).
+template <typename T>
+__global__ __launch_bounds__(256) void k_elem_prep(MeshDev m, ModelDev md, const double *S,
+                                                   const double *wp, const double *gradp, double dt,
+                                                   T *rec) {
+  const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.ne) return;
+  const int nn = m.nn;
+  const int q0 = m.mnode[3 * e], q1 = m.mnode[3 * e + 1], q2 = m.mnode[3 * e + 2];
+  const int qk[3] = {q0, q1, q2};
+#define AVG(arr, f) ((arr[(f) * nn + q0] + arr[(f) * nn + q1] + arr[(f) * nn + q2]) / 3.0)
+  const double U[3] = {AVG(S, 0), AVG(S, 1), AVG(S, 2)};
+  const double Om = AVG(S, 3), Phi = AVG(S, 4);
+  double R[6];
+  for (int i = 0; i < 6; ++i) R[i] = AVG(S, 5 + i);
+  const double lap[3] = {AVG(S, 21), AVG(S, 22), AVG(S, 23)};
+  const double gp[2] = {gradp ? AVG(gradp, 0) : 0.0, gradp ? AVG(gradp, 1) : 0.0};
+  double W[9];
+  if (md.model == PDF_MODEL_GLM)
+    for (int f = 0; f < 9; ++f) W[f] = AVG(wp, f);
+#undef AVG
+  double dU[3][2], gs[2];
+  elem_gradients(m, S, e, qk, dU, gs);
+  T *r = rec + (size_t)e * NREC;
+  record_from<T>(md, U, Om, Phi, R, lap, gp, W, dU, gs, dt, r);
   r[30] = (T)0;
   r[31] = (T)0;
+}
+
+// SHAPE records: the raw statistics of the element's three nodes and the
+// element-constant gradients; S == nullptr gives all-zero statistics.
+template <typename T>
+__global__ __launch_bounds__(256) void k_elem_prep_shape(MeshDev m, ModelDev md, const double *S,
+                                                         const double *wp, const double *gradp, T *rec) {
+  const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.ne) return;
+  const int nn = m.nn;
+  const int qk[3] = {m.mnode[3 * e], m.mnode[3 * e + 1], m.mnode[3 * e + 2]};
+  T *r = rec + (size_t)e * NRECS;
+  for (int k = 0; k < 3; ++k) {
+    T *o = r + k * S_NODE;
+    const int q = qk[k];
+    for (int f = 0; f < 11; ++f) o[S_U + f] = S ? (T)S[f * nn + q] : (T)0;  // U, omega, phi, R_ij
+    for (int f = 0; f < 3; ++f) o[S_L0 + f] = S ? (T)S[(21 + f) * nn + q] : (T)0;
+    for (int f = 0; f < 2; ++f) o[S_GP0 + f] = gradp ? (T)gradp[f * nn + q] : (T)0;
+    for (int f = 0; f < 9; ++f)
+      o[S_WP00 + f] = (wp && md.model == PDF_MODEL_GLM) ? (T)wp[f * nn + q] : (T)0;
+  }
+  double dU[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}}, gs[2] = {0.0, 0.0};
+  if (S) elem_gradients(m, S, e, qk, dU, gs);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 2; ++j) r[S_DU + 2 * i + j] = (T)dU[i][j];
+  r[S_GS] = (T)gs[0];
+  r[S_GS + 1] = (T)gs[1];
+  for (int f = S_GS + 2; f < NRECS; ++f) r[f] = (T)0;
+}
+
+template <typename T>
+void launch_elem_prep_shape(hipStream_t s, const MeshDev &m, const ModelDev &md, const double *stats,
+                            const double *wp, const double *gradp, T *rec) {
+  hipLaunchKernelGGL(k_elem_prep_shape<T>, dim3((m.ne + 255) / 256), dim3(256), 0, s, m, md, stats, wp,
+                     gradp, rec);
+}
+
+// shape-function values N^j at (x, y) of eq:approximation: the signed areas
+// of eq:element-test over their sum (the area coordinates)
+__device__ __forceinline__ void shape_w(const double lam[3], double w[3]) {
+  const double s = lam[0] + lam[1] + lam[2];
+  w[0] = lam[0] / s;
+  w[1] = lam[1] / s;
+  w[2] = lam[2] / s;
+}
+
+// statistics of a SHAPE record interpolated with weights w (eq:approximation),
+// then the step coefficients as for an element record
+template <typename T>
+__device__ __forceinline__ void shape_record(const ModelDev &md, const T *rs, const double w[3], double dt,
+                                             T *r) {
+#define INTERP(f) \
+  (w[0] * (double)rs[(f)] + w[1] * (double)rs[S_NODE + (f)] + w[2] * (double)rs[2 * S_NODE + (f)])
+  const double U[3] = {INTERP(S_U), INTERP(S_V), INTERP(S_W)};
+  const double Om = INTERP(S_OM), Phi = INTERP(S_PHI);
+  double R[6];
+  for (int i = 0; i < 6; ++i) R[i] = INTERP(S_R11 + i);
+  const double lap[3] = {INTERP(S_L0), INTERP(S_L1), INTERP(S_L2)};
+  const double gp[2] = {INTERP(S_GP0), INTERP(S_GP0 + 1)};
+  double W[9];
+  if (md.model == PDF_MODEL_GLM)
+    for (int f = 0; f < 9; ++f) W[f] = INTERP(S_WP00 + f);
+#undef INTERP
+  double dU[3][2];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 2; ++j) dU[i][j] = (double)rs[S_DU + 2 * i + j];
+  const double gs[2] = {(double)rs[S_GS], (double)rs[S_GS + 1]};
+  record_from<T>(md, U, Om, Phi, R, lap, gp, W, dU, gs, dt, r);
 }
 
 template <typename T>
@@ -381,6 +471,128 @@ __device__ __forceinline__ void table_flush(SumTable &t, double *sums) {
   }
 }
 
+// Table of the SHAPE reading, keyed by (master) node: the sum of the node's
+// shape-function weights and the 15 weighted shifted moments.
+struct SumTableW {
+  int32_t key[TAB];
+  double acc[NCOPY][16][TAB];
+};
+
+__device__ __forceinline__ void table_init(SumTableW &t) {
+  for (int s = threadIdx.x; s < TAB; s += blockDim.x) {
+    t.key[s] = -1;
+#pragma unroll
+    for (int c = 0; c < NCOPY; ++c)
+#pragma unroll
+      for (int f = 0; f < 16; ++f) t.acc[c][f][s] = 0.0;
+  }
+}
+
+__device__ __forceinline__ int table_slot(SumTableW &t, int32_t e) {
+  uint32_t h = ((uint32_t)e * 2654435761u) >> (32 - PDF_TAB_LOG2);
+  for (int probe = 0; probe < TAB; ++probe) {
+    const int32_t k = __hip_atomic_load(&t.key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (k == e) return (int)h;
+    if (k == -1) {
+      const int32_t old = atomicCAS(&t.key[h], -1, e);
+      if (old == -1 || old == e) return (int)h;
+    }
+    h = (h + 1u) & (uint32_t)(TAB - 1);
+  }
+  return -1;
+}
+
+// one particle's contribution to node `node` with weight wt, shifted by the
+// node's reference means ref[S_U .. S_PHI]
+template <typename T>
+__device__ __forceinline__ void table_add_w(SumTableW &t, double *nsums, int32_t node, double wt,
+                                            const T *ref, T u, T v, T w, T om, T psi) {
+  const double q0 = (double)u - (double)ref[S_U], q1 = (double)v - (double)ref[S_V],
+               q2 = (double)w - (double)ref[S_W], q3 = (double)om - (double)ref[S_OM],
+               q4 = (double)psi - (double)ref[S_PHI];
+  const double val[16] = {wt,           wt * q0,      wt * q1,      wt * q2,      wt * q3,      wt * q4,
+                          wt * q0 * q0, wt * q1 * q1, wt * q2 * q2, wt * q0 * q1, wt * q0 * q2, wt * q1 * q2,
+                          wt * q4 * q4, wt * q0 * q4, wt * q1 * q4, wt * q2 * q4};
+  const int s = table_slot(t, node);
+  if (s >= 0) {
+    const int c = (int)(threadIdx.x % NCOPY);
+#pragma unroll
+    for (int f = 0; f < 16; ++f) unsafeAtomicAdd(&t.acc[c][f][s], val[f]);
+  } else {
+    double *g = nsums + (size_t)node * NSUM;
+#pragma unroll
+    for (int f = 0; f < 16; ++f) unsafeAtomicAdd(&g[f], val[f]);
+  }
+}
+
+__device__ __forceinline__ void table_flush(SumTableW &t, double *nsums) {
+  __syncthreads();
+  for (int s = threadIdx.x; s < TAB; s += blockDim.x) {
+    const int32_t e = t.key[s];
+    if (e < 0) continue;
+    double *g = nsums + (size_t)e * NSUM;
+#pragma unroll
+    for (int f = 0; f < 16; ++f) {
+      double a = 0.0;
+#pragma unroll
+      for (int c = 0; c < NCOPY; ++c) a += t.acc[c][f][s];
+      unsafeAtomicAdd(&g[f], a);
+    }
+  }
+}
+
+// scatter of one particle at (x, y) in element e to the element's three nodes
+template <typename T>
+__device__ __forceinline__ void scatter_shape(SumTableW &t, const MeshDev &m, double *nsums, const T *rec,
+                                              int32_t e, double x, double y, T u, T v, T w, T om, T psi) {
+  const ElemGeo g = m.geo[e];
+  double lam[3], wt[3];
+  edge_lambdas(g, x, y, lam);
+  shape_w(lam, wt);
+  const T *rs = rec + (size_t)e * NRECS;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    table_add_w<T>(t, nsums, m.mnode[3 * e + k], wt[k], rs + k * S_NODE, u, v, w, om, psi);
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_accumulate_shape(MeshDev m, PartDev<T> p, int64_t np, int ppt,
+                                                         const T *rec, double *nsums) {
+  __shared__ SumTableW tab;
+  table_init(tab);
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * WG * ppt;
+  for (int j = 0; j < ppt; ++j) {
+    const int64_t i = base + (int64_t)j * WG + threadIdx.x;
+    if (i < np)
+      scatter_shape<T>(tab, m, nsums, rec, p.e[i], (double)p.x[i], (double)p.y[i], p.u[i], p.v[i], p.w[i],
+                       p.om[i], p.psi[i]);
+  }
+  table_flush(tab, nsums);
+}
+
+template <typename T>
+void launch_accumulate_shape(hipStream_t s, const MeshDev &m, PartDev<T> p, int64_t np, const T *rec,
+                             double *nsums) {
+  const int ppt = pick_ppt(np);
+  hipLaunchKernelGGL(k_accumulate_shape<T>,
+                     dim3((unsigned)((np + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt))), dim3(WG), 0, s,
+                     m, p, np, ppt, rec, nsums);
+}
+
+// particles per element (the histogram of the reorder), as doubles in the
+// count slot of each element's sums
+template <typename T>
+__global__ void k_elem_count(PartDev<T> p, int64_t np, double *sums) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < np) unsafeAtomicAdd(&sums[(size_t)p.e[i] * NSUM], 1.0);
+}
+
+template <typename T>
+void launch_elem_count(hipStream_t s, PartDev<T> p, int64_t np, double *sums) {
+  hipLaunchKernelGGL(k_elem_count<T>, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, p, np, sums);
+}
+
 template <typename T>
 __global__ __launch_bounds__(WG) void k_accumulate(PartDev<T> p, int64_t np, int ppt, const T *rec,
                                                    double *sums) {
@@ -461,12 +673,12 @@ __device__ __forceinline__ void noslip(const ModelDev &md, const T *r, double nx
 #define C_GFAIL(v) (cb += (uint64_t)(v) << 32)
 #define C_NAN(v) (cb += (uint64_t)(v) << 40)
 
-template <typename T, bool VISC, bool WALLB>
+template <typename T, bool VISC, bool WALLB, bool SHAPE>
 __global__ __launch_bounds__(WG) void k_advance(const KArgs *__restrict__ ka, PartDev<T> p, int64_t np,
                                                 int ppt, const T *__restrict__ rec, double *sums, uint32_t k0,
                                                 uint32_t k1, uint32_t step, double dt, double sdt,
                                                 double s2nu, unsigned long long *cnt) {
-  __shared__ SumTable tab;
+  __shared__ std::conditional_t<SHAPE, SumTableW, SumTable> tab;
   const MeshDev &m = ka->m;
   const ModelDev &md = ka->md;
   table_init(tab);
@@ -511,7 +723,18 @@ __global__ __launch_bounds__(WG) void k_advance(const KArgs *__restrict__ ka, Pa
       n_om = p.om[inx];
       n_psi = p.psi[inx];
     }
+    // statistics seen by the particle: its element's record (ELEM), or the
+    // nodal statistics interpolated at its position (SHAPE)
+    T rl[SHAPE ? NREC : 1];
     const T *r = rec + (size_t)e0 * NREC;
+    if constexpr (SHAPE) {
+      const ElemGeo g0 = m.geo[e0];
+      double lam0[3], w0[3];
+      edge_lambdas(g0, x0, y0, lam0);
+      shape_w(lam0, w0);
+      shape_record<T>(md, rec + (size_t)e0 * NRECS, w0, dt, rl);
+      r = rl;
+    }
 
     // ---- noise: six standard normals and one uniform per particle-step ----
     const u32x4 q0 = philox10(id, step, 0u, 0u, k0, k1);
@@ -738,7 +961,10 @@ __global__ __launch_bounds__(WG) void k_advance(const KArgs *__restrict__ ka, Pa
     p.om[i] = omn;
     p.psi[i] = psin;
     p.e[i] = found;
-    table_add<T>(tab, sums, rec, found, un0, un1, un2, omn, psin);
+    if constexpr (SHAPE)
+      scatter_shape<T>(tab, m, sums, rec, found, x, y, un0, un1, un2, omn, psin);
+    else
+      table_add<T>(tab, sums, rec, found, un0, un1, un2, omn, psin);
   }
   table_flush(tab, sums);
   wave_count(&cnt[PDF_CNT_WALK_STEPS], (int)(ca & 0xFFFF));
@@ -753,10 +979,10 @@ __global__ __launch_bounds__(WG) void k_advance(const KArgs *__restrict__ ka, Pa
   wave_count(&cnt[PDF_CNT_NONFINITE], (int)((cb >> 40) & 0xFF));
 }
 
-template <typename T>
-void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
-                    const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
-                    unsigned long long *cnt) {
+template <typename T, bool SHAPE>
+void launch_advance_m(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
+                      const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
+                      unsigned long long *cnt) {
   const int ppt = pick_ppt(np);
   const unsigned grid = (unsigned)((np + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt));
   const bool visc = md.nu > 0.0;
@@ -764,14 +990,24 @@ void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev
   const double sdt = sqrt(dt), s2nu = sqrt(2.0 * md.nu);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   if (visc && wallb)
-    hipLaunchKernelGGL((k_advance<T, true, true>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt, rec, sums,
-                       k0, k1, step, dt, sdt, s2nu, cnt);
+    hipLaunchKernelGGL((k_advance<T, true, true, SHAPE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt, rec,
+                       sums, k0, k1, step, dt, sdt, s2nu, cnt);
   else if (visc)
-    hipLaunchKernelGGL((k_advance<T, true, false>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt, rec, sums,
-                       k0, k1, step, dt, sdt, s2nu, cnt);
+    hipLaunchKernelGGL((k_advance<T, true, false, SHAPE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt, rec,
+                       sums, k0, k1, step, dt, sdt, s2nu, cnt);
   else
-    hipLaunchKernelGGL((k_advance<T, false, false>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt, rec, sums,
-                       k0, k1, step, dt, sdt, s2nu, cnt);
+    hipLaunchKernelGGL((k_advance<T, false, false, SHAPE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt,
+                       rec, sums, k0, k1, step, dt, sdt, s2nu, cnt);
+}
+
+template <typename T>
+void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
+                    const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
+                    unsigned long long *cnt) {
+  if (md.stats_mode == PDF_STATS_SHAPE)
+    launch_advance_m<T, true>(s, dka, md, p, np, rec, sums, seed, step, dt, cnt);
+  else
+    launch_advance_m<T, false>(s, dka, md, p, np, rec, sums, seed, step, dt, cnt);
 }
 
 #define INST(T)                                                                                  \
@@ -784,6 +1020,11 @@ void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev
                                   const T *, double *, uint64_t, uint32_t, double,                 \
                                   unsigned long long *);                                         \
   template void launch_accumulate<T>(hipStream_t, PartDev<T>, int64_t, const T *, double *);        \
+  template void launch_elem_prep_shape<T>(hipStream_t, const MeshDev &, const ModelDev &,           \
+                                          const double *, const double *, const double *, T *);    \
+  template void launch_accumulate_shape<T>(hipStream_t, const MeshDev &, PartDev<T>, int64_t,       \
+                                           const T *, double *);                                    \
+  template void launch_elem_count<T>(hipStream_t, PartDev<T>, int64_t, double *);                   \
   template void launch_ref_from_sums<T>(hipStream_t, int32_t, const double *, T *);
 INST(float)
 INST(double)

@@ -83,6 +83,54 @@ void launch_node_stats(hipStream_t s, const MeshDev &m, const double *emom, cons
                      out, cnt);
 }
 
+// SHAPE node values: weighted means and central moments from the node's sums
+// (weight W, 5 weighted first and 10 weighted second moments shifted by the
+// node's reference ref, as rounded to T in the records); nodes with W = 0
+// keep their previous values.  ref == nullptr: zero reference.
+template <typename T>
+__global__ __launch_bounds__(256) void k_node_stats_shape(MeshDev m, const double *nsums, const double *ref,
+                                                          const double *prev, double *out,
+                                                          unsigned long long *cnt) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  int empty = 0;
+  if (t < m.n_masters) {
+    const int32_t n = m.masters[t];
+    const int nn = m.nn;
+    const double *s = nsums + (size_t)n * NSUM;
+    const double W = s[0];
+    if (W > 0.0) {
+      double d[5];
+      for (int f = 0; f < 5; ++f) d[f] = s[1 + f] / W;
+      const int ca[10] = {0, 1, 2, 0, 0, 1, 4, 0, 1, 2};
+      const int cb[10] = {0, 1, 2, 1, 2, 2, 4, 4, 4, 4};
+      double mom[10];
+      for (int c = 0; c < 10; ++c) mom[c] = s[6 + c] / W - d[ca[c]] * d[cb[c]];
+      for (int f = 0; f < 5; ++f) {
+        const double r = ref ? (double)(T)ref[f * nn + n] : 0.0;
+        out[f * nn + n] = r + d[f];
+      }
+      for (int c = 0; c < 10; ++c) out[(5 + c) * nn + n] = mom[c];
+    } else {
+      for (int f = 0; f < 15; ++f) out[f * nn + n] = prev[f * nn + n];
+      empty = 1;
+    }
+    out[24 * nn + n] = W;
+  }
+  if (__ballot(empty) != 0) {
+    int v = empty;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&cnt[PDF_CNT_EMPTY_NODE], (unsigned long long)v);
+  }
+}
+
+template <typename T>
+void launch_node_stats_shape(hipStream_t s, const MeshDev &m, const double *nsums, const double *ref,
+                             const double *prev, double *out, unsigned long long *cnt) {
+  hipLaunchKernelGGL(k_node_stats_shape<T>, dim3((m.n_masters + 255) / 256), dim3(256), 0, s, m, nsums, ref,
+                     prev, out, cnt);
+}
+
 // first derivatives: eq:gradient in every surrounding element, averaged
 __global__ __launch_bounds__(256) void k_node_grad(MeshDev m, double *S) {
   const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -363,6 +411,9 @@ void launch_unpack_state(hipStream_t s, PartDev<T> p, int64_t np, const double *
 }
 
 #define INST(T)                                                                                  \
+  template void launch_node_stats_shape<T>(hipStream_t, const MeshDev &, const double *,            \
+                                           const double *, const double *, double *,                \
+                                           unsigned long long *);                                   \
   template void launch_elem_moments<T>(hipStream_t, int32_t, const double *, const T *, double *); \
   template void launch_reorder<T>(hipStream_t, int32_t, int64_t, const double *, int32_t *,         \
                                   int32_t *, int32_t *, PartDev<T>, PartDev<T>);                  \

@@ -33,6 +33,19 @@ enum RecField {
 };
 constexpr int NREC = 32;
 
+// Record of the SHAPE reading: the statistics of the element's three nodes
+// (raw nodal values, interpolated at each particle) and the element-constant
+// FEM gradients.  Per node: <U_i> (3), <omega>, <phi>, R_ij (6), Laplacian of
+// <U_i> (3), mean-pressure gradient (2), wp_ij (9).
+enum ShapeRecField {
+  S_U = 0, S_V, S_W, S_OM, S_PHI, S_R11, S_R22, S_R33, S_R12, S_R13, S_R23,
+  S_L0, S_L1, S_L2, S_GP0, S_GP1, S_WP00,  // S_WP00 .. S_WP00 + 8
+  S_NODE = 25                              // values per node
+};
+constexpr int S_DU = 3 * S_NODE;  // dU_i/dx_j (6): i = U,V,W; j = x,y
+constexpr int S_GS = S_DU + 6;    // gradient of sqrt(2k) (2)
+constexpr int NRECS = 88;         // padded record length
+
 // Element sums: count, 5 shifted first moments, 10 shifted second moments.
 constexpr int NSUM = 16;
 
@@ -63,7 +76,7 @@ struct PartDev {
 };
 
 struct ModelDev {
-  int32_t model, wp_source, omega_source, tm_mode, wall_b;
+  int32_t model, wp_source, omega_source, tm_mode, wall_b, stats_mode;
   double C0, C1, C2, C3, C4, CT, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
   double src_x, src_y, src_r;
 };
@@ -85,9 +98,22 @@ template <typename T>
 void launch_elem_prep(hipStream_t s, const MeshDev &m, const ModelDev &md, const double *stats,
                       const double *wp, const double *gradp, double dt, T *rec);
 template <typename T>
+void launch_elem_prep_shape(hipStream_t s, const MeshDev &m, const ModelDev &md, const double *stats,
+                            const double *wp, const double *gradp, T *rec);
+// ELEM: rec has NREC values per element, sums NSUM per element;
+// SHAPE: rec has NRECS values per element, sums NSUM per node
+template <typename T>
 void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
                     const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
                     unsigned long long *cnt);
+template <typename T>
+void launch_accumulate_shape(hipStream_t s, const MeshDev &m, PartDev<T> p, int64_t np, const T *rec,
+                             double *nsums);
+template <typename T>
+void launch_node_stats_shape(hipStream_t s, const MeshDev &m, const double *nsums, const double *ref,
+                             const double *prev, double *out, unsigned long long *cnt);
+template <typename T>
+void launch_elem_count(hipStream_t s, PartDev<T> p, int64_t np, double *sums);
 template <typename T>
 void launch_accumulate(hipStream_t s, PartDev<T> p, int64_t np, const T *rec, double *sums);
 template <typename T>
