@@ -37,15 +37,19 @@ WORKLOADS = {
 }
 
 
-def kernel_bytes(w, tsize):
+def kernel_bytes(w, tsize, shape=False):
     """Algorithmic HBM bytes of one launch of the fused particle kernel:
     per particle the state is read (7 values + element + id) and written
-    (7 values + element); per element its record is read once and its 16
-    FP64 sums are read and written once."""
-    n_p, n_e = w.n_particles, w.mesh.n_elems
+    (7 values + element); per element its record (32 values; 88 for the
+    shape-function mode) is read once; the 16 FP64 sums of every element
+    (every node in the shape-function mode) are read and written once."""
+    n_p, n_e, n_n = w.n_particles, w.mesh.n_elems, w.mesh.n_nodes
     per_particle = (7 * tsize + 4 + 4) + (7 * tsize + 4)
-    per_element = 32 * tsize + 2 * 16 * 8
-    return n_p * per_particle + n_e * per_element, per_particle, per_element
+    if shape:
+        per_element = 88 * tsize + 2 * 16 * 8 * n_n / n_e
+    else:
+        per_element = 32 * tsize + 2 * 16 * 8
+    return int(n_p * per_particle + n_e * per_element), per_particle, round(per_element, 1)
 
 
 def source_hash():
@@ -129,6 +133,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="channel_block", choices=sorted(WORKLOADS))
     ap.add_argument("--reorder-every", type=int, default=4)
+    ap.add_argument("--stats-mode", default="elem", choices=["elem", "shape"],
+                    help="statistics at particles and nodes: element averages (the paper's) or "
+                         "shape-function interpolation and weighting")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
@@ -151,6 +158,9 @@ def main():
 
     ctor, desc = WORKLOADS[args.workload]
     w = getattr(CF, ctor)()
+    shape = args.stats_mode == "shape"
+    if shape:
+        w.params = dict(w.params, stats_mode=CF.STATS_SHAPE)
     tsize = 4 if w.precision == "f32" else 8
     ctx = workload_context(w, device=0, reorder_every=args.reorder_every)
     stream = torch.cuda.current_stream()
@@ -179,10 +189,10 @@ def main():
     n_p = w.n_particles
     value = n_p * args.steps / wall
 
-    bytes_alg, per_p, per_e = kernel_bytes(w, tsize)
+    bytes_alg, per_p, per_e = kernel_bytes(w, tsize, shape)
     adv_ms = tm["advance"] / args.steps
     achieved = bytes_alg / (adv_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile(args.workload, bytes_alg)
+    traffic = None if shape else traffic_from_profile(args.workload, bytes_alg)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_advance", "kernel_ms": round(adv_ms, 4),
@@ -197,7 +207,7 @@ def main():
         "config": {"workload": f"{args.workload}: {desc}", "n_particles": n_p,
                    "n_elements": w.mesh.n_elems, "n_nodes": w.mesh.n_nodes,
                    "particles_per_element": int(w.seed["ppe"]), "dt": w.dt,
-                   "reorder_every": args.reorder_every},
+                   "reorder_every": args.reorder_every, "stats_mode": args.stats_mode},
         "roofline": roof,
         "phase_ms_per_step": {k: round(v / args.steps, 4) for k, v in tm.items()},
         "counters": {k: cnt[k] for k in ("lost", "brute", "fallback", "nonfinite", "empty_node")},

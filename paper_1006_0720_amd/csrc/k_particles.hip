@@ -371,7 +371,7 @@ void launch_elem_prep(hipStream_t s, const MeshDev &m, const ModelDev &md, const
 #define PDF_TAB_LOG2 7
 #endif
 #ifndef PDF_TAB_COPIES
-#define PDF_TAB_COPIES 4
+#define PDF_TAB_COPIES 3
 #endif
 #ifndef PDF_PPT
 #define PDF_PPT 8
@@ -673,8 +673,15 @@ __device__ __forceinline__ void noslip(const ModelDev &md, const T *r, double nx
 #define C_GFAIL(v) (cb += (uint64_t)(v) << 32)
 #define C_NAN(v) (cb += (uint64_t)(v) << 40)
 
+// Occupancy: the FP32 element-average kernel is held to 3 waves per SIMD
+// (at most 168 VGPRs; the LDS table of 3 copies, 48 KB, lets 3 workgroups
+// share a CU), which hides more of the latency of the walk's dependent loads
+// than the 2 waves its unconstrained register count would allow.
+template <typename T, bool SHAPE>
+constexpr int advance_waves() { return (sizeof(T) == 4 && !SHAPE) ? 3 : 1; }
+
 template <typename T, bool VISC, bool WALLB, bool SHAPE>
-__global__ __launch_bounds__(WG) void k_advance(const KArgs *__restrict__ ka, PartDev<T> p, int64_t np,
+__global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(const KArgs *__restrict__ ka, PartDev<T> p, int64_t np,
                                                 int ppt, const T *__restrict__ rec, double *sums, uint32_t k0,
                                                 uint32_t k1, uint32_t step, double dt, double sdt,
                                                 double s2nu, unsigned long long *cnt) {

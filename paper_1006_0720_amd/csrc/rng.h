@@ -26,8 +26,11 @@ __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
-    uint32_t lo0 = m0 * c0, hi0 = __umulhi(m0, c0);
-    uint32_t lo1 = m1 * c2, hi1 = __umulhi(m1, c2);
+    // one 32x32 -> 64-bit product each (v_mad_u64_u32) instead of separate
+    // low and high multiplies
+    const uint64_t p0 = (uint64_t)m0 * c0, p1 = (uint64_t)m1 * c2;
+    uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
     uint32_t t0 = hi1 ^ c1 ^ k0;
     uint32_t t2 = hi0 ^ c3 ^ k1;
     c0 = t0;
