@@ -132,7 +132,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="channel_block", choices=sorted(WORKLOADS))
-    ap.add_argument("--reorder-every", type=int, default=4)
+    ap.add_argument("--reorder-every", type=int, default=8)
     ap.add_argument("--stats-mode", default="elem", choices=["elem", "shape"],
                     help="statistics at particles and nodes: element averages (the paper's) or "
                          "shape-function interpolation and weighting")

@@ -414,8 +414,53 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   std::vector<int32_t> blocal(mesh->bedge_local, mesh->bedge_local + nb);
   std::vector<double> bshift(mesh->bedge_shift, mesh->bedge_shift + 2 * (size_t)nb);
   std::vector<int32_t> vmaster(master, master + nn);
+  // ---- bucket grid for the last-resort point location ----
+  double bx0 = xy[0], bx1 = xy[0], by0 = xy[1], by1 = xy[1];
+  for (int32_t n = 0; n < nn; ++n) {
+    bx0 = std::min(bx0, xy[2 * n]);
+    bx1 = std::max(bx1, xy[2 * n]);
+    by0 = std::min(by0, xy[2 * n + 1]);
+    by1 = std::max(by1, xy[2 * n + 1]);
+  }
+  const double wx = std::max(bx1 - bx0, 1e-300), wy = std::max(by1 - by0, 1e-300);
+  // about two elements per cell, cells roughly square
+  const double cells = std::max(1.0, 0.5 * ne);
+  int32_t gnx = (int32_t)std::max(1.0, std::floor(std::sqrt(cells * wx / wy)));
+  int32_t gny = (int32_t)std::max(1.0, std::floor(cells / gnx));
+  gnx = std::min(gnx, 1 << 14);
+  gny = std::min(gny, 1 << 14);
+  const double gsx = gnx / wx, gsy = gny / wy;
+  std::vector<int32_t> cell_off((size_t)gnx * gny + 1, 0), cell_list;
+  {
+    auto crange = [](double lo, double hi, double o, double sc, int32_t nmax, int32_t &a, int32_t &b) {
+      a = (int32_t)std::floor((lo - o) * sc - 1e-6);
+      b = (int32_t)std::floor((hi - o) * sc + 1e-6);
+      a = std::max(a, 0);
+      b = std::min(b, nmax - 1);
+    };
+    std::vector<int32_t> ia(ne), ib(ne), ja(ne), jb(ne);
+    for (int32_t e = 0; e < ne; ++e) {
+      const ElemGeo &g = geo[e];
+      crange(std::min({g.x[0], g.x[1], g.x[2]}), std::max({g.x[0], g.x[1], g.x[2]}), bx0, gsx, gnx, ia[e], ib[e]);
+      crange(std::min({g.y[0], g.y[1], g.y[2]}), std::max({g.y[0], g.y[1], g.y[2]}), by0, gsy, gny, ja[e], jb[e]);
+      for (int32_t j = ja[e]; j <= jb[e]; ++j)
+        for (int32_t i = ia[e]; i <= ib[e]; ++i) cell_off[(size_t)j * gnx + i + 1]++;
+    }
+    for (size_t k = 0; k < (size_t)gnx * gny; ++k) cell_off[k + 1] += cell_off[k];
+    cell_list.resize(cell_off.back());
+    std::vector<int32_t> fill(cell_off.begin(), cell_off.end() - 1);
+    for (int32_t e = 0; e < ne; ++e)  // ascending element order within every cell
+      for (int32_t j = ja[e]; j <= jb[e]; ++j)
+        for (int32_t i = ia[e]; i <= ib[e]; ++i) cell_list[fill[(size_t)j * gnx + i]++] = e;
+  }
   // ---- upload ----
   MeshDev &m = c->md;
+  m.gnx = gnx;
+  m.gny = gny;
+  m.gx0 = bx0;
+  m.gy0 = by0;
+  m.gsx = gsx;
+  m.gsy = gsy;
   m.ne = ne;
   m.nn = nn;
   m.nb = nb;
@@ -429,7 +474,8 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
             upload(c, w_list, &m.w_list) && upload(c, vmaster, &m.master) &&
             upload(c, nwall_off, &m.nwall_off) && upload(c, nwall, &m.nwall) &&
             upload(c, masters, &m.masters) && upload(c, slaves, &m.slaves) &&
-            upload(c, slave_master, &m.slave_master);
+            upload(c, slave_master, &m.slave_master) && upload(c, cell_off, &m.cell_off) &&
+            upload(c, cell_list, &m.cell_list);
   const size_t ts = tsize(c);
   c->stats_a = (double *)dalloc(c, (size_t)PDF_NSTAT * nn * sizeof(double));
   c->stats_b = (double *)dalloc(c, (size_t)PDF_NSTAT * nn * sizeof(double));

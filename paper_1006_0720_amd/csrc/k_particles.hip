@@ -64,9 +64,21 @@ __device__ int32_t search_patch(const MeshDev &m, int32_t e, double px, double p
   return -1;
 }
 
+// The lowest-numbered element whose closed triangle contains the point (the
+// plain brute-force answer), found among the elements listed for the point's
+// cell of the bucket grid: every element containing the point has its
+// bounding box, and so its cell list entry, there.
 __device__ int32_t locate_brute(const MeshDev &m, double px, double py) {
-  for (int32_t e = 0; e < m.ne; ++e)
+  const double fx = (px - m.gx0) * m.gsx, fy = (py - m.gy0) * m.gsy;
+  if (!(fx >= -1e-6 && fy >= -1e-6 && fx <= m.gnx + 1e-6 && fy <= m.gny + 1e-6)) return -1;
+  int32_t i = (int32_t)floor(fx), j = (int32_t)floor(fy);
+  i = i < 0 ? 0 : (i >= m.gnx ? m.gnx - 1 : i);
+  j = j < 0 ? 0 : (j >= m.gny ? m.gny - 1 : j);
+  const size_t c = (size_t)j * m.gnx + i;
+  for (int32_t k = m.cell_off[c]; k < m.cell_off[c + 1]; ++k) {
+    const int32_t e = m.cell_list[k];
     if (contains(m.geo[e], px, py)) return e;
+  }
   return -1;
 }
 

@@ -66,6 +66,12 @@ struct MeshDev {
   const int32_t *slaves;    // list of identified (non-master) nodes
   const int32_t *slave_master;
   int32_t n_slaves;
+  // uniform grid over the mesh bounding box for the last-resort point location:
+  // cell (i, j) lists, in ascending order, every element whose bounding box
+  // (padded by a millionth of a cell) meets the cell
+  int32_t gnx, gny;
+  double gx0, gy0, gsx, gsy;      // origin and cells per unit length
+  const int32_t *cell_off, *cell_list;
 };
 
 template <typename T>
