@@ -382,7 +382,15 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
       std::sort(l.begin(), l.end());
       w_list.insert(w_list.end(), l.begin(), l.end());
       w_off[e + 1] = (int32_t)w_list.size();
+      geo[e].wb = w_off[e];
+      geo[e].wn = w_off[e + 1] - w_off[e];
     }
+  }
+  std::vector<WallSeg> wseg(w_list.size());
+  for (size_t j = 0; j < w_list.size(); ++j) {
+    const int32_t b = w_list[j], e = mesh->bedge_elem[b], k = mesh->bedge_local[b];
+    const int32_t a = en[3 * e + (k + 1) % 3], c = en[3 * e + (k + 2) % 3];
+    wseg[j] = {xy[2 * a], xy[2 * a + 1], xy[2 * c], xy[2 * c + 1]};
   }
   // node -> wall edges (slip and no-slip) ending at the node (ascending)
   std::vector<int32_t> nwall_off(nn + 1, 0), nwall;
@@ -470,7 +478,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
             upload(c, btype, &m.btype) && upload(c, bpart, &m.bpart) && upload(c, belem, &m.belem) &&
             upload(c, blocal, &m.blocal) && upload(c, bshift, &m.bshift) &&
             upload(c, n2e_off, &m.n2e_off) && upload(c, n2e, &m.n2e) &&
-            upload(c, m2e_off, &m.m2e_off) && upload(c, m2e, &m.m2e) && upload(c, w_off, &m.w_off) &&
+            upload(c, m2e_off, &m.m2e_off) && upload(c, m2e, &m.m2e) && upload(c, w_off, &m.w_off) && upload(c, wseg, &m.wseg) &&
             upload(c, w_list, &m.w_list) && upload(c, vmaster, &m.master) &&
             upload(c, nwall_off, &m.nwall_off) && upload(c, nwall, &m.nwall) &&
             upload(c, masters, &m.masters) && upload(c, slaves, &m.slaves) &&

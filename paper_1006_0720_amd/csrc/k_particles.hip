@@ -440,13 +440,14 @@ __device__ __forceinline__ int table_slot(SumTable &t, int32_t e) {
   return -1;
 }
 
+// one particle's contribution to element e, shifted by the element's
+// reference means ref[0..4] (<U>, <V>, <W>, <omega>, <phi> of its record)
 template <typename T>
-__device__ __forceinline__ void table_add(SumTable &t, double *sums, const T *rec, int32_t e, T u, T v,
+__device__ __forceinline__ void table_add(SumTable &t, double *sums, const T ref[5], int32_t e, T u, T v,
                                           T w, T om, T psi) {
-  const T *r = rec + (size_t)e * NREC;
-  const double q0 = (double)u - (double)r[R_U], q1 = (double)v - (double)r[R_V],
-               q2 = (double)w - (double)r[R_W], q3 = (double)om - (double)r[R_OM],
-               q4 = (double)psi - (double)r[R_PHI];
+  const double q0 = (double)u - (double)ref[0], q1 = (double)v - (double)ref[1],
+               q2 = (double)w - (double)ref[2], q3 = (double)om - (double)ref[3],
+               q4 = (double)psi - (double)ref[4];
   const double val[15] = {q0,      q1,      q2,      q3,      q4,      q0 * q0, q1 * q1, q2 * q2,
                           q0 * q1, q0 * q2, q1 * q2, q4 * q4, q0 * q4, q1 * q4, q2 * q4};
   const int s = table_slot(t, e);
@@ -614,7 +615,12 @@ __global__ __launch_bounds__(WG) void k_accumulate(PartDev<T> p, int64_t np, int
   const int64_t base = (int64_t)blockIdx.x * WG * ppt;
   for (int j = 0; j < ppt; ++j) {
     const int64_t i = base + (int64_t)j * WG + threadIdx.x;
-    if (i < np) table_add<T>(tab, sums, rec, p.e[i], p.u[i], p.v[i], p.w[i], p.om[i], p.psi[i]);
+    if (i < np) {
+      const int32_t e = p.e[i];
+      const T *r = rec + (size_t)e * NREC;
+      const T ref[5] = {r[R_U], r[R_V], r[R_W], r[R_OM], r[R_PHI]};
+      table_add<T>(tab, sums, ref, e, p.u[i], p.v[i], p.w[i], p.om[i], p.psi[i]);
+    }
   }
   table_flush(tab, sums);
 }
@@ -786,7 +792,8 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
     y = stor<T>(y);
 
     // ---- velocity: eq:velocity-prediction with G_ij and C0 of the record ----
-    const T d0 = up0 - r[R_U], d1 = up1 - r[R_V], d2 = up2 - r[R_W];
+    const T ref0[5] = {r[R_U], r[R_V], r[R_W], r[R_OM], r[R_PHI]};
+    const T d0 = up0 - ref0[0], d1 = up1 - ref0[1], d2 = up2 - ref0[2];
     T un0 = up0 + r[R_A0], un1 = up1 + r[R_A1], un2 = up2 + r[R_A2];
     un0 = fmaT(r[R_G00], d0, fmaT(r[R_G01], d1, fmaT(r[R_G02], d2, un0)));
     un1 = fmaT(r[R_G10], d0, fmaT(r[R_G11], d1, fmaT(r[R_G12], d2, un1)));
@@ -804,16 +811,17 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
 
     // ---- frequency: eq:frequency-model, negative excursions folded back ----
     const T omp = om > (T)0 ? om : (T)0;
-    T omn = om - r[R_WA] * (om - r[R_OM]) - r[R_WB] * om + r[R_WC] * sqrt(omp) * xi5;
+    T omn = om - r[R_WA] * (om - ref0[3]) - r[R_WB] * om + r[R_WC] * sqrt(omp) * xi5;
     if (omn < (T)0) {
       omn = -omn;
       C_CLAMP(1);
     }
     // ---- scalar: eq:IEM ----
-    T psin = psi - r[R_MIX] * (psi - r[R_PHI]);
+    T psin = psi - r[R_MIX] * (psi - ref0[4]);
 
     // ---- tracking: next-best-element walk (Ch.3, Sec. Particle tracking) ----
     int32_t e = e0, found = -1, nrefl = 0;
+    int32_t fwb = 0, fwn = -1;  // wall segments near the host found by the walk
     double shx = 0.0, shy = 0.0;
     // a non-finite position cannot be located: the particle is lost at once
     const bool finite_pos = isfinite(x) && isfinite(y);
@@ -824,6 +832,8 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
       edge_lambdas(g, x, y, lam);
       if (lam[0] >= 0.0 && lam[1] >= 0.0 && lam[2] >= 0.0) {
         found = e;
+        fwb = g.wb;
+        fwn = g.wn;
         break;
       }
       int k = 0;
@@ -927,29 +937,30 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
 
     // ---- no-slip trajectory (b): eq:fw and eq:exp-wall-condition ----
     if (WALLB && nrefl == 0) {
+      if (fwn < 0) {  // host found by a fall-back search
+        fwb = m.geo[found].wb;
+        fwn = m.geo[found].wn;
+      }
       int32_t best = -1;
       double bd = 0.0;
-      for (int32_t j = m.w_off[found]; j < m.w_off[found + 1]; ++j) {
-        const int32_t b = m.w_list[j];
-        const ElemGeo g = m.geo[m.belem[b]];
-        const int kk = m.blocal[b];
-        const double xa = sel3(g.x, (kk + 1) % 3), ya = sel3(g.y, (kk + 1) % 3);
-        const double dx = sel3(g.x, (kk + 2) % 3) - xa, dy = sel3(g.y, (kk + 2) % 3) - ya;
+      for (int32_t j = fwb; j < fwb + fwn; ++j) {
+        const WallSeg ws = m.wseg[j];
+        const double xa = ws.xa, ya = ws.ya;
+        const double dx = ws.xb - xa, dy = ws.yb - ya;
         double t = ((x - xa) * dx + (y - ya) * dy) / (dx * dx + dy * dy);
         if (t < 0.0) t = 0.0;
         if (t > 1.0) t = 1.0;
         const double ex = x - (xa + t * dx), ey = y - (ya + t * dy);
         const double d2 = ex * ex + ey * ey;
         if (best < 0 || d2 < bd) {
-          best = b;
+          best = j;
           bd = d2;
         }
       }
       if (best >= 0) {
-        const ElemGeo g = m.geo[m.belem[best]];
-        const int kk = m.blocal[best];
-        const double xa = sel3(g.x, (kk + 1) % 3), ya = sel3(g.y, (kk + 1) % 3);
-        const double dx = sel3(g.x, (kk + 2) % 3) - xa, dy = sel3(g.y, (kk + 2) % 3) - ya;
+        const WallSeg ws = m.wseg[best];
+        const double xa = ws.xa, ya = ws.ya;
+        const double dx = ws.xb - xa, dy = ws.yb - ya;
         const double len = sqrt(dx * dx + dy * dy);
         const double nx = dy / len, ny = -dx / len;
         const double d1 = -((x - xa) * nx + (y - ya) * ny);
@@ -982,8 +993,13 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
     p.e[i] = found;
     if constexpr (SHAPE)
       scatter_shape<T>(tab, m, sums, rec, found, x, y, un0, un1, un2, omn, psin);
-    else
-      table_add<T>(tab, sums, rec, found, un0, un1, un2, omn, psin);
+    else if (found == e0)  // the references of the start element are at hand
+      table_add<T>(tab, sums, ref0, found, un0, un1, un2, omn, psin);
+    else {
+      const T *rf = rec + (size_t)found * NREC;
+      const T ref[5] = {rf[R_U], rf[R_V], rf[R_W], rf[R_OM], rf[R_PHI]};
+      table_add<T>(tab, sums, ref, found, un0, un1, un2, omn, psin);
+    }
   }
   table_flush(tab, sums);
   wave_count(&cnt[PDF_CNT_WALK_STEPS], (int)(ca & 0xFFFF));

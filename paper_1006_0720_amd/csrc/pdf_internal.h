@@ -10,12 +10,20 @@
 
 namespace pdfk {
 
-// Element geometry for the walk: node coordinates, global node ids and
-// neighbours (>= 0 element, < 0 boundary edge -(b+1)).  72 bytes.
+// Element geometry for the walk: node coordinates, global node ids,
+// neighbours (>= 0 element, < 0 boundary edge -(b+1)) and the range
+// [wb, wb + wn) of the element's nearby no-slip wall segments.  80 bytes.
 struct ElemGeo {
   double x[3], y[3];
   int32_t n[3];
   int32_t nb[3];
+  int32_t wb, wn;
+};
+
+// A no-slip wall edge near an element: its end points (local nodes k+1 and
+// k+2 of its boundary element, in that order).
+struct WallSeg {
+  double xa, ya, xb, yb;
 };
 
 // Element record: element-average statistics and the pre-multiplied
@@ -59,6 +67,7 @@ struct MeshDev {
   const int32_t *n2e_off, *n2e;  // node -> elements
   const int32_t *m2e_off, *m2e;  // master node -> elements (statistics)
   const int32_t *w_off, *w_list; // element -> nearby no-slip wall edges
+  const WallSeg *wseg;            // [w_off[ne]]: geometry of each w_list entry
   const int32_t *nwall_off, *nwall; // node -> wall (slip/no-slip) edges ending at it
   const int32_t *master;    // [nn] periodic identification
   const int32_t *masters;   // list of master nodes
