@@ -11,34 +11,38 @@
 
 namespace pdfk {
 
-// element means and central second moments (1/N) from the shifted sums
+// element means and central second moments (1/N) from the shifted sums:
+// 16 lanes per element, lane f producing output f, so that every load and
+// store of a wave covers whole 128-byte element rows
 template <typename T>
 __global__ __launch_bounds__(256) void k_elem_moments(int32_t ne, const double *sums, const T *rec,
                                                       double *emom) {
-  const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t e = (int32_t)(t >> 4);
+  const int f = (int)(t & 15);
   if (e >= ne) return;
   const double *s = sums + (size_t)e * NSUM;
-  const T *r = rec + (size_t)e * NREC;
-  double *o = emom + (size_t)e * 16;
   const double N = s[0];
-  o[0] = N;
-  if (!(N > 0.0)) {
-    for (int f = 1; f < 16; ++f) o[f] = 0.0;
-    return;
+  double v;
+  if (f == 0) {
+    v = N;
+  } else if (!(N > 0.0)) {
+    v = 0.0;
+  } else if (f < 6) {
+    v = (double)rec[(size_t)e * NREC + (f - 1)] + s[f] / N;
+  } else {
+    const int c = f - 6;
+    const int a = c < 3 ? c : (c < 5 ? 0 : (c == 5 ? 1 : (c == 6 ? 4 : c - 7)));
+    const int b = c < 3 ? c : (c == 3 ? 1 : (c == 4 ? 2 : (c == 5 ? 2 : 4)));
+    v = s[f] / N - (s[1 + a] / N) * (s[1 + b] / N);
   }
-  double m1[5];
-  for (int f = 0; f < 5; ++f) {
-    m1[f] = s[1 + f] / N;
-    o[1 + f] = (double)r[f] + m1[f];
-  }
-  const int ca[10] = {0, 1, 2, 0, 0, 1, 4, 0, 1, 2};
-  const int cb[10] = {0, 1, 2, 1, 2, 2, 4, 4, 4, 4};
-  for (int c = 0; c < 10; ++c) o[6 + c] = s[6 + c] / N - m1[ca[c]] * m1[cb[c]];
+  emom[(size_t)e * 16 + f] = v;
 }
 
 template <typename T>
 void launch_elem_moments(hipStream_t s, int32_t ne, const double *sums, const T *rec, double *emom) {
-  hipLaunchKernelGGL(k_elem_moments<T>, dim3((ne + 255) / 256), dim3(256), 0, s, ne, sums, rec, emom);
+  hipLaunchKernelGGL(k_elem_moments<T>, dim3((unsigned)(((int64_t)ne * 16 + 255) / 256)), dim3(256), 0, s, ne,
+                     sums, rec, emom);
 }
 
 // pass 2: node value = average over the surrounding elements holding particles;
