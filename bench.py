@@ -59,16 +59,20 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload, bytes_alg):
-    """HBM traffic of the particle kernel from committed rocprofv3 counter
-    summaries, or None when none exists or the kernel source changed since."""
+def profile_counters(workload):
+    """Committed rocprofv3 counter summary of the particle kernel for this
+    workload, or None when none exists or the kernel source changed since."""
     path = os.path.join(ROOT, "profiles", f"k_advance_{workload}_counters.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("source_hash") != source_hash():
         return None
-    return d.get("traffic_bytes_per_launch")
+    return d
+
+
+# plain (non-packed) VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
 def cpu_baseline(wname, w):
@@ -192,12 +196,20 @@ def main():
     bytes_alg, per_p, per_e = kernel_bytes(w, tsize, shape)
     adv_ms = tm["advance"] / args.steps
     achieved = bytes_alg / (adv_ms * 1e-3) / 1e9
-    traffic = None if shape else traffic_from_profile(args.workload, bytes_alg)
+    prof = None if shape else profile_counters(args.workload)
+    traffic = prof["traffic_bytes_per_launch"] if prof else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_advance", "kernel_ms": round(adv_ms, 4),
             "bytes_per_launch": bytes_alg, "bytes_per_particle": per_p,
             "bytes_per_element": per_e}
+    if prof:
+        # the second roof: measured VALU instructions per particle-step (SQ_INSTS_VALU)
+        ipp = prof["sq"]["valu_instructions_per_particle"]
+        ach = ipp * w.n_particles / (adv_ms * 1e-3)
+        roof["valu"] = {"instructions_per_particle": ipp, "achieved": round(ach / 1e12, 2),
+                        "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2), "unit": "Tlane-op/s",
+                        "frac": round(ach / VALU_PEAK_LANE_OPS, 4)}
     step_ms = wall * 1e3 / args.steps
     out = {
         "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,

@@ -993,9 +993,9 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
     p.e[i] = found;
     if constexpr (SHAPE)
       scatter_shape<T>(tab, m, sums, rec, found, x, y, un0, un1, un2, omn, psin);
-    else if (found == e0)  // the references of the start element are at hand
-      table_add<T>(tab, sums, ref0, found, un0, un1, un2, omn, psin);
     else {
+      // reloaded rather than kept from the start of the step: holding them
+      // across the walk costs register spills
       const T *rf = rec + (size_t)found * NREC;
       const T ref[5] = {rf[R_U], rf[R_V], rf[R_W], rf[R_OM], rf[R_PHI]};
       table_add<T>(tab, sums, ref, found, un0, un1, un2, omn, psin);
