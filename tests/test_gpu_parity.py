@@ -237,3 +237,58 @@ def test_brute_force_location_matches_oracle(L):
     # reaching the wall is lost (restored) on both sides alike
     assert oc["brute"] > 100 and c["brute"] == oc["brute"] and c["lost"] == oc["lost"]
     ctx.close()
+
+
+def test_kernel_parity_fp32_channel_block_full_size_sampled(L):
+    """The benchmark workload at full size in the benchmark's launch
+    configuration (~1M triangles, 100 per element, ~100M particles, FP32,
+    reorder every 8 steps).  After 9 GPU steps, one more step is compared on a
+    1% particle sample advanced by the oracle from the GPU's state and
+    statistics; the nodal statistics after that step are compared with the
+    oracle's estimate from the GPU's particles; particle count is conserved.
+    Particles are compared in storage order, which the 10th step keeps (the
+    reorder runs after steps 8, 16, ...)."""
+    import time
+
+    from paper_1006_0720_amd.runner import workload_context
+
+    t0 = time.time()
+
+    def say(msg):
+        print(f"[parity c5] {time.time() - t0:6.1f}s {msg}", flush=True)
+
+    w = CF.channel_block()
+    say(f"{w.name} np={w.n_particles}")
+    ctx = workload_context(w, reorder_every=8)
+    ctx.advance(9, w.dt)
+    st0, el0, pid0 = ctx.particles(sort_by_id=False)
+    stats0 = ctx.stats()
+    say("state after 9 steps copied")
+    ctx.advance(1, w.dt)
+    st1, el1, pid1 = ctx.particles(sort_by_id=False)
+    g1 = ctx.stats()
+    c = ctx.counters()
+    _, elst = ctx.stats(elem=True)
+    ctx.close()
+    say("state after 10 steps copied")
+    assert np.array_equal(pid0, pid1)
+    assert c["lost"] == 0 and c["nonfinite"] == 0
+    assert elst[0].sum() == w.n_particles
+    o = O.Oracle(w.mesh, w.params, store_fp32=True, gradp=w.gradp)
+    o.state, o.elem, o.id = st0, el0.copy(), pid0
+    o.seed_value = int(w.seed["seed"])
+    o.step_index = 9
+    o.set_stats(stats0)
+    mask = np.zeros(st0.shape[1], np.uint8)
+    mask[np.random.default_rng(1).choice(mask.size, mask.size // 100, replace=False)] = 1
+    o.step(w.dt, mask=mask)
+    say("oracle step on the 1% sample done")
+    sel = mask.astype(bool)
+    assert np.array_equal(el1[sel], o.elem[sel]), f"{(el1[sel] != o.elem[sel]).sum()} element mismatches"
+    compare_state(st1[:, sel], o.state[:, sel], w.mesh, 1e-5, "channel_block fp32 step (sample)")
+    # nodal statistics: the oracle's estimate from the GPU's particles after the step
+    o.state, o.elem = st1, el1
+    o.stats = stats0
+    est = o.estimate()
+    say("oracle estimate done")
+    compare_stats(g1, est, 1e-9, what="channel_block statistics")
