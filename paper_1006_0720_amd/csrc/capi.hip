@@ -988,6 +988,14 @@ pdf_status pdf_denoiser_features(pdf_denoiser *d, const double *nodal, float *fe
 pdf_status pdf_denoiser_forward(pdf_denoiser *d, const float *x, int32_t n, float *y) {
   if (!d || !x || !y || n < 0) return PDF_E_INVALID_ARG;
   pdf_ctx *c = d->ctx;
+  if (n == 0) return PDF_OK;
+  // the fused kernel keeps every activation in LDS (hidden widths up to 128)
+  if (launch_mlp_forward(c->stream, n, d->H, x, d->Pb + d->off[0], d->P + d->off[1], d->Pb + d->off[2],
+                         d->P + d->off[3], d->Pb + d->off[4], d->P + d->off[5], d->Pb + d->off[6],
+                         d->P + d->off[7], y)) {
+    HIPCHK(c, hipGetLastError());
+    return PDF_OK;
+  }
   const int32_t chunk = 65536;
   if (!dn_reserve(d, n < chunk ? n : chunk)) return fail(c, PDF_E_OOM, "denoiser buffers");
   for (int32_t r0 = 0; r0 < n; r0 += chunk) {

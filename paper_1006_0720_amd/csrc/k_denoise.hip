@@ -89,13 +89,124 @@ void launch_gemm_bf16(hipStream_t s, int M, int N, int K, const uint16_t *A, int
   hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta);
 }
 
-// ---------------------------------------------------------------------------
-// element-wise pieces of the MLP
-// ---------------------------------------------------------------------------
+// GELU (exact, through erf) and its derivative
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float dgelu(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.3989422804014327f * expf(-0.5f * x * x);
 }
+
+// ---------------------------------------------------------------------------
+// Fused inference: the whole MLP in one kernel.  A workgroup of 4 waves takes
+// 64 rows; each wave keeps its 16 rows' activations (bf16) in LDS through the
+// four layers, so activations never leave the CU.  Each layer's weights are
+// staged in LDS transposed ([n][k], k contiguous) so that both MFMA operands
+// are 8-byte LDS reads.  Rounding points are those of the layer-by-layer
+// path: fp32 accumulation, + bias, GELU, bf16.
+// ---------------------------------------------------------------------------
+constexpr int MLP_ROWS = 64, MLP_PAD = 8;
+
+__device__ __forceinline__ bf16x4 lds_frag(const uint16_t *p) {
+  const uint2 v = *(const uint2 *)p;
+  bf16x4 r;
+  r[0] = (short)(v.x & 0xFFFFu);
+  r[1] = (short)(v.x >> 16);
+  r[2] = (short)(v.y & 0xFFFFu);
+  r[3] = (short)(v.y >> 16);
+  return r;
+}
+
+// stage W [K][N] (row-major, global) as Wt [Np][K + MLP_PAD] (LDS), zero
+// columns N .. Np-1 (Np = N rounded up to 16)
+__device__ __forceinline__ void stage_wt(const uint16_t *W, int K, int N, uint16_t *Wt) {
+  const int Np = (N + 15) & ~15, ld = K + MLP_PAD;
+  for (int t = threadIdx.x; t < K * Np; t += blockDim.x) {
+    const int k = t / Np, n = t % Np;
+    Wt[n * ld + k] = n < N ? W[(size_t)k * N + n] : (uint16_t)0;
+  }
+}
+
+// one layer for the calling wave: out[16][N] = act(in[16][K] W + b)
+__device__ __forceinline__ void mlp_layer(const uint16_t *in, int K, const uint16_t *Wt, int N,
+                                          const float *b, bool gelu_act, uint16_t *out, float *y,
+                                          int64_t row0, int64_t nrows) {
+  const int lane = threadIdx.x & 63;
+  const int ldi = K + MLP_PAD;
+  const int kq = 4 * (lane >> 4), rc = lane & 15;
+  const int Np = (N + 15) & ~15;
+  for (int nt = 0; nt < Np; nt += 16) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      const bf16x4 fa = lds_frag(in + rc * ldi + k0 + kq);
+      const bf16x4 fb = lds_frag(Wt + (nt + rc) * ldi + k0 + kq);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa, fb, acc, 0, 0, 0);
+    }
+    const int col = nt + rc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = kq + q;
+      if (col < N) {
+        const float z = acc[q] + b[col];
+        if (y) {
+          if (row0 + row < nrows) y[(row0 + row) * N + col] = z;
+        } else {
+          out[row * (N + MLP_PAD) + col] = f2bf(gelu_act ? gelu(z) : z);
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(int64_t n, int H, const float *__restrict__ x,
+                                                     const uint16_t *W1, const float *b1, const uint16_t *W2,
+                                                     const float *b2, const uint16_t *W3, const float *b3,
+                                                     const uint16_t *W4, const float *b4, float *y) {
+  extern __shared__ uint16_t lds[];
+  const int ldh = H + MLP_PAD, ldx = 48 + MLP_PAD;
+  uint16_t *Wt = lds;                               // [H][max(H, 48) + PAD]
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint16_t *actA = lds + H * (H + MLP_PAD) + wave * 16 * ldh * 2;  // two [16][H + PAD] buffers
+  uint16_t *actB = actA + 16 * ldh;
+  const int64_t row0 = (int64_t)blockIdx.x * MLP_ROWS + wave * 16;
+  // inputs of this wave's 16 rows as bf16 [16][48 + PAD] in actA
+  for (int t = lane; t < 16 * 48; t += 64) {
+    const int r = t / 48, k = t % 48;
+    const int64_t g = row0 + r;
+    actA[r * ldx + k] = f2bf(g < n ? x[g * 48 + k] : 0.f);
+  }
+  stage_wt(W1, 48, H, Wt);
+  __syncthreads();
+  mlp_layer(actA, 48, Wt, H, b1, true, actB, nullptr, row0, n);
+  __syncthreads();
+  stage_wt(W2, H, H, Wt);
+  __syncthreads();
+  mlp_layer(actB, H, Wt, H, b2, true, actA, nullptr, row0, n);
+  __syncthreads();
+  stage_wt(W3, H, H, Wt);
+  __syncthreads();
+  mlp_layer(actA, H, Wt, H, b3, true, actB, nullptr, row0, n);
+  __syncthreads();
+  stage_wt(W4, H, 8, Wt);
+  __syncthreads();
+  mlp_layer(actB, H, Wt, 8, b4, false, nullptr, y, row0, n);
+}
+
+size_t mlp_forward_lds(int H) {
+  return ((size_t)H * (H + MLP_PAD) + 4 * 2 * 16 * (size_t)(H + MLP_PAD)) * sizeof(uint16_t);
+}
+
+bool launch_mlp_forward(hipStream_t s, int64_t n, int H, const float *x, const uint16_t *W1, const float *b1,
+                        const uint16_t *W2, const float *b2, const uint16_t *W3, const float *b3,
+                        const uint16_t *W4, const float *b4, float *y) {
+  if (H < 48 || H > 128 || n <= 0) return false;  // LDS holds H x (H + 8) weights and the activations
+  const unsigned g = (unsigned)((n + MLP_ROWS - 1) / MLP_ROWS);
+  hipLaunchKernelGGL(k_mlp_forward, dim3(g), dim3(256), mlp_forward_lds(H), s, n, H, x, W1, b1, W2, b2, W3,
+                     b3, W4, b4, y);
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// element-wise pieces of the MLP
+// ---------------------------------------------------------------------------
 
 // Z += b (in place, fp32) and H = gelu(Z) (bf16) or H = Z (bf16) when act == 0
 __global__ void k_bias_act(int M, int N, float *Z, const float *b, uint16_t *H, int act) {

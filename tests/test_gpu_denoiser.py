@@ -43,8 +43,10 @@ def _layer_slices(h):
     return [slice(o[i], o[i + 1]) for i in range(8)]
 
 
-@pytest.mark.parametrize("h,B", [(32, 100), (128, 1000)])
+@pytest.mark.parametrize("h,B", [(32, 100), (64, 333), (128, 1000), (128, 70001)])
 def test_forward_matches_reference(env, h, B):
+    """h = 32: layer-by-layer GEMMs; h = 64, 128: the fused one-kernel inference
+    (64-row workgroups; 70001 rows leave a ragged last workgroup)."""
     torch, L, ctx, w = env
     dn = L.Denoiser(ctx, hidden=h, seed=3)
     p = dn.params().astype(np.float64)
@@ -136,4 +138,21 @@ def test_merge_zero_network_and_fallback(env):
         assert np.all(d[se[fld] * 3.0 < 1e-9 * (1 - 1e-6)] == 0)
         rejected += int((se[fld] * 3.0 < 1e-9 * (1 - 1e-6)).sum())
     assert nf == rejected
+    dn.close()
+
+
+def test_fused_inference_matches_training_forward(env):
+    """The fused inference and the layer-by-layer forward of the training step
+    round at the same points: the training loss at lr = 0 equals the mean
+    squared error of the fused outputs."""
+    torch, L, ctx, w = env
+    dn = L.Denoiser(ctx, hidden=128, seed=9)
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=(4096, 48)).astype(np.float32)
+    t = rng.normal(size=(4096, 8)).astype(np.float32)
+    xt, tt = _tensors(torch, x, t)
+    y = dn.forward(xt).cpu().numpy().astype(np.float64)
+    loss = dn.train_step(xt, tt, 0.0)
+    ref = float(((y - t) ** 2).mean())
+    assert abs(loss - ref) <= 1e-5 * ref
     dn.close()
