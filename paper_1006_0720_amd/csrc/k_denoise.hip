@@ -7,6 +7,8 @@
 //   A: row l%16, columns 4*(l/16) .. +3      B: rows 4*(l/16) .. +3, column l%16
 //   C/D: rows 4*(l/16) .. +3, column l%16
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <hip/hip_bf16.h>
 
 #include "pdf_internal.h"
@@ -35,7 +37,7 @@ constexpr int GT = 64, GK = 16;
 __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const uint16_t *__restrict__ A,
                                                    int lda, int ta, const uint16_t *__restrict__ B,
                                                    int ldb, int tb, float *__restrict__ C, int ldc,
-                                                   float beta) {
+                                                   float beta, int kchunk) {
   __shared__ uint16_t sA[GT][GK + 4];  // [row i][k]
   __shared__ uint16_t sB[GK][GT + 4];  // [k][col j]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -44,18 +46,21 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
   f32x4 acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += GK) {
+  // split-K: workgroup z covers k in [kb, ke) and adds its partial product
+  const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  const bool split = gridDim.z > 1;
+  for (int k0 = kb; k0 < ke; k0 += GK) {
     // stage 64x16 of op(A) and 16x64 of op(B) (four elements per thread each)
     for (int t = tid; t < GT * GK; t += 256) {
       const int r = t / GK, k = t % GK;
       const int gi = i0 + r, gk = k0 + k;
       uint16_t v = 0;
-      if (gi < M && gk < K) v = ta ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk];
+      if (gi < M && gk < ke) v = ta ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk];
       sA[r][k] = v;
       const int kb = t / GT, c = t % GT;
       const int gj = j0 + c, gkb = k0 + kb;
       uint16_t w = 0;
-      if (gj < N && gkb < K) w = tb ? B[(size_t)gj * ldb + gkb] : B[(size_t)gkb * ldb + gj];
+      if (gj < N && gkb < ke) w = tb ? B[(size_t)gj * ldb + gkb] : B[(size_t)gkb * ldb + gj];
       sB[kb][c] = w;
     }
     __syncthreads();
@@ -78,15 +83,33 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
         const int gi = i0 + wi + 16 * a + rq + q, gj = j0 + wj + 16 * b + cc;
         if (gi < M && gj < N) {
           float *c = &C[(size_t)gi * ldc + gj];
-          *c = (beta != 0.f ? beta * *c : 0.f) + acc[a][b][q];
+          if (split)
+            unsafeAtomicAdd(c, acc[a][b][q]);
+          else
+            *c = (beta != 0.f ? beta * *c : 0.f) + acc[a][b][q];
         }
       }
 }
 
+__global__ void k_zero2d(int M, int N, float *C, int ldc) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < (int64_t)M * N) C[(t / N) * ldc + t % N] = 0.f;
+}
+
 void launch_gemm_bf16(hipStream_t s, int M, int N, int K, const uint16_t *A, int lda, int ta,
                       const uint16_t *B, int ldb, int tb, float *C, int ldc, float beta) {
-  dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
-  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta);
+  const int tiles = ((N + GT - 1) / GT) * ((M + GT - 1) / GT);
+  // few output tiles and a long K (weight gradients over a batch): split K
+  // so that the grid fills the GPU; partial products are added atomically
+  int splits = 1;
+  if (beta == 0.f && tiles < 512 && K >= 4 * 256) splits = std::min((K + 255) / 256, std::max(1, 2048 / tiles));
+  int kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + GK - 1) / GK * GK;
+  splits = (K + kchunk - 1) / kchunk;
+  if (splits > 1)
+    hipLaunchKernelGGL(k_zero2d, dim3((unsigned)(((int64_t)M * N + 255) / 256)), dim3(256), 0, s, M, N, C, ldc);
+  dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, splits);
+  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta, kchunk);
 }
 
 // GELU (exact, through erf) and its derivative

@@ -59,7 +59,7 @@ def test_forward_matches_reference(env, h, B):
     dn.close()
 
 
-@pytest.mark.parametrize("h,B", [(32, 64), (128, 777)])
+@pytest.mark.parametrize("h,B", [(32, 64), (128, 777), (128, 8191)])
 def test_gradients_match_reference(env, h, B):
     torch, L, ctx, w = env
     dn = L.Denoiser(ctx, hidden=h, seed=5)
