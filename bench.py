@@ -114,7 +114,7 @@ def denoise_study(mode, out_path=""):
                   batch=4096, eval_ppes=(20, 40))
     else:
         mesh = M.canyon(200_000, 0.15, 0)
-        kw = dict(n_train=12, n_test=3, steps_spin=100, n_snap=5, every=10, train_steps=3000,
+        kw = dict(n_train=12, n_test=3, steps_spin=100, n_snap=5, every=10, train_steps=8000,
                   batch=8192, eval_ppes=(20, 40, 80))
 
     def make(ppe, seed, src):

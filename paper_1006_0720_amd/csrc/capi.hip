@@ -789,6 +789,10 @@ struct pdf_denoiser {
   int64_t off[8] = {0};  // W1 b1 W2 b2 W3 b3 W4 b4
   float *P = nullptr, *G = nullptr, *Mom = nullptr, *Vel = nullptr;
   uint16_t *Pb = nullptr;  // bf16 copy of the parameters (weights used by the GEMMs)
+  uint16_t *Wt = nullptr;  // transposed, padded bf16 weights of the fused inference
+  bool wt_stale = true;    // Wt must be rebuilt from Pb before the next inference
+  float *R = nullptr;      // network outputs of pdf_denoise_stats [n_nodes][8]
+  double *res = nullptr;   // denoised statistics staging [PDF_NSTAT][n_nodes]
   float *mu = nullptr, *sig = nullptr, *scale = nullptr;
   bool norm_set = false;
   int64_t adam_t = 0;
@@ -871,6 +875,7 @@ pdf_status pdf_denoiser_create(pdf_ctx *c, int32_t hidden, uint64_t seed, pdf_de
   d->Mom = (float *)dalloc(c, o * 4);
   d->Vel = (float *)dalloc(c, o * 4);
   d->Pb = (uint16_t *)dalloc(c, o * 2);
+  if (hidden >= 48 && hidden <= 128) d->Wt = (uint16_t *)dalloc(c, mlp_transposed_elems(hidden) * 2);
   d->mu = (float *)dalloc(c, 64 * 4);
   d->sig = (float *)dalloc(c, 64 * 4);
   d->scale = (float *)dalloc(c, 16 * 4);
@@ -941,7 +946,7 @@ void pdf_denoiser_destroy(pdf_denoiser *d) {
   (void)hipStreamSynchronize(c->stream);
   void *ps[] = {d->P, d->G, d->Mom, d->Vel, d->Pb, d->mu, d->sig, d->scale, d->p2p_off, d->p2p, d->Xb,
                 d->H1, d->H2, d->H3, d->dYb, d->dZb, d->Z1, d->Z2, d->Z3, d->Y, d->dH, d->part, d->feat,
-                d->nfall};
+                d->nfall, d->Wt, d->R, d->res};
   for (void *p : ps) dfree(c, p);
   delete d;
 }
@@ -954,6 +959,7 @@ pdf_status pdf_denoiser_params(pdf_denoiser *d, float *host, int64_t n, int32_t 
     HIPCHK(c, hipMemsetAsync(d->Mom, 0, n * 4, c->stream));
     HIPCHK(c, hipMemsetAsync(d->Vel, 0, n * 4, c->stream));
     launch_to_bf16(c->stream, n, d->P, d->Pb);
+    d->wt_stale = true;
     d->adam_t = 0;
   } else {
     HIPCHK(c, hipMemcpyAsync(host, d->P, n * 4, hipMemcpyDeviceToHost, c->stream));
@@ -990,11 +996,17 @@ pdf_status pdf_denoiser_forward(pdf_denoiser *d, const float *x, int32_t n, floa
   pdf_ctx *c = d->ctx;
   if (n == 0) return PDF_OK;
   // the fused kernel keeps every activation in LDS (hidden widths up to 128)
-  if (launch_mlp_forward(c->stream, n, d->H, x, d->Pb + d->off[0], d->P + d->off[1], d->Pb + d->off[2],
-                         d->P + d->off[3], d->Pb + d->off[4], d->P + d->off[5], d->Pb + d->off[6],
-                         d->P + d->off[7], y)) {
-    HIPCHK(c, hipGetLastError());
-    return PDF_OK;
+  if (d->Wt) {
+    if (d->wt_stale) {
+      launch_transpose_weights(c->stream, d->H, d->Pb + d->off[0], d->Pb + d->off[2], d->Pb + d->off[4],
+                               d->Pb + d->off[6], d->Wt);
+      d->wt_stale = false;
+    }
+    if (launch_mlp_forward(c->stream, n, d->H, x, d->Wt, d->P + d->off[1], d->P + d->off[3], d->P + d->off[5],
+                           d->P + d->off[7], y)) {
+      HIPCHK(c, hipGetLastError());
+      return PDF_OK;
+    }
   }
   const int32_t chunk = 65536;
   if (!dn_reserve(d, n < chunk ? n : chunk)) return fail(c, PDF_E_OOM, "denoiser buffers");
@@ -1046,6 +1058,7 @@ pdf_status pdf_denoiser_train_step(pdf_denoiser *d, const float *x, const float 
     const float c1 = 1.f - (float)std::pow((double)b1, (double)d->adam_t);
     const float c2 = 1.f - (float)std::pow((double)b2, (double)d->adam_t);
     launch_adam(s, d->np, d->P, g, d->Mom, d->Vel, d->Pb, lr, b1, b2, 1e-8f, c1, c2);
+    d->wt_stale = true;
     HIPCHK(c, hipGetLastError());
   }
   if (loss) {
@@ -1071,8 +1084,10 @@ pdf_status pdf_denoise_stats(pdf_denoiser *d, double tau, double *out, int32_t o
   hipStream_t s = c->stream;
   const int32_t nn = c->md.nn;
   launch_features(s, c->md, d->p2p_off, d->p2p, c->latest, d->mu, d->sig, d->feat, nullptr);
-  float *R = (float *)dalloc(c, (size_t)nn * PDF_DN_NOUT * 4);
-  double *res = on_device ? out : (double *)dalloc(c, (size_t)PDF_NSTAT * nn * 8);
+  if (!d->R) d->R = (float *)dalloc(c, (size_t)nn * PDF_DN_NOUT * 4);
+  if (!on_device && !d->res) d->res = (double *)dalloc(c, (size_t)PDF_NSTAT * nn * 8);
+  float *R = d->R;
+  double *res = on_device ? out : d->res;
   if (!R || !res) return fail(c, PDF_E_OOM, "denoiser output buffers");
   pdf_status st = pdf_denoiser_forward(d, d->feat, nn, R);
   if (st != PDF_OK) return st;
@@ -1086,8 +1101,6 @@ pdf_status pdf_denoise_stats(pdf_denoiser *d, double tau, double *out, int32_t o
     HIPCHK(c, hipMemcpyAsync(out, res, (size_t)PDF_NSTAT * nn * 8, hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   if (n_fallback) *n_fallback = nf;
-  dfree(c, R);
-  if (!on_device) dfree(c, res);
   return PDF_OK;
 }
 

@@ -138,17 +138,38 @@ __device__ __forceinline__ bf16x4 lds_frag(const uint16_t *p) {
   return r;
 }
 
-// stage W [K][N] (row-major, global) as Wt [Np][K + MLP_PAD] (LDS), zero
-// columns N .. Np-1 (Np = N rounded up to 16)
-__device__ __forceinline__ void stage_wt(const uint16_t *W, int K, int N, uint16_t *Wt) {
+// W [K][N] (row-major) -> Wt [Np][K + MLP_PAD] (Np = N rounded up to 16,
+// columns N .. Np-1 zero): the LDS layout of a layer, kept in global memory
+// so that a workgroup stages it with 16-byte copies
+__global__ void k_transpose_w(const uint16_t *W, int K, int N, uint16_t *Wt) {
   const int Np = (N + 15) & ~15, ld = K + MLP_PAD;
-  for (int t = threadIdx.x; t < K * Np; t += blockDim.x) {
-    const int k = t / Np, n = t % Np;
-    Wt[n * ld + k] = n < N ? W[(size_t)k * N + n] : (uint16_t)0;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= Np * ld) return;
+  const int n = t / ld, k = t % ld;
+  Wt[t] = (n < N && k < K) ? W[(size_t)k * N + n] : (uint16_t)0;
+}
+
+__host__ __device__ inline size_t mlp_wt_elems(int K, int N) { return (size_t)((N + 15) & ~15) * (K + MLP_PAD); }
+
+void launch_transpose_weights(hipStream_t s, int H, const uint16_t *W1, const uint16_t *W2, const uint16_t *W3,
+                              const uint16_t *W4, uint16_t *Wt) {
+  const uint16_t *W[4] = {W1, W2, W3, W4};
+  const int K[4] = {48, H, H, H}, N[4] = {H, H, H, 8};
+  for (int l = 0; l < 4; ++l) {
+    const size_t ne = mlp_wt_elems(K[l], N[l]);
+    hipLaunchKernelGGL(k_transpose_w, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, W[l], K[l], N[l], Wt);
+    Wt += ne;
   }
 }
 
-// one layer for the calling wave: out[16][N] = act(in[16][K] W + b)
+__device__ __forceinline__ void stage_copy(const uint16_t *src, size_t n, uint16_t *dst) {
+  const uint4 *s4 = (const uint4 *)src;
+  uint4 *d4 = (uint4 *)dst;
+  for (size_t t = threadIdx.x; t < n / 8; t += blockDim.x) d4[t] = s4[t];
+}
+
+// one layer for the calling wave: out[16][N] = act(in[16][K] W + b); four
+// independent accumulators per pass over K
 __device__ __forceinline__ void mlp_layer(const uint16_t *in, int K, const uint16_t *Wt, int N,
                                           const float *b, bool gelu_act, uint16_t *out, float *y,
                                           int64_t row0, int64_t nrows) {
@@ -156,23 +177,34 @@ __device__ __forceinline__ void mlp_layer(const uint16_t *in, int K, const uint1
   const int ldi = K + MLP_PAD;
   const int kq = 4 * (lane >> 4), rc = lane & 15;
   const int Np = (N + 15) & ~15;
-  for (int nt = 0; nt < Np; nt += 16) {
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int n0 = 0; n0 < Np; n0 += 64) {
+    const int nt_cnt = min(4, (Np - n0) / 16);
+    f32x4 acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = (f32x4){0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < K; k0 += 16) {
       const bf16x4 fa = lds_frag(in + rc * ldi + k0 + kq);
-      const bf16x4 fb = lds_frag(Wt + (nt + rc) * ldi + k0 + kq);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa, fb, acc, 0, 0, 0);
-    }
-    const int col = nt + rc;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int row = kq + q;
-      if (col < N) {
-        const float z = acc[q] + b[col];
-        if (y) {
-          if (row0 + row < nrows) y[(row0 + row) * N + col] = z;
-        } else {
-          out[row * (N + MLP_PAD) + col] = f2bf(gelu_act ? gelu(z) : z);
+      for (int u = 0; u < 4; ++u)
+        if (u < nt_cnt) {
+          const bf16x4 fb = lds_frag(Wt + (n0 + 16 * u + rc) * ldi + k0 + kq);
+          acc[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa, fb, acc[u], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (u >= nt_cnt) break;
+      const int col = n0 + 16 * u + rc;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = kq + q;
+        if (col < N) {
+          const float z = acc[u][q] + b[col];
+          if (y) {
+            if (row0 + row < nrows) y[(row0 + row) * N + col] = z;
+          } else {
+            out[row * (N + MLP_PAD) + col] = f2bf(gelu_act ? gelu(z) : z);
+          }
         }
       }
     }
@@ -180,35 +212,36 @@ __device__ __forceinline__ void mlp_layer(const uint16_t *in, int K, const uint1
 }
 
 __global__ __launch_bounds__(256) void k_mlp_forward(int64_t n, int H, const float *__restrict__ x,
-                                                     const uint16_t *W1, const float *b1, const uint16_t *W2,
-                                                     const float *b2, const uint16_t *W3, const float *b3,
-                                                     const uint16_t *W4, const float *b4, float *y) {
+                                                     const uint16_t *__restrict__ Wt_all, const float *b1,
+                                                     const float *b2, const float *b3, const float *b4,
+                                                     float *y) {
   extern __shared__ uint16_t lds[];
   const int ldh = H + MLP_PAD, ldx = 48 + MLP_PAD;
-  uint16_t *Wt = lds;                               // [H][max(H, 48) + PAD]
+  uint16_t *Wt = lds;                               // one layer, [Np][K + PAD]
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   uint16_t *actA = lds + H * (H + MLP_PAD) + wave * 16 * ldh * 2;  // two [16][H + PAD] buffers
   uint16_t *actB = actA + 16 * ldh;
   const int64_t row0 = (int64_t)blockIdx.x * MLP_ROWS + wave * 16;
-  // inputs of this wave's 16 rows as bf16 [16][48 + PAD] in actA
+  const size_t n1 = mlp_wt_elems(48, H), n2 = mlp_wt_elems(H, H), n4 = mlp_wt_elems(H, 8);
+  const uint16_t *Wt1 = Wt_all, *Wt2 = Wt1 + n1, *Wt3 = Wt2 + n2, *Wt4 = Wt3 + n2;
   for (int t = lane; t < 16 * 48; t += 64) {
     const int r = t / 48, k = t % 48;
     const int64_t g = row0 + r;
     actA[r * ldx + k] = f2bf(g < n ? x[g * 48 + k] : 0.f);
   }
-  stage_wt(W1, 48, H, Wt);
+  stage_copy(Wt1, n1, Wt);
   __syncthreads();
   mlp_layer(actA, 48, Wt, H, b1, true, actB, nullptr, row0, n);
   __syncthreads();
-  stage_wt(W2, H, H, Wt);
+  stage_copy(Wt2, n2, Wt);
   __syncthreads();
   mlp_layer(actB, H, Wt, H, b2, true, actA, nullptr, row0, n);
   __syncthreads();
-  stage_wt(W3, H, H, Wt);
+  stage_copy(Wt3, n2, Wt);
   __syncthreads();
   mlp_layer(actA, H, Wt, H, b3, true, actB, nullptr, row0, n);
   __syncthreads();
-  stage_wt(W4, H, 8, Wt);
+  stage_copy(Wt4, n4, Wt);
   __syncthreads();
   mlp_layer(actB, H, Wt, 8, b4, false, nullptr, y, row0, n);
 }
@@ -217,13 +250,13 @@ size_t mlp_forward_lds(int H) {
   return ((size_t)H * (H + MLP_PAD) + 4 * 2 * 16 * (size_t)(H + MLP_PAD)) * sizeof(uint16_t);
 }
 
-bool launch_mlp_forward(hipStream_t s, int64_t n, int H, const float *x, const uint16_t *W1, const float *b1,
-                        const uint16_t *W2, const float *b2, const uint16_t *W3, const float *b3,
-                        const uint16_t *W4, const float *b4, float *y) {
+size_t mlp_transposed_elems(int H) { return mlp_wt_elems(48, H) + 2 * mlp_wt_elems(H, H) + mlp_wt_elems(H, 8); }
+
+bool launch_mlp_forward(hipStream_t s, int64_t n, int H, const float *x, const uint16_t *Wt_all, const float *b1,
+                        const float *b2, const float *b3, const float *b4, float *y) {
   if (H < 48 || H > 128 || n <= 0) return false;  // LDS holds H x (H + 8) weights and the activations
   const unsigned g = (unsigned)((n + MLP_ROWS - 1) / MLP_ROWS);
-  hipLaunchKernelGGL(k_mlp_forward, dim3(g), dim3(256), mlp_forward_lds(H), s, n, H, x, W1, b1, W2, b2, W3,
-                     b3, W4, b4, y);
+  hipLaunchKernelGGL(k_mlp_forward, dim3(g), dim3(256), mlp_forward_lds(H), s, n, H, x, Wt_all, b1, b2, b3, b4, y);
   return true;
 }
 
@@ -349,55 +382,53 @@ void launch_to_bf16(hipStream_t s, int64_t n, const float *x, uint16_t *y) {
 // ---------------------------------------------------------------------------
 __constant__ int kQuant[8] = {0, 1, 4, 5, 6, 8, 11, 3};
 
+// one thread per (node, statistic): the 6 features of statistic a at node n
 __global__ __launch_bounds__(256) void k_features(MeshDev m, const int32_t *p2p_off, const int32_t *p2p,
                                                   const double *S, const float *mu, const float *sig,
                                                   float *F, uint16_t *Fb) {
-  const int32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t n = (int32_t)(t >> 3);
+  const int a = (int)(t & 7);
   if (n >= m.nn) return;
   const int nn = m.nn;
   const int32_t q = m.master[n];
-  float f[48];
-  for (int a = 0; a < 8; ++a) {
-    const int fld = kQuant[a];
-    const double v0 = S[(size_t)fld * nn + q];
-    double sum = v0, sum2 = v0 * v0, mn = v0, mx = v0;
-    int c = 1;
-    for (int32_t i = p2p_off[q]; i < p2p_off[q + 1]; ++i) {
-      const double v = S[(size_t)fld * nn + p2p[i]];
-      sum += v;
-      sum2 += v * v;
-      mn = v < mn ? v : mn;
-      mx = v > mx ? v : mx;
-      c++;
-    }
-    const double mean = sum / c;
-    double var = sum2 / c - mean * mean;
-    var = var > 0.0 ? var : 0.0;
-    double gx = 0.0, gy = 0.0;
-    int ce = 0;
-    for (int32_t i = m.m2e_off[q]; i < m.m2e_off[q + 1]; ++i) {
-      const int32_t e = m.m2e[i];
-      const double *d = m.dN + 6 * (size_t)e;
-      for (int k = 0; k < 3; ++k) {
-        const double val = S[(size_t)fld * nn + m.mnode[3 * e + k]];
-        gx += d[k] * val;
-        gy += d[3 + k] * val;
-      }
-      ce++;
-    }
-    if (ce) {
-      gx /= ce;
-      gy /= ce;
-    }
-    f[6 * a + 0] = (float)v0;
-    f[6 * a + 1] = (float)mean;
-    f[6 * a + 2] = (float)sqrt(var);
-    f[6 * a + 3] = (float)mn;
-    f[6 * a + 4] = (float)mx;
-    f[6 * a + 5] = (float)sqrt(gx * gx + gy * gy);
+  const int fld = kQuant[a];
+  const double *Sf = S + (size_t)fld * nn;
+  const double v0 = Sf[q];
+  double sum = v0, sum2 = v0 * v0, mn = v0, mx = v0;
+  int c = 1;
+  for (int32_t i = p2p_off[q]; i < p2p_off[q + 1]; ++i) {
+    const double v = Sf[p2p[i]];
+    sum += v;
+    sum2 += v * v;
+    mn = v < mn ? v : mn;
+    mx = v > mx ? v : mx;
+    c++;
   }
-  for (int k = 0; k < 48; ++k) {
-    const float z = mu ? (f[k] - mu[k]) / sig[k] : f[k];
+  const double mean = sum / c;
+  double var = sum2 / c - mean * mean;
+  var = var > 0.0 ? var : 0.0;
+  double gx = 0.0, gy = 0.0;
+  int ce = 0;
+  for (int32_t i = m.m2e_off[q]; i < m.m2e_off[q + 1]; ++i) {
+    const int32_t e = m.m2e[i];
+    const double *d = m.dN + 6 * (size_t)e;
+    for (int k = 0; k < 3; ++k) {
+      const double val = Sf[m.mnode[3 * e + k]];
+      gx += d[k] * val;
+      gy += d[3 + k] * val;
+    }
+    ce++;
+  }
+  if (ce) {
+    gx /= ce;
+    gy /= ce;
+  }
+  const float f[6] = {(float)v0, (float)mean, (float)sqrt(var), (float)mn, (float)mx,
+                      (float)sqrt(gx * gx + gy * gy)};
+  for (int j = 0; j < 6; ++j) {
+    const int k = 6 * a + j;
+    const float z = mu ? (f[j] - mu[k]) / sig[k] : f[j];
     F[(size_t)n * 48 + k] = z;
     if (Fb) Fb[(size_t)n * 48 + k] = f2bf(z);
   }
@@ -405,8 +436,8 @@ __global__ __launch_bounds__(256) void k_features(MeshDev m, const int32_t *p2p_
 
 void launch_features(hipStream_t s, const MeshDev &m, const int32_t *p2p_off, const int32_t *p2p,
                      const double *S, const float *mu, const float *sig, float *F, uint16_t *Fb) {
-  hipLaunchKernelGGL(k_features, dim3((m.nn + 255) / 256), dim3(256), 0, s, m, p2p_off, p2p, S, mu, sig,
-                     F, Fb);
+  hipLaunchKernelGGL(k_features, dim3((unsigned)(((int64_t)m.nn * 8 + 255) / 256)), dim3(256), 0, s, m, p2p_off,
+                     p2p, S, mu, sig, F, Fb);
 }
 
 // Merge: q = q_plain + scale_q * r_q, except where |scale_q r_q| exceeds tau

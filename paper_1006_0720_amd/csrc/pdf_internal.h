@@ -163,10 +163,13 @@ int launch_mse(hipStream_t s, int M, int nout, int ldy, float *Y, const float *T
 void launch_adam(hipStream_t s, int64_t n, float *w, const float *g, float *m, float *v, uint16_t *wb,
                  float lr, float b1, float b2, float eps, float c1, float c2);
 void launch_to_bf16(hipStream_t s, int64_t n, const float *x, uint16_t *y);
-// fused inference of the whole MLP (hidden width 48 .. 128); false: not applicable
-bool launch_mlp_forward(hipStream_t s, int64_t n, int H, const float *x, const uint16_t *W1, const float *b1,
-                        const uint16_t *W2, const float *b2, const uint16_t *W3, const float *b3,
-                        const uint16_t *W4, const float *b4, float *y);
+// fused inference of the whole MLP (hidden width 48 .. 128) from the
+// transposed weight copy; false: not applicable
+size_t mlp_transposed_elems(int H);
+void launch_transpose_weights(hipStream_t s, int H, const uint16_t *W1, const uint16_t *W2, const uint16_t *W3,
+                              const uint16_t *W4, uint16_t *Wt);
+bool launch_mlp_forward(hipStream_t s, int64_t n, int H, const float *x, const uint16_t *Wt_all, const float *b1,
+                        const float *b2, const float *b3, const float *b4, float *y);
 void launch_features(hipStream_t s, const MeshDev &m, const int32_t *p2p_off, const int32_t *p2p,
                      const double *S, const float *mu, const float *sig, float *F, uint16_t *Fb);
 void launch_merge(hipStream_t s, int nn, const int32_t *master, const double *S, const float *R, int ldr,

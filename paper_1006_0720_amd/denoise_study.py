@@ -186,8 +186,13 @@ def study(make_workload, n_train=12, n_test=3, ppe_low=10, ppe_high=200, eval_pp
     t_eq = float(slope * ppe_eq + icpt) if np.isfinite(ppe_eq) else float("inf")
     t_dn = float(np.median(t_den))
     ratio = t_eq / (T_plain[ppe_low] + t_dn)
+    inv_nf = E_learned_nofb ** 2 / a_fit - 1.0 / ppe_high
+    ppe_eq_nf = float(1.0 / inv_nf) if inv_nf > 0 else float("inf")
+    t_eq_nf = float(slope * ppe_eq_nf + icpt) if np.isfinite(ppe_eq_nf) else float("inf")
+    ratio_nf = t_eq_nf / (T_plain[ppe_low] + t_dn)
     out = {"E_plain": E_plain, "E_learned": E_learned, "E_learned_no_fallback": E_learned_nofb, "ppe_eq": ppe_eq, "a_fit": a_fit,
            "T_plain_s": T_plain, "T_denoise_s": t_dn, "cost_ratio": ratio,
+           "ppe_eq_no_fallback": ppe_eq_nf, "cost_ratio_no_fallback": ratio_nf,
            "per_statistic_ratio": (np.mean(e_learn, axis=0) / norm).tolist(),
            "per_statistic_ratio_no_fallback": (np.mean(e_learn_nofb, axis=0) / norm).tolist(),
            "per_statistic_rejected_fraction": np.mean(rej, axis=0).tolist(),

@@ -155,4 +155,9 @@ def test_fused_inference_matches_training_forward(env):
     loss = dn.train_step(xt, tt, 0.0)
     ref = float(((y - t) ** 2).mean())
     assert abs(loss - ref) <= 1e-5 * ref
+    # after an update the inference must use the new weights
+    dn.train_step(xt, tt, 1e-2)
+    y2 = dn.forward(xt).cpu().numpy().astype(np.float64)
+    loss2 = dn.train_step(xt, tt, 0.0)
+    assert abs(loss2 - float(((y2 - t) ** 2).mean())) <= 1e-5 * loss2 and abs(loss2 - loss) > 1e-4 * loss
     dn.close()
