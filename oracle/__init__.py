@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "liboracle.so")
 NSTAT = 25
 CNT_NAMES = ["walk_steps", "fallback", "brute", "lost", "reflect", "periodic", "noslip_b",
-             "omega_clamp", "gamma_fail", "empty_node"]
+             "omega_clamp", "gamma_fail", "empty_node", "redist"]
 
 
 def build(force=False):
@@ -65,13 +65,15 @@ def lib():
         L.or_step.argtypes = [C.c_void_p, C.c_void_p, dp, dp, dp, C.c_int64, dp, ip, up,
                               C.c_uint64, C.c_uint32, C.c_double, C.POINTER(C.c_uint8), u64p]
         L.or_step.restype = C.c_int32
+        L.or_redistribute.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, dp, ip, up, C.c_uint64, C.c_uint32]
+        L.or_redistribute.restype = C.c_int64
         _lib = L
     return _lib
 
 
 class _Params(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("model", "wp_source", "omega_source", "tm_mode", "frozen",
-                                         "wall_b", "store_fp32", "stats_mode")] + \
+                                         "wall_b", "store_fp32", "stats_mode", "min_ppe", "pad")] + \
                [(n, C.c_double) for n in ("C0", "C1", "C2", "C3", "C4", "CT", "CL", "Ceta", "Cv",
                                           "gamma5", "Cw1", "Cw2", "Cphi", "nu", "k_floor",
                                           "src_x", "src_y", "src_r")]
@@ -95,6 +97,10 @@ def _params(params: dict, store_fp32: bool):
             p.store_fp32 = int(store_fp32)
         elif name == "stats_mode":
             p.stats_mode = int(params.get("stats_mode", 0))
+        elif name == "min_ppe":
+            p.min_ppe = int(params.get("min_ppe", 0))
+        elif name == "pad":
+            p.pad = 0
         else:
             setattr(p, name, params[name])
     return p
@@ -252,6 +258,11 @@ class Oracle:
             wpp = _p(wp, C.c_double)
         else:
             wpp = None
+        if int(self.params.get("min_ppe", 0)) > 0:
+            moved = lib().or_redistribute(self.om.h, C.byref(self.cp), self.state.shape[1],
+                                          _p(self.state, C.c_double), _p(self.elem, C.c_int32),
+                                          _p(self.id, C.c_uint32), self.seed_value, self.step_index)
+            self.counters[CNT_NAMES.index("redist")] += moved
         gp = None if self.gradp is None else _p(self.gradp, C.c_double)
         mk = None if mask is None else _p(np.ascontiguousarray(mask, np.uint8), C.c_uint8)
         if mask is not None:

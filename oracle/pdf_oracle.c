@@ -693,6 +693,102 @@ void or_seed(const or_mesh *m, const or_params *p, const or_seedspec *s, double 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Particle redistribution (App. D, improved algorithm).                     */
+/* The elements are ordered by increasing particle count (ties: increasing   */
+/* element number).  The k-th element of that order with fewer than         */
+/* min_ppe particles receives particles from the k-th element from the top:  */
+/* m = min(min_ppe - N_receiver, N_donor - min_ppe) of the donor's particles */
+/* (its first ones by increasing id) move, each taking the whole state of a   */
+/* receiver resident (its residents by increasing id, cycled).  An empty     */
+/* receiver gets a uniform position in the element instead (uniforms from    */
+/* sub-stream 3 of the particle's step counter), the rest of the moving      */
+/* particle's state kept.  Donors never fall below min_ppe; a donor at or    */
+/* below its receiver's place in the order ends the pass.                    */
+/* ------------------------------------------------------------------------ */
+typedef struct { int32_t n, e; } or_ne;
+static int cmp_ne(const void *a, const void *b) {
+  const or_ne *x = (const or_ne *)a, *y = (const or_ne *)b;
+  if (x->n != y->n) return x->n < y->n ? -1 : 1;
+  return x->e < y->e ? -1 : (x->e > y->e ? 1 : 0);
+}
+typedef struct { uint32_t id; int64_t i; } or_idx;
+static int cmp_idx(const void *a, const void *b) {
+  const or_idx *x = (const or_idx *)a, *y = (const or_idx *)b;
+  return x->id < y->id ? -1 : (x->id > y->id ? 1 : 0);
+}
+/* the particles of element e in increasing id order */
+static int64_t members(int64_t np, const int32_t *elem, const uint32_t *id, int32_t e, or_idx *out) {
+  int64_t c = 0;
+  for (int64_t i = 0; i < np; ++i)
+    if (elem[i] == e) {
+      out[c].id = id[i];
+      out[c].i = i;
+      c++;
+    }
+  qsort(out, (size_t)c, sizeof(or_idx), cmp_idx);
+  return c;
+}
+
+int64_t or_redistribute(const or_mesh *m, const or_params *p, int64_t np, double *state, int32_t *elem,
+                        const uint32_t *id, uint64_t seed, uint32_t step) {
+  const int32_t ne = m->ne, mn = p->min_ppe;
+  if (mn <= 0) return 0;
+  or_ne *ord = (or_ne *)malloc(sizeof(or_ne) * (size_t)ne);
+  for (int32_t e = 0; e < ne; ++e) {
+    ord[e].n = 0;
+    ord[e].e = e;
+  }
+  for (int64_t i = 0; i < np; ++i) ord[elem[i]].n++;
+  qsort(ord, (size_t)ne, sizeof(or_ne), cmp_ne);
+  or_idx *don = (or_idx *)malloc(sizeof(or_idx) * (size_t)(np + 1));
+  or_idx *rec = (or_idx *)malloc(sizeof(or_idx) * (size_t)(np + 1));
+  /* the moves are decided on the counts and residents before any move */
+  int32_t *e0 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(np + 1));
+  double *s0 = (double *)malloc(sizeof(double) * 7 * (size_t)(np + 1));
+  memcpy(e0, elem, sizeof(int32_t) * (size_t)np);
+  memcpy(s0, state, sizeof(double) * 7 * (size_t)np);
+  int64_t moved = 0;
+  for (int32_t k = 0; k < ne && ord[k].n < mn; ++k) {
+    const int32_t kd = ne - 1 - k;
+    if (kd <= k) break;
+    const int32_t c = ord[k].e, d = ord[kd].e, nc = ord[k].n, nd = ord[kd].n;
+    int32_t mv = mn - nc;
+    if (nd - mn < mv) mv = nd - mn;
+    if (mv <= 0) continue;
+    int64_t cd = members(np, e0, id, d, don);
+    int64_t cr = members(np, e0, id, c, rec);
+    (void)cd;
+    for (int32_t q = 0; q < mv; ++q) {
+      const int64_t P = don[q].i;
+      if (cr > 0) {
+        const int64_t T = rec[q % cr].i;
+        for (int f = 0; f < 7; ++f) state[(size_t)f * np + P] = s0[(size_t)f * np + T];
+      } else {
+        uint32_t r[4];
+        draw(seed, id[P], step, 3, r);
+        double r1 = or_uniform(r[0]), r2 = or_uniform(r[1]);
+        if (r1 + r2 > 1.0) {
+          r1 = 1.0 - r1;
+          r2 = 1.0 - r2;
+        }
+        const double *A = &m->xy[2 * m->en[3 * c]], *B = &m->xy[2 * m->en[3 * c + 1]],
+                     *C = &m->xy[2 * m->en[3 * c + 2]];
+        state[P] = st(p, A[0] + r1 * (B[0] - A[0]) + r2 * (C[0] - A[0]));
+        state[(size_t)np + P] = st(p, A[1] + r1 * (B[1] - A[1]) + r2 * (C[1] - A[1]));
+      }
+      elem[P] = c;
+      moved++;
+    }
+  }
+  free(ord);
+  free(don);
+  free(rec);
+  free(e0);
+  free(s0);
+  return moved;
+}
+
+/* ------------------------------------------------------------------------ */
 /* One explicit Euler-Maruyama step for every particle (mask: optional       */
 /* subset), with tracking and boundary conditions.                           */
 /* ------------------------------------------------------------------------ */

@@ -33,6 +33,8 @@ typedef struct or_params {
   int32_t stats_mode;   /* 0 ELEM: element average of nodal values at particles, element -> node
                            averages; 1 SHAPE: shape-function (eq:approximation) values at the
                            particle, N_j-weighted particle sums at the nodes */
+  int32_t min_ppe;      /* particle redistribution (App. D): minimum particles per element; 0 = off */
+  int32_t pad;
   double C0, C1, C2, C3, C4, CT, CL, Ceta, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
   double src_x, src_y, src_r;
 } or_params;
@@ -52,7 +54,7 @@ typedef struct or_mesh or_mesh;
 /* counters (index) */
 enum { OR_CNT_WALK_STEPS = 0, OR_CNT_FALLBACK, OR_CNT_BRUTE, OR_CNT_LOST, OR_CNT_REFLECT,
        OR_CNT_PERIODIC, OR_CNT_NOSLIP_B, OR_CNT_OMEGA_CLAMP, OR_CNT_GAMMA_FAIL, OR_CNT_EMPTY_NODE,
-       OR_CNT_N };
+       OR_CNT_REDIST, OR_CNT_N };
 
 #ifdef __cplusplus
 extern "C" {
@@ -79,6 +81,12 @@ void or_estimate(const or_mesh *m, const or_params *p, int64_t np, const double 
 
 void or_derivatives(const or_mesh *m, double *stats /*[OR_NSTAT][nn]*/);
 void or_local_wp(const or_mesh *m, const or_params *p, const double *stats, double *wp /*[9][nn]*/);
+
+/* Particle redistribution (App. D, the improved algorithm) before step `step`:
+ * elements below p->min_ppe particles receive particles from the most
+ * populated ones; returns the number of particles moved. */
+int64_t or_redistribute(const or_mesh *m, const or_params *p, int64_t np, double *state, int32_t *elem,
+                        const uint32_t *id, uint64_t seed, uint32_t step);
 
 int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const double *wp,
                 const double *gradp, int64_t np, double *state, int32_t *elem, const uint32_t *id,

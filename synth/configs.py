@@ -30,7 +30,7 @@ STATS_ELEM, STATS_SHAPE = 0, 1
 
 def params(**kw):
     p = dict(model=MODEL_SLM, wp_source=WP_LOCAL, omega_source=0, tm_mode=TM_CPHI, frozen=0,
-             wall_b=0, stats_mode=STATS_ELEM, C0=2.1, Cphi=2.0, nu=0.0, k_floor=1e-10, src_x=0.0, src_y=0.0, src_r=0.0)
+             wall_b=0, stats_mode=STATS_ELEM, min_ppe=0, C0=2.1, Cphi=2.0, nu=0.0, k_floor=1e-10, src_x=0.0, src_y=0.0, src_r=0.0)
     p.update(PAPER_CONSTANTS)
     p.update(kw)
     return p
