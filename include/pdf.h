@@ -68,7 +68,8 @@ enum { PDF_STATS_ELEM = 0, PDF_STATS_SHAPE = 1 };             /* statistics at p
 enum {
   PDF_CNT_WALK_STEPS = 0, PDF_CNT_FALLBACK = 1, PDF_CNT_BRUTE = 2, PDF_CNT_LOST = 3,
   PDF_CNT_REFLECT = 4, PDF_CNT_PERIODIC = 5, PDF_CNT_NOSLIP_B = 6, PDF_CNT_OMEGA_CLAMP = 7,
-  PDF_CNT_GAMMA_FAIL = 8, PDF_CNT_EMPTY_NODE = 9, PDF_CNT_NONFINITE = 10, PDF_CNT_STEPS = 11
+  PDF_CNT_GAMMA_FAIL = 8, PDF_CNT_EMPTY_NODE = 9, PDF_CNT_NONFINITE = 10, PDF_CNT_STEPS = 11,
+  PDF_CNT_REDIST = 12 /* particles moved by the redistribution */
 };
 
 /* Device allocator hook.  alloc returns device memory of at least `bytes`
@@ -130,9 +131,14 @@ typedef struct pdf_mesh_desc {
  *                statistics interpolated at its position by the shape functions of
  *                eq:approximation, and node j's values are the N^j(x_p)-weighted
  *                means and central moments of the particles in the elements around j
+ *   min_ppe      particle redistribution (App. D, improved algorithm) at the start of
+ *                every step: elements with fewer than min_ppe particles (0: off; at
+ *                most 64) receive particles from the most populated ones, as copies
+ *                of their residents
  *   src_x,src_y,src_r  continuous scalar source disc: psi = 1 inside (r <= 0: none) */
 typedef struct pdf_model_params {
   int32_t model, wp_source, omega_source, tm_mode, frozen, wall_b, reorder_every, stats_mode;
+  int32_t min_ppe, pad;
   double C0, C1, C2, C3, C4, CT, CL, Ceta, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
   double src_x, src_y, src_r;
 } pdf_model_params;

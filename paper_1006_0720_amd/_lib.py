@@ -22,7 +22,7 @@ NSTAT = 25
 NELEMSTAT = 16
 NCOUNTERS = 16
 COUNTER_NAMES = ["walk_steps", "fallback", "brute", "lost", "reflect", "periodic", "noslip_b",
-                 "omega_clamp", "gamma_fail", "empty_node", "nonfinite", "steps"]
+                 "omega_clamp", "gamma_fail", "empty_node", "nonfinite", "steps", "redist"]
 STATUS = {0: "PDF_OK", 1: "PDF_E_INVALID_ARG", 2: "PDF_E_BAD_MESH", 3: "PDF_E_OOM",
           4: "PDF_E_DEVICE", 5: "PDF_E_STATE", 6: "PDF_E_LOST_PARTICLE", 7: "PDF_E_NUMERIC"}
 
@@ -43,7 +43,7 @@ class MeshDesc(C.Structure):
 
 class ModelParams(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("model", "wp_source", "omega_source", "tm_mode", "frozen",
-                                         "wall_b", "reorder_every", "stats_mode")] + \
+                                         "wall_b", "reorder_every", "stats_mode", "min_ppe", "pad")] + \
                [(n, C.c_double) for n in ("C0", "C1", "C2", "C3", "C4", "CT", "CL", "Ceta", "Cv",
                                           "gamma5", "Cw1", "Cw2", "Cphi", "nu", "k_floor",
                                           "src_x", "src_y", "src_r")]
@@ -130,6 +130,9 @@ class Context:
         for name, _ in ModelParams._fields_:
             if name == "stats_mode":
                 mp.stats_mode = int(params.get("stats_mode", 0))
+                continue
+            if name in ("min_ppe", "pad"):
+                setattr(mp, name, int(params.get(name, 0)))
                 continue
             if name == "reorder_every":
                 mp.reorder_every = int(params.get("reorder_every", 0) if reorder_every is None

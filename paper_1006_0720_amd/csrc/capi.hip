@@ -37,6 +37,7 @@ struct pdf_ctx {
   void *rec = nullptr;        // element records (NREC, or NRECS in the SHAPE mode, values each)
   double *sums = nullptr, *emom = nullptr;
   double *nsums = nullptr;    // SHAPE: per-node weighted sums
+  RedistBuf rb;               // particle redistribution (min_ppe > 0)
   int32_t *offs = nullptr, *cursor = nullptr, *blocksums = nullptr;
   // particles (two buffers for the reorder)
   void *pbuf[2] = {nullptr, nullptr};
@@ -177,12 +178,34 @@ pdf_status estimate_from_scratch(pdf_ctx *c, const double *prev) {
   return PDF_OK;
 }
 
+void *rb_alloc(size_t n, void *u) { return dalloc((pdf_ctx *)u, n); }
+
+bool redist_reserve(pdf_ctx *c) {
+  if (c->rb.cnt && c->rb.np == c->np) return true;
+  RedistBuf &b = c->rb;
+  void *old[] = {b.cnt, b.iota, b.skey, b.sval, b.role, b.plan, b.psize, b.poff, b.fill, b.list, b.npairs, b.temp};
+  for (void *q : old) dfree(c, q);
+  b = RedistBuf();
+  return redist_alloc(b, c->md.ne, c->np, rb_alloc, c);
+}
+
 template <typename T>
 pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt) {
   const int32_t ne = c->md.ne;
   T *rec = (T *)c->rec;
+  if (c->params.min_ppe > 0 && !redist_reserve(c)) return fail(c, PDF_E_OOM, "redistribution buffers");
   for (int32_t s = 0; s < nsteps; ++s) {
     mark(c, 0);
+    if (c->params.min_ppe > 0) {
+      // particle counts per element: the count slot of the element sums (the
+      // last accumulation, ELEM) or a fresh count (SHAPE)
+      if (c->model.stats_mode == PDF_STATS_SHAPE) {
+        HIPCHK(c, hipMemsetAsync(c->sums, 0, (size_t)ne * NSUM * sizeof(double), c->stream));
+        launch_elem_count<T>(c->stream, part_view<T>(c, c->cur), c->np, c->sums);
+      }
+      launch_redistribute<T>(c->stream, c->dka, c->rb, c->sums, NSUM, part_view<T>(c, c->cur), c->params.min_ppe,
+                             c->seed, c->step, c->cnt);
+    }
     if (c->params.model == PDF_MODEL_GLM && c->params.wp_source == PDF_WP_LOCAL)
       launch_local_wp(c->stream, c->md, c->model, c->stats_cur, c->wp);
     const bool shape = c->model.stats_mode == PDF_STATS_SHAPE;
@@ -259,6 +282,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
     return PDF_E_INVALID_ARG;
   if (params->model != PDF_MODEL_SLM && params->model != PDF_MODEL_GLM) return PDF_E_INVALID_ARG;
   if (params->stats_mode != PDF_STATS_ELEM && params->stats_mode != PDF_STATS_SHAPE) return PDF_E_INVALID_ARG;
+  if (params->min_ppe < 0 || params->min_ppe > 64) return PDF_E_INVALID_ARG;
   if (!(params->C4 > 0.0 && params->C4 <= 1.0) || params->nu < 0.0 || params->reorder_every < 0)
     return PDF_E_INVALID_ARG;
   pdf_ctx *c = new pdf_ctx();

@@ -104,6 +104,21 @@ struct KArgs {
   ModelDev md;
 };
 
+// Buffers of the particle redistribution (k_redist.hip)
+struct RedistBuf {
+  int32_t ne = 0;
+  int64_t np = 0;
+  int32_t *cnt = nullptr, *iota = nullptr, *skey = nullptr, *sval = nullptr, *role = nullptr;
+  int4 *plan = nullptr;
+  int32_t *psize = nullptr, *poff = nullptr, *fill = nullptr, *list = nullptr, *npairs = nullptr;
+  void *temp = nullptr;
+  size_t temp_bytes = 0;
+};
+bool redist_alloc(RedistBuf &b, int32_t ne, int64_t np, void *(*alloc)(size_t, void *), void *user);
+template <typename T>
+void launch_redistribute(hipStream_t s, const KArgs *dka, const RedistBuf &b, const double *sums, int stride,
+                         PartDev<T> p, int32_t min_ppe, uint64_t seed, uint32_t step, unsigned long long *cnt);
+
 // ---- launchers (defined in the kernel translation units) ----
 template <typename T>
 void launch_seed(hipStream_t s, const MeshDev &m, const ModelDev &md, PartDev<T> p, int32_t ppe,
