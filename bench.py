@@ -108,6 +108,8 @@ def denoise_study(mode, out_path=""):
     from synth import configs as CF
     from synth import meshes as M
 
+    fed = mode.endswith("-fed")
+    mode = mode[:-4] if fed else mode
     if mode == "quick":
         mesh = M.canyon(20_000, 0.15, 0)
         kw = dict(n_train=6, n_test=2, steps_spin=40, n_snap=4, every=10, train_steps=600,
@@ -120,6 +122,8 @@ def denoise_study(mode, out_path=""):
     def make(ppe, seed, src):
         return CF.canyon(mesh=mesh, ppe=ppe, seed=seed, src=src)
 
+    if fed:  # statistics fed back, particle redistribution keeping 3 per element
+        kw.update(frozen=False, min_ppe=3)
     res, params, norm = study(make, log=lambda m: print(m, file=sys.stderr, flush=True), **kw)
     res["mesh_elements"] = mesh.n_elems
     res["mode"] = mode
@@ -137,6 +141,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="channel_block", choices=sorted(WORKLOADS))
     ap.add_argument("--reorder-every", type=int, default=8)
+    ap.add_argument("--min-ppe", type=int, default=0,
+                    help="particle redistribution: minimum particles per element (0: off)")
     ap.add_argument("--stats-mode", default="elem", choices=["elem", "shape"],
                     help="statistics at particles and nodes: element averages (the paper's) or "
                          "shape-function interpolation and weighting")
@@ -144,8 +150,9 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--denoise-study", default="",
-                    help="run the learned-vs-plain study on the canyon mesh: 'full' or 'quick'; "
-                         "the result is added as learned_vs_plain")
+                    help="run the learned-vs-plain study on the canyon mesh: 'full' or 'quick' (coefficients "
+                         "frozen), 'full-fed' or 'quick-fed' (statistics fed back, redistribution with a "
+                         "minimum of 3 per element); the result is added as learned_vs_plain")
     ap.add_argument("--study-out", default="", help="write the study result and weights here (.json/.npz)")
     args = ap.parse_args()
 
@@ -165,6 +172,8 @@ def main():
     shape = args.stats_mode == "shape"
     if shape:
         w.params = dict(w.params, stats_mode=CF.STATS_SHAPE)
+    if args.min_ppe > 0:
+        w.params = dict(w.params, min_ppe=args.min_ppe)
     tsize = 4 if w.precision == "f32" else 8
     ctx = workload_context(w, device=0, reorder_every=args.reorder_every)
     stream = torch.cuda.current_stream()
@@ -219,10 +228,11 @@ def main():
         "config": {"workload": f"{args.workload}: {desc}", "n_particles": n_p,
                    "n_elements": w.mesh.n_elems, "n_nodes": w.mesh.n_nodes,
                    "particles_per_element": int(w.seed["ppe"]), "dt": w.dt,
-                   "reorder_every": args.reorder_every, "stats_mode": args.stats_mode},
+                   "reorder_every": args.reorder_every, "stats_mode": args.stats_mode,
+                   "min_ppe": args.min_ppe},
         "roofline": roof,
         "phase_ms_per_step": {k: round(v / args.steps, 4) for k, v in tm.items()},
-        "counters": {k: cnt[k] for k in ("lost", "brute", "fallback", "nonfinite", "empty_node")},
+        "counters": {k: cnt[k] for k in ("lost", "brute", "fallback", "nonfinite", "empty_node", "redist")},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, w)

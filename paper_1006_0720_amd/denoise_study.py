@@ -10,10 +10,10 @@ features of the low-count estimate; the plain estimator stays the fallback.
 With frozen=True (default) the model coefficients of every run come from one
 fixed field: the high-count estimate of the seeded initial state.  Low- and
 high-count runs then sample the same particle process, so their statistics
-differ only by estimator noise and bias.  Fed-back statistics at low counts
-need the mean-pressure projection and particle redistribution of the full
-method (elements drain to one particle, k -> 0 and the generalized Langevin
-drift, proportional to 1/k, diverges).
+differ only by estimator noise and bias.  With frozen=False the statistics
+are fed back, which at low counts needs the particle redistribution
+(min_ppe > 0): without it elements drain to one particle, k -> 0 and the
+generalized Langevin drift, proportional to 1/k, diverges.
 
 Evaluation on held-out pairs, per statistic q normalised by the RMS error of
 the plain low-count estimate against the high-count reference:
@@ -34,9 +34,11 @@ from . import _lib
 from .runner import workload_context
 
 QUANT = [0, 1, 4, 5, 6, 8, 11, 3]
+TAU_SWEEP = (1.0, 3.0, 10.0, 30.0, 100.0)
 
 
-def _run(make_workload, ppe, seed, src, steps_spin, n_snap, every, frozen_field=None, reorder_every=4):
+def _run(make_workload, ppe, seed, src, steps_spin, n_snap, every, frozen_field=None, reorder_every=4,
+         min_ppe=0):
     """Advance one run; returns the snapshots of nodal statistics (torch,
     device) and the measured time per step."""
     import torch
@@ -44,6 +46,8 @@ def _run(make_workload, ppe, seed, src, steps_spin, n_snap, every, frozen_field=
     w = make_workload(ppe=ppe, seed=seed, src=src)
     if frozen_field is not None:
         w.params = dict(w.params, frozen=1)
+    if min_ppe > 0:
+        w.params = dict(w.params, min_ppe=min_ppe)
     ctx = workload_context(w, reorder_every=reorder_every)
     if frozen_field is not None:
         ctx.set_nodal_field(_lib.FIELD_STATS, frozen_field)
@@ -69,7 +73,7 @@ def _sources(rng, n, box):
 
 def study(make_workload, n_train=12, n_test=3, ppe_low=10, ppe_high=200, eval_ppes=(20, 40, 80),
           steps_spin=100, n_snap=5, every=10, hidden=128, train_steps=2000, batch=8192, lr=1e-3,
-          tau=3.0, seed=0, source_box=(4.0, 16.0, 3.5, 6.5, 0.3), frozen=True, log=print):
+          tau=3.0, seed=0, source_box=(4.0, 16.0, 3.5, 6.5, 0.3), frozen=True, min_ppe=0, log=print):
     """make_workload(ppe=, seed=, src=(x, y, r)) -> workload (see runner);
     source_box = (x0, x1, y0, y1, r): disc sources uniform in the box."""
     import torch
@@ -87,9 +91,11 @@ def study(make_workload, n_train=12, n_test=3, ppe_low=10, ppe_high=200, eval_pp
     ctx_keep = None
     t_low = []
     for r in range(n_train + n_test):
-        c_lo, w, s_lo, tl, _ = _run(make_workload, ppe_low, 1000 + r, srcs[r], steps_spin, n_snap, every, F)
+        c_lo, w, s_lo, tl, _ = _run(make_workload, ppe_low, 1000 + r, srcs[r], steps_spin, n_snap, every, F,
+                                    min_ppe=min_ppe)
         t_low.append(tl)
-        c_hi, _, s_hi, _, _ = _run(make_workload, ppe_high, 5000 + r, srcs[r], steps_spin, n_snap, every, F)
+        c_hi, _, s_hi, _, _ = _run(make_workload, ppe_high, 5000 + r, srcs[r], steps_spin, n_snap, every, F,
+                                   min_ppe=min_ppe)
         c_hi.close()
         if dn is None:
             dn = _lib.Denoiser(c_lo, hidden=hidden, seed=seed)
@@ -133,6 +139,7 @@ def study(make_workload, n_train=12, n_test=3, ppe_low=10, ppe_high=200, eval_pp
     test_runs = range(n_train, n_train + n_test)
     e_plain10, e_learn, e_learn_nofb, rej = [], [], [], []
     t_den, n_fall = [], []
+    e_tau = {}
     for r in test_runs:
         pairs = [(a, b) for (ra, a), (rb, b) in zip(lows, highs) if ra == r]
         for a, b in pairs:
@@ -147,6 +154,9 @@ def study(make_workload, n_train=12, n_test=3, ppe_low=10, ppe_high=200, eval_pp
             t_den.append(time.perf_counter() - t1)
             n_fall.append(nf)
             den_all, _ = dn.denoise(float("inf"), device=True)
+            for tau_v in TAU_SWEEP:
+                den_t, _ = dn.denoise(tau_v, device=True)
+                e_tau.setdefault(tau_v, []).append(rms_err(den_t.cpu().numpy(), ref, valid))
             e_plain10.append(rms_err(plain, ref, valid))
             e_learn.append(rms_err(den.cpu().numpy(), ref, valid))
             e_learn_nofb.append(rms_err(den_all.cpu().numpy(), ref, valid))
@@ -162,7 +172,8 @@ def study(make_workload, n_train=12, n_test=3, ppe_low=10, ppe_high=200, eval_pp
     for ppe in eval_ppes:
         errs, ts = [], []
         for r in test_runs:
-            c, _, s, tstep, _ = _run(make_workload, ppe, 9000 + r, srcs[r], steps_spin, n_snap, every, F)
+            c, _, s, tstep, _ = _run(make_workload, ppe, 9000 + r, srcs[r], steps_spin, n_snap, every, F,
+                                     min_ppe=min_ppe)
             c.close()
             ts.append(tstep)
             hs = [b for (rb, b) in highs if rb == r]
@@ -186,13 +197,24 @@ def study(make_workload, n_train=12, n_test=3, ppe_low=10, ppe_high=200, eval_pp
     t_eq = float(slope * ppe_eq + icpt) if np.isfinite(ppe_eq) else float("inf")
     t_dn = float(np.median(t_den))
     ratio = t_eq / (T_plain[ppe_low] + t_dn)
+    def eq_cost(E):
+        inv = E ** 2 / a_fit - 1.0 / ppe_high
+        pe = float(1.0 / inv) if inv > 0 else float("inf")
+        te = float(slope * pe + icpt) if np.isfinite(pe) else float("inf")
+        return pe, te / (T_plain[ppe_low] + t_dn)
+
+    tau_sweep = {}
+    for tau_v, errs_t in e_tau.items():
+        Et = float(np.mean(np.mean(errs_t, axis=0) / norm))
+        pe, cr = eq_cost(Et)
+        tau_sweep[str(tau_v)] = {"E_learned": Et, "ppe_eq": pe, "cost_ratio": cr}
     inv_nf = E_learned_nofb ** 2 / a_fit - 1.0 / ppe_high
     ppe_eq_nf = float(1.0 / inv_nf) if inv_nf > 0 else float("inf")
     t_eq_nf = float(slope * ppe_eq_nf + icpt) if np.isfinite(ppe_eq_nf) else float("inf")
     ratio_nf = t_eq_nf / (T_plain[ppe_low] + t_dn)
     out = {"E_plain": E_plain, "E_learned": E_learned, "E_learned_no_fallback": E_learned_nofb, "ppe_eq": ppe_eq, "a_fit": a_fit,
            "T_plain_s": T_plain, "T_denoise_s": t_dn, "cost_ratio": ratio,
-           "ppe_eq_no_fallback": ppe_eq_nf, "cost_ratio_no_fallback": ratio_nf,
+           "ppe_eq_no_fallback": ppe_eq_nf, "cost_ratio_no_fallback": ratio_nf, "tau_sweep": tau_sweep,
            "per_statistic_ratio": (np.mean(e_learn, axis=0) / norm).tolist(),
            "per_statistic_ratio_no_fallback": (np.mean(e_learn_nofb, axis=0) / norm).tolist(),
            "per_statistic_rejected_fraction": np.mean(rej, axis=0).tolist(),
@@ -200,7 +222,7 @@ def study(make_workload, n_train=12, n_test=3, ppe_low=10, ppe_high=200, eval_pp
            "train_loss_first": float(losses[0]), "train_loss_last": float(np.mean(losses[-50:])),
            "train_seconds": t_train, "n_train_samples": int(n), "hidden": hidden,
            "n_train_runs": n_train, "n_test_runs": n_test, "ppe_low": ppe_low, "ppe_high": ppe_high,
-           "frozen_coefficients": bool(frozen), "steps_spin": steps_spin, "n_snap": n_snap, "every": every,
+           "frozen_coefficients": bool(frozen), "min_ppe": min_ppe, "steps_spin": steps_spin, "n_snap": n_snap, "every": every,
            "tau": tau, "fallback_fraction": float(np.mean(n_fall)) / (8.0 * ctx_keep.n_nodes)}
     params = dn.params()
     norm_arrays = dn.norm
