@@ -15,7 +15,14 @@ def state_scales(ref_state, mesh):
 
 
 def max_rel_err(a, b, scale):
-    return float((np.abs(a - b) / (np.abs(b) + scale)).max()) if a.size else 0.0
+    """Largest |a - b| / (|b| + scale); identical values count as 0 (also
+    when both and the scale are zero)."""
+    if not a.size:
+        return 0.0
+    d = np.abs(a - b)
+    den = np.abs(b) + scale
+    r = np.where(d == 0.0, 0.0, d / np.where(den > 0.0, den, 1e-300))
+    return float(r.max())
 
 
 def compare_state(gpu_state, ref_state, mesh, rtol, what=""):
