@@ -65,6 +65,8 @@ def lib():
         L.or_step.argtypes = [C.c_void_p, C.c_void_p, dp, dp, dp, C.c_int64, dp, ip, up,
                               C.c_uint64, C.c_uint32, C.c_double, C.POINTER(C.c_uint8), u64p]
         L.or_step.restype = C.c_int32
+        L.or_cfl_dt.argtypes = [C.c_void_p, dp, C.c_double, C.c_double]
+        L.or_cfl_dt.restype = C.c_double
         L.or_redistribute.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, dp, ip, up, C.c_uint64, C.c_uint32]
         L.or_redistribute.restype = C.c_int64
         _lib = L
@@ -276,6 +278,20 @@ class Oracle:
         self.step_index += 1
         self.estimate(into_stats=not self.params["frozen"])
         return lost
+
+    def cfl_dt(self, c_cfl, dt_max):
+        """Time step of eq:CFL from the current nodal statistics."""
+        st = np.ascontiguousarray(self.stats, np.float64)
+        return lib().or_cfl_dt(self.om.h, _p(st, C.c_double), float(c_cfl), float(dt_max))
+
+    def run_cfl(self, c_cfl, dt_max, nsteps):
+        """nsteps steps, each with the time step of eq:CFL; returns the time advanced."""
+        t = 0.0
+        for _ in range(nsteps):
+            dt = self.cfl_dt(c_cfl, dt_max)
+            self.step(dt)
+            t += dt
+        return t
 
     def run(self, dt, nsteps):
         for _ in range(nsteps):

@@ -693,6 +693,32 @@ void or_seed(const or_mesh *m, const or_params *p, const or_seedspec *s, double 
 }
 
 /* ------------------------------------------------------------------------ */
+/* eq:CFL: the time step from the smallest characteristic time of the grid   */
+/* nodes, sqrt of the average surrounding element area over the length of    */
+/* the in-plane mean velocity.                                               */
+/* ------------------------------------------------------------------------ */
+double or_cfl_dt(const or_mesh *m, const double *stats, double c_cfl, double dt_max) {
+  const int32_t nn = m->nn;
+  double best = -1.0;
+  for (int32_t n = 0; n < nn; ++n) {
+    if (m->master[n] != n) continue;
+    const int32_t a = m->m2e_off[n], b = m->m2e_off[n + 1];
+    if (b <= a) continue;
+    double area = 0.0;
+    for (int32_t i = a; i < b; ++i) area += m->area[m->m2e[i]];
+    const double sa = sqrt(area / (double)(b - a));
+    const double u = S(0, n), v = S(1, n);
+    const double sp = sqrt(u * u + v * v);
+    if (!(sp > 0.0)) continue;
+    const double t = sa / sp;
+    if (best < 0.0 || t < best) best = t;
+  }
+  if (best < 0.0) return dt_max;
+  const double dt = c_cfl * best;
+  return dt < dt_max ? dt : dt_max;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Particle redistribution (App. D, improved algorithm).                     */
 /* The elements are ordered by increasing particle count (ties: increasing   */
 /* element number).  The k-th element of that order with fewer than         */

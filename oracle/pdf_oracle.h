@@ -82,6 +82,12 @@ void or_estimate(const or_mesh *m, const or_params *p, int64_t np, const double 
 void or_derivatives(const or_mesh *m, double *stats /*[OR_NSTAT][nn]*/);
 void or_local_wp(const or_mesh *m, const or_params *p, const double *stats, double *wp /*[9][nn]*/);
 
+/* Time step of eq:CFL from the nodal mean velocity: c_cfl times the smallest,
+ * over master nodes with a non-zero in-plane mean velocity, of sqrt(A_n) /
+ * |(<U>, <V>)| with A_n the average area of the elements around node n;
+ * dt_max when that is larger or no node moves. */
+double or_cfl_dt(const or_mesh *m, const double *stats, double c_cfl, double dt_max);
+
 /* Particle redistribution (App. D, the improved algorithm) before step `step`:
  * elements below p->min_ppe particles receive particles from the most
  * populated ones; returns the number of particles moved. */

@@ -341,10 +341,28 @@ __global__ __launch_bounds__(SC_WG) void k_scatter(int64_t np, const int32_t *of
       }
       h = (h + 1u) & (uint32_t)(SC_TAB - 1);
     }
-    if (slot[j] >= 0)
-      rank[j] = atomicAdd(&cntl[slot[j]], 1);
-    else
-      rank[j] = atomicAdd(&cursor[e], 1);  // global rank (overflow path)
+    if (slot[j] < 0) rank[j] = atomicAdd(&cursor[e], 1);  // global rank (overflow path)
+  }
+  // ranks within the table: the lanes of a wave holding the same element get
+  // consecutive ranks in lane order (one LDS atomic per distinct element and
+  // wave), so that neighbouring lanes write neighbouring destinations
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int j = 0; j < SC_PPT; ++j) {
+    bool pending = slot[j] >= 0;
+    while (__ballot(pending) != 0) {
+      const uint64_t act = __ballot(pending);
+      const int leader = __ffsll((unsigned long long)act) - 1;
+      const int lkey = __shfl(slot[j], leader, 64);
+      const uint64_t same = __ballot(pending && slot[j] == lkey);
+      int base_r = 0;
+      if (lane == leader) base_r = atomicAdd(&cntl[lkey], __popcll(same));
+      base_r = __shfl(base_r, leader, 64);
+      if (pending && slot[j] == lkey) {
+        rank[j] = base_r + __popcll(same & below);
+        pending = false;
+      }
+    }
   }
   __syncthreads();
   for (int s = threadIdx.x; s < SC_TAB; s += SC_WG)
