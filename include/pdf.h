@@ -185,6 +185,20 @@ pdf_status pdf_seed_particles(pdf_ctx *ctx, const pdf_seed_desc *seed);
  * Asynchronous; lost particles are reported through the counters. */
 pdf_status pdf_advance(pdf_ctx *ctx, int32_t nsteps, double dt);
 
+/* As pdf_advance, with each step's size chosen by the condition eq:CFL from
+ * the statistics current at the start of that step (Ch.3, Sec.
+ * Timestepping):
+ *   dt = min(dt_max, c_cfl * min_n sqrt(A_n) / |<U>_n|),
+ * n over the master nodes, A_n the mean area of the elements around node n,
+ * |<U>_n| the magnitude of the in-plane mean velocity (<U>,<V>); nodes where
+ * it is zero (or not a number) do not bound the step, and with none left
+ * dt = dt_max.  The step size is formed and consumed on the device (no host
+ * round trip per step).  c_cfl > 0 and dt_max > 0, both finite
+ * (PDF_E_INVALID_ARG otherwise).  t_advanced (host, may be NULL) receives the
+ * sum of the nsteps step sizes; when it is given the call waits for the
+ * stream, otherwise it is asynchronous. */
+pdf_status pdf_advance_cfl(pdf_ctx *ctx, int32_t nsteps, double c_cfl, double dt_max, double *t_advanced);
+
 /* Copy the latest nodal statistics (and optionally element statistics) out.
  * nodal [PDF_NSTAT][n_nodes]: 0-2 <U>,<V>,<W>; 3 <omega>; 4 <phi>; 5-10 <u_i u_j>
  * (11,22,33,12,13,23); 11 <phi'^2>; 12-14 <u_i phi'>; 15-20 d<U_i>/dx, d<U_i>/dy

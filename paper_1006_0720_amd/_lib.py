@@ -74,6 +74,7 @@ def _load():
         "pdf_set_nodal_field": ([vp, i32, vp, i32], i32),
         "pdf_seed_particles": ([vp, vp], i32),
         "pdf_advance": ([vp, i32, dbl], i32),
+        "pdf_advance_cfl": ([vp, i32, dbl, dbl, C.POINTER(dbl)], i32),
         "pdf_estimate_stats": ([vp, vp, vp, i32], i32),
         "pdf_num_particles": ([vp, C.POINTER(i64)], i32),
         "pdf_get_particles": ([vp, vp, vp, vp], i32),
@@ -206,6 +207,15 @@ class Context:
     # ---- stepping ------------------------------------------------------
     def advance(self, nsteps, dt):
         self._chk(lib.pdf_advance(self.h, int(nsteps), float(dt)))
+
+    def advance_cfl(self, nsteps, c_cfl, dt_max, wait=True):
+        """nsteps steps whose sizes follow eq:CFL (chosen on the device);
+        returns the time advanced (waits for the stream), or None with
+        wait=False (asynchronous)."""
+        t = C.c_double(0.0)
+        self._chk(lib.pdf_advance_cfl(self.h, int(nsteps), float(c_cfl), float(dt_max),
+                                      C.byref(t) if wait else None))
+        return t.value if wait else None
 
     # ---- outputs -------------------------------------------------------
     def stats(self, elem=False):

@@ -36,6 +36,7 @@ struct pdf_ctx {
   // element data
   void *rec = nullptr;        // element records (NREC, or NRECS in the SHAPE mode, values each)
   double *sums = nullptr, *emom = nullptr;
+  double *cfl = nullptr;      // time step of eq:CFL: dt, time advanced, running minimum
   double *nsums = nullptr;    // SHAPE: per-node weighted sums
   RedistBuf rb;               // particle redistribution (min_ppe > 0)
   int32_t *offs = nullptr, *cursor = nullptr, *blocksums = nullptr;
@@ -190,12 +191,17 @@ bool redist_reserve(pdf_ctx *c) {
 }
 
 template <typename T>
-pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt) {
+pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt, const double *cfl) {
   const int32_t ne = c->md.ne;
   T *rec = (T *)c->rec;
   if (c->params.min_ppe > 0 && !redist_reserve(c)) return fail(c, PDF_E_OOM, "redistribution buffers");
+  // cfl = {C_CFL, dt_max}: each step's dt is formed on the device from the
+  // current statistics and read there by the record and particle kernels
+  const double *dtp = cfl ? c->cfl : nullptr;
+  if (cfl) launch_cfl_begin(c->stream, c->cfl);
   for (int32_t s = 0; s < nsteps; ++s) {
     mark(c, 0);
+    if (cfl) launch_cfl_dt(c->stream, c->md, c->stats_cur, cfl[0], cfl[1], c->cfl);
     if (c->params.min_ppe > 0) {
       // particle counts per element: the count slot of the element sums (the
       // last accumulation, ELEM) or a fresh count (SHAPE)
@@ -217,12 +223,12 @@ pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt) {
     } else {
       launch_elem_prep<T>(c->stream, c->md, c->model, c->stats_cur,
                           c->params.model == PDF_MODEL_GLM ? c->wp : nullptr,
-                          c->gradp_set ? c->gradp : nullptr, dt, rec);
+                          c->gradp_set ? c->gradp : nullptr, dt, dtp, rec);
       HIPCHK(c, hipMemsetAsync(c->sums, 0, (size_t)ne * NSUM * sizeof(double), c->stream));
     }
     mark(c, 1);
     launch_advance<T>(c->stream, c->dka, c->model, part_view<T>(c, c->cur), c->np, rec,
-                      shape ? c->nsums : c->sums, c->seed, c->step, dt, c->cnt);
+                      shape ? c->nsums : c->sums, c->seed, c->step, dt, dtp, c->cnt);
     mark(c, 2);
     if (shape) {
       launch_node_stats_shape<T>(c->stream, c->md, c->nsums, c->stats_cur, c->stats_cur, c->stats_est,
@@ -307,7 +313,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
       return bad("node_master is not a projection at node " + std::to_string(n));
   }
   std::vector<ElemGeo> geo(ne);
-  std::vector<double> dN(6 * (size_t)ne);
+  std::vector<double> dN(6 * (size_t)ne), area(ne);
   std::vector<int32_t> mnode(3 * (size_t)ne);
   for (int32_t e = 0; e < ne; ++e) {
     ElemGeo &g = geo[e];
@@ -325,6 +331,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
     const double xCA = g.x[2] - g.x[0], yCA = g.y[2] - g.y[0];
     const double twoA = xBA * yCA - xCA * yBA;
     if (!(twoA > 0.0)) return bad("non-positive area or clockwise element " + std::to_string(e));
+    area[e] = 0.5 * twoA;
     dN[6 * e + 0] = (yBA - yCA) / twoA;
     dN[6 * e + 1] = yCA / twoA;
     dN[6 * e + 2] = -yBA / twoA;
@@ -387,6 +394,15 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
     for (int32_t n = 0; n < nn; ++n) m2e_off[n + 1] = m2e_off[n] + (int32_t)lists[n].size();
     m2e.reserve(m2e_off[nn]);
     for (int32_t n = 0; n < nn; ++n) m2e.insert(m2e.end(), lists[n].begin(), lists[n].end());
+  }
+  // length scale of eq:CFL per master node: sqrt of the mean area of the
+  // elements around it (ascending element order), -1 where none
+  std::vector<double> cfl_len(nn, -1.0);
+  for (int32_t n = 0; n < nn; ++n) {
+    if (master[n] != n || m2e_off[n + 1] <= m2e_off[n]) continue;
+    double a = 0.0;
+    for (int32_t i = m2e_off[n]; i < m2e_off[n + 1]; ++i) a += area[m2e[i]];
+    cfl_len[n] = std::sqrt(a / (double)(m2e_off[n + 1] - m2e_off[n]));
   }
   // element -> no-slip wall edges sharing a node with the element (ascending)
   std::vector<int32_t> w_off(ne + 1, 0), w_list;
@@ -507,7 +523,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
             upload(c, nwall_off, &m.nwall_off) && upload(c, nwall, &m.nwall) &&
             upload(c, masters, &m.masters) && upload(c, slaves, &m.slaves) &&
             upload(c, slave_master, &m.slave_master) && upload(c, cell_off, &m.cell_off) &&
-            upload(c, cell_list, &m.cell_list);
+            upload(c, cell_list, &m.cell_list) && upload(c, cfl_len, &m.cfl_len);
   const size_t ts = tsize(c);
   c->stats_a = (double *)dalloc(c, (size_t)PDF_NSTAT * nn * sizeof(double));
   c->stats_b = (double *)dalloc(c, (size_t)PDF_NSTAT * nn * sizeof(double));
@@ -525,8 +541,9 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   c->cursor = (int32_t *)dalloc(c, ((size_t)ne + 1) * sizeof(int32_t));
   c->blocksums = (int32_t *)dalloc(c, ((size_t)ne / 1024 + 2) * sizeof(int32_t));
   c->cnt = (unsigned long long *)dalloc(c, PDF_NCOUNTERS * sizeof(unsigned long long));
+  c->cfl = (double *)dalloc(c, 4 * sizeof(double));
   if (!ok || !c->stats_a || !c->stats_b || !c->wp || !c->gradp || !c->rec || !c->sums || !c->emom ||
-      !c->offs || !c->cursor || !c->blocksums || !c->cnt) {
+      !c->offs || !c->cursor || !c->blocksums || !c->cnt || !c->cfl) {
     c->err = "device allocation or upload failed";
     pdf_destroy(c);
     return PDF_E_OOM;
@@ -653,8 +670,8 @@ pdf_status pdf_seed_particles(pdf_ctx *c, const pdf_seed_desc *sd) {
   return PDF_OK;
 }
 
-pdf_status pdf_advance(pdf_ctx *c, int32_t nsteps, double dt) {
-  if (!c || nsteps < 0 || !(dt > 0.0)) return PDF_E_INVALID_ARG;
+namespace {
+pdf_status advance_checks(pdf_ctx *c) {
   if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_advance before pdf_seed_particles");
   if (c->params.model == PDF_MODEL_GLM && c->params.wp_source == PDF_WP_INPUT && !c->wp_set)
     return fail(c, PDF_E_STATE, "GLM with PDF_WP_INPUT needs the PDF_FIELD_WP field");
@@ -663,7 +680,34 @@ pdf_status pdf_advance(pdf_ctx *c, int32_t nsteps, double dt) {
     c->ev.clear();
     c->ev_phase.clear();
   }
-  return c->prec == PDF_FP32 ? advance_impl<float>(c, nsteps, dt) : advance_impl<double>(c, nsteps, dt);
+  return PDF_OK;
+}
+}  // namespace
+
+pdf_status pdf_advance(pdf_ctx *c, int32_t nsteps, double dt) {
+  if (!c || nsteps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return PDF_E_INVALID_ARG;
+  const pdf_status st = advance_checks(c);
+  if (st != PDF_OK) return st;
+  return c->prec == PDF_FP32 ? advance_impl<float>(c, nsteps, dt, nullptr)
+                             : advance_impl<double>(c, nsteps, dt, nullptr);
+}
+
+pdf_status pdf_advance_cfl(pdf_ctx *c, int32_t nsteps, double c_cfl, double dt_max, double *t_advanced) {
+  if (!c || nsteps < 0 || !(c_cfl > 0.0) || !std::isfinite(c_cfl) || !(dt_max > 0.0) || !std::isfinite(dt_max))
+    return PDF_E_INVALID_ARG;
+  pdf_status st = advance_checks(c);
+  if (st != PDF_OK) return st;
+  const double cfl[2] = {c_cfl, dt_max};
+  st = c->prec == PDF_FP32 ? advance_impl<float>(c, nsteps, dt_max, cfl)
+                           : advance_impl<double>(c, nsteps, dt_max, cfl);
+  if (st != PDF_OK || !t_advanced) return st;
+  if (nsteps == 0) {
+    *t_advanced = 0.0;
+    return PDF_OK;
+  }
+  HIPCHK(c, hipMemcpyAsync(t_advanced, c->cfl + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PDF_OK;
 }
 
 pdf_status pdf_estimate_stats(pdf_ctx *c, double *nodal, double *elem, int32_t on_device) {

@@ -269,9 +269,10 @@ __device__ __forceinline__ void elem_gradients(const MeshDev &m, const double *S
 template <typename T>
 __global__ __launch_bounds__(256) void k_elem_prep(MeshDev m, ModelDev md, const double *S,
                                                    const double *wp, const double *gradp, double dt,
-                                                   T *rec) {
+                                                   const double *dtp, T *rec) {
   const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m.ne) return;
+  if (dtp) dt = dtp[0];  // time step chosen on the device this step
   const int nn = m.nn;
   const int q0 = m.mnode[3 * e], q1 = m.mnode[3 * e + 1], q2 = m.mnode[3 * e + 2];
   const int qk[3] = {q0, q1, q2};
@@ -364,9 +365,9 @@ __device__ __forceinline__ void shape_record(const ModelDev &md, const T *rs, co
 
 template <typename T>
 void launch_elem_prep(hipStream_t s, const MeshDev &m, const ModelDev &md, const double *stats,
-                      const double *wp, const double *gradp, double dt, T *rec) {
+                      const double *wp, const double *gradp, double dt, const double *dtp, T *rec) {
   hipLaunchKernelGGL(k_elem_prep<T>, dim3((m.ne + 255) / 256), dim3(256), 0, s, m, md, stats, wp,
-                     gradp, dt, rec);
+                     gradp, dt, dtp, rec);
 }
 
 // ---------------------------------------------------------------------------
@@ -702,10 +703,14 @@ template <typename T, bool VISC, bool WALLB, bool SHAPE>
 __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(const KArgs *__restrict__ ka, PartDev<T> p, int64_t np,
                                                 int ppt, const T *__restrict__ rec, double *sums, uint32_t k0,
                                                 uint32_t k1, uint32_t step, double dt, double sdt,
-                                                double s2nu, unsigned long long *cnt) {
+                                                const double *dtp, double s2nu, unsigned long long *cnt) {
   __shared__ std::conditional_t<SHAPE, SumTableW, SumTable> tab;
   const MeshDev &m = ka->m;
   const ModelDev &md = ka->md;
+  if (dtp) {  // time step chosen on the device this step
+    dt = dtp[0];
+    sdt = sqrt(dt);
+  }
   table_init(tab);
   __syncthreads();
   uint64_t ca = 0, cb = 0;
@@ -1017,7 +1022,7 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
 template <typename T, bool SHAPE>
 void launch_advance_m(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
                       const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
-                      unsigned long long *cnt) {
+                      const double *dtp, unsigned long long *cnt) {
   const int ppt = pick_ppt(np);
   const unsigned grid = (unsigned)((np + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt));
   const bool visc = md.nu > 0.0;
@@ -1026,23 +1031,23 @@ void launch_advance_m(hipStream_t s, const KArgs *dka, const ModelDev &md, PartD
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   if (visc && wallb)
     hipLaunchKernelGGL((k_advance<T, true, true, SHAPE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt, rec,
-                       sums, k0, k1, step, dt, sdt, s2nu, cnt);
+                       sums, k0, k1, step, dt, sdt, dtp, s2nu, cnt);
   else if (visc)
     hipLaunchKernelGGL((k_advance<T, true, false, SHAPE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt, rec,
-                       sums, k0, k1, step, dt, sdt, s2nu, cnt);
+                       sums, k0, k1, step, dt, sdt, dtp, s2nu, cnt);
   else
     hipLaunchKernelGGL((k_advance<T, false, false, SHAPE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt,
-                       rec, sums, k0, k1, step, dt, sdt, s2nu, cnt);
+                       rec, sums, k0, k1, step, dt, sdt, dtp, s2nu, cnt);
 }
 
 template <typename T>
 void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
                     const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
-                    unsigned long long *cnt) {
+                    const double *dtp, unsigned long long *cnt) {
   if (md.stats_mode == PDF_STATS_SHAPE)
-    launch_advance_m<T, true>(s, dka, md, p, np, rec, sums, seed, step, dt, cnt);
+    launch_advance_m<T, true>(s, dka, md, p, np, rec, sums, seed, step, dt, dtp, cnt);
   else
-    launch_advance_m<T, false>(s, dka, md, p, np, rec, sums, seed, step, dt, cnt);
+    launch_advance_m<T, false>(s, dka, md, p, np, rec, sums, seed, step, dt, dtp, cnt);
 }
 
 #define INST(T)                                                                                  \
@@ -1050,10 +1055,10 @@ void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev
                                uint64_t, int32_t, double, double, double, const double *,         \
                                const double *, const double *, unsigned long long *);            \
   template void launch_elem_prep<T>(hipStream_t, const MeshDev &, const ModelDev &, const double *, \
-                                    const double *, const double *, double, T *);                \
+                                    const double *, const double *, double, const double *, T *); \
   template void launch_advance<T>(hipStream_t, const KArgs *, const ModelDev &, PartDev<T>, int64_t, \
                                   const T *, double *, uint64_t, uint32_t, double,                 \
-                                  unsigned long long *);                                         \
+                                  const double *, unsigned long long *);                         \
   template void launch_accumulate<T>(hipStream_t, PartDev<T>, int64_t, const T *, double *);        \
   template void launch_elem_prep_shape<T>(hipStream_t, const MeshDev &, const ModelDev &,           \
                                           const double *, const double *, const double *, T *);    \

@@ -1,7 +1,7 @@
 // Statistics kernels for gfx950: the two-pass particle-in-cell estimator
 // (Ch.3, Sec. Estimation of Eulerian statistics), FEM derivatives (Sec.
-// Derivatives), the local elliptic-relaxation tensor, and the counting-sort
-// reorder of particles by host element.
+// Derivatives), the local elliptic-relaxation tensor, the time step of
+// eq:CFL, and the counting-sort reorder of particles by host element.
 //
 // Every nodal kernel is a gather over the linked list "elements surrounding
 // master node" (no atomics), so nodal results do not depend on launch order.
@@ -192,6 +192,63 @@ void launch_node_derivs(hipStream_t s, const MeshDev &m, double *stats) {
   if (m.n_slaves > 0)
     hipLaunchKernelGGL(k_copy_slaves, dim3((m.n_slaves + 255) / 256), dim3(256), 0, s, m, stats,
                        PDF_NSTAT);
+}
+
+// ---- time step of eq:CFL ----
+// dt = C_CFL * min over master nodes of sqrt(A_n) / |<U>_n|, A_n the mean
+// area of the elements around the node and <U>_n the in-plane mean velocity;
+// nodes at rest do not bound the step; capped at dt_max (also when every node
+// is at rest).  The minimum runs over the bit patterns of the positive
+// candidates (their order as unsigned integers is their order as numbers), so
+// the result does not depend on the reduction order.  Products and sums are
+// rounded one by one (no contraction), as written.
+__global__ void k_cfl_begin(double *buf) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    buf[1] = 0.0;
+    reinterpret_cast<unsigned long long *>(buf)[2] = ~0ull;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cfl_min(int32_t nn, const double *len, const double *S, double *buf) {
+#pragma clang fp contract(off)
+  const int32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long best = ~0ull;
+  if (n < nn) {
+    const double a = len[n];
+    if (a >= 0.0) {
+      const double u = S[n], v = S[nn + n];
+      const double sp = sqrt(u * u + v * v);
+      if (sp > 0.0) best = (unsigned long long)__double_as_longlong(a / sp);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(best, off, 64);
+    best = o < best ? o : best;
+  }
+  if ((threadIdx.x & 63) == 0 && best != ~0ull)
+    atomicMin(reinterpret_cast<unsigned long long *>(buf) + 2, best);
+}
+
+__global__ void k_cfl_final(double c_cfl, double dt_max, double *buf) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  unsigned long long *bits = reinterpret_cast<unsigned long long *>(buf) + 2;
+  double dt = dt_max;
+  if (*bits != ~0ull) {
+    const double d = c_cfl * __longlong_as_double((long long)*bits);
+    dt = d < dt_max ? d : dt_max;
+  }
+  buf[0] = dt;
+  buf[1] = buf[1] + dt;
+  *bits = ~0ull;  // ready for the next step
+}
+
+void launch_cfl_begin(hipStream_t s, double *buf) { hipLaunchKernelGGL(k_cfl_begin, dim3(1), dim3(64), 0, s, buf); }
+
+void launch_cfl_dt(hipStream_t s, const MeshDev &m, const double *stats, double c_cfl, double dt_max,
+                   double *buf) {
+  hipLaunchKernelGGL(k_cfl_min, dim3((m.nn + 255) / 256), dim3(256), 0, s, m.nn, m.cfl_len, stats, buf);
+  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, s, c_cfl, dt_max, buf);
 }
 
 // Local elliptic-relaxation tensor: the right-hand side of

@@ -68,6 +68,7 @@ struct MeshDev {
   const int32_t *m2e_off, *m2e;  // master node -> elements (statistics)
   const int32_t *w_off, *w_list; // element -> nearby no-slip wall edges
   const WallSeg *wseg;            // [w_off[ne]]: geometry of each w_list entry
+  const double *cfl_len;          // [nn]: sqrt of the mean area of the elements around a master node, -1 elsewhere
   const int32_t *nwall_off, *nwall; // node -> wall (slip/no-slip) edges ending at it
   const int32_t *master;    // [nn] periodic identification
   const int32_t *masters;   // list of master nodes
@@ -126,16 +127,18 @@ void launch_seed(hipStream_t s, const MeshDev &m, const ModelDev &md, PartDev<T>
                  const double *R0, const double *Om0, unsigned long long *cnt);
 template <typename T>
 void launch_elem_prep(hipStream_t s, const MeshDev &m, const ModelDev &md, const double *stats,
-                      const double *wp, const double *gradp, double dt, T *rec);
+                      const double *wp, const double *gradp, double dt, const double *dtp, T *rec);
 template <typename T>
 void launch_elem_prep_shape(hipStream_t s, const MeshDev &m, const ModelDev &md, const double *stats,
                             const double *wp, const double *gradp, T *rec);
 // ELEM: rec has NREC values per element, sums NSUM per element;
-// SHAPE: rec has NRECS values per element, sums NSUM per node
+// SHAPE: rec has NRECS values per element, sums NSUM per node.
+// dtp (record and particle kernels): when non-null, the step's time step is
+// read from dtp[0] on the device and the dt argument is ignored
 template <typename T>
 void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
                     const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
-                    unsigned long long *cnt);
+                    const double *dtp, unsigned long long *cnt);
 template <typename T>
 void launch_accumulate_shape(hipStream_t s, const MeshDev &m, PartDev<T> p, int64_t np, const T *rec,
                              double *nsums);
@@ -153,6 +156,11 @@ void launch_elem_moments(hipStream_t s, int32_t ne, const double *sums, const T 
 void launch_node_stats(hipStream_t s, const MeshDev &m, const double *emom, const double *prev,
                        double *out, unsigned long long *cnt);
 void launch_node_derivs(hipStream_t s, const MeshDev &m, double *stats);
+// time step of eq:CFL on the device.  buf: [0] the step's dt, [1] the time
+// advanced since launch_cfl_begin, [2] scratch (the running minimum's bits)
+void launch_cfl_begin(hipStream_t s, double *buf);
+void launch_cfl_dt(hipStream_t s, const MeshDev &m, const double *stats, double c_cfl, double dt_max,
+                   double *buf);
 void launch_local_wp(hipStream_t s, const MeshDev &m, const ModelDev &md, const double *stats,
                      double *wp);
 void launch_export_elem(hipStream_t s, int32_t ne, const double *emom, double *out);

@@ -1,0 +1,146 @@
+"""GPU parity of the adaptive time step of eq:CFL through the C ABI
+(pdf_advance_cfl) against the oracle's run_cfl.
+
+With frozen statistics both sides form each step size from the same input
+field, so the step sizes and the time advanced agree bit for bit, in FP64 and
+FP32, and the trajectory equals a fixed-step run at the oracle's step size.
+With statistics fed back the step size follows the estimated mean velocity,
+which the two sides sum in different orders: element indices bit-exact, the
+state, the statistics and the time advanced within 1e-12."""
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import configs as CF
+from tests.parity import compare_state, compare_stats
+
+pytestmark = pytest.mark.gpu
+
+C_CFL, DT_MAX = 0.3, 0.01
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1006_0720_amd import _lib
+    return _lib
+
+
+def _channel(precision="f64", frozen=0):
+    w = CF.channel(nx=20, n_half=8, ppe=30, precision=precision)
+    w.params = dict(w.params, frozen=frozen)
+    return w
+
+
+def _frozen_field(w, U, V):
+    fz = CF.frozen_stats_for(w.mesh, U=(0.0, 0.0, 0.0), R_diag=(0.5, 0.4, 0.3), Om=2.0)
+    fz[0], fz[1] = U, V
+    return fz
+
+
+def _pair(L, w, fz=None):
+    from paper_1006_0720_amd.runner import workload_context
+
+    print(f"[cfl] {w.name} np={w.n_particles} prec={w.precision} frozen={w.params['frozen']}", flush=True)
+    ctx = workload_context(w)
+    o = O.Oracle(w.mesh, w.params, store_fp32=(w.precision == "f32"), gradp=w.gradp, wp=w.wp)
+    o.seed(w.seed)
+    if fz is not None:
+        ctx.set_nodal_field(L.FIELD_STATS, fz)
+        o.set_stats(fz)
+    return ctx, o
+
+
+def test_cfl_fed_back_fp64_channel(L):
+    """Generalized Langevin model, no-slip walls, statistics fed back: the
+    step size changes every step with the estimated mean velocity."""
+    w = _channel()
+    ctx, o = _pair(L, w)
+    t_g = t_o = 0.0
+    dts = set()
+    for chunk in range(3):
+        dts.add(o.cfl_dt(C_CFL, DT_MAX))
+        t_o += o.run_cfl(C_CFL, DT_MAX, 10)
+        t_g += ctx.advance_cfl(10, C_CFL, DT_MAX)
+        st, el, pid = ctx.particles()
+        assert np.array_equal(pid, o.id)
+        assert np.array_equal(el, o.elem), f"chunk {chunk}: {(el != o.elem).sum()} element mismatches"
+        compare_state(st, o.state, w.mesh, 1e-12, f"cfl channel chunk {chunk}")
+        compare_stats(ctx.stats(), o.stats, 1e-12, what=f"cfl channel chunk {chunk}")
+        assert abs(t_g - t_o) <= 1e-12 * t_o, (t_g, t_o)
+    assert len(dts) == 3 and max(dts) < DT_MAX  # the condition, not the cap, sets the step
+    c, oc = ctx.counters(), o.counter_dict()
+    for k in ("walk_steps", "reflect", "noslip_b", "periodic", "lost"):
+        assert c[k] == oc[k], (k, c[k], oc[k])
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_cfl_frozen_exact_step(L, precision):
+    """Frozen statistics with a mean velocity that varies over the domain: the
+    device's step size is the oracle's to the bit, and the run equals a
+    fixed-step run at that size."""
+    w = _channel(precision, frozen=1)
+    xy = w.mesh.node_xy
+    fz = _frozen_field(w, 5.0 + 20.0 * xy[:, 1] * (2.0 - xy[:, 1]), 2.0 * np.sin(xy[:, 0]))
+    ctx, o = _pair(L, w, fz)
+    dt = o.cfl_dt(C_CFL, DT_MAX)
+    assert dt < DT_MAX
+    # FP32 is held to the oracle one step from the common seeded state, FP64
+    # over the whole run
+    t_o = o.run_cfl(C_CFL, DT_MAX, 1)
+    t_g = ctx.advance_cfl(1, C_CFL, DT_MAX)
+    assert t_g == t_o == dt
+    st, el, _ = ctx.particles()
+    assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
+    compare_state(st, o.state, w.mesh, 1e-12 if precision == "f64" else 1e-5, "cfl frozen, one step")
+    t_o += o.run_cfl(C_CFL, DT_MAX, 3)
+    t_g += ctx.advance_cfl(3, C_CFL, DT_MAX)
+    assert t_g == t_o
+    st, el, _ = ctx.particles()
+    if precision == "f64":
+        assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
+        compare_state(st, o.state, w.mesh, 1e-12, "cfl frozen, four steps")
+    ref, _ = _pair(L, w, fz)
+    ref.advance(4, dt)
+    st2, el2, _ = ref.particles()
+    assert np.array_equal(el2, el) and np.array_equal(st2, st)
+    ctx.close()
+    ref.close()
+
+
+def test_cfl_cap_and_rest(L):
+    """At rest everywhere no node bounds the step: dt = dt_max, the same run
+    as pdf_advance(dt_max), bit for bit; a large C_CFL is capped the same way.
+    Asynchronous calls (no time returned) advance the same steps."""
+    w = _channel(frozen=1)
+    fz = _frozen_field(w, 0.0, 0.0)
+    a, o = _pair(L, w, fz)
+    b, _ = _pair(L, w, fz)
+    assert o.cfl_dt(C_CFL, DT_MAX) == DT_MAX
+    assert a.advance_cfl(3, C_CFL, DT_MAX) == DT_MAX + DT_MAX + DT_MAX
+    b.advance(3, DT_MAX)
+    a.advance_cfl(2, 1e6, DT_MAX, wait=False)
+    b.advance(2, DT_MAX)
+    sa, ea, _ = a.particles()
+    sb, eb, _ = b.particles()
+    assert np.array_equal(ea, eb) and np.array_equal(sa, sb)
+    assert a.advance_cfl(0, C_CFL, DT_MAX) == 0.0
+    a.close()
+    b.close()
+
+
+def test_cfl_invalid_arguments(L):
+    w = _channel(frozen=1)
+    ctx, _ = _pair(L, w, _frozen_field(w, 1.0, 0.0))
+    for c_cfl, dt_max in ((0.0, 1.0), (-1.0, 1.0), (float("nan"), 1.0), (float("inf"), 1.0),
+                          (0.5, 0.0), (0.5, float("nan")), (0.5, float("inf"))):
+        with pytest.raises(L.PdfError) as ei:
+            ctx.advance_cfl(1, c_cfl, dt_max)
+        assert ei.value.status == 1, (c_cfl, dt_max)
+    with pytest.raises(L.PdfError):
+        ctx.advance_cfl(-1, C_CFL, DT_MAX)
+    ctx.close()
