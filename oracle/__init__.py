@@ -68,6 +68,8 @@ def lib():
         L.or_cfl_dt.argtypes = [C.c_void_p, dp, C.c_double, C.c_double]
         L.or_cfl_dt.restype = C.c_double
         L.or_redistribute.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, dp, ip, up, C.c_uint64, C.c_uint32]
+        L.or_cond_means.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, dp, ip, up, dp]
+        L.or_cond_means.restype = None
         L.or_redistribute.restype = C.c_int64
         _lib = L
     return _lib
@@ -75,10 +77,17 @@ def lib():
 
 class _Params(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("model", "wp_source", "omega_source", "tm_mode", "frozen",
-                                         "wall_b", "store_fp32", "stats_mode", "min_ppe", "pad")] + \
+                                         "wall_b", "store_fp32", "stats_mode", "min_ppe", "mix_model",
+                                         "cond_nu", "cond_nv", "cond_nw", "cond_min")] + \
                [(n, C.c_double) for n in ("C0", "C1", "C2", "C3", "C4", "CT", "CL", "Ceta", "Cv",
                                           "gamma5", "Cw1", "Cw2", "Cphi", "nu", "k_floor",
-                                          "src_x", "src_y", "src_r")]
+                                          "src_x", "src_y", "src_r", "Cs", "Ct")]
+
+
+# parameters that older parameter sets may lack: IEM, 5x5x5 bins, at least 2
+# particles per subgroup, the constants of tab:constants
+_DEFAULTS = dict(stats_mode=0, min_ppe=0, mix_model=0, cond_nu=5, cond_nv=5, cond_nw=5, cond_min=2,
+                 Cs=0.02, Ct=0.7)
 
 
 class _Seed(C.Structure):
@@ -97,12 +106,8 @@ def _params(params: dict, store_fp32: bool):
     for name, _ in _Params._fields_:
         if name == "store_fp32":
             p.store_fp32 = int(store_fp32)
-        elif name == "stats_mode":
-            p.stats_mode = int(params.get("stats_mode", 0))
-        elif name == "min_ppe":
-            p.min_ppe = int(params.get("min_ppe", 0))
-        elif name == "pad":
-            p.pad = 0
+        elif name in _DEFAULTS:
+            setattr(p, name, type(_DEFAULTS[name])(params.get(name, _DEFAULTS[name])))
         else:
             setattr(p, name, params[name])
     return p
@@ -278,6 +283,14 @@ class Oracle:
         self.step_index += 1
         self.estimate(into_stats=not self.params["frozen"])
         return lost
+
+    def cond_means(self):
+        """<phi|V> of every particle from the current state (App. B binning)."""
+        cm = np.empty(self.state.shape[1])
+        st = np.ascontiguousarray(self.state, np.float64)
+        lib().or_cond_means(self.om.h, C.byref(self.cp), st.shape[1], _p(st, C.c_double),
+                            _p(self.elem, C.c_int32), _p(self.id, C.c_uint32), _p(cm, C.c_double))
+        return cm
 
     def cfl_dt(self, c_cfl, dt_max):
         """Time step of eq:CFL from the current nodal statistics."""

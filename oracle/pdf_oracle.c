@@ -350,7 +350,7 @@ static void shape_values(const or_mesh *m, int32_t e, double x, double y, double
  * element average of the nodal values (w == NULL, the paper's reading) or
  * from their shape-function values at one particle position (w = N^j). */
 static void elem_record(const or_mesh *m, const or_params *p, const double *stats, const double *wp,
-                        const double *gradp, int32_t e, const double *w, orec *r) {
+                        const double *gradp, int32_t e, const double *w, const double *pt, orec *r) {
   int32_t nn = m->nn;
   int32_t mk[3];
   for (int k = 0; k < 3; ++k) mk[k] = m->master[m->en[3 * e + k]];
@@ -413,8 +413,31 @@ static void elem_record(const or_mesh *m, const or_params *p, const double *stat
     r->inv_tm = 0.5 * p->Cphi * r->Om;
   } else {
     double a = k / r->eps, b = p->CT * sqrt(p->nu / r->eps);
-    r->inv_tm = 1.0 / (a > b ? a : b);
+    double tm = a > b ? a : b;
+    if (p->tm_mode == 2) {
+      /* eq:micromixing-timescale-canyon at the point pt: the source term
+       * C_s (r0^2/eps)^(1/3) + C_t d / U_c, with d the distance from the
+       * source centre and U_c the magnitude of the mean velocity; it drops
+       * out where U_c = 0 */
+      double dx = pt[0] - p->src_x, dy = pt[1] - p->src_y;
+      double d = sqrt(dx * dx + dy * dy);
+      double uc = sqrt(r->U[0] * r->U[0] + r->U[1] * r->U[1] + r->U[2] * r->U[2]);
+      if (uc > 0.0) {
+        double ts = p->Cs * cbrt(p->src_r * p->src_r / r->eps) + p->Ct * d / uc;
+        if (ts < tm) tm = ts;
+      }
+    }
+    r->inv_tm = 1.0 / tm;
   }
+}
+
+/* the point at which the source-aware time scale is evaluated for element e
+ * in the ELEM reading: the centroid */
+static void centroid(const or_mesh *m, int32_t e, double pt[2]) {
+  const double *A = &m->xy[2 * m->en[3 * e]], *B = &m->xy[2 * m->en[3 * e + 1]],
+               *C = &m->xy[2 * m->en[3 * e + 2]];
+  pt[0] = (A[0] + B[0] + C[0]) / 3.0;
+  pt[1] = (A[1] + B[1] + C[1]) / 3.0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -844,6 +867,86 @@ static void noslip(const or_params *p, const orec *r, double nx, double ny, uint
   }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Velocity-conditioned scalar mean (Sec. Estimation of the velocity-        */
+/* conditioned scalar mean; App. B).  In every element the particles are     */
+/* sorted by their U velocity and divided into n_u groups; each group is     */
+/* sorted by V and divided into n_v; each of those by W into n_w.  A level   */
+/* is taken only while every subgroup keeps at least cond_min particles (the */
+/* adaptive stop); the groups taken last are the bins.  Group boundaries    */
+/* follow the bin index of App. B at every level: with P groups over the n  */
+/* particles of the element, the particle at position j of the order belongs */
+/* to group P*j/n (integer division).  The particles start in increasing id */
+/* order, and ties in a velocity component are ordered by id; a direction   */
+/* with a single interval is not sorted.  <phi|V> of a particle is the mean  */
+/* scalar of its bin, summed in the order of the final positions.            */
+/* ------------------------------------------------------------------------ */
+typedef struct { double k; uint32_t id; int64_t i; } or_ck;
+static int cmp_ck(const void *a, const void *b) {
+  const or_ck *x = (const or_ck *)a, *y = (const or_ck *)b;
+  if (x->k != y->k) return x->k < y->k ? -1 : 1;
+  return x->id < y->id ? -1 : (x->id > y->id ? 1 : 0);
+}
+
+void or_cond_means(const or_mesh *m, const or_params *p, int64_t np, const double *state,
+                   const int32_t *elem, const uint32_t *id, double *cm) {
+  const int32_t ne = m->ne;
+  const int32_t f[3] = {p->cond_nu, p->cond_nv, p->cond_nw};
+  const int32_t cmin = p->cond_min > 1 ? p->cond_min : 1;
+  /* the particles of every element (storage order; the sorts fix the order) */
+  int64_t *off = (int64_t *)calloc((size_t)ne + 1, sizeof(int64_t));
+  for (int64_t i = 0; i < np; ++i) off[elem[i] + 1]++;
+  for (int32_t e = 0; e < ne; ++e) off[e + 1] += off[e];
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * ((size_t)ne + 1));
+  memcpy(fill, off, sizeof(int64_t) * ((size_t)ne + 1));
+  or_ck *all = (or_ck *)malloc(sizeof(or_ck) * (size_t)(np + 1));
+  for (int64_t i = 0; i < np; ++i) {
+    or_ck *c = &all[fill[elem[i]]++];
+    c->id = id[i];
+    c->i = i;
+  }
+  for (int32_t e = 0; e < ne; ++e) {
+    or_ck *b = all + off[e];
+    const int64_t n = off[e + 1] - off[e];
+    if (n == 0) continue;
+    /* the starting order: increasing id */
+    for (int64_t j = 0; j < n; ++j) b[j].k = 0.0;
+    qsort(b, (size_t)n, sizeof(or_ck), cmp_ck);
+    /* levels: a direction with one interval divides nothing and is skipped;
+     * nc groups after the levels taken */
+    int64_t nc = 1;
+    for (int l = 0; l < 3; ++l) {
+      if (f[l] <= 1) continue;
+      const int64_t next = nc * f[l];
+      if (n / next < cmin) break; /* the adaptive stop */
+      /* sort each group of the previous level by velocity component l */
+      for (int64_t j = 0; j < n; ++j) b[j].k = state[(size_t)(2 + l) * np + b[j].i];
+      for (int64_t g = 0; g < nc; ++g) {
+        const int64_t s0 = (g * n + nc - 1) / nc, s1 = ((g + 1) * n + nc - 1) / nc;
+        qsort(b + s0, (size_t)(s1 - s0), sizeof(or_ck), cmp_ck);
+      }
+      nc = next;
+    }
+    /* App. B: bin index, particle count and scalar sum per bin, bin means */
+    double *sum = (double *)calloc((size_t)nc, sizeof(double));
+    int64_t *cnt = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
+    for (int64_t j = 0; j < n; ++j) {
+      const int64_t bin = nc * j / n;
+      cnt[bin]++;
+      sum[bin] += state[(size_t)6 * np + b[j].i];
+    }
+    for (int64_t j = 0; j < n; ++j) {
+      const int64_t bin = nc * j / n;
+      cm[b[j].i] = sum[bin] / (double)cnt[bin];
+    }
+    free(sum);
+    free(cnt);
+  }
+  free(off);
+  free(fill);
+  free(all);
+}
+
 int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const double *wp,
                 const double *gradp, int64_t np, double *state, int32_t *elem, const uint32_t *id,
                 uint64_t seed, uint32_t step, double dt, const uint8_t *mask, uint64_t *cnt) {
@@ -851,11 +954,22 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
   const int shape = (p->stats_mode == 1);
   orec *rec = (orec *)malloc(sizeof(orec) * (size_t)ne);
   if (!shape)
-    for (int32_t e = 0; e < ne; ++e) elem_record(m, p, stats, wp, gradp, e, NULL, &rec[e]);
+    for (int32_t e = 0; e < ne; ++e) {
+      double pt[2];
+      centroid(m, e, pt);
+      elem_record(m, p, stats, wp, gradp, e, NULL, pt, &rec[e]);
+    }
   orec rl;
   double *X = state, *Y = state + np, *Uu = state + 2 * np, *Vv = state + 3 * np,
          *Ww = state + 4 * np, *OM = state + 5 * np, *PS = state + 6 * np;
   int32_t lost = 0;
+  /* eq:IECM: the conditioned means from the particles at the start of the step */
+  double *cm = NULL;
+  if (p->mix_model == 1) {
+    cm = (double *)malloc(sizeof(double) * (size_t)(np + 1));
+    or_cond_means(m, p, np, state, elem, id, cm);
+    for (int64_t i = 0; i < np; ++i) cm[i] = st(p, cm[i]);
+  }
   double sdt = sqrt(dt), s2nu = sqrt(2.0 * p->nu);
   for (int64_t i = 0; i < np; ++i) {
     if (mask && !mask[i]) continue;
@@ -865,7 +979,8 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
       /* statistics at the particle's position at the start of the step */
       double w[3];
       shape_values(m, e0, X[i], Y[i], w);
-      elem_record(m, p, stats, wp, gradp, e0, w, &rl);
+      const double pt[2] = {X[i], Y[i]};
+      elem_record(m, p, stats, wp, gradp, e0, w, pt, &rl);
       r = &rl;
     }
     uint32_t pid = id[i];
@@ -906,8 +1021,8 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
       omn = -omn;
       if (cnt) cnt[OR_CNT_OMEGA_CLAMP]++;
     }
-    /* eq:IEM */
-    double psin = psi - dt * r->inv_tm * (psi - r->Phi);
+    /* eq:IEM, or eq:IECM with the particle's velocity-conditioned mean */
+    double psin = psi - dt * r->inv_tm * (psi - (cm ? cm[i] : r->Phi));
     /* tracking: next best element walk with boundary conditions */
     int32_t e = e0, found = -1, nrefl = 0;
     double shx = 0.0, shy = 0.0;
@@ -1071,5 +1186,6 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
     elem[i] = found;
   }
   free(rec);
+  free(cm);
   return lost;
 }

@@ -26,7 +26,8 @@ typedef struct or_params {
   int32_t model;        /* 0 = simplified Langevin (eq:wall-GandC), 1 = generalized Langevin (eq:GandC) */
   int32_t wp_source;    /* GLM: 0 = nodal field given, 1 = local right-hand side of eq:elliptic-relaxation-Lagrangian */
   int32_t omega_source; /* 1 = S_omega of eq:frequency-source, 0 = S_omega = 0 */
-  int32_t tm_mode;      /* 0: 1/t_m = C_phi <omega>/2 ; 1: t_m = max(k/eps, C_T sqrt(nu/eps)) */
+  int32_t tm_mode;      /* 0: 1/t_m = C_phi <omega>/2 ; 1: t_m = max(k/eps, C_T sqrt(nu/eps));
+                           2: eq:micromixing-timescale-canyon (source-aware) */
   int32_t frozen;       /* 1: statistics are not fed back (fixed nodal fields) */
   int32_t wall_b;       /* 1: apply the no-slip trajectory (b) test of eq:fw */
   int32_t store_fp32;   /* 1: particle state is rounded to binary32 wherever the GPU stores it */
@@ -34,9 +35,12 @@ typedef struct or_params {
                            averages; 1 SHAPE: shape-function (eq:approximation) values at the
                            particle, N_j-weighted particle sums at the nodes */
   int32_t min_ppe;      /* particle redistribution (App. D): minimum particles per element; 0 = off */
-  int32_t pad;
+  int32_t mix_model;    /* 0 IEM (eq:IEM), 1 IECM (eq:IECM) */
+  int32_t cond_nu, cond_nv, cond_nw; /* IECM binning structure (n_u x n_v x n_w) */
+  int32_t cond_min;     /* IECM: fewest particles a subgroup may keep (the adaptive stop) */
   double C0, C1, C2, C3, C4, CT, CL, Ceta, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
   double src_x, src_y, src_r;
+  double Cs, Ct;        /* constants of eq:micromixing-timescale-canyon */
 } or_params;
 
 typedef struct or_seedspec {
@@ -87,6 +91,12 @@ void or_local_wp(const or_mesh *m, const or_params *p, const double *stats, doub
  * |(<U>, <V>)| with A_n the average area of the elements around node n;
  * dt_max when that is larger or no node moves. */
 double or_cfl_dt(const or_mesh *m, const double *stats, double c_cfl, double dt_max);
+
+/* Velocity-conditioned scalar mean <phi|V> of every particle (Sec. Estimation
+ * of the velocity-conditioned scalar mean, App. B): the mean scalar of its
+ * subgroup in its host element after the sort-and-divide binning. */
+void or_cond_means(const or_mesh *m, const or_params *p, int64_t np, const double *state,
+                   const int32_t *elem, const uint32_t *id, double *cm /*[np]*/);
 
 /* Particle redistribution (App. D, the improved algorithm) before step `step`:
  * elements below p->min_ppe particles receive particles from the most

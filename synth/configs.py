@@ -19,18 +19,20 @@ from . import meshes as M
 
 # Ch.4 / Ch.5 constant tables
 PAPER_CONSTANTS = dict(C1=1.85, C2=0.63, C3=5.0, C4=0.25, CT=6.0, CL=0.134, Ceta=72.0, Cv=1.4,
-                       gamma5=0.1, Cw1=0.5, Cw2=0.73)
+                       gamma5=0.1, Cw1=0.5, Cw2=0.73, Cs=0.02, Ct=0.7)
 
 MODEL_SLM, MODEL_GLM = 0, 1
 WP_INPUT, WP_LOCAL = 0, 1
-TM_CPHI, TM_KEPS = 0, 1
+TM_CPHI, TM_KEPS, TM_SOURCE = 0, 1, 2
+MIX_IEM, MIX_IECM = 0, 1
 PSI_ZERO, PSI_STEP_X, PSI_GAUSS_X, PSI_BERNOULLI, PSI_DISC = 0, 1, 2, 3, 4
 STATS_ELEM, STATS_SHAPE = 0, 1
 
 
 def params(**kw):
     p = dict(model=MODEL_SLM, wp_source=WP_LOCAL, omega_source=0, tm_mode=TM_CPHI, frozen=0,
-             wall_b=0, stats_mode=STATS_ELEM, min_ppe=0, C0=2.1, Cphi=2.0, nu=0.0, k_floor=1e-10, src_x=0.0, src_y=0.0, src_r=0.0)
+             wall_b=0, stats_mode=STATS_ELEM, min_ppe=0, mix_model=MIX_IEM, cond_nu=5, cond_nv=5,
+             cond_nw=5, cond_min=2, C0=2.1, Cphi=2.0, nu=0.0, k_floor=1e-10, src_x=0.0, src_y=0.0, src_r=0.0)
     p.update(PAPER_CONSTANTS)
     p.update(kw)
     return p
