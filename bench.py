@@ -146,6 +146,9 @@ def main():
     ap.add_argument("--stats-mode", default="elem", choices=["elem", "shape"],
                     help="statistics at particles and nodes: element averages (the paper's) or "
                          "shape-function interpolation and weighting")
+    ap.add_argument("--mix", default="iem", choices=["iem", "iecm"],
+                    help="micromixing: IEM (eq:IEM) or IECM with the velocity-conditioned mean "
+                         "(eq:IECM, 5 x 5 x 5 bins, at least 2 per subgroup)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
@@ -174,6 +177,8 @@ def main():
         w.params = dict(w.params, stats_mode=CF.STATS_SHAPE)
     if args.min_ppe > 0:
         w.params = dict(w.params, min_ppe=args.min_ppe)
+    if args.mix == "iecm":
+        w.params = dict(w.params, mix_model=CF.MIX_IECM, cond_nu=5, cond_nv=5, cond_nw=5, cond_min=2)
     tsize = 4 if w.precision == "f32" else 8
     ctx = workload_context(w, device=0, reorder_every=args.reorder_every)
     stream = torch.cuda.current_stream()
@@ -229,7 +234,7 @@ def main():
                    "n_elements": w.mesh.n_elems, "n_nodes": w.mesh.n_nodes,
                    "particles_per_element": int(w.seed["ppe"]), "dt": w.dt,
                    "reorder_every": args.reorder_every, "stats_mode": args.stats_mode,
-                   "min_ppe": args.min_ppe},
+                   "min_ppe": args.min_ppe, "mix": args.mix},
         "roofline": roof,
         "phase_ms_per_step": {k: round(v / args.steps, 4) for k, v in tm.items()},
         "counters": {k: cnt[k] for k in ("lost", "brute", "fallback", "nonfinite", "empty_node", "redist")},

@@ -54,7 +54,8 @@ enum { PDF_FP64 = 0, PDF_FP32 = 1 };                          /* particle-state 
 enum { PDF_BC_PERIODIC = 1, PDF_BC_SLIP = 2, PDF_BC_NOSLIP = 3 }; /* boundary-edge types */
 enum { PDF_MODEL_SLM = 0, PDF_MODEL_GLM = 1 };                /* eq:wall-GandC / eq:GandC */
 enum { PDF_WP_INPUT = 0, PDF_WP_LOCAL = 1 };                  /* source of the tensor wp_ij (GLM) */
-enum { PDF_TM_CPHI = 0, PDF_TM_KEPS = 1 };                    /* micromixing time scale */
+enum { PDF_TM_CPHI = 0, PDF_TM_KEPS = 1, PDF_TM_SOURCE = 2 }; /* micromixing time scale */
+enum { PDF_MIX_IEM = 0, PDF_MIX_IECM = 1 };                  /* micromixing model */
 enum { PDF_PSI_ZERO = 0, PDF_PSI_STEP_X = 1, PDF_PSI_GAUSS_X = 2, PDF_PSI_BERNOULLI = 3,
        PDF_PSI_DISC = 4 };                                    /* scalar initial conditions */
 enum { PDF_FIELD_STATS = 0, PDF_FIELD_WP = 1, PDF_FIELD_GRADP = 2 }; /* pdf_set_nodal_field ids */
@@ -119,7 +120,12 @@ typedef struct pdf_mesh_desc {
  *                or PDF_WP_LOCAL (right-hand side of eq:elliptic-relaxation-Lagrangian
  *                evaluated at the nodes from the estimated statistics)
  *   omega_source 1: S_omega of eq:frequency-source; 0: S_omega = 0
- *   tm_mode      PDF_TM_CPHI: 1/t_m = C_phi <omega>/2; PDF_TM_KEPS: t_m = max(k/eps, C_T sqrt(nu/eps))
+ *   tm_mode      PDF_TM_CPHI: 1/t_m = C_phi <omega>/2; PDF_TM_KEPS: t_m = max(k/eps, C_T sqrt(nu/eps));
+ *                PDF_TM_SOURCE: eq:micromixing-timescale-canyon, t_m = min(C_s (r0^2/eps)^(1/3)
+ *                + C_t d/U_c, max(k/eps, C_T sqrt(nu/eps))) with r0 = src_r, d the distance
+ *                from (src_x, src_y) to the element centroid (PDF_STATS_ELEM) or the
+ *                particle (PDF_STATS_SHAPE) and U_c = |<U>| there (the first argument
+ *                drops out where U_c = 0)
  *   frozen       1: element records always come from the PDF_FIELD_STATS field;
  *                the estimator still runs but is not fed back
  *   wall_b       1: apply the no-slip trajectory (b) condition of eq:fw (nu > 0)
@@ -135,12 +141,25 @@ typedef struct pdf_mesh_desc {
  *                every step: elements with fewer than min_ppe particles (0: off; at
  *                most 64) receive particles from the most populated ones, as copies
  *                of their residents
- *   src_x,src_y,src_r  continuous scalar source disc: psi = 1 inside (r <= 0: none) */
+ *   mix_model    PDF_MIX_IEM: psi relaxes toward <phi> (eq:IEM); PDF_MIX_IECM: toward the
+ *                velocity-conditioned mean <phi|V> (eq:IECM), estimated at the start of
+ *                each step in every element by the sort-and-divide binning of Ch.3,
+ *                Sec. Estimation of the velocity-conditioned scalar mean and App. B:
+ *                the element's particles (from increasing id) are sorted by U and
+ *                divided into cond_nu groups, each by V into cond_nv, each by W into
+ *                cond_nw (ties by id; group g of P over n particles holds the positions
+ *                j with P*j/n = g; a direction with one interval is skipped); a level is
+ *                taken only while every subgroup keeps at least cond_min particles;
+ *                <phi|V> is the mean psi of the particle's final subgroup
+ *   cond_nu, cond_nv, cond_nw  binning structure, each 1..16 (the paper: 5 x 5 x 5)
+ *   cond_min     fewest particles per subgroup, 1..64 (the paper's example: 2)
+ *   src_x,src_y,src_r  continuous scalar source disc: psi = 1 inside (r <= 0: none)
+ *   Cs, Ct       constants of eq:micromixing-timescale-canyon (tab:constants: 0.02, 0.7) */
 typedef struct pdf_model_params {
   int32_t model, wp_source, omega_source, tm_mode, frozen, wall_b, reorder_every, stats_mode;
-  int32_t min_ppe, pad;
+  int32_t min_ppe, mix_model, cond_nu, cond_nv, cond_nw, cond_min;
   double C0, C1, C2, C3, C4, CT, CL, Ceta, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
-  double src_x, src_y, src_r;
+  double src_x, src_y, src_r, Cs, Ct;
 } pdf_model_params;
 
 /* Initial particle population (Ch.3, Sec. Particle-number control): ppe
@@ -229,7 +248,9 @@ pdf_status pdf_get_counters(pdf_ctx *ctx, uint64_t *out, int32_t n, int32_t rese
 
 /* Per-kernel timing of the last pdf_advance call, measured with HIP events on
  * the context stream: out[0] element records, out[1] particle kernel,
- * out[2] estimator, out[3] reorder (milliseconds, summed over its steps).
+ * out[2] estimator, out[3] reorder, out[4] the work at the start of a step
+ * (time step of eq:CFL, redistribution, conditioned means) (milliseconds,
+ * summed over its steps; n <= 5 values are written).
  * Timing is recorded only while enabled (pdf_enable_timing). */
 pdf_status pdf_enable_timing(pdf_ctx *ctx, int32_t on);
 pdf_status pdf_get_timing(pdf_ctx *ctx, double *out_ms, int32_t n);

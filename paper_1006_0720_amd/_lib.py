@@ -43,10 +43,18 @@ class MeshDesc(C.Structure):
 
 class ModelParams(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("model", "wp_source", "omega_source", "tm_mode", "frozen",
-                                         "wall_b", "reorder_every", "stats_mode", "min_ppe", "pad")] + \
+                                         "wall_b", "reorder_every", "stats_mode", "min_ppe", "mix_model",
+                                         "cond_nu", "cond_nv", "cond_nw", "cond_min")] + \
                [(n, C.c_double) for n in ("C0", "C1", "C2", "C3", "C4", "CT", "CL", "Ceta", "Cv",
                                           "gamma5", "Cw1", "Cw2", "Cphi", "nu", "k_floor",
-                                          "src_x", "src_y", "src_r")]
+                                          "src_x", "src_y", "src_r", "Cs", "Ct")]
+
+
+# fields a parameter set may omit: ELEM statistics, no redistribution, IEM,
+# 5 x 5 x 5 conditioning bins with at least 2 particles each, and the
+# micromixing constants of tab:constants
+PARAM_DEFAULTS = dict(stats_mode=0, min_ppe=0, mix_model=0, cond_nu=5, cond_nv=5, cond_nw=5,
+                      cond_min=2, Cs=0.02, Ct=0.7)
 
 
 class SeedDesc(C.Structure):
@@ -129,11 +137,9 @@ class Context:
         md = MeshDesc(mesh.n_nodes, mesh.n_elems, mesh.n_bedges, 0, *[_ptr(x) for x in a])
         mp = ModelParams()
         for name, _ in ModelParams._fields_:
-            if name == "stats_mode":
-                mp.stats_mode = int(params.get("stats_mode", 0))
-                continue
-            if name in ("min_ppe", "pad"):
-                setattr(mp, name, int(params.get(name, 0)))
+            if name in PARAM_DEFAULTS:
+                d = PARAM_DEFAULTS[name]
+                setattr(mp, name, type(d)(params.get(name, d)))
                 continue
             if name == "reorder_every":
                 mp.reorder_every = int(params.get("reorder_every", 0) if reorder_every is None
@@ -261,9 +267,9 @@ class Context:
         self._chk(lib.pdf_enable_timing(self.h, int(on)))
 
     def timing(self):
-        out = np.zeros(4)
-        self._chk(lib.pdf_get_timing(self.h, _ptr(out), 4))
-        return dict(elem_prep=out[0], advance=out[1], estimator=out[2], reorder=out[3])
+        out = np.zeros(5)
+        self._chk(lib.pdf_get_timing(self.h, _ptr(out), 5))
+        return dict(elem_prep=out[0], advance=out[1], estimator=out[2], reorder=out[3], step_start=out[4])
 
 
 def _declare_denoiser():

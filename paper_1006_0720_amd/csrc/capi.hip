@@ -39,6 +39,7 @@ struct pdf_ctx {
   double *cfl = nullptr;      // time step of eq:CFL: dt, time advanced, running minimum
   double *nsums = nullptr;    // SHAPE: per-node weighted sums
   RedistBuf rb;               // particle redistribution (min_ppe > 0)
+  CondBuf cb;                 // velocity-conditioned scalar means (IECM)
   int32_t *offs = nullptr, *cursor = nullptr, *blocksums = nullptr;
   // particles (two buffers for the reorder)
   void *pbuf[2] = {nullptr, nullptr};
@@ -190,17 +191,28 @@ bool redist_reserve(pdf_ctx *c) {
   return redist_alloc(b, c->md.ne, c->np, rb_alloc, c);
 }
 
+bool cond_reserve(pdf_ctx *c) {
+  if (c->cb.cnt && c->cb.np == c->np) return true;
+  CondBuf &b = c->cb;
+  void *old[] = {b.cnt, b.off, b.cursor, b.big, b.nbig, b.list, b.list2, b.cm, b.temp};
+  for (void *q : old) dfree(c, q);
+  b = CondBuf();
+  return cond_alloc(b, c->md.ne, c->np, tsize(c), rb_alloc, c);
+}
+
 template <typename T>
 pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt, const double *cfl) {
   const int32_t ne = c->md.ne;
   T *rec = (T *)c->rec;
   if (c->params.min_ppe > 0 && !redist_reserve(c)) return fail(c, PDF_E_OOM, "redistribution buffers");
+  const bool iecm = c->params.mix_model == PDF_MIX_IECM;
+  if (iecm && !cond_reserve(c)) return fail(c, PDF_E_OOM, "conditioned-mean buffers");
   // cfl = {C_CFL, dt_max}: each step's dt is formed on the device from the
   // current statistics and read there by the record and particle kernels
   const double *dtp = cfl ? c->cfl : nullptr;
   if (cfl) launch_cfl_begin(c->stream, c->cfl);
   for (int32_t s = 0; s < nsteps; ++s) {
-    mark(c, 0);
+    mark(c, 4);
     if (cfl) launch_cfl_dt(c->stream, c->md, c->stats_cur, cfl[0], cfl[1], c->cfl);
     if (c->params.min_ppe > 0) {
       // particle counts per element: the count slot of the element sums (the
@@ -212,6 +224,13 @@ pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt, const double *cfl
       launch_redistribute<T>(c->stream, c->dka, c->rb, c->sums, NSUM, part_view<T>(c, c->cur), c->params.min_ppe,
                              c->seed, c->step, c->cnt);
     }
+    // eq:IECM: <phi|V> of every particle from the state at the start of the step
+    const T *cm = nullptr;
+    if (iecm) {
+      launch_cond_means<T>(c->stream, c->model, c->cb, part_view<T>(c, c->cur));
+      cm = (const T *)c->cb.cm;
+    }
+    mark(c, 0);
     if (c->params.model == PDF_MODEL_GLM && c->params.wp_source == PDF_WP_LOCAL)
       launch_local_wp(c->stream, c->md, c->model, c->stats_cur, c->wp);
     const bool shape = c->model.stats_mode == PDF_STATS_SHAPE;
@@ -228,7 +247,7 @@ pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt, const double *cfl
     }
     mark(c, 1);
     launch_advance<T>(c->stream, c->dka, c->model, part_view<T>(c, c->cur), c->np, rec,
-                      shape ? c->nsums : c->sums, c->seed, c->step, dt, dtp, c->cnt);
+                      shape ? c->nsums : c->sums, c->seed, c->step, dt, dtp, cm, c->cnt);
     mark(c, 2);
     if (shape) {
       launch_node_stats_shape<T>(c->stream, c->md, c->nsums, c->stats_cur, c->stats_cur, c->stats_est,
@@ -255,7 +274,7 @@ pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt, const double *cfl
                         part_view<T>(c, c->cur), part_view<T>(c, 1 - c->cur));
       c->cur = 1 - c->cur;
     }
-    mark(c, 4);
+    mark(c, 5);
     HIPCHK(c, hipGetLastError());
   }
   return PDF_OK;
@@ -289,6 +308,11 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   if (params->model != PDF_MODEL_SLM && params->model != PDF_MODEL_GLM) return PDF_E_INVALID_ARG;
   if (params->stats_mode != PDF_STATS_ELEM && params->stats_mode != PDF_STATS_SHAPE) return PDF_E_INVALID_ARG;
   if (params->min_ppe < 0 || params->min_ppe > 64) return PDF_E_INVALID_ARG;
+  if (params->tm_mode < PDF_TM_CPHI || params->tm_mode > PDF_TM_SOURCE) return PDF_E_INVALID_ARG;
+  if (params->mix_model != PDF_MIX_IEM && params->mix_model != PDF_MIX_IECM) return PDF_E_INVALID_ARG;
+  if (params->cond_nu < 1 || params->cond_nu > 16 || params->cond_nv < 1 || params->cond_nv > 16 ||
+      params->cond_nw < 1 || params->cond_nw > 16 || params->cond_min < 1 || params->cond_min > 64)
+    return PDF_E_INVALID_ARG;
   if (!(params->C4 > 0.0 && params->C4 <= 1.0) || params->nu < 0.0 || params->reorder_every < 0)
     return PDF_E_INVALID_ARG;
   pdf_ctx *c = new pdf_ctx();
@@ -587,6 +611,14 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   md.src_x = params->src_x;
   md.src_y = params->src_y;
   md.src_r = params->src_r;
+  md.Cs = params->Cs;
+  md.Ct = params->Ct;
+  md.mix_model = params->mix_model;
+  md.cond_nu = params->cond_nu;
+  md.cond_nv = params->cond_nv;
+  md.cond_nw = params->cond_nw;
+  md.cond_min = params->cond_min;
+  md.pad = 0;
   KArgs hka;
   hka.m = c->md;
   hka.md = c->model;
@@ -833,15 +865,15 @@ pdf_status pdf_enable_timing(pdf_ctx *c, int32_t on) {
 pdf_status pdf_get_timing(pdf_ctx *c, double *out_ms, int32_t n) {
   if (!c || !out_ms || n < 0) return PDF_E_INVALID_ARG;
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  double acc[4] = {0, 0, 0, 0};
+  double acc[5] = {0, 0, 0, 0, 0};
   for (size_t i = 0; i + 1 < c->ev.size(); ++i) {
     const int ph = c->ev_phase[i];
-    if (ph > 3) continue;  // phase 4 marks the end of a step
+    if (ph > 4) continue;  // phase 5 marks the end of a step
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
     acc[ph] += ms;
   }
-  for (int i = 0; i < n && i < 4; ++i) out_ms[i] = acc[i];
+  for (int i = 0; i < n && i < 5; ++i) out_ms[i] = acc[i];
   return PDF_OK;
 }
 

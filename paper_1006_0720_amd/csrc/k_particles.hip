@@ -182,12 +182,13 @@ void launch_seed(hipStream_t s, const MeshDev &m, const ModelDev &md, PartDev<T>
 // Table tab:loops): k, eps (eq:dissipation-from-frequency_wall), G_ij and C0
 // (eq:wall-GandC or eq:GandC with the tensor W = wp_ij), production, S_omega
 // (eq:frequency-source) and t_m, pre-multiplied by dt where the step uses them.
+// (px, py) is the point where the source-aware t_m measures its distance.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void record_from(const ModelDev &md, const double U[3], double Om, double Phi,
                                             const double R[6], const double lap[3], const double gp[2],
                                             const double *W, const double dU[3][2], const double gs[2],
-                                            double dt, T *r) {
+                                            double dt, double px, double py, T *r) {
   double k = 0.5 * (R[0] + R[1] + R[2]);
   if (!(k > md.k_floor)) k = md.k_floor;
   const double eps = Om * (k + md.nu * md.CT * md.CT * Om);
@@ -217,7 +218,19 @@ __device__ __forceinline__ void record_from(const ModelDev &md, const double U[3
     inv_tm = 0.5 * md.Cphi * Om;
   } else {
     const double ta = k / eps, tb = md.CT * sqrt(md.nu / eps);
-    inv_tm = 1.0 / (ta > tb ? ta : tb);
+    double tm = ta > tb ? ta : tb;
+    if (md.tm_mode == PDF_TM_SOURCE) {
+      // eq:micromixing-timescale-canyon: the source term C_s (r0^2/eps)^(1/3)
+      // + C_t d / U_c drops out where U_c = |<U>| = 0
+      const double dx = px - md.src_x, dy = py - md.src_y;
+      const double d = sqrt(dx * dx + dy * dy);
+      const double uc = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+      if (uc > 0.0) {
+        const double ts = md.Cs * cbrt(md.src_r * md.src_r / eps) + md.Ct * d / uc;
+        if (ts < tm) tm = ts;
+      }
+    }
+    inv_tm = 1.0 / tm;
   }
   r[R_U] = (T)U[0];
   r[R_V] = (T)U[1];
@@ -290,7 +303,10 @@ __global__ __launch_bounds__(256) void k_elem_prep(MeshDev m, ModelDev md, const
   double dU[3][2], gs[2];
   elem_gradients(m, S, e, qk, dU, gs);
   T *r = rec + (size_t)e * NREC;
-  record_from<T>(md, U, Om, Phi, R, lap, gp, W, dU, gs, dt, r);
+  // the element centroid locates the element for the source-aware t_m
+  const ElemGeo &g = m.geo[e];
+  const double cx = (g.x[0] + g.x[1] + g.x[2]) / 3.0, cy = (g.y[0] + g.y[1] + g.y[2]) / 3.0;
+  record_from<T>(md, U, Om, Phi, R, lap, gp, W, dU, gs, dt, cx, cy, r);
   r[30] = (T)0;
   r[31] = (T)0;
 }
@@ -343,7 +359,7 @@ __device__ __forceinline__ void shape_w(const double lam[3], double w[3]) {
 // then the step coefficients as for an element record
 template <typename T>
 __device__ __forceinline__ void shape_record(const ModelDev &md, const T *rs, const double w[3], double dt,
-                                             T *r) {
+                                             double px, double py, T *r) {
 #define INTERP(f) \
   (w[0] * (double)rs[(f)] + w[1] * (double)rs[S_NODE + (f)] + w[2] * (double)rs[2 * S_NODE + (f)])
   const double U[3] = {INTERP(S_U), INTERP(S_V), INTERP(S_W)};
@@ -360,7 +376,7 @@ __device__ __forceinline__ void shape_record(const ModelDev &md, const T *rs, co
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 2; ++j) dU[i][j] = (double)rs[S_DU + 2 * i + j];
   const double gs[2] = {(double)rs[S_GS], (double)rs[S_GS + 1]};
-  record_from<T>(md, U, Om, Phi, R, lap, gp, W, dU, gs, dt, r);
+  record_from<T>(md, U, Om, Phi, R, lap, gp, W, dU, gs, dt, px, py, r);
 }
 
 template <typename T>
@@ -703,7 +719,8 @@ template <typename T, bool VISC, bool WALLB, bool SHAPE>
 __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(const KArgs *__restrict__ ka, PartDev<T> p, int64_t np,
                                                 int ppt, const T *__restrict__ rec, double *sums, uint32_t k0,
                                                 uint32_t k1, uint32_t step, double dt, double sdt,
-                                                const double *dtp, double s2nu, unsigned long long *cnt) {
+                                                const double *dtp, double s2nu, const T *__restrict__ cm,
+                                                unsigned long long *cnt) {
   __shared__ std::conditional_t<SHAPE, SumTableW, SumTable> tab;
   const MeshDev &m = ka->m;
   const ModelDev &md = ka->md;
@@ -719,10 +736,11 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
   // while the current one is advanced
   int32_t n_e = 0;
   uint32_t n_id = 0;
-  T n_x = (T)0, n_y = (T)0, n_u = (T)0, n_v = (T)0, n_w = (T)0, n_om = (T)0, n_psi = (T)0;
+  T n_x = (T)0, n_y = (T)0, n_u = (T)0, n_v = (T)0, n_w = (T)0, n_om = (T)0, n_psi = (T)0, n_cm = (T)0;
   {
     const int64_t i0 = base + threadIdx.x;
     if (i0 < np) {
+      if (cm) n_cm = cm[i0];
       n_e = p.e[i0];
       n_id = p.id[i0];
       n_x = p.x[i0];
@@ -740,9 +758,10 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
     const int32_t e0 = n_e;
     const uint32_t id = n_id;
     const double x0 = (double)n_x, y0 = (double)n_y;
-    const T up0 = n_u, up1 = n_v, up2 = n_w, om = n_om, psi = n_psi;
+    const T up0 = n_u, up1 = n_v, up2 = n_w, om = n_om, psi = n_psi, cmv = n_cm;
     const int64_t inx = i + WG;
     if (jj + 1 < ppt && inx < np) {
+      if (cm) n_cm = cm[inx];
       n_e = p.e[inx];
       n_id = p.id[inx];
       n_x = p.x[inx];
@@ -762,7 +781,7 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
       double lam0[3], w0[3];
       edge_lambdas(g0, x0, y0, lam0);
       shape_w(lam0, w0);
-      shape_record<T>(md, rec + (size_t)e0 * NRECS, w0, dt, rl);
+      shape_record<T>(md, rec + (size_t)e0 * NRECS, w0, dt, x0, y0, rl);
       r = rl;
     }
 
@@ -821,8 +840,8 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
       omn = -omn;
       C_CLAMP(1);
     }
-    // ---- scalar: eq:IEM ----
-    T psin = psi - r[R_MIX] * (psi - ref0[4]);
+    // ---- scalar: eq:IEM, or eq:IECM with the conditioned mean <phi|V> ----
+    T psin = psi - r[R_MIX] * (psi - (cm ? cmv : ref0[4]));
 
     // ---- tracking: next-best-element walk (Ch.3, Sec. Particle tracking) ----
     int32_t e = e0, found = -1, nrefl = 0;
@@ -1022,7 +1041,7 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
 template <typename T, bool SHAPE>
 void launch_advance_m(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
                       const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
-                      const double *dtp, unsigned long long *cnt) {
+                      const double *dtp, const T *cm, unsigned long long *cnt) {
   const int ppt = pick_ppt(np);
   const unsigned grid = (unsigned)((np + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt));
   const bool visc = md.nu > 0.0;
@@ -1031,23 +1050,23 @@ void launch_advance_m(hipStream_t s, const KArgs *dka, const ModelDev &md, PartD
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   if (visc && wallb)
     hipLaunchKernelGGL((k_advance<T, true, true, SHAPE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt, rec,
-                       sums, k0, k1, step, dt, sdt, dtp, s2nu, cnt);
+                       sums, k0, k1, step, dt, sdt, dtp, s2nu, cm, cnt);
   else if (visc)
     hipLaunchKernelGGL((k_advance<T, true, false, SHAPE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt, rec,
-                       sums, k0, k1, step, dt, sdt, dtp, s2nu, cnt);
+                       sums, k0, k1, step, dt, sdt, dtp, s2nu, cm, cnt);
   else
     hipLaunchKernelGGL((k_advance<T, false, false, SHAPE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt,
-                       rec, sums, k0, k1, step, dt, sdt, dtp, s2nu, cnt);
+                       rec, sums, k0, k1, step, dt, sdt, dtp, s2nu, cm, cnt);
 }
 
 template <typename T>
 void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
                     const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
-                    const double *dtp, unsigned long long *cnt) {
+                    const double *dtp, const T *cm, unsigned long long *cnt) {
   if (md.stats_mode == PDF_STATS_SHAPE)
-    launch_advance_m<T, true>(s, dka, md, p, np, rec, sums, seed, step, dt, dtp, cnt);
+    launch_advance_m<T, true>(s, dka, md, p, np, rec, sums, seed, step, dt, dtp, cm, cnt);
   else
-    launch_advance_m<T, false>(s, dka, md, p, np, rec, sums, seed, step, dt, dtp, cnt);
+    launch_advance_m<T, false>(s, dka, md, p, np, rec, sums, seed, step, dt, dtp, cm, cnt);
 }
 
 #define INST(T)                                                                                  \
@@ -1058,7 +1077,7 @@ void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev
                                     const double *, const double *, double, const double *, T *); \
   template void launch_advance<T>(hipStream_t, const KArgs *, const ModelDev &, PartDev<T>, int64_t, \
                                   const T *, double *, uint64_t, uint32_t, double,                 \
-                                  const double *, unsigned long long *);                         \
+                                  const double *, const T *, unsigned long long *);              \
   template void launch_accumulate<T>(hipStream_t, PartDev<T>, int64_t, const T *, double *);        \
   template void launch_elem_prep_shape<T>(hipStream_t, const MeshDev &, const ModelDev &,           \
                                           const double *, const double *, const double *, T *);    \

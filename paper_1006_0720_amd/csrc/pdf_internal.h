@@ -93,8 +93,9 @@ struct PartDev {
 
 struct ModelDev {
   int32_t model, wp_source, omega_source, tm_mode, wall_b, stats_mode;
+  int32_t mix_model, cond_nu, cond_nv, cond_nw, cond_min, pad;
   double C0, C1, C2, C3, C4, CT, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
-  double src_x, src_y, src_r;
+  double src_x, src_y, src_r, Cs, Ct;
 };
 
 // Mesh and model parameters of the particle kernel, kept in device memory and
@@ -116,6 +117,20 @@ struct RedistBuf {
   size_t temp_bytes = 0;
 };
 bool redist_alloc(RedistBuf &b, int32_t ne, int64_t np, void *(*alloc)(size_t, void *), void *user);
+
+// velocity-conditioned scalar means (eq:IECM): per-element particle lists and
+// the result cm (T[np], storage order)
+struct CondBuf {
+  int32_t ne = 0;
+  int64_t np = 0;
+  int32_t *cnt = nullptr, *off = nullptr, *cursor = nullptr, *big = nullptr, *nbig = nullptr;
+  int32_t *list = nullptr, *list2 = nullptr;
+  void *cm = nullptr, *temp = nullptr;
+  size_t temp_bytes = 0;
+};
+bool cond_alloc(CondBuf &b, int32_t ne, int64_t np, size_t tsize, void *(*alloc)(size_t, void *), void *user);
+template <typename T>
+void launch_cond_means(hipStream_t s, const ModelDev &md, const CondBuf &b, PartDev<T> p);
 template <typename T>
 void launch_redistribute(hipStream_t s, const KArgs *dka, const RedistBuf &b, const double *sums, int stride,
                          PartDev<T> p, int32_t min_ppe, uint64_t seed, uint32_t step, unsigned long long *cnt);
@@ -134,11 +149,13 @@ void launch_elem_prep_shape(hipStream_t s, const MeshDev &m, const ModelDev &md,
 // ELEM: rec has NREC values per element, sums NSUM per element;
 // SHAPE: rec has NRECS values per element, sums NSUM per node.
 // dtp (record and particle kernels): when non-null, the step's time step is
-// read from dtp[0] on the device and the dt argument is ignored
+// read from dtp[0] on the device and the dt argument is ignored.  cm (particle
+// kernel): when non-null, each particle's velocity-conditioned scalar mean
+// (storage order), used by eq:IECM in place of the element's <phi>
 template <typename T>
 void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
                     const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
-                    const double *dtp, unsigned long long *cnt);
+                    const double *dtp, const T *cm, unsigned long long *cnt);
 template <typename T>
 void launch_accumulate_shape(hipStream_t s, const MeshDev &m, PartDev<T> p, int64_t np, const T *rec,
                              double *nsums);
