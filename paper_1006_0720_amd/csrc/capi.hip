@@ -194,7 +194,7 @@ bool redist_reserve(pdf_ctx *c) {
 bool cond_reserve(pdf_ctx *c) {
   if (c->cb.cnt && c->cb.np == c->np) return true;
   CondBuf &b = c->cb;
-  void *old[] = {b.cnt, b.off, b.cursor, b.big, b.nbig, b.list, b.list2, b.cm, b.temp};
+  void *old[] = {b.cnt, b.off, b.cursor, b.big, b.mid, b.nbig, b.list, b.list2, b.cm, b.temp};
   for (void *q : old) dfree(c, q);
   b = CondBuf();
   return cond_alloc(b, c->md.ne, c->np, tsize(c), rb_alloc, c);

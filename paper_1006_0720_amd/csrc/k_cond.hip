@@ -11,15 +11,19 @@
 // mean psi of its final subgroup, summed in FP64 in the order of the positions.
 //
 // Every sort is a rank count within the group: the rank of a particle is the
-// number of group members before it in (key, id) order, which is a
-// permutation because ids are unique and the keys are compared as integers
-// (an order-preserving map of the float bits, with -0 taken as +0).
+// number of group members before it in (key, id) order.  The keys are
+// compared as integers (an order-preserving map of the float bits, -0 taken
+// as +0); in FP32 the key and the id form one 64-bit word.  Ids are unique,
+// so the ranks are a permutation; FP64 and the large-element path also break
+// ties of equal ids by position, and the FP32 LDS path pre-fills its target
+// positions, so that no input can make an index leave its element.
 //
-// Launch sequence: count the particles per element (wave-aggregated atomics),
-// scan, list the particles of every element; one 64-thread workgroup per
-// element with at most 256 particles, all staged in LDS; elements with more go
-// to a list that 256-thread workgroups work through in global memory, with
-// LDS tiles for the rank counts.
+// Launch sequence: count the particles per element (runs merged per wave,
+// then an LDS hash table per tile), scan, list the particles of every element
+// the same way; one 64-thread workgroup per element with at most 128
+// particles, its particles staged in LDS; elements of 129-512 particles the
+// same with larger LDS arrays; larger elements go to 256-thread workgroups
+// that keep the order in global memory and count ranks over LDS tiles.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -29,7 +33,6 @@ namespace pdfk {
 
 namespace {
 
-constexpr int CW = 256;  // particles of an element handled in LDS by one wave
 constexpr int BT = 256;  // threads of the large-element workgroups
 
 __device__ __forceinline__ uint64_t ordkey(float v) {
@@ -98,89 +101,295 @@ __device__ __forceinline__ void wave_runs(int32_t e, bool valid, int &head_lane,
   len = end - lane;
 }
 
-__global__ __launch_bounds__(256) void k_cond_count(int64_t np, int32_t ne, const int32_t *pe, int32_t *cnt) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t e = i < np ? pe[i] : -1;
-  const bool valid = e >= 0 && e < ne;
-  int hl, len;
-  wave_runs(e, valid, hl, len);
-  if (hl == (int)(threadIdx.x & 63)) atomicAdd(&cnt[e], len);
+// ---- per-element particle lists ------------------------------------------
+// A workgroup takes a tile of TT * TP consecutive particles.  Equal elements
+// in consecutive lanes are merged first (wave_runs); the run heads then add
+// their run lengths into an LDS hash table keyed by element, so that each
+// distinct element of the tile costs one global atomic.  A run whose element
+// finds no table slot goes to global memory directly.
+constexpr int TT = 256, TP = 8;
+constexpr int HS_LOG2 = 10, HS = 1 << HS_LOG2;
+
+__device__ __forceinline__ int hslot(int32_t *hk, int32_t e) {
+  uint32_t h = ((uint32_t)e * 2654435761u) >> (32 - HS_LOG2);
+  for (int probe = 0; probe < 32; ++probe) {
+    const int32_t k = __hip_atomic_load(&hk[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (k == e) return (int)h;
+    if (k == -1) {
+      const int32_t old = atomicCAS(&hk[h], -1, e);
+      if (old == -1 || old == e) return (int)h;
+    }
+    h = (h + 1u) & (uint32_t)(HS - 1);
+  }
+  return -1;
 }
 
-__global__ __launch_bounds__(256) void k_cond_fill(int64_t np, int32_t ne, const int32_t *pe, const int32_t *off,
-                                                   int32_t *cursor, int32_t *list) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t e = i < np ? pe[i] : -1;
-  const bool valid = e >= 0 && e < ne;
-  int hl, len;
-  wave_runs(e, valid, hl, len);
-  const int lane = threadIdx.x & 63;
-  int32_t base = 0;
-  if (hl == lane) base = atomicAdd(&cursor[e], len);
-  base = __shfl(base, hl < 0 ? lane : hl, 64);
-  if (valid) list[off[e] + base + (lane - hl)] = (int32_t)i;
+__global__ __launch_bounds__(TT) void k_cond_count(int64_t np, int32_t ne, const int32_t *pe, int32_t *cnt) {
+  __shared__ int32_t hk[HS], hc[HS];
+  const int t = threadIdx.x, lane = t & 63;
+  for (int s = t; s < HS; s += TT) {
+    hk[s] = -1;
+    hc[s] = 0;
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * TT * TP;
+  for (int j = 0; j < TP; ++j) {
+    const int64_t i = base + (int64_t)j * TT + t;
+    const int32_t e = i < np ? pe[i] : -1;
+    const bool valid = e >= 0 && e < ne;
+    int hl, len;
+    wave_runs(e, valid, hl, len);
+    if (hl == lane) {
+      const int s = hslot(hk, e);
+      if (s >= 0)
+        atomicAdd(&hc[s], len);
+      else
+        atomicAdd(&cnt[e], len);
+    }
+  }
+  __syncthreads();
+  for (int s = t; s < HS; s += TT) {
+    const int32_t k = hk[s];
+    if (k >= 0) atomicAdd(&cnt[k], hc[s]);
+  }
 }
 
-// one element of at most CW particles per 64-thread workgroup, in LDS
-template <typename T>
-__global__ __launch_bounds__(64) void k_cond_wave(int32_t ne, ModelDev md, PartDev<T> p, const int32_t *cnt,
-                                                  const int32_t *off, const int32_t *list, int32_t *big,
-                                                  int32_t *nbig, T *cm) {
-  __shared__ uint64_t kp[CW];
-  __shared__ uint32_t ip[2][CW];
-  __shared__ int32_t sp[2][CW];
-  const int32_t e = blockIdx.x;
-  if (e >= ne) return;
-  const int32_t n = cnt[e];
-  if (n == 0) return;
+__global__ __launch_bounds__(TT) void k_cond_fill(int64_t np, int32_t ne, const int32_t *pe, const int32_t *off,
+                                                  int32_t *cursor, int32_t *list) {
+  __shared__ int32_t hk[HS], hc[HS], hb[HS];
+  const int t = threadIdx.x, lane = t & 63;
+  for (int s = t; s < HS; s += TT) {
+    hk[s] = -1;
+    hc[s] = 0;
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * TT * TP;
+  int32_t pe_[TP], slot[TP], rank[TP];
+#pragma unroll
+  for (int j = 0; j < TP; ++j) {
+    const int64_t i = base + (int64_t)j * TT + t;
+    const int32_t e = i < np ? pe[i] : -1;
+    const bool valid = e >= 0 && e < ne;
+    int hl, len;
+    wave_runs(e, valid, hl, len);
+    int s = -1, r = 0;
+    if (hl == lane) {
+      s = hslot(hk, e);
+      r = s >= 0 ? atomicAdd(&hc[s], len) : atomicAdd(&cursor[e], len);  // no slot: the global base
+    }
+    const int src = hl < 0 ? lane : hl;
+    s = __shfl(s, src, 64);
+    r = __shfl(r, src, 64) + (lane - src);
+    pe_[j] = valid ? e : -1;
+    slot[j] = s;
+    rank[j] = r;
+  }
+  __syncthreads();
+  for (int s = t; s < HS; s += TT) {
+    const int32_t k = hk[s];
+    if (k >= 0) hb[s] = atomicAdd(&cursor[k], hc[s]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < TP; ++j) {
+    const int32_t e = pe_[j];
+    if (e < 0) continue;
+    const int64_t i = base + (int64_t)j * TT + t;
+    const int32_t pos = slot[j] >= 0 ? hb[slot[j]] + rank[j] : rank[j];
+    list[off[e] + pos] = (int32_t)i;
+  }
+}
+
+// ---- sort and divide in LDS: one element of at most CAP particles per
+// 64-thread workgroup ----
+constexpr int CAP_S = 128, CAP_M = 512;
+
+template <typename T, int CAP>
+struct CondLds {
+  T ku[CAP], kv[CAP], kw[CAP], psi[CAP];  // by slot (the element's list order)
+  uint32_t id[CAP];
+  int32_t idx[CAP];
+  // by position, two buffers: the sort key (FP32: the 32-bit key over the id
+  // in one word; FP64: the 64-bit key, the id apart) and the slot
+  uint64_t k[2][CAP];
+  uint32_t ki[sizeof(T) == 8 ? 2 : 1][sizeof(T) == 8 ? CAP : 1];
+  uint16_t s[2][CAP];
+};
+
+template <typename T, int CAP>
+__device__ __forceinline__ void set_key(CondLds<T, CAP> &L, int buf, int pos, int slot, int dir) {
+  if constexpr (sizeof(T) == 4) {
+    const uint64_t kk = dir < 0 ? 0 : ordkey(dir == 0 ? L.ku[slot] : (dir == 1 ? L.kv[slot] : L.kw[slot]));
+    L.k[buf][pos] = (kk << 32) | L.id[slot];
+  } else {
+    L.k[buf][pos] = dir < 0 ? 0 : ordkey(dir == 0 ? L.ku[slot] : (dir == 1 ? L.kv[slot] : L.kw[slot]));
+    L.ki[buf][pos] = L.id[slot];
+  }
+}
+
+// rank of position q within its group [s0, s1) in (key, id, position) order
+template <typename T, int CAP>
+__device__ __forceinline__ int32_t rank_in(const CondLds<T, CAP> &L, int cur, int32_t s0, int32_t s1, int32_t q) {
+  const uint64_t mk = L.k[cur][q];
+  int32_t rank = 0;
+  if constexpr (sizeof(T) == 4) {
+    // (key, id) in one word, unique while the ids are
+#pragma unroll 8
+    for (int32_t r = s0; r < s1; ++r) rank += L.k[cur][r] < mk;
+  } else {
+    const uint32_t mi = L.ki[cur][q];
+#pragma unroll 8
+    for (int32_t r = s0; r < s1; ++r) {
+      const uint64_t k = L.k[cur][r];
+      const uint32_t id = L.ki[cur][r];
+      rank += (k < mk) | ((k == mk) & ((id < mi) | ((id == mi) & (r < q))));
+    }
+  }
+  return rank;
+}
+
+// the first division (one group): each thread ranks its QP positions in one
+// sweep over all n keys, read once per sweep
+template <typename T, int CAP, int NT>
+__device__ __forceinline__ void rank_all(const CondLds<T, CAP> &L, int cur, int32_t n, int32_t rank[]) {
+  constexpr int QP = CAP / NT;
   const int t = threadIdx.x;
-  if (n > CW) {
-    if (t == 0) big[atomicAdd(nbig, 1)] = e;
-    return;
+  uint64_t mk[QP];
+  uint32_t mi[QP];
+#pragma unroll
+  for (int j = 0; j < QP; ++j) {
+    const int32_t q = t + j * NT;
+    mk[j] = q < n ? L.k[cur][q] : 0;
+    if constexpr (sizeof(T) == 8) mi[j] = q < n ? L.ki[cur][q] : 0;
+    rank[j] = 0;
   }
-  const int32_t base = off[e];
-  for (int q = t; q < n; q += 64) {
+#pragma unroll 4
+  for (int32_t r = 0; r < n; ++r) {
+    const uint64_t k = L.k[cur][r];
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+      for (int j = 0; j < QP; ++j) rank[j] += k < mk[j];
+    } else {
+      const uint32_t id = L.ki[cur][r];
+#pragma unroll
+      for (int j = 0; j < QP; ++j)
+        rank[j] += (k < mk[j]) | ((k == mk[j]) & ((id < mi[j]) | ((id == mi[j]) & (r < t + j * NT))));
+    }
+  }
+}
+
+// sort and divide the n <= CAP particles of one element (list[base, base+n))
+// with NT threads, and write every particle's bin mean
+template <typename T, int CAP, int NT>
+__device__ void cond_element(CondLds<T, CAP> &L, const ModelDev &md, const PartDev<T> &p, int32_t n, int32_t base,
+                             const int32_t *list, T *cm) {
+  constexpr int QP = CAP / NT;
+  const int t = threadIdx.x;
+  for (int q = t; q < n; q += NT) {
     const int32_t i = list[base + q];
-    sp[0][q] = i;
-    ip[0][q] = p.id[i];
+    L.idx[q] = i;
+    L.id[q] = p.id[i];
+    L.ku[q] = p.u[i];
+    L.kv[q] = p.v[i];
+    L.kw[q] = p.w[i];
+    L.psi[q] = p.psi[i];
   }
+  __syncthreads();
   const Passes ps = plan_passes(md, n);
+  for (int q = t; q < n; q += NT) {
+    L.s[0][q] = (uint16_t)q;
+    set_key(L, 0, q, q, ps.dir[0]);
+  }
+  __syncthreads();
   int cur = 0;
   int32_t nc = 1;
   for (int pass = 0; pass < ps.n_pass; ++pass) {
-    for (int q = t; q < n; q += 64) kp[q] = level_key(p, ps.dir[pass], sp[cur][q]);
-    __syncthreads();
-    for (int q = t; q < n; q += 64) {
-      const int32_t g = (int32_t)((int64_t)nc * q / n);
-      const int32_t s0 = gstart(g, n, nc), s1 = gstart(g + 1, n, nc);
-      const uint64_t mk = kp[q];
-      const uint32_t mid = ip[cur][q];
-      int32_t rank = 0;
-      for (int32_t r = s0; r < s1; ++r) {
-        const uint64_t k = kp[r];
-        const uint32_t id = ip[cur][r];
-        // (key, id) order; the position breaks ties of equal ids, so the
-        // ranks are a permutation whatever the input
-        rank += (k < mk) | ((k == mk) & ((id < mid) | ((id == mid) & (r < q))));
+    const bool more = pass + 1 < ps.n_pass;
+    const int nextdir = more ? ps.dir[pass + 1] : 0;
+    // FP32 ranks are strict-order counts, a permutation only while the ids are
+    // unique: the target positions first get a valid slot so that repeated
+    // ids can only give wrong bins, never an index outside the element
+    if constexpr (sizeof(T) == 4) {
+      for (int q = t; q < n; q += NT) L.s[1 - cur][q] = 0;
+      __syncthreads();
+    }
+    int32_t rank[QP];
+    if (nc == 1) {
+      rank_all<T, CAP, NT>(L, cur, n, rank);
+    } else {
+#pragma unroll
+      for (int j = 0; j < QP; ++j) {
+        const int32_t q = t + j * NT;
+        rank[j] = 0;
+        if (q < n) {
+          const int32_t g = (int32_t)((int64_t)nc * q / n);
+          rank[j] = gstart(g, n, nc) + rank_in(L, cur, gstart(g, n, nc), gstart(g + 1, n, nc), q);
+        }
       }
-      sp[1 - cur][s0 + rank] = sp[cur][q];
-      ip[1 - cur][s0 + rank] = mid;
+    }
+#pragma unroll
+    for (int j = 0; j < QP; ++j) {
+      const int32_t q = t + j * NT;
+      if (q < n) {
+        const int np_ = rank[j];  // the group start is 0 for the single group
+        const int sl = L.s[cur][q];
+        L.s[1 - cur][np_] = (uint16_t)sl;
+        if (more) set_key(L, 1 - cur, np_, sl, nextdir);
+      }
     }
     __syncthreads();
     cur = 1 - cur;
     nc = ps.groups[pass];
   }
   // bin means (App. B), each bin summed in the order of its positions
-  for (int32_t b = t; b < nc; b += 64) {
+  for (int32_t b = t; b < nc; b += NT) {
     const int32_t s0 = gstart(b, n, nc), s1 = gstart(b + 1, n, nc);
     double sum = 0.0;
-    for (int32_t r = s0; r < s1; ++r) sum += (double)p.psi[sp[cur][r]];
+    for (int32_t r = s0; r < s1; ++r) sum += (double)L.psi[L.s[cur][r]];
     const T mean = (T)(sum / (double)(s1 - s0));
-    for (int32_t r = s0; r < s1; ++r) cm[sp[cur][r]] = mean;
+    for (int32_t r = s0; r < s1; ++r) cm[L.idx[L.s[cur][r]]] = mean;
   }
 }
 
-// elements of more than CW particles: one 256-thread workgroup each, the
+// every element: those of at most CAP_S particles here, the others listed
+// for the mid-size and large-element kernels
+template <typename T>
+__global__ __launch_bounds__(64) void k_cond_small(int32_t ne, ModelDev md, PartDev<T> p, const int32_t *cnt,
+                                                   const int32_t *off, const int32_t *list, int32_t *mid,
+                                                   int32_t *big, int32_t *counters, T *cm) {
+  __shared__ CondLds<T, CAP_S> L;
+  const int32_t e = blockIdx.x;
+  if (e >= ne) return;
+  const int32_t n = cnt[e];
+  if (n == 0) return;
+  if (n > CAP_S) {
+    if (threadIdx.x == 0) {
+      if (n > CAP_M)
+        big[atomicAdd(&counters[0], 1)] = e;
+      else
+        mid[atomicAdd(&counters[1], 1)] = e;
+    }
+    return;
+  }
+  cond_element<T, CAP_S, 64>(L, md, p, n, off[e], list, cm);
+}
+
+// the listed elements of CAP_S+1..CAP_M particles, one per 256-thread
+// workgroup (the grid covers every element; workgroups beyond the list exit)
+template <typename T>
+__global__ __launch_bounds__(256) void k_cond_mid(ModelDev md, PartDev<T> p, const int32_t *cnt, const int32_t *off,
+                                                  const int32_t *list, const int32_t *mid, const int32_t *counters,
+                                                  T *cm) {
+  __shared__ CondLds<T, CAP_M> L;
+  const int32_t nm = counters[1];
+  for (int32_t k = blockIdx.x; k < nm; k += gridDim.x) {
+    const int32_t e = mid[k];
+    cond_element<T, CAP_M, 256>(L, md, p, cnt[e], off[e], list, cm);
+    __syncthreads();  // before the next element overwrites the LDS
+  }
+}
+
+// elements of more than CAP_M particles: one 256-thread workgroup each, the
 // order held in global memory (list <-> list2), the rank counts over LDS tiles
 template <typename T>
 __global__ __launch_bounds__(BT) void k_cond_block(ModelDev md, PartDev<T> p, const int32_t *cnt,
@@ -266,12 +475,13 @@ bool cond_alloc(CondBuf &b, int32_t ne, int64_t np, size_t tsize, void *(*alloc)
   b.off = (int32_t *)alloc(((size_t)ne + 1) * 4, user);
   b.cursor = (int32_t *)alloc((size_t)ne * 4, user);
   b.big = (int32_t *)alloc((size_t)ne * 4, user);
-  b.nbig = (int32_t *)alloc(256, user);
+  b.mid = (int32_t *)alloc((size_t)ne * 4, user);
+  b.nbig = (int32_t *)alloc(256, user);  // [0] large elements listed, [1] mid-size
   b.list = (int32_t *)alloc(npl * 4, user);
   b.list2 = (int32_t *)alloc(npl * 4, user);
   b.cm = alloc(npl * tsize, user);
   b.temp = alloc(b.temp_bytes, user);
-  return b.cnt && b.off && b.cursor && b.big && b.nbig && b.list && b.list2 && b.cm && b.temp;
+  return b.cnt && b.off && b.cursor && b.big && b.mid && b.nbig && b.list && b.list2 && b.cm && b.temp;
 }
 
 template <typename T>
@@ -279,18 +489,21 @@ void launch_cond_means(hipStream_t s, const ModelDev &md, const CondBuf &b, Part
   const int32_t ne = b.ne;
   const int64_t np = b.np;
   if (np == 0) return;
-  const unsigned gp = (unsigned)((np + 255) / 256);
+  const unsigned gt = (unsigned)((np + (int64_t)TT * TP - 1) / ((int64_t)TT * TP));
   (void)hipMemsetAsync(b.cnt, 0, ((size_t)ne + 1) * 4, s);
-  hipLaunchKernelGGL(k_cond_count, dim3(gp), dim3(256), 0, s, np, ne, p.e, b.cnt);
+  hipLaunchKernelGGL(k_cond_count, dim3(gt), dim3(TT), 0, s, np, ne, p.e, b.cnt);
   size_t tb = b.temp_bytes;
   hipcub::DeviceScan::ExclusiveSum(b.temp, tb, b.cnt, b.off, ne + 1, s);
   (void)hipMemsetAsync(b.cursor, 0, (size_t)ne * 4, s);
-  (void)hipMemsetAsync(b.nbig, 0, 4, s);
-  hipLaunchKernelGGL(k_cond_fill, dim3(gp), dim3(256), 0, s, np, ne, p.e, b.off, b.cursor, b.list);
-  hipLaunchKernelGGL(k_cond_wave<T>, dim3((unsigned)ne), dim3(64), 0, s, ne, md, p, b.cnt, b.off, b.list,
-                     b.big, b.nbig, (T *)b.cm);
+  (void)hipMemsetAsync(b.nbig, 0, 8, s);
+  hipLaunchKernelGGL(k_cond_fill, dim3(gt), dim3(TT), 0, s, np, ne, p.e, b.off, b.cursor, b.list);
+  T *cm = (T *)b.cm;
+  hipLaunchKernelGGL(k_cond_small<T>, dim3((unsigned)ne), dim3(64), 0, s, ne, md, p, b.cnt, b.off, b.list, b.mid,
+                     b.big, b.nbig, cm);
+  hipLaunchKernelGGL(k_cond_mid<T>, dim3((unsigned)(ne < 65536 ? ne : 65536)), dim3(256), 0, s, md, p, b.cnt, b.off,
+                     b.list, b.mid, b.nbig, cm);
   hipLaunchKernelGGL(k_cond_block<T>, dim3(512), dim3(BT), 0, s, md, p, b.cnt, b.off, b.list, b.list2, b.big,
-                     b.nbig, (T *)b.cm);
+                     b.nbig, cm);
 }
 
 template void launch_cond_means<float>(hipStream_t, const ModelDev &, const CondBuf &, PartDev<float>);

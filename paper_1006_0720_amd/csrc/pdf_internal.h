@@ -123,7 +123,7 @@ bool redist_alloc(RedistBuf &b, int32_t ne, int64_t np, void *(*alloc)(size_t, v
 struct CondBuf {
   int32_t ne = 0;
   int64_t np = 0;
-  int32_t *cnt = nullptr, *off = nullptr, *cursor = nullptr, *big = nullptr, *nbig = nullptr;
+  int32_t *cnt = nullptr, *off = nullptr, *cursor = nullptr, *big = nullptr, *mid = nullptr, *nbig = nullptr;
   int32_t *list = nullptr, *list2 = nullptr;
   void *cm = nullptr, *temp = nullptr;
   size_t temp_bytes = 0;
