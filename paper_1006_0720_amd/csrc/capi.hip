@@ -197,7 +197,9 @@ bool cond_reserve(pdf_ctx *c) {
   void *old[] = {b.cnt, b.off, b.cursor, b.big, b.mid, b.nbig, b.list, b.list2, b.cm, b.temp};
   for (void *q : old) dfree(c, q);
   b = CondBuf();
-  return cond_alloc(b, c->md.ne, c->np, tsize(c), rb_alloc, c);
+  if (!cond_alloc(b, c->md.ne, c->np, tsize(c), rb_alloc, c)) return false;
+  // valid particle indices from the start, whatever a list position holds
+  return hipMemsetAsync(b.list, 0, (size_t)(c->np > 0 ? c->np : 1) * 4, c->stream) == hipSuccess;
 }
 
 template <typename T>
@@ -227,7 +229,10 @@ pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt, const double *cfl
     // eq:IECM: <phi|V> of every particle from the state at the start of the step
     const T *cm = nullptr;
     if (iecm) {
-      launch_cond_means<T>(c->stream, c->model, c->cb, part_view<T>(c, c->cur));
+      // ELEM statistics without redistribution: the last accumulation's count
+      // slot holds the particles per element
+      const bool sums_valid = c->model.stats_mode == PDF_STATS_ELEM && c->params.min_ppe == 0;
+      launch_cond_means<T>(c->stream, c->model, c->cb, part_view<T>(c, c->cur), sums_valid ? c->sums : nullptr);
       cm = (const T *)c->cb.cm;
     }
     mark(c, 0);

@@ -124,6 +124,12 @@ __device__ __forceinline__ int hslot(int32_t *hk, int32_t e) {
   return -1;
 }
 
+// counts from the count slot of the element sums of the last accumulation
+__global__ void k_cond_counts_from_sums(int32_t ne, const double *sums, int32_t *cnt) {
+  const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < ne) cnt[e] = (int32_t)sums[(size_t)e * NSUM];
+}
+
 __global__ __launch_bounds__(TT) void k_cond_count(int64_t np, int32_t ne, const int32_t *pe, int32_t *cnt) {
   __shared__ int32_t hk[HS], hc[HS];
   const int t = threadIdx.x, lane = t & 63;
@@ -196,6 +202,7 @@ __global__ __launch_bounds__(TT) void k_cond_fill(int64_t np, int32_t ne, const 
     if (e < 0) continue;
     const int64_t i = base + (int64_t)j * TT + t;
     const int32_t pos = slot[j] >= 0 ? hb[slot[j]] + rank[j] : rank[j];
+    if (pos >= off[e + 1] - off[e]) continue;  // counts that disagree with the elements stay in bounds
     list[off[e] + pos] = (int32_t)i;
   }
 }
@@ -485,13 +492,16 @@ bool cond_alloc(CondBuf &b, int32_t ne, int64_t np, size_t tsize, void *(*alloc)
 }
 
 template <typename T>
-void launch_cond_means(hipStream_t s, const ModelDev &md, const CondBuf &b, PartDev<T> p) {
+void launch_cond_means(hipStream_t s, const ModelDev &md, const CondBuf &b, PartDev<T> p, const double *elem_sums) {
   const int32_t ne = b.ne;
   const int64_t np = b.np;
   if (np == 0) return;
   const unsigned gt = (unsigned)((np + (int64_t)TT * TP - 1) / ((int64_t)TT * TP));
   (void)hipMemsetAsync(b.cnt, 0, ((size_t)ne + 1) * 4, s);
-  hipLaunchKernelGGL(k_cond_count, dim3(gt), dim3(TT), 0, s, np, ne, p.e, b.cnt);
+  if (elem_sums)
+    hipLaunchKernelGGL(k_cond_counts_from_sums, dim3((ne + 255) / 256), dim3(256), 0, s, ne, elem_sums, b.cnt);
+  else
+    hipLaunchKernelGGL(k_cond_count, dim3(gt), dim3(TT), 0, s, np, ne, p.e, b.cnt);
   size_t tb = b.temp_bytes;
   hipcub::DeviceScan::ExclusiveSum(b.temp, tb, b.cnt, b.off, ne + 1, s);
   (void)hipMemsetAsync(b.cursor, 0, (size_t)ne * 4, s);
@@ -506,7 +516,9 @@ void launch_cond_means(hipStream_t s, const ModelDev &md, const CondBuf &b, Part
                      b.nbig, cm);
 }
 
-template void launch_cond_means<float>(hipStream_t, const ModelDev &, const CondBuf &, PartDev<float>);
-template void launch_cond_means<double>(hipStream_t, const ModelDev &, const CondBuf &, PartDev<double>);
+template void launch_cond_means<float>(hipStream_t, const ModelDev &, const CondBuf &, PartDev<float>,
+                                       const double *);
+template void launch_cond_means<double>(hipStream_t, const ModelDev &, const CondBuf &, PartDev<double>,
+                                        const double *);
 
 }  // namespace pdfk
