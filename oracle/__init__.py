@@ -70,6 +70,8 @@ def lib():
         L.or_redistribute.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, dp, ip, up, C.c_uint64, C.c_uint32]
         L.or_cond_means.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, dp, ip, up, dp]
         L.or_cond_means.restype = None
+        L.or_wall_function.argtypes = [C.c_void_p, C.c_int32, dp, dp, C.c_int32] + [C.c_double] * 6 + [dp] * 4
+        L.or_wall_function.restype = None
         L.or_redistribute.restype = C.c_int64
         _lib = L
     return _lib
@@ -81,13 +83,13 @@ class _Params(C.Structure):
                                          "cond_nu", "cond_nv", "cond_nw", "cond_min")] + \
                [(n, C.c_double) for n in ("C0", "C1", "C2", "C3", "C4", "CT", "CL", "Ceta", "Cv",
                                           "gamma5", "Cw1", "Cw2", "Cphi", "nu", "k_floor",
-                                          "src_x", "src_y", "src_r", "Cs", "Ct")]
+                                          "src_x", "src_y", "src_r", "Cs", "Ct", "nu_wall")]
 
 
 # parameters that older parameter sets may lack: IEM, 5x5x5 bins, at least 2
 # particles per subgroup, the constants of tab:constants
 _DEFAULTS = dict(stats_mode=0, min_ppe=0, mix_model=0, cond_nu=5, cond_nv=5, cond_nw=5, cond_min=2,
-                 Cs=0.02, Ct=0.7)
+                 Cs=0.02, Ct=0.7, nu_wall=0.0)
 
 
 class _Seed(C.Structure):

@@ -849,6 +849,61 @@ static void edge_geom(const or_mesh *m, int32_t e, int k, double *xa, double *ya
   *yb = m->xy[2 * b + 1];
 }
 
+/* ------------------------------------------------------------------------ */
+/* Wall functions (the wall treatment for complex geometries reported in    */
+/* Ch.2): a particle reflected at a wall-function edge keeps its spanwise    */
+/* velocity; in the edge's frame (tangent t along the edge, normal n into    */
+/* the domain) its normal velocity reverses (eq:wall-normal-velocity) and its */
+/* tangential velocity changes by alpha times the incident normal velocity   */
+/* (eq:particle-wallcondition-wf), with alpha from the statistics at the      */
+/* first gridpoint off the wall (eq:alpha, eq:hatu, eq:Ue and                */
+/* eq:friction-velocity, all in the edge's frame); its frequency is scaled   */
+/* by eq:wall-omega.  Constants: C_mu = 0.09, kappa = 0.41, E = 8.5.         */
+/* ------------------------------------------------------------------------ */
+void or_wall_function(const or_params *p, int32_t nn, const double *stats, const double *gradp, int32_t node,
+                      double xa, double ya, double xb, double yb, double xc, double yc, double *u, double *v,
+                      double *w, double *om) {
+  const double Cmu = 0.09, kappa = 0.41, E = 8.5;
+  (void)w; /* the spanwise component is not changed */
+  double dx = xb - xa, dy = yb - ya, len = sqrt(dx * dx + dy * dy);
+  double tx = dx / len, ty = dy / len; /* tangent */
+  double nx = -ty, ny = tx;             /* normal into the domain */
+  double yp = (xc - xa) * nx + (yc - ya) * ny;
+  /* statistics at y_p in the edge's frame */
+  double U = S(0, node), V = S(1, node), Om = S(3, node);
+  double R11 = S(5, node), R22 = S(6, node), R33 = S(7, node), R12 = S(8, node);
+  double Up = U * tx + V * ty;
+  double vvp = R11 * nx * nx + 2.0 * R12 * nx * ny + R22 * ny * ny;
+  double uvp = R11 * tx * nx + R12 * (tx * ny + ty * nx) + R22 * ty * ny;
+  double kp = 0.5 * (R11 + R22 + R33);
+  double dPdx = gradp ? gradp[node] * tx + gradp[(size_t)nn + node] * ty : 0.0;
+  /* eq:hatu */
+  double uhat2 = sqrt(Cmu) * (kp > 0.0 ? kp : 0.0);
+  /* eq:friction-velocity */
+  double gam = (uvp * dPdx > 0.0) ? 1.0 : 0.0;
+  double utau = sqrt(uhat2 + gam * fabs(yp * dPdx));
+  /* eq:Ue */
+  double Ue = utau / kappa * log(E * yp * utau / p->nu_wall);
+  /* eq:alpha; no transfer where the log law gives no positive U_e */
+  double alpha = (Ue > 0.0 && vvp > 0.0) ? 2.0 * uhat2 * Up * fabs(Up) / (vvp * Ue * Ue) : 0.0;
+  /* incident components, eq:wall-normal-velocity and eq:particle-wallcondition-wf */
+  double UI = *u * tx + *v * ty, VI = *u * nx + *v * ny;
+  double UR = UI + alpha * VI, VR = -VI;
+  *u = UR * tx + VR * nx;
+  *v = UR * ty + VR * ny;
+  /* eq:wall-omega */
+  double beta = -2.0 / (0.5 + 0.75 * p->C0 + p->C3 + p->Cw2 - p->Cw1);
+  if (Om > 0.0 && yp > 0.0) *om = *om * exp(beta * VI / (yp * Om));
+}
+
+/* the condition at a wall-function edge of element e: its vertex c off the
+ * edge is the first gridpoint from the wall (statistics of its master node) */
+static void wall_fn_at(const or_params *p, const or_mesh *m, const double *stats, const double *gradp, int32_t c,
+                       double xa, double ya, double xb, double yb, double *u, double *v, double *w, double *om) {
+  or_wall_function(p, m->nn, stats, gradp, m->master[c], xa, ya, xb, yb, m->xy[2 * c], m->xy[2 * c + 1], u, v, w,
+                   om);
+}
+
 /* no-slip particle condition: U_i = 0 and a gamma frequency with the mean and
  * variance of eq:frequency-wallstats (mean from the inward derivative of
  * sqrt(2k)); sub-stream block 16 + 32*hit */
@@ -1113,6 +1168,10 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
         double un_n = un[0] * nx + un[1] * ny;
         un[0] = un[0] - 2.0 * un_n * nx;
         un[1] = un[1] - 2.0 * un_n * ny;
+      } else if (m->bt[b] == OR_BC_WALLFN) {
+        /* the element's vertex off the edge is the first gridpoint from the wall */
+        const int32_t c = m->en[3 * e + k];
+        wall_fn_at(p, m, stats, gradp, c, xa, ya, xb, yb, &un[0], &un[1], &un[2], &omn);
       } else {
         noslip(p, r, nx, ny, seed, pid, step, nrefl, &un[0], &un[1], &un[2], &omn, cnt);
       }

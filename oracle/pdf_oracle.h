@@ -21,6 +21,7 @@
 #define OR_BC_PERIODIC 1
 #define OR_BC_SLIP 2
 #define OR_BC_NOSLIP 3
+#define OR_BC_WALLFN 4 /* wall treated by the wall functions of eq:wall-normal-velocity to eq:wall-omega */
 
 typedef struct or_params {
   int32_t model;        /* 0 = simplified Langevin (eq:wall-GandC), 1 = generalized Langevin (eq:GandC) */
@@ -41,6 +42,7 @@ typedef struct or_params {
   double C0, C1, C2, C3, C4, CT, CL, Ceta, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
   double src_x, src_y, src_r;
   double Cs, Ct;        /* constants of eq:micromixing-timescale-canyon */
+  double nu_wall;       /* kinematic viscosity of the log law eq:Ue (wall-function walls) */
 } or_params;
 
 typedef struct or_seedspec {
@@ -91,6 +93,17 @@ void or_local_wp(const or_mesh *m, const or_params *p, const double *stats, doub
  * |(<U>, <V>)| with A_n the average area of the elements around node n;
  * dt_max when that is larger or no node moves. */
 double or_cfl_dt(const or_mesh *m, const double *stats, double c_cfl, double dt_max);
+
+/* Wall-function condition on a particle reflected at a wall-function edge
+ * (eq:wall-normal-velocity, eq:particle-wallcondition-wf with eq:alpha,
+ * eq:hatu, eq:Ue, eq:friction-velocity, and eq:wall-omega).  The edge runs
+ * from (xa, ya) to (xb, yb) with the domain on its left; the statistics at y_p
+ * are the nodal statistics stats[f*nn + node] (and gradp[f*nn + node], may be
+ * NULL) at `node`, the element's vertex off the edge, at (xc, yc).  u, v, w,
+ * om: the incident velocity and frequency, replaced by the reflected ones. */
+void or_wall_function(const or_params *p, int32_t nn, const double *stats, const double *gradp, int32_t node,
+                      double xa, double ya, double xb, double yb, double xc, double yc, double *u, double *v,
+                      double *w, double *om);
 
 /* Velocity-conditioned scalar mean <phi|V> of every particle (Sec. Estimation
  * of the velocity-conditioned scalar mean, App. B): the mean scalar of its

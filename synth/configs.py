@@ -32,7 +32,7 @@ STATS_ELEM, STATS_SHAPE = 0, 1
 def params(**kw):
     p = dict(model=MODEL_SLM, wp_source=WP_LOCAL, omega_source=0, tm_mode=TM_CPHI, frozen=0,
              wall_b=0, stats_mode=STATS_ELEM, min_ppe=0, mix_model=MIX_IEM, cond_nu=5, cond_nv=5,
-             cond_nw=5, cond_min=2, C0=2.1, Cphi=2.0, nu=0.0, k_floor=1e-10, src_x=0.0, src_y=0.0, src_r=0.0)
+             cond_nw=5, cond_min=2, nu_wall=0.0, C0=2.1, Cphi=2.0, nu=0.0, k_floor=1e-10, src_x=0.0, src_y=0.0, src_r=0.0)
     p.update(PAPER_CONSTANTS)
     p.update(kw)
     return p
@@ -176,6 +176,25 @@ def channel(nx=100, n_half=50, ppe=100, seed=0, steps=500, dt=1e-3, precision="f
     sd = dict(ppe=ppe, seed=seed, psi_mode=PSI_GAUSS_X, a=0.5, b=0.02, c=0.0, U0=U0, R0=R,
               Om0=Om)
     return Workload(f"channel_{mesh.n_elems}_ppe{ppe}_{precision}", mesh, p, sd, dt, steps,
+                    precision, gradp=gradp)
+
+
+def channel_wallfn(nx=40, n_half=10, ppe=50, seed=0, steps=200, dt=2e-3, precision="f64", re_tau=392.0):
+    """Plane channel [0,6]x[0,2] with wall functions at both walls (the
+    coarse-wall variant of Ch.2): a uniform grid whose first gridpoints sit at
+    y+ ~ 40; the simplified Langevin model with C0 = 3.5 (eq:wall-GandC), no
+    viscous terms in the particle equations (nu = 0), nu = 1/Re_tau only in
+    the log law eq:Ue; unit mean pressure gradient; gamma frequency, IEM."""
+    mesh = M.uniform_channel(nx, 2 * n_half, 6.0, 1.0, 0.15, seed)
+    nu = 1.0 / re_tau
+    xy = mesh.node_xy
+    d = np.minimum(xy[:, 1], 2.0 - xy[:, 1])
+    U, R, Om = _wall_fields(np.maximum(d, 2.0 / (2 * n_half)), 1.0, nu)
+    U0 = np.stack([U, np.zeros_like(U), np.zeros_like(U)])
+    gradp = np.stack([np.full(mesh.n_nodes, -1.0), np.zeros(mesh.n_nodes)])
+    p = params(model=MODEL_SLM, C0=3.5, omega_source=1, tm_mode=TM_KEPS, nu=0.0, nu_wall=nu)
+    sd = dict(ppe=ppe, seed=seed, psi_mode=PSI_GAUSS_X, a=0.5, b=0.05, c=0.0, U0=U0, R0=R, Om0=Om)
+    return Workload(f"channel_wallfn_{mesh.n_elems}_ppe{ppe}_{precision}", mesh, p, sd, dt, steps,
                     precision, gradp=gradp)
 
 

@@ -22,6 +22,7 @@ import numpy as np
 BC_PERIODIC = 1
 BC_SLIP = 2
 BC_NOSLIP = 3
+BC_WALLFN = 4   # wall treated by wall functions
 
 
 @dataclass
@@ -321,6 +322,27 @@ def graded_channel(nx=100, n_half=50, Lx=6.0, h=1.0, jitter=0.15, seed=0, top=BC
 
     return _finish(xy, quads, used, rng, jitter, "delaunay", fixed, classify, (Lx, 0.0),
                    f"channel_{nx}x{2 * n_half}", {"Lx": Lx, "H": 2 * h})
+
+
+def uniform_channel(nx=40, ny=20, Lx=6.0, h=1.0, jitter=0.15, seed=0, wall=BC_WALLFN):
+    """Plane channel [0,Lx]x[0,2h] on a uniform grid: streamwise periodic,
+    both walls of type `wall` (wall functions by default: the first gridpoint
+    off the wall sits in the log layer instead of the viscous sublayer)."""
+    rng = np.random.default_rng(seed)
+    xs = np.linspace(0.0, Lx, nx + 1)
+    ys = np.linspace(0.0, 2 * h, ny + 1)
+    keep = np.ones((nx, ny), bool)
+    xy, quads, used, _ = _tensor_triangulation(xs, ys, keep, rng, jitter, "delaunay")
+    fixed = ((np.abs(xy[:, 0]) < 1e-12) | (np.abs(xy[:, 0] - Lx) < 1e-12)
+             | (np.abs(xy[:, 1]) < 1e-12) | (np.abs(xy[:, 1] - 2 * h) < 1e-12))
+
+    def classify(m, nrm):
+        t = np.full(m.shape[0], wall, np.int32)
+        t[(np.abs(m[:, 0]) < 1e-9) | (np.abs(m[:, 0] - Lx) < 1e-9)] = BC_PERIODIC
+        return t
+
+    return _finish(xy, quads, used, rng, jitter, "delaunay", fixed, classify, (Lx, 0.0),
+                   f"uniform_channel_{nx}x{ny}", {"Lx": Lx, "H": 2 * h})
 
 
 def _box_with_blocks(Lx, Ly, blocks, h, ratio, jitter, seed, top_bc, name):
