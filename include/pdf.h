@@ -51,7 +51,7 @@ typedef enum pdf_status {
 } pdf_status;
 
 enum { PDF_FP64 = 0, PDF_FP32 = 1 };                          /* particle-state precision */
-enum { PDF_BC_PERIODIC = 1, PDF_BC_SLIP = 2, PDF_BC_NOSLIP = 3 }; /* boundary-edge types */
+enum { PDF_BC_PERIODIC = 1, PDF_BC_SLIP = 2, PDF_BC_NOSLIP = 3, PDF_BC_WALLFN = 4 }; /* boundary-edge types */
 enum { PDF_MODEL_SLM = 0, PDF_MODEL_GLM = 1 };                /* eq:wall-GandC / eq:GandC */
 enum { PDF_WP_INPUT = 0, PDF_WP_LOCAL = 1 };                  /* source of the tensor wp_ij (GLM) */
 enum { PDF_TM_CPHI = 0, PDF_TM_KEPS = 1, PDF_TM_SOURCE = 2 }; /* micromixing time scale */
@@ -90,7 +90,8 @@ typedef struct pdf_allocator {
  *   elem_nbr      3*n_elems: element across the edge opposite local node k, or
  *                 -(b+1) for boundary edge b
  *   bedge_elem/local  element and local edge index of boundary edge b
- *   bedge_type    PDF_BC_* per boundary edge
+ *   bedge_type    PDF_BC_* per boundary edge (PDF_BC_WALLFN: a wall with the
+ *                 wall-function particle condition, see pdf_model_params.nu_wall)
  *   bedge_partner periodic partner edge, or -1
  *   bedge_shift   2*n_bedges: translation added to a particle crossing edge b
  *                 (periodic edges only)
@@ -154,12 +155,25 @@ typedef struct pdf_mesh_desc {
  *   cond_nu, cond_nv, cond_nw  binning structure, each 1..16 (the paper: 5 x 5 x 5)
  *   cond_min     fewest particles per subgroup, 1..64 (the paper's example: 2)
  *   src_x,src_y,src_r  continuous scalar source disc: psi = 1 inside (r <= 0: none)
- *   Cs, Ct       constants of eq:micromixing-timescale-canyon (tab:constants: 0.02, 0.7) */
+ *   Cs, Ct       constants of eq:micromixing-timescale-canyon (tab:constants: 0.02, 0.7)
+ *   nu_wall      kinematic viscosity of the log law eq:Ue at PDF_BC_WALLFN edges (> 0 when
+ *                the mesh has such edges).  A particle reflected at such an edge gets the
+ *                wall-function condition: in the edge's frame (tangent along the edge,
+ *                normal into the domain) V_R = -V_I (eq:wall-normal-velocity),
+ *                U_R = U_I + alpha V_I (eq:particle-wallcondition-wf, alpha from eq:alpha,
+ *                eq:hatu, eq:Ue, eq:friction-velocity with C_mu = 0.09, kappa = 0.41,
+ *                E = 8.5; alpha = 0 where U_e <= 0), omega_R by eq:wall-omega (unchanged where
+ *                <omega> <= 0), the spanwise velocity kept.  The statistics at y_p are the
+ *                current nodal statistics at the wall element's vertex off the edge; y_p is
+ *                that vertex's distance to the edge's line.  Wall functions replace the
+ *                viscous terms of the particle equations (eq:Lagrangian-position-wf,
+ *                eq:Lagrangian-model-wf): a mesh with PDF_BC_WALLFN edges needs nu = 0
+ *                (PDF_E_INVALID_ARG otherwise). */
 typedef struct pdf_model_params {
   int32_t model, wp_source, omega_source, tm_mode, frozen, wall_b, reorder_every, stats_mode;
   int32_t min_ppe, mix_model, cond_nu, cond_nv, cond_nw, cond_min;
   double C0, C1, C2, C3, C4, CT, CL, Ceta, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
-  double src_x, src_y, src_r, Cs, Ct;
+  double src_x, src_y, src_r, Cs, Ct, nu_wall;
 } pdf_model_params;
 
 /* Initial particle population (Ch.3, Sec. Particle-number control): ppe

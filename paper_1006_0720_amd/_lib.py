@@ -47,14 +47,14 @@ class ModelParams(C.Structure):
                                          "cond_nu", "cond_nv", "cond_nw", "cond_min")] + \
                [(n, C.c_double) for n in ("C0", "C1", "C2", "C3", "C4", "CT", "CL", "Ceta", "Cv",
                                           "gamma5", "Cw1", "Cw2", "Cphi", "nu", "k_floor",
-                                          "src_x", "src_y", "src_r", "Cs", "Ct")]
+                                          "src_x", "src_y", "src_r", "Cs", "Ct", "nu_wall")]
 
 
 # fields a parameter set may omit: ELEM statistics, no redistribution, IEM,
-# 5 x 5 x 5 conditioning bins with at least 2 particles each, and the
-# micromixing constants of tab:constants
+# 5 x 5 x 5 conditioning bins with at least 2 particles each, the
+# micromixing constants of tab:constants, no wall-function viscosity
 PARAM_DEFAULTS = dict(stats_mode=0, min_ppe=0, mix_model=0, cond_nu=5, cond_nv=5, cond_nw=5,
-                      cond_min=2, Cs=0.02, Ct=0.7)
+                      cond_min=2, Cs=0.02, Ct=0.7, nu_wall=0.0)
 
 
 class SeedDesc(C.Structure):

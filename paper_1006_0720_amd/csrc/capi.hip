@@ -252,7 +252,8 @@ pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt, const double *cfl
     }
     mark(c, 1);
     launch_advance<T>(c->stream, c->dka, c->model, part_view<T>(c, c->cur), c->np, rec,
-                      shape ? c->nsums : c->sums, c->seed, c->step, dt, dtp, cm, c->cnt);
+                      shape ? c->nsums : c->sums, c->seed, c->step, dt, dtp, cm, c->stats_cur,
+                      c->gradp_set ? c->gradp : nullptr, c->cnt);
     mark(c, 2);
     if (shape) {
       launch_node_stats_shape<T>(c->stream, c->md, c->nsums, c->stats_cur, c->stats_cur, c->stats_est,
@@ -314,6 +315,12 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   if (params->stats_mode != PDF_STATS_ELEM && params->stats_mode != PDF_STATS_SHAPE) return PDF_E_INVALID_ARG;
   if (params->min_ppe < 0 || params->min_ppe > 64) return PDF_E_INVALID_ARG;
   if (params->tm_mode < PDF_TM_CPHI || params->tm_mode > PDF_TM_SOURCE) return PDF_E_INVALID_ARG;
+  // wall functions replace the viscous terms of the particle equations and
+  // need the viscosity of the log law
+  bool has_wallfn = false;
+  for (int32_t b = 0; b < mesh->n_bedges; ++b) has_wallfn |= mesh->bedge_type[b] == PDF_BC_WALLFN;
+  if (has_wallfn && (params->nu != 0.0 || !(params->nu_wall > 0.0) || !std::isfinite(params->nu_wall)))
+    return PDF_E_INVALID_ARG;
   if (params->mix_model != PDF_MIX_IEM && params->mix_model != PDF_MIX_IECM) return PDF_E_INVALID_ARG;
   if (params->cond_nu < 1 || params->cond_nu > 16 || params->cond_nv < 1 || params->cond_nv > 16 ||
       params->cond_nw < 1 || params->cond_nw > 16 || params->cond_min < 1 || params->cond_min > 64)
@@ -386,7 +393,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
     }
   for (int32_t b = 0; b < nb; ++b) {
     const int32_t t = mesh->bedge_type[b];
-    if (t != PDF_BC_PERIODIC && t != PDF_BC_SLIP && t != PDF_BC_NOSLIP)
+    if (t != PDF_BC_PERIODIC && t != PDF_BC_SLIP && t != PDF_BC_NOSLIP && t != PDF_BC_WALLFN)
       return bad("unknown boundary type at edge " + std::to_string(b));
     const int32_t e = mesh->bedge_elem[b], k = mesh->bedge_local[b];
     if (e < 0 || e >= ne || k < 0 || k > 2 || nbr[3 * e + k] != -(b + 1))
@@ -624,6 +631,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   md.cond_nw = params->cond_nw;
   md.cond_min = params->cond_min;
   md.pad = 0;
+  md.nu_wall = params->nu_wall;
   KArgs hka;
   hka.m = c->md;
   hka.md = c->model;

@@ -708,6 +708,38 @@ __device__ __forceinline__ void noslip(const ModelDev &md, const T *r, double nx
 #define C_GFAIL(v) (cb += (uint64_t)(v) << 32)
 #define C_NAN(v) (cb += (uint64_t)(v) << 40)
 
+// Wall-function condition (eq:wall-normal-velocity, eq:particle-wallcondition-wf
+// with eq:alpha, eq:hatu, eq:Ue and eq:friction-velocity; eq:wall-omega) for a
+// particle reflected at the edge from (xa, ya) along (dx, dy), the domain on
+// its left.  The first gridpoint from the wall is the element's vertex off the
+// edge, at (xc, yc), with master node q; its nodal statistics S (and the mean-
+// pressure gradient gp, may be null) are taken in the edge's frame.  Returns
+// the reflected in-plane velocity and frequency; the spanwise velocity is kept.
+__device__ __noinline__ double3 wall_function(const ModelDev &md, const double *S, const double *gp, int32_t nn,
+                                              int32_t q, double xa, double ya, double dx, double dy, double xc,
+                                              double yc, double u, double v, double om) {
+  constexpr double Cmu_sqrt = 0.3, kappa = 0.41, E = 8.5;  // sqrt(0.09)
+  const double len = sqrt(dx * dx + dy * dy);
+  const double tx = dx / len, ty = dy / len, nx = -ty, ny = tx;
+  const double yp = (xc - xa) * nx + (yc - ya) * ny;
+  const double Up = S[q] * tx + S[nn + q] * ty;
+  const double Om = S[3 * nn + q];
+  const double R11 = S[5 * nn + q], R22 = S[6 * nn + q], R33 = S[7 * nn + q], R12 = S[8 * nn + q];
+  const double vvp = R11 * nx * nx + 2.0 * R12 * nx * ny + R22 * ny * ny;
+  const double uvp = R11 * tx * nx + R12 * (tx * ny + ty * nx) + R22 * ty * ny;
+  const double kp = 0.5 * (R11 + R22 + R33);
+  const double dPdx = gp ? gp[q] * tx + gp[nn + q] * ty : 0.0;
+  const double uhat2 = Cmu_sqrt * (kp > 0.0 ? kp : 0.0);
+  const double utau = sqrt(uhat2 + ((uvp * dPdx > 0.0) ? fabs(yp * dPdx) : 0.0));
+  const double Ue = utau / kappa * log(E * yp * utau / md.nu_wall);
+  const double alpha = (Ue > 0.0 && vvp > 0.0) ? 2.0 * uhat2 * Up * fabs(Up) / (vvp * Ue * Ue) : 0.0;
+  const double UI = u * tx + v * ty, VI = u * nx + v * ny;
+  const double UR = UI + alpha * VI, VR = -VI;
+  const double beta = -2.0 / (0.5 + 0.75 * md.C0 + md.C3 + md.Cw2 - md.Cw1);
+  const double omr = (Om > 0.0 && yp > 0.0) ? om * exp(beta * VI / (yp * Om)) : om;
+  return make_double3(UR * tx + VR * nx, UR * ty + VR * ny, omr);
+}
+
 // Occupancy: the FP32 element-average kernel is held to 3 waves per SIMD
 // (at most 168 VGPRs; the LDS table of 3 copies, 48 KB, lets 3 workgroups
 // share a CU), which hides more of the latency of the walk's dependent loads
@@ -720,7 +752,7 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
                                                 int ppt, const T *__restrict__ rec, double *sums, uint32_t k0,
                                                 uint32_t k1, uint32_t step, double dt, double sdt,
                                                 const double *dtp, double s2nu, const T *__restrict__ cm,
-                                                unsigned long long *cnt) {
+                                                const double *S, const double *gradp, unsigned long long *cnt) {
   __shared__ std::conditional_t<SHAPE, SumTableW, SumTable> tab;
   const MeshDev &m = ka->m;
   const ModelDev &md = ka->md;
@@ -938,6 +970,13 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
         const double vn = (double)un0 * nx + (double)un1 * ny;
         un0 = (T)((double)un0 - 2.0 * vn * nx);
         un1 = (T)((double)un1 - 2.0 * vn * ny);
+      } else if (!VISC && bt == PDF_BC_WALLFN) {
+        // wall functions go with the inviscid particle equations
+        const double3 rw = wall_function(md, S, gradp, m.nn, m.master[sel3(g.n, k)], xa, ya, dx, dy,
+                                         sel3(g.x, k), sel3(g.y, k), (double)un0, (double)un1, (double)omn);
+        un0 = (T)rw.x;
+        un1 = (T)rw.y;
+        omn = (T)rw.z;
       } else {
         { int gf = 0; noslip<T>(md, r, nx, ny, k0, k1, id, step, nrefl, un0, un1, un2, omn, gf); C_GFAIL(gf); }
       }
@@ -1041,7 +1080,8 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
 template <typename T, bool SHAPE>
 void launch_advance_m(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
                       const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
-                      const double *dtp, const T *cm, unsigned long long *cnt) {
+                      const double *dtp, const T *cm, const double *S, const double *gradp,
+                      unsigned long long *cnt) {
   const int ppt = pick_ppt(np);
   const unsigned grid = (unsigned)((np + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt));
   const bool visc = md.nu > 0.0;
@@ -1050,23 +1090,24 @@ void launch_advance_m(hipStream_t s, const KArgs *dka, const ModelDev &md, PartD
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   if (visc && wallb)
     hipLaunchKernelGGL((k_advance<T, true, true, SHAPE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt, rec,
-                       sums, k0, k1, step, dt, sdt, dtp, s2nu, cm, cnt);
+                       sums, k0, k1, step, dt, sdt, dtp, s2nu, cm, S, gradp, cnt);
   else if (visc)
     hipLaunchKernelGGL((k_advance<T, true, false, SHAPE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt, rec,
-                       sums, k0, k1, step, dt, sdt, dtp, s2nu, cm, cnt);
+                       sums, k0, k1, step, dt, sdt, dtp, s2nu, cm, S, gradp, cnt);
   else
     hipLaunchKernelGGL((k_advance<T, false, false, SHAPE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt,
-                       rec, sums, k0, k1, step, dt, sdt, dtp, s2nu, cm, cnt);
+                       rec, sums, k0, k1, step, dt, sdt, dtp, s2nu, cm, S, gradp, cnt);
 }
 
 template <typename T>
 void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
                     const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
-                    const double *dtp, const T *cm, unsigned long long *cnt) {
+                    const double *dtp, const T *cm, const double *S, const double *gradp,
+                    unsigned long long *cnt) {
   if (md.stats_mode == PDF_STATS_SHAPE)
-    launch_advance_m<T, true>(s, dka, md, p, np, rec, sums, seed, step, dt, dtp, cm, cnt);
+    launch_advance_m<T, true>(s, dka, md, p, np, rec, sums, seed, step, dt, dtp, cm, S, gradp, cnt);
   else
-    launch_advance_m<T, false>(s, dka, md, p, np, rec, sums, seed, step, dt, dtp, cm, cnt);
+    launch_advance_m<T, false>(s, dka, md, p, np, rec, sums, seed, step, dt, dtp, cm, S, gradp, cnt);
 }
 
 #define INST(T)                                                                                  \
@@ -1077,7 +1118,8 @@ void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev
                                     const double *, const double *, double, const double *, T *); \
   template void launch_advance<T>(hipStream_t, const KArgs *, const ModelDev &, PartDev<T>, int64_t, \
                                   const T *, double *, uint64_t, uint32_t, double,                 \
-                                  const double *, const T *, unsigned long long *);              \
+                                  const double *, const T *, const double *, const double *,       \
+                                  unsigned long long *);                                         \
   template void launch_accumulate<T>(hipStream_t, PartDev<T>, int64_t, const T *, double *);        \
   template void launch_elem_prep_shape<T>(hipStream_t, const MeshDev &, const ModelDev &,           \
                                           const double *, const double *, const double *, T *);    \

@@ -95,7 +95,7 @@ struct ModelDev {
   int32_t model, wp_source, omega_source, tm_mode, wall_b, stats_mode;
   int32_t mix_model, cond_nu, cond_nv, cond_nw, cond_min, pad;
   double C0, C1, C2, C3, C4, CT, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
-  double src_x, src_y, src_r, Cs, Ct;
+  double src_x, src_y, src_r, Cs, Ct, nu_wall;
 };
 
 // Mesh and model parameters of the particle kernel, kept in device memory and
@@ -153,11 +153,14 @@ void launch_elem_prep_shape(hipStream_t s, const MeshDev &m, const ModelDev &md,
 // dtp (record and particle kernels): when non-null, the step's time step is
 // read from dtp[0] on the device and the dt argument is ignored.  cm (particle
 // kernel): when non-null, each particle's velocity-conditioned scalar mean
-// (storage order), used by eq:IECM in place of the element's <phi>
+// (storage order), used by eq:IECM in place of the element's <phi>.  S, gradp:
+// the current nodal statistics and mean-pressure gradient (gradp may be null),
+// read at wall-function edges
 template <typename T>
 void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
                     const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
-                    const double *dtp, const T *cm, unsigned long long *cnt);
+                    const double *dtp, const T *cm, const double *S, const double *gradp,
+                    unsigned long long *cnt);
 template <typename T>
 void launch_accumulate_shape(hipStream_t s, const MeshDev &m, PartDev<T> p, int64_t np, const T *rec,
                              double *nsums);
