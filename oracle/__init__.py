@@ -262,7 +262,11 @@ class Oracle:
         m = self.mesh
         st = np.ascontiguousarray(self.stats)
         if self.params["model"] == 1:
-            wp = self.local_wp(st) if self.params["wp_source"] == 1 else self.wp_input
+            if self.params["wp_source"] == 2:  # the elliptic relaxation solved by FEM
+                from oracle import elliptic
+                wp = elliptic.solve(m, self.params, st, self.local_wp(st))
+            else:
+                wp = self.local_wp(st) if self.params["wp_source"] == 1 else self.wp_input
             wp = np.ascontiguousarray(wp)
             wpp = _p(wp, C.c_double)
         else:

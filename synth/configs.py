@@ -22,7 +22,7 @@ PAPER_CONSTANTS = dict(C1=1.85, C2=0.63, C3=5.0, C4=0.25, CT=6.0, CL=0.134, Ceta
                        gamma5=0.1, Cw1=0.5, Cw2=0.73, Cs=0.02, Ct=0.7)
 
 MODEL_SLM, MODEL_GLM = 0, 1
-WP_INPUT, WP_LOCAL = 0, 1
+WP_INPUT, WP_LOCAL, WP_ELLIPTIC = 0, 1, 2
 TM_CPHI, TM_KEPS, TM_SOURCE = 0, 1, 2
 MIX_IEM, MIX_IECM = 0, 1
 PSI_ZERO, PSI_STEP_X, PSI_GAUSS_X, PSI_BERNOULLI, PSI_DISC = 0, 1, 2, 3, 4
