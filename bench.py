@@ -149,6 +149,9 @@ def main():
     ap.add_argument("--mix", default="iem", choices=["iem", "iecm"],
                     help="micromixing: IEM (eq:IEM) or IECM with the velocity-conditioned mean "
                          "(eq:IECM, 5 x 5 x 5 bins, at least 2 per subgroup)")
+    ap.add_argument("--wp", default="local", choices=["local", "elliptic"],
+                    help="tensor wp_ij of the generalized Langevin model: the local right-hand side of the "
+                         "elliptic relaxation, or its finite-element solve every step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
@@ -177,6 +180,8 @@ def main():
         w.params = dict(w.params, stats_mode=CF.STATS_SHAPE)
     if args.min_ppe > 0:
         w.params = dict(w.params, min_ppe=args.min_ppe)
+    if args.wp == "elliptic":
+        w.params = dict(w.params, wp_source=CF.WP_ELLIPTIC, ell_tol=1e-10, ell_maxit=500)
     if args.mix == "iecm":
         w.params = dict(w.params, mix_model=CF.MIX_IECM, cond_nu=5, cond_nv=5, cond_nw=5, cond_min=2)
     tsize = 4 if w.precision == "f32" else 8
@@ -234,10 +239,11 @@ def main():
                    "n_elements": w.mesh.n_elems, "n_nodes": w.mesh.n_nodes,
                    "particles_per_element": int(w.seed["ppe"]), "dt": w.dt,
                    "reorder_every": args.reorder_every, "stats_mode": args.stats_mode,
-                   "min_ppe": args.min_ppe, "mix": args.mix},
+                   "min_ppe": args.min_ppe, "mix": args.mix, "wp": args.wp},
         "roofline": roof,
         "phase_ms_per_step": {k: round(v / args.steps, 4) for k, v in tm.items()},
-        "counters": {k: cnt[k] for k in ("lost", "brute", "fallback", "nonfinite", "empty_node", "redist")},
+        "counters": {k: cnt[k] for k in ("lost", "brute", "fallback", "nonfinite", "empty_node", "redist",
+                                         "ell_iters")},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, w)

@@ -53,7 +53,7 @@ typedef enum pdf_status {
 enum { PDF_FP64 = 0, PDF_FP32 = 1 };                          /* particle-state precision */
 enum { PDF_BC_PERIODIC = 1, PDF_BC_SLIP = 2, PDF_BC_NOSLIP = 3, PDF_BC_WALLFN = 4 }; /* boundary-edge types */
 enum { PDF_MODEL_SLM = 0, PDF_MODEL_GLM = 1 };                /* eq:wall-GandC / eq:GandC */
-enum { PDF_WP_INPUT = 0, PDF_WP_LOCAL = 1 };                  /* source of the tensor wp_ij (GLM) */
+enum { PDF_WP_INPUT = 0, PDF_WP_LOCAL = 1, PDF_WP_ELLIPTIC = 2 };                  /* source of the tensor wp_ij (GLM) */
 enum { PDF_TM_CPHI = 0, PDF_TM_KEPS = 1, PDF_TM_SOURCE = 2 }; /* micromixing time scale */
 enum { PDF_MIX_IEM = 0, PDF_MIX_IECM = 1 };                  /* micromixing model */
 enum { PDF_PSI_ZERO = 0, PDF_PSI_STEP_X = 1, PDF_PSI_GAUSS_X = 2, PDF_PSI_BERNOULLI = 3,
@@ -70,7 +70,8 @@ enum {
   PDF_CNT_WALK_STEPS = 0, PDF_CNT_FALLBACK = 1, PDF_CNT_BRUTE = 2, PDF_CNT_LOST = 3,
   PDF_CNT_REFLECT = 4, PDF_CNT_PERIODIC = 5, PDF_CNT_NOSLIP_B = 6, PDF_CNT_OMEGA_CLAMP = 7,
   PDF_CNT_GAMMA_FAIL = 8, PDF_CNT_EMPTY_NODE = 9, PDF_CNT_NONFINITE = 10, PDF_CNT_STEPS = 11,
-  PDF_CNT_REDIST = 12 /* particles moved by the redistribution */
+  PDF_CNT_REDIST = 12, /* particles moved by the redistribution */
+  PDF_CNT_ELL_ITERS = 13 /* conjugate-gradient iterations of the elliptic relaxation */
 };
 
 /* Device allocator hook.  alloc returns device memory of at least `bytes`
@@ -120,6 +121,17 @@ typedef struct pdf_mesh_desc {
  *   wp_source    GLM only: PDF_WP_INPUT (nodal field set by pdf_set_nodal_field)
  *                or PDF_WP_LOCAL (right-hand side of eq:elliptic-relaxation-Lagrangian
  *                evaluated at the nodes from the estimated statistics)
+ *                or PDF_WP_ELLIPTIC: eq:elliptic-relaxation-Lagrangian solved every step
+ *                with linear finite elements (Ch.3, Sec. Solution of the Eulerian
+ *                equations): per component (M + L_ij^2 K) wp = M f with M the consistent
+ *                mass and K the stiffness matrix, f the local right-hand side, L_ij from
+ *                eq:L (element averages of k and eps; C_xi,ij = 1 + 1.3 n_i n_j of eq:Cxi
+ *                with n the outward normal of the no-slip wall edge closest to the
+ *                element), wp_ij = -4.5 eps n_i n_j at no-slip wall nodes; Jacobi-
+ *                preconditioned conjugate gradients from the previous solution until the
+ *                preconditioned residual of every component is below ell_tol times that
+ *                of its right-hand side, at most ell_maxit iterations (the call then
+ *                waits for the stream every 8 iterations)
  *   omega_source 1: S_omega of eq:frequency-source; 0: S_omega = 0
  *   tm_mode      PDF_TM_CPHI: 1/t_m = C_phi <omega>/2; PDF_TM_KEPS: t_m = max(k/eps, C_T sqrt(nu/eps));
  *                PDF_TM_SOURCE: eq:micromixing-timescale-canyon, t_m = min(C_s (r0^2/eps)^(1/3)
@@ -171,9 +183,9 @@ typedef struct pdf_mesh_desc {
  *                (PDF_E_INVALID_ARG otherwise). */
 typedef struct pdf_model_params {
   int32_t model, wp_source, omega_source, tm_mode, frozen, wall_b, reorder_every, stats_mode;
-  int32_t min_ppe, mix_model, cond_nu, cond_nv, cond_nw, cond_min;
+  int32_t min_ppe, mix_model, cond_nu, cond_nv, cond_nw, cond_min, ell_maxit;
   double C0, C1, C2, C3, C4, CT, CL, Ceta, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
-  double src_x, src_y, src_r, Cs, Ct, nu_wall;
+  double src_x, src_y, src_r, Cs, Ct, nu_wall, ell_tol;
 } pdf_model_params;
 
 /* Initial particle population (Ch.3, Sec. Particle-number control): ppe
@@ -205,6 +217,13 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
  *   PDF_FIELD_GRADP [2][n_nodes]          mean-pressure gradient / rho
  *                                         (eq:velocity-prediction; default 0) */
 pdf_status pdf_set_nodal_field(pdf_ctx *ctx, int32_t field, const double *data, int32_t on_device);
+
+/* Copy a nodal field out, same ids and layouts: PDF_FIELD_STATS the latest
+ * statistics, PDF_FIELD_WP the tensor wp_ij the last step used (the solution
+ * of the elliptic relaxation with PDF_WP_ELLIPTIC), PDF_FIELD_GRADP the
+ * mean-pressure gradient.  on_device = 0: host memory (synchronizes); 1:
+ * device memory (asynchronous). */
+pdf_status pdf_get_nodal_field(pdf_ctx *ctx, int32_t field, double *data, int32_t on_device);
 
 /* Seed n_elems*ppe particles (ids e*ppe+j) and estimate the initial statistics. */
 pdf_status pdf_seed_particles(pdf_ctx *ctx, const pdf_seed_desc *seed);

@@ -22,7 +22,7 @@ NSTAT = 25
 NELEMSTAT = 16
 NCOUNTERS = 16
 COUNTER_NAMES = ["walk_steps", "fallback", "brute", "lost", "reflect", "periodic", "noslip_b",
-                 "omega_clamp", "gamma_fail", "empty_node", "nonfinite", "steps", "redist"]
+                 "omega_clamp", "gamma_fail", "empty_node", "nonfinite", "steps", "redist", "ell_iters"]
 STATUS = {0: "PDF_OK", 1: "PDF_E_INVALID_ARG", 2: "PDF_E_BAD_MESH", 3: "PDF_E_OOM",
           4: "PDF_E_DEVICE", 5: "PDF_E_STATE", 6: "PDF_E_LOST_PARTICLE", 7: "PDF_E_NUMERIC"}
 
@@ -44,17 +44,18 @@ class MeshDesc(C.Structure):
 class ModelParams(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("model", "wp_source", "omega_source", "tm_mode", "frozen",
                                          "wall_b", "reorder_every", "stats_mode", "min_ppe", "mix_model",
-                                         "cond_nu", "cond_nv", "cond_nw", "cond_min")] + \
+                                         "cond_nu", "cond_nv", "cond_nw", "cond_min", "ell_maxit")] + \
                [(n, C.c_double) for n in ("C0", "C1", "C2", "C3", "C4", "CT", "CL", "Ceta", "Cv",
                                           "gamma5", "Cw1", "Cw2", "Cphi", "nu", "k_floor",
-                                          "src_x", "src_y", "src_r", "Cs", "Ct", "nu_wall")]
+                                          "src_x", "src_y", "src_r", "Cs", "Ct", "nu_wall", "ell_tol")]
 
 
 # fields a parameter set may omit: ELEM statistics, no redistribution, IEM,
 # 5 x 5 x 5 conditioning bins with at least 2 particles each, the
-# micromixing constants of tab:constants, no wall-function viscosity
+# micromixing constants of tab:constants, no wall-function viscosity, and
+# the conjugate-gradient limits of the elliptic relaxation
 PARAM_DEFAULTS = dict(stats_mode=0, min_ppe=0, mix_model=0, cond_nu=5, cond_nv=5, cond_nw=5,
-                      cond_min=2, Cs=0.02, Ct=0.7, nu_wall=0.0)
+                      cond_min=2, Cs=0.02, Ct=0.7, nu_wall=0.0, ell_maxit=500, ell_tol=1e-12)
 
 
 class SeedDesc(C.Structure):
@@ -84,6 +85,7 @@ def _load():
         "pdf_advance": ([vp, i32, dbl], i32),
         "pdf_advance_cfl": ([vp, i32, dbl, dbl, C.POINTER(dbl)], i32),
         "pdf_estimate_stats": ([vp, vp, vp, i32], i32),
+        "pdf_get_nodal_field": ([vp, i32, vp, i32], i32),
         "pdf_num_particles": ([vp, C.POINTER(i64)], i32),
         "pdf_get_particles": ([vp, vp, vp, vp], i32),
         "pdf_set_particles": ([vp, i64, vp, vp, vp], i32),
@@ -224,6 +226,13 @@ class Context:
         return t.value if wait else None
 
     # ---- outputs -------------------------------------------------------
+    def nodal_field(self, field):
+        """A nodal field (FIELD_STATS, FIELD_WP or FIELD_GRADP) as (nf, n_nodes)."""
+        nf = {FIELD_STATS: NSTAT, FIELD_WP: 9, FIELD_GRADP: 2}[field]
+        out = np.empty((nf, self.n_nodes))
+        self._chk(lib.pdf_get_nodal_field(self.h, int(field), _ptr(out), 0))
+        return out
+
     def stats(self, elem=False):
         nodal = np.empty((NSTAT, self.n_nodes))
         el = np.empty((NELEMSTAT, self.n_elems)) if elem else None

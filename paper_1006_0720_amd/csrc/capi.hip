@@ -40,6 +40,8 @@ struct pdf_ctx {
   double *nsums = nullptr;    // SHAPE: per-node weighted sums
   RedistBuf rb;               // particle redistribution (min_ppe > 0)
   CondBuf cb;                 // velocity-conditioned scalar means (IECM)
+  EllBuf ell;                 // elliptic relaxation (PDF_WP_ELLIPTIC)
+  uint64_t ell_iters = 0;     // conjugate-gradient iterations since the last counter reset
   int32_t *offs = nullptr, *cursor = nullptr, *blocksums = nullptr;
   // particles (two buffers for the reorder)
   void *pbuf[2] = {nullptr, nullptr};
@@ -202,6 +204,65 @@ bool cond_reserve(pdf_ctx *c) {
   return hipMemsetAsync(b.list, 0, (size_t)(c->np > 0 ? c->np : 1) * 4, c->stream) == hipSuccess;
 }
 
+// elliptic relaxation: buffers, the nodes of no-slip edges (Dirichlet rows)
+// with the normalised sum of their edges' outward unit normals, and each
+// element's closest no-slip wall normal (computed once, on the device)
+pdf_status ell_setup(pdf_ctx *c, const pdf_mesh_desc *mesh) {
+  const int32_t nn = c->md.nn, ne = c->md.ne, nb = mesh->n_bedges;
+  EllBuf &b = c->ell;
+  const size_t v9 = 9 * (size_t)nn * sizeof(double);
+  b.L2 = (double4 *)dalloc(c, (size_t)ne * sizeof(double4));
+  b.nrm = (double2 *)dalloc(c, (size_t)ne * sizeof(double2));
+  b.dnv = (double2 *)dalloc(c, (size_t)nn * sizeof(double2));
+  b.dir = (int8_t *)dalloc(c, (size_t)nn);
+  b.f = (double *)dalloc(c, v9);
+  b.r = (double *)dalloc(c, v9);
+  b.z = (double *)dalloc(c, v9);
+  b.p = (double *)dalloc(c, v9);
+  b.q = (double *)dalloc(c, v9);
+  b.diag = (double *)dalloc(c, v9);
+  b.scal = (double *)dalloc(c, (size_t)(18 * (c->params.ell_maxit + 1)) * sizeof(double));
+  b.stop = (int *)dalloc(c, 256);
+  if (!b.L2 || !b.nrm || !b.dnv || !b.dir || !b.f || !b.r || !b.z || !b.p || !b.q || !b.diag || !b.scal || !b.stop)
+    return fail(c, PDF_E_OOM, "elliptic relaxation buffers");
+  const double *xy = mesh->node_xy;
+  const int32_t *en = mesh->elem_nodes, *master = mesh->node_master;
+  std::vector<double4> wall;
+  std::vector<double2> dn((size_t)nn, make_double2(0.0, 0.0));
+  std::vector<int8_t> dir((size_t)nn, 0);
+  for (int32_t e = 0; e < nb; ++e) {
+    if (mesh->bedge_type[e] != PDF_BC_NOSLIP) continue;
+    const int32_t el = mesh->bedge_elem[e], k = mesh->bedge_local[e];
+    const int32_t na = en[3 * el + (k + 1) % 3], nc = en[3 * el + (k + 2) % 3];
+    const double xa = xy[2 * na], ya = xy[2 * na + 1], xb = xy[2 * nc], yb = xy[2 * nc + 1];
+    wall.push_back(make_double4(xa, ya, xb, yb));
+    const double dx = xb - xa, dy = yb - ya, len = std::sqrt(dx * dx + dy * dy);
+    for (const int32_t n : {master[na], master[nc]}) {
+      dn[n].x += dy / len;
+      dn[n].y += -dx / len;
+      dir[n] = 1;
+    }
+  }
+  for (int32_t n = 0; n < nn; ++n)
+    if (dir[n]) {
+      const double l = std::sqrt(dn[n].x * dn[n].x + dn[n].y * dn[n].y);
+      dn[n].x /= l;
+      dn[n].y /= l;
+    }
+  hipStream_t s = c->stream;
+  HIPCHK(c, hipMemcpyAsync(b.dnv, dn.data(), dn.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(b.dir, dir.data(), dir.size(), hipMemcpyHostToDevice, s));
+  double4 *wd = (double4 *)dalloc(c, (wall.size() + 1) * sizeof(double4));
+  if (!wd) return fail(c, PDF_E_OOM, "elliptic relaxation wall list");
+  if (!wall.empty())
+    HIPCHK(c, hipMemcpyAsync(wd, wall.data(), wall.size() * sizeof(double4), hipMemcpyHostToDevice, s));
+  launch_ell_normals(s, c->md, (int32_t)wall.size(), wd, b.nrm);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  dfree(c, wd);
+  return PDF_OK;
+}
+
 template <typename T>
 pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt, const double *cfl) {
   const int32_t ne = c->md.ne;
@@ -238,6 +299,13 @@ pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt, const double *cfl
     mark(c, 0);
     if (c->params.model == PDF_MODEL_GLM && c->params.wp_source == PDF_WP_LOCAL)
       launch_local_wp(c->stream, c->md, c->model, c->stats_cur, c->wp);
+    if (c->params.model == PDF_MODEL_GLM && c->params.wp_source == PDF_WP_ELLIPTIC) {
+      // the local right-hand side, then the solve from the previous wp
+      launch_local_wp(c->stream, c->md, c->model, c->stats_cur, c->ell.f);
+      c->ell_iters += (uint64_t)launch_ell_solve(c->stream, c->md, c->model, c->ell, c->stats_cur, c->ell.f, c->wp,
+                                                 c->params.ell_tol, c->params.ell_maxit);
+      HIPCHK(c, hipGetLastError());
+    }
     const bool shape = c->model.stats_mode == PDF_STATS_SHAPE;
     if (shape) {
       launch_elem_prep_shape<T>(c->stream, c->md, c->model, c->stats_cur,
@@ -315,6 +383,11 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   if (params->stats_mode != PDF_STATS_ELEM && params->stats_mode != PDF_STATS_SHAPE) return PDF_E_INVALID_ARG;
   if (params->min_ppe < 0 || params->min_ppe > 64) return PDF_E_INVALID_ARG;
   if (params->tm_mode < PDF_TM_CPHI || params->tm_mode > PDF_TM_SOURCE) return PDF_E_INVALID_ARG;
+  if (params->wp_source < PDF_WP_INPUT || params->wp_source > PDF_WP_ELLIPTIC) return PDF_E_INVALID_ARG;
+  if (params->model == PDF_MODEL_GLM && params->wp_source == PDF_WP_ELLIPTIC &&
+      (params->ell_maxit < 1 || params->ell_maxit > 100000 || !(params->ell_tol > 0.0) ||
+       !std::isfinite(params->ell_tol)))
+    return PDF_E_INVALID_ARG;
   // wall functions replace the viscous terms of the particle equations and
   // need the viscosity of the log law
   bool has_wallfn = false;
@@ -632,6 +705,15 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   md.cond_min = params->cond_min;
   md.pad = 0;
   md.nu_wall = params->nu_wall;
+  md.CL = params->CL;
+  md.Ceta = params->Ceta;
+  if (params->model == PDF_MODEL_GLM && params->wp_source == PDF_WP_ELLIPTIC) {
+    const pdf_status es = ell_setup(c, mesh);
+    if (es != PDF_OK) {
+      pdf_destroy(c);
+      return es;
+    }
+  }
   KArgs hka;
   hka.m = c->md;
   hka.md = c->model;
@@ -755,6 +837,29 @@ pdf_status pdf_advance_cfl(pdf_ctx *c, int32_t nsteps, double c_cfl, double dt_m
   return PDF_OK;
 }
 
+pdf_status pdf_get_nodal_field(pdf_ctx *c, int32_t field, double *data, int32_t on_device) {
+  if (!c || !data) return PDF_E_INVALID_ARG;
+  const size_t nn = (size_t)c->md.nn;
+  const double *src;
+  size_t nf;
+  if (field == PDF_FIELD_STATS) {
+    src = c->latest;
+    nf = PDF_NSTAT;
+  } else if (field == PDF_FIELD_WP) {
+    src = c->wp;
+    nf = 9;
+  } else if (field == PDF_FIELD_GRADP) {
+    src = c->gradp;
+    nf = 2;
+  } else {
+    return fail(c, PDF_E_INVALID_ARG, "unknown field id");
+  }
+  HIPCHK(c, hipMemcpyAsync(data, src, nf * nn * sizeof(double),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  if (!on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PDF_OK;
+}
+
 pdf_status pdf_estimate_stats(pdf_ctx *c, double *nodal, double *elem, int32_t on_device) {
   if (!c || (!nodal && !elem)) return PDF_E_INVALID_ARG;
   if (!c->seeded) return fail(c, PDF_E_STATE, "no particles");
@@ -861,6 +966,8 @@ pdf_status pdf_get_counters(pdf_ctx *c, uint64_t *out, int32_t n, int32_t reset)
   HIPCHK(c, hipMemcpyAsync(h, c->cnt, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   h[PDF_CNT_STEPS] = c->step;
+  h[PDF_CNT_ELL_ITERS] = c->ell_iters;
+  if (reset) c->ell_iters = 0;
   for (int i = 0; i < n; ++i) out[i] = h[i];
   if (reset) {
     HIPCHK(c, hipMemsetAsync(c->cnt, 0, sizeof(h), c->stream));

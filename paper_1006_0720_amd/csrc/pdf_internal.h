@@ -96,6 +96,7 @@ struct ModelDev {
   int32_t mix_model, cond_nu, cond_nv, cond_nw, cond_min, pad;
   double C0, C1, C2, C3, C4, CT, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
   double src_x, src_y, src_r, Cs, Ct, nu_wall;
+  double CL, Ceta;  // eq:L
 };
 
 // Mesh and model parameters of the particle kernel, kept in device memory and
@@ -117,6 +118,24 @@ struct RedistBuf {
   size_t temp_bytes = 0;
 };
 bool redist_alloc(RedistBuf &b, int32_t ne, int64_t np, void *(*alloc)(size_t, void *), void *user);
+
+// elliptic relaxation for wp_ij: per-element L^2 classes and wall normals,
+// Dirichlet flags and normals per node, conjugate-gradient vectors ([9][nn])
+// and scalars
+struct EllBuf {
+  double4 *L2 = nullptr;
+  double2 *nrm = nullptr, *dnv = nullptr;
+  int8_t *dir = nullptr;
+  double *f = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *diag = nullptr;
+  double *scal = nullptr;
+  int *stop = nullptr;
+};
+void launch_ell_normals(hipStream_t s, const MeshDev &m, int32_t nw, const double4 *wall, double2 *nrm);
+// solves into x ([9][nn], warm start; wall values set), from the right-hand
+// side f ([9][nn]); returns the iterations taken (the host checks convergence
+// every 8 iterations, so the call waits for the stream)
+int launch_ell_solve(hipStream_t s, const MeshDev &m, const ModelDev &md, const EllBuf &b, const double *S,
+                     const double *f, double *x, double tol, int maxit);
 
 // velocity-conditioned scalar means (eq:IECM): per-element particle lists and
 // the result cm (T[np], storage order)
