@@ -216,6 +216,7 @@ pdf_status ell_setup(pdf_ctx *c, const pdf_mesh_desc *mesh) {
   b.dnv = (double2 *)dalloc(c, (size_t)nn * sizeof(double2));
   b.dir = (int8_t *)dalloc(c, (size_t)nn);
   b.f = (double *)dalloc(c, v9);
+  b.x = (double *)dalloc(c, v9);
   b.r = (double *)dalloc(c, v9);
   b.z = (double *)dalloc(c, v9);
   b.p = (double *)dalloc(c, v9);
@@ -223,10 +224,31 @@ pdf_status ell_setup(pdf_ctx *c, const pdf_mesh_desc *mesh) {
   b.diag = (double *)dalloc(c, v9);
   b.scal = (double *)dalloc(c, (size_t)(18 * (c->params.ell_maxit + 1)) * sizeof(double));
   b.stop = (int *)dalloc(c, 256);
-  if (!b.L2 || !b.nrm || !b.dnv || !b.dir || !b.f || !b.r || !b.z || !b.p || !b.q || !b.diag || !b.scal || !b.stop)
+  if (!b.L2 || !b.nrm || !b.dnv || !b.dir || !b.f || !b.x || !b.r || !b.z || !b.p || !b.q || !b.diag || !b.scal ||
+      !b.stop)
     return fail(c, PDF_E_OOM, "elliptic relaxation buffers");
   const double *xy = mesh->node_xy;
   const int32_t *en = mesh->elem_nodes, *master = mesh->node_master;
+  // CSR sparsity over the master nodes: the masters of the elements around each
+  std::vector<std::vector<int32_t>> adj((size_t)nn);
+  for (int32_t e = 0; e < ne; ++e)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) adj[master[en[3 * e + i]]].push_back(master[en[3 * e + j]]);
+  std::vector<int32_t> row_off((size_t)nn + 1, 0), cols;
+  for (int32_t n = 0; n < nn; ++n) {
+    std::vector<int32_t> &r = adj[n];
+    std::sort(r.begin(), r.end());
+    r.erase(std::unique(r.begin(), r.end()), r.end());
+    row_off[n + 1] = row_off[n] + (int32_t)r.size();
+    cols.insert(cols.end(), r.begin(), r.end());
+  }
+  adj.clear();
+  const size_t nnz = cols.size();
+  b.mv = (double *)dalloc(c, (nnz + 1) * sizeof(double));
+  b.av = (double4 *)dalloc(c, (nnz + 1) * sizeof(double4));
+  if (!b.mv || !b.av || !upload(c, row_off, (const int32_t **)&b.row_off) ||
+      !upload(c, cols, (const int32_t **)&b.cols))
+    return fail(c, PDF_E_OOM, "elliptic relaxation matrix");
   std::vector<double4> wall;
   std::vector<double2> dn((size_t)nn, make_double2(0.0, 0.0));
   std::vector<int8_t> dir((size_t)nn, 0);
@@ -249,6 +271,9 @@ pdf_status ell_setup(pdf_ctx *c, const pdf_mesh_desc *mesh) {
       dn[n].x /= l;
       dn[n].y /= l;
     }
+  // row roles: 0 a free master row, 1 a wall (Dirichlet) master row, 2 no row
+  for (int32_t n = 0; n < nn; ++n)
+    if (master[n] != n) dir[n] = 2;
   hipStream_t s = c->stream;
   HIPCHK(c, hipMemcpyAsync(b.dnv, dn.data(), dn.size() * sizeof(double2), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(b.dir, dir.data(), dir.size(), hipMemcpyHostToDevice, s));

@@ -12,10 +12,11 @@
 // no-slip wall edge closest to the element's centroid; L2 = 0 where eps <= 0.
 // Rows of nodes on no-slip walls hold the Dirichlet values; the conjugate
 // gradients run on the other rows (the search directions vanish on the wall
-// rows).  The operator is applied matrix-free: every master node gathers the
-// contributions of the elements around it (no atomics), so the products do
-// not depend on scheduling; the dot products are block sums added with
-// atomics.
+// rows).  Each solve assembles the CSR values of the mass matrix and of the
+// four L2 classes row by row (every master node gathers the elements around
+// it, no atomics); the iteration vectors are node-major ([nn][9]) so that a
+// column's nine components are one contiguous read; the dot products are
+// block sums added with atomics.
 #include <hip/hip_runtime.h>
 
 #include "pdf_internal.h"
@@ -97,42 +98,49 @@ __global__ __launch_bounds__(NB) void k_ell_elem(MeshDev m, ModelDev md, const d
   L2[e] = out;
 }
 
-// element matrices: mass (A/12)(1 + delta) and stiffness A grad N_a . grad N_b
-__device__ __forceinline__ void elem_ab(const MeshDev &m, int32_t e, int la, int lb, double &M, double &K) {
-  const double *d = m.dN + 6 * (size_t)e;
-  const ElemGeo g = m.geo[e];
-  const double A = 0.5 * ((g.x[1] - g.x[0]) * (g.y[2] - g.y[0]) - (g.x[2] - g.x[0]) * (g.y[1] - g.y[0]));
-  M = A / 12.0 * (la == lb ? 2.0 : 1.0);
-  K = A * (d[la] * d[lb] + d[3 + la] * d[3 + lb]);
+// element mass (A/12)(1 + delta) and stiffness A grad N_a . grad N_b
+__device__ __forceinline__ double elem_area(const ElemGeo &g) {
+  return 0.5 * ((g.x[1] - g.x[0]) * (g.y[2] - g.y[0]) - (g.x[2] - g.x[0]) * (g.y[1] - g.y[0]));
 }
 
 __device__ __forceinline__ double l2_of(const double4 &v, int cls) {
   return cls == 0 ? v.x : (cls == 1 ? v.y : (cls == 2 ? v.z : v.w));
 }
 
-// y_c(a) = sum over the elements around master a of their rows of a:
-// (M + L2 K) x (mass=true) or M x alone (mass-only right-hand side)
-__device__ __forceinline__ void gather_row(const MeshDev &m, const double4 *L2, int32_t a, const double *x,
-                                           bool mass_only, double y[9], double *dg) {
-  const int nn = m.nn;
-  for (int c = 0; c < 9; ++c) y[c] = 0.0;
-  if (dg)
-    for (int c = 0; c < 9; ++c) dg[c] = 0.0;
+// the CSR values of row a (a master node): the mass matrix and, for the four
+// L2 classes, M + L2 K, gathered from the elements around a (the row is this
+// thread's alone, so no atomics)
+__global__ __launch_bounds__(NB) void k_ell_assemble(MeshDev m, const double4 *L2, const int32_t *row_off,
+                                                     const int32_t *cols, double *mv, double4 *av) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.n_masters) return;
+  const int32_t a = m.masters[t];
+  const int32_t j0 = row_off[a], j1 = row_off[a + 1];
+  for (int32_t j = j0; j < j1; ++j) {
+    mv[j] = 0.0;
+    av[j] = make_double4(0.0, 0.0, 0.0, 0.0);
+  }
   for (int32_t i = m.m2e_off[a]; i < m.m2e_off[a + 1]; ++i) {
     const int32_t e = m.m2e[i];
+    const ElemGeo g = m.geo[e];
+    const double A = elem_area(g);
+    const double *d = m.dN + 6 * (size_t)e;
     const double4 l2 = L2[e];
     const int32_t qk[3] = {m.mnode[3 * e], m.mnode[3 * e + 1], m.mnode[3 * e + 2]};
     for (int la = 0; la < 3; ++la) {
       if (qk[la] != a) continue;
       for (int lb = 0; lb < 3; ++lb) {
-        double M, K;
-        elem_ab(m, e, la, lb, M, K);
-        const int32_t qb = qk[lb];
-        for (int c = 0; c < 9; ++c) {
-          const double A = mass_only ? M : M + l2_of(l2, ell_class(c)) * K;
-          y[c] += A * x[(size_t)c * nn + qb];
-          if (dg && qb == a) dg[c] += M + l2_of(l2, ell_class(c)) * K;
-        }
+        int32_t j = j0;
+        while (j + 1 < j1 && cols[j] != qk[lb]) ++j;  // the column is in the row by construction
+        const double M = A / 12.0 * (la == lb ? 2.0 : 1.0);
+        const double K = A * (d[la] * d[lb] + d[3 + la] * d[3 + lb]);
+        mv[j] += M;
+        double4 v = av[j];
+        v.x += M + l2.x * K;
+        v.y += M + l2.y * K;
+        v.z += M + l2.z * K;
+        v.w += M + l2.w * K;
+        av[j] = v;
       }
     }
   }
@@ -153,29 +161,56 @@ __device__ __forceinline__ void block_add9(const double v[9], double *dst) {
   }
 }
 
-// right-hand side, Jacobi diagonal, initial residual (the wall values are
-// already in x), preconditioned residual and first search direction;
-// rz0 += r.z, bb += b.(b / diag)
-__global__ __launch_bounds__(NB) void k_ell_start(MeshDev m, const double *f, const double4 *L2, const int8_t *dir,
-                                                  const double *x, double *r, double *z, double *p, double *diag,
-                                                  double *rz0, double *bb) {
+// the vectors of the iteration are node-major, [nn][9]
+// wall rows: the Dirichlet values in x, zero residual and direction, unit
+// diagonal
+__global__ __launch_bounds__(NB) void k_ell_start(MeshDev m, ModelDev md, const double *S, const int8_t *dir,
+                                                  const double2 *dnv, double *x, double *r, double *z, double *p,
+                                                  double *diag) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.n_masters) return;
+  const int nn = m.nn;
+  const int32_t a = m.masters[t];
+  if (dir[a] == 0) return;
+  const double k = k_of(S, nn, a, md.k_floor);
+  const double Om = S[3 * nn + a];
+  const double eps = Om * (k + md.nu * md.CT * md.CT * Om);
+  const double n[3] = {dnv[a].x, dnv[a].y, 0.0};
+  for (int c = 0; c < 9; ++c) {
+    const size_t o = 9 * (size_t)a + c;
+    x[o] = -4.5 * eps * n[c / 3] * n[c % 3];
+    r[o] = z[o] = p[o] = 0.0;
+    diag[o] = 1.0;
+  }
+}
+
+// b = M f, r = b - A x, z = r / diag, p = z on the free rows (every x, wall
+// rows included, in place); rz0 += r.z, bb += b.(b / diag)
+__global__ __launch_bounds__(NB) void k_ell_resid(MeshDev m, const double *f, const int8_t *dir,
+                                                  const int32_t *row_off, const int32_t *cols, const double *mv,
+                                                  const double4 *av, const double *x, double *r, double *z,
+                                                  double *p, double *diag, double *rz0, double *bb) {
   const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   double part[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, pb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (t < m.n_masters) {
     const int nn = m.nn;
     const int32_t a = m.masters[t];
-    if (dir[a]) {
-      for (int c = 0; c < 9; ++c) {
-        const size_t o = (size_t)c * nn + a;
-        r[o] = z[o] = p[o] = 0.0;
-        diag[o] = 1.0;
+    if (dir[a] == 0) {
+      double b[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ax[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, dg[9];
+      for (int32_t j = row_off[a]; j < row_off[a + 1]; ++j) {
+        const int32_t q = cols[j];
+        const double M = mv[j];
+        const double4 v = av[j];
+        const double *xq = x + 9 * (size_t)q;
+        for (int c = 0; c < 9; ++c) {
+          const double A = l2_of(v, ell_class(c));
+          b[c] += M * f[(size_t)c * nn + q];
+          ax[c] += A * xq[c];
+          if (q == a) dg[c] = A;
+        }
       }
-    } else {
-      double b[9], ax[9], dg[9];
-      gather_row(m, L2, a, f, true, b, nullptr);
-      gather_row(m, L2, a, x, false, ax, dg);
       for (int c = 0; c < 9; ++c) {
-        const size_t o = (size_t)c * nn + a;
+        const size_t o = 9 * (size_t)a + c;
         const double rr = b[c] - ax[c];
         const double zz = rr / dg[c];
         r[o] = rr;
@@ -192,85 +227,73 @@ __global__ __launch_bounds__(NB) void k_ell_start(MeshDev m, const double *f, co
   block_add9(pb, bb);
 }
 
-// Dirichlet values on the wall rows (before the residual is formed)
-__global__ __launch_bounds__(NB) void k_ell_walls(MeshDev m, ModelDev md, const double *S, const int8_t *dir,
-                                                  const double2 *dnv, double *x) {
-  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m.n_masters) return;
-  const int nn = m.nn;
-  const int32_t a = m.masters[t];
-  if (!dir[a]) return;
-  const double k = k_of(S, nn, a, md.k_floor);
-  const double Om = S[3 * nn + a];
-  const double eps = Om * (k + md.nu * md.CT * md.CT * Om);
-  const double n[3] = {dnv[a].x, dnv[a].y, 0.0};
-  for (int c = 0; c < 9; ++c) x[(size_t)c * nn + a] = -4.5 * eps * n[c / 3] * n[c % 3];
-}
-
 // q = A p on the free rows; pq += p.q
-__global__ __launch_bounds__(NB) void k_ell_apply(MeshDev m, const double4 *L2, const int8_t *dir, const double *p,
-                                                  double *q, double *pq, const int *stop) {
+__global__ __launch_bounds__(NB) void k_ell_apply(MeshDev m, const int8_t *dir, const int32_t *row_off,
+                                                  const int32_t *cols, const double4 *av, const double *p, double *q,
+                                                  double *pq, const int *stop) {
   if (*stop) return;
   const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   double part[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (t < m.n_masters) {
-    const int nn = m.nn;
     const int32_t a = m.masters[t];
-    if (!dir[a]) {
-      double y[9];
-      gather_row(m, L2, a, p, false, y, nullptr);
-      for (int c = 0; c < 9; ++c) {
-        q[(size_t)c * nn + a] = y[c];
-        part[c] = p[(size_t)c * nn + a] * y[c];
+    double y[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (dir[a] == 0) {
+      for (int32_t j = row_off[a]; j < row_off[a + 1]; ++j) {
+        const double4 v = av[j];
+        const double *pq_ = p + 9 * (size_t)cols[j];
+        const double cl[4] = {v.x, v.y, v.z, v.w};
+        for (int c = 0; c < 9; ++c) y[c] += cl[ell_class(c)] * pq_[c];
       }
-    } else {
-      for (int c = 0; c < 9; ++c) q[(size_t)c * nn + a] = 0.0;
+      for (int c = 0; c < 9; ++c) part[c] = p[9 * (size_t)a + c] * y[c];
     }
+    for (int c = 0; c < 9; ++c) q[9 * (size_t)a + c] = y[c];
   }
   block_add9(part, pq);
 }
 
-// x += alpha p, r -= alpha q, z = r / diag; rz_next += r.z
-__global__ __launch_bounds__(NB) void k_ell_update(MeshDev m, const int8_t *dir, const double *p, const double *q,
-                                                   const double *diag, double *x, double *r, double *z,
-                                                   const double *rz, const double *pq, double *rz_next,
-                                                   const int *stop) {
+// x += alpha p, r -= alpha q, z = r / diag; rz_next += r.z.  Over the vector
+// entries (node-major: entry i is node i / 9, component i % 9) with a grid-
+// stride loop whose block size and stride are multiples of 9, so that a thread
+// keeps one component, every access is coalesced, and each block adds nine
+// sums; only the free rows (role 0) change
+constexpr int NB9 = 252;
+
+__global__ __launch_bounds__(NB9) void k_ell_update(int64_t n9, const int8_t *role, const double *p, const double *q,
+                                                    const double *diag, double *x, double *r, double *z,
+                                                    const double *rz, const double *pq, double *rz_next,
+                                                    const int *stop) {
   if (*stop) return;
-  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  double part[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  if (t < m.n_masters) {
-    const int nn = m.nn;
-    const int32_t a = m.masters[t];
-    if (!dir[a]) {
-      for (int c = 0; c < 9; ++c) {
-        const double alpha = (pq[c] != 0.0) ? rz[c] / pq[c] : 0.0;
-        const size_t o = (size_t)c * nn + a;
-        x[o] += alpha * p[o];
-        const double rr = r[o] - alpha * q[o];
-        r[o] = rr;
-        const double zz = rr / diag[o];
-        z[o] = zz;
-        part[c] = rr * zz;
-      }
-    }
+  __shared__ double part[NB9];
+  const int c = threadIdx.x % 9;
+  const double alpha = (pq[c] != 0.0) ? rz[c] / pq[c] : 0.0;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * NB9 + threadIdx.x; i < n9; i += (int64_t)gridDim.x * NB9) {
+    if (role[i / 9] != 0) continue;
+    x[i] += alpha * p[i];
+    const double rr = r[i] - alpha * q[i];
+    r[i] = rr;
+    const double zz = rr / diag[i];
+    z[i] = zz;
+    acc += rr * zz;
   }
-  block_add9(part, rz_next);
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < 9) {
+    double sum = 0.0;
+    for (int k = threadIdx.x; k < NB9; k += 9) sum += part[k];
+    atomicAdd(&rz_next[threadIdx.x], sum);
+  }
 }
 
-// p = z + beta p with beta = rz_next / rz
-__global__ __launch_bounds__(NB) void k_ell_dir(MeshDev m, const int8_t *dir, const double *z, double *p,
+// p = z + beta p with beta = rz_next / rz, per entry
+__global__ __launch_bounds__(NB) void k_ell_dir(int64_t n9, const int8_t *role, const double *z, double *p,
                                                 const double *rz, const double *rz_next, const int *stop) {
   if (*stop) return;
-  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m.n_masters) return;
-  const int nn = m.nn;
-  const int32_t a = m.masters[t];
-  if (dir[a]) return;
-  for (int c = 0; c < 9; ++c) {
-    const double beta = (rz[c] != 0.0) ? rz_next[c] / rz[c] : 0.0;
-    const size_t o = (size_t)c * nn + a;
-    p[o] = z[o] + beta * p[o];
-  }
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n9 || role[i / 9] != 0) return;
+  const int c = (int)(i % 9);
+  const double beta = (rz[c] != 0.0) ? rz_next[c] / rz[c] : 0.0;
+  p[i] = z[i] + beta * p[i];
 }
 
 // stop once every component's preconditioned residual r.D^-1 r is below tol^2
@@ -282,12 +305,20 @@ __global__ void k_ell_check(const double *bb, const double *rz, double tol2, int
   if (done) *stop = iters + 1;
 }
 
-// masters to all nodes
-__global__ __launch_bounds__(NB) void k_ell_slaves(MeshDev m, double *x) {
+// node-major x to the component-major wp, masters then their identified nodes
+__global__ __launch_bounds__(NB) void k_ell_out(MeshDev m, const double *x, double *wp) {
+  const int32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= m.nn) return;
+  const int32_t q = m.master[n];
+  for (int c = 0; c < 9; ++c) wp[(size_t)c * m.nn + n] = x[9 * (size_t)q + c];
+}
+
+// component-major warm start to node-major (masters)
+__global__ __launch_bounds__(NB) void k_ell_in(MeshDev m, const double *wp, double *x) {
   const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m.n_slaves) return;
-  const int32_t n = m.slaves[t], q = m.slave_master[t];
-  for (int c = 0; c < 9; ++c) x[(size_t)c * m.nn + n] = x[(size_t)c * m.nn + q];
+  if (t >= m.n_masters) return;
+  const int32_t a = m.masters[t];
+  for (int c = 0; c < 9; ++c) x[9 * (size_t)a + c] = wp[(size_t)c * m.nn + a];
 }
 
 }  // namespace
@@ -297,17 +328,24 @@ void launch_ell_normals(hipStream_t s, const MeshDev &m, int32_t nw, const doubl
 }
 
 int launch_ell_solve(hipStream_t s, const MeshDev &m, const ModelDev &md, const EllBuf &b, const double *S,
-                     const double *f, double *x, double tol, int maxit) {
+                     const double *f, double *wp, double tol, int maxit) {
   const unsigned gm = (unsigned)((m.n_masters + NB - 1) / NB);
   const unsigned ge = (unsigned)((m.ne + NB - 1) / NB);
+  const unsigned gn = (unsigned)((m.nn + NB - 1) / NB);
+  const int64_t n9 = 9 * (int64_t)m.nn;
+  const unsigned g9 = (unsigned)((n9 + NB - 1) / NB);
+  const int64_t gu_ = (n9 + NB9 - 1) / NB9;
+  const unsigned gu = (unsigned)(gu_ < 2048 ? gu_ : 2048);
   // scal: [0, 9) rz0, [9, 18) bb, then per iteration k: pq at 18 + 18k, the
   // next rz at 27 + 18k
   (void)hipMemsetAsync(b.scal, 0, (size_t)(18 * (maxit + 1)) * sizeof(double), s);
   (void)hipMemsetAsync(b.stop, 0, sizeof(int), s);
   hipLaunchKernelGGL(k_ell_elem, dim3(ge), dim3(NB), 0, s, m, md, S, b.nrm, b.L2);
-  hipLaunchKernelGGL(k_ell_walls, dim3(gm), dim3(NB), 0, s, m, md, S, b.dir, b.dnv, x);
-  hipLaunchKernelGGL(k_ell_start, dim3(gm), dim3(NB), 0, s, m, f, b.L2, b.dir, x, b.r, b.z, b.p, b.diag, b.scal,
-                     b.scal + 9);
+  hipLaunchKernelGGL(k_ell_assemble, dim3(gm), dim3(NB), 0, s, m, b.L2, b.row_off, b.cols, b.mv, b.av);
+  hipLaunchKernelGGL(k_ell_in, dim3(gm), dim3(NB), 0, s, m, wp, b.x);
+  hipLaunchKernelGGL(k_ell_start, dim3(gm), dim3(NB), 0, s, m, md, S, b.dir, b.dnv, b.x, b.r, b.z, b.p, b.diag);
+  hipLaunchKernelGGL(k_ell_resid, dim3(gm), dim3(NB), 0, s, m, f, b.dir, b.row_off, b.cols, b.mv, b.av, b.x, b.r,
+                     b.z, b.p, b.diag, b.scal, b.scal + 9);
   const double *rz0 = b.scal, *bb = b.scal + 9;
   hipLaunchKernelGGL(k_ell_check, dim3(1), dim3(64), 0, s, bb, rz0, tol * tol, 0, b.stop);
   int it = 0;
@@ -318,17 +356,17 @@ int launch_ell_solve(hipStream_t s, const MeshDev &m, const ModelDev &md, const 
       const double *rz = it == 0 ? rz0 : b.scal + 27 + 18 * (it - 1);
       double *pq = b.scal + 18 + 18 * it;
       double *rzn = b.scal + 27 + 18 * it;
-      hipLaunchKernelGGL(k_ell_apply, dim3(gm), dim3(NB), 0, s, m, b.L2, b.dir, b.p, b.q, pq, b.stop);
-      hipLaunchKernelGGL(k_ell_update, dim3(gm), dim3(NB), 0, s, m, b.dir, b.p, b.q, b.diag, x, b.r, b.z, rz, pq,
-                         rzn, b.stop);
+      hipLaunchKernelGGL(k_ell_apply, dim3(gm), dim3(NB), 0, s, m, b.dir, b.row_off, b.cols, b.av, b.p, b.q, pq,
+                         b.stop);
+      hipLaunchKernelGGL(k_ell_update, dim3(gu), dim3(NB9), 0, s, n9, b.dir, b.p, b.q, b.diag, b.x, b.r, b.z, rz,
+                         pq, rzn, b.stop);
       hipLaunchKernelGGL(k_ell_check, dim3(1), dim3(64), 0, s, bb, rzn, tol * tol, it + 1, b.stop);
-      hipLaunchKernelGGL(k_ell_dir, dim3(gm), dim3(NB), 0, s, m, b.dir, b.z, b.p, rz, rzn, b.stop);
+      hipLaunchKernelGGL(k_ell_dir, dim3(g9), dim3(NB), 0, s, n9, b.dir, b.z, b.p, rz, rzn, b.stop);
     }
     (void)hipMemcpyAsync(&stop_host, b.stop, sizeof(int), hipMemcpyDeviceToHost, s);
     (void)hipStreamSynchronize(s);
   }
-  if (m.n_slaves > 0)
-    hipLaunchKernelGGL(k_ell_slaves, dim3((m.n_slaves + NB - 1) / NB), dim3(NB), 0, s, m, x);
+  hipLaunchKernelGGL(k_ell_out, dim3(gn), dim3(NB), 0, s, m, b.x, wp);
   return stop_host > 0 ? stop_host - 1 : it;
 }
 

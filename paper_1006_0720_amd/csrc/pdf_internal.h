@@ -125,17 +125,21 @@ bool redist_alloc(RedistBuf &b, int32_t ne, int64_t np, void *(*alloc)(size_t, v
 struct EllBuf {
   double4 *L2 = nullptr;
   double2 *nrm = nullptr, *dnv = nullptr;
-  int8_t *dir = nullptr;
-  double *f = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *diag = nullptr;
+  int8_t *dir = nullptr;                        // row role: 0 free master, 1 wall master, 2 not a master
+  int32_t *row_off = nullptr, *cols = nullptr;  // CSR over master nodes (rows of other nodes empty)
+  double *mv = nullptr;                         // mass matrix values
+  double4 *av = nullptr;                        // M + L2 K for the four L2 classes
+  double *f = nullptr;                          // local right-hand side, [9][nn]
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *diag = nullptr;  // [nn][9]
   double *scal = nullptr;
   int *stop = nullptr;
 };
 void launch_ell_normals(hipStream_t s, const MeshDev &m, int32_t nw, const double4 *wall, double2 *nrm);
-// solves into x ([9][nn], warm start; wall values set), from the right-hand
-// side f ([9][nn]); returns the iterations taken (the host checks convergence
-// every 8 iterations, so the call waits for the stream)
+// solves into wp ([9][nn], also the warm start), from the right-hand side f
+// ([9][nn]); returns the iterations taken (the host checks convergence every
+// 8 iterations, so the call waits for the stream)
 int launch_ell_solve(hipStream_t s, const MeshDev &m, const ModelDev &md, const EllBuf &b, const double *S,
-                     const double *f, double *x, double tol, int maxit);
+                     const double *f, double *wp, double tol, int maxit);
 
 // velocity-conditioned scalar means (eq:IECM): per-element particle lists and
 // the result cm (T[np], storage order)
