@@ -202,6 +202,9 @@ class Oracle:
         self.cp = _params(self.params, self.store_fp32)
         nn = mesh.n_nodes
         self.gradp = None if gradp is None else np.ascontiguousarray(gradp, np.float64).reshape(2, nn)
+        # pressure projection: the imposed gradient, the solved pressure P'
+        self.gradp_in = np.zeros((2, nn)) if self.gradp is None else self.gradp.copy()
+        self.Pp = np.zeros(nn)
         self.wp_input = None if wp is None else np.ascontiguousarray(wp, np.float64).reshape(9, nn)
         self.stats = np.zeros((NSTAT, nn))
         self.elem_stats = None
@@ -287,8 +290,27 @@ class Oracle:
                              self.seed_value, self.step_index, float(dt), mk,
                              _p(self.counters, C.c_uint64))
         self.step_index += 1
+        if int(self.params.get("proj", 0)):
+            self._project(dt)
         self.estimate(into_stats=not self.params["frozen"])
         return lost
+
+    def _project(self, dt):
+        """eq:pressure-projection-smooth from the predicted statistics, then
+        eq:velocity-correction on the particles (oracle/projection.py)."""
+        from oracle import projection as PR
+        m = self.mesh
+        est = self.estimate(into_stats=False)
+        dP = PR.solve_dp(m, est[0], est[1], self.Pp, dt, float(self.params.get("Cp", 1e-3)))
+        g = PR.elem_gradient(m, dP)
+        u = self.state[2] - dt * g[self.elem, 0]
+        v = self.state[3] - dt * g[self.elem, 1]
+        if self.store_fp32:
+            u, v = u.astype(np.float32).astype(np.float64), v.astype(np.float32).astype(np.float64)
+        self.state[2], self.state[3] = u, v
+        self.Pp = self.Pp + dP
+        self.gradp = np.ascontiguousarray(self.gradp_in + PR.node_gradient(m, self.Pp))
+        self.last_dp = dP
 
     def cond_means(self):
         """<phi|V> of every particle from the current state (App. B binning)."""
