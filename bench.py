@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--wp", default="local", choices=["local", "elliptic"],
                     help="tensor wp_ij of the generalized Langevin model: the local right-hand side of the "
                          "elliptic relaxation, or its finite-element solve every step")
+    ap.add_argument("--proj", action="store_true",
+                    help="the stabilized mean-pressure projection every step (statistics fed back)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
@@ -183,6 +185,9 @@ def main():
     if args.wp == "elliptic":
         # solved to 1e-6 of the right-hand side, far below the statistical noise of its input
         w.params = dict(w.params, wp_source=CF.WP_ELLIPTIC, ell_tol=1e-6, ell_maxit=500)
+    if args.proj:
+        # solved to 1e-6 of the right-hand side, below the statistical noise of its input
+        w.params = dict(w.params, proj=1, Cp=1e-3, proj_tol=1e-6, proj_maxit=2000, frozen=0)
     if args.mix == "iecm":
         w.params = dict(w.params, mix_model=CF.MIX_IECM, cond_nu=5, cond_nv=5, cond_nw=5, cond_min=2)
     tsize = 4 if w.precision == "f32" else 8
@@ -240,11 +245,11 @@ def main():
                    "n_elements": w.mesh.n_elems, "n_nodes": w.mesh.n_nodes,
                    "particles_per_element": int(w.seed["ppe"]), "dt": w.dt,
                    "reorder_every": args.reorder_every, "stats_mode": args.stats_mode,
-                   "min_ppe": args.min_ppe, "mix": args.mix, "wp": args.wp},
+                   "min_ppe": args.min_ppe, "mix": args.mix, "wp": args.wp, "proj": bool(args.proj)},
         "roofline": roof,
         "phase_ms_per_step": {k: round(v / args.steps, 4) for k, v in tm.items()},
         "counters": {k: cnt[k] for k in ("lost", "brute", "fallback", "nonfinite", "empty_node", "redist",
-                                         "ell_iters")},
+                                         "ell_iters", "proj_iters")},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, w)

@@ -58,7 +58,7 @@ enum { PDF_TM_CPHI = 0, PDF_TM_KEPS = 1, PDF_TM_SOURCE = 2 }; /* micromixing tim
 enum { PDF_MIX_IEM = 0, PDF_MIX_IECM = 1 };                  /* micromixing model */
 enum { PDF_PSI_ZERO = 0, PDF_PSI_STEP_X = 1, PDF_PSI_GAUSS_X = 2, PDF_PSI_BERNOULLI = 3,
        PDF_PSI_DISC = 4 };                                    /* scalar initial conditions */
-enum { PDF_FIELD_STATS = 0, PDF_FIELD_WP = 1, PDF_FIELD_GRADP = 2 }; /* pdf_set_nodal_field ids */
+enum { PDF_FIELD_STATS = 0, PDF_FIELD_WP = 1, PDF_FIELD_GRADP = 2, PDF_FIELD_PRESSURE = 3 }; /* nodal field ids */
 enum { PDF_STATS_ELEM = 0, PDF_STATS_SHAPE = 1 };             /* statistics at particles and nodes */
 
 #define PDF_NSTAT 25     /* nodal statistics per node, see pdf_estimate_stats */
@@ -71,7 +71,8 @@ enum {
   PDF_CNT_REFLECT = 4, PDF_CNT_PERIODIC = 5, PDF_CNT_NOSLIP_B = 6, PDF_CNT_OMEGA_CLAMP = 7,
   PDF_CNT_GAMMA_FAIL = 8, PDF_CNT_EMPTY_NODE = 9, PDF_CNT_NONFINITE = 10, PDF_CNT_STEPS = 11,
   PDF_CNT_REDIST = 12, /* particles moved by the redistribution */
-  PDF_CNT_ELL_ITERS = 13 /* conjugate-gradient iterations of the elliptic relaxation */
+  PDF_CNT_ELL_ITERS = 13, /* conjugate-gradient iterations of the elliptic relaxation */
+  PDF_CNT_PROJ_ITERS = 14 /* conjugate-gradient iterations of the pressure projection */
 };
 
 /* Device allocator hook.  alloc returns device memory of at least `bytes`
@@ -168,6 +169,21 @@ typedef struct pdf_mesh_desc {
  *   cond_min     fewest particles per subgroup, 1..64 (the paper's example: 2)
  *   src_x,src_y,src_r  continuous scalar source disc: psi = 1 inside (r <= 0: none)
  *   Cs, Ct       constants of eq:micromixing-timescale-canyon (tab:constants: 0.02, 0.7)
+ *   proj         1: the stabilized mean-pressure projection every step (Ch.3, Sec. Solution
+ *                of the Eulerian equations; PDF_STATS_ELEM, statistics fed back): with
+ *                P = x.G + P' (G the PDF_FIELD_GRADP input, zero if unset), after the
+ *                velocity prediction and its estimate <U>*, K dP = -(d + Cp K P')/dt
+ *                (eq:pressure-projection-smooth in weak form: K the linear-element
+ *                stiffness matrix over the master nodes, d_a = sum_e A_e/3 div_e <U>*,
+ *                natural conditions at walls, the right-hand side's mean removed, dP of
+ *                zero mean), solved by Jacobi-preconditioned conjugate gradients to
+ *                proj_tol (preconditioned residual against the right-hand side's) in at
+ *                most proj_maxit iterations (the call waits for the stream every 8);
+ *                then every particle's velocity changes by -dt grad dP of its element
+ *                (eq:velocity-correction), P' += dP, and the next prediction uses G plus
+ *                the node average of the element gradients of P' (PDF_FIELD_GRADP then
+ *                returns that sum, PDF_FIELD_PRESSURE returns P')
+ *   Cp           stabilization constant of eq:pressure-projection-smooth (the paper: 1e-3)
  *   nu_wall      kinematic viscosity of the log law eq:Ue at PDF_BC_WALLFN edges (> 0 when
  *                the mesh has such edges).  A particle reflected at such an edge gets the
  *                wall-function condition: in the edge's frame (tangent along the edge,
@@ -183,9 +199,9 @@ typedef struct pdf_mesh_desc {
  *                (PDF_E_INVALID_ARG otherwise). */
 typedef struct pdf_model_params {
   int32_t model, wp_source, omega_source, tm_mode, frozen, wall_b, reorder_every, stats_mode;
-  int32_t min_ppe, mix_model, cond_nu, cond_nv, cond_nw, cond_min, ell_maxit;
+  int32_t min_ppe, mix_model, cond_nu, cond_nv, cond_nw, cond_min, ell_maxit, proj, proj_maxit;
   double C0, C1, C2, C3, C4, CT, CL, Ceta, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
-  double src_x, src_y, src_r, Cs, Ct, nu_wall, ell_tol;
+  double src_x, src_y, src_r, Cs, Ct, nu_wall, ell_tol, Cp, proj_tol;
 } pdf_model_params;
 
 /* Initial particle population (Ch.3, Sec. Particle-number control): ppe
@@ -221,7 +237,8 @@ pdf_status pdf_set_nodal_field(pdf_ctx *ctx, int32_t field, const double *data, 
 /* Copy a nodal field out, same ids and layouts: PDF_FIELD_STATS the latest
  * statistics, PDF_FIELD_WP the tensor wp_ij the last step used (the solution
  * of the elliptic relaxation with PDF_WP_ELLIPTIC), PDF_FIELD_GRADP the
- * mean-pressure gradient.  on_device = 0: host memory (synchronizes); 1:
+ * mean-pressure gradient (with the projection: the one the next step uses),
+ * PDF_FIELD_PRESSURE [1][n_nodes] the solved pressure P' (projection only).  on_device = 0: host memory (synchronizes); 1:
  * device memory (asynchronous). */
 pdf_status pdf_get_nodal_field(pdf_ctx *ctx, int32_t field, double *data, int32_t on_device);
 

@@ -17,12 +17,13 @@ LIB_PATH = os.environ.get("PDF_LIBRARY") or os.path.join(HERE, "libpdf.so")
 
 PDF_OK = 0
 PDF_FP64, PDF_FP32 = 0, 1
-FIELD_STATS, FIELD_WP, FIELD_GRADP = 0, 1, 2
+FIELD_STATS, FIELD_WP, FIELD_GRADP, FIELD_PRESSURE = 0, 1, 2, 3
 NSTAT = 25
 NELEMSTAT = 16
 NCOUNTERS = 16
 COUNTER_NAMES = ["walk_steps", "fallback", "brute", "lost", "reflect", "periodic", "noslip_b",
-                 "omega_clamp", "gamma_fail", "empty_node", "nonfinite", "steps", "redist", "ell_iters"]
+                 "omega_clamp", "gamma_fail", "empty_node", "nonfinite", "steps", "redist", "ell_iters",
+                 "proj_iters"]
 STATUS = {0: "PDF_OK", 1: "PDF_E_INVALID_ARG", 2: "PDF_E_BAD_MESH", 3: "PDF_E_OOM",
           4: "PDF_E_DEVICE", 5: "PDF_E_STATE", 6: "PDF_E_LOST_PARTICLE", 7: "PDF_E_NUMERIC"}
 
@@ -44,10 +45,12 @@ class MeshDesc(C.Structure):
 class ModelParams(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("model", "wp_source", "omega_source", "tm_mode", "frozen",
                                          "wall_b", "reorder_every", "stats_mode", "min_ppe", "mix_model",
-                                         "cond_nu", "cond_nv", "cond_nw", "cond_min", "ell_maxit")] + \
+                                         "cond_nu", "cond_nv", "cond_nw", "cond_min", "ell_maxit", "proj",
+                                         "proj_maxit")] + \
                [(n, C.c_double) for n in ("C0", "C1", "C2", "C3", "C4", "CT", "CL", "Ceta", "Cv",
                                           "gamma5", "Cw1", "Cw2", "Cphi", "nu", "k_floor",
-                                          "src_x", "src_y", "src_r", "Cs", "Ct", "nu_wall", "ell_tol")]
+                                          "src_x", "src_y", "src_r", "Cs", "Ct", "nu_wall", "ell_tol", "Cp",
+                                          "proj_tol")]
 
 
 # fields a parameter set may omit: ELEM statistics, no redistribution, IEM,
@@ -55,7 +58,8 @@ class ModelParams(C.Structure):
 # micromixing constants of tab:constants, no wall-function viscosity, and
 # the conjugate-gradient limits of the elliptic relaxation
 PARAM_DEFAULTS = dict(stats_mode=0, min_ppe=0, mix_model=0, cond_nu=5, cond_nv=5, cond_nw=5,
-                      cond_min=2, Cs=0.02, Ct=0.7, nu_wall=0.0, ell_maxit=500, ell_tol=1e-12)
+                      cond_min=2, Cs=0.02, Ct=0.7, nu_wall=0.0, ell_maxit=500, ell_tol=1e-12, proj=0,
+                      proj_maxit=2000, Cp=1e-3, proj_tol=1e-12)
 
 
 class SeedDesc(C.Structure):
@@ -228,7 +232,7 @@ class Context:
     # ---- outputs -------------------------------------------------------
     def nodal_field(self, field):
         """A nodal field (FIELD_STATS, FIELD_WP or FIELD_GRADP) as (nf, n_nodes)."""
-        nf = {FIELD_STATS: NSTAT, FIELD_WP: 9, FIELD_GRADP: 2}[field]
+        nf = {FIELD_STATS: NSTAT, FIELD_WP: 9, FIELD_GRADP: 2, FIELD_PRESSURE: 1}[field]
         out = np.empty((nf, self.n_nodes))
         self._chk(lib.pdf_get_nodal_field(self.h, int(field), _ptr(out), 0))
         return out

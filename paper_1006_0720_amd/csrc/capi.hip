@@ -41,6 +41,8 @@ struct pdf_ctx {
   RedistBuf rb;               // particle redistribution (min_ppe > 0)
   CondBuf cb;                 // velocity-conditioned scalar means (IECM)
   EllBuf ell;                 // elliptic relaxation (PDF_WP_ELLIPTIC)
+  ProjBuf pb;                 // pressure projection (params.proj)
+  uint64_t proj_iters = 0;    // its conjugate-gradient iterations since the last counter reset
   uint64_t ell_iters = 0;     // conjugate-gradient iterations since the last counter reset
   int32_t *offs = nullptr, *cursor = nullptr, *blocksums = nullptr;
   // particles (two buffers for the reorder)
@@ -204,6 +206,81 @@ bool cond_reserve(pdf_ctx *c) {
   return hipMemsetAsync(b.list, 0, (size_t)(c->np > 0 ? c->np : 1) * 4, c->stream) == hipSuccess;
 }
 
+// CSR sparsity over the master nodes: row a holds the masters of the
+// elements around a (sorted); rows of identified nodes are empty
+void master_csr(const pdf_mesh_desc *mesh, std::vector<int32_t> &row_off, std::vector<int32_t> &cols) {
+  const int32_t nn = mesh->n_nodes, ne = mesh->n_elems;
+  const int32_t *en = mesh->elem_nodes, *master = mesh->node_master;
+  std::vector<std::vector<int32_t>> adj((size_t)nn);
+  for (int32_t e = 0; e < ne; ++e)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) adj[master[en[3 * e + i]]].push_back(master[en[3 * e + j]]);
+  row_off.assign((size_t)nn + 1, 0);
+  cols.clear();
+  for (int32_t n = 0; n < nn; ++n) {
+    std::vector<int32_t> &r = adj[n];
+    std::sort(r.begin(), r.end());
+    r.erase(std::unique(r.begin(), r.end()), r.end());
+    row_off[n + 1] = row_off[n] + (int32_t)r.size();
+    cols.insert(cols.end(), r.begin(), r.end());
+  }
+}
+
+// pressure projection: the stiffness matrix (assembled once on the host, the
+// element entries A grad N_a . grad N_b added into the masters' rows) and the
+// buffers
+pdf_status proj_setup(pdf_ctx *c, const pdf_mesh_desc *mesh) {
+  const int32_t nn = c->md.nn, ne = c->md.ne;
+  ProjBuf &b = c->pb;
+  std::vector<int32_t> row_off, cols;
+  master_csr(mesh, row_off, cols);
+  std::vector<double> kval(cols.size(), 0.0), kdiag((size_t)nn, 1.0);
+  const double *xy = mesh->node_xy;
+  const int32_t *en = mesh->elem_nodes, *master = mesh->node_master;
+  for (int32_t e = 0; e < ne; ++e) {
+    const int32_t n0 = en[3 * e], n1 = en[3 * e + 1], n2 = en[3 * e + 2];
+    const double xBA = xy[2 * n1] - xy[2 * n0], yBA = xy[2 * n1 + 1] - xy[2 * n0 + 1];
+    const double xCA = xy[2 * n2] - xy[2 * n0], yCA = xy[2 * n2 + 1] - xy[2 * n0 + 1];
+    const double twoA = xBA * yCA - xCA * yBA, A = 0.5 * twoA;
+    const double dx[3] = {(yBA - yCA) / twoA, yCA / twoA, -yBA / twoA};
+    const double dy[3] = {(xCA - xBA) / twoA, -xCA / twoA, xBA / twoA};
+    for (int i = 0; i < 3; ++i) {
+      const int32_t qa = master[en[3 * e + i]];
+      for (int j = 0; j < 3; ++j) {
+        const int32_t qb = master[en[3 * e + j]];
+        const int32_t *r0 = cols.data() + row_off[qa], *r1 = cols.data() + row_off[qa + 1];
+        const int32_t pos = (int32_t)(std::lower_bound(r0, r1, qb) - cols.data());
+        kval[pos] += A * (dx[i] * dx[j] + dy[i] * dy[j]);
+      }
+    }
+  }
+  for (int32_t n = 0; n < nn; ++n)
+    for (int32_t j = row_off[n]; j < row_off[n + 1]; ++j)
+      if (cols[j] == n) kdiag[n] = kval[j] > 0.0 ? kval[j] : 1.0;
+  const size_t vn = (size_t)nn * sizeof(double);
+  bool ok = upload(c, row_off, (const int32_t **)&b.row_off) && upload(c, cols, (const int32_t **)&b.cols) &&
+            upload(c, kval, (const double **)&b.kval) && upload(c, kdiag, (const double **)&b.kdiag);
+  b.P = (double *)dalloc(c, vn);
+  b.dP = (double *)dalloc(c, vn);
+  b.b = (double *)dalloc(c, vn);
+  b.x = (double *)dalloc(c, vn);
+  b.r = (double *)dalloc(c, vn);
+  b.z = (double *)dalloc(c, vn);
+  b.p = (double *)dalloc(c, vn);
+  b.q = (double *)dalloc(c, vn);
+  b.ge = (double2 *)dalloc(c, (size_t)ne * sizeof(double2));
+  b.gtot = (double *)dalloc(c, 2 * vn);
+  b.scal = (double *)dalloc(c, (size_t)(2 * c->params.proj_maxit + 6) * sizeof(double));
+  b.stop = (int *)dalloc(c, 256);
+  ok = ok && b.P && b.dP && b.b && b.x && b.r && b.z && b.p && b.q && b.ge && b.gtot && b.scal && b.stop;
+  if (!ok) return fail(c, PDF_E_OOM, "pressure projection buffers");
+  HIPCHK(c, hipMemsetAsync(b.P, 0, vn, c->stream));
+  HIPCHK(c, hipMemsetAsync(b.dP, 0, vn, c->stream));
+  HIPCHK(c, hipMemsetAsync(b.gtot, 0, 2 * vn, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PDF_OK;
+}
+
 // elliptic relaxation: buffers, the nodes of no-slip edges (Dirichlet rows)
 // with the normalised sum of their edges' outward unit normals, and each
 // element's closest no-slip wall normal (computed once, on the device)
@@ -229,20 +306,8 @@ pdf_status ell_setup(pdf_ctx *c, const pdf_mesh_desc *mesh) {
     return fail(c, PDF_E_OOM, "elliptic relaxation buffers");
   const double *xy = mesh->node_xy;
   const int32_t *en = mesh->elem_nodes, *master = mesh->node_master;
-  // CSR sparsity over the master nodes: the masters of the elements around each
-  std::vector<std::vector<int32_t>> adj((size_t)nn);
-  for (int32_t e = 0; e < ne; ++e)
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) adj[master[en[3 * e + i]]].push_back(master[en[3 * e + j]]);
-  std::vector<int32_t> row_off((size_t)nn + 1, 0), cols;
-  for (int32_t n = 0; n < nn; ++n) {
-    std::vector<int32_t> &r = adj[n];
-    std::sort(r.begin(), r.end());
-    r.erase(std::unique(r.begin(), r.end()), r.end());
-    row_off[n + 1] = row_off[n] + (int32_t)r.size();
-    cols.insert(cols.end(), r.begin(), r.end());
-  }
-  adj.clear();
+  std::vector<int32_t> row_off, cols;
+  master_csr(mesh, row_off, cols);
   const size_t nnz = cols.size();
   b.mv = (double *)dalloc(c, (nnz + 1) * sizeof(double));
   b.av = (double4 *)dalloc(c, (nnz + 1) * sizeof(double4));
@@ -332,6 +397,11 @@ pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt, const double *cfl
       HIPCHK(c, hipGetLastError());
     }
     const bool shape = c->model.stats_mode == PDF_STATS_SHAPE;
+    const bool proj = c->params.proj != 0;
+    // the mean-pressure gradient of the prediction: the input, plus grad P'
+    // with the projection
+    if (proj) launch_proj_gradp(c->stream, c->md, c->pb, c->gradp_set ? c->gradp : nullptr);
+    const double *gp = proj ? c->pb.gtot : (c->gradp_set ? c->gradp : nullptr);
     if (shape) {
       launch_elem_prep_shape<T>(c->stream, c->md, c->model, c->stats_cur,
                                 c->params.model == PDF_MODEL_GLM ? c->wp : nullptr,
@@ -339,8 +409,7 @@ pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt, const double *cfl
       HIPCHK(c, hipMemsetAsync(c->nsums, 0, (size_t)c->md.nn * NSUM * sizeof(double), c->stream));
     } else {
       launch_elem_prep<T>(c->stream, c->md, c->model, c->stats_cur,
-                          c->params.model == PDF_MODEL_GLM ? c->wp : nullptr,
-                          c->gradp_set ? c->gradp : nullptr, dt, dtp, rec);
+                          c->params.model == PDF_MODEL_GLM ? c->wp : nullptr, gp, dt, dtp, rec);
       HIPCHK(c, hipMemsetAsync(c->sums, 0, (size_t)ne * NSUM * sizeof(double), c->stream));
     }
     mark(c, 1);
@@ -356,6 +425,17 @@ pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt, const double *cfl
       launch_node_stats(c->stream, c->md, c->emom, c->stats_cur, c->stats_est, c->cnt);
     }
     launch_node_derivs(c->stream, c->md, c->stats_est);
+    if (proj) {
+      // eq:pressure-projection-smooth from the predicted statistics, the
+      // correction of the particles and element means, then the statistics
+      // of the corrected particles
+      c->proj_iters += (uint64_t)launch_proj_solve<T>(c->stream, c->md, c->pb, c->stats_est, c->params.Cp, dt, dtp,
+                                                      c->params.proj_tol, c->params.proj_maxit,
+                                                      part_view<T>(c, c->cur), c->np, c->emom);
+      launch_node_stats(c->stream, c->md, c->emom, c->stats_cur, c->stats_est, c->cnt);
+      launch_node_derivs(c->stream, c->md, c->stats_est);
+      HIPCHK(c, hipGetLastError());
+    }
     if (!c->params.frozen) {
       std::swap(c->stats_cur, c->stats_est);
       c->latest = c->stats_cur;
@@ -409,6 +489,12 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   if (params->min_ppe < 0 || params->min_ppe > 64) return PDF_E_INVALID_ARG;
   if (params->tm_mode < PDF_TM_CPHI || params->tm_mode > PDF_TM_SOURCE) return PDF_E_INVALID_ARG;
   if (params->wp_source < PDF_WP_INPUT || params->wp_source > PDF_WP_ELLIPTIC) return PDF_E_INVALID_ARG;
+  if (params->proj != 0 && params->proj != 1) return PDF_E_INVALID_ARG;
+  if (params->proj &&
+      (params->stats_mode != PDF_STATS_ELEM || params->frozen || !(params->Cp >= 0.0) || !std::isfinite(params->Cp) ||
+       params->proj_maxit < 1 || params->proj_maxit > 100000 || !(params->proj_tol > 0.0) ||
+       !std::isfinite(params->proj_tol)))
+    return PDF_E_INVALID_ARG;
   if (params->model == PDF_MODEL_GLM && params->wp_source == PDF_WP_ELLIPTIC &&
       (params->ell_maxit < 1 || params->ell_maxit > 100000 || !(params->ell_tol > 0.0) ||
        !std::isfinite(params->ell_tol)))
@@ -739,6 +825,13 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
       return es;
     }
   }
+  if (params->proj) {
+    const pdf_status ps = proj_setup(c, mesh);
+    if (ps != PDF_OK) {
+      pdf_destroy(c);
+      return ps;
+    }
+  }
   KArgs hka;
   hka.m = c->md;
   hka.md = c->model;
@@ -874,8 +967,12 @@ pdf_status pdf_get_nodal_field(pdf_ctx *c, int32_t field, double *data, int32_t 
     src = c->wp;
     nf = 9;
   } else if (field == PDF_FIELD_GRADP) {
-    src = c->gradp;
+    if (c->params.proj) launch_proj_gradp(c->stream, c->md, c->pb, c->gradp_set ? c->gradp : nullptr);
+    src = c->params.proj ? c->pb.gtot : c->gradp;
     nf = 2;
+  } else if (field == PDF_FIELD_PRESSURE && c->params.proj) {
+    src = c->pb.P;
+    nf = 1;
   } else {
     return fail(c, PDF_E_INVALID_ARG, "unknown field id");
   }
@@ -992,7 +1089,8 @@ pdf_status pdf_get_counters(pdf_ctx *c, uint64_t *out, int32_t n, int32_t reset)
   HIPCHK(c, hipStreamSynchronize(c->stream));
   h[PDF_CNT_STEPS] = c->step;
   h[PDF_CNT_ELL_ITERS] = c->ell_iters;
-  if (reset) c->ell_iters = 0;
+  h[PDF_CNT_PROJ_ITERS] = c->proj_iters;
+  if (reset) c->ell_iters = c->proj_iters = 0;
   for (int i = 0; i < n; ++i) out[i] = h[i];
   if (reset) {
     HIPCHK(c, hipMemsetAsync(c->cnt, 0, sizeof(h), c->stream));

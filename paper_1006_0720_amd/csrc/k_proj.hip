@@ -1,0 +1,264 @@
+// Stabilized mean-pressure projection on gfx950 (Ch.3, Sec. Solution of the
+// Eulerian equations: eq:pressure-projection-smooth, eq:velocity-correction).
+//
+// With rho = 1 and P = x.G + P' (G the imposed gradient, P' solved), per step
+// after the velocity prediction and its estimate <U>*:
+//   K dP = -(d + C_p K P') / dt,  d_a = sum_e (A_e / 3) div_e(<U>*),
+// K the stiffness matrix over the master nodes (CSR, assembled once), natural
+// conditions at walls; the right-hand side is made compatible by removing its
+// mean and dP has zero mean over the masters.  Jacobi-preconditioned
+// conjugate gradients from zero.  Then every particle's velocity changes by
+// -dt grad(dP) of its element, the element means by the same amount (the
+// central moments are unchanged), P' += dP, and the next prediction uses G
+// plus the node average of the element gradients of P'.
+#include <hip/hip_runtime.h>
+
+#include "pdf_internal.h"
+
+namespace pdfk {
+
+namespace {
+
+constexpr int NB = 256;
+
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[NB / 64];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < NB / 64; ++w) s += red[w];
+  return s;  // valid in thread 0
+}
+
+__device__ __forceinline__ double elem_area(const ElemGeo &g) {
+  return 0.5 * ((g.x[1] - g.x[0]) * (g.y[2] - g.y[0]) - (g.x[2] - g.x[0]) * (g.y[1] - g.y[0]));
+}
+
+// b_a = -(d_a + C_p (K P')_a) / dt; bsum += b
+__global__ __launch_bounds__(NB) void k_proj_rhs(MeshDev m, const double *S, const int32_t *row_off,
+                                                 const int32_t *cols, const double *kval, const double *P,
+                                                 double Cp, double dt, const double *dtp, double *b, double *bsum) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (t < m.n_masters) {
+    const double dtv = dtp ? dtp[0] : dt;
+    const int nn = m.nn;
+    const int32_t a = m.masters[t];
+    double d = 0.0;
+    for (int32_t i = m.m2e_off[a]; i < m.m2e_off[a + 1]; ++i) {
+      const int32_t e = m.m2e[i];
+      const double *dN = m.dN + 6 * (size_t)e;
+      const int32_t qk[3] = {m.mnode[3 * e], m.mnode[3 * e + 1], m.mnode[3 * e + 2]};
+      double div = 0.0;
+      for (int k = 0; k < 3; ++k) div += dN[k] * S[qk[k]] + dN[3 + k] * S[nn + qk[k]];
+      const double w = elem_area(m.geo[e]) / 3.0 * div;
+      for (int la = 0; la < 3; ++la)
+        if (qk[la] == a) d += w;
+    }
+    double kp = 0.0;
+    for (int32_t j = row_off[a]; j < row_off[a + 1]; ++j) kp += kval[j] * P[cols[j]];
+    v = -(d + Cp * kp) / dtv;
+    b[a] = v;
+  }
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) atomicAdd(bsum, s);
+}
+
+// b -= mean(b); x = 0; r = b; z = r / diag; p = z; rz0 += r.z; bb += b.b/diag
+__global__ __launch_bounds__(NB) void k_proj_start(MeshDev m, const double *kdiag, const double *bsum, double *b,
+                                                   double *x, double *r, double *z, double *p, double *rz0,
+                                                   double *bb) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0, w = 0.0;
+  if (t < m.n_masters) {
+    const int32_t a = m.masters[t];
+    const double bv = b[a] - bsum[0] / (double)m.n_masters;
+    b[a] = bv;
+    x[a] = 0.0;
+    r[a] = bv;
+    const double zz = bv / kdiag[a];
+    z[a] = zz;
+    p[a] = zz;
+    v = bv * zz;
+    w = v;
+  }
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) atomicAdd(rz0, s);
+  __syncthreads();
+  const double s2 = block_sum(w);
+  if (threadIdx.x == 0) atomicAdd(bb, s2);
+}
+
+__global__ __launch_bounds__(NB) void k_proj_apply(MeshDev m, const int32_t *row_off, const int32_t *cols,
+                                                   const double *kval, const double *p, double *q, double *pq,
+                                                   const int *stop) {
+  if (*stop) return;
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (t < m.n_masters) {
+    const int32_t a = m.masters[t];
+    double y = 0.0;
+    for (int32_t j = row_off[a]; j < row_off[a + 1]; ++j) y += kval[j] * p[cols[j]];
+    q[a] = y;
+    v = p[a] * y;
+  }
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) atomicAdd(pq, s);
+}
+
+__global__ __launch_bounds__(NB) void k_proj_update(MeshDev m, const double *kdiag, const double *p, const double *q,
+                                                    double *x, double *r, double *z, const double *rz,
+                                                    const double *pq, double *rzn, const int *stop) {
+  if (*stop) return;
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (t < m.n_masters) {
+    const int32_t a = m.masters[t];
+    const double alpha = (pq[0] != 0.0) ? rz[0] / pq[0] : 0.0;
+    x[a] += alpha * p[a];
+    const double rr = r[a] - alpha * q[a];
+    r[a] = rr;
+    const double zz = rr / kdiag[a];
+    z[a] = zz;
+    v = rr * zz;
+  }
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) atomicAdd(rzn, s);
+}
+
+__global__ __launch_bounds__(NB) void k_proj_dir(MeshDev m, const double *z, double *p, const double *rz,
+                                                 const double *rzn, const int *stop) {
+  if (*stop) return;
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.n_masters) return;
+  const int32_t a = m.masters[t];
+  const double beta = (rz[0] != 0.0) ? rzn[0] / rz[0] : 0.0;
+  p[a] = z[a] + beta * p[a];
+}
+
+__global__ void k_proj_check(const double *bb, const double *rz, double tol2, int iters, int *stop) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || *stop) return;
+  if (!(rz[0] > tol2 * bb[0])) *stop = iters + 1;
+}
+
+// xsum += x over the masters
+__global__ __launch_bounds__(NB) void k_proj_xsum(MeshDev m, const double *x, double *xsum) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  const double v = t < m.n_masters ? x[m.masters[t]] : 0.0;
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) atomicAdd(xsum, s);
+}
+
+// dP = x - mean at every node (identified nodes from their master); P' += dP
+__global__ __launch_bounds__(NB) void k_proj_accum(MeshDev m, const double *x, const double *xsum, double *dP,
+                                                   double *P) {
+  const int32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= m.nn) return;
+  const double v = x[m.master[n]] - xsum[0] / (double)m.n_masters;
+  dP[n] = v;
+  P[n] += v;
+}
+
+// element gradient of dP; the element means of u and v shift by -dt grad dP
+__global__ __launch_bounds__(NB) void k_proj_egrad(MeshDev m, const double *dP, double dt, const double *dtp,
+                                                   double2 *ge, double *emom) {
+  const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.ne) return;
+  const double dtv = dtp ? dtp[0] : dt;
+  const double *dN = m.dN + 6 * (size_t)e;
+  double gx = 0.0, gy = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double v = dP[m.mnode[3 * e + k]];
+    gx += dN[k] * v;
+    gy += dN[3 + k] * v;
+  }
+  ge[e] = make_double2(dtv * gx, dtv * gy);
+  double *em = emom + (size_t)e * 16;
+  if (em[0] > 0.0) {
+    em[1] -= dtv * gx;
+    em[2] -= dtv * gy;
+  }
+}
+
+// eq:velocity-correction on the particles
+template <typename T>
+__global__ __launch_bounds__(NB) void k_proj_correct(PartDev<T> p, int64_t np, const double2 *ge) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const double2 g = ge[p.e[i]];
+  p.u[i] = (T)((double)p.u[i] - g.x);
+  p.v[i] = (T)((double)p.v[i] - g.y);
+}
+
+// the gradient of the next prediction: G (input, or zero) plus the average
+// over the elements around each master of the element gradients of P'
+__global__ __launch_bounds__(NB) void k_proj_gradp(MeshDev m, const double *P, const double *gin, double *gtot) {
+  const int32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= m.nn) return;
+  const int32_t a = m.master[n];
+  double gx = 0.0, gy = 0.0;
+  int c = 0;
+  for (int32_t i = m.m2e_off[a]; i < m.m2e_off[a + 1]; ++i) {
+    const int32_t e = m.m2e[i];
+    const double *dN = m.dN + 6 * (size_t)e;
+    for (int k = 0; k < 3; ++k) {
+      const double v = P[m.mnode[3 * e + k]];
+      gx += dN[k] * v;
+      gy += dN[3 + k] * v;
+    }
+    c++;
+  }
+  gtot[n] = (gin ? gin[n] : 0.0) + (c ? gx / c : 0.0);
+  gtot[m.nn + n] = (gin ? gin[m.nn + n] : 0.0) + (c ? gy / c : 0.0);
+}
+
+}  // namespace
+
+void launch_proj_gradp(hipStream_t s, const MeshDev &m, const ProjBuf &b, const double *gin) {
+  hipLaunchKernelGGL(k_proj_gradp, dim3((m.nn + NB - 1) / NB), dim3(NB), 0, s, m, b.P, gin, b.gtot);
+}
+
+template <typename T>
+int launch_proj_solve(hipStream_t s, const MeshDev &m, const ProjBuf &b, const double *S, double Cp, double dt,
+                      const double *dtp, double tol, int maxit, PartDev<T> p, int64_t np, double *emom) {
+  const unsigned gm = (unsigned)((m.n_masters + NB - 1) / NB);
+  // scal: [0] bsum, [1] rz0, [2] bb, [3] xsum, then per iteration k: pq at
+  // 4 + 2k, the next rz at 5 + 2k
+  (void)hipMemsetAsync(b.scal, 0, (size_t)(2 * maxit + 6) * sizeof(double), s);
+  (void)hipMemsetAsync(b.stop, 0, sizeof(int), s);
+  hipLaunchKernelGGL(k_proj_rhs, dim3(gm), dim3(NB), 0, s, m, S, b.row_off, b.cols, b.kval, b.P, Cp, dt, dtp, b.b,
+                     b.scal);
+  hipLaunchKernelGGL(k_proj_start, dim3(gm), dim3(NB), 0, s, m, b.kdiag, b.scal, b.b, b.x, b.r, b.z, b.p,
+                     b.scal + 1, b.scal + 2);
+  hipLaunchKernelGGL(k_proj_check, dim3(1), dim3(64), 0, s, b.scal + 2, b.scal + 1, tol * tol, 0, b.stop);
+  int it = 0, stop_host = 0;
+  while (it < maxit && !stop_host) {
+    const int chunk = (maxit - it) < 8 ? (maxit - it) : 8;
+    for (int j = 0; j < chunk; ++j, ++it) {
+      const double *rz = it == 0 ? b.scal + 1 : b.scal + 5 + 2 * (it - 1);
+      double *pq = b.scal + 4 + 2 * it, *rzn = b.scal + 5 + 2 * it;
+      hipLaunchKernelGGL(k_proj_apply, dim3(gm), dim3(NB), 0, s, m, b.row_off, b.cols, b.kval, b.p, b.q, pq, b.stop);
+      hipLaunchKernelGGL(k_proj_update, dim3(gm), dim3(NB), 0, s, m, b.kdiag, b.p, b.q, b.x, b.r, b.z, rz, pq, rzn,
+                         b.stop);
+      hipLaunchKernelGGL(k_proj_check, dim3(1), dim3(64), 0, s, b.scal + 2, rzn, tol * tol, it + 1, b.stop);
+      hipLaunchKernelGGL(k_proj_dir, dim3(gm), dim3(NB), 0, s, m, b.z, b.p, rz, rzn, b.stop);
+    }
+    (void)hipMemcpyAsync(&stop_host, b.stop, sizeof(int), hipMemcpyDeviceToHost, s);
+    (void)hipStreamSynchronize(s);
+  }
+  hipLaunchKernelGGL(k_proj_xsum, dim3(gm), dim3(NB), 0, s, m, b.x, b.scal + 3);
+  hipLaunchKernelGGL(k_proj_accum, dim3((m.nn + NB - 1) / NB), dim3(NB), 0, s, m, b.x, b.scal + 3, b.dP, b.P);
+  hipLaunchKernelGGL(k_proj_egrad, dim3((m.ne + NB - 1) / NB), dim3(NB), 0, s, m, b.dP, dt, dtp, b.ge, emom);
+  if (np > 0)
+    hipLaunchKernelGGL(k_proj_correct<T>, dim3((unsigned)((np + NB - 1) / NB)), dim3(NB), 0, s, p, np, b.ge);
+  return stop_host > 0 ? stop_host - 1 : it;
+}
+
+template int launch_proj_solve<float>(hipStream_t, const MeshDev &, const ProjBuf &, const double *, double, double,
+                                      const double *, double, int, PartDev<float>, int64_t, double *);
+template int launch_proj_solve<double>(hipStream_t, const MeshDev &, const ProjBuf &, const double *, double, double,
+                                       const double *, double, int, PartDev<double>, int64_t, double *);
+
+}  // namespace pdfk

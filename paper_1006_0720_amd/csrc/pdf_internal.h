@@ -141,6 +141,27 @@ void launch_ell_normals(hipStream_t s, const MeshDev &m, int32_t nw, const doubl
 int launch_ell_solve(hipStream_t s, const MeshDev &m, const ModelDev &md, const EllBuf &b, const double *S,
                      const double *f, double *wp, double tol, int maxit);
 
+// stabilized pressure projection: stiffness matrix (CSR over the masters),
+// the solved pressure P', the increment, CG vectors (nn), element gradients
+// (dt grad dP), the gradient of the next prediction ([2][nn]) and scalars
+struct ProjBuf {
+  int32_t *row_off = nullptr, *cols = nullptr;
+  double *kval = nullptr, *kdiag = nullptr;
+  double *P = nullptr, *dP = nullptr, *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr,
+         *q = nullptr;
+  double2 *ge = nullptr;
+  double *gtot = nullptr;
+  double *scal = nullptr;
+  int *stop = nullptr;
+};
+void launch_proj_gradp(hipStream_t s, const MeshDev &m, const ProjBuf &b, const double *gin);
+// from the predicted statistics S: dP, P' += dP, the particle correction and
+// the shift of the element means (emom); returns the iterations taken (waits
+// for the stream every 8 iterations)
+template <typename T>
+int launch_proj_solve(hipStream_t s, const MeshDev &m, const ProjBuf &b, const double *S, double Cp, double dt,
+                      const double *dtp, double tol, int maxit, PartDev<T> p, int64_t np, double *emom);
+
 // velocity-conditioned scalar means (eq:IECM): per-element particle lists and
 // the result cm (T[np], storage order)
 struct CondBuf {

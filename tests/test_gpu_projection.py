@@ -1,0 +1,92 @@
+"""GPU parity of the stabilized mean-pressure projection (eq:pressure-
+projection-smooth, eq:velocity-correction on the particles) through the C
+ABI, against the oracle's exact sparse solve.
+
+The solve is iterative: with the conjugate gradients stopped at 1e-14 of the
+right-hand side, FP64 trajectories are held to 1e-11 (element indices
+bit-exact) and the solved pressure P' to 1e-9 of its largest magnitude; one
+FP32 step to 1e-5."""
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import configs as CF
+from tests.parity import compare_state, compare_stats
+
+pytestmark = pytest.mark.gpu
+
+PROJ = dict(proj=1, Cp=1e-3, proj_tol=1e-14, proj_maxit=5000)
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1006_0720_amd import _lib
+    return _lib
+
+
+def _pair(w):
+    from paper_1006_0720_amd.runner import workload_context
+
+    print(f"[projection] {w.name} np={w.n_particles} prec={w.precision}", flush=True)
+    ctx = workload_context(w)
+    o = O.Oracle(w.mesh, w.params, store_fp32=(w.precision == "f32"), gradp=w.gradp, wp=w.wp)
+    o.seed(w.seed)
+    return ctx, o
+
+
+def _square(precision="f64"):
+    w = CF.periodic_square(n=12, ppe=40, seed=3)
+    w.params = dict(w.params, **PROJ)
+    w.precision = precision
+    return w
+
+
+def _channel():
+    w = CF.channel(nx=20, n_half=8, ppe=30, precision="f64")
+    w.params = dict(w.params, **PROJ)
+    return w
+
+
+@pytest.mark.parametrize("make", [_square, _channel], ids=["periodic_square", "channel_glm_walls"])
+def test_projection_trajectory_fp64(L, make):
+    w = make()
+    ctx, o = _pair(w)
+    for c in range(2):
+        ctx.advance(5, w.dt)
+        o.run(w.dt, 5)
+        st, el, pid = ctx.particles()
+        assert np.array_equal(pid, o.id)
+        assert np.array_equal(el, o.elem), f"chunk {c}: {(el != o.elem).sum()} element mismatches"
+        compare_state(st, o.state, w.mesh, 1e-11, f"projection chunk {c}")
+        compare_stats(ctx.stats(), o.stats, 1e-11, what=f"projection chunk {c}")
+        P = ctx.nodal_field(L.FIELD_PRESSURE)[0]
+        scale = np.abs(o.Pp).max()
+        assert scale > 0 and np.abs(P - o.Pp).max() <= 1e-9 * scale
+        gp = ctx.nodal_field(L.FIELD_GRADP)
+        assert np.abs(gp - o.gradp).max() <= 1e-9 * max(1.0, np.abs(o.gradp).max())
+    assert ctx.counters()["proj_iters"] > 0
+    ctx.close()
+
+
+def test_projection_fp32_one_step(L):
+    w = _square("f32")
+    ctx, o = _pair(w)
+    ctx.advance(1, w.dt)
+    o.step(w.dt)
+    st, el, _ = ctx.particles()
+    assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
+    compare_state(st, o.state, w.mesh, 1e-5, "projection fp32 step")
+    ctx.close()
+
+
+def test_projection_parameter_checks(L):
+    w = _square()
+    for bad in (dict(stats_mode=CF.STATS_SHAPE), dict(frozen=1), dict(Cp=-1.0), dict(proj_maxit=0),
+                dict(proj_tol=0.0), dict(proj=2)):
+        with pytest.raises(L.PdfError) as ei:
+            L.Context(w.mesh, dict(w.params, **bad))
+        assert ei.value.status == 1, bad
