@@ -186,8 +186,9 @@ def main():
         # solved to 1e-6 of the right-hand side, far below the statistical noise of its input
         w.params = dict(w.params, wp_source=CF.WP_ELLIPTIC, ell_tol=1e-6, ell_maxit=500)
     if args.proj:
-        # solved to 1e-6 of the right-hand side, below the statistical noise of its input
-        w.params = dict(w.params, proj=1, Cp=1e-3, proj_tol=1e-6, proj_maxit=2000, frozen=0)
+        # solved to 1e-6 of the right-hand side, below the statistical noise of its input;
+        # C_p = 0.1 dt: the stabilizing term multiplies P' by (1 - C_p/dt) every step
+        w.params = dict(w.params, proj=1, Cp=0.1 * w.dt, proj_tol=1e-6, proj_maxit=2000, frozen=0)
     if args.mix == "iecm":
         w.params = dict(w.params, mix_model=CF.MIX_IECM, cond_nu=5, cond_nv=5, cond_nw=5, cond_min=2)
     tsize = 4 if w.precision == "f32" else 8
