@@ -72,6 +72,22 @@ def test_projection_trajectory_fp64(L, make):
     ctx.close()
 
 
+def test_projection_canyon_corners_fp64(L):
+    """A small street canyon (floor blocks: reflex corners and the patch
+    search) with the GLM, slip top, periodic streamwise: 5 projected steps."""
+    w = CF.canyon(target_elems=4000, ppe=12, precision="f64")
+    w.params = dict(w.params, **PROJ)
+    ctx, o = _pair(w)
+    ctx.advance(5, w.dt)
+    o.run(w.dt, 5)
+    st, el, pid = ctx.particles()
+    assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
+    compare_state(st, o.state, w.mesh, 1e-11, "projection canyon")
+    P = ctx.nodal_field(L.FIELD_PRESSURE)[0]
+    assert np.abs(P - o.Pp).max() <= 1e-9 * np.abs(o.Pp).max()
+    ctx.close()
+
+
 def test_projection_fp32_one_step(L):
     w = _square("f32")
     ctx, o = _pair(w)
