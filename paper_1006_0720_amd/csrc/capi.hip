@@ -170,10 +170,10 @@ pdf_status estimate_from_scratch(pdf_ctx *c, const double *prev) {
   }
   HIPCHK(c, hipMemsetAsync(rec, 0, (size_t)ne * NREC * sizeof(T), c->stream));
   HIPCHK(c, hipMemsetAsync(c->sums, 0, (size_t)ne * NSUM * sizeof(double), c->stream));
-  launch_accumulate<T>(c->stream, part_view<T>(c, c->cur), c->np, rec, c->sums);
+  launch_accumulate<T>(c->stream, part_view<T>(c, c->cur), c->np, c->md.ne, rec, c->sums);
   launch_ref_from_sums<T>(c->stream, ne, c->sums, rec);
   HIPCHK(c, hipMemsetAsync(c->sums, 0, (size_t)ne * NSUM * sizeof(double), c->stream));
-  launch_accumulate<T>(c->stream, part_view<T>(c, c->cur), c->np, rec, c->sums);
+  launch_accumulate<T>(c->stream, part_view<T>(c, c->cur), c->np, c->md.ne, rec, c->sums);
   launch_elem_moments<T>(c->stream, ne, c->sums, rec, c->emom);
   launch_node_stats(c->stream, c->md, c->emom, prev, c->stats_est, c->cnt);
   launch_node_derivs(c->stream, c->md, c->stats_est);
@@ -413,7 +413,7 @@ pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt, const double *cfl
       HIPCHK(c, hipMemsetAsync(c->sums, 0, (size_t)ne * NSUM * sizeof(double), c->stream));
     }
     mark(c, 1);
-    launch_advance<T>(c->stream, c->dka, c->model, part_view<T>(c, c->cur), c->np, rec,
+    launch_advance<T>(c->stream, c->dka, c->model, part_view<T>(c, c->cur), c->np, c->md.ne, rec,
                       shape ? c->nsums : c->sums, c->seed, c->step, dt, dtp, cm, c->stats_cur,
                       c->gradp_set ? c->gradp : nullptr, c->cnt);
     mark(c, 2);

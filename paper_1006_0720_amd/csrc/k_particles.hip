@@ -53,12 +53,12 @@ __device__ __forceinline__ bool contains(const ElemGeo &g, double px, double py)
 
 // fall-back for concave corners (Fig. corner): elements surrounding the nodes of e
 __device__ int32_t search_patch(const MeshDev &m, int32_t e, double px, double py) {
-  const ElemGeo g = m.geo[e];
+  const ElemGeo g = ldg(m.geo, e);
   for (int k = 0; k < 3; ++k) {
     const int32_t n = g.n[k];
-    for (int32_t i = m.n2e_off[n]; i < m.n2e_off[n + 1]; ++i) {
-      const int32_t c = m.n2e[i];
-      if (contains(m.geo[c], px, py)) return c;
+    for (int32_t i = ldg(m.n2e_off, n); i < ldg(m.n2e_off, n + 1); ++i) {
+      const int32_t c = ldg(m.n2e, i);
+      if (contains(ldg(m.geo, c), px, py)) return c;
     }
   }
   return -1;
@@ -75,9 +75,9 @@ __device__ int32_t locate_brute(const MeshDev &m, double px, double py) {
   i = i < 0 ? 0 : (i >= m.gnx ? m.gnx - 1 : i);
   j = j < 0 ? 0 : (j >= m.gny ? m.gny - 1 : j);
   const size_t c = (size_t)j * m.gnx + i;
-  for (int32_t k = m.cell_off[c]; k < m.cell_off[c + 1]; ++k) {
-    const int32_t e = m.cell_list[k];
-    if (contains(m.geo[e], px, py)) return e;
+  for (int32_t k = ldg(m.cell_off, c); k < ldg(m.cell_off, c + 1); ++k) {
+    const int32_t e = ldg(m.cell_list, k);
+    if (contains(ldg(m.geo, e), px, py)) return e;
   }
   return -1;
 }
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_seed(MeshDev m, ModelDev md, PartDev<T>
   if (i < np) {
     const int32_t e = (int32_t)(i / ppe);
     const uint32_t id = (uint32_t)i;
-    const ElemGeo g = m.geo[e];
+    const ElemGeo g = ldg(m.geo, e);
     const int nn = m.nn;
     const u32x4 r = philox10(id, 0xFFFFFFFFu, 0u, 0u, k0, k1);
     const u32x4 r2 = philox10(id, 0xFFFFFFFFu, 1u, 0u, k0, k1);
@@ -403,20 +403,26 @@ void launch_elem_prep(hipStream_t s, const MeshDev &m, const ModelDev &md, const
 #define PDF_TAB_COPIES 3
 #endif
 #ifndef PDF_PPT
-#define PDF_PPT 8
+#define PDF_PPT 16
 #endif
 constexpr int TAB = 1 << PDF_TAB_LOG2;  // LDS table slots per workgroup (power of two)
 constexpr int NCOPY = PDF_TAB_COPIES;    // accumulator copies (lane % NCOPY picks one)
 constexpr int WG = 256;                  // threads per workgroup of the particle kernels
 constexpr int PPT = PDF_PPT;             // most particles per thread: chunk of WG*ppt particles
 
-// Particles per thread for np particles: PPT when the grid still has at least
-// MIN_WGS workgroups, else halved until it does (or 1).  Small problems then
-// spread over more waves, which hides the latency of the per-particle
-// dependent loads; large ones amortise the table set-up and flush.
+// Particles per thread for np particles over ne elements: at most PPT, halved
+// while a workgroup's chunk of WG*ppt particles (sorted by element) would hold
+// more than about CHUNK_ELEMS elements' worth at the mean count per element
+// (the LDS table keeps room for the elements its particles move into), and
+// halved again while the grid has fewer than MIN_WGS workgroups (small
+// problems then spread over more waves, which hides the latency of the
+// per-particle dependent loads).  Large chunks amortise the table set-up and
+// flush.
 constexpr int64_t MIN_WGS = 2048;
-inline int pick_ppt(int64_t np) {
+constexpr int64_t CHUNK_ELEMS = 48;
+inline int pick_ppt(int64_t np, int64_t ne) {
   int ppt = PPT;
+  while (ppt > 1 && (int64_t)WG * ppt * (ne > 0 ? ne : 1) > CHUNK_ELEMS * np) ppt >>= 1;
   while (ppt > 1 && (np + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt) < MIN_WGS) ppt >>= 1;
   return ppt;
 }
@@ -575,7 +581,7 @@ __device__ __forceinline__ void table_flush(SumTableW &t, double *nsums) {
 template <typename T>
 __device__ __forceinline__ void scatter_shape(SumTableW &t, const MeshDev &m, double *nsums, const T *rec,
                                               int32_t e, double x, double y, T u, T v, T w, T om, T psi) {
-  const ElemGeo g = m.geo[e];
+  const ElemGeo g = ldg(m.geo, e);
   double lam[3], wt[3];
   edge_lambdas(g, x, y, lam);
   shape_w(lam, wt);
@@ -604,7 +610,7 @@ __global__ __launch_bounds__(WG) void k_accumulate_shape(MeshDev m, PartDev<T> p
 template <typename T>
 void launch_accumulate_shape(hipStream_t s, const MeshDev &m, PartDev<T> p, int64_t np, const T *rec,
                              double *nsums) {
-  const int ppt = pick_ppt(np);
+  const int ppt = pick_ppt(np, m.ne);
   hipLaunchKernelGGL(k_accumulate_shape<T>,
                      dim3((unsigned)((np + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt))), dim3(WG), 0, s,
                      m, p, np, ppt, rec, nsums);
@@ -643,8 +649,8 @@ __global__ __launch_bounds__(WG) void k_accumulate(PartDev<T> p, int64_t np, int
 }
 
 template <typename T>
-void launch_accumulate(hipStream_t s, PartDev<T> p, int64_t np, const T *rec, double *sums) {
-  const int ppt = pick_ppt(np);
+void launch_accumulate(hipStream_t s, PartDev<T> p, int64_t np, int32_t ne, const T *rec, double *sums) {
+  const int ppt = pick_ppt(np, ne);
   hipLaunchKernelGGL(k_accumulate<T>, dim3((unsigned)((np + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt))),
                      dim3(WG), 0, s, p, np, ppt, rec, sums);
 }
@@ -809,7 +815,7 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
     T rl[SHAPE ? NREC : 1];
     const T *r = rec + (size_t)e0 * NREC;
     if constexpr (SHAPE) {
-      const ElemGeo g0 = m.geo[e0];
+      const ElemGeo g0 = ldg(m.geo, e0);
       double lam0[3], w0[3];
       edge_lambdas(g0, x0, y0, lam0);
       shape_w(lam0, w0);
@@ -883,7 +889,7 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
     const bool finite_pos = isfinite(x) && isfinite(y);
     for (int it = 0; it < 64 && finite_pos; ++it) {
       C_WALK(1);
-      const ElemGeo g = m.geo[e];
+      const ElemGeo g = ldg(m.geo, e);
       double lam[3];
       edge_lambdas(g, x, y, lam);
       if (lam[0] >= 0.0 && lam[1] >= 0.0 && lam[2] >= 0.0) {
@@ -901,14 +907,14 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
         continue;
       }
       const int32_t b = -(nb + 1);
-      const int32_t bt = m.btype[b];
+      const int32_t bt = ldg(m.btype, b);
       if (bt == PDF_BC_PERIODIC) {
-        const double sx = m.bshift[2 * b], sy = m.bshift[2 * b + 1];
+        const double sx = ldg(m.bshift, 2 * b), sy = ldg(m.bshift, 2 * b + 1);
         x = stor<T>(x + sx);
         y = stor<T>(y + sy);
         shx += sx;
         shy += sy;
-        e = m.belem[m.bpart[b]];
+        e = ldg(m.belem, ldg(m.bpart, b));
         C_PER(1);
         continue;
       }
@@ -924,16 +930,16 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
         // at a reflex corner it is outside only if also behind the other wall
         const int32_t cn = sel3(g.n, t < 0.0 ? ia : ib);
         int32_t wdg = -1;
-        for (int32_t j = m.nwall_off[cn]; j < m.nwall_off[cn + 1]; ++j)
-          if (m.nwall[j] != b) {
-            wdg = m.nwall[j];
+        for (int32_t j = ldg(m.nwall_off, cn); j < ldg(m.nwall_off, cn + 1); ++j)
+          if (ldg(m.nwall, j) != b) {
+            wdg = ldg(m.nwall, j);
             break;
           }
         if (wdg < 0) {
           refl = true;  // the wall ends at a periodic or open boundary
         } else {
-          const ElemGeo gw = m.geo[m.belem[wdg]];
-          const int kw = m.blocal[wdg];
+          const ElemGeo gw = ldg(m.geo, ldg(m.belem, wdg));
+          const int kw = ldg(m.blocal, wdg);
           const double wa = sel3(gw.x, (kw + 1) % 3), wya = sel3(gw.y, (kw + 1) % 3);
           const double wdx = sel3(gw.x, (kw + 2) % 3) - wa, wdy = sel3(gw.y, (kw + 2) % 3) - wya;
           const double turn = (t < 0.0) ? (wdx * dy - wdy * dx) : (dx * wdy - dy * wdx);
@@ -972,7 +978,7 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
         un1 = (T)((double)un1 - 2.0 * vn * ny);
       } else if (!VISC && bt == PDF_BC_WALLFN) {
         // wall functions go with the inviscid particle equations
-        const double3 rw = wall_function(md, S, gradp, m.nn, m.master[sel3(g.n, k)], xa, ya, dx, dy,
+        const double3 rw = wall_function(md, S, gradp, m.nn, ldg(m.master, sel3(g.n, k)), xa, ya, dx, dy,
                                          sel3(g.x, k), sel3(g.y, k), (double)un0, (double)un1, (double)omn);
         un0 = (T)rw.x;
         un1 = (T)rw.y;
@@ -1001,13 +1007,13 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
     // ---- no-slip trajectory (b): eq:fw and eq:exp-wall-condition ----
     if (WALLB && nrefl == 0) {
       if (fwn < 0) {  // host found by a fall-back search
-        fwb = m.geo[found].wb;
-        fwn = m.geo[found].wn;
+        fwb = ldg(m.geo, found).wb;
+        fwn = ldg(m.geo, found).wn;
       }
       int32_t best = -1;
       double bd = 0.0;
       for (int32_t j = fwb; j < fwb + fwn; ++j) {
-        const WallSeg ws = m.wseg[j];
+        const WallSeg ws = ldg(m.wseg, j);
         const double xa = ws.xa, ya = ws.ya;
         const double dx = ws.xb - xa, dy = ws.yb - ya;
         double t = ((x - xa) * dx + (y - ya) * dy) / (dx * dx + dy * dy);
@@ -1021,7 +1027,7 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
         }
       }
       if (best >= 0) {
-        const WallSeg ws = m.wseg[best];
+        const WallSeg ws = ldg(m.wseg, best);
         const double xa = ws.xa, ya = ws.ya;
         const double dx = ws.xb - xa, dy = ws.yb - ya;
         const double len = sqrt(dx * dx + dy * dy);
@@ -1079,10 +1085,10 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
 
 template <typename T, bool SHAPE>
 void launch_advance_m(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
-                      const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
+                      int32_t ne, const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
                       const double *dtp, const T *cm, const double *S, const double *gradp,
                       unsigned long long *cnt) {
-  const int ppt = pick_ppt(np);
+  const int ppt = pick_ppt(np, ne);
   const unsigned grid = (unsigned)((np + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt));
   const bool visc = md.nu > 0.0;
   const bool wallb = visc && md.wall_b;
@@ -1101,13 +1107,13 @@ void launch_advance_m(hipStream_t s, const KArgs *dka, const ModelDev &md, PartD
 
 template <typename T>
 void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
-                    const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
+                    int32_t ne, const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
                     const double *dtp, const T *cm, const double *S, const double *gradp,
                     unsigned long long *cnt) {
   if (md.stats_mode == PDF_STATS_SHAPE)
-    launch_advance_m<T, true>(s, dka, md, p, np, rec, sums, seed, step, dt, dtp, cm, S, gradp, cnt);
+    launch_advance_m<T, true>(s, dka, md, p, np, ne, rec, sums, seed, step, dt, dtp, cm, S, gradp, cnt);
   else
-    launch_advance_m<T, false>(s, dka, md, p, np, rec, sums, seed, step, dt, dtp, cm, S, gradp, cnt);
+    launch_advance_m<T, false>(s, dka, md, p, np, ne, rec, sums, seed, step, dt, dtp, cm, S, gradp, cnt);
 }
 
 #define INST(T)                                                                                  \
@@ -1117,10 +1123,10 @@ void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev
   template void launch_elem_prep<T>(hipStream_t, const MeshDev &, const ModelDev &, const double *, \
                                     const double *, const double *, double, const double *, T *); \
   template void launch_advance<T>(hipStream_t, const KArgs *, const ModelDev &, PartDev<T>, int64_t, \
-                                  const T *, double *, uint64_t, uint32_t, double,                 \
+                                  int32_t, const T *, double *, uint64_t, uint32_t, double,                 \
                                   const double *, const T *, const double *, const double *,       \
                                   unsigned long long *);                                         \
-  template void launch_accumulate<T>(hipStream_t, PartDev<T>, int64_t, const T *, double *);        \
+  template void launch_accumulate<T>(hipStream_t, PartDev<T>, int64_t, int32_t, const T *, double *);        \
   template void launch_elem_prep_shape<T>(hipStream_t, const MeshDev &, const ModelDev &,           \
                                           const double *, const double *, const double *, T *);    \
   template void launch_accumulate_shape<T>(hipStream_t, const MeshDev &, PartDev<T>, int64_t,       \

@@ -99,6 +99,19 @@ struct ModelDev {
   double CL, Ceta;  // eq:L
 };
 
+// p[i] for p pointing into device memory, loaded through a global-segment
+// pointer so that it compiles to a global rather than a flat instruction (flat
+// loads also count against the LDS wait counter, which makes every LDS wait
+// drain them).  The host pass only parses this device function.
+template <typename T>
+__device__ __forceinline__ T ldg(const T *p, size_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ((const __attribute__((address_space(1))) T *)p)[i];
+#else
+  return p[i];
+#endif
+}
+
 // Mesh and model parameters of the particle kernel, kept in device memory and
 // passed by pointer (uniform loads through the scalar cache instead of ~120
 // kernel-argument registers).
@@ -202,7 +215,7 @@ void launch_elem_prep_shape(hipStream_t s, const MeshDev &m, const ModelDev &md,
 // read at wall-function edges
 template <typename T>
 void launch_advance(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
-                    const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
+                    int32_t ne, const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
                     const double *dtp, const T *cm, const double *S, const double *gradp,
                     unsigned long long *cnt);
 template <typename T>
@@ -214,7 +227,7 @@ void launch_node_stats_shape(hipStream_t s, const MeshDev &m, const double *nsum
 template <typename T>
 void launch_elem_count(hipStream_t s, PartDev<T> p, int64_t np, double *sums);
 template <typename T>
-void launch_accumulate(hipStream_t s, PartDev<T> p, int64_t np, const T *rec, double *sums);
+void launch_accumulate(hipStream_t s, PartDev<T> p, int64_t np, int32_t ne, const T *rec, double *sums);
 template <typename T>
 void launch_ref_from_sums(hipStream_t s, int32_t ne, const double *sums, T *rec);
 template <typename T>
