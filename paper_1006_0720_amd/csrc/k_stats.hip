@@ -425,20 +425,46 @@ __global__ __launch_bounds__(SC_WG) void k_scatter(int64_t np, const int32_t *of
   for (int s = threadIdx.x; s < SC_TAB; s += SC_WG)
     if (key[s] >= 0) basel[s] = atomicAdd(&cursor[key[s]], cntl[s]);
   __syncthreads();
+  // destinations first, then the moves in groups of four particles per thread
+  // with every load of a group issued before its stores (the source and
+  // destination buffers are distinct, which the compiler cannot assume)
+  int64_t dd[SC_PPT];
   for (int j = 0; j < SC_PPT; ++j) {
     const int64_t i = base + (int64_t)j * SC_WG + threadIdx.x;
-    if (i >= np) continue;
-    const int32_t e = el[j];
-    const int64_t d = (int64_t)offs[e] + (slot[j] >= 0 ? basel[slot[j]] + rank[j] : rank[j]);
-    dst.x[d] = src.x[i];
-    dst.y[d] = src.y[i];
-    dst.u[d] = src.u[i];
-    dst.v[d] = src.v[i];
-    dst.w[d] = src.w[i];
-    dst.om[d] = src.om[i];
-    dst.psi[d] = src.psi[i];
-    dst.e[d] = e;
-    dst.id[d] = src.id[i];
+    dd[j] = (i < np) ? (int64_t)ldg(offs, el[j]) + (slot[j] >= 0 ? basel[slot[j]] + rank[j] : rank[j]) : -1;
+  }
+  constexpr int GRP = 4;
+  static_assert(SC_PPT % GRP == 0, "groups of four");
+  for (int j0 = 0; j0 < SC_PPT; j0 += GRP) {
+    T vx[GRP], vy[GRP], vu[GRP], vv[GRP], vw[GRP], vo[GRP], vp[GRP];
+    uint32_t vid[GRP];
+#pragma unroll
+    for (int q = 0; q < GRP; ++q) {
+      const int64_t i = base + (int64_t)(j0 + q) * SC_WG + threadIdx.x;
+      if (dd[j0 + q] < 0) continue;
+      vx[q] = ldg(src.x, i);
+      vy[q] = ldg(src.y, i);
+      vu[q] = ldg(src.u, i);
+      vv[q] = ldg(src.v, i);
+      vw[q] = ldg(src.w, i);
+      vo[q] = ldg(src.om, i);
+      vp[q] = ldg(src.psi, i);
+      vid[q] = ldg(src.id, i);
+    }
+#pragma unroll
+    for (int q = 0; q < GRP; ++q) {
+      const int64_t d = dd[j0 + q];
+      if (d < 0) continue;
+      dst.x[d] = vx[q];
+      dst.y[d] = vy[q];
+      dst.u[d] = vu[q];
+      dst.v[d] = vv[q];
+      dst.w[d] = vw[q];
+      dst.om[d] = vo[q];
+      dst.psi[d] = vp[q];
+      dst.e[d] = el[j0 + q];
+      dst.id[d] = vid[q];
+    }
   }
 }
 
