@@ -430,11 +430,15 @@ inline int pick_ppt(int64_t np, int64_t ne) {
 // One key array and NCOPY copies of the accumulators: lanes of a wave that add
 // to the same element (typically the particles that stayed in their host)
 // are spread over the copies, dividing the serialisation of same-address LDS
-// atomics by NCOPY; the copies are summed when the table is flushed.
+// atomics by NCOPY; the copies are summed when the table is flushed.  Rows are
+// padded by one word (TPAD) so that the copies of a value fall in different
+// LDS banks: unpadded, the copy stride is a multiple of the bank count and
+// the copies would conflict on the bank instead of on the address.
+constexpr int TPAD = 1;
 struct SumTable {
   int32_t key[TAB];
-  uint32_t n[NCOPY][TAB];
-  double acc[NCOPY][15][TAB];
+  uint32_t n[NCOPY][TAB + TPAD];
+  double acc[NCOPY][15][TAB + TPAD];
 };
 
 __device__ __forceinline__ void table_init(SumTable &t) {
@@ -511,7 +515,7 @@ __device__ __forceinline__ void table_flush(SumTable &t, double *sums) {
 // shape-function weights and the 15 weighted shifted moments.
 struct SumTableW {
   int32_t key[TAB];
-  double acc[NCOPY][16][TAB];
+  double acc[NCOPY][16][TAB + TPAD];
 };
 
 __device__ __forceinline__ void table_init(SumTableW &t) {

@@ -58,12 +58,32 @@ __global__ __launch_bounds__(256) void k_node_stats(MeshDev m, const double *emo
     for (int f = 0; f < 15; ++f) acc[f] = 0.0;
     double sup = 0.0;
     int c = 0;
-    for (int32_t i = m.m2e_off[n]; i < m.m2e_off[n + 1]; ++i) {
-      const double *o = emom + (size_t)m.m2e[i] * 16;
-      if (!(o[0] > 0.0)) continue;
-      c++;
-      sup += o[0];
-      for (int f = 0; f < 15; ++f) acc[f] += o[1 + f];
+    // two elements per step, each row loaded whole before it is tested, so
+    // that the dependent loads of a node overlap; summed in list order
+    const int32_t i0 = ldg(m.m2e_off, n), i1 = ldg(m.m2e_off, n + 1);
+    for (int32_t i = i0; i < i1; i += 2) {
+      const bool two = i + 1 < i1;
+      const int32_t ea = ldg(m.m2e, i), eb = two ? ldg(m.m2e, i + 1) : ea;
+      double ra[16], rb[16];
+#pragma unroll
+      for (int f = 0; f < 16; f += 2) {
+        const double2 a = ldg((const double2 *)(emom + (size_t)ea * 16), f / 2);
+        const double2 b = ldg((const double2 *)(emom + (size_t)eb * 16), f / 2);
+        ra[f] = a.x;
+        ra[f + 1] = a.y;
+        rb[f] = b.x;
+        rb[f + 1] = b.y;
+      }
+      if (ra[0] > 0.0) {
+        c++;
+        sup += ra[0];
+        for (int f = 0; f < 15; ++f) acc[f] += ra[1 + f];
+      }
+      if (two && rb[0] > 0.0) {
+        c++;
+        sup += rb[0];
+        for (int f = 0; f < 15; ++f) acc[f] += rb[1 + f];
+      }
     }
     if (c > 0) {
       for (int f = 0; f < 15; ++f) out[f * nn + n] = acc[f] / (double)c;
@@ -142,18 +162,35 @@ __global__ __launch_bounds__(256) void k_node_grad(MeshDev m, double *S) {
   const int32_t n = m.masters[t];
   const int nn = m.nn;
   double g[6] = {0, 0, 0, 0, 0, 0};
-  int c = 0;
-  for (int32_t i = m.m2e_off[n]; i < m.m2e_off[n + 1]; ++i) {
-    const int32_t e = m.m2e[i];
-    const double *d = m.dN + 6 * (size_t)e;
-    c++;
-    for (int f = 0; f < 3; ++f)
+  // two elements per step (loads of both issued before either is used),
+  // summed in list order
+  const int32_t i0 = ldg(m.m2e_off, n), i1 = ldg(m.m2e_off, n + 1);
+  for (int32_t i = i0; i < i1; i += 2) {
+    const bool two = i + 1 < i1;
+    const int32_t ee[2] = {ldg(m.m2e, i), two ? ldg(m.m2e, i + 1) : ldg(m.m2e, i)};
+    double d[2][6], q[2][3][3];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) d[h][k] = ldg(m.dN, 6 * (size_t)ee[h] + k);
+#pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const double q = S[f * nn + m.mnode[3 * e + k]];
-        g[2 * f] += d[k] * q;
-        g[2 * f + 1] += d[3 + k] * q;
+        const int32_t nd = ldg(m.mnode, 3 * (size_t)ee[h] + k);
+#pragma unroll
+        for (int f = 0; f < 3; ++f) q[h][f][k] = ldg(S, (size_t)f * nn + nd);
       }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h == 1 && !two) break;
+      for (int f = 0; f < 3; ++f)
+        for (int k = 0; k < 3; ++k) {
+          g[2 * f] += d[h][k] * q[h][f][k];
+          g[2 * f + 1] += d[h][3 + k] * q[h][f][k];
+        }
+    }
   }
+  const int c = i1 - i0;
   for (int f = 0; f < 6; ++f) S[(15 + f) * nn + n] = c ? g[f] / (double)c : 0.0;
 }
 
@@ -164,17 +201,35 @@ __global__ __launch_bounds__(256) void k_node_lap(MeshDev m, double *S) {
   const int32_t n = m.masters[t];
   const int nn = m.nn;
   double l[3] = {0, 0, 0};
-  int c = 0;
-  for (int32_t i = m.m2e_off[n]; i < m.m2e_off[n + 1]; ++i) {
-    const int32_t e = m.m2e[i];
-    const double *d = m.dN + 6 * (size_t)e;
-    c++;
-    for (int f = 0; f < 3; ++f)
+  // two elements per step (loads of both issued before either is used),
+  // summed in list order
+  const int32_t i0 = ldg(m.m2e_off, n), i1 = ldg(m.m2e_off, n + 1);
+  for (int32_t i = i0; i < i1; i += 2) {
+    const bool two = i + 1 < i1;
+    const int32_t ee[2] = {ldg(m.m2e, i), two ? ldg(m.m2e, i + 1) : ldg(m.m2e, i)};
+    double d[2][6], gx[2][3][3], gy[2][3][3];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) d[h][k] = ldg(m.dN, 6 * (size_t)ee[h] + k);
+#pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const int32_t q = m.mnode[3 * e + k];
-        l[f] += d[k] * S[(15 + 2 * f) * nn + q] + d[3 + k] * S[(16 + 2 * f) * nn + q];
+        const int32_t nd = ldg(m.mnode, 3 * (size_t)ee[h] + k);
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          gx[h][f][k] = ldg(S, (size_t)(15 + 2 * f) * nn + nd);
+          gy[h][f][k] = ldg(S, (size_t)(16 + 2 * f) * nn + nd);
+        }
       }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h == 1 && !two) break;
+      for (int f = 0; f < 3; ++f)
+        for (int k = 0; k < 3; ++k) l[f] += d[h][k] * gx[h][f][k] + d[h][3 + k] * gy[h][f][k];
+    }
   }
+  const int c = i1 - i0;
   for (int f = 0; f < 3; ++f) S[(21 + f) * nn + n] = c ? l[f] / (double)c : 0.0;
 }
 
