@@ -154,6 +154,8 @@ def main():
                          "elliptic relaxation, or its finite-element solve every step")
     ap.add_argument("--proj", action="store_true",
                     help="the stabilized mean-pressure projection every step (statistics fed back)")
+    ap.add_argument("--proj-precond", default="multigrid", choices=["multigrid", "jacobi"],
+                    help="preconditioner of the projection's conjugate gradients")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
@@ -188,7 +190,8 @@ def main():
     if args.proj:
         # solved to 1e-6 of the right-hand side, below the statistical noise of its input;
         # C_p = 0.1 dt: the stabilizing term multiplies P' by (1 - C_p/dt) every step
-        w.params = dict(w.params, proj=1, Cp=0.1 * w.dt, proj_tol=1e-6, proj_maxit=2000, frozen=0)
+        w.params = dict(w.params, proj=1, Cp=0.1 * w.dt, proj_tol=1e-6, proj_maxit=2000, frozen=0,
+                        proj_precond=1 if args.proj_precond == "multigrid" else 0)
     if args.mix == "iecm":
         w.params = dict(w.params, mix_model=CF.MIX_IECM, cond_nu=5, cond_nv=5, cond_nw=5, cond_min=2)
     tsize = 4 if w.precision == "f32" else 8
@@ -246,7 +249,8 @@ def main():
                    "n_elements": w.mesh.n_elems, "n_nodes": w.mesh.n_nodes,
                    "particles_per_element": int(w.seed["ppe"]), "dt": w.dt,
                    "reorder_every": args.reorder_every, "stats_mode": args.stats_mode,
-                   "min_ppe": args.min_ppe, "mix": args.mix, "wp": args.wp, "proj": bool(args.proj)},
+                   "min_ppe": args.min_ppe, "mix": args.mix, "wp": args.wp, "proj": bool(args.proj)} |
+                  ({"proj_precond": args.proj_precond} if args.proj else {}),
         "roofline": roof,
         "phase_ms_per_step": {k: round(v / args.steps, 4) for k, v in tm.items()},
         "counters": {k: cnt[k] for k in ("lost", "brute", "fallback", "nonfinite", "empty_node", "redist",

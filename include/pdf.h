@@ -176,13 +176,17 @@ typedef struct pdf_mesh_desc {
  *                (eq:pressure-projection-smooth in weak form: K the linear-element
  *                stiffness matrix over the master nodes, d_a = sum_e A_e/3 div_e <U>*,
  *                natural conditions at walls, the right-hand side's mean removed, dP of
- *                zero mean), solved by Jacobi-preconditioned conjugate gradients to
- *                proj_tol (preconditioned residual against the right-hand side's) in at
- *                most proj_maxit iterations (the call waits for the stream every 8);
+ *                zero mean), solved by preconditioned conjugate gradients to proj_tol
+ *                (preconditioned residual against the right-hand side's) in at most
+ *                proj_maxit iterations (the call waits for the stream every 8);
  *                then every particle's velocity changes by -dt grad dP of its element
  *                (eq:velocity-correction), P' += dP, and the next prediction uses G plus
  *                the node average of the element gradients of P' (PDF_FIELD_GRADP then
  *                returns that sum, PDF_FIELD_PRESSURE returns P')
+ *   proj_precond preconditioner of the projection: 0 Jacobi (the paper's), 1 one V-cycle of
+ *                a smoothed-aggregation multigrid hierarchy of K (built once by
+ *                pdf_init_mesh on the host; Jacobi smoothing, Galerkin coarse levels,
+ *                a dense coarsest solve; PDF_E_NUMERIC if it cannot be built)
  *   Cp           stabilization constant of eq:pressure-projection-smooth (the paper: 1e-3)
  *   nu_wall      kinematic viscosity of the log law eq:Ue at PDF_BC_WALLFN edges (> 0 when
  *                the mesh has such edges).  A particle reflected at such an edge gets the
@@ -199,7 +203,7 @@ typedef struct pdf_mesh_desc {
  *                (PDF_E_INVALID_ARG otherwise). */
 typedef struct pdf_model_params {
   int32_t model, wp_source, omega_source, tm_mode, frozen, wall_b, reorder_every, stats_mode;
-  int32_t min_ppe, mix_model, cond_nu, cond_nv, cond_nw, cond_min, ell_maxit, proj, proj_maxit;
+  int32_t min_ppe, mix_model, cond_nu, cond_nv, cond_nw, cond_min, ell_maxit, proj, proj_maxit, proj_precond;
   double C0, C1, C2, C3, C4, CT, CL, Ceta, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
   double src_x, src_y, src_r, Cs, Ct, nu_wall, ell_tol, Cp, proj_tol;
 } pdf_model_params;

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdf.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["capi.hip", "k_particles.hip", "k_stats.hip", "k_denoise.hip", "k_redist.hip", "k_cond.hip",
-           "k_elliptic.hip", "k_proj.hip"]
+           "k_elliptic.hip", "k_proj.hip", "k_amg.hip"]
 ARCH = os.environ.get("PDF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

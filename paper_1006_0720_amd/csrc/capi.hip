@@ -274,6 +274,49 @@ pdf_status proj_setup(pdf_ctx *c, const pdf_mesh_desc *mesh) {
   b.stop = (int *)dalloc(c, 256);
   ok = ok && b.P && b.dP && b.b && b.x && b.r && b.z && b.p && b.q && b.ge && b.gtot && b.scal && b.stop;
   if (!ok) return fail(c, PDF_E_OOM, "pressure projection buffers");
+  AmgHost h;  // kept until the uploads below have completed
+  if (c->params.proj_precond == 1) {
+    // K over the masters in their compact order (the k-th master is the k-th
+    // node that is its own master, as in the device list of masters)
+    std::vector<int32_t> cidx((size_t)nn, -1);
+    int32_t nm = 0;
+    for (int32_t n = 0; n < nn; ++n)
+      if (master[n] == n) cidx[n] = nm++;
+    std::vector<int32_t> aoff((size_t)nm + 1, 0), acol;
+    std::vector<double> aval;
+    for (int32_t n = 0; n < nn; ++n) {
+      if (master[n] != n) continue;
+      for (int32_t j = row_off[n]; j < row_off[n + 1]; ++j) {
+        acol.push_back(cidx[cols[j]]);
+        aval.push_back(kval[j]);
+      }
+      aoff[cidx[n] + 1] = (int32_t)acol.size();
+    }
+    if (!amg_build(nm, aoff, acol, aval, h))
+      return fail(c, PDF_E_NUMERIC, "the multigrid hierarchy of the projection could not be built");
+    AmgDev &a = b.amg;
+    a.nl = (int)h.lv.size();
+    for (int l = 0; l < a.nl; ++l) {
+      const AmgHostLevel &H = h.lv[l];
+      AmgDevLevel &D = a.lv[l];
+      D.n = H.n;
+      D.omega = H.omega;
+      const size_t vb = (size_t)H.n * sizeof(double);
+      D.b = (double *)dalloc(c, vb);
+      D.y = (double *)dalloc(c, vb);
+      ok = ok && D.b && D.y;
+      if (l + 1 < a.nl) {
+        D.x = (double *)dalloc(c, vb);
+        D.r = (double *)dalloc(c, vb);
+        ok = ok && D.x && D.r && upload(c, H.a_off, &D.a_off) && upload(c, H.a_col, &D.a_col) &&
+             upload(c, H.a_val, &D.a_val) && upload(c, H.dinv, &D.dinv) && upload(c, H.p_off, &D.p_off) &&
+             upload(c, H.p_col, &D.p_col) && upload(c, H.p_val, &D.p_val) && upload(c, H.r_off, &D.r_off) &&
+             upload(c, H.r_col, &D.r_col) && upload(c, H.r_val, &D.r_val);
+      }
+    }
+    ok = ok && upload(c, h.cinv, &a.cinv);
+    if (!ok) return fail(c, PDF_E_OOM, "multigrid hierarchy of the projection");
+  }
   HIPCHK(c, hipMemsetAsync(b.P, 0, vn, c->stream));
   HIPCHK(c, hipMemsetAsync(b.dP, 0, vn, c->stream));
   HIPCHK(c, hipMemsetAsync(b.gtot, 0, 2 * vn, c->stream));
@@ -493,7 +536,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   if (params->proj &&
       (params->stats_mode != PDF_STATS_ELEM || params->frozen || !(params->Cp >= 0.0) || !std::isfinite(params->Cp) ||
        params->proj_maxit < 1 || params->proj_maxit > 100000 || !(params->proj_tol > 0.0) ||
-       !std::isfinite(params->proj_tol)))
+       !std::isfinite(params->proj_tol) || (params->proj_precond != 0 && params->proj_precond != 1)))
     return PDF_E_INVALID_ARG;
   if (params->model == PDF_MODEL_GLM && params->wp_source == PDF_WP_ELLIPTIC &&
       (params->ell_maxit < 1 || params->ell_maxit > 100000 || !(params->ell_tol > 0.0) ||

@@ -6,8 +6,9 @@
 //   K dP = -(d + C_p K P') / dt,  d_a = sum_e (A_e / 3) div_e(<U>*),
 // K the stiffness matrix over the master nodes (CSR, assembled once), natural
 // conditions at walls; the right-hand side is made compatible by removing its
-// mean and dP has zero mean over the masters.  Jacobi-preconditioned
-// conjugate gradients from zero.  Then every particle's velocity changes by
+// mean and dP has zero mean over the masters.  Conjugate gradients from zero,
+// preconditioned by one V-cycle of the smoothed-aggregation hierarchy
+// (k_amg.hip) or, without one, by Jacobi as in the paper.  Then every particle's velocity changes by
 // -dt grad(dP) of its element, the element means by the same amount (the
 // central moments are unchanged), P' += dP, and the next prediction uses G
 // plus the node average of the element gradients of P'.
@@ -66,7 +67,8 @@ __global__ __launch_bounds__(NB) void k_proj_rhs(MeshDev m, const double *S, con
   if (threadIdx.x == 0) atomicAdd(bsum, s);
 }
 
-// b -= mean(b); x = 0; r = b; z = r / diag; p = z; rz0 += r.z; bb += b.b/diag
+// b -= mean(b); x = 0; r = b; with Jacobi (kdiag != null) also z = r / diag,
+// p = z, rz0 += r.z and bb += r.z (the multigrid start is k_proj_pinit)
 __global__ __launch_bounds__(NB) void k_proj_start(MeshDev m, const double *kdiag, const double *bsum, double *b,
                                                    double *x, double *r, double *z, double *p, double *rz0,
                                                    double *bb) {
@@ -78,17 +80,51 @@ __global__ __launch_bounds__(NB) void k_proj_start(MeshDev m, const double *kdia
     b[a] = bv;
     x[a] = 0.0;
     r[a] = bv;
-    const double zz = bv / kdiag[a];
-    z[a] = zz;
-    p[a] = zz;
-    v = bv * zz;
-    w = v;
+    if (kdiag) {
+      const double zz = bv / kdiag[a];
+      z[a] = zz;
+      p[a] = zz;
+      v = bv * zz;
+      w = v;
+    }
   }
+  if (!kdiag) return;
   const double s = block_sum(v);
   if (threadIdx.x == 0) atomicAdd(rz0, s);
   __syncthreads();
   const double s2 = block_sum(w);
   if (threadIdx.x == 0) atomicAdd(bb, s2);
+}
+
+// multigrid start: p = z (= M^-1 r); rz0 += r.z; bb += r.z
+__global__ __launch_bounds__(NB) void k_proj_pinit(MeshDev m, const double *r, const double *z, double *p, double *rz0,
+                                                   double *bb) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (t < m.n_masters) {
+    const int32_t a = m.masters[t];
+    p[a] = z[a];
+    v = r[a] * z[a];
+  }
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) {
+    atomicAdd(rz0, s);
+    atomicAdd(bb, s);
+  }
+}
+
+// rzn += r.z after the multigrid step
+__global__ __launch_bounds__(NB) void k_proj_rz(MeshDev m, const double *r, const double *z, double *rzn,
+                                                const int *stop) {
+  if (*stop) return;
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (t < m.n_masters) {
+    const int32_t a = m.masters[t];
+    v = r[a] * z[a];
+  }
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) atomicAdd(rzn, s);
 }
 
 __global__ __launch_bounds__(NB) void k_proj_apply(MeshDev m, const int32_t *row_off, const int32_t *cols,
@@ -120,10 +156,13 @@ __global__ __launch_bounds__(NB) void k_proj_update(MeshDev m, const double *kdi
     x[a] += alpha * p[a];
     const double rr = r[a] - alpha * q[a];
     r[a] = rr;
-    const double zz = rr / kdiag[a];
-    z[a] = zz;
-    v = rr * zz;
+    if (kdiag) {  // Jacobi; with the multigrid, z and r.z follow in their own kernels
+      const double zz = rr / kdiag[a];
+      z[a] = zz;
+      v = rr * zz;
+    }
   }
+  if (!kdiag) return;
   const double s = block_sum(v);
   if (threadIdx.x == 0) atomicAdd(rzn, s);
 }
@@ -230,8 +269,14 @@ int launch_proj_solve(hipStream_t s, const MeshDev &m, const ProjBuf &b, const d
   (void)hipMemsetAsync(b.stop, 0, sizeof(int), s);
   hipLaunchKernelGGL(k_proj_rhs, dim3(gm), dim3(NB), 0, s, m, S, b.row_off, b.cols, b.kval, b.P, Cp, dt, dtp, b.b,
                      b.scal);
-  hipLaunchKernelGGL(k_proj_start, dim3(gm), dim3(NB), 0, s, m, b.kdiag, b.scal, b.b, b.x, b.r, b.z, b.p,
-                     b.scal + 1, b.scal + 2);
+  const bool mg = b.amg.nl > 0;
+  const double *kd = mg ? nullptr : b.kdiag;
+  hipLaunchKernelGGL(k_proj_start, dim3(gm), dim3(NB), 0, s, m, kd, b.scal, b.b, b.x, b.r, b.z, b.p, b.scal + 1,
+                     b.scal + 2);
+  if (mg) {
+    launch_amg_apply(s, b.amg, m.masters, b.r, b.z, b.stop);
+    hipLaunchKernelGGL(k_proj_pinit, dim3(gm), dim3(NB), 0, s, m, b.r, b.z, b.p, b.scal + 1, b.scal + 2);
+  }
   hipLaunchKernelGGL(k_proj_check, dim3(1), dim3(64), 0, s, b.scal + 2, b.scal + 1, tol * tol, 0, b.stop);
   int it = 0, stop_host = 0;
   while (it < maxit && !stop_host) {
@@ -240,8 +285,12 @@ int launch_proj_solve(hipStream_t s, const MeshDev &m, const ProjBuf &b, const d
       const double *rz = it == 0 ? b.scal + 1 : b.scal + 5 + 2 * (it - 1);
       double *pq = b.scal + 4 + 2 * it, *rzn = b.scal + 5 + 2 * it;
       hipLaunchKernelGGL(k_proj_apply, dim3(gm), dim3(NB), 0, s, m, b.row_off, b.cols, b.kval, b.p, b.q, pq, b.stop);
-      hipLaunchKernelGGL(k_proj_update, dim3(gm), dim3(NB), 0, s, m, b.kdiag, b.p, b.q, b.x, b.r, b.z, rz, pq, rzn,
+      hipLaunchKernelGGL(k_proj_update, dim3(gm), dim3(NB), 0, s, m, kd, b.p, b.q, b.x, b.r, b.z, rz, pq, rzn,
                          b.stop);
+      if (mg) {
+        launch_amg_apply(s, b.amg, m.masters, b.r, b.z, b.stop);
+        hipLaunchKernelGGL(k_proj_rz, dim3(gm), dim3(NB), 0, s, m, b.r, b.z, rzn, b.stop);
+      }
       hipLaunchKernelGGL(k_proj_check, dim3(1), dim3(64), 0, s, b.scal + 2, rzn, tol * tol, it + 1, b.stop);
       hipLaunchKernelGGL(k_proj_dir, dim3(gm), dim3(NB), 0, s, m, b.z, b.p, rz, rzn, b.stop);
     }

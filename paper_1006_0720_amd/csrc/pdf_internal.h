@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/pdf.h"
 
@@ -157,7 +158,44 @@ int launch_ell_solve(hipStream_t s, const MeshDev &m, const ModelDev &md, const 
 // stabilized pressure projection: stiffness matrix (CSR over the masters),
 // the solved pressure P', the increment, CG vectors (nn), element gradients
 // (dt grad dP), the gradient of the next prediction ([2][nn]) and scalars
+// Smoothed-aggregation multigrid hierarchy of the projection's stiffness
+// matrix (k_amg.hip): built on the host, applied as one V-cycle per
+// conjugate-gradient step.  Level l holds A (CSR), D^-1, the damping omega and
+// the prolongator P to level l+1 with its transpose; the last level is solved
+// by a dense inverse.
+constexpr int AMG_MAXL = 12;
+struct AmgHostLevel {
+  int32_t n = 0;
+  double omega = 0.0;
+  std::vector<int32_t> a_off, a_col, p_off, p_col, r_off, r_col;
+  std::vector<double> a_val, dinv, p_val, r_val;
+};
+struct AmgHost {
+  std::vector<AmgHostLevel> lv;
+  std::vector<double> cinv;  // coarsest level, n x n row-major
+};
+// false if the hierarchy could not be built (the caller keeps Jacobi)
+bool amg_build(int32_t n, const std::vector<int32_t> &off, const std::vector<int32_t> &col,
+               const std::vector<double> &val, AmgHost &h);
+struct AmgDevLevel {
+  int32_t n = 0;
+  double omega = 0.0;
+  const int32_t *a_off = nullptr, *a_col = nullptr, *p_off = nullptr, *p_col = nullptr, *r_off = nullptr,
+                *r_col = nullptr;
+  const double *a_val = nullptr, *dinv = nullptr, *p_val = nullptr, *r_val = nullptr;
+  double *b = nullptr, *x = nullptr, *r = nullptr, *y = nullptr;
+};
+struct AmgDev {
+  int nl = 0;
+  AmgDevLevel lv[AMG_MAXL];
+  const double *cinv = nullptr;
+};
+// zout[masters[k]] = (V-cycle applied to rin gathered at masters[k]), k < lv[0].n
+void launch_amg_apply(hipStream_t s, const AmgDev &a, const int32_t *masters, const double *rin, double *zout,
+                      const int *stop);
+
 struct ProjBuf {
+  AmgDev amg;  // nl == 0: Jacobi preconditioning
   int32_t *row_off = nullptr, *cols = nullptr;
   double *kval = nullptr, *kdiag = nullptr;
   double *P = nullptr, *dP = nullptr, *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr,
