@@ -270,10 +270,16 @@ pdf_status proj_setup(pdf_ctx *c, const pdf_mesh_desc *mesh) {
   b.q = (double *)dalloc(c, vn);
   b.ge = (double2 *)dalloc(c, (size_t)ne * sizeof(double2));
   b.gtot = (double *)dalloc(c, 2 * vn);
-  b.scal = (double *)dalloc(c, (size_t)(2 * c->params.proj_maxit + 6) * sizeof(double));
+  b.scal = (double *)dalloc(c, 4 * sizeof(double));
+  b.ring = (double *)dalloc(c, 16 * sizeof(double));
   b.stop = (int *)dalloc(c, 256);
-  ok = ok && b.P && b.dP && b.b && b.x && b.r && b.z && b.p && b.q && b.ge && b.gtot && b.scal && b.stop;
+  b.iter = b.stop ? b.stop + 1 : nullptr;
+  ok = ok && b.P && b.dP && b.b && b.x && b.r && b.z && b.p && b.q && b.ge && b.gtot && b.scal && b.ring && b.stop;
   if (!ok) return fail(c, PDF_E_OOM, "pressure projection buffers");
+  // the conjugate-gradient iterations are captured on a stream of the
+  // library's own (capture is not possible on the legacy default stream);
+  // without it they are launched one by one
+  if (hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking) != hipSuccess) b.cap = nullptr;
   AmgHost h;  // kept until the uploads below have completed
   if (c->params.proj_precond == 1) {
     // K over the masters in their compact order (the k-th master is the k-th
@@ -301,6 +307,19 @@ pdf_status proj_setup(pdf_ctx *c, const pdf_mesh_desc *mesh) {
       AmgDevLevel &D = a.lv[l];
       D.n = H.n;
       D.omega = H.omega;
+      // lanes per row: the power of two at or above the mean row length, at most 64
+      auto lanes = [](const std::vector<int32_t> &off) {
+        const int32_t rows = (int32_t)off.size() - 1;
+        const double mean = rows > 0 ? (double)off.back() / rows : 1.0;
+        int g = 1;
+        while (g < 64 && g < mean) g *= 2;
+        return g;
+      };
+      if (l + 1 < a.nl) {
+        D.ga = lanes(H.a_off);
+        D.gp = lanes(H.p_off);
+        D.gr = lanes(H.r_off);
+      }
       const size_t vb = (size_t)H.n * sizeof(double);
       D.b = (double *)dalloc(c, vb);
       D.y = (double *)dalloc(c, vb);
@@ -512,6 +531,8 @@ void pdf_destroy(pdf_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
   for (auto e : ctx->ev) (void)hipEventDestroy(e);
+  if (ctx->pb.chunk) (void)hipGraphExecDestroy(ctx->pb.chunk);
+  if (ctx->pb.cap) (void)hipStreamDestroy(ctx->pb.cap);
   std::vector<void *> own = ctx->owned;
   for (void *p : own) dfree(ctx, p);
   delete ctx;

@@ -308,49 +308,70 @@ __global__ __launch_bounds__(AB) void k_amg_smooth0(int32_t n, double omega, con
   if (i < n) x[i] = omega * dinv[i] * b[i];
 }
 
+// Sparse products row by row, G lanes per row (G a power of two near the mean
+// row length, chosen on the host): the lanes of a row read consecutive
+// entries, then sum their partial products across the group.
+template <int G>
+__device__ __forceinline__ double row_dot(const int32_t *off, const int32_t *col, const double *val, const double *v,
+                                          int32_t i, int g) {
+  double s = 0.0;
+  for (int32_t j = off[i] + g; j < off[i + 1]; j += G) s += val[j] * v[col[j]];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+  return s;
+}
+
 // r = b - A x
+template <int G>
 __global__ __launch_bounds__(AB) void k_amg_resid(int32_t n, const int32_t *off, const int32_t *col, const double *val,
                                                   const double *b, const double *x, double *r, const int *stop) {
   if (*stop) return;
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t i = (int32_t)(t / G);
+  const int g = (int)(t % G);
   if (i >= n) return;
-  double s = 0.0;
-  for (int32_t j = off[i]; j < off[i + 1]; ++j) s += val[j] * x[col[j]];
-  r[i] = b[i] - s;
+  const double s = row_dot<G>(off, col, val, x, i, g);
+  if (g == 0) r[i] = b[i] - s;
 }
 
 // y = M v (restriction by P^T)
+template <int G>
 __global__ __launch_bounds__(AB) void k_amg_spmv(int32_t n, const int32_t *off, const int32_t *col, const double *val,
                                                  const double *v, double *y, const int *stop) {
   if (*stop) return;
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t i = (int32_t)(t / G);
+  const int g = (int)(t % G);
   if (i >= n) return;
-  double s = 0.0;
-  for (int32_t j = off[i]; j < off[i + 1]; ++j) s += val[j] * v[col[j]];
-  y[i] = s;
+  const double s = row_dot<G>(off, col, val, v, i, g);
+  if (g == 0) y[i] = s;
 }
 
 // x += P yc
+template <int G>
 __global__ __launch_bounds__(AB) void k_amg_prolong(int32_t n, const int32_t *off, const int32_t *col,
                                                     const double *val, const double *yc, double *x, const int *stop) {
   if (*stop) return;
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t i = (int32_t)(t / G);
+  const int g = (int)(t % G);
   if (i >= n) return;
-  double s = 0.0;
-  for (int32_t j = off[i]; j < off[i + 1]; ++j) s += val[j] * yc[col[j]];
-  x[i] += s;
+  const double s = row_dot<G>(off, col, val, yc, i, g);
+  if (g == 0) x[i] += s;
 }
 
 // y = x + omega D^-1 (b - A x)
+template <int G>
 __global__ __launch_bounds__(AB) void k_amg_post(int32_t n, const int32_t *off, const int32_t *col, const double *val,
                                                  double omega, const double *dinv, const double *b, const double *x,
                                                  double *y, const int *stop) {
   if (*stop) return;
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t i = (int32_t)(t / G);
+  const int g = (int)(t % G);
   if (i >= n) return;
-  double s = 0.0;
-  for (int32_t j = off[i]; j < off[i + 1]; ++j) s += val[j] * x[col[j]];
-  y[i] = x[i] + omega * dinv[i] * (b[i] - s);
+  const double s = row_dot<G>(off, col, val, x, i, g);
+  if (g == 0) y[i] = x[i] + omega * dinv[i] * (b[i] - s);
 }
 
 // y = Cinv b on the coarsest level: one wave per row
@@ -366,6 +387,21 @@ __global__ __launch_bounds__(64) void k_amg_dense(int32_t n, const double *cinv,
 }
 
 inline unsigned blocks(int32_t n) { return (unsigned)((n + AB - 1) / AB); }
+inline unsigned blocks_g(int32_t n, int g) { return (unsigned)(((int64_t)n * g + AB - 1) / AB); }
+
+// launch K<G> with the group size g (1, 2, 4, ..., 64)
+#define AMG_LAUNCH_G(K, g, n, s, ...)                                                                   \
+  do {                                                                                                  \
+    switch (g) {                                                                                        \
+      case 1: hipLaunchKernelGGL(K<1>, dim3(blocks_g(n, 1)), dim3(AB), 0, s, n, __VA_ARGS__); break;   \
+      case 2: hipLaunchKernelGGL(K<2>, dim3(blocks_g(n, 2)), dim3(AB), 0, s, n, __VA_ARGS__); break;   \
+      case 4: hipLaunchKernelGGL(K<4>, dim3(blocks_g(n, 4)), dim3(AB), 0, s, n, __VA_ARGS__); break;   \
+      case 8: hipLaunchKernelGGL(K<8>, dim3(blocks_g(n, 8)), dim3(AB), 0, s, n, __VA_ARGS__); break;   \
+      case 16: hipLaunchKernelGGL(K<16>, dim3(blocks_g(n, 16)), dim3(AB), 0, s, n, __VA_ARGS__); break; \
+      case 32: hipLaunchKernelGGL(K<32>, dim3(blocks_g(n, 32)), dim3(AB), 0, s, n, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL(K<64>, dim3(blocks_g(n, 64)), dim3(AB), 0, s, n, __VA_ARGS__); break; \
+    }                                                                                                   \
+  } while (0)
 
 void vcycle(hipStream_t s, const AmgDev &a, int l, const int *stop) {
   const AmgDevLevel &L = a.lv[l];
@@ -375,14 +411,11 @@ void vcycle(hipStream_t s, const AmgDev &a, int l, const int *stop) {
   }
   const AmgDevLevel &C = a.lv[l + 1];
   hipLaunchKernelGGL(k_amg_smooth0, dim3(blocks(L.n)), dim3(AB), 0, s, L.n, L.omega, L.dinv, L.b, L.x, stop);
-  hipLaunchKernelGGL(k_amg_resid, dim3(blocks(L.n)), dim3(AB), 0, s, L.n, L.a_off, L.a_col, L.a_val, L.b, L.x, L.r,
-                     stop);
-  hipLaunchKernelGGL(k_amg_spmv, dim3(blocks(C.n)), dim3(AB), 0, s, C.n, L.r_off, L.r_col, L.r_val, L.r, C.b, stop);
+  AMG_LAUNCH_G(k_amg_resid, L.ga, L.n, s, L.a_off, L.a_col, L.a_val, L.b, L.x, L.r, stop);
+  AMG_LAUNCH_G(k_amg_spmv, L.gr, C.n, s, L.r_off, L.r_col, L.r_val, L.r, C.b, stop);
   vcycle(s, a, l + 1, stop);
-  hipLaunchKernelGGL(k_amg_prolong, dim3(blocks(L.n)), dim3(AB), 0, s, L.n, L.p_off, L.p_col, L.p_val, C.y, L.x,
-                     stop);
-  hipLaunchKernelGGL(k_amg_post, dim3(blocks(L.n)), dim3(AB), 0, s, L.n, L.a_off, L.a_col, L.a_val, L.omega, L.dinv,
-                     L.b, L.x, L.y, stop);
+  AMG_LAUNCH_G(k_amg_prolong, L.gp, L.n, s, L.p_off, L.p_col, L.p_val, C.y, L.x, stop);
+  AMG_LAUNCH_G(k_amg_post, L.ga, L.n, s, L.a_off, L.a_col, L.a_val, L.omega, L.dinv, L.b, L.x, L.y, stop);
 }
 
 }  // namespace

@@ -127,18 +127,27 @@ __global__ __launch_bounds__(NB) void k_proj_rz(MeshDev m, const double *r, cons
   if (threadIdx.x == 0) atomicAdd(rzn, s);
 }
 
+// q = K p, pq += p.q; GA lanes per row (consecutive entries, then a sum across
+// the group)
+constexpr int GA = 8;
 __global__ __launch_bounds__(NB) void k_proj_apply(MeshDev m, const int32_t *row_off, const int32_t *cols,
                                                    const double *kval, const double *p, double *q, double *pq,
                                                    const int *stop) {
   if (*stop) return;
-  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t k = (int32_t)(t / GA);
+  const int g = (int)(t % GA);
   double v = 0.0;
-  if (t < m.n_masters) {
-    const int32_t a = m.masters[t];
+  if (k < m.n_masters) {
+    const int32_t a = m.masters[k];
     double y = 0.0;
-    for (int32_t j = row_off[a]; j < row_off[a + 1]; ++j) y += kval[j] * p[cols[j]];
-    q[a] = y;
-    v = p[a] * y;
+    for (int32_t j = row_off[a] + g; j < row_off[a + 1]; j += GA) y += kval[j] * p[cols[j]];
+#pragma unroll
+    for (int o = GA / 2; o > 0; o >>= 1) y += __shfl_xor(y, o, GA);
+    if (g == 0) {
+      q[a] = y;
+      v = p[a] * y;
+    }
   }
   const double s = block_sum(v);
   if (threadIdx.x == 0) atomicAdd(pq, s);
@@ -177,9 +186,22 @@ __global__ __launch_bounds__(NB) void k_proj_dir(MeshDev m, const double *z, dou
   p[a] = z[a] + beta * p[a];
 }
 
-__global__ void k_proj_check(const double *bb, const double *rz, double tol2, int iters, int *stop) {
+// after the iteration that produced rz: count it, stop (stop = iterations + 1)
+// at the tolerance or at maxit, and clear the ring slot of the next iteration
+// (its previous contents belong to the iteration 8 steps back, long consumed)
+__global__ void k_proj_check(const double *bb, const double *rz, double tol2, int maxit, int *iter, int *stop,
+                             double *next_slot) {
   if (threadIdx.x != 0 || blockIdx.x != 0 || *stop) return;
-  if (!(rz[0] > tol2 * bb[0])) *stop = iters + 1;
+  const int it = ++(*iter);
+  if (!(rz[0] > tol2 * bb[0]) || it >= maxit) *stop = it + 1;
+  next_slot[0] = 0.0;
+  next_slot[1] = 0.0;
+}
+
+// before the first iteration: converged already (stop = 1)?
+__global__ void k_proj_check0(const double *bb, const double *rz, double tol2, int *stop) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (!(rz[0] > tol2 * bb[0])) *stop = 1;
 }
 
 // xsum += x over the masters
@@ -259,41 +281,70 @@ void launch_proj_gradp(hipStream_t s, const MeshDev &m, const ProjBuf &b, const 
   hipLaunchKernelGGL(k_proj_gradp, dim3((m.nn + NB - 1) / NB), dim3(NB), 0, s, m, b.P, gin, b.gtot);
 }
 
+// One conjugate-gradient iteration j (0..7) of a chunk: the scalars of
+// iteration j live in ring slot j (pq, then r.z), the previous r.z in slot
+// (j + 7) % 8, so the 8-iteration chunk is the same sequence of launches every
+// time and is captured once as a HIP graph.
+void proj_iteration(hipStream_t s, const MeshDev &m, const ProjBuf &b, int j, double tol2, int maxit) {
+  const unsigned gm = (unsigned)((m.n_masters + NB - 1) / NB);
+  const bool mg = b.amg.nl > 0;
+  const double *kd = mg ? nullptr : b.kdiag;
+  const double *rz = b.ring + 2 * ((j + 7) % 8) + 1;
+  double *pq = b.ring + 2 * j, *rzn = b.ring + 2 * j + 1;
+  const unsigned ga = (unsigned)(((int64_t)m.n_masters * GA + NB - 1) / NB);
+  hipLaunchKernelGGL(k_proj_apply, dim3(ga), dim3(NB), 0, s, m, b.row_off, b.cols, b.kval, b.p, b.q, pq, b.stop);
+  hipLaunchKernelGGL(k_proj_update, dim3(gm), dim3(NB), 0, s, m, kd, b.p, b.q, b.x, b.r, b.z, rz, pq, rzn, b.stop);
+  if (mg) {
+    launch_amg_apply(s, b.amg, m.masters, b.r, b.z, b.stop);
+    hipLaunchKernelGGL(k_proj_rz, dim3(gm), dim3(NB), 0, s, m, b.r, b.z, rzn, b.stop);
+  }
+  hipLaunchKernelGGL(k_proj_check, dim3(1), dim3(64), 0, s, b.scal + 2, rzn, tol2, maxit, b.iter, b.stop,
+                     b.ring + 2 * ((j + 1) % 8));
+  hipLaunchKernelGGL(k_proj_dir, dim3(gm), dim3(NB), 0, s, m, b.z, b.p, rz, rzn, b.stop);
+}
+
 template <typename T>
-int launch_proj_solve(hipStream_t s, const MeshDev &m, const ProjBuf &b, const double *S, double Cp, double dt,
+int launch_proj_solve(hipStream_t s, const MeshDev &m, ProjBuf &b, const double *S, double Cp, double dt,
                       const double *dtp, double tol, int maxit, PartDev<T> p, int64_t np, double *emom) {
   const unsigned gm = (unsigned)((m.n_masters + NB - 1) / NB);
-  // scal: [0] bsum, [1] rz0, [2] bb, [3] xsum, then per iteration k: pq at
-  // 4 + 2k, the next rz at 5 + 2k
-  (void)hipMemsetAsync(b.scal, 0, (size_t)(2 * maxit + 6) * sizeof(double), s);
-  (void)hipMemsetAsync(b.stop, 0, sizeof(int), s);
+  const double tol2 = tol * tol;
+  // scal: [0] bsum, [1] unused, [2] bb, [3] xsum; ring: 8 slots of (pq, r.z),
+  // slot 7's r.z holding the starting r.z
+  (void)hipMemsetAsync(b.scal, 0, 4 * sizeof(double), s);
+  (void)hipMemsetAsync(b.ring, 0, 16 * sizeof(double), s);
+  (void)hipMemsetAsync(b.stop, 0, 2 * sizeof(int), s);  // stop and the iteration counter
   hipLaunchKernelGGL(k_proj_rhs, dim3(gm), dim3(NB), 0, s, m, S, b.row_off, b.cols, b.kval, b.P, Cp, dt, dtp, b.b,
                      b.scal);
   const bool mg = b.amg.nl > 0;
   const double *kd = mg ? nullptr : b.kdiag;
-  hipLaunchKernelGGL(k_proj_start, dim3(gm), dim3(NB), 0, s, m, kd, b.scal, b.b, b.x, b.r, b.z, b.p, b.scal + 1,
+  hipLaunchKernelGGL(k_proj_start, dim3(gm), dim3(NB), 0, s, m, kd, b.scal, b.b, b.x, b.r, b.z, b.p, b.ring + 15,
                      b.scal + 2);
   if (mg) {
     launch_amg_apply(s, b.amg, m.masters, b.r, b.z, b.stop);
-    hipLaunchKernelGGL(k_proj_pinit, dim3(gm), dim3(NB), 0, s, m, b.r, b.z, b.p, b.scal + 1, b.scal + 2);
+    hipLaunchKernelGGL(k_proj_pinit, dim3(gm), dim3(NB), 0, s, m, b.r, b.z, b.p, b.ring + 15, b.scal + 2);
   }
-  hipLaunchKernelGGL(k_proj_check, dim3(1), dim3(64), 0, s, b.scal + 2, b.scal + 1, tol * tol, 0, b.stop);
-  int it = 0, stop_host = 0;
-  while (it < maxit && !stop_host) {
-    const int chunk = (maxit - it) < 8 ? (maxit - it) : 8;
-    for (int j = 0; j < chunk; ++j, ++it) {
-      const double *rz = it == 0 ? b.scal + 1 : b.scal + 5 + 2 * (it - 1);
-      double *pq = b.scal + 4 + 2 * it, *rzn = b.scal + 5 + 2 * it;
-      hipLaunchKernelGGL(k_proj_apply, dim3(gm), dim3(NB), 0, s, m, b.row_off, b.cols, b.kval, b.p, b.q, pq, b.stop);
-      hipLaunchKernelGGL(k_proj_update, dim3(gm), dim3(NB), 0, s, m, kd, b.p, b.q, b.x, b.r, b.z, rz, pq, rzn,
-                         b.stop);
-      if (mg) {
-        launch_amg_apply(s, b.amg, m.masters, b.r, b.z, b.stop);
-        hipLaunchKernelGGL(k_proj_rz, dim3(gm), dim3(NB), 0, s, m, b.r, b.z, rzn, b.stop);
+  hipLaunchKernelGGL(k_proj_check0, dim3(1), dim3(64), 0, s, b.scal + 2, b.ring + 15, tol2, b.stop);
+  // the chunk of 8 iterations: captured on the private capture stream the
+  // first time, then replayed on s
+  if (!b.chunk && b.cap) {
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      for (int j = 0; j < 8; ++j) proj_iteration(b.cap, m, b, j, tol2, maxit);
+      if (hipStreamEndCapture(b.cap, &g) == hipSuccess && g) {
+        hipGraphExec_t e = nullptr;
+        if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) == hipSuccess) b.chunk = e;
+        (void)hipGraphDestroy(g);
       }
-      hipLaunchKernelGGL(k_proj_check, dim3(1), dim3(64), 0, s, b.scal + 2, rzn, tol * tol, it + 1, b.stop);
-      hipLaunchKernelGGL(k_proj_dir, dim3(gm), dim3(NB), 0, s, m, b.z, b.p, rz, rzn, b.stop);
     }
+  }
+  int stop_host = 0, launched = 0;
+  while (launched < maxit && !stop_host) {
+    if (b.chunk) {
+      (void)hipGraphLaunch(b.chunk, s);
+    } else {
+      for (int j = 0; j < 8; ++j) proj_iteration(s, m, b, j, tol2, maxit);
+    }
+    launched += 8;
     (void)hipMemcpyAsync(&stop_host, b.stop, sizeof(int), hipMemcpyDeviceToHost, s);
     (void)hipStreamSynchronize(s);
   }
@@ -302,12 +353,12 @@ int launch_proj_solve(hipStream_t s, const MeshDev &m, const ProjBuf &b, const d
   hipLaunchKernelGGL(k_proj_egrad, dim3((m.ne + NB - 1) / NB), dim3(NB), 0, s, m, b.dP, dt, dtp, b.ge, emom);
   if (np > 0)
     hipLaunchKernelGGL(k_proj_correct<T>, dim3((unsigned)((np + NB - 1) / NB)), dim3(NB), 0, s, p, np, b.ge);
-  return stop_host > 0 ? stop_host - 1 : it;
+  return stop_host > 0 ? stop_host - 1 : maxit;
 }
 
-template int launch_proj_solve<float>(hipStream_t, const MeshDev &, const ProjBuf &, const double *, double, double,
+template int launch_proj_solve<float>(hipStream_t, const MeshDev &, ProjBuf &, const double *, double, double,
                                       const double *, double, int, PartDev<float>, int64_t, double *);
-template int launch_proj_solve<double>(hipStream_t, const MeshDev &, const ProjBuf &, const double *, double, double,
+template int launch_proj_solve<double>(hipStream_t, const MeshDev &, ProjBuf &, const double *, double, double,
                                        const double *, double, int, PartDev<double>, int64_t, double *);
 
 }  // namespace pdfk

@@ -179,6 +179,7 @@ bool amg_build(int32_t n, const std::vector<int32_t> &off, const std::vector<int
                const std::vector<double> &val, AmgHost &h);
 struct AmgDevLevel {
   int32_t n = 0;
+  int ga = 1, gp = 1, gr = 1;  // lanes per row of the products with A, P and P^T
   double omega = 0.0;
   const int32_t *a_off = nullptr, *a_col = nullptr, *p_off = nullptr, *p_col = nullptr, *r_off = nullptr,
                 *r_col = nullptr;
@@ -203,14 +204,18 @@ struct ProjBuf {
   double2 *ge = nullptr;
   double *gtot = nullptr;
   double *scal = nullptr;
-  int *stop = nullptr;
+  double *ring = nullptr;  // 8 x (p.q, r.z) of the conjugate-gradient iterations
+  int *stop = nullptr;     // stop flag; the iteration counter follows it (iter = stop + 1)
+  int *iter = nullptr;
+  hipStream_t cap = nullptr;       // private stream on which the iteration chunk is captured
+  hipGraphExec_t chunk = nullptr;  // 8 iterations as one graph (null: launched one by one)
 };
 void launch_proj_gradp(hipStream_t s, const MeshDev &m, const ProjBuf &b, const double *gin);
 // from the predicted statistics S: dP, P' += dP, the particle correction and
 // the shift of the element means (emom); returns the iterations taken (waits
-// for the stream every 8 iterations)
+// for the stream every 8 iterations; the 8 are one captured graph)
 template <typename T>
-int launch_proj_solve(hipStream_t s, const MeshDev &m, const ProjBuf &b, const double *S, double Cp, double dt,
+int launch_proj_solve(hipStream_t s, const MeshDev &m, ProjBuf &b, const double *S, double Cp, double dt,
                       const double *dtp, double tol, int maxit, PartDev<T> p, int64_t np, double *emom);
 
 // velocity-conditioned scalar means (eq:IECM): per-element particle lists and
