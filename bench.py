@@ -52,6 +52,28 @@ def kernel_bytes(w, tsize, shape=False):
     return int(n_p * per_particle + n_e * per_element), per_particle, round(per_element, 1)
 
 
+def copy_bandwidth(mib=2048, reps=5):
+    """Best read-plus-write rate (GB/s) of a plain device-to-device copy of
+    mib MiB, timed with events on the current stream."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * n * 4 / best / 1e9
+
+
 def source_hash():
     h = hashlib.sha256()
     for f in ("k_particles.hip", "rng.h", "pdf_internal.h"):
@@ -206,6 +228,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    copy_gbs = copy_bandwidth()
     ctx.advance(args.warmup, w.dt)
     torch.cuda.synchronize()
     ctx.counters(reset=True)
@@ -231,7 +254,9 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_advance", "kernel_ms": round(adv_ms, 4),
             "bytes_per_launch": bytes_alg, "bytes_per_particle": per_p,
-            "bytes_per_element": per_e}
+            "bytes_per_element": per_e,
+            # what a plain device copy reaches on this GPU (read + write bytes)
+            "copy_achievable": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
     if prof:
         # the second roof: measured VALU instructions per particle-step (SQ_INSTS_VALU)
         ipp = prof["sq"]["valu_instructions_per_particle"]
