@@ -97,6 +97,16 @@ def profile_counters(workload):
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host (from /proc/cpuinfo)."""
+    try:
+        lines = open("/proc/cpuinfo").read().splitlines()
+    except OSError:
+        return None
+    names = [ln.split(":", 1)[1].strip() for ln in lines if ln.startswith("model name")]
+    return f"{names[0]} ({len(names)} logical CPUs)" if names else None
+
+
 def cpu_baseline(wname, w):
     """The FP64 oracle (single thread) on a bounded sample of the workload:
     the full mesh at a reduced particle count, a few steps."""
@@ -118,7 +128,8 @@ def cpu_baseline(wname, w):
     return {"value": n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"same mesh ({w.mesh.n_elems} elements) at {ppe} particles/element "
                       f"({n} particles), {steps} steps, FP64 oracle, 1 thread, includes the "
-                      f"statistics estimate of each step"}
+                      f"statistics estimate of each step",
+            "host_cpu": host_cpu()}
 
 
 def denoise_study(mode, out_path=""):
