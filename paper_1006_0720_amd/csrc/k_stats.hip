@@ -413,7 +413,7 @@ __global__ void k_scan_add(int32_t ne, int32_t *offs, const int32_t *blocksums, 
 // workgroup with a single global atomic, then writes every particle to
 // offs[e] + range base + local rank.  Elements that do not fit in the table
 // fall back to one global atomic per particle.
-constexpr int SC_WG = 256, SC_PPT = 8, SC_TAB = 512;
+constexpr int SC_WG = 256, SC_PPT = 16, SC_TAB = 512;
 
 template <typename T>
 __global__ __launch_bounds__(SC_WG) void k_scatter(int64_t np, const int32_t *offs, int32_t *cursor,
