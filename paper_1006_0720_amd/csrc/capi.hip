@@ -436,8 +436,8 @@ pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt, const double *cfl
         HIPCHK(c, hipMemsetAsync(c->sums, 0, (size_t)ne * NSUM * sizeof(double), c->stream));
         launch_elem_count<T>(c->stream, part_view<T>(c, c->cur), c->np, c->sums);
       }
-      launch_redistribute<T>(c->stream, c->dka, c->rb, c->sums, NSUM, part_view<T>(c, c->cur), c->params.min_ppe,
-                             c->seed, c->step, c->cnt);
+      HIPCHK(c, launch_redistribute<T>(c->stream, c->dka, c->rb, c->sums, NSUM, part_view<T>(c, c->cur),
+                                       c->params.min_ppe, c->seed, c->step, c->cnt));
     }
     // eq:IECM: <phi|V> of every particle from the state at the start of the step
     const T *cm = nullptr;
@@ -445,7 +445,8 @@ pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt, const double *cfl
       // ELEM statistics without redistribution: the last accumulation's count
       // slot holds the particles per element
       const bool sums_valid = c->model.stats_mode == PDF_STATS_ELEM && c->params.min_ppe == 0;
-      launch_cond_means<T>(c->stream, c->model, c->cb, part_view<T>(c, c->cur), sums_valid ? c->sums : nullptr);
+      HIPCHK(c, launch_cond_means<T>(c->stream, c->model, c->cb, part_view<T>(c, c->cur),
+                                     sums_valid ? c->sums : nullptr));
       cm = (const T *)c->cb.cm;
     }
     mark(c, 0);
@@ -1291,12 +1292,18 @@ pdf_status pdf_denoiser_create(pdf_ctx *c, int32_t hidden, uint64_t seed, pdf_de
   d->feat = (float *)dalloc(c, (size_t)nn * PDF_DN_NIN * 4);
   // points surrounding points (masters): masters of the nodes of the elements around each master
   std::vector<int32_t> m2e_off(nn + 1), m2e, mnode(3 * (size_t)c->md.ne), master(nn);
-  (void)hipStreamSynchronize(c->stream);
-  hipMemcpy(m2e_off.data(), c->md.m2e_off, (nn + 1) * 4, hipMemcpyDeviceToHost);
-  m2e.resize(m2e_off[nn]);
-  if (!m2e.empty()) hipMemcpy(m2e.data(), c->md.m2e, m2e.size() * 4, hipMemcpyDeviceToHost);
-  hipMemcpy(mnode.data(), c->md.mnode, mnode.size() * 4, hipMemcpyDeviceToHost);
-  hipMemcpy(master.data(), c->md.master, nn * 4, hipMemcpyDeviceToHost);
+  bool copied = hipStreamSynchronize(c->stream) == hipSuccess &&
+                hipMemcpy(m2e_off.data(), c->md.m2e_off, (nn + 1) * 4, hipMemcpyDeviceToHost) == hipSuccess;
+  if (copied) {
+    m2e.resize(m2e_off[nn]);
+    copied = (m2e.empty() || hipMemcpy(m2e.data(), c->md.m2e, m2e.size() * 4, hipMemcpyDeviceToHost) == hipSuccess) &&
+             hipMemcpy(mnode.data(), c->md.mnode, mnode.size() * 4, hipMemcpyDeviceToHost) == hipSuccess &&
+             hipMemcpy(master.data(), c->md.master, nn * 4, hipMemcpyDeviceToHost) == hipSuccess;
+  }
+  if (!copied) {
+    pdf_denoiser_destroy(d);
+    return fail(c, PDF_E_DEVICE, "denoiser set-up: reading the mesh tables back failed");
+  }
   std::vector<int32_t> poff(nn + 1, 0), plist;
   for (int32_t n = 0; n < nn; ++n) {
     std::vector<int32_t> l;

@@ -475,7 +475,9 @@ bool cond_alloc(CondBuf &b, int32_t ne, int64_t np, size_t tsize, void *(*alloc)
   b.ne = ne;
   b.np = np;
   size_t scan_bytes = 0;
-  hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (int32_t *)nullptr, (int32_t *)nullptr, ne + 1);
+  if (hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (int32_t *)nullptr, (int32_t *)nullptr, ne + 1) !=
+      hipSuccess)
+    return false;
   b.temp_bytes = scan_bytes > 0 ? scan_bytes : 256;
   const size_t npl = (size_t)(np > 0 ? np : 1);
   b.cnt = (int32_t *)alloc(((size_t)ne + 1) * 4, user);
@@ -492,10 +494,11 @@ bool cond_alloc(CondBuf &b, int32_t ne, int64_t np, size_t tsize, void *(*alloc)
 }
 
 template <typename T>
-void launch_cond_means(hipStream_t s, const ModelDev &md, const CondBuf &b, PartDev<T> p, const double *elem_sums) {
+hipError_t launch_cond_means(hipStream_t s, const ModelDev &md, const CondBuf &b, PartDev<T> p,
+                             const double *elem_sums) {
   const int32_t ne = b.ne;
   const int64_t np = b.np;
-  if (np == 0) return;
+  if (np == 0) return hipSuccess;
   const unsigned gt = (unsigned)((np + (int64_t)TT * TP - 1) / ((int64_t)TT * TP));
   (void)hipMemsetAsync(b.cnt, 0, ((size_t)ne + 1) * 4, s);
   if (elem_sums)
@@ -503,7 +506,8 @@ void launch_cond_means(hipStream_t s, const ModelDev &md, const CondBuf &b, Part
   else
     hipLaunchKernelGGL(k_cond_count, dim3(gt), dim3(TT), 0, s, np, ne, p.e, b.cnt);
   size_t tb = b.temp_bytes;
-  hipcub::DeviceScan::ExclusiveSum(b.temp, tb, b.cnt, b.off, ne + 1, s);
+  const hipError_t se = hipcub::DeviceScan::ExclusiveSum(b.temp, tb, b.cnt, b.off, ne + 1, s);
+  if (se != hipSuccess) return se;
   (void)hipMemsetAsync(b.cursor, 0, (size_t)ne * 4, s);
   (void)hipMemsetAsync(b.nbig, 0, 8, s);
   hipLaunchKernelGGL(k_cond_fill, dim3(gt), dim3(TT), 0, s, np, ne, p.e, b.off, b.cursor, b.list);
@@ -514,11 +518,12 @@ void launch_cond_means(hipStream_t s, const ModelDev &md, const CondBuf &b, Part
                      b.list, b.mid, b.nbig, cm);
   hipLaunchKernelGGL(k_cond_block<T>, dim3(512), dim3(BT), 0, s, md, p, b.cnt, b.off, b.list, b.list2, b.big,
                      b.nbig, cm);
+  return hipGetLastError();
 }
 
-template void launch_cond_means<float>(hipStream_t, const ModelDev &, const CondBuf &, PartDev<float>,
+template hipError_t launch_cond_means<float>(hipStream_t, const ModelDev &, const CondBuf &, PartDev<float>,
                                        const double *);
-template void launch_cond_means<double>(hipStream_t, const ModelDev &, const CondBuf &, PartDev<double>,
+template hipError_t launch_cond_means<double>(hipStream_t, const ModelDev &, const CondBuf &, PartDev<double>,
                                         const double *);
 
 }  // namespace pdfk

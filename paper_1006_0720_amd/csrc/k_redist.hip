@@ -163,9 +163,11 @@ bool redist_alloc(RedistBuf &b, int32_t ne, int64_t np, void *(*alloc)(size_t, v
   b.ne = ne;
   b.np = np;
   size_t sort_bytes = 0, scan_bytes = 0;
-  hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (int32_t *)nullptr, (int32_t *)nullptr,
-                                     (int32_t *)nullptr, (int32_t *)nullptr, ne);
-  hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (int32_t *)nullptr, (int32_t *)nullptr, ne + 1);
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (int32_t *)nullptr, (int32_t *)nullptr,
+                                         (int32_t *)nullptr, (int32_t *)nullptr, ne) != hipSuccess ||
+      hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (int32_t *)nullptr, (int32_t *)nullptr, ne + 1) !=
+          hipSuccess)
+    return false;
   b.temp_bytes = sort_bytes > scan_bytes ? sort_bytes : scan_bytes;
   b.cnt = (int32_t *)alloc((size_t)ne * 4, user);
   b.iota = (int32_t *)alloc((size_t)ne * 4, user);
@@ -184,30 +186,35 @@ bool redist_alloc(RedistBuf &b, int32_t ne, int64_t np, void *(*alloc)(size_t, v
 }
 
 template <typename T>
-void launch_redistribute(hipStream_t s, const KArgs *dka, const RedistBuf &b, const double *sums, int stride,
-                         PartDev<T> p, int32_t min_ppe, uint64_t seed, uint32_t step, unsigned long long *cnt) {
+hipError_t launch_redistribute(hipStream_t s, const KArgs *dka, const RedistBuf &b, const double *sums, int stride,
+                               PartDev<T> p, int32_t min_ppe, uint64_t seed, uint32_t step,
+                               unsigned long long *cnt) {
   const int32_t ne = b.ne;
   const unsigned ge = (unsigned)((ne + 255) / 256);
   hipLaunchKernelGGL(k_counts_from_sums, dim3(ge), dim3(256), 0, s, ne, sums, stride, b.cnt, b.iota);
   size_t tb = b.temp_bytes;
-  hipcub::DeviceRadixSort::SortPairs(b.temp, tb, b.cnt, b.skey, b.iota, b.sval, ne, 0, 32, s);
+  hipError_t he = hipcub::DeviceRadixSort::SortPairs(b.temp, tb, b.cnt, b.skey, b.iota, b.sval, ne, 0, 32, s);
+  if (he != hipSuccess) return he;
   (void)hipMemsetAsync(b.role, 0xFF, (size_t)ne * 4, s);  // -1: no role
   (void)hipMemsetAsync(b.npairs, 0, 4, s);
   (void)hipMemsetAsync(b.psize + ne, 0, 4, s);
   hipLaunchKernelGGL(k_redist_plan, dim3(ge), dim3(256), 0, s, ne, min_ppe, b.skey, b.sval, b.plan, b.role,
                      b.psize, b.npairs);
   tb = b.temp_bytes;
-  hipcub::DeviceScan::ExclusiveSum(b.temp, tb, b.psize, b.poff, ne + 1, s);
+  he = hipcub::DeviceScan::ExclusiveSum(b.temp, tb, b.psize, b.poff, ne + 1, s);
+  if (he != hipSuccess) return he;
   (void)hipMemsetAsync(b.fill, 0, (size_t)ne * 2 * 4, s);
   hipLaunchKernelGGL(k_redist_collect<T>, dim3((unsigned)((b.np + 255) / 256)), dim3(256), 0, s, b.np, p.e,
                      b.role, b.plan, b.poff, b.fill, b.fill + ne, b.list, b.npairs);
   hipLaunchKernelGGL(k_redist_apply<T>, dim3(1024), dim3(256), 0, s, dka, p, b.plan, b.poff, b.list, b.npairs,
                      (uint32_t)seed, (uint32_t)(seed >> 32), step, cnt);
+  return hipGetLastError();
 }
 
-template void launch_redistribute<float>(hipStream_t, const KArgs *, const RedistBuf &, const double *, int,
-                                         PartDev<float>, int32_t, uint64_t, uint32_t, unsigned long long *);
-template void launch_redistribute<double>(hipStream_t, const KArgs *, const RedistBuf &, const double *, int,
-                                          PartDev<double>, int32_t, uint64_t, uint32_t, unsigned long long *);
+template hipError_t launch_redistribute<float>(hipStream_t, const KArgs *, const RedistBuf &, const double *, int,
+                                               PartDev<float>, int32_t, uint64_t, uint32_t, unsigned long long *);
+template hipError_t launch_redistribute<double>(hipStream_t, const KArgs *, const RedistBuf &, const double *, int,
+                                                PartDev<double>, int32_t, uint64_t, uint32_t,
+                                                unsigned long long *);
 
 }  // namespace pdfk

@@ -232,10 +232,12 @@ bool cond_alloc(CondBuf &b, int32_t ne, int64_t np, size_t tsize, void *(*alloc)
 // elem_sums: the element sums of the last accumulation when their count slot
 // holds the current particles per element (else null: counted afresh)
 template <typename T>
-void launch_cond_means(hipStream_t s, const ModelDev &md, const CondBuf &b, PartDev<T> p, const double *elem_sums);
+hipError_t launch_cond_means(hipStream_t s, const ModelDev &md, const CondBuf &b, PartDev<T> p,
+                             const double *elem_sums);
 template <typename T>
-void launch_redistribute(hipStream_t s, const KArgs *dka, const RedistBuf &b, const double *sums, int stride,
-                         PartDev<T> p, int32_t min_ppe, uint64_t seed, uint32_t step, unsigned long long *cnt);
+hipError_t launch_redistribute(hipStream_t s, const KArgs *dka, const RedistBuf &b, const double *sums, int stride,
+                               PartDev<T> p, int32_t min_ppe, uint64_t seed, uint32_t step,
+                               unsigned long long *cnt);
 
 // ---- launchers (defined in the kernel translation units) ----
 template <typename T>
