@@ -285,10 +285,13 @@ def test_kernel_parity_fp32_channel_block_full_size_sampled(L):
     say("oracle step on the 1% sample done")
     sel = mask.astype(bool)
     assert np.array_equal(el1[sel], o.elem[sel]), f"{(el1[sel] != o.elem[sel]).sum()} element mismatches"
-    compare_state(st1[:, sel], o.state[:, sel], w.mesh, 1e-5, "channel_block fp32 step (sample)")
+    es = compare_state(st1[:, sel], o.state[:, sel], w.mesh, 1e-5, "channel_block fp32 step (sample)")
+    say("state error vs the FP64 oracle (max relative): " + ", ".join(f"{k} {v:.2e}" for k, v in es.items()))
     # nodal statistics: the oracle's estimate from the GPU's particles after the step
     o.state, o.elem = st1, el1
     o.stats = stats0
     est = o.estimate()
     say("oracle estimate done")
-    compare_stats(g1, est, 1e-9, what="channel_block statistics")
+    en = compare_stats(g1, est, 1e-9, what="channel_block statistics")
+    say("nodal statistics error vs the FP64 oracle (max relative, field: error): " +
+        ", ".join(f"{f}: {v:.1e}" for f, v in en.items()))
