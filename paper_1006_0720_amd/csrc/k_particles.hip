@@ -302,13 +302,24 @@ __global__ __launch_bounds__(256) void k_elem_prep(MeshDev m, ModelDev md, const
 #undef AVG
   double dU[3][2], gs[2];
   elem_gradients(m, S, e, qk, dU, gs);
-  T *r = rec + (size_t)e * NREC;
   // the element centroid locates the element for the source-aware t_m
   const ElemGeo &g = m.geo[e];
   const double cx = (g.x[0] + g.x[1] + g.x[2]) / 3.0, cy = (g.y[0] + g.y[1] + g.y[2]) / 3.0;
+  // formed in registers, stored as whole 16-byte words (the record is
+  // NREC * sizeof(T) = 128 or 256 bytes, aligned)
+  T r[NREC];
   record_from<T>(md, U, Om, Phi, R, lap, gp, W, dU, gs, dt, cx, cy, r);
   r[30] = (T)0;
   r[31] = (T)0;
+  using V4 = std::conditional_t<sizeof(T) == 4, float4, double2>;
+  constexpr int PER = 16 / sizeof(T);
+  V4 *dst = reinterpret_cast<V4 *>(rec + (size_t)e * NREC);
+#pragma unroll
+  for (int k = 0; k < NREC / PER; ++k) {
+    V4 v;
+    __builtin_memcpy(&v, &r[k * PER], 16);
+    dst[k] = v;
+  }
 }
 
 // SHAPE records: the raw statistics of the element's three nodes and the
