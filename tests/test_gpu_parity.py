@@ -295,3 +295,61 @@ def test_kernel_parity_fp32_channel_block_full_size_sampled(L):
     en = compare_stats(g1, est, 1e-9, what="channel_block statistics")
     say("nodal statistics error vs the FP64 oracle (max relative, field: error): " +
         ", ".join(f"{f}: {v:.1e}" for f, v in en.items()))
+
+
+def test_kernel_parity_fp32_channel_block_driven_200_steps(L):
+    """The benchmark workload over 200 steps in the benchmark's launch
+    configuration, compared with the FP64 oracle in driven mode: at steps 20,
+    40, ..., 200 the oracle advances a fresh 1% particle sample one step from
+    the GPU's state and statistics, and that step's elements must match
+    bit-exactly and the state within 1e-5 (the comparison re-synchronises each
+    time, so FP32 rounding does not accumulate into it).  At the end the nodal
+    statistics equal the oracle's estimate from the GPU's particles (1e-9)."""
+    import time
+
+    from paper_1006_0720_amd.runner import workload_context
+
+    t0 = time.time()
+
+    def say(msg):
+        print(f"[driven c5] {time.time() - t0:6.1f}s {msg}", flush=True)
+
+    w = CF.channel_block()
+    say(f"{w.name} np={w.n_particles}")
+    ctx = workload_context(w, reorder_every=8)
+    rng = np.random.default_rng(7)
+    worst = {}
+    done = 0
+    for k in range(1, 11):
+        ctx.advance(20 * k - done, w.dt)  # to step 20k (the reorder follows steps 8, 16, ...)
+        done = 20 * k
+        st0, el0, pid0 = ctx.particles(sort_by_id=False)
+        stats0 = ctx.stats()
+        ctx.advance(1, w.dt)  # step 20k + 1 is odd: no reorder, storage order kept
+        done += 1
+        st1, el1, pid1 = ctx.particles(sort_by_id=False)
+        assert np.array_equal(pid0, pid1)
+        o = O.Oracle(w.mesh, w.params, store_fp32=True, gradp=w.gradp)
+        o.state, o.elem, o.id = st0, el0.copy(), pid0
+        o.seed_value = int(w.seed["seed"])
+        o.step_index = 20 * k
+        o.set_stats(stats0)
+        mask = np.zeros(st0.shape[1], np.uint8)
+        mask[rng.choice(mask.size, mask.size // 100, replace=False)] = 1
+        o.step(w.dt, mask=mask)
+        sel = mask.astype(bool)
+        assert np.array_equal(el1[sel], o.elem[sel]), f"step {20 * k + 1}: {(el1[sel] != o.elem[sel]).sum()} element mismatches"
+        es = compare_state(st1[:, sel], o.state[:, sel], w.mesh, 1e-5, f"channel_block step {20 * k + 1} (sample)")
+        worst = {n: max(worst.get(n, 0.0), e) for n, e in es.items()}
+        say(f"step {20 * k + 1}: " + ", ".join(f"{n} {e:.1e}" for n, e in es.items()))
+    c = ctx.counters()
+    assert c["lost"] == 0 and c["nonfinite"] == 0
+    g1 = ctx.stats()
+    _, elst = ctx.stats(elem=True)
+    ctx.close()
+    assert elst[0].sum() == w.n_particles
+    o.state, o.elem = st1, el1
+    o.stats = stats0
+    en = compare_stats(g1, o.estimate(), 1e-9, what="channel_block statistics after 201 steps")
+    say("worst state error over the 10 driven steps: " + ", ".join(f"{n} {e:.1e}" for n, e in worst.items()))
+    say("nodal statistics error after 201 steps (max over fields): %.1e" % max(en.values()))
