@@ -133,8 +133,10 @@ def cpu_baseline(wname, w):
 
 
 def denoise_study(mode, out_path=""):
-    """Learned-vs-plain cost at equal nodal-statistics error on the street-canyon
-    mesh (denoiser trained on the GPU from 10 vs 200 particles/element runs)."""
+    """Learned-vs-plain cost at equal nodal-statistics error: on the street-
+    canyon mesh (denoiser trained on the GPU from 10 vs 200 particles/element
+    runs), or ('c5') on the 1M-triangle channel with a floor block (10 vs 100
+    particles/element, the scalar line placed at a different x in each run)."""
     import numpy as np
 
     from paper_1006_0720_amd.denoise_study import study
@@ -143,17 +145,28 @@ def denoise_study(mode, out_path=""):
 
     fed = mode.endswith("-fed")
     mode = mode[:-4] if fed else mode
-    if mode == "quick":
-        mesh = M.canyon(20_000, 0.15, 0)
-        kw = dict(n_train=6, n_test=2, steps_spin=40, n_snap=4, every=10, train_steps=600,
-                  batch=4096, eval_ppes=(20, 40))
-    else:
-        mesh = M.canyon(200_000, 0.15, 0)
+    if mode == "c5":
+        mesh = M.channel_block(1_000_000, 0.15, 0)
         kw = dict(n_train=12, n_test=3, steps_spin=100, n_snap=5, every=10, train_steps=8000,
-                  batch=8192, eval_ppes=(20, 40, 80))
+                  batch=8192, ppe_low=10, ppe_high=100, eval_ppes=(20, 40),
+                  source_box=(1.0, 4.0, 0.5, 1.5, 0.05))
 
-    def make(ppe, seed, src):
-        return CF.canyon(mesh=mesh, ppe=ppe, seed=seed, src=src)
+        def make(ppe, seed, src):
+            w = CF.channel_block(mesh=mesh, ppe=ppe, seed=seed)
+            w.seed = dict(w.seed, a=src[0])  # the Gaussian scalar line at x = src[0]
+            return w
+    else:
+        if mode == "quick":
+            mesh = M.canyon(20_000, 0.15, 0)
+            kw = dict(n_train=6, n_test=2, steps_spin=40, n_snap=4, every=10, train_steps=600,
+                      batch=4096, eval_ppes=(20, 40))
+        else:
+            mesh = M.canyon(200_000, 0.15, 0)
+            kw = dict(n_train=12, n_test=3, steps_spin=100, n_snap=5, every=10, train_steps=8000,
+                      batch=8192, eval_ppes=(20, 40, 80))
+
+        def make(ppe, seed, src):
+            return CF.canyon(mesh=mesh, ppe=ppe, seed=seed, src=src)
 
     if fed:  # statistics fed back, particle redistribution keeping 3 per element
         kw.update(frozen=False, min_ppe=3)
@@ -195,7 +208,8 @@ def main():
     ap.add_argument("--denoise-study", default="",
                     help="run the learned-vs-plain study on the canyon mesh: 'full' or 'quick' (coefficients "
                          "frozen), 'full-fed' or 'quick-fed' (statistics fed back, redistribution with a "
-                         "minimum of 3 per element); the result is added as learned_vs_plain")
+                         "minimum of 3 per element); 'c5' or 'c5-fed' on the 1M-triangle channel with a floor "
+                         "block at 10 vs 100 per element; the result is added as learned_vs_plain")
     ap.add_argument("--study-out", default="", help="write the study result and weights here (.json/.npz)")
     args = ap.parse_args()
 
