@@ -431,9 +431,9 @@ constexpr int PPT = PDF_PPT;             // most particles per thread: chunk of 
 // flush.
 constexpr int64_t MIN_WGS = 2048;
 constexpr int64_t CHUNK_ELEMS = 48;
-inline int pick_ppt(int64_t np, int64_t ne) {
+inline int pick_ppt(int64_t np, int64_t ne, int64_t chunk_elems = CHUNK_ELEMS) {
   int ppt = PPT;
-  while (ppt > 1 && (int64_t)WG * ppt * (ne > 0 ? ne : 1) > CHUNK_ELEMS * np) ppt >>= 1;
+  while (ppt > 1 && (int64_t)WG * ppt * (ne > 0 ? ne : 1) > chunk_elems * np) ppt >>= 1;
   while (ppt > 1 && (np + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt) < MIN_WGS) ppt >>= 1;
   return ppt;
 }
@@ -445,18 +445,31 @@ inline int pick_ppt(int64_t np, int64_t ne) {
 // padded by one word (TPAD) so that the copies of a value fall in different
 // LDS banks: unpadded, the copy stride is a multiple of the bank count and
 // the copies would conflict on the bank instead of on the address.
+//
+// Two geometries: at many particles per element (the default) 2^PDF_TAB_LOG2
+// slots with NCOPY copies; at few per element (below SPARSE_PPE) the lanes of
+// a wave seldom share an element, so one copy of 256 slots serves a chunk of
+// more elements in the same LDS, and the flush (one global atomic per value,
+// slot and workgroup) is spread over more particles.
 constexpr int TPAD = 1;
-struct SumTable {
-  int32_t key[TAB];
-  uint32_t n[NCOPY][TAB + TPAD];
-  double acc[NCOPY][15][TAB + TPAD];
+template <int LOG2, int COPIES>
+struct SumTableT {
+  static constexpr int SLOTS = 1 << LOG2, NC = COPIES;
+  int32_t key[SLOTS];
+  uint32_t n[COPIES][SLOTS + TPAD];
+  double acc[COPIES][15][SLOTS + TPAD];
 };
+using SumTable = SumTableT<PDF_TAB_LOG2, NCOPY>;
+using SumTableSparse = SumTableT<8, 1>;
+constexpr int64_t SPARSE_PPE = 32;           // mean particles per element below which the sparse table is used
+constexpr int64_t CHUNK_ELEMS_SPARSE = 120;  // elements' worth of particles per workgroup chunk with it
 
-__device__ __forceinline__ void table_init(SumTable &t) {
-  for (int s = threadIdx.x; s < TAB; s += blockDim.x) {
+template <int LOG2, int COPIES>
+__device__ __forceinline__ void table_init(SumTableT<LOG2, COPIES> &t) {
+  for (int s = threadIdx.x; s < SumTableT<LOG2, COPIES>::SLOTS; s += blockDim.x) {
     t.key[s] = -1;
 #pragma unroll
-    for (int c = 0; c < NCOPY; ++c) {
+    for (int c = 0; c < COPIES; ++c) {
       t.n[c][s] = 0u;
 #pragma unroll
       for (int f = 0; f < 15; ++f) t.acc[c][f][s] = 0.0;
@@ -464,25 +477,27 @@ __device__ __forceinline__ void table_init(SumTable &t) {
   }
 }
 
-__device__ __forceinline__ int table_slot(SumTable &t, int32_t e) {
-  uint32_t h = ((uint32_t)e * 2654435761u) >> (32 - PDF_TAB_LOG2);
-  for (int probe = 0; probe < TAB; ++probe) {
+template <int LOG2, int COPIES>
+__device__ __forceinline__ int table_slot(SumTableT<LOG2, COPIES> &t, int32_t e) {
+  constexpr int SL = SumTableT<LOG2, COPIES>::SLOTS;
+  uint32_t h = ((uint32_t)e * 2654435761u) >> (32 - LOG2);
+  for (int probe = 0; probe < SL; ++probe) {
     const int32_t k = __hip_atomic_load(&t.key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (k == e) return (int)h;
     if (k == -1) {
       const int32_t old = atomicCAS(&t.key[h], -1, e);
       if (old == -1 || old == e) return (int)h;
     }
-    h = (h + 1u) & (uint32_t)(TAB - 1);
+    h = (h + 1u) & (uint32_t)(SL - 1);
   }
   return -1;
 }
 
 // one particle's contribution to element e, shifted by the element's
 // reference means ref[0..4] (<U>, <V>, <W>, <omega>, <phi> of its record)
-template <typename T>
-__device__ __forceinline__ void table_add(SumTable &t, double *sums, const T ref[5], int32_t e, T u, T v,
-                                          T w, T om, T psi) {
+template <typename T, int LOG2, int COPIES>
+__device__ __forceinline__ void table_add(SumTableT<LOG2, COPIES> &t, double *sums, const T ref[5], int32_t e,
+                                          T u, T v, T w, T om, T psi) {
   const double q0 = (double)u - (double)ref[0], q1 = (double)v - (double)ref[1],
                q2 = (double)w - (double)ref[2], q3 = (double)om - (double)ref[3],
                q4 = (double)psi - (double)ref[4];
@@ -490,7 +505,7 @@ __device__ __forceinline__ void table_add(SumTable &t, double *sums, const T ref
                           q0 * q1, q0 * q2, q1 * q2, q4 * q4, q0 * q4, q1 * q4, q2 * q4};
   const int s = table_slot(t, e);
   if (s >= 0) {
-    const int c = (int)(threadIdx.x % NCOPY);
+    const int c = (int)(threadIdx.x % COPIES);
     atomicAdd(&t.n[c][s], 1u);
 #pragma unroll
     for (int f = 0; f < 15; ++f) unsafeAtomicAdd(&t.acc[c][f][s], val[f]);
@@ -502,21 +517,22 @@ __device__ __forceinline__ void table_add(SumTable &t, double *sums, const T ref
   }
 }
 
-__device__ __forceinline__ void table_flush(SumTable &t, double *sums) {
+template <int LOG2, int COPIES>
+__device__ __forceinline__ void table_flush(SumTableT<LOG2, COPIES> &t, double *sums) {
   __syncthreads();
-  for (int s = threadIdx.x; s < TAB; s += blockDim.x) {
+  for (int s = threadIdx.x; s < SumTableT<LOG2, COPIES>::SLOTS; s += blockDim.x) {
     const int32_t e = t.key[s];
     if (e < 0) continue;
     double *g = sums + (size_t)e * NSUM;
     uint32_t n = 0;
 #pragma unroll
-    for (int c = 0; c < NCOPY; ++c) n += t.n[c][s];
+    for (int c = 0; c < COPIES; ++c) n += t.n[c][s];
     unsafeAtomicAdd(&g[0], (double)n);
 #pragma unroll
     for (int f = 0; f < 15; ++f) {
       double a = 0.0;
 #pragma unroll
-      for (int c = 0; c < NCOPY; ++c) a += t.acc[c][f][s];
+      for (int c = 0; c < COPIES; ++c) a += t.acc[c][f][s];
       unsafeAtomicAdd(&g[1 + f], a);
     }
   }
@@ -768,13 +784,13 @@ __device__ __noinline__ double3 wall_function(const ModelDev &md, const double *
 template <typename T, bool SHAPE>
 constexpr int advance_waves() { return (sizeof(T) == 4 && !SHAPE) ? 3 : 1; }
 
-template <typename T, bool VISC, bool WALLB, bool SHAPE>
+template <typename T, bool VISC, bool WALLB, bool SHAPE, bool SPARSE>
 __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(const KArgs *__restrict__ ka, PartDev<T> p, int64_t np,
                                                 int ppt, const T *__restrict__ rec, double *sums, uint32_t k0,
                                                 uint32_t k1, uint32_t step, double dt, double sdt,
                                                 const double *dtp, double s2nu, const T *__restrict__ cm,
                                                 const double *S, const double *gradp, unsigned long long *cnt) {
-  __shared__ std::conditional_t<SHAPE, SumTableW, SumTable> tab;
+  __shared__ std::conditional_t<SHAPE, SumTableW, std::conditional_t<SPARSE, SumTableSparse, SumTable>> tab;
   const MeshDev &m = ka->m;
   const ModelDev &md = ka->md;
   if (dtp) {  // time step chosen on the device this step
@@ -1098,26 +1114,40 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
   wave_count(&cnt[PDF_CNT_NONFINITE], (int)((cb >> 40) & 0xFF));
 }
 
-template <typename T, bool SHAPE>
-void launch_advance_m(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
-                      int32_t ne, const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
-                      const double *dtp, const T *cm, const double *S, const double *gradp,
-                      unsigned long long *cnt) {
-  const int ppt = pick_ppt(np, ne);
+template <typename T, bool SHAPE, bool SPARSE>
+void launch_advance_k(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np, int ppt,
+                      const T *rec, double *sums, uint64_t seed, uint32_t step, double dt, const double *dtp,
+                      const T *cm, const double *S, const double *gradp, unsigned long long *cnt) {
   const unsigned grid = (unsigned)((np + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt));
   const bool visc = md.nu > 0.0;
   const bool wallb = visc && md.wall_b;
   const double sdt = sqrt(dt), s2nu = sqrt(2.0 * md.nu);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   if (visc && wallb)
-    hipLaunchKernelGGL((k_advance<T, true, true, SHAPE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt, rec,
-                       sums, k0, k1, step, dt, sdt, dtp, s2nu, cm, S, gradp, cnt);
-  else if (visc)
-    hipLaunchKernelGGL((k_advance<T, true, false, SHAPE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt, rec,
-                       sums, k0, k1, step, dt, sdt, dtp, s2nu, cm, S, gradp, cnt);
-  else
-    hipLaunchKernelGGL((k_advance<T, false, false, SHAPE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt,
+    hipLaunchKernelGGL((k_advance<T, true, true, SHAPE, SPARSE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt,
                        rec, sums, k0, k1, step, dt, sdt, dtp, s2nu, cm, S, gradp, cnt);
+  else if (visc)
+    hipLaunchKernelGGL((k_advance<T, true, false, SHAPE, SPARSE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt,
+                       rec, sums, k0, k1, step, dt, sdt, dtp, s2nu, cm, S, gradp, cnt);
+  else
+    hipLaunchKernelGGL((k_advance<T, false, false, SHAPE, SPARSE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt,
+                       rec, sums, k0, k1, step, dt, sdt, dtp, s2nu, cm, S, gradp, cnt);
+}
+
+template <typename T, bool SHAPE>
+void launch_advance_m(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np,
+                      int32_t ne, const T *rec, double *sums, uint64_t seed, uint32_t step, double dt,
+                      const double *dtp, const T *cm, const double *S, const double *gradp,
+                      unsigned long long *cnt) {
+  if constexpr (!SHAPE) {
+    if (np < SPARSE_PPE * (int64_t)ne) {  // few particles per element: the sparse table
+      launch_advance_k<T, false, true>(s, dka, md, p, np, pick_ppt(np, ne, CHUNK_ELEMS_SPARSE), rec, sums, seed,
+                                       step, dt, dtp, cm, S, gradp, cnt);
+      return;
+    }
+  }
+  launch_advance_k<T, SHAPE, false>(s, dka, md, p, np, pick_ppt(np, ne), rec, sums, seed, step, dt, dtp, cm, S,
+                                    gradp, cnt);
 }
 
 template <typename T>
