@@ -461,8 +461,14 @@ struct SumTableT {
 };
 using SumTable = SumTableT<PDF_TAB_LOG2, NCOPY>;
 using SumTableSparse = SumTableT<8, 1>;
-constexpr int64_t SPARSE_PPE = 32;           // mean particles per element below which the sparse table is used
-constexpr int64_t CHUNK_ELEMS_SPARSE = 120;  // elements' worth of particles per workgroup chunk with it
+#ifndef PDF_SPARSE_PPE
+#define PDF_SPARSE_PPE 45
+#endif
+constexpr int64_t SPARSE_PPE = PDF_SPARSE_PPE;  // mean particles per element below which the sparse table is used
+#ifndef PDF_CHUNK_SPARSE
+#define PDF_CHUNK_SPARSE 120
+#endif
+constexpr int64_t CHUNK_ELEMS_SPARSE = PDF_CHUNK_SPARSE;  // elements' worth of particles per workgroup chunk with it
 
 template <int LOG2, int COPIES>
 __device__ __forceinline__ void table_init(SumTableT<LOG2, COPIES> &t) {

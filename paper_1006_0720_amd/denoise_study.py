@@ -89,13 +89,14 @@ def study(make_workload, n_train=12, n_test=3, ppe_low=10, ppe_high=200, eval_pp
     feats, targs, lows, highs = [], [], [], []
     dn = None
     ctx_keep = None
-    t_low = []
+    t_low, t_high = [], []
     for r in range(n_train + n_test):
         c_lo, w, s_lo, tl, _ = _run(make_workload, ppe_low, 1000 + r, srcs[r], steps_spin, n_snap, every, F,
                                     min_ppe=min_ppe)
         t_low.append(tl)
-        c_hi, _, s_hi, _, _ = _run(make_workload, ppe_high, 5000 + r, srcs[r], steps_spin, n_snap, every, F,
-                                   min_ppe=min_ppe)
+        c_hi, _, s_hi, th, _ = _run(make_workload, ppe_high, 5000 + r, srcs[r], steps_spin, n_snap, every, F,
+                                    min_ppe=min_ppe)
+        t_high.append(th)
         c_hi.close()
         if dn is None:
             dn = _lib.Denoiser(c_lo, hidden=hidden, seed=seed)
@@ -190,18 +191,26 @@ def study(make_workload, n_train=12, n_test=3, ppe_low=10, ppe_high=200, eval_pp
     a_fit = float(np.sum(xfit * es ** 2) / np.sum(xfit * xfit))
     inv = E_learned ** 2 / a_fit - 1.0 / ppe_high
     ppe_eq = float(1.0 / inv) if inv > 0 else float("inf")
-    # step time linear in particle count
-    pt = np.array(sorted(T_plain))
-    tt = np.array([T_plain[p] for p in pt])
-    slope, icpt = np.polyfit(pt, tt, 1)
-    t_eq = float(slope * ppe_eq + icpt) if np.isfinite(ppe_eq) else float("inf")
+    # step time between the measured counts (the reference runs included):
+    # piecewise linear, since the kernel's launch shape changes with the count
+    T_plain[ppe_high] = float(np.mean(t_high))
+    pt = np.array(sorted(T_plain), dtype=float)
+    tt = np.array([T_plain[p] for p in sorted(T_plain)])
+
+    def t_at(pe):
+        if not np.isfinite(pe):
+            return float("inf")
+        if pe > pt[-1]:  # beyond the last point: its segment's slope
+            return float(tt[-1] + (pe - pt[-1]) * (tt[-1] - tt[-2]) / (pt[-1] - pt[-2]))
+        return float(np.interp(pe, pt, tt))
+
+    t_eq = t_at(ppe_eq)
     t_dn = float(np.median(t_den))
     ratio = t_eq / (T_plain[ppe_low] + t_dn)
     def eq_cost(E):
         inv = E ** 2 / a_fit - 1.0 / ppe_high
         pe = float(1.0 / inv) if inv > 0 else float("inf")
-        te = float(slope * pe + icpt) if np.isfinite(pe) else float("inf")
-        return pe, te / (T_plain[ppe_low] + t_dn)
+        return pe, t_at(pe) / (T_plain[ppe_low] + t_dn)
 
     tau_sweep = {}
     for tau_v, errs_t in e_tau.items():
@@ -210,7 +219,7 @@ def study(make_workload, n_train=12, n_test=3, ppe_low=10, ppe_high=200, eval_pp
         tau_sweep[str(tau_v)] = {"E_learned": Et, "ppe_eq": pe, "cost_ratio": cr}
     inv_nf = E_learned_nofb ** 2 / a_fit - 1.0 / ppe_high
     ppe_eq_nf = float(1.0 / inv_nf) if inv_nf > 0 else float("inf")
-    t_eq_nf = float(slope * ppe_eq_nf + icpt) if np.isfinite(ppe_eq_nf) else float("inf")
+    t_eq_nf = t_at(ppe_eq_nf)
     ratio_nf = t_eq_nf / (T_plain[ppe_low] + t_dn)
     out = {"E_plain": E_plain, "E_learned": E_learned, "E_learned_no_fallback": E_learned_nofb, "ppe_eq": ppe_eq, "a_fit": a_fit,
            "T_plain_s": T_plain, "T_denoise_s": t_dn, "cost_ratio": ratio,
