@@ -20,10 +20,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // round-to-nearest-even binary32 -> bfloat16 bits
 __device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  const uint32_t u = __float_as_uint(f);
+  const uint32_t r = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;  // to nearest, ties to even (inf stays inf)
+  return (uint16_t)((u & 0x7FFFFFFFu) > 0x7F800000u ? (u >> 16) | 0x40u : r);  // NaN stays a quiet NaN
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
@@ -112,21 +111,35 @@ void launch_gemm_bf16(hipStream_t s, int M, int N, int K, const uint16_t *A, int
   hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta, kchunk);
 }
 
-// GELU (exact, through erf) and its derivative
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// erf by the rational approximation of Abramowitz & Stegun (Handbook of
+// Mathematical Functions, formula 7.1.26; absolute error at most 1.5e-7):
+// one reciprocal and one exponential, no branches, where the library erff
+// takes about four times the instructions (it dominated the fused inference)
+__device__ __forceinline__ float erf_as(float x) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * ax);
+  const float poly = ((((1.061405429f * t - 1.453152027f) * t + 1.421413741f) * t - 0.284496736f) * t +
+                      0.254829592f) * t;
+  return copysignf(1.0f - poly * __expf(-ax * ax), x);
+}
+
+// GELU through erf, and its derivative
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float dgelu(float x) {
-  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.3989422804014327f * expf(-0.5f * x * x);
+  return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) + x * 0.3989422804014327f * __expf(-0.5f * x * x);
 }
 
 // ---------------------------------------------------------------------------
-// Fused inference: the whole MLP in one kernel.  A workgroup of 4 waves takes
-// 64 rows; each wave keeps its 16 rows' activations (bf16) in LDS through the
-// four layers, so activations never leave the CU.  Each layer's weights are
-// staged in LDS transposed ([n][k], k contiguous) so that both MFMA operands
-// are 8-byte LDS reads.  Rounding points are those of the layer-by-layer
+// Fused inference: the whole MLP in one kernel.  A workgroup of MLPF_WAVES
+// waves stages all four layers' weights (transposed, [n][k] with k contiguous,
+// so that both MFMA operands are 8-byte LDS reads) and biases in LDS once;
+// each wave then takes 16-row tiles in turn and keeps a tile's activations
+// (bf16) in LDS through the four layers, so neither weights nor activations
+// are re-read from memory, and the next tile's inputs are loaded while the
+// current one is computed.  Rounding points are those of the layer-by-layer
 // path: fp32 accumulation, + bias, GELU, bf16.
 // ---------------------------------------------------------------------------
-constexpr int MLP_ROWS = 64, MLP_PAD = 8;
+constexpr int MLP_PAD = 8, MLPF_WAVES = 8;
 
 __device__ __forceinline__ bf16x4 lds_frag(const uint16_t *p) {
   const uint2 v = *(const uint2 *)p;
@@ -168,95 +181,157 @@ __device__ __forceinline__ void stage_copy(const uint16_t *src, size_t n, uint16
   for (size_t t = threadIdx.x; t < n / 8; t += blockDim.x) d4[t] = s4[t];
 }
 
-// one layer for the calling wave: out[16][N] = act(in[16][K] W + b); four
-// independent accumulators per pass over K
-__device__ __forceinline__ void mlp_layer(const uint16_t *in, int K, const uint16_t *Wt, int N,
-                                          const float *b, bool gelu_act, uint16_t *out, float *y,
-                                          int64_t row0, int64_t nrows) {
+// NT 16-column tiles of one layer, starting at column n0, for the calling
+// wave's 16 rows: fp32 accumulation over K, then + bias and GELU (bf16 into
+// out) or + bias (fp32 into y, rows below nrows)
+template <int NT>
+__device__ __forceinline__ void mlp_pass(const uint16_t *in, int K, const uint16_t *Wt, int N, int n0,
+                                         const float *b, bool gelu_act, uint16_t *out, float *y, int64_t row0,
+                                         int64_t nrows) {
   const int lane = threadIdx.x & 63;
   const int ldi = K + MLP_PAD;
   const int kq = 4 * (lane >> 4), rc = lane & 15;
-  const int Np = (N + 15) & ~15;
-  for (int n0 = 0; n0 < Np; n0 += 64) {
-    const int nt_cnt = min(4, (Np - n0) / 16);
-    f32x4 acc[4];
+  f32x4 acc[NT];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc[u] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 16) {
-      const bf16x4 fa = lds_frag(in + rc * ldi + k0 + kq);
+  for (int u = 0; u < NT; ++u) acc[u] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const bf16x4 fa = lds_frag(in + rc * ldi + k0 + kq);
+    bf16x4 fb[NT];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (u < nt_cnt) {
-          const bf16x4 fb = lds_frag(Wt + (n0 + 16 * u + rc) * ldi + k0 + kq);
-          acc[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa, fb, acc[u], 0, 0, 0);
-        }
-    }
+    for (int u = 0; u < NT; ++u) fb[u] = lds_frag(Wt + (n0 + 16 * u + rc) * ldi + k0 + kq);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (u >= nt_cnt) break;
-      const int col = n0 + 16 * u + rc;
+    for (int u = 0; u < NT; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa, fb[u], acc[u], 0, 0, 0);
+  }
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    const int col = n0 + 16 * u + rc;
+    if (col < N) {
+      const float bc = b[col];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int row = kq + q;
-        if (col < N) {
-          const float z = acc[u][q] + b[col];
-          if (y) {
-            if (row0 + row < nrows) y[(row0 + row) * N + col] = z;
-          } else {
-            out[row * (N + MLP_PAD) + col] = f2bf(gelu_act ? gelu(z) : z);
-          }
+        const float z = acc[u][q] + bc;
+        if (y) {
+          if (row0 + row < nrows) y[(row0 + row) * N + col] = z;
+        } else {
+          out[row * (N + MLP_PAD) + col] = f2bf(gelu_act ? gelu(z) : z);
         }
       }
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_mlp_forward(int64_t n, int H, const float *__restrict__ x,
-                                                     const uint16_t *__restrict__ Wt_all, const float *b1,
-                                                     const float *b2, const float *b3, const float *b4,
-                                                     float *y) {
-  extern __shared__ uint16_t lds[];
-  const int ldh = H + MLP_PAD, ldx = 48 + MLP_PAD;
-  uint16_t *Wt = lds;                               // one layer, [Np][K + PAD]
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  uint16_t *actA = lds + H * (H + MLP_PAD) + wave * 16 * ldh * 2;  // two [16][H + PAD] buffers
-  uint16_t *actB = actA + 16 * ldh;
-  const int64_t row0 = (int64_t)blockIdx.x * MLP_ROWS + wave * 16;
-  const size_t n1 = mlp_wt_elems(48, H), n2 = mlp_wt_elems(H, H), n4 = mlp_wt_elems(H, 8);
-  const uint16_t *Wt1 = Wt_all, *Wt2 = Wt1 + n1, *Wt3 = Wt2 + n2, *Wt4 = Wt3 + n2;
-  for (int t = lane; t < 16 * 48; t += 64) {
-    const int r = t / 48, k = t % 48;
-    const int64_t g = row0 + r;
-    actA[r * ldx + k] = f2bf(g < n ? x[g * 48 + k] : 0.f);
+// one layer for the calling wave: out[16][N] = act(in[16][K] W + b), in
+// passes of four 16-column tiles and a narrower last pass
+__device__ __forceinline__ void mlp_layer(const uint16_t *in, int K, const uint16_t *Wt, int N,
+                                          const float *b, bool gelu_act, uint16_t *out, float *y,
+                                          int64_t row0, int64_t nrows) {
+  const int Np = (N + 15) & ~15;
+  int n0 = 0;
+  for (; n0 + 64 <= Np; n0 += 64) mlp_pass<4>(in, K, Wt, N, n0, b, gelu_act, out, y, row0, nrows);
+  switch ((Np - n0) / 16) {
+    case 3: mlp_pass<3>(in, K, Wt, N, n0, b, gelu_act, out, y, row0, nrows); break;
+    case 2: mlp_pass<2>(in, K, Wt, N, n0, b, gelu_act, out, y, row0, nrows); break;
+    case 1: mlp_pass<1>(in, K, Wt, N, n0, b, gelu_act, out, y, row0, nrows); break;
+    default: break;
   }
-  stage_copy(Wt1, n1, Wt);
-  __syncthreads();
-  mlp_layer(actA, 48, Wt, H, b1, true, actB, nullptr, row0, n);
-  __syncthreads();
-  stage_copy(Wt2, n2, Wt);
-  __syncthreads();
-  mlp_layer(actB, H, Wt, H, b2, true, actA, nullptr, row0, n);
-  __syncthreads();
-  stage_copy(Wt3, n2, Wt);
-  __syncthreads();
-  mlp_layer(actA, H, Wt, H, b3, true, actB, nullptr, row0, n);
-  __syncthreads();
-  stage_copy(Wt4, n4, Wt);
-  __syncthreads();
-  mlp_layer(actB, H, Wt, 8, b4, false, nullptr, y, row0, n);
 }
 
-size_t mlp_forward_lds(int H) {
-  return ((size_t)H * (H + MLP_PAD) + 4 * 2 * 16 * (size_t)(H + MLP_PAD)) * sizeof(uint16_t);
+// orders one wave's LDS writes before its later LDS reads (no other wave
+// takes part)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// one 16-row tile of inputs (16 x 48 fp32, contiguous): 192 float4, three per
+// lane; rows at or beyond n read as zero
+__device__ __forceinline__ void mlp_load_tile(const float *__restrict__ x, int64_t tile, int64_t n, int lane,
+                                              float4 v[3]) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int q = lane + 64 * j;
+    const int64_t g = tile * 16 + q / 12;
+    v[j] = g < n ? ldg((const float4 *)(x + g * 48), (size_t)(q % 12)) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+__global__ __launch_bounds__(64 * MLPF_WAVES) void k_mlp_forward(int64_t n, int H, const float *__restrict__ x,
+                                                                 const uint16_t *__restrict__ Wt_all,
+                                                                 const float *b1, const float *b2,
+                                                                 const float *b3, const float *b4, float *y) {
+  extern __shared__ uint16_t lds[];
+  const int ldh = H + MLP_PAD, ldx = 48 + MLP_PAD;
+  const size_t n1 = mlp_wt_elems(48, H), n2 = mlp_wt_elems(H, H), n4 = mlp_wt_elems(H, 8);
+  const size_t nw = n1 + 2 * n2 + n4;  // a multiple of 8 (H is)
+  uint16_t *Wt1 = lds, *Wt2 = Wt1 + n1, *Wt3 = Wt2 + n2, *Wt4 = Wt3 + n2;
+  float *bl = (float *)(lds + nw);  // biases: H, H, H, 8
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint16_t *actA = (uint16_t *)(bl + 3 * H + 8) + wave * 32 * ldh;  // two [16][H + PAD] buffers
+  uint16_t *actB = actA + 16 * ldh;
+  {  // weights: four 16-byte loads in flight per thread before they are stored
+    const uint4 *s4 = (const uint4 *)Wt_all;
+    uint4 *d4 = (uint4 *)lds;
+    const int n16 = (int)(nw / 8), nt = (int)blockDim.x;
+    for (int t0 = (int)threadIdx.x; t0 < n16; t0 += 4 * nt) {
+      uint4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = s4[min(t0 + u * nt, n16 - 1)];  // in bounds; extra copies unused
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (t0 + u * nt < n16) d4[t0 + u * nt] = v[u];
+    }
+    for (int t = (int)threadIdx.x; t < 3 * H + 8; t += nt)
+      bl[t] = t < H ? b1[t] : t < 2 * H ? b2[t - H] : t < 3 * H ? b3[t - 2 * H] : b4[t - 3 * H];
+  }
+  const int64_t ntiles = (n + 15) / 16, tstride = (int64_t)gridDim.x * MLPF_WAVES;
+  int64_t tile = (int64_t)blockIdx.x * MLPF_WAVES + wave;
+  float4 xv[3];
+  mlp_load_tile(x, tile, n, lane, xv);
+  __syncthreads();  // every wave passes here exactly once
+  for (; tile < ntiles; tile += tstride) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int q = lane + 64 * j, r = q / 12, k = 4 * (q % 12);
+      uint2 w;
+      w.x = (uint32_t)f2bf(xv[j].x) | ((uint32_t)f2bf(xv[j].y) << 16);
+      w.y = (uint32_t)f2bf(xv[j].z) | ((uint32_t)f2bf(xv[j].w) << 16);
+      *(uint2 *)(actA + r * ldx + k) = w;
+    }
+    if (tile + tstride < ntiles) mlp_load_tile(x, tile + tstride, n, lane, xv);
+    const int64_t row0 = tile * 16;
+    wave_lds_sync();
+    mlp_layer(actA, 48, Wt1, H, bl, true, actB, nullptr, row0, n);
+    wave_lds_sync();
+    mlp_layer(actB, H, Wt2, H, bl + H, true, actA, nullptr, row0, n);
+    wave_lds_sync();
+    mlp_layer(actA, H, Wt3, H, bl + 2 * H, true, actB, nullptr, row0, n);
+    wave_lds_sync();
+    mlp_layer(actB, H, Wt4, 8, bl + 3 * H, false, nullptr, y, row0, n);
+    wave_lds_sync();
+  }
 }
 
 size_t mlp_transposed_elems(int H) { return mlp_wt_elems(48, H) + 2 * mlp_wt_elems(H, H) + mlp_wt_elems(H, 8); }
 
+size_t mlp_forward_lds(int H) {
+  return mlp_transposed_elems(H) * sizeof(uint16_t) + (3 * (size_t)H + 8) * sizeof(float) +
+         (size_t)MLPF_WAVES * 2 * 16 * (size_t)(H + MLP_PAD) * sizeof(uint16_t);
+}
+
 bool launch_mlp_forward(hipStream_t s, int64_t n, int H, const float *x, const uint16_t *Wt_all, const float *b1,
                         const float *b2, const float *b3, const float *b4, float *y) {
-  if (H < 48 || H > 128 || n <= 0) return false;  // LDS holds H x (H + 8) weights and the activations
-  const unsigned g = (unsigned)((n + MLP_ROWS - 1) / MLP_ROWS);
-  hipLaunchKernelGGL(k_mlp_forward, dim3(g), dim3(256), mlp_forward_lds(H), s, n, H, x, Wt_all, b1, b2, b3, b4, y);
+  // LDS holds all weights and each wave's activations: hidden widths 48..128, multiples of 16
+  if (H < 48 || H > 128 || H % 16 || n <= 0) return false;
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+    return false;
+  const int64_t tiles = (n + 15) / 16, wgs = (tiles + MLPF_WAVES - 1) / MLPF_WAVES;
+  const unsigned g = (unsigned)(wgs < ncu ? wgs : ncu);  // one workgroup per CU: the LDS holds one
+  hipLaunchKernelGGL(k_mlp_forward, dim3(g), dim3(64 * MLPF_WAVES), mlp_forward_lds(H), s, n, H, x, Wt_all, b1,
+                     b2, b3, b4, y);
   return true;
 }
 
@@ -397,28 +472,56 @@ __global__ __launch_bounds__(256) void k_features(MeshDev m, const int32_t *p2p_
   const double v0 = Sf[q];
   double sum = v0, sum2 = v0 * v0, mn = v0, mx = v0;
   int c = 1;
-  for (int32_t i = p2p_off[q]; i < p2p_off[q + 1]; ++i) {
-    const double v = Sf[p2p[i]];
-    sum += v;
-    sum2 += v * v;
-    mn = v < mn ? v : mn;
-    mx = v > mx ? v : mx;
-    c++;
+  // neighbours four at a time, so that their gathers are in flight together
+  // (the sums still run in list order)
+  const int32_t pb = p2p_off[q], pe = p2p_off[q + 1];
+  for (int32_t i = pb; i < pe; i += 4) {
+    int32_t jn[4];
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) jn[u] = p2p[min(i + u, pe - 1)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = Sf[jn[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u < pe) {
+        sum += v[u];
+        sum2 += v[u] * v[u];
+        mn = v[u] < mn ? v[u] : mn;
+        mx = v[u] > mx ? v[u] : mx;
+        c++;
+      }
   }
   const double mean = sum / c;
   double var = sum2 / c - mean * mean;
   var = var > 0.0 ? var : 0.0;
   double gx = 0.0, gy = 0.0;
   int ce = 0;
-  for (int32_t i = m.m2e_off[q]; i < m.m2e_off[q + 1]; ++i) {
-    const int32_t e = m.m2e[i];
-    const double *d = m.dN + 6 * (size_t)e;
-    for (int k = 0; k < 3; ++k) {
-      const double val = Sf[m.mnode[3 * e + k]];
-      gx += d[k] * val;
-      gy += d[3 + k] * val;
-    }
-    ce++;
+  const int32_t eb = m.m2e_off[q], ee = m.m2e_off[q + 1];
+  for (int32_t i = eb; i < ee; i += 2) {  // two elements at a time, summed in list order
+    int32_t e2[2], nd[6];
+    double d[12], val[6];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) e2[u] = m.m2e[min(i + u, ee - 1)];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) nd[3 * u + k] = m.mnode[3 * e2[u] + k];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) d[6 * u + k] = m.dN[6 * (size_t)e2[u] + k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) val[k] = Sf[nd[k]];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      if (i + u < ee) {
+        for (int k = 0; k < 3; ++k) {
+          gx += d[6 * u + k] * val[3 * u + k];
+          gy += d[6 * u + 3 + k] * val[3 * u + k];
+        }
+        ce++;
+      }
   }
   if (ce) {
     gx /= ce;
@@ -474,7 +577,11 @@ __global__ void k_merge(int nn, const int32_t *master, const double *S, const fl
         fb++;
     }
   }
-  if (nfall && fb) atomicAdd(nfall, (unsigned long long)fb);
+  // one atomic per wave: many nodes reject a correction, and one counter
+  // taking an atomic from each of them serialises the launch
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) fb += __shfl_xor(fb, o, 64);
+  if (nfall && fb && (threadIdx.x & 63) == 0) atomicAdd(nfall, (unsigned long long)fb);
 }
 
 void launch_merge(hipStream_t s, int nn, const int32_t *master, const double *S, const float *R, int ldr,
