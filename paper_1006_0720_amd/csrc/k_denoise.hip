@@ -19,10 +19,13 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // round-to-nearest-even binary32 -> bfloat16 bits
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  const uint32_t u = __float_as_uint(f);
-  const uint32_t r = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;  // to nearest, ties to even (inf stays inf)
-  return (uint16_t)((u & 0x7FFFFFFFu) > 0x7F800000u ? (u >> 16) | 0x40u : r);  // NaN stays a quiet NaN
+// fp32 -> bf16 bits, to nearest with ties to even (the conversion instruction)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+// two values in one word, a in the low half
+__device__ __forceinline__ uint32_t f2bf2(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2v){a, b}, bf16x2v));
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
@@ -117,14 +120,17 @@ void launch_gemm_bf16(hipStream_t s, int M, int N, int K, const uint16_t *A, int
 // takes about four times the instructions (it dominated the fused inference)
 __device__ __forceinline__ float erf_as(float x) {
   const float ax = fabsf(x);
-  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * ax);
-  const float poly = ((((1.061405429f * t - 1.453152027f) * t + 1.421413741f) * t - 0.284496736f) * t +
-                      0.254829592f) * t;
-  return copysignf(1.0f - poly * __expf(-ax * ax), x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+  const float poly =
+      fmaf(fmaf(fmaf(fmaf(1.061405429f, t, -1.453152027f), t, 1.421413741f), t, -0.284496736f), t, 0.254829592f) * t;
+  return copysignf(fmaf(-poly, __expf(-ax * ax), 1.0f), x);
 }
 
 // GELU through erf, and its derivative
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu(float x) {
+  const float h = 0.5f * x;
+  return fmaf(h, erf_as(x * 0.70710678118654752f), h);
+}
 __device__ __forceinline__ float dgelu(float x) {
   return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) + x * 0.3989422804014327f * __expf(-0.5f * x * x);
 }
@@ -183,7 +189,9 @@ __device__ __forceinline__ void stage_copy(const uint16_t *src, size_t n, uint16
 
 // NT 16-column tiles of one layer, starting at column n0, for the calling
 // wave's 16 rows: fp32 accumulation over K, then + bias and GELU (bf16 into
-// out) or + bias (fp32 into y, rows below nrows)
+// out) or + bias (fp32 into y, rows below nrows).  The product is formed
+// transposed (weights as the first MFMA operand), so that each lane ends
+// with four adjacent columns of one row: one 8-byte LDS store per tile.
 template <int NT>
 __device__ __forceinline__ void mlp_pass(const uint16_t *in, int K, const uint16_t *Wt, int N, int n0,
                                          const float *b, bool gelu_act, uint16_t *out, float *y, int64_t row0,
@@ -200,23 +208,28 @@ __device__ __forceinline__ void mlp_pass(const uint16_t *in, int K, const uint16
 #pragma unroll
     for (int u = 0; u < NT; ++u) fb[u] = lds_frag(Wt + (n0 + 16 * u + rc) * ldi + k0 + kq);
 #pragma unroll
-    for (int u = 0; u < NT; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa, fb[u], acc[u], 0, 0, 0);
+    for (int u = 0; u < NT; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fb[u], fa, acc[u], 0, 0, 0);
   }
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
-    const int col = n0 + 16 * u + rc;
-    if (col < N) {
-      const float bc = b[col];
+    const int c0 = n0 + 16 * u + kq;  // this lane's columns c0 .. c0 + 3 of row rc
+    if (c0 >= N) continue;
+    if (y) {
+      if (row0 + rc < nrows)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (c0 + q < N) y[(row0 + rc) * N + c0 + q] = acc[u][q] + b[c0 + q];
+    } else {  // N is a multiple of 16 here
+      float g[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int row = kq + q;
-        const float z = acc[u][q] + bc;
-        if (y) {
-          if (row0 + row < nrows) y[(row0 + row) * N + col] = z;
-        } else {
-          out[row * (N + MLP_PAD) + col] = f2bf(gelu_act ? gelu(z) : z);
-        }
+        const float z = acc[u][q] + b[c0 + q];
+        g[q] = gelu_act ? gelu(z) : z;
       }
+      uint2 w;
+      w.x = f2bf2(g[0], g[1]);
+      w.y = f2bf2(g[2], g[3]);
+      *(uint2 *)(out + rc * (N + MLP_PAD) + c0) = w;
     }
   }
 }
