@@ -1505,7 +1505,6 @@ pdf_status pdf_denoise_stats(pdf_denoiser *d, double tau, double *out, int32_t o
   if (!R || !res) return fail(c, PDF_E_OOM, "denoiser output buffers");
   pdf_status st = pdf_denoiser_forward(d, d->feat, nn, R);
   if (st != PDF_OK) return st;
-  HIPCHK(c, hipMemcpyAsync(res, c->latest, (size_t)PDF_NSTAT * nn * 8, hipMemcpyDeviceToDevice, s));
   HIPCHK(c, hipMemsetAsync(d->nfall, 0, 8, s));
   launch_merge(s, nn, c->md.master, c->latest, R, PDF_DN_NOUT, d->scale, tau, c->params.C4, res, d->nfall);
   HIPCHK(c, hipGetLastError());

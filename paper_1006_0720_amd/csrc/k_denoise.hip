@@ -468,7 +468,8 @@ void launch_to_bf16(hipStream_t s, int64_t n, const float *x, uint16_t *y) {
 // (eq:gradient in the surrounding elements, averaged).  Output row n: 48
 // features, standardised with (x - mu) / sigma, as bf16 and fp32.
 // ---------------------------------------------------------------------------
-__constant__ int kQuant[8] = {0, 1, 4, 5, 6, 8, 11, 3};
+constexpr int kQuant[8] = {0, 1, 4, 5, 6, 8, 11, 3};
+__constant__ int kQuantDev[8] = {0, 1, 4, 5, 6, 8, 11, 3};
 
 // one thread per (node, statistic): the 6 features of statistic a at node n
 __global__ __launch_bounds__(256) void k_features(MeshDev m, const int32_t *p2p_off, const int32_t *p2p,
@@ -480,7 +481,7 @@ __global__ __launch_bounds__(256) void k_features(MeshDev m, const int32_t *p2p_
   if (n >= m.nn) return;
   const int nn = m.nn;
   const int32_t q = m.master[n];
-  const int fld = kQuant[a];
+  const int fld = kQuantDev[a];
   const double *Sf = S + (size_t)fld * nn;
   const double v0 = Sf[q];
   double sum = v0, sum2 = v0 * v0, mn = v0, mx = v0;
@@ -561,7 +562,7 @@ void launch_features(hipStream_t s, const MeshDev &m, const int32_t *p2p_off, co
 // Standard errors from the plain second moments and the particle support N:
 // <U>: sqrt(<uu>/N), <V>: sqrt(<vv>/N), <phi>: sqrt(<phi'^2>/N), second
 // moments s: s sqrt(2/N), <uv>: sqrt((<uu><vv> + <uv>^2)/N), <omega>: <omega>
-// sqrt(C4/N).  out starts as a copy of the plain statistics.
+// sqrt(C4/N).  Every other statistic is copied from the plain estimate.
 __global__ void k_merge(int nn, const int32_t *master, const double *S, const float *R, int ldr,
                         const float *scale, double tau, double C4, double *out, unsigned long long *nfall) {
   const int32_t n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -581,13 +582,24 @@ __global__ void k_merge(int nn, const int32_t *master, const double *S, const fl
     se[5] = sqrt((fabs(uu * vv) + uv * uv) * iN);
     se[6] = fabs(pp) * sqrt(2.0 * iN);
     se[7] = fabs(om) * sqrt(C4 * iN);
+    double mv[8];
+    bool ok[8];
+#pragma unroll
     for (int a = 0; a < 8; ++a) {
       const int fld = kQuant[a];
       const double corr = (double)scale[a] * (double)R[(size_t)n * ldr + a];
-      if (fabs(corr) <= tau * se[a])
-        out[(size_t)fld * nn + n] = S[(size_t)fld * nn + q] + corr;
-      else
-        fb++;
+      ok[a] = fabs(corr) <= tau * se[a];
+      mv[a] = S[(size_t)fld * nn + q] + corr;
+      fb += ok[a] ? 0 : 1;
+    }
+    // all statistics written, every line whole
+#pragma unroll
+    for (int f = 0; f < PDF_NSTAT; ++f) {
+      double v = S[(size_t)f * nn + n];
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (kQuant[a] == f && ok[a]) v = mv[a];
+      out[(size_t)f * nn + n] = v;
     }
   }
   // one atomic per wave: many nodes reject a correction, and one counter
