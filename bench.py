@@ -132,6 +132,29 @@ def cpu_baseline(wname, w):
             "host_cpu": host_cpu()}
 
 
+def denoise_timing(ctx, calls):
+    """Wall time of one pdf_denoise_stats call on the context's latest
+    statistics (the call ends with a stream synchronisation)."""
+    import numpy as np
+    import torch
+
+    from paper_1006_0720_amd import _lib
+
+    dn = _lib.Denoiser(ctx, hidden=128, seed=1)
+    dn.set_norm(np.zeros(48, np.float32), np.ones(48, np.float32), np.ones(8, np.float32))
+    for _ in range(3):
+        dn.denoise(3.0, device=True)
+    ts = []
+    for _ in range(calls):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dn.denoise(3.0, device=True)
+        ts.append(time.perf_counter() - t0)
+    dn.close()
+    return {"n_nodes": ctx.n_nodes, "hidden": 128, "calls": calls, "ms_per_call_median": 1e3 * float(np.median(ts)),
+            "weights": "seeded, untrained"}
+
+
 def denoise_study(mode, out_path=""):
     """Learned-vs-plain cost at equal nodal-statistics error: on the street-
     canyon mesh (denoiser trained on the GPU from 10 vs 200 particles/element
@@ -210,6 +233,9 @@ def main():
                          "frozen), 'full-fed' or 'quick-fed' (statistics fed back, redistribution with a "
                          "minimum of 3 per element); 'c5' or 'c5-fed' on the 1M-triangle channel with a floor "
                          "block at 10 vs 100 per element; the result is added as learned_vs_plain")
+    ap.add_argument("--denoise-calls", type=int, default=0,
+                    help="also time this many pdf_denoise_stats calls (features, fused MLP, merge; H = 128, "
+                         "seeded untrained weights) on the workload's nodal statistics")
     ap.add_argument("--study-out", default="", help="write the study result and weights here (.json/.npz)")
     args = ap.parse_args()
 
@@ -306,6 +332,8 @@ def main():
         "counters": {k: cnt[k] for k in ("lost", "brute", "fallback", "nonfinite", "empty_node", "redist",
                                          "ell_iters", "proj_iters")},
     }
+    if args.denoise_calls > 0:
+        out["denoise_inference"] = denoise_timing(ctx, args.denoise_calls)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, w)
     ctx.close()
