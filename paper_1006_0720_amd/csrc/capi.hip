@@ -1206,6 +1206,7 @@ struct pdf_denoiser {
   int64_t adam_t = 0;
   // point-surrounding-point lists over master nodes
   int32_t *p2p_off = nullptr, *p2p = nullptr;
+  double2 *gw = nullptr;  // gradient weights: masters' own [n_nodes], then ring entries
   // batch buffers
   int32_t cap = 0;
   uint16_t *Xb = nullptr, *H1 = nullptr, *H2 = nullptr, *H3 = nullptr, *dYb = nullptr, *dZb = nullptr;
@@ -1323,9 +1324,24 @@ pdf_status pdf_denoiser_create(pdf_ctx *c, int32_t hidden, uint64_t seed, pdf_de
   d->p2p_off = (int32_t *)cp;
   ok = ok && upload(c, plist, &cp);
   d->p2p = (int32_t *)cp;
+  d->gw = (double2 *)dalloc(c, ((size_t)nn + plist.size()) * sizeof(double2));
+  ok = ok && d->gw;
   if (!ok) {
     pdf_denoiser_destroy(d);
     return fail(c, PDF_E_OOM, "denoiser allocation failed");
+  }
+  {
+    unsigned long long bad = 0;
+    const bool run = hipMemsetAsync(d->nfall, 0, 8, c->stream) == hipSuccess &&
+                     (launch_grad_weights(c->stream, c->md, d->p2p_off, d->p2p, d->gw, d->nfall),
+                      hipGetLastError() == hipSuccess) &&
+                     hipMemcpyAsync(&bad, d->nfall, 8, hipMemcpyDeviceToHost, c->stream) == hipSuccess &&
+                     hipStreamSynchronize(c->stream) == hipSuccess;
+    if (!run || bad) {
+      pdf_denoiser_destroy(d);
+      return fail(c, PDF_E_DEVICE, run ? "denoiser set-up: an element node outside its master's ring"
+                                       : "denoiser set-up: the gradient weights failed");
+    }
   }
   // initial parameters: uniform in +-1/sqrt(fan_in) (splitmix64 stream), zero biases
   std::vector<float> h(o, 0.f);
@@ -1360,7 +1376,7 @@ void pdf_denoiser_destroy(pdf_denoiser *d) {
   (void)hipStreamSynchronize(c->stream);
   void *ps[] = {d->P, d->G, d->Mom, d->Vel, d->Pb, d->mu, d->sig, d->scale, d->p2p_off, d->p2p, d->Xb,
                 d->H1, d->H2, d->H3, d->dYb, d->dZb, d->Z1, d->Z2, d->Z3, d->Y, d->dH, d->part, d->feat,
-                d->nfall, d->Wt, d->R, d->res};
+                d->nfall, d->Wt, d->R, d->res, d->gw};
   for (void *p : ps) dfree(c, p);
   delete d;
 }
@@ -1399,7 +1415,7 @@ pdf_status pdf_denoiser_features(pdf_denoiser *d, const double *nodal, float *fe
   if (!d || !feat) return PDF_E_INVALID_ARG;
   pdf_ctx *c = d->ctx;
   if (!nodal && !c->seeded) return fail(c, PDF_E_STATE, "no statistics");
-  launch_features(c->stream, c->md, d->p2p_off, d->p2p, nodal ? nodal : c->latest,
+  launch_features(c->stream, c->md, d->p2p_off, d->p2p, d->gw, nodal ? nodal : c->latest,
                   standardized ? d->mu : nullptr, d->sig, feat, nullptr);
   HIPCHK(c, hipGetLastError());
   return PDF_OK;
@@ -1497,7 +1513,7 @@ pdf_status pdf_denoise_stats(pdf_denoiser *d, double tau, double *out, int32_t o
   if (!c->seeded) return fail(c, PDF_E_STATE, "no statistics");
   hipStream_t s = c->stream;
   const int32_t nn = c->md.nn;
-  launch_features(s, c->md, d->p2p_off, d->p2p, c->latest, d->mu, d->sig, d->feat, nullptr);
+  launch_features(s, c->md, d->p2p_off, d->p2p, d->gw, c->latest, d->mu, d->sig, d->feat, nullptr);
   if (!d->R) d->R = (float *)dalloc(c, (size_t)nn * PDF_DN_NOUT * 4);
   if (!on_device && !d->res) d->res = (double *)dalloc(c, (size_t)PDF_NSTAT * nn * 8);
   float *R = d->R;

@@ -472,9 +472,59 @@ constexpr int kQuant[8] = {0, 1, 4, 5, 6, 8, 11, 3};
 __constant__ int kQuantDev[8] = {0, 1, 4, 5, 6, 8, 11, 3};
 
 // one thread per (node, statistic): the 6 features of statistic a at node n
+// The averaged element gradient at a master q, (1/c) sum over the c elements
+// around q of sum_k dN_e,k f(node k), is linear in the values at q and at
+// its ring: weights w_j = (1/c) sum over (e, k) with node k of e = j of
+// dN_e,k, formed once per mesh.  gw[q] holds q's own weight, gw[nn + i] the
+// weight of ring entry i.  A ring entry that the elements do not reach
+// (none, by the ring's construction) is counted in bad.
+__global__ void k_grad_weights(MeshDev m, const int32_t *p2p_off, const int32_t *p2p, double2 *gw,
+                               unsigned long long *bad) {
+  const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m.nn) return;
+  const int32_t rb = p2p_off[q], re = p2p_off[q + 1];
+  double2 self = make_double2(0.0, 0.0);
+  for (int32_t i = rb; i < re; ++i) gw[m.nn + i] = make_double2(0.0, 0.0);
+  if (m.master[q] != q) {
+    gw[q] = self;
+    return;
+  }
+  const int32_t eb = m.m2e_off[q], ee = m.m2e_off[q + 1];
+  for (int32_t i = eb; i < ee; ++i) {
+    const int32_t e = m.m2e[i];
+    for (int k = 0; k < 3; ++k) {
+      const int32_t j = m.mnode[3 * e + k];
+      const double wx = m.dN[6 * (size_t)e + k], wy = m.dN[6 * (size_t)e + 3 + k];
+      if (j == q) {
+        self.x += wx;
+        self.y += wy;
+        continue;
+      }
+      int32_t pos = -1;
+      for (int32_t r = rb; r < re; ++r)
+        if (p2p[r] == j) pos = r;
+      if (pos < 0) {
+        atomicAdd(bad, 1ull);
+        continue;
+      }
+      gw[m.nn + pos].x += wx;
+      gw[m.nn + pos].y += wy;
+    }
+  }
+  const double ic = ee > eb ? 1.0 / (double)(ee - eb) : 0.0;
+  gw[q] = make_double2(self.x * ic, self.y * ic);
+  for (int32_t i = rb; i < re; ++i) gw[m.nn + i] = make_double2(gw[m.nn + i].x * ic, gw[m.nn + i].y * ic);
+}
+
+void launch_grad_weights(hipStream_t s, const MeshDev &m, const int32_t *p2p_off, const int32_t *p2p, double2 *gw,
+                         unsigned long long *bad) {
+  hipLaunchKernelGGL(k_grad_weights, dim3((unsigned)((m.nn + 255) / 256)), dim3(256), 0, s, m, p2p_off, p2p, gw,
+                     bad);
+}
+
 __global__ __launch_bounds__(256) void k_features(MeshDev m, const int32_t *p2p_off, const int32_t *p2p,
-                                                  const double *S, const float *mu, const float *sig,
-                                                  float *F, uint16_t *Fb) {
+                                                  const double2 *gw, const double *S, const float *mu,
+                                                  const float *sig, float *F, uint16_t *Fb) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t n = (int32_t)(t >> 3);
   const int a = (int)(t & 7);
@@ -485,6 +535,8 @@ __global__ __launch_bounds__(256) void k_features(MeshDev m, const int32_t *p2p_
   const double *Sf = S + (size_t)fld * nn;
   const double v0 = Sf[q];
   double sum = v0, sum2 = v0 * v0, mn = v0, mx = v0;
+  const double2 w0 = gw[q];
+  double gx = w0.x * v0, gy = w0.y * v0;  // the averaged element gradient, through the ring weights
   int c = 1;
   // neighbours four at a time, so that their gathers are in flight together
   // (the sums still run in list order)
@@ -492,13 +544,18 @@ __global__ __launch_bounds__(256) void k_features(MeshDev m, const int32_t *p2p_
   for (int32_t i = pb; i < pe; i += 4) {
     int32_t jn[4];
     double v[4];
+    double2 w[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) jn[u] = p2p[min(i + u, pe - 1)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) w[u] = gw[m.nn + min(i + u, pe - 1)];
 #pragma unroll
     for (int u = 0; u < 4; ++u) v[u] = Sf[jn[u]];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (i + u < pe) {
+        gx += w[u].x * v[u];
+        gy += w[u].y * v[u];
         sum += v[u];
         sum2 += v[u] * v[u];
         mn = v[u] < mn ? v[u] : mn;
@@ -509,38 +566,6 @@ __global__ __launch_bounds__(256) void k_features(MeshDev m, const int32_t *p2p_
   const double mean = sum / c;
   double var = sum2 / c - mean * mean;
   var = var > 0.0 ? var : 0.0;
-  double gx = 0.0, gy = 0.0;
-  int ce = 0;
-  const int32_t eb = m.m2e_off[q], ee = m.m2e_off[q + 1];
-  for (int32_t i = eb; i < ee; i += 2) {  // two elements at a time, summed in list order
-    int32_t e2[2], nd[6];
-    double d[12], val[6];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) e2[u] = m.m2e[min(i + u, ee - 1)];
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) nd[3 * u + k] = m.mnode[3 * e2[u] + k];
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int k = 0; k < 6; ++k) d[6 * u + k] = m.dN[6 * (size_t)e2[u] + k];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) val[k] = Sf[nd[k]];
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-      if (i + u < ee) {
-        for (int k = 0; k < 3; ++k) {
-          gx += d[6 * u + k] * val[3 * u + k];
-          gy += d[6 * u + 3 + k] * val[3 * u + k];
-        }
-        ce++;
-      }
-  }
-  if (ce) {
-    gx /= ce;
-    gy /= ce;
-  }
   const float f[6] = {(float)v0, (float)mean, (float)sqrt(var), (float)mn, (float)mx,
                       (float)sqrt(gx * gx + gy * gy)};
   for (int j = 0; j < 6; ++j) {
@@ -552,9 +577,10 @@ __global__ __launch_bounds__(256) void k_features(MeshDev m, const int32_t *p2p_
 }
 
 void launch_features(hipStream_t s, const MeshDev &m, const int32_t *p2p_off, const int32_t *p2p,
-                     const double *S, const float *mu, const float *sig, float *F, uint16_t *Fb) {
+                     const double2 *gw, const double *S, const float *mu, const float *sig, float *F,
+                     uint16_t *Fb) {
   hipLaunchKernelGGL(k_features, dim3((unsigned)(((int64_t)m.nn * 8 + 255) / 256)), dim3(256), 0, s, m, p2p_off,
-                     p2p, S, mu, sig, F, Fb);
+                     p2p, gw, S, mu, sig, F, Fb);
 }
 
 // Merge: q = q_plain + scale_q * r_q, except where |scale_q r_q| exceeds tau

@@ -318,7 +318,10 @@ void launch_transpose_weights(hipStream_t s, int H, const uint16_t *W1, const ui
 bool launch_mlp_forward(hipStream_t s, int64_t n, int H, const float *x, const uint16_t *Wt_all, const float *b1,
                         const float *b2, const float *b3, const float *b4, float *y);
 void launch_features(hipStream_t s, const MeshDev &m, const int32_t *p2p_off, const int32_t *p2p,
-                     const double *S, const float *mu, const float *sig, float *F, uint16_t *Fb);
+                     const double2 *gw, const double *S, const float *mu, const float *sig, float *F,
+                     uint16_t *Fb);
+void launch_grad_weights(hipStream_t s, const MeshDev &m, const int32_t *p2p_off, const int32_t *p2p, double2 *gw,
+                         unsigned long long *bad);
 void launch_merge(hipStream_t s, int nn, const int32_t *master, const double *S, const float *R, int ldr,
                   const float *scale, double tau, double C4, double *out, unsigned long long *nfall);
 }  // namespace pdfk
