@@ -786,6 +786,22 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
       for (int32_t j = ja[e]; j <= jb[e]; ++j)
         for (int32_t i = ia[e]; i <= ib[e]; ++i) cell_list[fill[(size_t)j * gnx + i]++] = e;
   }
+  // rings of the masters: the masters of the nodes of the elements around each
+  std::vector<int32_t> ring_off(nn + 1, 0), ring;
+  for (int32_t n = 0; n < nn; ++n) {
+    std::vector<int32_t> l;
+    if (vmaster[n] == n)
+      for (int32_t i = m2e_off[n]; i < m2e_off[n + 1]; ++i)
+        for (int k = 0; k < 3; ++k) {
+          const int32_t q = mnode[3 * (size_t)m2e[i] + k];
+          if (q != n && std::find(l.begin(), l.end(), q) == l.end()) l.push_back(q);
+        }
+    std::sort(l.begin(), l.end());
+    ring.insert(ring.end(), l.begin(), l.end());
+    ring_off[n + 1] = (int32_t)ring.size();
+  }
+  const size_t n_gw = (size_t)nn + ring.size();
+  if (ring.empty()) ring.push_back(0);  // never read: every ring is empty
   // ---- upload ----
   MeshDev &m = c->md;
   m.gnx = gnx;
@@ -808,7 +824,12 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
             upload(c, nwall_off, &m.nwall_off) && upload(c, nwall, &m.nwall) &&
             upload(c, masters, &m.masters) && upload(c, slaves, &m.slaves) &&
             upload(c, slave_master, &m.slave_master) && upload(c, cell_off, &m.cell_off) &&
-            upload(c, cell_list, &m.cell_list) && upload(c, cfl_len, &m.cfl_len);
+            upload(c, cell_list, &m.cell_list) && upload(c, cfl_len, &m.cfl_len) &&
+            upload(c, ring_off, &m.ring_off) && upload(c, ring, &m.ring);
+  double2 *gw = (double2 *)dalloc(c, n_gw * sizeof(double2));
+  unsigned long long *gw_bad = (unsigned long long *)dalloc(c, sizeof(unsigned long long));
+  m.gw = gw;
+  ok = ok && gw && gw_bad;
   const size_t ts = tsize(c);
   c->stats_a = (double *)dalloc(c, (size_t)PDF_NSTAT * nn * sizeof(double));
   c->stats_b = (double *)dalloc(c, (size_t)PDF_NSTAT * nn * sizeof(double));
@@ -844,10 +865,22 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
       hipMemsetAsync(c->rec, 0, (size_t)ne * nrec * ts, s) != hipSuccess ||
       hipMemsetAsync(c->emom, 0, (size_t)ne * 16 * sizeof(double), s) != hipSuccess ||
       hipMemsetAsync(c->cnt, 0, PDF_NCOUNTERS * sizeof(unsigned long long), s) != hipSuccess ||
+      hipMemsetAsync(gw_bad, 0, sizeof(unsigned long long), s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
     c->err = "device initialisation failed";
     pdf_destroy(c);
     return PDF_E_DEVICE;
+  }
+  {  // the gradient weights over the rings
+    unsigned long long bad = 0;
+    launch_grad_weights(s, m, m.ring_off, m.ring, gw, gw_bad);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&bad, gw_bad, sizeof(bad), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess || bad) {
+      c->err = bad ? "mesh set-up: an element node outside its master's ring" : "mesh set-up: gradient weights failed";
+      pdf_destroy(c);
+      return PDF_E_DEVICE;
+    }
   }
   ModelDev &md = c->model;
   md.model = params->model;
@@ -1205,8 +1238,8 @@ struct pdf_denoiser {
   bool norm_set = false;
   int64_t adam_t = 0;
   // point-surrounding-point lists over master nodes
-  int32_t *p2p_off = nullptr, *p2p = nullptr;
-  double2 *gw = nullptr;  // gradient weights: masters' own [n_nodes], then ring entries
+  const int32_t *p2p_off = nullptr, *p2p = nullptr;  // the mesh's rings (not owned)
+  const double2 *gw = nullptr;                       // and gradient weights (not owned)
   // batch buffers
   int32_t cap = 0;
   uint16_t *Xb = nullptr, *H1 = nullptr, *H2 = nullptr, *H3 = nullptr, *dYb = nullptr, *dZb = nullptr;
@@ -1291,57 +1324,14 @@ pdf_status pdf_denoiser_create(pdf_ctx *c, int32_t hidden, uint64_t seed, pdf_de
   d->nfall = (unsigned long long *)dalloc(c, 8);
   const int32_t nn = c->md.nn;
   d->feat = (float *)dalloc(c, (size_t)nn * PDF_DN_NIN * 4);
-  // points surrounding points (masters): masters of the nodes of the elements around each master
-  std::vector<int32_t> m2e_off(nn + 1), m2e, mnode(3 * (size_t)c->md.ne), master(nn);
-  bool copied = hipStreamSynchronize(c->stream) == hipSuccess &&
-                hipMemcpy(m2e_off.data(), c->md.m2e_off, (nn + 1) * 4, hipMemcpyDeviceToHost) == hipSuccess;
-  if (copied) {
-    m2e.resize(m2e_off[nn]);
-    copied = (m2e.empty() || hipMemcpy(m2e.data(), c->md.m2e, m2e.size() * 4, hipMemcpyDeviceToHost) == hipSuccess) &&
-             hipMemcpy(mnode.data(), c->md.mnode, mnode.size() * 4, hipMemcpyDeviceToHost) == hipSuccess &&
-             hipMemcpy(master.data(), c->md.master, nn * 4, hipMemcpyDeviceToHost) == hipSuccess;
-  }
-  if (!copied) {
-    pdf_denoiser_destroy(d);
-    return fail(c, PDF_E_DEVICE, "denoiser set-up: reading the mesh tables back failed");
-  }
-  std::vector<int32_t> poff(nn + 1, 0), plist;
-  for (int32_t n = 0; n < nn; ++n) {
-    std::vector<int32_t> l;
-    if (master[n] == n)
-      for (int32_t i = m2e_off[n]; i < m2e_off[n + 1]; ++i)
-        for (int k = 0; k < 3; ++k) {
-          const int32_t q = mnode[3 * (size_t)m2e[i] + k];
-          if (q != n && std::find(l.begin(), l.end(), q) == l.end()) l.push_back(q);
-        }
-    std::sort(l.begin(), l.end());
-    plist.insert(plist.end(), l.begin(), l.end());
-    poff[n + 1] = (int32_t)plist.size();
-  }
-  const int32_t *cp = nullptr;
-  bool ok = d->P && d->G && d->Mom && d->Vel && d->Pb && d->mu && d->sig && d->scale && d->nfall &&
-            d->feat && upload(c, poff, &cp);
-  d->p2p_off = (int32_t *)cp;
-  ok = ok && upload(c, plist, &cp);
-  d->p2p = (int32_t *)cp;
-  d->gw = (double2 *)dalloc(c, ((size_t)nn + plist.size()) * sizeof(double2));
-  ok = ok && d->gw;
+  // the rings and gradient weights of the mesh
+  d->p2p_off = c->md.ring_off;
+  d->p2p = c->md.ring;
+  d->gw = c->md.gw;
+  const bool ok = d->P && d->G && d->Mom && d->Vel && d->Pb && d->mu && d->sig && d->scale && d->nfall && d->feat;
   if (!ok) {
     pdf_denoiser_destroy(d);
     return fail(c, PDF_E_OOM, "denoiser allocation failed");
-  }
-  {
-    unsigned long long bad = 0;
-    const bool run = hipMemsetAsync(d->nfall, 0, 8, c->stream) == hipSuccess &&
-                     (launch_grad_weights(c->stream, c->md, d->p2p_off, d->p2p, d->gw, d->nfall),
-                      hipGetLastError() == hipSuccess) &&
-                     hipMemcpyAsync(&bad, d->nfall, 8, hipMemcpyDeviceToHost, c->stream) == hipSuccess &&
-                     hipStreamSynchronize(c->stream) == hipSuccess;
-    if (!run || bad) {
-      pdf_denoiser_destroy(d);
-      return fail(c, PDF_E_DEVICE, run ? "denoiser set-up: an element node outside its master's ring"
-                                       : "denoiser set-up: the gradient weights failed");
-    }
   }
   // initial parameters: uniform in +-1/sqrt(fan_in) (splitmix64 stream), zero biases
   std::vector<float> h(o, 0.f);
@@ -1374,9 +1364,9 @@ void pdf_denoiser_destroy(pdf_denoiser *d) {
   if (!d) return;
   pdf_ctx *c = d->ctx;
   (void)hipStreamSynchronize(c->stream);
-  void *ps[] = {d->P, d->G, d->Mom, d->Vel, d->Pb, d->mu, d->sig, d->scale, d->p2p_off, d->p2p, d->Xb,
+  void *ps[] = {d->P, d->G, d->Mom, d->Vel, d->Pb, d->mu, d->sig, d->scale, d->Xb,
                 d->H1, d->H2, d->H3, d->dYb, d->dZb, d->Z1, d->Z2, d->Z3, d->Y, d->dH, d->part, d->feat,
-                d->nfall, d->Wt, d->R, d->res, d->gw};
+                d->nfall, d->Wt, d->R, d->res};
   for (void *p : ps) dfree(c, p);
   delete d;
 }

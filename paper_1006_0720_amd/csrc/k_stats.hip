@@ -161,76 +161,80 @@ __global__ __launch_bounds__(256) void k_node_grad(MeshDev m, double *S) {
   if (t >= m.n_masters) return;
   const int32_t n = m.masters[t];
   const int nn = m.nn;
-  double g[6] = {0, 0, 0, 0, 0, 0};
-  // two elements per step (loads of both issued before either is used),
-  // summed in list order
-  const int32_t i0 = ldg(m.m2e_off, n), i1 = ldg(m.m2e_off, n + 1);
-  for (int32_t i = i0; i < i1; i += 2) {
-    const bool two = i + 1 < i1;
-    const int32_t ee[2] = {ldg(m.m2e, i), two ? ldg(m.m2e, i + 1) : ldg(m.m2e, i)};
-    double d[2][6], q[2][3][3];
+  // the average of the element gradients is a weighted sum over the master
+  // and its ring (weights formed once per mesh); ring entries four at a time
+  const double2 w0 = ldg(m.gw, n);
+  double g[6];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-#pragma unroll
-      for (int k = 0; k < 6; ++k) d[h][k] = ldg(m.dN, 6 * (size_t)ee[h] + k);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int32_t nd = ldg(m.mnode, 3 * (size_t)ee[h] + k);
-#pragma unroll
-        for (int f = 0; f < 3; ++f) q[h][f][k] = ldg(S, (size_t)f * nn + nd);
-      }
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      if (h == 1 && !two) break;
-      for (int f = 0; f < 3; ++f)
-        for (int k = 0; k < 3; ++k) {
-          g[2 * f] += d[h][k] * q[h][f][k];
-          g[2 * f + 1] += d[h][3 + k] * q[h][f][k];
-        }
-    }
+  for (int f = 0; f < 3; ++f) {
+    const double v = ldg(S, (size_t)f * nn + n);
+    g[2 * f] = w0.x * v;
+    g[2 * f + 1] = w0.y * v;
   }
-  const int c = i1 - i0;
-  for (int f = 0; f < 6; ++f) S[(15 + f) * nn + n] = c ? g[f] / (double)c : 0.0;
+  const int32_t rb = ldg(m.ring_off, n), re = ldg(m.ring_off, n + 1);
+  for (int32_t i = rb; i < re; i += 4) {
+    int32_t j[4];
+    double2 w[4];
+    double v[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t k = min(i + u, re - 1);
+      j[u] = ldg(m.ring, k);
+      w[u] = ldg(m.gw, (size_t)nn + k);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int f = 0; f < 3; ++f) v[u][f] = ldg(S, (size_t)f * nn + j[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u < re)
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          g[2 * f] += w[u].x * v[u][f];
+          g[2 * f + 1] += w[u].y * v[u][f];
+        }
+  }
+  for (int f = 0; f < 6; ++f) S[(15 + f) * nn + n] = g[f];
 }
 
-// second derivatives: eq:gradient applied to the nodal first derivatives
+// second derivatives: eq:gradient applied to the nodal first derivatives,
+// through the same ring weights
 __global__ __launch_bounds__(256) void k_node_lap(MeshDev m, double *S) {
   const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= m.n_masters) return;
   const int32_t n = m.masters[t];
   const int nn = m.nn;
-  double l[3] = {0, 0, 0};
-  // two elements per step (loads of both issued before either is used),
-  // summed in list order
-  const int32_t i0 = ldg(m.m2e_off, n), i1 = ldg(m.m2e_off, n + 1);
-  for (int32_t i = i0; i < i1; i += 2) {
-    const bool two = i + 1 < i1;
-    const int32_t ee[2] = {ldg(m.m2e, i), two ? ldg(m.m2e, i + 1) : ldg(m.m2e, i)};
-    double d[2][6], gx[2][3][3], gy[2][3][3];
+  const double2 w0 = ldg(m.gw, n);
+  double l[3];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+  for (int f = 0; f < 3; ++f)
+    l[f] = w0.x * ldg(S, (size_t)(15 + 2 * f) * nn + n) + w0.y * ldg(S, (size_t)(16 + 2 * f) * nn + n);
+  const int32_t rb = ldg(m.ring_off, n), re = ldg(m.ring_off, n + 1);
+  for (int32_t i = rb; i < re; i += 4) {
+    int32_t j[4];
+    double2 w[4];
+    double gx[4][3], gy[4][3];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) d[h][k] = ldg(m.dN, 6 * (size_t)ee[h] + k);
+    for (int u = 0; u < 4; ++u) {
+      const int32_t k = min(i + u, re - 1);
+      j[u] = ldg(m.ring, k);
+      w[u] = ldg(m.gw, (size_t)nn + k);
+    }
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int32_t nd = ldg(m.mnode, 3 * (size_t)ee[h] + k);
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int f = 0; f < 3; ++f) {
-          gx[h][f][k] = ldg(S, (size_t)(15 + 2 * f) * nn + nd);
-          gy[h][f][k] = ldg(S, (size_t)(16 + 2 * f) * nn + nd);
-        }
+      for (int f = 0; f < 3; ++f) {
+        gx[u][f] = ldg(S, (size_t)(15 + 2 * f) * nn + j[u]);
+        gy[u][f] = ldg(S, (size_t)(16 + 2 * f) * nn + j[u]);
       }
-    }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      if (h == 1 && !two) break;
-      for (int f = 0; f < 3; ++f)
-        for (int k = 0; k < 3; ++k) l[f] += d[h][k] * gx[h][f][k] + d[h][3 + k] * gy[h][f][k];
-    }
+    for (int u = 0; u < 4; ++u)
+      if (i + u < re)
+#pragma unroll
+        for (int f = 0; f < 3; ++f) l[f] += w[u].x * gx[u][f] + w[u].y * gy[u][f];
   }
-  const int c = i1 - i0;
-  for (int f = 0; f < 3; ++f) S[(21 + f) * nn + n] = c ? l[f] / (double)c : 0.0;
+  for (int f = 0; f < 3; ++f) S[(21 + f) * nn + n] = l[f];
 }
 
 __global__ void k_copy_slaves(MeshDev m, double *S, int nf) {

@@ -83,6 +83,12 @@ struct MeshDev {
   int32_t gnx, gny;
   double gx0, gy0, gsx, gsy;      // origin and cells per unit length
   const int32_t *cell_off, *cell_list;
+  // each master's ring (the other masters it shares an element with,
+  // ascending; empty for identified nodes) and the weights that give the
+  // average over its elements of their gradients from the values at it and
+  // at its ring: gw[q] its own, gw[nn + i] that of ring entry i
+  const int32_t *ring_off, *ring;
+  const double2 *gw;
 };
 
 template <typename T>
