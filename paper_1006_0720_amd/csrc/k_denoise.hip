@@ -472,56 +472,6 @@ constexpr int kQuant[8] = {0, 1, 4, 5, 6, 8, 11, 3};
 __constant__ int kQuantDev[8] = {0, 1, 4, 5, 6, 8, 11, 3};
 
 // one thread per (node, statistic): the 6 features of statistic a at node n
-// The averaged element gradient at a master q, (1/c) sum over the c elements
-// around q of sum_k dN_e,k f(node k), is linear in the values at q and at
-// its ring: weights w_j = (1/c) sum over (e, k) with node k of e = j of
-// dN_e,k, formed once per mesh.  gw[q] holds q's own weight, gw[nn + i] the
-// weight of ring entry i.  A ring entry that the elements do not reach
-// (none, by the ring's construction) is counted in bad.
-__global__ void k_grad_weights(MeshDev m, const int32_t *p2p_off, const int32_t *p2p, double2 *gw,
-                               unsigned long long *bad) {
-  const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m.nn) return;
-  const int32_t rb = p2p_off[q], re = p2p_off[q + 1];
-  double2 self = make_double2(0.0, 0.0);
-  for (int32_t i = rb; i < re; ++i) gw[m.nn + i] = make_double2(0.0, 0.0);
-  if (m.master[q] != q) {
-    gw[q] = self;
-    return;
-  }
-  const int32_t eb = m.m2e_off[q], ee = m.m2e_off[q + 1];
-  for (int32_t i = eb; i < ee; ++i) {
-    const int32_t e = m.m2e[i];
-    for (int k = 0; k < 3; ++k) {
-      const int32_t j = m.mnode[3 * e + k];
-      const double wx = m.dN[6 * (size_t)e + k], wy = m.dN[6 * (size_t)e + 3 + k];
-      if (j == q) {
-        self.x += wx;
-        self.y += wy;
-        continue;
-      }
-      int32_t pos = -1;
-      for (int32_t r = rb; r < re; ++r)
-        if (p2p[r] == j) pos = r;
-      if (pos < 0) {
-        atomicAdd(bad, 1ull);
-        continue;
-      }
-      gw[m.nn + pos].x += wx;
-      gw[m.nn + pos].y += wy;
-    }
-  }
-  const double ic = ee > eb ? 1.0 / (double)(ee - eb) : 0.0;
-  gw[q] = make_double2(self.x * ic, self.y * ic);
-  for (int32_t i = rb; i < re; ++i) gw[m.nn + i] = make_double2(gw[m.nn + i].x * ic, gw[m.nn + i].y * ic);
-}
-
-void launch_grad_weights(hipStream_t s, const MeshDev &m, const int32_t *p2p_off, const int32_t *p2p, double2 *gw,
-                         unsigned long long *bad) {
-  hipLaunchKernelGGL(k_grad_weights, dim3((unsigned)((m.nn + 255) / 256)), dim3(256), 0, s, m, p2p_off, p2p, gw,
-                     bad);
-}
-
 __global__ __launch_bounds__(256) void k_features(MeshDev m, const int32_t *p2p_off, const int32_t *p2p,
                                                   const double2 *gw, const double *S, const float *mu,
                                                   const float *sig, float *F, uint16_t *Fb) {
