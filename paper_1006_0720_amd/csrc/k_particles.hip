@@ -526,21 +526,23 @@ __device__ __forceinline__ void table_add(SumTableT<LOG2, COPIES> &t, double *su
 template <int LOG2, int COPIES>
 __device__ __forceinline__ void table_flush(SumTableT<LOG2, COPIES> &t, double *sums) {
   __syncthreads();
-  for (int s = threadIdx.x; s < SumTableT<LOG2, COPIES>::SLOTS; s += blockDim.x) {
+  // sixteen lanes to a slot, one per value: each atomic instruction of a wave
+  // then covers four elements' lines instead of one line per lane
+  for (int idx = threadIdx.x; idx < SumTableT<LOG2, COPIES>::SLOTS * 16; idx += blockDim.x) {
+    const int s = idx >> 4, f = idx & 15;
     const int32_t e = t.key[s];
     if (e < 0) continue;
-    double *g = sums + (size_t)e * NSUM;
-    uint32_t n = 0;
+    double v = 0.0;
+    if (f == 0) {
+      uint32_t n = 0;
 #pragma unroll
-    for (int c = 0; c < COPIES; ++c) n += t.n[c][s];
-    unsafeAtomicAdd(&g[0], (double)n);
+      for (int c = 0; c < COPIES; ++c) n += t.n[c][s];
+      v = (double)n;
+    } else {
 #pragma unroll
-    for (int f = 0; f < 15; ++f) {
-      double a = 0.0;
-#pragma unroll
-      for (int c = 0; c < COPIES; ++c) a += t.acc[c][f][s];
-      unsafeAtomicAdd(&g[1 + f], a);
+      for (int c = 0; c < COPIES; ++c) v += t.acc[c][f - 1][s];
     }
+    unsafeAtomicAdd(&sums[(size_t)e * NSUM + f], v);
   }
 }
 
@@ -600,17 +602,15 @@ __device__ __forceinline__ void table_add_w(SumTableW &t, double *nsums, int32_t
 
 __device__ __forceinline__ void table_flush(SumTableW &t, double *nsums) {
   __syncthreads();
-  for (int s = threadIdx.x; s < TAB; s += blockDim.x) {
+  // sixteen lanes to a slot, one per value (as for the element table)
+  for (int idx = threadIdx.x; idx < TAB * 16; idx += blockDim.x) {
+    const int s = idx >> 4, f = idx & 15;
     const int32_t e = t.key[s];
     if (e < 0) continue;
-    double *g = nsums + (size_t)e * NSUM;
+    double a = 0.0;
 #pragma unroll
-    for (int f = 0; f < 16; ++f) {
-      double a = 0.0;
-#pragma unroll
-      for (int c = 0; c < NCOPY; ++c) a += t.acc[c][f][s];
-      unsafeAtomicAdd(&g[f], a);
-    }
+    for (int c = 0; c < NCOPY; ++c) a += t.acc[c][f][s];
+    unsafeAtomicAdd(&nsums[(size_t)e * NSUM + f], a);
   }
 }
 
