@@ -223,8 +223,11 @@ typedef struct pdf_seed_desc {
 } pdf_seed_desc;
 
 /* Create a context: validate and upload the mesh, derive the linked lists
- * (elements surrounding nodes, wall edges near each element) and shape-function
- * derivatives (Ch.3, Sec. Derivatives).  precision is PDF_FP64 or PDF_FP32;
+ * (elements surrounding nodes, wall edges near each element, the ring of
+ * masters around each master) and shape-function derivatives (Ch.3, Sec.
+ * Derivatives), with the weights that apply the average over a master's
+ * elements of their gradients as a sum over its ring (formed on the device;
+ * PDF_E_DEVICE if that fails).  precision is PDF_FP64 or PDF_FP32;
  * hip_stream is a hipStream_t (NULL: the null stream); alloc may be NULL.
  * On success *out owns all device memory until pdf_destroy. */
 pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *params,
