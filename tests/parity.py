@@ -2,16 +2,28 @@
 
 Tolerance definition: |a - b| <= rtol * (|b| + s_q) with a per-quantity scale
 s_q: velocity -> RMS speed of the reference state, omega -> mean omega,
-psi -> 1, position -> the domain extent; nodal statistics -> RMS of the field.
+psi -> 1; nodal statistics -> RMS of the field.
+
+Positions are compared against the size of the particle's host element,
+h_e = sqrt(2 A_e) (the leg of a right triangle of that area):
+|a - b| <= rtol * h_e + 2 u_T |b|, where u_T is the unit roundoff of the
+stored precision (2^-53 for binary64, 2^-24 for binary32).  A coordinate's
+magnitude depends only on where the origin is, so it does not scale the
+tolerance; the second term allows the storage rounding of the coordinate
+itself (one unit in the last place).
 """
 import numpy as np
 
 
-def state_scales(ref_state, mesh):
-    ext = float(np.ptp(mesh.node_xy, axis=0).max())
+def elem_size(mesh):
+    """h_e = sqrt(2 A_e) of every element."""
+    return np.sqrt(2.0 * np.abs(mesh.areas()))
+
+
+def state_scales(ref_state):
     u_rms = float(np.sqrt((ref_state[2:5] ** 2).sum(0).mean()))
     om = float(np.abs(ref_state[5]).mean())
-    return np.array([ext, ext, u_rms, u_rms, u_rms, om, 1.0])
+    return np.array([0.0, 0.0, u_rms, u_rms, u_rms, om, 1.0])
 
 
 def max_rel_err(a, b, scale):
@@ -25,9 +37,27 @@ def max_rel_err(a, b, scale):
     return float(r.max())
 
 
-def compare_state(gpu_state, ref_state, mesh, rtol, what=""):
-    s = state_scales(ref_state, mesh)
-    errs = [max_rel_err(gpu_state[f], ref_state[f], s[f]) for f in range(7)]
+def position_err(a, b, h, unit_roundoff):
+    """Largest (|a - b| - 2 u_T |b|) / h_e, at least 0."""
+    if not a.size:
+        return 0.0
+    d = np.abs(a - b) - 2.0 * unit_roundoff * np.abs(b)
+    return float(np.max(np.maximum(d, 0.0) / h))
+
+
+def compare_state(gpu_state, ref_state, mesh, rtol, what="", *, elem, fp32=None):
+    """Compare (7, n) particle states.  elem: the reference host elements (n,)
+    that set the position scale.  fp32: whether the state is stored in
+    binary32 (default: inferred from rtol > 1e-9)."""
+    elem = np.asarray(elem)
+    assert elem.shape == (ref_state.shape[1],)
+    if fp32 is None:
+        fp32 = rtol > 1e-9
+    u = 2.0 ** -24 if fp32 else 2.0 ** -53
+    h = elem_size(mesh)[elem]
+    s = state_scales(ref_state)
+    errs = [position_err(gpu_state[f], ref_state[f], h, u) for f in range(2)]
+    errs += [max_rel_err(gpu_state[f], ref_state[f], s[f]) for f in range(2, 7)]
     names = ["x", "y", "u", "v", "w", "omega", "psi"]
     bad = [(n, e) for n, e in zip(names, errs) if not e <= rtol]
     assert not bad, f"{what} state mismatch (rtol {rtol}): {bad}"

@@ -109,12 +109,12 @@ def test_two_triangles_one_particle_each(L):
     ctx.advance(0, w.dt)  # zero steps: nothing changes
     st_b, el_b, _ = ctx.particles()
     assert np.array_equal(st_a, st_b) and np.array_equal(el_a, el_b)
-    compare_state(st_a, o.state, mesh, 1e-12, "two triangles, seeded")
+    compare_state(st_a, o.state, mesh, 1e-12, "two triangles, seeded", elem=o.elem)
     ctx.advance(20, w.dt)
     o.run(w.dt, 20)
     st, el, pid = ctx.particles()
     assert np.array_equal(el, o.elem)
-    compare_state(st, o.state, mesh, 1e-12, "two triangles")
+    compare_state(st, o.state, mesh, 1e-12, "two triangles", elem=o.elem)
     assert ctx.counters()["reflect"] == o.counter_dict()["reflect"] > 0
     ctx.close()
 
@@ -134,5 +134,5 @@ def test_zero_mean_frequency(L):
     o.run(w.dt, 5)
     st, el, _ = ctx.particles()
     assert np.array_equal(el, o.elem) and np.all(np.isfinite(st)) and np.all(st[5] == 0.0)
-    compare_state(st, o.state, w.mesh, 1e-12, "zero frequency")
+    compare_state(st, o.state, w.mesh, 1e-12, "zero frequency", elem=o.elem)
     ctx.close()

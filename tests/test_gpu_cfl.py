@@ -68,7 +68,7 @@ def test_cfl_fed_back_fp64_channel(L):
         st, el, pid = ctx.particles()
         assert np.array_equal(pid, o.id)
         assert np.array_equal(el, o.elem), f"chunk {chunk}: {(el != o.elem).sum()} element mismatches"
-        compare_state(st, o.state, w.mesh, 1e-12, f"cfl channel chunk {chunk}")
+        compare_state(st, o.state, w.mesh, 1e-12, f"cfl channel chunk {chunk}", elem=o.elem)
         compare_stats(ctx.stats(), o.stats, 1e-12, what=f"cfl channel chunk {chunk}")
         assert abs(t_g - t_o) <= 1e-12 * t_o, (t_g, t_o)
     assert len(dts) == 3 and max(dts) < DT_MAX  # the condition, not the cap, sets the step
@@ -96,14 +96,14 @@ def test_cfl_frozen_exact_step(L, precision):
     assert t_g == t_o == dt
     st, el, _ = ctx.particles()
     assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
-    compare_state(st, o.state, w.mesh, 1e-12 if precision == "f64" else 1e-5, "cfl frozen, one step")
+    compare_state(st, o.state, w.mesh, 1e-12 if precision == "f64" else 1e-5, "cfl frozen, one step", elem=o.elem)
     t_o += o.run_cfl(C_CFL, DT_MAX, 3)
     t_g += ctx.advance_cfl(3, C_CFL, DT_MAX)
     assert t_g == t_o
     st, el, _ = ctx.particles()
     if precision == "f64":
         assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
-        compare_state(st, o.state, w.mesh, 1e-12, "cfl frozen, four steps")
+        compare_state(st, o.state, w.mesh, 1e-12, "cfl frozen, four steps", elem=o.elem)
     ref, _ = _pair(L, w, fz)
     ref.advance(4, dt)
     st2, el2, _ = ref.particles()

@@ -82,7 +82,7 @@ def test_trajectory_and_warm_start(L):
     st, el, pid = ctx.particles()
     assert np.array_equal(pid, o.id)
     assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
-    compare_state(st, o.state, w.mesh, 1e-10, "GLM with the elliptic relaxation")
+    compare_state(st, o.state, w.mesh, 1e-10, "GLM with the elliptic relaxation", elem=o.elem)
     ctx.close()
 
 

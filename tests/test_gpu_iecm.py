@@ -3,10 +3,11 @@ mean (App. B binning) and of the source-aware micromixing time scale
 (eq:micromixing-timescale-canyon), through the C ABI, against the oracle.
 
 FP64 trajectories: element indices bit-exact, state and statistics within
-1e-12.  The cases cover elements small enough for the one-wave LDS path and
-large enough (more than 256 particles) for the workgroup path, the adaptive
-stop at low counts, ties from the copies the particle redistribution makes,
-SHAPE statistics, and one FP32 step (1e-5)."""
+1e-12.  The cases cover the three element paths (at most 128 particles: one
+wave with the particles in LDS; 129-512: a 256-thread workgroup with the
+particles in LDS; more than 512: a 256-thread workgroup keeping the order in
+global memory), the adaptive stop at low counts, ties from the copies the
+particle redistribution makes, SHAPE statistics, and FP32 steps (1e-5)."""
 import numpy as np
 import pytest
 
@@ -53,17 +54,18 @@ def _run_and_check(ctx, o, w, chunks, steps, what):
         st, el, pid = ctx.particles()
         assert np.array_equal(pid, o.id)
         assert np.array_equal(el, o.elem), f"{what} {c}: {(el != o.elem).sum()} element mismatches"
-        compare_state(st, o.state, w.mesh, 1e-12, f"{what} {c}")
+        compare_state(st, o.state, w.mesh, 1e-12, f"{what} {c}", elem=o.elem)
         compare_stats(ctx.stats(), o.stats, 1e-12, what=f"{what} {c}")
 
 
-@pytest.mark.parametrize("ppe,reorder", [(60, 0), (60, 4), (250, 0)])
+@pytest.mark.parametrize("ppe,reorder", [(60, 0), (60, 4), (250, 0), (510, 0), (1500, 4)])
 def test_iecm_trajectory_fp64(L, ppe, reorder):
     """5 x 5 x 5 bins, at least 2 per subgroup: 60 per element takes two
-    levels (60 // 25 = 2); 250 takes three, and as the counts spread to
-    either side of 256 the elements run on both the one-wave and the
-    workgroup path."""
-    w = _square(4 if ppe > 200 else 8, ppe)
+    levels (60 // 25 = 2) on the one-wave path; 250 takes three on the
+    129-512 path; at 510 the counts spread to either side of 512, so elements
+    run on both the 129-512 and the large-element path; 1500 runs every
+    element on the large-element path."""
+    w = _square(2 if ppe > 1000 else (3 if ppe > 400 else (4 if ppe > 200 else 8)), ppe)
     ctx, o = _pair(w, reorder)
     cm = o.cond_means()
     assert np.unique(cm).size > 10 * w.mesh.n_elems  # conditioning is active
@@ -103,7 +105,7 @@ def test_iecm_with_redistribution_copies(L):
         o.run(w.dt, 10)
         st, el, _ = ctx.particles()
         assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
-        compare_state(st, o.state, w.mesh, 1e-12, f"iecm redistribution {c}")
+        compare_state(st, o.state, w.mesh, 1e-12, f"iecm redistribution {c}", elem=o.elem)
     assert ctx.counters()["redist"] == o.counter_dict()["redist"] > 0
     ctx.close()
 
@@ -128,17 +130,19 @@ def test_source_timescale_shape_fp64(L, mix):
     ctx.close()
 
 
-def test_iecm_fp32_one_step(L):
+@pytest.mark.parametrize("n,ppe", [(8, 120), (2, 700)])
+def test_iecm_fp32_one_step(L, n, ppe):
     """FP32: one step from the common seeded state (the oracle rounds the
-    conditioned means to binary32 as the GPU stores them)."""
-    w = _square(8, 120)
+    conditioned means to binary32 as the GPU stores them); 700 per element
+    runs on the large-element path."""
+    w = _square(n, ppe)
     w.precision = "f32"
     ctx, o = _pair(w)
     ctx.advance(1, w.dt)
     o.step(w.dt)
     st, el, _ = ctx.particles()
     assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
-    compare_state(st, o.state, w.mesh, 1e-5, "iecm fp32 step")
+    compare_state(st, o.state, w.mesh, 1e-5, "iecm fp32 step", elem=o.elem)
     ctx.close()
 
 

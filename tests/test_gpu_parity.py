@@ -43,7 +43,7 @@ def _check(ctx, o, w, rtol, what, stats_rtol=None):
     st, el, pid = ctx.particles()
     assert np.array_equal(pid, o.id)
     assert np.array_equal(el, o.elem), f"{what}: {(el != o.elem).sum()} element mismatches"
-    errs = compare_state(st, o.state, w.mesh, rtol, what)
+    errs = compare_state(st, o.state, w.mesh, rtol, what, elem=o.elem)
     g = ctx.stats()
     serr = compare_stats(g, o.stats, stats_rtol or rtol, what=what)
     return errs, serr
@@ -132,7 +132,7 @@ def test_frozen_glm_input_wp_fp64(L):
     o.run(w.dt, 10)
     st, el, pid = ctx.particles()
     assert np.array_equal(el, o.elem)
-    compare_state(st, o.state, w.mesh, 1e-12, "frozen GLM")
+    compare_state(st, o.state, w.mesh, 1e-12, "frozen GLM", elem=o.elem)
     compare_stats(ctx.stats(), o.est, 1e-12, what="frozen GLM estimate")
     ctx.close()
 
@@ -143,13 +143,13 @@ def test_kernel_parity_fp32_channel(L):
     ctx, o = _pair(L, w)
     st, el, pid = ctx.particles()
     assert np.array_equal(el, o.elem)
-    compare_state(st, o.state, w.mesh, 1e-6, "fp32 seed")
+    compare_state(st, o.state, w.mesh, 1e-6, "fp32 seed", elem=o.elem)
     compare_stats(ctx.stats(), o.stats, 1e-5, what="fp32 seed stats")
     ctx.advance(1, w.dt)
     o.step(w.dt)
     st, el, pid = ctx.particles()
     assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
-    compare_state(st, o.state, w.mesh, 1e-5, "fp32 step")
+    compare_state(st, o.state, w.mesh, 1e-5, "fp32 step", elem=o.elem)
     compare_stats(ctx.stats(), o.stats, 1e-5, what="fp32 step stats")
     ctx.close()
 
@@ -163,7 +163,7 @@ def test_kernel_parity_fp32_canyon_full_size_sampled(L):
     ctx, o = _pair(L, w)
     st, el, pid = ctx.particles()
     assert np.array_equal(el, o.elem)
-    compare_state(st, o.state, w.mesh, 1e-6, "canyon fp32 seed")
+    compare_state(st, o.state, w.mesh, 1e-6, "canyon fp32 seed", elem=o.elem)
     compare_stats(ctx.stats(), o.stats, 1e-5, what="canyon fp32 seed stats")
     ctx.advance(1, w.dt)
     mask = np.zeros(o.state.shape[1], np.uint8)
@@ -172,7 +172,7 @@ def test_kernel_parity_fp32_canyon_full_size_sampled(L):
     st, el, pid = ctx.particles()
     sel = mask.astype(bool)
     assert np.array_equal(el[sel], o.elem[sel])
-    compare_state(st[:, sel], o.state[:, sel], w.mesh, 1e-5, "canyon fp32 step (sample)")
+    compare_state(st[:, sel], o.state[:, sel], w.mesh, 1e-5, "canyon fp32 step (sample)", elem=o.elem[sel])
     c = ctx.counters()
     assert c["lost"] == 0 and c["nonfinite"] == 0
     # particle count conservation: element counts add up to N_p
@@ -231,7 +231,7 @@ def test_brute_force_location_matches_oracle(L):
     st, el, pid = ctx.particles()
     assert np.array_equal(pid, o.id)
     assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
-    compare_state(st, o.state, mesh, 1e-12, "brute force")
+    compare_state(st, o.state, mesh, 1e-12, "brute force", elem=o.elem)
     c, oc = ctx.counters(), o.counter_dict()
     # a particle that stepped outside the box and whose walk ran out before
     # reaching the wall is lost (restored) on both sides alike
@@ -285,7 +285,7 @@ def test_kernel_parity_fp32_channel_block_full_size_sampled(L):
     say("oracle step on the 1% sample done")
     sel = mask.astype(bool)
     assert np.array_equal(el1[sel], o.elem[sel]), f"{(el1[sel] != o.elem[sel]).sum()} element mismatches"
-    es = compare_state(st1[:, sel], o.state[:, sel], w.mesh, 1e-5, "channel_block fp32 step (sample)")
+    es = compare_state(st1[:, sel], o.state[:, sel], w.mesh, 1e-5, "channel_block fp32 step (sample)", elem=o.elem[sel])
     say("state error vs the FP64 oracle (max relative): " + ", ".join(f"{k} {v:.2e}" for k, v in es.items()))
     # nodal statistics: the oracle's estimate from the GPU's particles after the step
     o.state, o.elem = st1, el1
@@ -339,7 +339,7 @@ def test_kernel_parity_fp32_channel_block_driven_200_steps(L):
         o.step(w.dt, mask=mask)
         sel = mask.astype(bool)
         assert np.array_equal(el1[sel], o.elem[sel]), f"step {20 * k + 1}: {(el1[sel] != o.elem[sel]).sum()} element mismatches"
-        es = compare_state(st1[:, sel], o.state[:, sel], w.mesh, 1e-5, f"channel_block step {20 * k + 1} (sample)")
+        es = compare_state(st1[:, sel], o.state[:, sel], w.mesh, 1e-5, f"channel_block step {20 * k + 1} (sample)", elem=o.elem[sel])
         worst = {n: max(worst.get(n, 0.0), e) for n, e in es.items()}
         say(f"step {20 * k + 1}: " + ", ".join(f"{n} {e:.1e}" for n, e in es.items()))
     c = ctx.counters()

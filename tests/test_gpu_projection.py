@@ -65,7 +65,7 @@ def test_projection_trajectory_fp64(L, make, precond):
         st, el, pid = ctx.particles()
         assert np.array_equal(pid, o.id)
         assert np.array_equal(el, o.elem), f"chunk {c}: {(el != o.elem).sum()} element mismatches"
-        compare_state(st, o.state, w.mesh, 1e-11, f"projection chunk {c}")
+        compare_state(st, o.state, w.mesh, 1e-11, f"projection chunk {c}", elem=o.elem)
         compare_stats(ctx.stats(), o.stats, 1e-11, what=f"projection chunk {c}")
         P = ctx.nodal_field(L.FIELD_PRESSURE)[0]
         scale = np.abs(o.Pp).max()
@@ -88,7 +88,7 @@ def test_projection_canyon_corners_fp64(L, precond):
     o.run(w.dt, 5)
     st, el, pid = ctx.particles()
     assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
-    compare_state(st, o.state, w.mesh, 1e-11, "projection canyon")
+    compare_state(st, o.state, w.mesh, 1e-11, "projection canyon", elem=o.elem)
     P = ctx.nodal_field(L.FIELD_PRESSURE)[0]
     assert np.abs(P - o.Pp).max() <= 1e-9 * np.abs(o.Pp).max()
     its = ctx.counters()["proj_iters"]
@@ -124,7 +124,7 @@ def test_projection_fp32_one_step(L):
     o.step(w.dt)
     st, el, _ = ctx.particles()
     assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
-    compare_state(st, o.state, w.mesh, 1e-5, "projection fp32 step")
+    compare_state(st, o.state, w.mesh, 1e-5, "projection fp32 step", elem=o.elem)
     ctx.close()
 
 

@@ -55,7 +55,7 @@ def _check(ctx, o, w, rtol, what, stats=True):
     st, el, pid = ctx.particles()
     assert np.array_equal(pid, o.id)
     assert np.array_equal(el, o.elem), f"{what}: {(el != o.elem).sum()} element mismatches"
-    compare_state(st, o.state, w.mesh, rtol, what)
+    compare_state(st, o.state, w.mesh, rtol, what, elem=o.elem)
     if stats:
         compare_stats(ctx.stats(), o.est if w.params["frozen"] else o.stats, rtol, what=what)
 
@@ -119,6 +119,6 @@ def test_redistribution_kernel_fp32(L):
     o2.step(w.dt)
     st, el, pid = ctx.particles()
     assert np.array_equal(el, o2.elem), f"{(el != o2.elem).sum()} element mismatches"
-    compare_state(st, o2.state, w.mesh, 1e-5, "redistribution fp32 step")
+    compare_state(st, o2.state, w.mesh, 1e-5, "redistribution fp32 step", elem=o2.elem)
     assert ctx.counters()["redist"] == o2.counter_dict()["redist"] > 0
     ctx.close()

@@ -43,7 +43,7 @@ def _check(ctx, o, w, rtol, what):
     st, el, pid = ctx.particles()
     assert np.array_equal(pid, o.id)
     assert np.array_equal(el, o.elem), f"{what}: {(el != o.elem).sum()} element mismatches"
-    compare_state(st, o.state, w.mesh, rtol, what)
+    compare_state(st, o.state, w.mesh, rtol, what, elem=o.elem)
     compare_stats(ctx.stats(), o.stats, rtol, what=what)
 
 
@@ -97,7 +97,7 @@ def test_shape_kernel_fp32_channel(L):
     o.step(w.dt)
     st, el, _ = ctx.particles()
     assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
-    compare_state(st, o.state, w.mesh, 1e-5, "shape fp32 step")
+    compare_state(st, o.state, w.mesh, 1e-5, "shape fp32 step", elem=o.elem)
     compare_stats(ctx.stats(), o.stats, 1e-5, what="shape fp32 step stats")
     ctx.close()
 

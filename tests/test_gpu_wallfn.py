@@ -48,7 +48,7 @@ def test_wallfn_channel_trajectory_fp64(L, frozen):
         st, el, pid = ctx.particles()
         assert np.array_equal(pid, o.id)
         assert np.array_equal(el, o.elem), f"chunk {c}: {(el != o.elem).sum()} element mismatches"
-        compare_state(st, o.state, w.mesh, 1e-12, f"wall functions, chunk {c}")
+        compare_state(st, o.state, w.mesh, 1e-12, f"wall functions, chunk {c}", elem=o.elem)
         compare_stats(ctx.stats(), o.est if frozen else o.stats, 1e-12, what=f"wall functions, chunk {c}")
     g, oc = ctx.counters(), o.counter_dict()
     for k in ("walk_steps", "reflect", "periodic", "lost", "noslip_b"):
@@ -64,7 +64,7 @@ def test_wallfn_fp32_one_step(L):
     o.step(w.dt)
     st, el, _ = ctx.particles()
     assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
-    compare_state(st, o.state, w.mesh, 1e-5, "wall functions fp32 step")
+    compare_state(st, o.state, w.mesh, 1e-5, "wall functions fp32 step", elem=o.elem)
     assert ctx.counters()["reflect"] == o.counter_dict()["reflect"] > 0
     ctx.close()
 
