@@ -65,7 +65,9 @@ def test_iecm_trajectory_fp64(L, ppe, reorder):
     129-512 path; at 510 the counts spread to either side of 512, so elements
     run on both the 129-512 and the large-element path; 1500 runs every
     element on the large-element path."""
-    w = _square(2 if ppe > 1000 else (3 if ppe > 400 else (4 if ppe > 200 else 8)), ppe)
+    # (on a 2 x 2 periodic square every averaged nodal gradient is zero by
+    # symmetry, leaving only rounding to compare: 3 x 3 is the smallest useful)
+    w = _square(3 if ppe > 400 else (4 if ppe > 200 else 8), ppe)
     ctx, o = _pair(w, reorder)
     cm = o.cond_means()
     assert np.unique(cm).size > 10 * w.mesh.n_elems  # conditioning is active
@@ -130,7 +132,7 @@ def test_source_timescale_shape_fp64(L, mix):
     ctx.close()
 
 
-@pytest.mark.parametrize("n,ppe", [(8, 120), (2, 700)])
+@pytest.mark.parametrize("n,ppe", [(8, 120), (3, 700)])
 def test_iecm_fp32_one_step(L, n, ppe):
     """FP32: one step from the common seeded state (the oracle rounds the
     conditioned means to binary32 as the GPU stores them); 700 per element
