@@ -372,6 +372,26 @@ pdf_status pdf_denoiser_train_step(pdf_denoiser *dn, const float *x, const float
 pdf_status pdf_denoise_stats(pdf_denoiser *dn, double tau, double *out, int32_t on_device,
                              uint64_t *n_fallback);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as pdf_denoise_stats with out on the device, computed without any
+ * allocation.  The work runs over chunks of 32768 nodes through a fixed
+ * scratch area of 7 MiB (the features and network outputs of one chunk) that
+ * the library holds in device memory on every GPU it runs on, until the
+ * process ends; pdf_init_mesh sets it up on the current device.
+ *   out            device [PDF_NSTAT][n_nodes]: the plain statistics with the 8
+ *                  corrected fields
+ *   n_fallback_dev device, 8-byte aligned, or NULL: receives the number of
+ *                  rejected corrections (cleared by the call)
+ * Asynchronous on the context's stream: no host synchronisation, no memset and
+ * no allocation, so the call can be captured in a graph.  Needs the fused
+ * inference: PDF_E_INVALID_ARG for a hidden width outside 48..128 (its
+ * activations would not fit the scratch), as for a negative tau or a NULL out;
+ * PDF_E_STATE before seeding.  All calls on one GPU share its scratch: calls
+ * that overlap in time on one GPU (other streams or threads) race and give
+ * undefined results. */
+pdf_status pdf_denoise_stats_noalloc(pdf_denoiser *dn, double tau, double *out, uint64_t *n_fallback_dev);
+
 #ifdef __cplusplus
 }
 #endif

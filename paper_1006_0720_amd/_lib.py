@@ -297,6 +297,7 @@ def _declare_denoiser():
         "pdf_denoiser_forward": ([vp, vp, i32, vp], i32),
         "pdf_denoiser_train_step": ([vp, vp, vp, i32, C.c_float, C.POINTER(C.c_float), vp], i32),
         "pdf_denoise_stats": ([vp, dbl, vp, i32, C.POINTER(u64)], i32),
+        "pdf_denoise_stats_noalloc": ([vp, dbl, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -393,3 +394,14 @@ class Denoiser:
             out = np.empty((NSTAT, self.ctx.n_nodes))
             self.ctx._chk(lib.pdf_denoise_stats(self.h, float(tau), _ptr(out), 0, C.byref(nf)))
         return out, nf.value
+
+    def denoise_noalloc(self, out, n_fallback=None, tau=3.0):
+        """pdf_denoise_stats_noalloc into caller-owned device tensors: out
+        (float64 [25, n_nodes]) and n_fallback (int64 [1] or None)."""
+        t = self.torch
+        assert out.dtype == t.float64 and out.is_contiguous() and tuple(out.shape) == (NSTAT, self.ctx.n_nodes)
+        nfp = None
+        if n_fallback is not None:
+            assert n_fallback.dtype == t.int64 and n_fallback.numel() >= 1
+            nfp = C.c_void_p(n_fallback.data_ptr())
+        self.ctx._chk(lib.pdf_denoise_stats_noalloc(self.h, float(tau), C.c_void_p(out.data_ptr()), nfp))

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "pdf_internal.h"
@@ -20,6 +21,7 @@ using namespace pdfk;
 
 struct pdf_ctx {
   int32_t prec = PDF_FP64;
+  int32_t device = -1;        // the HIP device current at pdf_init_mesh
   hipStream_t stream = nullptr;
   pdf_allocator alloc{};
   bool has_alloc = false;
@@ -61,6 +63,40 @@ struct pdf_ctx {
   std::vector<int> ev_phase;
   double phase_ms[4] = {0, 0, 0, 0};
 };
+
+// ---------------------------------------------------------------------------
+// Scratch of pdf_denoise_stats_noalloc: the features and network outputs of
+// one chunk of nodes.  Each GPU the library runs on holds its own copy until
+// the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (scratch_dev), never through the
+// array's name.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int32_t NOALLOC_CHUNK = 32768;  // nodes per chunk
+constexpr size_t NOALLOC_BYTES = (size_t)NOALLOC_CHUNK * (PDF_DN_NIN + PDF_DN_NOUT) * sizeof(float);
+constexpr int NOALLOC_MAX_DEV = 64;
+void *scratch_dev[NOALLOC_MAX_DEV] = {nullptr};
+std::mutex scratch_mu;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+// once per device, with that device current (called by pdf_init_mesh)
+hipError_t scratch_setup(int dev) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEV) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (scratch_dev[dev]) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  scratch_dev[dev] = ptr;
+  return hipSuccess;
+}
+
+__global__ void k_clear_u64(unsigned long long *p) {
+  if (threadIdx.x == 0) *p = 0ull;
+}
+}  // namespace
 
 namespace {
 
@@ -576,9 +612,17 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
     return PDF_E_INVALID_ARG;
   if (!(params->C4 > 0.0 && params->C4 <= 1.0) || params->nu < 0.0 || params->reorder_every < 0)
     return PDF_E_INVALID_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return PDF_E_DEVICE;
   pdf_ctx *c = new pdf_ctx();
   c->prec = precision;
+  c->device = dev;
   c->stream = (hipStream_t)hip_stream;
+  if (scratch_setup(dev) != hipSuccess) {
+    c->err = "hipGetSymbolAddress of the allocation-free scratch failed on device " + std::to_string(dev);
+    *out = c;  // the caller can read the message, then destroy
+    return PDF_E_DEVICE;
+  }
   c->params = *params;
   if (alloc && alloc->alloc && alloc->free) {
     c->alloc = *alloc;
@@ -1520,6 +1564,41 @@ pdf_status pdf_denoise_stats(pdf_denoiser *d, double tau, double *out, int32_t o
     HIPCHK(c, hipMemcpyAsync(out, res, (size_t)PDF_NSTAT * nn * 8, hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   if (n_fallback) *n_fallback = nf;
+  return PDF_OK;
+}
+
+pdf_status pdf_denoise_stats_noalloc(pdf_denoiser *d, double tau, double *out, uint64_t *n_fallback_dev) {
+  if (!d || !out || !(tau >= 0.0)) return PDF_E_INVALID_ARG;
+  pdf_ctx *c = d->ctx;
+  if (!c->seeded) return fail(c, PDF_E_STATE, "no statistics");
+  if (!d->Wt)
+    return fail(c, PDF_E_INVALID_ARG,
+                "pdf_denoise_stats_noalloc needs the fused inference (hidden width 48..128, a multiple of 16)");
+  void *base = (c->device >= 0 && c->device < NOALLOC_MAX_DEV) ? scratch_dev[c->device] : nullptr;
+  if (!base) return fail(c, PDF_E_STATE, "the allocation-free scratch is not set up on this device");
+  hipStream_t s = c->stream;
+  float *F = (float *)base;                          // [chunk][48] features
+  float *R = F + (size_t)NOALLOC_CHUNK * PDF_DN_NIN;  // [chunk][8] network outputs
+  if (d->wt_stale) {
+    launch_transpose_weights(s, d->H, d->Pb + d->off[0], d->Pb + d->off[2], d->Pb + d->off[4], d->Pb + d->off[6],
+                             d->Wt);
+    d->wt_stale = false;
+  }
+  // the caller's counter is cleared by a kernel, not a memset, so that the
+  // call can be captured in a graph
+  auto *nfall = reinterpret_cast<unsigned long long *>(n_fallback_dev);
+  if (nfall) hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, s, nfall);
+  const int32_t nn = c->md.nn;
+  for (int32_t n0 = 0; n0 < nn; n0 += NOALLOC_CHUNK) {
+    const int32_t cnt = (nn - n0) < NOALLOC_CHUNK ? (nn - n0) : NOALLOC_CHUNK;
+    launch_features_range(s, c->md, d->p2p_off, d->p2p, d->gw, c->latest, d->mu, d->sig, n0, cnt, F, nullptr);
+    if (!launch_mlp_forward(s, cnt, d->H, F, d->Wt, d->P + d->off[1], d->P + d->off[3], d->P + d->off[5],
+                            d->P + d->off[7], R))
+      return fail(c, PDF_E_DEVICE, "fused inference launch failed");
+    launch_merge_range(s, nn, c->md.master, c->latest, n0, cnt, R, PDF_DN_NOUT, d->scale, tau, c->params.C4, out,
+                       nfall);
+  }
+  HIPCHK(c, hipGetLastError());
   return PDF_OK;
 }
 

@@ -471,14 +471,17 @@ void launch_to_bf16(hipStream_t s, int64_t n, const float *x, uint16_t *y) {
 constexpr int kQuant[8] = {0, 1, 4, 5, 6, 8, 11, 3};
 __constant__ int kQuantDev[8] = {0, 1, 4, 5, 6, 8, 11, 3};
 
-// one thread per (node, statistic): the 6 features of statistic a at node n
+// one thread per (node, statistic): the 6 features of statistic a at node
+// n = n0 + r, written to row r of F (rows r < cnt)
 __global__ __launch_bounds__(256) void k_features(MeshDev m, const int32_t *p2p_off, const int32_t *p2p,
                                                   const double2 *gw, const double *S, const float *mu,
-                                                  const float *sig, float *F, uint16_t *Fb) {
+                                                  const float *sig, int32_t n0, int32_t cnt, float *F,
+                                                  uint16_t *Fb) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t n = (int32_t)(t >> 3);
+  const int32_t r = (int32_t)(t >> 3);
   const int a = (int)(t & 7);
-  if (n >= m.nn) return;
+  if (r >= cnt) return;
+  const int32_t n = n0 + r;
   const int nn = m.nn;
   const int32_t q = m.master[n];
   const int fld = kQuantDev[a];
@@ -521,16 +524,23 @@ __global__ __launch_bounds__(256) void k_features(MeshDev m, const int32_t *p2p_
   for (int j = 0; j < 6; ++j) {
     const int k = 6 * a + j;
     const float z = mu ? (f[j] - mu[k]) / sig[k] : f[j];
-    F[(size_t)n * 48 + k] = z;
-    if (Fb) Fb[(size_t)n * 48 + k] = f2bf(z);
+    F[(size_t)r * 48 + k] = z;
+    if (Fb) Fb[(size_t)r * 48 + k] = f2bf(z);
   }
+}
+
+void launch_features_range(hipStream_t s, const MeshDev &m, const int32_t *p2p_off, const int32_t *p2p,
+                           const double2 *gw, const double *S, const float *mu, const float *sig, int32_t n0,
+                           int32_t cnt, float *F, uint16_t *Fb) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(k_features, dim3((unsigned)(((int64_t)cnt * 8 + 255) / 256)), dim3(256), 0, s, m, p2p_off,
+                     p2p, gw, S, mu, sig, n0, cnt, F, Fb);
 }
 
 void launch_features(hipStream_t s, const MeshDev &m, const int32_t *p2p_off, const int32_t *p2p,
                      const double2 *gw, const double *S, const float *mu, const float *sig, float *F,
                      uint16_t *Fb) {
-  hipLaunchKernelGGL(k_features, dim3((unsigned)(((int64_t)m.nn * 8 + 255) / 256)), dim3(256), 0, s, m, p2p_off,
-                     p2p, gw, S, mu, sig, F, Fb);
+  launch_features_range(s, m, p2p_off, p2p, gw, S, mu, sig, 0, m.nn, F, Fb);
 }
 
 // Merge: q = q_plain + scale_q * r_q, except where |scale_q r_q| exceeds tau
@@ -539,11 +549,14 @@ void launch_features(hipStream_t s, const MeshDev &m, const int32_t *p2p_off, co
 // <U>: sqrt(<uu>/N), <V>: sqrt(<vv>/N), <phi>: sqrt(<phi'^2>/N), second
 // moments s: s sqrt(2/N), <uv>: sqrt((<uu><vv> + <uv>^2)/N), <omega>: <omega>
 // sqrt(C4/N).  Every other statistic is copied from the plain estimate.
-__global__ void k_merge(int nn, const int32_t *master, const double *S, const float *R, int ldr,
-                        const float *scale, double tau, double C4, double *out, unsigned long long *nfall) {
-  const int32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+// Node n = n0 + r takes its network output from row r of R (rows r < cnt).
+__global__ void k_merge(int nn, const int32_t *master, const double *S, int32_t n0, int32_t cnt, const float *R,
+                        int ldr, const float *scale, double tau, double C4, double *out,
+                        unsigned long long *nfall) {
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t n = n0 + r;
   int fb = 0;
-  if (n < nn) {
+  if (r < cnt) {
     const int32_t q = master[n];
     const double N = S[24 * (size_t)nn + q];
     const double uu = S[5 * (size_t)nn + q], vv = S[6 * (size_t)nn + q], uv = S[8 * (size_t)nn + q];
@@ -563,7 +576,7 @@ __global__ void k_merge(int nn, const int32_t *master, const double *S, const fl
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       const int fld = kQuant[a];
-      const double corr = (double)scale[a] * (double)R[(size_t)n * ldr + a];
+      const double corr = (double)scale[a] * (double)R[(size_t)r * ldr + a];
       ok[a] = fabs(corr) <= tau * se[a];
       mv[a] = S[(size_t)fld * nn + q] + corr;
       fb += ok[a] ? 0 : 1;
@@ -585,10 +598,17 @@ __global__ void k_merge(int nn, const int32_t *master, const double *S, const fl
   if (nfall && fb && (threadIdx.x & 63) == 0) atomicAdd(nfall, (unsigned long long)fb);
 }
 
+void launch_merge_range(hipStream_t s, int nn, const int32_t *master, const double *S, int32_t n0, int32_t cnt,
+                        const float *R, int ldr, const float *scale, double tau, double C4, double *out,
+                        unsigned long long *nfall) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(k_merge, dim3((cnt + 255) / 256), dim3(256), 0, s, nn, master, S, n0, cnt, R, ldr, scale,
+                     tau, C4, out, nfall);
+}
+
 void launch_merge(hipStream_t s, int nn, const int32_t *master, const double *S, const float *R, int ldr,
                   const float *scale, double tau, double C4, double *out, unsigned long long *nfall) {
-  hipLaunchKernelGGL(k_merge, dim3((nn + 255) / 256), dim3(256), 0, s, nn, master, S, R, ldr, scale, tau,
-                     C4, out, nfall);
+  launch_merge_range(s, nn, master, S, 0, nn, R, ldr, scale, tau, C4, out, nfall);
 }
 
 }  // namespace pdfk

@@ -330,4 +330,12 @@ void launch_grad_weights(hipStream_t s, const MeshDev &m, const int32_t *p2p_off
                          unsigned long long *bad);
 void launch_merge(hipStream_t s, int nn, const int32_t *master, const double *S, const float *R, int ldr,
                   const float *scale, double tau, double C4, double *out, unsigned long long *nfall);
+// the same over the nodes n0 .. n0 + cnt - 1 only, with row r of F and R
+// belonging to node n0 + r
+void launch_features_range(hipStream_t s, const MeshDev &m, const int32_t *p2p_off, const int32_t *p2p,
+                           const double2 *gw, const double *S, const float *mu, const float *sig, int32_t n0,
+                           int32_t cnt, float *F, uint16_t *Fb);
+void launch_merge_range(hipStream_t s, int nn, const int32_t *master, const double *S, int32_t n0, int32_t cnt,
+                        const float *R, int ldr, const float *scale, double tau, double C4, double *out,
+                        unsigned long long *nfall);
 }  // namespace pdfk
