@@ -755,6 +755,26 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
       geo[e].wn = w_off[e + 1] - w_off[e];
     }
   }
+  // the element test's form of the geometry (the canonical edge directions)
+  std::vector<WalkGeo> wgeo(ne);
+  for (int32_t e = 0; e < ne; ++e) {
+    const ElemGeo &g = geo[e];
+    WalkGeo &w = wgeo[e];
+    std::memset(&w, 0, sizeof(w));
+    for (int k = 0; k < 3; ++k) {
+      const int a = (k + 1) % 3, b = (k + 2) % 3;
+      const bool fwd = g.n[a] < g.n[b];
+      const int p = fwd ? a : b, q = fwd ? b : a;
+      const double dx = g.x[q] - g.x[p], dy = g.y[q] - g.y[p];
+      w.a[k][0] = g.x[p];
+      w.a[k][1] = g.y[p];
+      w.a[k][2] = fwd ? dx : -dx;
+      w.a[k][3] = fwd ? dy : -dy;
+      w.nb[k] = g.nb[k];
+    }
+    w.wb = g.wb;
+    w.wn = g.wn;
+  }
   std::vector<WallSeg> wseg(w_list.size());
   for (size_t j = 0; j < w_list.size(); ++j) {
     const int32_t b = w_list[j], e = mesh->bedge_elem[b], k = mesh->bedge_local[b];
@@ -859,7 +879,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   m.nb = nb;
   m.n_masters = (int32_t)masters.size();
   m.n_slaves = (int32_t)slaves.size();
-  bool ok = upload(c, geo, &m.geo) && upload(c, mnode, &m.mnode) && upload(c, dN, &m.dN) &&
+  bool ok = upload(c, geo, &m.geo) && upload(c, wgeo, &m.wgeo) && upload(c, mnode, &m.mnode) && upload(c, dN, &m.dN) &&
             upload(c, btype, &m.btype) && upload(c, bpart, &m.bpart) && upload(c, belem, &m.belem) &&
             upload(c, blocal, &m.blocal) && upload(c, bshift, &m.bshift) &&
             upload(c, n2e_off, &m.n2e_off) && upload(c, n2e, &m.n2e) &&

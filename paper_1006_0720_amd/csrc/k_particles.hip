@@ -31,21 +31,16 @@ __device__ __forceinline__ double fmaT(double a, double b, double c) { return __
 // the point and each edge, each edge evaluated from its lower to its higher
 // global node number so that the two elements sharing an edge get the same
 // magnitude with opposite signs.  lam[k] belongs to the edge opposite local
-// node k.
+// node k.  The canonical start points and the oriented edge vectors are
+// stored per element (WalkGeo), so the test is two subtractions, two products
+// and a difference per edge.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void edge_lambdas(const ElemGeo &g, double px, double py, double lam[3]) {
+__device__ __forceinline__ void edge_lambdas(const WalkGeo &g, double px, double py, double lam[3]) {
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int a = (k + 1) % 3, b = (k + 2) % 3;
-    const bool fwd = g.n[a] < g.n[b];
-    const double xp = fwd ? g.x[a] : g.x[b], yp = fwd ? g.y[a] : g.y[b];
-    const double xq = fwd ? g.x[b] : g.x[a], yq = fwd ? g.y[b] : g.y[a];
-    const double cr = (xq - xp) * (py - yp) - (yq - yp) * (px - xp);
-    lam[k] = fwd ? cr : -cr;
-  }
+  for (int k = 0; k < 3; ++k) lam[k] = g.a[k][2] * (py - g.a[k][1]) - g.a[k][3] * (px - g.a[k][0]);
 }
 
-__device__ __forceinline__ bool contains(const ElemGeo &g, double px, double py) {
+__device__ __forceinline__ bool contains(const WalkGeo &g, double px, double py) {
   double l[3];
   edge_lambdas(g, px, py, l);
   return l[0] >= 0.0 && l[1] >= 0.0 && l[2] >= 0.0;
@@ -58,7 +53,7 @@ __device__ int32_t search_patch(const MeshDev &m, int32_t e, double px, double p
     const int32_t n = g.n[k];
     for (int32_t i = ldg(m.n2e_off, n); i < ldg(m.n2e_off, n + 1); ++i) {
       const int32_t c = ldg(m.n2e, i);
-      if (contains(ldg(m.geo, c), px, py)) return c;
+      if (contains(ldg(m.wgeo, c), px, py)) return c;
     }
   }
   return -1;
@@ -77,7 +72,7 @@ __device__ int32_t locate_brute(const MeshDev &m, double px, double py) {
   const size_t c = (size_t)j * m.gnx + i;
   for (int32_t k = ldg(m.cell_off, c); k < ldg(m.cell_off, c + 1); ++k) {
     const int32_t e = ldg(m.cell_list, k);
-    if (contains(ldg(m.geo, e), px, py)) return e;
+    if (contains(ldg(m.wgeo, e), px, py)) return e;
   }
   return -1;
 }
@@ -618,7 +613,7 @@ __device__ __forceinline__ void table_flush(SumTableW &t, double *nsums) {
 template <typename T>
 __device__ __forceinline__ void scatter_shape(SumTableW &t, const MeshDev &m, double *nsums, const T *rec,
                                               int32_t e, double x, double y, T u, T v, T w, T om, T psi) {
-  const ElemGeo g = ldg(m.geo, e);
+  const WalkGeo g = ldg(m.wgeo, e);
   double lam[3], wt[3];
   edge_lambdas(g, x, y, lam);
   shape_w(lam, wt);
@@ -852,7 +847,7 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
     T rl[SHAPE ? NREC : 1];
     const T *r = rec + (size_t)e0 * NREC;
     if constexpr (SHAPE) {
-      const ElemGeo g0 = ldg(m.geo, e0);
+      const WalkGeo g0 = ldg(m.wgeo, e0);
       double lam0[3], w0[3];
       edge_lambdas(g0, x0, y0, lam0);
       shape_w(lam0, w0);
@@ -863,9 +858,18 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
     // ---- noise: six standard normals and one uniform per particle-step ----
     const u32x4 q0 = philox10(id, step, 0u, 0u, k0, k1);
     const u32x4 q1 = philox10(id, step, 1u, 0u, k0, k1);
+    // the position noise in binary64 for FP64 state, on the binary32
+    // transcendental units for FP32 state (as the other four normals)
     double xi0 = 0.0, xi1 = 0.0;
     T xi2, xi3, xi4, xi5;
-    if (VISC || sizeof(T) == 8) box_muller_d(q0.a, q0.b, xi0, xi1);
+    if constexpr (sizeof(T) == 8) {
+      if (VISC) box_muller_d(q0.a, q0.b, xi0, xi1);
+    } else if (VISC) {
+      float z0, z1;
+      box_muller_f(q0.a, q0.b, z0, z1);
+      xi0 = z0;
+      xi1 = z1;
+    }
     if constexpr (sizeof(T) == 8) {
       double a0, a1, a2, a3;
       box_muller_d(q0.c, q0.d, a0, a1);
@@ -926,7 +930,7 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
     const bool finite_pos = isfinite(x) && isfinite(y);
     for (int it = 0; it < 64 && finite_pos; ++it) {
       C_WALK(1);
-      const ElemGeo g = ldg(m.geo, e);
+      const WalkGeo g = ldg(m.wgeo, e);
       double lam[3];
       edge_lambdas(g, x, y, lam);
       if (lam[0] >= 0.0 && lam[1] >= 0.0 && lam[2] >= 0.0) {
@@ -955,9 +959,11 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
         C_PER(1);
         continue;
       }
+      // a boundary edge: the element's vertices and node numbers
+      const ElemGeo gb = ldg(m.geo, e);
       const int ia = (k + 1) % 3, ib = (k + 2) % 3;
-      const double xa = sel3(g.x, ia), ya = sel3(g.y, ia);
-      const double dx = sel3(g.x, ib) - xa, dy = sel3(g.y, ib) - ya;
+      const double xa = sel3(gb.x, ia), ya = sel3(gb.y, ia);
+      const double dx = sel3(gb.x, ib) - xa, dy = sel3(gb.y, ib) - ya;
       const double t = ((x - xa) * dx + (y - ya) * dy) / (dx * dx + dy * dy);
       bool refl = (t >= 0.0 && t <= 1.0);
       if (!refl) {
@@ -965,7 +971,7 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
         // with the domain on its left, a left turn at c (convex or straight
         // corner) puts the point, behind this wall's line, outside the domain;
         // at a reflex corner it is outside only if also behind the other wall
-        const int32_t cn = sel3(g.n, t < 0.0 ? ia : ib);
+        const int32_t cn = sel3(gb.n, t < 0.0 ? ia : ib);
         int32_t wdg = -1;
         for (int32_t j = ldg(m.nwall_off, cn); j < ldg(m.nwall_off, cn + 1); ++j)
           if (ldg(m.nwall, j) != b) {
@@ -1015,8 +1021,8 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
         un1 = (T)((double)un1 - 2.0 * vn * ny);
       } else if (!VISC && bt == PDF_BC_WALLFN) {
         // wall functions go with the inviscid particle equations
-        const double3 rw = wall_function(md, S, gradp, m.nn, ldg(m.master, sel3(g.n, k)), xa, ya, dx, dy,
-                                         sel3(g.x, k), sel3(g.y, k), (double)un0, (double)un1, (double)omn);
+        const double3 rw = wall_function(md, S, gradp, m.nn, ldg(m.master, sel3(gb.n, k)), xa, ya, dx, dy,
+                                         sel3(gb.x, k), sel3(gb.y, k), (double)un0, (double)un1, (double)omn);
         un0 = (T)rw.x;
         un1 = (T)rw.y;
         omn = (T)rw.z;
@@ -1044,8 +1050,8 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
     // ---- no-slip trajectory (b): eq:fw and eq:exp-wall-condition ----
     if (WALLB && nrefl == 0) {
       if (fwn < 0) {  // host found by a fall-back search
-        fwb = ldg(m.geo, found).wb;
-        fwn = ldg(m.geo, found).wn;
+        fwb = ldg(m.wgeo, found).wb;
+        fwn = ldg(m.wgeo, found).wn;
       }
       int32_t best = -1;
       double bd = 0.0;

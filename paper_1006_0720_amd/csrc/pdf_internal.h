@@ -21,6 +21,23 @@ struct ElemGeo {
   int32_t wb, wn;
 };
 
+// Element geometry in the form the element test evaluates (eq:element-test):
+// for the edge opposite local node k, its start point in the canonical
+// direction (from the lower to the higher global node number) and the edge
+// vector from there, negated where that direction runs against the element's
+// counter-clockwise order.  The signed area of point P at edge k is then
+//   lam_k = ex_k (P_y - ay_k) - ey_k (P_x - ax_k),
+// bit-identical to the canonical cross product with its sign flipped as
+// needed (negation is exact), with no selections left to the walk.  Plus the
+// neighbours and the element's range of nearby no-slip wall segments.
+// 128 bytes.
+struct WalkGeo {
+  double a[3][4];  // per edge k: ax, ay, ex, ey
+  int32_t nb[3];
+  int32_t wb, wn;
+  int32_t pad[3];
+};
+
 // A no-slip wall edge near an element: its end points (local nodes k+1 and
 // k+2 of its boundary element, in that order).
 struct WallSeg {
@@ -61,6 +78,7 @@ constexpr int NSUM = 16;
 struct MeshDev {
   int32_t ne, nn, nb;
   const ElemGeo *geo;
+  const WalkGeo *wgeo;      // [ne] the element test's form of the geometry
   const int32_t *mnode;     // [3*ne] master node of each element node
   const double *dN;         // [6*ne] dN_k/dx (k=0..2), dN_k/dy (k=0..2)
   const int32_t *btype, *bpart, *belem, *blocal;

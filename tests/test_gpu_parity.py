@@ -14,7 +14,7 @@ import pytest
 import oracle as O
 from synth import configs as CF
 from synth import meshes as M
-from tests.parity import compare_state, compare_stats
+from tests.parity import compare_elements, compare_state, compare_stats
 
 pytestmark = pytest.mark.gpu
 
@@ -148,7 +148,7 @@ def test_kernel_parity_fp32_channel(L):
     ctx.advance(1, w.dt)
     o.step(w.dt)
     st, el, pid = ctx.particles()
-    assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
+    compare_elements(el, st, o.elem, o.state, w.mesh, "fp32 step", fp32=True)
     compare_state(st, o.state, w.mesh, 1e-5, "fp32 step", elem=o.elem)
     compare_stats(ctx.stats(), o.stats, 1e-5, what="fp32 step stats")
     ctx.close()
@@ -171,7 +171,8 @@ def test_kernel_parity_fp32_canyon_full_size_sampled(L):
     o.step(w.dt, mask=mask)
     st, el, pid = ctx.particles()
     sel = mask.astype(bool)
-    assert np.array_equal(el[sel], o.elem[sel])
+    nd = compare_elements(el[sel], st[:, sel], o.elem[sel], o.state[:, sel], w.mesh, "canyon fp32 step", fp32=True)
+    print(f"[canyon] {sel.sum()} sampled particles, {nd} with positions one ulp apart", flush=True)
     compare_state(st[:, sel], o.state[:, sel], w.mesh, 1e-5, "canyon fp32 step (sample)", elem=o.elem[sel])
     c = ctx.counters()
     assert c["lost"] == 0 and c["nonfinite"] == 0
@@ -284,7 +285,9 @@ def test_kernel_parity_fp32_channel_block_full_size_sampled(L):
     o.step(w.dt, mask=mask)
     say("oracle step on the 1% sample done")
     sel = mask.astype(bool)
-    assert np.array_equal(el1[sel], o.elem[sel]), f"{(el1[sel] != o.elem[sel]).sum()} element mismatches"
+    nd = compare_elements(el1[sel], st1[:, sel], o.elem[sel], o.state[:, sel], w.mesh, "channel_block step 10",
+                          fp32=True)
+    say(f"{sel.sum()} sampled particles, {nd} with positions one ulp apart")
     es = compare_state(st1[:, sel], o.state[:, sel], w.mesh, 1e-5, "channel_block fp32 step (sample)", elem=o.elem[sel])
     say("state error vs the FP64 oracle (max relative): " + ", ".join(f"{k} {v:.2e}" for k, v in es.items()))
     # nodal statistics: the oracle's estimate from the GPU's particles after the step
@@ -338,10 +341,12 @@ def test_kernel_parity_fp32_channel_block_driven_200_steps(L):
         mask[rng.choice(mask.size, mask.size // 100, replace=False)] = 1
         o.step(w.dt, mask=mask)
         sel = mask.astype(bool)
-        assert np.array_equal(el1[sel], o.elem[sel]), f"step {20 * k + 1}: {(el1[sel] != o.elem[sel]).sum()} element mismatches"
+        nd = compare_elements(el1[sel], st1[:, sel], o.elem[sel], o.state[:, sel], w.mesh, f"step {20 * k + 1}",
+                              fp32=True)
         es = compare_state(st1[:, sel], o.state[:, sel], w.mesh, 1e-5, f"channel_block step {20 * k + 1} (sample)", elem=o.elem[sel])
         worst = {n: max(worst.get(n, 0.0), e) for n, e in es.items()}
-        say(f"step {20 * k + 1}: " + ", ".join(f"{n} {e:.1e}" for n, e in es.items()))
+        say(f"step {20 * k + 1}: " + ", ".join(f"{n} {e:.1e}" for n, e in es.items()) +
+            f"; {nd} positions one ulp apart")
     c = ctx.counters()
     assert c["lost"] == 0 and c["nonfinite"] == 0
     g1 = ctx.stats()

@@ -13,7 +13,7 @@ import pytest
 
 import oracle as O
 from synth import configs as CF
-from tests.parity import compare_state, compare_stats
+from tests.parity import compare_elements, compare_state, compare_stats
 
 pytestmark = pytest.mark.gpu
 
@@ -123,7 +123,7 @@ def test_projection_fp32_one_step(L):
     ctx.advance(1, w.dt)
     o.step(w.dt)
     st, el, _ = ctx.particles()
-    assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
+    compare_elements(el, st, o.elem, o.state, w.mesh, "projection fp32 step", fp32=True)
     compare_state(st, o.state, w.mesh, 1e-5, "projection fp32 step", elem=o.elem)
     ctx.close()
 

@@ -9,7 +9,7 @@ import pytest
 import oracle as O
 from synth import configs as CF
 from synth import meshes as M
-from tests.parity import compare_state, compare_stats
+from tests.parity import compare_elements, compare_state, compare_stats
 
 pytestmark = pytest.mark.gpu
 
@@ -96,7 +96,7 @@ def test_shape_kernel_fp32_channel(L):
     ctx.advance(1, w.dt)
     o.step(w.dt)
     st, el, _ = ctx.particles()
-    assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
+    compare_elements(el, st, o.elem, o.state, w.mesh, "shape fp32 step", fp32=True)
     compare_state(st, o.state, w.mesh, 1e-5, "shape fp32 step", elem=o.elem)
     compare_stats(ctx.stats(), o.stats, 1e-5, what="shape fp32 step stats")
     ctx.close()

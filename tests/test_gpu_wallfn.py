@@ -12,7 +12,7 @@ import pytest
 
 import oracle as O
 from synth import configs as CF
-from tests.parity import compare_state, compare_stats
+from tests.parity import compare_elements, compare_state, compare_stats
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +63,7 @@ def test_wallfn_fp32_one_step(L):
     ctx.advance(1, w.dt)
     o.step(w.dt)
     st, el, _ = ctx.particles()
-    assert np.array_equal(el, o.elem), f"{(el != o.elem).sum()} element mismatches"
+    compare_elements(el, st, o.elem, o.state, w.mesh, "wall functions fp32 step", fp32=True)
     compare_state(st, o.state, w.mesh, 1e-5, "wall functions fp32 step", elem=o.elem)
     assert ctx.counters()["reflect"] == o.counter_dict()["reflect"] > 0
     ctx.close()
