@@ -205,6 +205,7 @@ class Oracle:
         # pressure projection: the imposed gradient, the solved pressure P'
         self.gradp_in = np.zeros((2, nn)) if self.gradp is None else self.gradp.copy()
         self.Pp = np.zeros(nn)
+        self.B_prev = None  # the wall data of eq:wall-pressure-condition that P' satisfies
         self.wp_input = None if wp is None else np.ascontiguousarray(wp, np.float64).reshape(9, nn)
         self.stats = np.zeros((NSTAT, nn))
         self.elem_stats = None
@@ -301,7 +302,16 @@ class Oracle:
         from oracle import projection as PR
         m = self.mesh
         est = self.estimate(into_stats=False)
-        dP = PR.solve_dp(m, est[0], est[1], self.Pp, dt, float(self.params.get("Cp", 1e-3)))
+        Cp = float(self.params.get("Cp", 1e-3))
+        # the Neumann data of eq:wall-pressure-condition from the predicted
+        # statistics; B_prev the data P^n satisfies (G.n before the first step)
+        BG = PR.boundary_vector(m, PR.imposed_normal(m, self.gradp_in))
+        if self.B_prev is None:
+            self.B_prev = BG
+        B_new = PR.boundary_vector(m, PR.neumann_data(m, est, float(self.params["nu"])))
+        flux = (Cp / dt) * (self.B_prev - BG) + (B_new - self.B_prev)
+        dP = PR.solve_dp(m, est[0], est[1], self.Pp, dt, Cp, flux=flux)
+        self.B_prev = B_new
         g = PR.elem_gradient(m, dP)
         u = self.state[2] - dt * g[self.elem, 0]
         v = self.state[3] - dt * g[self.elem, 1]

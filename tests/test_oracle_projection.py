@@ -70,3 +70,103 @@ def test_step_corrects_particle_velocities():
     np.testing.assert_allclose(proj.state[3], base.state[3] - w.dt * g[base.elem, 1], rtol=0, atol=1e-15)
     assert np.abs(proj.last_dp).max() > 0
     np.testing.assert_allclose(proj.gradp, PR.node_gradient(w.mesh, proj.Pp), rtol=0, atol=1e-15)
+
+
+# ---- walls: the Neumann condition of eq:wall-pressure-condition ----
+
+def _wall_case(n, with_flux, dt=0.01):
+    """u* = dt grad(phi) on a box with walls: dP = phi when the walls carry
+    dP/dn = dphi/dn (here phi has non-zero normal derivatives on every side)."""
+    mesh = M.box(n, n, 1.0, 1.0, bc=M.BC_NOSLIP)
+    x, y = mesh.node_xy.T
+    phi = np.cos(1.3 * x + 0.4) * np.sin(2.1 * y + 0.7) + 0.5 * x * x
+    U = dt * (-1.3 * np.sin(1.3 * x + 0.4) * np.sin(2.1 * y + 0.7) + x)
+    V = dt * (2.1 * np.cos(1.3 * x + 0.4) * np.cos(2.1 * y + 0.7))
+    W = PR.wall_edges(mesh)
+    g = []
+    for end in ("a", "b"):
+        q = W[end]
+        gx = -1.3 * np.sin(1.3 * x[q] + 0.4) * np.sin(2.1 * y[q] + 0.7) + x[q]
+        gy = 2.1 * np.cos(1.3 * x[q] + 0.4) * np.cos(2.1 * y[q] + 0.7)
+        g.append(gx * W["n"][:, 0] + gy * W["n"][:, 1])
+    flux = PR.boundary_vector(mesh, np.array(g)) if with_flux else None
+    dP = PR.solve_dp(mesh, U, V, np.zeros(mesh.n_nodes), dt, 0.0, flux=flux)
+    return np.abs(dP - (phi - phi.mean())).max()
+
+
+def test_wall_neumann_condition_second_order():
+    # the maximum nodal error approaches second order from below (1.48, 1.63,
+    # 1.70 over 8 -> 16 -> 32 -> 64 cells a side)
+    e1, e2 = _wall_case(32, True), _wall_case(64, True)
+    assert e2 < 1e-3 and 1.6 < math.log2(e1 / e2) < 2.4
+    # natural (zero-flux) conditions miss it by O(1)
+    assert _wall_case(32, False) > 100 * e2
+
+
+def test_wall_edges_and_boundary_vector():
+    mesh = M.box(6, 4, 3.0, 2.0, bc=M.BC_SLIP)
+    W = PR.wall_edges(mesh)
+    # the outward normals of the rectangle's four sides; the lengths add up
+    assert np.isclose(W["L"].sum(), 2 * (3.0 + 2.0))
+    mid = 0.5 * (mesh.node_xy[W["a"]] + mesh.node_xy[W["b"]])
+    out = np.where(np.isclose(mid[:, 0], 0)[:, None], [-1, 0], 0) + np.where(np.isclose(mid[:, 0], 3)[:, None], [1, 0], 0) \
+        + np.where(np.isclose(mid[:, 1], 0)[:, None], [0, -1], 0) + np.where(np.isclose(mid[:, 1], 2)[:, None], [0, 1], 0)
+    np.testing.assert_allclose(W["n"], out, atol=1e-15)
+    # B of a constant integrates it over the boundary; of a linear q, exactly
+    B1 = PR.boundary_vector(mesh, np.ones((2, W["L"].size)))
+    assert np.isclose(B1.sum(), 10.0)
+    xa, xb = mesh.node_xy[W["a"], 0], mesh.node_xy[W["b"], 0]
+    Bx = PR.boundary_vector(mesh, np.array([xa, xb]))
+    # the integral of x over the boundary: two horizontal sides (3^2/2 each) + the right side (3 * 2)
+    assert np.isclose(Bx.sum(), 9.0 + 6.0)
+
+
+def test_neumann_data_closed_form():
+    """Linear Reynolds stresses (their element gradients exact) and given
+    nodal Laplacians: g = nu lap<U>.n - div<uu>.n at every wall edge end."""
+    mesh = M.box(5, 5, 1.0, 1.0, jitter=0.2, seed=3, bc=M.BC_NOSLIP)
+    x, y = mesh.node_xy.T
+    st = np.zeros((25, mesh.n_nodes))
+    st[5] = 0.3 + 0.5 * x - 0.2 * y      # R11
+    st[6] = 0.1 - 0.4 * x + 0.7 * y      # R22
+    st[8] = -0.05 + 0.9 * x + 0.3 * y    # R12
+    st[21] = 1.0 + 2.0 * x               # lap <U>
+    st[22] = -3.0 + y                    # lap <V>
+    nu = 0.02
+    g = PR.neumann_data(mesh, st, nu)
+    W = PR.wall_edges(mesh)
+    divR = np.array([0.5 + 0.3, 0.9 + 0.7])
+    for j, end in enumerate(("a", "b")):
+        q = W[end]
+        ref = nu * (st[21][q] * W["n"][:, 0] + st[22][q] * W["n"][:, 1]) - (divR[0] * W["n"][:, 0] + divR[1] * W["n"][:, 1])
+        np.testing.assert_allclose(g[j], ref, rtol=0, atol=1e-13)
+
+
+def test_step_flux_bookkeeping():
+    """In a step, the boundary term is (C_p/dt) B(g^n - G.n) + B(g^{n+1} - g^n)
+    with g^n the previous step's data (G.n before the first step)."""
+    w = CF.channel(nx=8, n_half=4, ppe=20, precision="f64")
+    w.params = dict(w.params, proj=1, Cp=1e-4)
+    o = O.Oracle(w.mesh, w.params, gradp=w.gradp)
+    o.seed(w.seed)
+    BG = PR.boundary_vector(w.mesh, PR.imposed_normal(w.mesh, o.gradp_in))
+    o.step(w.dt)
+    B1 = o.B_prev
+    assert np.abs(B1).max() > 0
+    # the flux of the first step: (Cp/dt) * 0 + (B1 - BG)
+    est = o.est
+    o2 = O.Oracle(w.mesh, w.params, gradp=w.gradp)
+    o2.seed(w.seed)
+    o2.step(w.dt)
+    assert np.array_equal(o2.B_prev, B1)
+    P0 = np.zeros(w.mesh.n_nodes)
+    # recompute the first solve by hand from the predicted statistics of a third run
+    o3 = O.Oracle(w.mesh, dict(w.params, proj=0), gradp=w.gradp)
+    o3.seed(w.seed)
+    o3.step(w.dt)
+    pred = o3.est
+    Bp = PR.boundary_vector(w.mesh, PR.neumann_data(w.mesh, pred, w.params["nu"]))
+    np.testing.assert_allclose(Bp, B1, rtol=0, atol=1e-14)
+    dP = PR.solve_dp(w.mesh, pred[0], pred[1], P0, w.dt, 1e-4, flux=Bp - BG)
+    np.testing.assert_allclose(dP, o.last_dp, rtol=0, atol=1e-12 * np.abs(dP).max())
+    assert est is not None
