@@ -175,8 +175,13 @@ typedef struct pdf_mesh_desc {
  *                velocity prediction and its estimate <U>*, K dP = -(d + Cp K P')/dt
  *                (eq:pressure-projection-smooth in weak form: K the linear-element
  *                stiffness matrix over the master nodes, d_a = sum_e A_e/3 div_e <U>*,
- *                natural conditions at walls, the right-hand side's mean removed, dP of
- *                zero mean), solved by preconditioned conjugate gradients to proj_tol
+ *                the right-hand side's mean removed, dP of zero mean; at walls the
+ *                Neumann datum g of eq:wall-pressure-condition, nu lap<U_i> n_i -
+ *                d<u_i u_j>/dx_j n_i, less <U_j> d<U_i>/dx_j n_i at PDF_BC_WALLFN
+ *                edges, from the predicted statistics, enters as the boundary
+ *                integrals (Cp/dt) B(g_old - G.n) + B(g_new - g_old), B(q)_a the
+ *                integral of N_a q over the wall edges and g_old the datum P
+ *                satisfies, G.n before the first step), solved by preconditioned conjugate gradients to proj_tol
  *                (preconditioned residual against the right-hand side's) in at most
  *                proj_maxit iterations (the call waits for the stream every 8);
  *                then every particle's velocity changes by -dt grad dP of its element

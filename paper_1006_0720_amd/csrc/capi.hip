@@ -312,6 +312,32 @@ pdf_status proj_setup(pdf_ctx *c, const pdf_mesh_desc *mesh) {
   b.iter = b.stop ? b.stop + 1 : nullptr;
   ok = ok && b.P && b.dP && b.b && b.x && b.r && b.z && b.p && b.q && b.ge && b.gtot && b.scal && b.ring && b.stop;
   if (!ok) return fail(c, PDF_E_OOM, "pressure projection buffers");
+  // the wall edges of eq:wall-pressure-condition: every non-periodic boundary
+  // edge, from local node k+1 to k+2 of its element (the domain on its left),
+  // its outward unit normal and length
+  {
+    std::vector<int4> we;
+    std::vector<double4> wg;
+    for (int32_t bi = 0; bi < mesh->n_bedges; ++bi) {
+      if (mesh->bedge_type[bi] == PDF_BC_PERIODIC) continue;
+      const int32_t e = mesh->bedge_elem[bi], k = mesh->bedge_local[bi];
+      const int32_t na = en[3 * e + (k + 1) % 3], nb = en[3 * e + (k + 2) % 3];
+      const double dx = xy[2 * nb] - xy[2 * na], dy = xy[2 * nb + 1] - xy[2 * na + 1];
+      const double L = std::sqrt(dx * dx + dy * dy);
+      we.push_back(make_int4(master[na], master[nb], e, mesh->bedge_type[bi] == PDF_BC_WALLFN ? 1 : 0));
+      wg.push_back(make_double4(dy / L, -dx / L, L, 0.0));
+    }
+    b.nwe = (int32_t)we.size();
+    if (b.nwe > 0) {
+      ok = upload(c, we, &b.we) && upload(c, wg, &b.wgeom);
+      b.Bnew = (double *)dalloc(c, vn);
+      b.Bprev = (double *)dalloc(c, vn);
+      b.BG = (double *)dalloc(c, vn);
+      if (!ok || !b.Bnew || !b.Bprev || !b.BG) return fail(c, PDF_E_OOM, "pressure projection wall buffers");
+      HIPCHK(c, hipStreamSynchronize(c->stream));  // the host arrays end with this block
+    }
+    b.wall_started = false;
+  }
   // the conjugate-gradient iterations are captured on a stream of the
   // library's own (capture is not possible on the legacy default stream);
   // without it they are launched one by one
@@ -530,7 +556,8 @@ pdf_status advance_impl(pdf_ctx *c, int32_t nsteps, double dt, const double *cfl
       // of the corrected particles
       c->proj_iters += (uint64_t)launch_proj_solve<T>(c->stream, c->md, c->pb, c->stats_est, c->params.Cp, dt, dtp,
                                                       c->params.proj_tol, c->params.proj_maxit,
-                                                      part_view<T>(c, c->cur), c->np, c->emom);
+                                                      part_view<T>(c, c->cur), c->np, c->emom, c->params.nu,
+                                                      c->gradp_set ? c->gradp : nullptr);
       launch_node_stats(c->stream, c->md, c->emom, c->stats_cur, c->stats_est, c->cnt);
       launch_node_derivs(c->stream, c->md, c->stats_est);
       HIPCHK(c, hipGetLastError());

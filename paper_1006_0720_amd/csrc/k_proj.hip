@@ -3,9 +3,15 @@
 //
 // With rho = 1 and P = x.G + P' (G the imposed gradient, P' solved), per step
 // after the velocity prediction and its estimate <U>*:
-//   K dP = -(d + C_p K P') / dt,  d_a = sum_e (A_e / 3) div_e(<U>*),
-// K the stiffness matrix over the master nodes (CSR, assembled once), natural
-// conditions at walls; the right-hand side is made compatible by removing its
+//   K dP = -(d + C_p K P') / dt + (C_p/dt) B(g^n - G.n) + B(g^{n+1} - g^n),
+// d_a = sum_e (A_e / 3) div_e(<U>*), K the stiffness matrix over the master
+// nodes (CSR, assembled once).  g is the wall datum of eq:wall-pressure-
+// condition, dP/dn = nu lap<U_i> n_i - d<u_i u_j>/dx_j n_i (less <U_j>
+// d<U_i>/dx_j n_i at wall-function edges), from the predicted statistics: the
+// nodal Laplacians at an edge's ends and the element gradients of the nodal
+// Reynolds stresses of its element; B(q)_a integrates N_a q over the wall
+// edges (q linear along an edge); g^n is the datum P^n satisfies (G.n before
+// the first step).  The right-hand side is made compatible by removing its
 // mean and dP has zero mean over the masters.  Conjugate gradients from zero,
 // preconditioned by one V-cycle of the smoothed-aggregation hierarchy
 // (k_amg.hip) or, without one, by Jacobi as in the paper.  Then every particle's velocity changes by
@@ -15,6 +21,8 @@
 #include <hip/hip_runtime.h>
 
 #include "pdf_internal.h"
+
+#include <utility>
 
 namespace pdfk {
 
@@ -37,10 +45,70 @@ __device__ __forceinline__ double elem_area(const ElemGeo &g) {
   return 0.5 * ((g.x[1] - g.x[0]) * (g.y[2] - g.y[0]) - (g.x[2] - g.x[0]) * (g.y[1] - g.y[0]));
 }
 
-// b_a = -(d_a + C_p (K P')_a) / dt; bsum += b
+// the wall data at both ends of every wall edge, integrated against the
+// shape functions into Bnew (and G.n into BG); one thread per edge
+__global__ __launch_bounds__(NB) void k_proj_wallflux(MeshDev m, int32_t nwe, const int4 *we, const double4 *wg,
+                                                      const double *S, double nu, const double *gin, double *Bnew,
+                                                      double *BG) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nwe) return;
+  const int nn = m.nn;
+  const int4 w = we[t];
+  const double4 G4 = wg[t];
+  const double nx = G4.x, ny = G4.y, L = G4.z;
+  const int32_t e = w.z;
+  const double *dN = m.dN + 6 * (size_t)e;
+  const int32_t qk[3] = {m.mnode[3 * e], m.mnode[3 * e + 1], m.mnode[3 * e + 2]};
+  // element gradients of the nodal Reynolds stresses R11, R22, R12
+  double g5x = 0.0, g5y = 0.0, g6x = 0.0, g6y = 0.0, g8x = 0.0, g8y = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double r5 = S[5 * (size_t)nn + qk[k]], r6 = S[6 * (size_t)nn + qk[k]], r8 = S[8 * (size_t)nn + qk[k]];
+    g5x += dN[k] * r5;
+    g5y += dN[3 + k] * r5;
+    g6x += dN[k] * r6;
+    g6y += dN[3 + k] * r6;
+    g8x += dN[k] * r8;
+    g8y += dN[3 + k] * r8;
+  }
+  const double dRx = g5x + g8y, dRy = g8x + g6y;
+  double ux = 0.0, uy = 0.0, vx = 0.0, vy = 0.0;
+  if (w.w) {
+    for (int k = 0; k < 3; ++k) {
+      const double u = S[qk[k]], v = S[(size_t)nn + qk[k]];
+      ux += dN[k] * u;
+      uy += dN[3 + k] * u;
+      vx += dN[k] * v;
+      vy += dN[3 + k] * v;
+    }
+  }
+  double g[2], gn[2];
+  const int32_t q[2] = {w.x, w.y};
+  for (int j = 0; j < 2; ++j) {
+    double v = nu * (S[21 * (size_t)nn + q[j]] * nx + S[22 * (size_t)nn + q[j]] * ny) - (dRx * nx + dRy * ny);
+    if (w.w) {
+      const double U = S[q[j]], V = S[(size_t)nn + q[j]];
+      v = v - ((U * ux + V * uy) * nx + (U * vx + V * vy) * ny);
+    }
+    g[j] = v;
+    gn[j] = gin ? gin[q[j]] * nx + gin[(size_t)nn + q[j]] * ny : 0.0;
+  }
+  atomicAdd(&Bnew[q[0]], L * (2.0 * g[0] + g[1]) / 6.0);
+  atomicAdd(&Bnew[q[1]], L * (g[0] + 2.0 * g[1]) / 6.0);
+  atomicAdd(&BG[q[0]], L * (2.0 * gn[0] + gn[1]) / 6.0);
+  atomicAdd(&BG[q[1]], L * (gn[0] + 2.0 * gn[1]) / 6.0);
+}
+
+// before the first step P' = 0 satisfies the imposed gradient's data
+__global__ __launch_bounds__(NB) void k_proj_copy(int32_t n, const double *src, double *dst) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) dst[t] = src[t];
+}
+
+// b_a = -(d_a + C_p (K P')_a) / dt + (C_p/dt) (Bprev - BG)_a + (Bnew - Bprev)_a; bsum += b
 __global__ __launch_bounds__(NB) void k_proj_rhs(MeshDev m, const double *S, const int32_t *row_off,
                                                  const int32_t *cols, const double *kval, const double *P,
-                                                 double Cp, double dt, const double *dtp, double *b, double *bsum) {
+                                                 double Cp, double dt, const double *dtp, const double *Bnew,
+                                                 const double *Bprev, const double *BG, double *b, double *bsum) {
   const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   double v = 0.0;
   if (t < m.n_masters) {
@@ -61,6 +129,7 @@ __global__ __launch_bounds__(NB) void k_proj_rhs(MeshDev m, const double *S, con
     double kp = 0.0;
     for (int32_t j = row_off[a]; j < row_off[a + 1]; ++j) kp += kval[j] * P[cols[j]];
     v = -(d + Cp * kp) / dtv;
+    if (Bnew) v = v + ((Cp / dtv) * (Bprev[a] - BG[a]) + (Bnew[a] - Bprev[a]));
     b[a] = v;
   }
   const double s = block_sum(v);
@@ -305,7 +374,8 @@ void proj_iteration(hipStream_t s, const MeshDev &m, const ProjBuf &b, int j, do
 
 template <typename T>
 int launch_proj_solve(hipStream_t s, const MeshDev &m, ProjBuf &b, const double *S, double Cp, double dt,
-                      const double *dtp, double tol, int maxit, PartDev<T> p, int64_t np, double *emom) {
+                      const double *dtp, double tol, int maxit, PartDev<T> p, int64_t np, double *emom,
+                      double nu, const double *gin) {
   const unsigned gm = (unsigned)((m.n_masters + NB - 1) / NB);
   const double tol2 = tol * tol;
   // scal: [0] bsum, [1] unused, [2] bb, [3] xsum; ring: 8 slots of (pq, r.z),
@@ -313,8 +383,20 @@ int launch_proj_solve(hipStream_t s, const MeshDev &m, ProjBuf &b, const double 
   (void)hipMemsetAsync(b.scal, 0, 4 * sizeof(double), s);
   (void)hipMemsetAsync(b.ring, 0, 16 * sizeof(double), s);
   (void)hipMemsetAsync(b.stop, 0, 2 * sizeof(int), s);  // stop and the iteration counter
-  hipLaunchKernelGGL(k_proj_rhs, dim3(gm), dim3(NB), 0, s, m, S, b.row_off, b.cols, b.kval, b.P, Cp, dt, dtp, b.b,
-                     b.scal);
+  const bool walls = b.nwe > 0;
+  if (walls) {
+    (void)hipMemsetAsync(b.Bnew, 0, (size_t)m.nn * sizeof(double), s);
+    (void)hipMemsetAsync(b.BG, 0, (size_t)m.nn * sizeof(double), s);
+    hipLaunchKernelGGL(k_proj_wallflux, dim3((b.nwe + NB - 1) / NB), dim3(NB), 0, s, m, b.nwe, b.we, b.wgeom, S, nu,
+                       gin, b.Bnew, b.BG);
+    if (!b.wall_started) {
+      hipLaunchKernelGGL(k_proj_copy, dim3((m.nn + NB - 1) / NB), dim3(NB), 0, s, m.nn, b.BG, b.Bprev);
+      b.wall_started = true;
+    }
+  }
+  hipLaunchKernelGGL(k_proj_rhs, dim3(gm), dim3(NB), 0, s, m, S, b.row_off, b.cols, b.kval, b.P, Cp, dt, dtp,
+                     walls ? b.Bnew : nullptr, b.Bprev, b.BG, b.b, b.scal);
+  if (walls) std::swap(b.Bnew, b.Bprev);  // the new data is what P' satisfies from now on
   const bool mg = b.amg.nl > 0;
   const double *kd = mg ? nullptr : b.kdiag;
   hipLaunchKernelGGL(k_proj_start, dim3(gm), dim3(NB), 0, s, m, kd, b.scal, b.b, b.x, b.r, b.z, b.p, b.ring + 15,
@@ -357,8 +439,10 @@ int launch_proj_solve(hipStream_t s, const MeshDev &m, ProjBuf &b, const double 
 }
 
 template int launch_proj_solve<float>(hipStream_t, const MeshDev &, ProjBuf &, const double *, double, double,
-                                      const double *, double, int, PartDev<float>, int64_t, double *);
+                                      const double *, double, int, PartDev<float>, int64_t, double *, double,
+                                      const double *);
 template int launch_proj_solve<double>(hipStream_t, const MeshDev &, ProjBuf &, const double *, double, double,
-                                       const double *, double, int, PartDev<double>, int64_t, double *);
+                                       const double *, double, int, PartDev<double>, int64_t, double *, double,
+                                       const double *);
 
 }  // namespace pdfk

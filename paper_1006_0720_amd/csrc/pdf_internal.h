@@ -233,6 +233,14 @@ struct ProjBuf {
   int *iter = nullptr;
   hipStream_t cap = nullptr;       // private stream on which the iteration chunk is captured
   hipGraphExec_t chunk = nullptr;  // 8 iterations as one graph (null: launched one by one)
+  // wall edges of eq:wall-pressure-condition: (master a, master b, element,
+  // wall-function edge) and (outward normal x, y, length, 0); the boundary
+  // vectors B of the new data, of the data P' satisfies and of G.n
+  int32_t nwe = 0;
+  const int4 *we = nullptr;
+  const double4 *wgeom = nullptr;
+  double *Bnew = nullptr, *Bprev = nullptr, *BG = nullptr;
+  bool wall_started = false;
 };
 void launch_proj_gradp(hipStream_t s, const MeshDev &m, const ProjBuf &b, const double *gin);
 // from the predicted statistics S: dP, P' += dP, the particle correction and
@@ -240,7 +248,8 @@ void launch_proj_gradp(hipStream_t s, const MeshDev &m, const ProjBuf &b, const 
 // for the stream every 8 iterations; the 8 are one captured graph)
 template <typename T>
 int launch_proj_solve(hipStream_t s, const MeshDev &m, ProjBuf &b, const double *S, double Cp, double dt,
-                      const double *dtp, double tol, int maxit, PartDev<T> p, int64_t np, double *emom);
+                      const double *dtp, double tol, int maxit, PartDev<T> p, int64_t np, double *emom,
+                      double nu, const double *gin);
 
 // velocity-conditioned scalar means (eq:IECM): per-element particle lists and
 // the result cm (T[np], storage order)
