@@ -156,23 +156,34 @@ def denoise_timing(ctx, calls):
 
 
 def denoise_study(mode, out_path=""):
-    """Learned-vs-plain cost at equal nodal-statistics error: on the street-
-    canyon mesh (denoiser trained on the GPU from 10 vs 200 particles/element
-    runs), or ('c5') on the 1M-triangle channel with a floor block (10 vs 100
-    particles/element, the scalar line placed at a different x in each run)."""
+    """Learned-vs-plain cost at equal nodal-statistics error (the protocol of
+    paper_1006_0720_amd/denoise_study.py: held-out source positions scored
+    against the ensemble mean of independent high-count runs).
+      bench     the default line's bounded study: the street-canyon mesh
+                (~200k triangles), statistics fed back with the particle
+                redistribution keeping 3 per element, 10 vs 200 particles per
+                element, 16 training pairs, 4 held-out sources x 4 reference
+                runs
+      full      the same with 64 training pairs (4 x 4 = 16 held-out runs)
+      quick     a 20k-triangle canyon, for tests
+      c5        the 1M-triangle channel with a floor block, 10 vs 100 per
+                element, fed back with redistribution, the scalar line at a
+                different x in each run
+    A '-frozen' suffix freezes the model coefficients instead of feeding the
+    statistics back."""
     import numpy as np
 
     from paper_1006_0720_amd.denoise_study import study
     from synth import configs as CF
     from synth import meshes as M
 
-    fed = mode.endswith("-fed")
-    mode = mode[:-4] if fed else mode
+    frozen = mode.endswith("-frozen")
+    mode = mode[:-7] if frozen else mode
+    base = dict(frozen=frozen, min_ppe=0 if frozen else 3)
     if mode == "c5":
         mesh = M.channel_block(1_000_000, 0.15, 0)
-        kw = dict(n_train=12, n_test=3, steps_spin=100, n_snap=5, every=10, train_steps=8000,
-                  batch=8192, ppe_low=10, ppe_high=100, eval_ppes=(20, 40),
-                  source_box=(1.0, 4.0, 0.5, 1.5, 0.05))
+        kw = dict(n_train=16, n_test=3, n_ref=3, steps_spin=100, n_snap=5, every=10, train_steps=4000,
+                  batch=8192, ppe_low=10, ppe_high=100, eval_ppes=(20, 40), source_box=(1.0, 4.0, 0.5, 1.5, 0.05))
 
         def make(ppe, seed, src):
             w = CF.channel_block(mesh=mesh, ppe=ppe, seed=seed)
@@ -181,25 +192,30 @@ def denoise_study(mode, out_path=""):
     else:
         if mode == "quick":
             mesh = M.canyon(20_000, 0.15, 0)
-            kw = dict(n_train=6, n_test=2, steps_spin=40, n_snap=4, every=10, train_steps=600,
+            kw = dict(n_train=8, n_test=2, n_ref=3, steps_spin=40, n_snap=4, every=10, train_steps=1500,
                       batch=4096, eval_ppes=(20, 40))
         else:
             mesh = M.canyon(200_000, 0.15, 0)
-            kw = dict(n_train=12, n_test=3, steps_spin=100, n_snap=5, every=10, train_steps=8000,
-                      batch=8192, eval_ppes=(20, 40, 80))
+            kw = dict(n_train=64 if mode == "full" else 16, n_test=4, n_ref=4, steps_spin=100, n_snap=5,
+                      every=10, train_steps=4000, batch=8192, eval_ppes=(20, 40, 80))
 
         def make(ppe, seed, src):
             return CF.canyon(mesh=mesh, ppe=ppe, seed=seed, src=src)
 
-    if fed:  # statistics fed back, particle redistribution keeping 3 per element
-        kw.update(frozen=False, min_ppe=3)
+    kw.update(base)
     res, params, norm = study(make, log=lambda m: print(m, file=sys.stderr, flush=True), **kw)
     res["mesh_elements"] = mesh.n_elems
-    res["mode"] = mode
+    res["mode"] = mode + ("-frozen" if frozen else "")
+    lv = res["learned"]
+    res["summary"] = {k: {"E": round(lv[k]["E"], 4), "ppe_eq": round(lv[k]["ppe_eq"], 1),
+                          "cost_ratio": round(lv[k]["cost_ratio"], 3)}
+                      for k in ("tau3_noise", "tau3_calibrated", "no_fallback")}
+    res["target_cost_ratio"] = 4.0
+    res["target_met_with_fallback"] = bool(lv["tau3_calibrated"]["cost_ratio"] >= 4.0)
     if out_path:
-        base = os.path.splitext(out_path)[0]
-        json.dump(res, open(base + ".json", "w"), indent=1)
-        np.savez(base + ".npz", params=params, mu=norm[0], sig=norm[1], scale=norm[2])
+        base_p = os.path.splitext(out_path)[0]
+        json.dump(res, open(base_p + ".json", "w"), indent=1)
+        np.savez(base_p + ".npz", params=params, mu=norm[0], sig=norm[1], scale=norm[2])
     return res
 
 
@@ -228,11 +244,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
-    ap.add_argument("--denoise-study", default="",
-                    help="run the learned-vs-plain study on the canyon mesh: 'full' or 'quick' (coefficients "
-                         "frozen), 'full-fed' or 'quick-fed' (statistics fed back, redistribution with a "
-                         "minimum of 3 per element); 'c5' or 'c5-fed' on the 1M-triangle channel with a floor "
-                         "block at 10 vs 100 per element; the result is added as learned_vs_plain")
+    ap.add_argument("--denoise-study", default="bench",
+                    help="the learned-vs-plain study added to the line as learned_vs_plain: 'bench' (the "
+                         "default, bounded: street canyon, fed back, 16 training pairs, 4 held-out sources x 4 "
+                         "reference runs), 'full' (64 training pairs), 'quick', 'c5' (the 1M-triangle channel, "
+                         "10 vs 100 per element), each with an optional '-frozen' suffix; 'none' to skip")
     ap.add_argument("--denoise-calls", type=int, default=0,
                     help="also time this many pdf_denoise_stats calls (features, fused MLP, merge; H = 128, "
                          "seeded untrained weights) on the workload's nodal statistics")
@@ -337,7 +353,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, w)
     ctx.close()
-    if args.denoise_study:
+    if args.denoise_study and args.denoise_study != "none":
         out["learned_vs_plain"] = denoise_study(args.denoise_study, args.study_out)
     print(json.dumps(out), flush=True)
 

@@ -330,7 +330,8 @@ void pdf_destroy(pdf_ctx *ctx);
  * features of the plain estimate (for each statistic: node value, mean, std,
  * min and max over the node and its neighbours, gradient magnitude).  The
  * plain estimator stays as the fallback: a correction larger than tau times
- * the plain standard error at the node is rejected.
+ * the plain standard error at the node (times a per-statistic calibration,
+ * pdf_denoiser_set_fallback) is rejected.
  *
  * Parameter vector (float32, PDF_DN_NPARAM(H) values): W1 [48][H], b1 [H],
  * W2 [H][H], b2 [H], W3 [H][H], b3 [H], W4 [H][8], b4 [8]; y = x W + b.
@@ -353,6 +354,15 @@ pdf_status pdf_denoiser_params(pdf_denoiser *dn, float *host, int64_t n, int32_t
  * scales of the 8 statistics (correction = scale_q * network output q). */
 pdf_status pdf_denoiser_set_norm(pdf_denoiser *dn, const float *mu48, const float *sig48,
                                  const float *scale8);
+
+/* The fallback test's calibration: a correction of statistic q is rejected
+ * where it exceeds tau * kappa8[q] times the plain standard error at the node
+ * (pdf_denoise_stats).  kappa_q = 1 (the default) judges corrections against
+ * the estimator's noise alone; a larger kappa_q against its actual error,
+ * noise and bias, e.g. tau * kappa_q set to a high quantile of the ratio
+ * |error| / standard error that the plain estimator shows on calibration runs.
+ * Each factor positive and finite (PDF_E_INVALID_ARG otherwise). */
+pdf_status pdf_denoiser_set_fallback(pdf_denoiser *dn, const float *kappa8);
 
 /* Features of nodal statistics [PDF_NSTAT][n_nodes] (device pointer; NULL: the
  * context's latest estimate) into feat [n_nodes][48] (device, float32),

@@ -8,6 +8,7 @@ has not been built this module raises at import: there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes as C
+import weakref
 import os
 
 import numpy as np
@@ -187,6 +188,10 @@ class Context:
             raise PdfError(st, lib.pdf_last_error(self.h).decode())
 
     def close(self):
+        """Destroy the context, after the denoisers made on it (their memory
+        comes from the context's allocator and they borrow its mesh)."""
+        for dn in list(getattr(self, "_denoisers", ())):
+            dn.close()
         if getattr(self, "h", None):
             lib.pdf_destroy(self.h)
             self.h = None
@@ -293,6 +298,7 @@ def _declare_denoiser():
         "pdf_denoiser_destroy": ([vp], None),
         "pdf_denoiser_params": ([vp, vp, i64, i32], i32),
         "pdf_denoiser_set_norm": ([vp, vp, vp, vp], i32),
+        "pdf_denoiser_set_fallback": ([vp, vp], i32),
         "pdf_denoiser_features": ([vp, vp, vp, i32], i32),
         "pdf_denoiser_forward": ([vp, vp, i32, vp], i32),
         "pdf_denoiser_train_step": ([vp, vp, vp, i32, C.c_float, C.POINTER(C.c_float), vp], i32),
@@ -326,11 +332,15 @@ class Denoiser:
         h = C.c_void_p()
         ctx._chk(lib.pdf_denoiser_create(ctx.h, hidden, seed, C.byref(h)))
         self.h = h
+        if not hasattr(ctx, "_denoisers"):
+            ctx._denoisers = weakref.WeakSet()
+        ctx._denoisers.add(self)
 
     def close(self):
-        if getattr(self, "h", None):
+        # a denoiser whose context is already gone was destroyed with it
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
             lib.pdf_denoiser_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
@@ -352,6 +362,13 @@ class Denoiser:
         mu, sig, scale = (np.ascontiguousarray(a, np.float32) for a in (mu, sig, scale))
         self.ctx._chk(lib.pdf_denoiser_set_norm(self.h, _ptr(mu), _ptr(sig), _ptr(scale)))
         self.norm = (mu.copy(), sig.copy(), scale.copy())
+
+    def set_fallback(self, kappa):
+        """Per-statistic calibration of the fallback test (8 positive factors)."""
+        kappa = np.ascontiguousarray(kappa, np.float32)
+        assert kappa.size == DN_NOUT
+        self.ctx._chk(lib.pdf_denoiser_set_fallback(self.h, _ptr(kappa)))
+        self.kappa = kappa.copy()
 
     def features(self, nodal=None, standardized=False):
         """Features [n_nodes, 48] (torch, device) of nodal statistics (torch

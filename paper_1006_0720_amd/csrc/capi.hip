@@ -1492,6 +1492,17 @@ pdf_status pdf_denoiser_set_norm(pdf_denoiser *d, const float *mu48, const float
   return PDF_OK;
 }
 
+pdf_status pdf_denoiser_set_fallback(pdf_denoiser *d, const float *kappa8) {
+  if (!d || !kappa8) return PDF_E_INVALID_ARG;
+  for (int i = 0; i < PDF_DN_NOUT; ++i)
+    if (!(kappa8[i] > 0.f) || !std::isfinite(kappa8[i]))
+      return fail(d->ctx, PDF_E_INVALID_ARG, "fallback factors must be positive and finite");
+  pdf_ctx *c = d->ctx;
+  HIPCHK(c, hipMemcpyAsync(d->scale + PDF_DN_NOUT, kappa8, PDF_DN_NOUT * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PDF_OK;
+}
+
 pdf_status pdf_denoiser_features(pdf_denoiser *d, const double *nodal, float *feat, int32_t standardized) {
   if (!d || !feat) return PDF_E_INVALID_ARG;
   pdf_ctx *c = d->ctx;

@@ -543,8 +543,10 @@ void launch_features(hipStream_t s, const MeshDev &m, const int32_t *p2p_off, co
   launch_features_range(s, m, p2p_off, p2p, gw, S, mu, sig, 0, m.nn, F, Fb);
 }
 
-// Merge: q = q_plain + scale_q * r_q, except where |scale_q r_q| exceeds tau
-// times the plain estimator's standard error at the node (then q = q_plain).
+// Merge: q = q_plain + scale_q * r_q, except where |scale_q r_q| exceeds
+// tau * kappa_q times the plain estimator's standard error at the node (then
+// q = q_plain).  scale holds 16 values: scale_q (0..7), then kappa_q (8..15),
+// the calibration of the standard error to the plain estimator's actual error.
 // Standard errors from the plain second moments and the particle support N:
 // <U>: sqrt(<uu>/N), <V>: sqrt(<vv>/N), <phi>: sqrt(<phi'^2>/N), second
 // moments s: s sqrt(2/N), <uv>: sqrt((<uu><vv> + <uv>^2)/N), <omega>: <omega>
@@ -577,7 +579,7 @@ __global__ void k_merge(int nn, const int32_t *master, const double *S, int32_t 
     for (int a = 0; a < 8; ++a) {
       const int fld = kQuant[a];
       const double corr = (double)scale[a] * (double)R[(size_t)r * ldr + a];
-      ok[a] = fabs(corr) <= tau * se[a];
+      ok[a] = fabs(corr) <= tau * (double)scale[8 + a] * se[a];
       mv[a] = S[(size_t)fld * nn + q] + corr;
       fb += ok[a] ? 0 : 1;
     }

@@ -29,7 +29,8 @@ def env():
 
     w = CF.periodic_square(n=8, ppe=20)
     ctx = workload_context(w)
-    return torch, _lib, ctx, w
+    yield torch, _lib, ctx, w
+    ctx.close()  # and any denoiser a failed test left open
 
 
 def _tensors(torch, x, t):
@@ -138,6 +139,56 @@ def test_merge_zero_network_and_fallback(env):
         assert np.all(d[se[fld] * 3.0 < 1e-9 * (1 - 1e-6)] == 0)
         rejected += int((se[fld] * 3.0 < 1e-9 * (1 - 1e-6)).sum())
     assert nf == rejected
+    dn.close()
+
+
+def test_merge_calibrated_fallback(env):
+    """pdf_denoiser_set_fallback: with factor kappa_q the threshold of
+    statistic q is tau * kappa_q * SE_q; a correction of size c is taken where
+    tau * kappa_q * SE_q >= c, per statistic; invalid factors are refused."""
+    torch, L, ctx, w = env
+    dn = L.Denoiser(ctx, hidden=32)
+    plain = ctx.stats()
+    p = np.zeros(dn.n_param, np.float32)
+    p[-8:] = 1.0  # a constant network output of 1 for every statistic
+    dn.set_params(p)
+    N = plain[24]
+    se = {0: np.sqrt(np.abs(plain[5]) / N), 1: np.sqrt(np.abs(plain[6]) / N),
+          4: np.sqrt(np.abs(plain[11]) / N), 5: np.abs(plain[5]) * np.sqrt(2 / N),
+          6: np.abs(plain[6]) * np.sqrt(2 / N), 8: np.sqrt((np.abs(plain[5] * plain[6]) + plain[8] ** 2) / N),
+          11: np.abs(plain[11]) * np.sqrt(2 / N), 3: np.abs(plain[3]) * np.sqrt(0.25 / N)}
+    kappa = np.array([1.0, 2.0, 4.0, 8.0, 1.5, 3.0, 6.0, 10.0], np.float32)
+    # corrections c_q that split the nodes: the 60th percentile of the
+    # positive thresholds tau kappa_q SE_q (tau = 1)
+    # (a statistic with no spread anywhere, such as the scalar variance of a
+    # scalar that is uniform in every element, gets 1: every correction rejected)
+    cs = np.array([np.percentile((kappa[a] * se[fld])[se[fld] > 0], 60) if (se[fld] > 0).any() else 1.0
+                   for a, fld in enumerate(M.QUANT)])
+    dn.set_norm(np.zeros(48), np.ones(48), cs.astype(np.float32))
+    cs = cs.astype(np.float32).astype(np.float64)
+    dn.set_fallback(kappa)
+    out, nf = dn.denoise(tau=1.0)
+    rejected = border = 0
+    for a, fld in enumerate(M.QUANT):
+        c = cs[a]
+        thr = 1.0 * float(kappa[a]) * se[fld]
+        d = out[fld] - plain[fld]
+        acc = thr >= c * (1 + 1e-6)
+        rej = thr < c * (1 - 1e-6)
+        if (se[fld] > 0).any():
+            assert acc.any() and rej.any(), fld  # the case splits the nodes
+        assert np.allclose(d[acc], c, rtol=1e-6, atol=0)
+        assert np.all(d[rej] == 0)
+        rejected += int(rej.sum())
+        border += int((~acc & ~rej).sum())  # within rounding of the threshold: either way
+    assert rejected <= nf <= rejected + border
+    # back to the noise-only test
+    dn.set_fallback(np.ones(8))
+    _, nf1 = dn.denoise(tau=1.0)
+    assert nf1 > nf
+    for bad in (np.zeros(8), np.full(8, -1.0), np.full(8, np.inf)):
+        with pytest.raises(L.PdfError):
+            dn.set_fallback(bad)
     dn.close()
 
 
