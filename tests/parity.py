@@ -99,3 +99,62 @@ def compare_elements(gpu_el, gpu_state, ref_el, ref_state, mesh, what="", fp32=F
             lam = om.lambdas(int(gpu_el[i]), float(gpu_state[0, i]), float(gpu_state[1, i]))
             assert (lam >= 0.0).all(), f"{what}: particle {i} is outside its GPU host element"
     return int(idx.size)
+
+
+def derivative_bounds(mesh, gpu, ref):
+    """Per-node bounds (tol1, tol2) on the discrepancy of the FEM derivative
+    fields, first derivatives 15-20 and Laplacians 21-23, that follows from
+    the discrepancy of the nodal means 0-2 they are formed from (eq:gradient
+    with the two-pass node averaging).
+
+    A nodal first derivative averages, over the c elements of the node's ring,
+    the element gradient sum_k m_k grad N_k.  For a linear triangle
+    |grad N_k| = L_k / (2A), L_k the edge opposite vertex k, so a change of
+    at most d in every mean moves each component by at most a1 d, with
+    r_e = P_e / (2A_e) (P_e the perimeter) and a1 = max of r_e over the ring.
+    The Laplacians apply the same operator to the first derivatives: their
+    change is at most max over the ring of r_e times the largest tol1 at the
+    element's nodes.  Each side also rounds its own sums, at most 6c
+    operations (forming ring weights, then applying them) on terms of size at
+    most a M, M the largest magnitude of the operator's input: gamma a M with
+    gamma = 12 c_max 2^-53 covers both sides.  d is the measured largest
+    discrepancy of fields 0-2."""
+    xy = np.asarray(mesh.node_xy, np.float64)
+    en = np.asarray(mesh.elem_nodes)
+    mst = np.asarray(mesh.node_master)
+    nn = xy.shape[0]
+    p = xy[en]  # (ne, 3, 2)
+    edges = np.roll(p, -1, axis=1) - p
+    perim = np.sqrt((edges ** 2).sum(-1)).sum(1)
+    area2 = np.abs(edges[:, 0, 0] * edges[:, 1, 1] - edges[:, 0, 1] * edges[:, 1, 0])
+    r = perim / area2
+    q = mst[en]  # masters of each element's nodes
+    a1 = np.zeros(nn)
+    cnt = np.zeros(nn, np.int64)
+    for k in range(3):
+        np.maximum.at(a1, q[:, k], r)
+        np.add.at(cnt, q[:, k], 1)
+    s = r * a1[q].max(1)
+    a2 = np.zeros(nn)
+    for k in range(3):
+        np.maximum.at(a2, q[:, k], s)
+    gamma = 12.0 * int(cnt.max()) * 2.0 ** -53
+    d0 = float(np.abs(np.asarray(gpu)[0:3] - np.asarray(ref)[0:3]).max())
+    M0 = float(np.abs(np.asarray(ref)[0:3]).max())
+    M1 = float(np.abs(np.asarray(ref)[15:21]).max())
+    e0 = d0 + gamma * M0
+    tol1 = (a1 * e0)[mst]
+    tol2 = (a2 * e0 + gamma * a1 * M1)[mst]
+    return tol1, tol2
+
+
+def compare_derivatives(mesh, gpu, ref, what=""):
+    """Fields 15-23 within derivative_bounds; returns the largest ratio of
+    discrepancy to bound for the first derivatives and the Laplacians."""
+    tol1, tol2 = derivative_bounds(mesh, gpu, ref)
+    gpu = np.asarray(gpu)
+    ref = np.asarray(ref)
+    r1 = float((np.abs(gpu[15:21] - ref[15:21]) / np.maximum(tol1, 1e-300)).max())
+    r2 = float((np.abs(gpu[21:24] - ref[21:24]) / np.maximum(tol2, 1e-300)).max())
+    assert r1 <= 1.0 and r2 <= 1.0, f"{what}: derivative discrepancy over its bound ({r1:.3g}, {r2:.3g})"
+    return r1, r2

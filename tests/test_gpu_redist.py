@@ -11,7 +11,7 @@ import pytest
 import oracle as O
 from synth import configs as CF
 from synth import meshes as M
-from tests.parity import compare_elements, compare_state, compare_stats
+from tests.parity import compare_derivatives, compare_elements, compare_state, compare_stats
 
 pytestmark = pytest.mark.gpu
 
@@ -77,9 +77,10 @@ def test_redistribution_trajectory_fp64(L, reorder):
 def test_redistribution_fed_back_shape_fp64(L):
     """Fed-back SHAPE statistics with redistribution.  The estimated moments
     (fields 0-14, 24) are held to 1e-12; their FEM first and second
-    derivatives (15-23) to 1e-10: the two sides sum the nodal means in
-    different orders, and on this grid (element sizes from 1e-3 to 6e-2) the
-    derivatives amplify those rounding differences by 1/h and 1/h^2."""
+    derivatives (15-23) to the bound that the measured discrepancy of the
+    nodal means implies through the derivative operator on this grid (element
+    sizes from 1e-3 to 6e-2 amplify it by up to P/(2A) per derivative), see
+    tests/parity.derivative_bounds."""
     w, fz = _workload(power=2.0, ppe=16, min_ppe=5, stats_mode=CF.STATS_SHAPE, frozen=0)
     ctx, o = _pair(w, fz)
     ctx.advance(15, w.dt)
@@ -87,7 +88,8 @@ def test_redistribution_fed_back_shape_fp64(L):
     _check(ctx, o, w, 1e-12, "redistribution, SHAPE, fed back", stats=False)
     g = ctx.stats()
     compare_stats(g, o.stats, 1e-12, fields=list(range(15)) + [24], what="SHAPE fed back, moments")
-    compare_stats(g, o.stats, 1e-10, fields=range(15, 24), what="SHAPE fed back, derivatives")
+    r1, r2 = compare_derivatives(w.mesh, g, o.stats, what="SHAPE fed back, derivatives")
+    print(f"[redist] derivative discrepancy / bound: first {r1:.3g}, Laplacian {r2:.3g}", flush=True)
     assert ctx.counters()["redist"] == o.counter_dict()["redist"] > 0
     ctx.close()
 
