@@ -342,7 +342,8 @@ def main():
                    "particles_per_element": int(w.seed["ppe"]), "dt": w.dt,
                    "reorder_every": args.reorder_every, "stats_mode": args.stats_mode,
                    "min_ppe": args.min_ppe, "mix": args.mix, "wp": args.wp, "proj": bool(args.proj)} |
-                  ({"proj_precond": args.proj_precond} if args.proj else {}),
+                  ({"proj_precond": args.proj_precond, "Cp": w.params["Cp"],
+                    "proj_tol": w.params["proj_tol"]} if args.proj else {}),
         "roofline": roof,
         "phase_ms_per_step": {k: round(v / args.steps, 4) for k, v in tm.items()},
         "counters": {k: cnt[k] for k in ("lost", "brute", "fallback", "nonfinite", "empty_node", "redist",

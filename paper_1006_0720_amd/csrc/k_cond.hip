@@ -59,29 +59,60 @@ struct Passes {
   int32_t groups[3];
 };
 
+// entry k of a 3-array by selects (a dynamic index would go through scratch)
+__device__ __forceinline__ int32_t pick3(const int32_t (&a)[3], int k) { return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]); }
+
 __device__ __forceinline__ Passes plan_passes(const ModelDev &md, int32_t n) {
   const int32_t f[3] = {md.cond_nu, md.cond_nv, md.cond_nw};
   Passes ps;
   ps.n_pass = 0;
+  ps.dir[0] = -1;  // with no level taken: one pass by id
+  ps.dir[1] = ps.dir[2] = 0;
+  ps.groups[0] = 1;
+  ps.groups[1] = ps.groups[2] = 1;
   int32_t nc = 1;
+  bool go = true;
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    if (f[d] <= 1) continue;
+    if (!go || f[d] <= 1) continue;
     const int32_t next = nc * f[d];
-    if (n / next < md.cond_min) break;  // the adaptive stop
-    ps.dir[ps.n_pass] = d;
-    ps.groups[ps.n_pass] = next;
+    if (n / next < md.cond_min) {  // the adaptive stop
+      go = false;
+      continue;
+    }
+    // slot ps.n_pass, written through selects (a dynamic index goes through scratch)
+    const int k = ps.n_pass;
+    if (k == 0) {
+      ps.dir[0] = d;
+      ps.groups[0] = next;
+    } else if (k == 1) {
+      ps.dir[1] = d;
+      ps.groups[1] = next;
+    } else {
+      ps.dir[2] = d;
+      ps.groups[2] = next;
+    }
     ps.n_pass++;
     nc = next;
   }
-  if (ps.n_pass == 0) {
-    ps.n_pass = 1;
-    ps.dir[0] = -1;
-    ps.groups[0] = 1;
-  }
+  if (ps.n_pass == 0) ps.n_pass = 1;
   return ps;
 }
 
 __device__ __forceinline__ int32_t gstart(int64_t g, int64_t n, int64_t P) { return (int32_t)((g * n + P - 1) / P); }
+
+// barrier of the NT threads that share one element's LDS: a whole workgroup,
+// or (NT = 64) one wave, whose LDS accesses complete in issue order
+template <int NT>
+__device__ __forceinline__ void grp_sync() {
+  if constexpr (NT == 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
 
 // run-length aggregation of equal element numbers over a wave (particles are
 // mostly sorted by element): a run is a stretch of valid lanes with the same
@@ -210,6 +241,7 @@ __global__ __launch_bounds__(TT) void k_cond_fill(int64_t np, int32_t ne, const 
 // ---- sort and divide in LDS: one element of at most CAP particles per
 // 64-thread workgroup ----
 constexpr int CAP_S = 128, CAP_M = 512;
+constexpr int32_t SMALL_GRID = 1 << 30;  // workgroups of k_cond_small at most
 
 template <typename T, int CAP>
 struct CondLds {
@@ -258,9 +290,8 @@ __device__ __forceinline__ int32_t rank_in(const CondLds<T, CAP> &L, int cur, in
 // the first division (one group): each thread ranks its QP positions in one
 // sweep over all n keys, read once per sweep
 template <typename T, int CAP, int NT>
-__device__ __forceinline__ void rank_all(const CondLds<T, CAP> &L, int cur, int32_t n, int32_t rank[]) {
+__device__ __forceinline__ void rank_all(const CondLds<T, CAP> &L, int cur, int32_t n, int32_t rank[], int t) {
   constexpr int QP = CAP / NT;
-  const int t = threadIdx.x;
   uint64_t mk[QP];
   uint32_t mi[QP];
 #pragma unroll
@@ -286,12 +317,11 @@ __device__ __forceinline__ void rank_all(const CondLds<T, CAP> &L, int cur, int3
 }
 
 // sort and divide the n <= CAP particles of one element (list[base, base+n))
-// with NT threads, and write every particle's bin mean
+// with NT threads (t = 0..NT-1), and write every particle's bin mean
 template <typename T, int CAP, int NT>
 __device__ void cond_element(CondLds<T, CAP> &L, const ModelDev &md, const PartDev<T> &p, int32_t n, int32_t base,
-                             const int32_t *list, T *cm) {
+                             const int32_t *list, T *cm, int t) {
   constexpr int QP = CAP / NT;
-  const int t = threadIdx.x;
   for (int q = t; q < n; q += NT) {
     const int32_t i = list[base + q];
     L.idx[q] = i;
@@ -301,28 +331,28 @@ __device__ void cond_element(CondLds<T, CAP> &L, const ModelDev &md, const PartD
     L.kw[q] = p.w[i];
     L.psi[q] = p.psi[i];
   }
-  __syncthreads();
+  grp_sync<NT>();
   const Passes ps = plan_passes(md, n);
   for (int q = t; q < n; q += NT) {
     L.s[0][q] = (uint16_t)q;
     set_key(L, 0, q, q, ps.dir[0]);
   }
-  __syncthreads();
+  grp_sync<NT>();
   int cur = 0;
   int32_t nc = 1;
   for (int pass = 0; pass < ps.n_pass; ++pass) {
     const bool more = pass + 1 < ps.n_pass;
-    const int nextdir = more ? ps.dir[pass + 1] : 0;
+    const int nextdir = more ? pick3(ps.dir, pass + 1) : 0;
     // FP32 ranks are strict-order counts, a permutation only while the ids are
     // unique: the target positions first get a valid slot so that repeated
     // ids can only give wrong bins, never an index outside the element
     if constexpr (sizeof(T) == 4) {
       for (int q = t; q < n; q += NT) L.s[1 - cur][q] = 0;
-      __syncthreads();
+      grp_sync<NT>();
     }
     int32_t rank[QP];
     if (nc == 1) {
-      rank_all<T, CAP, NT>(L, cur, n, rank);
+      rank_all<T, CAP, NT>(L, cur, n, rank, t);
     } else {
 #pragma unroll
       for (int j = 0; j < QP; ++j) {
@@ -344,9 +374,9 @@ __device__ void cond_element(CondLds<T, CAP> &L, const ModelDev &md, const PartD
         if (more) set_key(L, 1 - cur, np_, sl, nextdir);
       }
     }
-    __syncthreads();
+    grp_sync<NT>();
     cur = 1 - cur;
-    nc = ps.groups[pass];
+    nc = pick3(ps.groups, pass);
   }
   // bin means (App. B), each bin summed in the order of its positions
   for (int32_t b = t; b < nc; b += NT) {
@@ -358,27 +388,31 @@ __device__ void cond_element(CondLds<T, CAP> &L, const ModelDev &md, const PartD
   }
 }
 
-// every element: those of at most CAP_S particles here, the others listed
-// for the mid-size and large-element kernels
+// every element: those of at most CAP_S particles here, one per wave at a
+// time (SW waves per workgroup, each with its own LDS), the others listed for
+// the mid-size and large-element kernels
+constexpr int SW = 4;
 template <typename T>
-__global__ __launch_bounds__(64) void k_cond_small(int32_t ne, ModelDev md, PartDev<T> p, const int32_t *cnt,
-                                                   const int32_t *off, const int32_t *list, int32_t *mid,
-                                                   int32_t *big, int32_t *counters, T *cm) {
-  __shared__ CondLds<T, CAP_S> L;
-  const int32_t e = blockIdx.x;
-  if (e >= ne) return;
-  const int32_t n = cnt[e];
-  if (n == 0) return;
-  if (n > CAP_S) {
-    if (threadIdx.x == 0) {
-      if (n > CAP_M)
-        big[atomicAdd(&counters[0], 1)] = e;
-      else
-        mid[atomicAdd(&counters[1], 1)] = e;
+__global__ __launch_bounds__(64 * SW) void k_cond_small(int32_t ne, ModelDev md, PartDev<T> p, const int32_t *cnt,
+                                                        const int32_t *off, const int32_t *list, int32_t *mid,
+                                                        int32_t *big, int32_t *counters, T *cm) {
+  __shared__ CondLds<T, CAP_S> L[SW];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int32_t e = blockIdx.x * SW + w; e < ne; e += gridDim.x * SW) {
+    const int32_t n = cnt[e];
+    if (n == 0) continue;
+    if (n > CAP_S) {
+      if (lane == 0) {
+        if (n > CAP_M)
+          big[atomicAdd(&counters[0], 1)] = e;
+        else
+          mid[atomicAdd(&counters[1], 1)] = e;
+      }
+      continue;
     }
-    return;
+    cond_element<T, CAP_S, 64>(L[w], md, p, n, off[e], list, cm, lane);
+    grp_sync<64>();  // before the wave's next element overwrites its LDS
   }
-  cond_element<T, CAP_S, 64>(L, md, p, n, off[e], list, cm);
 }
 
 // the listed elements of CAP_S+1..CAP_M particles, one per 256-thread
@@ -391,7 +425,7 @@ __global__ __launch_bounds__(256) void k_cond_mid(ModelDev md, PartDev<T> p, con
   const int32_t nm = counters[1];
   for (int32_t k = blockIdx.x; k < nm; k += gridDim.x) {
     const int32_t e = mid[k];
-    cond_element<T, CAP_M, 256>(L, md, p, cnt[e], off[e], list, cm);
+    cond_element<T, CAP_M, 256>(L, md, p, cnt[e], off[e], list, cm, threadIdx.x);
     __syncthreads();  // before the next element overwrites the LDS
   }
 }
@@ -414,7 +448,7 @@ __global__ __launch_bounds__(BT) void k_cond_block(ModelDev md, PartDev<T> p, co
     const Passes ps = plan_passes(md, n);
     int32_t nc = 1;
     for (int pass = 0; pass < ps.n_pass; ++pass) {
-      const int dir = ps.dir[pass];
+      const int dir = pick3(ps.dir, pass);
       for (int32_t c0 = 0; c0 < n; c0 += BT) {
         const int32_t q = c0 + t;
         const int32_t qlast = (c0 + BT < n ? c0 + BT : n) - 1;
@@ -456,7 +490,7 @@ __global__ __launch_bounds__(BT) void k_cond_block(ModelDev md, PartDev<T> p, co
       int32_t *tmp = A;
       A = B;
       B = tmp;
-      nc = ps.groups[pass];
+      nc = pick3(ps.groups, pass);
     }
     for (int32_t b = t; b < nc; b += BT) {
       const int32_t s0 = gstart(b, n, nc), s1 = gstart(b + 1, n, nc);
@@ -512,8 +546,9 @@ hipError_t launch_cond_means(hipStream_t s, const ModelDev &md, const CondBuf &b
   (void)hipMemsetAsync(b.nbig, 0, 8, s);
   hipLaunchKernelGGL(k_cond_fill, dim3(gt), dim3(TT), 0, s, np, ne, p.e, b.off, b.cursor, b.list);
   T *cm = (T *)b.cm;
-  hipLaunchKernelGGL(k_cond_small<T>, dim3((unsigned)ne), dim3(64), 0, s, ne, md, p, b.cnt, b.off, b.list, b.mid,
-                     b.big, b.nbig, cm);
+  const int32_t gs = (ne + SW - 1) / SW;
+  hipLaunchKernelGGL(k_cond_small<T>, dim3((unsigned)(gs < SMALL_GRID ? gs : SMALL_GRID)), dim3(64 * SW), 0, s, ne,
+                     md, p, b.cnt, b.off, b.list, b.mid, b.big, b.nbig, cm);
   hipLaunchKernelGGL(k_cond_mid<T>, dim3((unsigned)(ne < 65536 ? ne : 65536)), dim3(256), 0, s, md, p, b.cnt, b.off,
                      b.list, b.mid, b.nbig, cm);
   hipLaunchKernelGGL(k_cond_block<T>, dim3(512), dim3(BT), 0, s, md, p, b.cnt, b.off, b.list, b.list2, b.big,

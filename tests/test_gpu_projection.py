@@ -135,3 +135,52 @@ def test_projection_parameter_checks(L):
         with pytest.raises(L.PdfError) as ei:
             L.Context(w.mesh, dict(w.params, **bad))
         assert ei.value.status == 1, bad
+
+
+def test_projection_canyon_200_steps(L):
+    """The street canyon with the projection and the wall datum over 200
+    steps (C_p = 0.1 dt, redistribution keeping 3 per element): the GPU run
+    stays with the oracle's (element indices bit-exact, FP64 state within
+    1e-10, the solved P' within 1e-9 of its largest magnitude), both finite
+    and without lost particles."""
+    w = CF.canyon(target_elems=4000, ppe=12, precision="f64")
+    w.params = dict(w.params, proj=1, Cp=0.1 * w.dt, min_ppe=3, proj_tol=1e-14, proj_maxit=5000)
+    ctx, o = _pair(w)
+    for chunk in range(4):
+        ctx.advance(50, w.dt)
+        o.run(w.dt, 50)
+        st, el, _ = ctx.particles()
+        what = f"canyon projection step {50 * (chunk + 1)}"
+        assert np.array_equal(el, o.elem), f"{what}: {(el != o.elem).sum()} element mismatches"
+        compare_state(st, o.state, w.mesh, 1e-10, what, elem=o.elem)
+        P = ctx.nodal_field(L.FIELD_PRESSURE)[0]
+        assert np.abs(P - o.Pp).max() <= 1e-9 * np.abs(o.Pp).max(), what
+    c, oc = ctx.counters(), o.counter_dict()
+    assert c["lost"] == oc["lost"] == 0 and c["nonfinite"] == 0
+    assert c["redist"] == oc["redist"] > 0
+    ctx.close()
+
+
+def test_projection_canyon_20k_stable(L):
+    """At 20k triangles and 20 particles per element (the bench's projected
+    canyon, C_p = 0.1 dt, solved to 1e-6) 200 projected steps stay finite,
+    lose no particle and keep the RMS speed within 25 % of its start."""
+    from paper_1006_0720_amd.runner import workload_context
+
+    w = CF.canyon(target_elems=20000, ppe=20, precision="f64")
+    w.params = dict(w.params, proj=1, Cp=0.1 * w.dt, min_ppe=3, proj_tol=1e-6, proj_maxit=2000)
+    ctx = workload_context(w)
+    st, _, _ = ctx.particles()
+    rms0 = np.sqrt((st[2] ** 2 + st[3] ** 2).mean())
+    for k in range(4):
+        ctx.advance(50, w.dt)
+        st, _, _ = ctx.particles()
+        rms = np.sqrt((st[2] ** 2 + st[3] ** 2).mean())
+        P = ctx.nodal_field(L.FIELD_PRESSURE)[0]
+        print(f"[projection] canyon 20k step {50 * (k + 1)}: rms speed {rms:.4g} (start {rms0:.4g}), "
+              f"P' {P.min():.4g}..{P.max():.4g}", flush=True)
+        assert np.isfinite(st).all() and np.isfinite(P).all()
+        assert 0.75 * rms0 <= rms <= 1.25 * rms0
+    c = ctx.counters()
+    assert c["lost"] == 0 and c["nonfinite"] == 0
+    ctx.close()

@@ -170,3 +170,21 @@ def test_step_flux_bookkeeping():
     dP = PR.solve_dp(w.mesh, pred[0], pred[1], P0, w.dt, 1e-4, flux=Bp - BG)
     np.testing.assert_allclose(dP, o.last_dp, rtol=0, atol=1e-12 * np.abs(dP).max())
     assert est is not None
+
+
+def test_canyon_with_projection_stays_finite_200_steps():
+    """The street canyon (floor blocks with reflex corners, slip top,
+    streamwise periodic) with the projection and the wall datum, C_p = 0.1 dt
+    and the redistribution keeping 3 per element: 200 steps stay finite, lose
+    no particle and keep the RMS speed within 25 % of its start."""
+    w = CF.canyon(target_elems=4000, ppe=12, precision="f64")
+    w.params = dict(w.params, proj=1, Cp=0.1 * w.dt, min_ppe=3)
+    o = O.Oracle(w.mesh, w.params, gradp=w.gradp)
+    o.seed(w.seed)
+    rms0 = np.sqrt((o.state[2] ** 2 + o.state[3] ** 2).mean())
+    for _ in range(4):
+        o.run(w.dt, 50)
+        rms = np.sqrt((o.state[2] ** 2 + o.state[3] ** 2).mean())
+        assert np.isfinite(o.state).all() and np.isfinite(o.Pp).all()
+        assert 0.75 * rms0 <= rms <= 1.25 * rms0, (rms, rms0)
+    assert o.counter_dict()["lost"] == 0
