@@ -237,6 +237,8 @@ def main():
     ap.add_argument("--wp", default="local", choices=["local", "elliptic"],
                     help="tensor wp_ij of the generalized Langevin model: the local right-hand side of the "
                          "elliptic relaxation, or its finite-element solve every step")
+    ap.add_argument("--ell-precond", default="multigrid", choices=["multigrid", "jacobi"],
+                    help="preconditioner of the elliptic relaxation's conjugate gradients")
     ap.add_argument("--proj", action="store_true",
                     help="the stabilized mean-pressure projection every step (statistics fed back)")
     ap.add_argument("--proj-precond", default="multigrid", choices=["multigrid", "jacobi"],
@@ -275,7 +277,8 @@ def main():
         w.params = dict(w.params, min_ppe=args.min_ppe)
     if args.wp == "elliptic":
         # solved to 1e-6 of the right-hand side, far below the statistical noise of its input
-        w.params = dict(w.params, wp_source=CF.WP_ELLIPTIC, ell_tol=1e-6, ell_maxit=500)
+        w.params = dict(w.params, wp_source=CF.WP_ELLIPTIC, ell_tol=1e-6, ell_maxit=500,
+                        ell_precond=1 if args.ell_precond == "multigrid" else 0)
     if args.proj:
         # solved to 1e-6 of the right-hand side, below the statistical noise of its input;
         # C_p = 0.1 dt: the stabilizing term multiplies P' by (1 - C_p/dt) every step
@@ -342,6 +345,7 @@ def main():
                    "particles_per_element": int(w.seed["ppe"]), "dt": w.dt,
                    "reorder_every": args.reorder_every, "stats_mode": args.stats_mode,
                    "min_ppe": args.min_ppe, "mix": args.mix, "wp": args.wp, "proj": bool(args.proj)} |
+                  ({"ell_precond": args.ell_precond} if args.wp == "elliptic" else {}) |
                   ({"proj_precond": args.proj_precond, "Cp": w.params["Cp"],
                     "proj_tol": w.params["proj_tol"]} if args.proj else {}),
         "roofline": roof,

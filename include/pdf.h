@@ -128,10 +128,10 @@ typedef struct pdf_mesh_desc {
  *                mass and K the stiffness matrix, f the local right-hand side, L_ij from
  *                eq:L (element averages of k and eps; C_xi,ij = 1 + 1.3 n_i n_j of eq:Cxi
  *                with n the outward normal of the no-slip wall edge closest to the
- *                element), wp_ij = -4.5 eps n_i n_j at no-slip wall nodes; Jacobi-
- *                preconditioned conjugate gradients from the previous solution until the
- *                preconditioned residual of every component is below ell_tol times that
- *                of its right-hand side, at most ell_maxit iterations (the call then
+ *                element), wp_ij = -4.5 eps n_i n_j at no-slip wall nodes; conjugate
+ *                gradients from the previous solution (preconditioner: ell_precond) until
+ *                the preconditioned residual of every component is below ell_tol times
+ *                that of its right-hand side, at most ell_maxit iterations (the call then
  *                waits for the stream every 8 iterations)
  *   omega_source 1: S_omega of eq:frequency-source; 0: S_omega = 0
  *   tm_mode      PDF_TM_CPHI: 1/t_m = C_phi <omega>/2; PDF_TM_KEPS: t_m = max(k/eps, C_T sqrt(nu/eps));
@@ -192,6 +192,13 @@ typedef struct pdf_mesh_desc {
  *                a smoothed-aggregation multigrid hierarchy of K (built once by
  *                pdf_init_mesh on the host; Jacobi smoothing, Galerkin coarse levels,
  *                a dense coarsest solve; PDF_E_NUMERIC if it cannot be built)
+ *   ell_precond  preconditioner of the elliptic relaxation: 0 Jacobi (the paper's), 1 one
+ *                V-cycle of a plain-aggregation multigrid hierarchy (aggregates built once by
+ *                pdf_init_mesh from the stiffness matrix over the free master nodes; every
+ *                solve sums the matrix entries over pairs of aggregates for the coarser
+ *                levels, one l1-Jacobi step before and after each coarse correction, 8
+ *                l1-Jacobi sweeps on the last level of at most 512 rows; PDF_E_NUMERIC if it
+ *                cannot be built)
  *   Cp           stabilization constant of eq:pressure-projection-smooth (the paper: 1e-3)
  *   nu_wall      kinematic viscosity of the log law eq:Ue at PDF_BC_WALLFN edges (> 0 when
  *                the mesh has such edges).  A particle reflected at such an edge gets the
@@ -209,6 +216,7 @@ typedef struct pdf_mesh_desc {
 typedef struct pdf_model_params {
   int32_t model, wp_source, omega_source, tm_mode, frozen, wall_b, reorder_every, stats_mode;
   int32_t min_ppe, mix_model, cond_nu, cond_nv, cond_nw, cond_min, ell_maxit, proj, proj_maxit, proj_precond;
+  int32_t ell_precond;
   double C0, C1, C2, C3, C4, CT, CL, Ceta, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
   double src_x, src_y, src_r, Cs, Ct, nu_wall, ell_tol, Cp, proj_tol;
 } pdf_model_params;
@@ -383,7 +391,10 @@ pdf_status pdf_denoiser_train_step(pdf_denoiser *dn, const float *x, const float
 
 /* Denoised nodal statistics of the context's latest estimate into out
  * [PDF_NSTAT][n_nodes] (host or device): the plain statistics with the 8
- * corrected fields; *n_fallback (may be NULL) counts rejected corrections. */
+ * corrected fields; *n_fallback (may be NULL) counts rejected corrections.
+ * tau >= 0; tau = +inf (HUGE_VAL) takes every finite correction, also at
+ * nodes where the standard error is zero; a non-finite correction is always
+ * rejected. */
 pdf_status pdf_denoise_stats(pdf_denoiser *dn, double tau, double *out, int32_t on_device,
                              uint64_t *n_fallback);
 

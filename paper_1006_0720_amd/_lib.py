@@ -47,7 +47,7 @@ class ModelParams(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("model", "wp_source", "omega_source", "tm_mode", "frozen",
                                          "wall_b", "reorder_every", "stats_mode", "min_ppe", "mix_model",
                                          "cond_nu", "cond_nv", "cond_nw", "cond_min", "ell_maxit", "proj",
-                                         "proj_maxit", "proj_precond")] + \
+                                         "proj_maxit", "proj_precond", "ell_precond")] + \
                [(n, C.c_double) for n in ("C0", "C1", "C2", "C3", "C4", "CT", "CL", "Ceta", "Cv",
                                           "gamma5", "Cw1", "Cw2", "Cphi", "nu", "k_floor",
                                           "src_x", "src_y", "src_r", "Cs", "Ct", "nu_wall", "ell_tol", "Cp",
@@ -58,10 +58,10 @@ class ModelParams(C.Structure):
 # 5 x 5 x 5 conditioning bins with at least 2 particles each, the
 # micromixing constants of tab:constants, no wall-function viscosity, the
 # conjugate-gradient limits of the elliptic relaxation and of the projection,
-# and the multigrid preconditioner of the projection
+# and the multigrid preconditioners of the projection and the elliptic relaxation
 PARAM_DEFAULTS = dict(stats_mode=0, min_ppe=0, mix_model=0, cond_nu=5, cond_nv=5, cond_nw=5,
                       cond_min=2, Cs=0.02, Ct=0.7, nu_wall=0.0, ell_maxit=500, ell_tol=1e-12, proj=0,
-                      proj_maxit=2000, proj_precond=1, Cp=1e-3, proj_tol=1e-12)
+                      proj_maxit=2000, proj_precond=1, ell_precond=1, Cp=1e-3, proj_tol=1e-12)
 
 
 class SeedDesc(C.Structure):

@@ -265,14 +265,14 @@ void master_csr(const pdf_mesh_desc *mesh, std::vector<int32_t> &row_off, std::v
 // pressure projection: the stiffness matrix (assembled once on the host, the
 // element entries A grad N_a . grad N_b added into the masters' rows) and the
 // buffers
-pdf_status proj_setup(pdf_ctx *c, const pdf_mesh_desc *mesh) {
-  const int32_t nn = c->md.nn, ne = c->md.ne;
-  ProjBuf &b = c->pb;
-  std::vector<int32_t> row_off, cols;
-  master_csr(mesh, row_off, cols);
-  std::vector<double> kval(cols.size(), 0.0), kdiag((size_t)nn, 1.0);
+// the stiffness matrix over the masters on the pattern of master_csr: the
+// element entries A grad N_a . grad N_b added into the masters' rows
+void stiffness_values(const pdf_mesh_desc *mesh, const std::vector<int32_t> &row_off,
+                      const std::vector<int32_t> &cols, std::vector<double> &kval) {
+  const int32_t ne = mesh->n_elems;
   const double *xy = mesh->node_xy;
   const int32_t *en = mesh->elem_nodes, *master = mesh->node_master;
+  kval.assign(cols.size(), 0.0);
   for (int32_t e = 0; e < ne; ++e) {
     const int32_t n0 = en[3 * e], n1 = en[3 * e + 1], n2 = en[3 * e + 2];
     const double xBA = xy[2 * n1] - xy[2 * n0], yBA = xy[2 * n1 + 1] - xy[2 * n0 + 1];
@@ -290,6 +290,17 @@ pdf_status proj_setup(pdf_ctx *c, const pdf_mesh_desc *mesh) {
       }
     }
   }
+}
+
+pdf_status proj_setup(pdf_ctx *c, const pdf_mesh_desc *mesh) {
+  const int32_t nn = c->md.nn, ne = c->md.ne;
+  ProjBuf &b = c->pb;
+  std::vector<int32_t> row_off, cols;
+  master_csr(mesh, row_off, cols);
+  std::vector<double> kval, kdiag((size_t)nn, 1.0);
+  stiffness_values(mesh, row_off, cols, kval);
+  const double *xy = mesh->node_xy;
+  const int32_t *en = mesh->elem_nodes, *master = mesh->node_master;
   for (int32_t n = 0; n < nn; ++n)
     for (int32_t j = row_off[n]; j < row_off[n + 1]; ++j)
       if (cols[j] == n) kdiag[n] = kval[j] > 0.0 ? kval[j] : 1.0;
@@ -474,6 +485,59 @@ pdf_status ell_setup(pdf_ctx *c, const pdf_mesh_desc *mesh) {
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));
   dfree(c, wd);
+  if (c->params.ell_precond == 1) {
+    // the multigrid hierarchy over the free masters (row role 0), in node
+    // order; its aggregates come from the stiffness matrix
+    std::vector<double> kval;
+    stiffness_values(mesh, row_off, cols, kval);
+    std::vector<int32_t> fidx, lidx((size_t)nn, -1);
+    for (int32_t n = 0; n < nn; ++n)
+      if (dir[n] == 0) {
+        lidx[n] = (int32_t)fidx.size();
+        fidx.push_back(n);
+      }
+    const int32_t n0 = (int32_t)fidx.size();
+    if (n0 > 0) {
+      std::vector<int32_t> off0((size_t)n0 + 1, 0), col0, g0;
+      std::vector<double> val0;
+      for (int32_t k = 0; k < n0; ++k) {
+        const int32_t a = fidx[k];
+        for (int32_t j = row_off[a]; j < row_off[a + 1]; ++j)
+          if (lidx[cols[j]] >= 0) {
+            col0.push_back(lidx[cols[j]]);
+            g0.push_back(j);
+            val0.push_back(kval[j]);
+          }
+        off0[k + 1] = (int32_t)col0.size();
+      }
+      std::vector<AggHostLevel> lv;
+      if (!agg_chain(n0, off0, col0, val0, ELL_COARSE_MAX, lv))
+        return fail(c, PDF_E_NUMERIC, "the multigrid hierarchy of the elliptic relaxation could not be built");
+      EllMg &g = b.mg;
+      bool ok = upload(c, fidx, &g.fidx) && upload(c, g0, &g.g0);
+      for (size_t l = 0; l < lv.size() && ok; ++l) {
+        const AggHostLevel &H = lv[l];
+        EllMgLevel &D = g.lv[l];
+        D.n = H.n;
+        D.nnz = (int32_t)H.col.size();
+        const size_t v9b = 9 * (size_t)H.n * sizeof(double);
+        D.val = (double4 *)dalloc(c, ((size_t)D.nnz + 1) * sizeof(double4));
+        D.dinv = (double4 *)dalloc(c, (size_t)H.n * sizeof(double4));
+        D.b = (double *)dalloc(c, v9b);
+        D.x = (double *)dalloc(c, v9b);
+        D.r = (double *)dalloc(c, v9b);
+        D.y = (double *)dalloc(c, v9b);
+        ok = D.val && D.dinv && D.b && D.x && D.r && D.y && upload(c, H.off, &D.off) && upload(c, H.col, &D.col);
+        if (ok && l + 1 < lv.size())
+          ok = upload(c, H.agg, &D.agg) && upload(c, H.m_off, &D.m_off) && upload(c, H.mem, &D.mem) &&
+               upload(c, H.g_off, &D.g_off) && upload(c, H.g_idx, &D.g_idx);
+      }
+      if (!ok) return fail(c, PDF_E_OOM, "multigrid hierarchy of the elliptic relaxation");
+      g.nl = (int)lv.size();
+      g.sweeps = 8;
+      HIPCHK(c, hipStreamSynchronize(s));  // the host arrays end with this block
+    }
+  }
   return PDF_OK;
 }
 
@@ -625,7 +689,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
     return PDF_E_INVALID_ARG;
   if (params->model == PDF_MODEL_GLM && params->wp_source == PDF_WP_ELLIPTIC &&
       (params->ell_maxit < 1 || params->ell_maxit > 100000 || !(params->ell_tol > 0.0) ||
-       !std::isfinite(params->ell_tol)))
+       !std::isfinite(params->ell_tol) || (params->ell_precond != 0 && params->ell_precond != 1)))
     return PDF_E_INVALID_ARG;
   // wall functions replace the viscous terms of the particle equations and
   // need the viscosity of the log law

@@ -282,6 +282,85 @@ bool amg_build(int32_t n, const std::vector<int32_t> &off, const std::vector<int
   return true;
 }
 
+// Plain-aggregation chain for the elliptic relaxation: the same strength
+// rule and greedy aggregates as above, with the tentative prolongator
+// (T[i, agg(i)] = 1), so that the Galerkin product T^T A T sums the entries of
+// A over pairs of aggregates and the coarse values of every solve are plain
+// sums of the finer ones.  The coarser patterns come from the aggregated
+// stiffness matrix, whose values also decide the next level's aggregates.
+bool agg_chain(int32_t n, const std::vector<int32_t> &off, const std::vector<int32_t> &col,
+               const std::vector<double> &val, int32_t max_last, std::vector<AggHostLevel> &lv) {
+  lv.clear();
+  Csr a;
+  a.nr = a.nc = n;
+  a.off = off;
+  a.col = col;
+  a.val = val;
+  for (;;) {
+    AggHostLevel L;
+    L.n = a.nr;
+    L.off = a.off;
+    L.col = a.col;
+    if (a.nr <= max_last || (int)lv.size() + 1 >= ELL_MAXL) {
+      lv.push_back(std::move(L));
+      return a.nr <= max_last && a.nr > 0;
+    }
+    std::vector<int32_t> agg;
+    const int32_t na = aggregate(a, agg);
+    if (na >= a.nr || na < 1) return false;
+    L.m_off.assign((size_t)na + 1, 0);
+    for (int32_t i = 0; i < a.nr; ++i) L.m_off[agg[i] + 1]++;
+    for (int32_t k = 0; k < na; ++k) L.m_off[k + 1] += L.m_off[k];
+    L.mem.resize((size_t)a.nr);
+    {
+      std::vector<int32_t> cur(L.m_off.begin(), L.m_off.end() - 1);
+      for (int32_t i = 0; i < a.nr; ++i) L.mem[cur[agg[i]]++] = i;
+    }
+    // coarse row I: the fine entries of its member rows, grouped by the
+    // aggregate of their column
+    Csr c;
+    c.nr = c.nc = na;
+    c.off.assign((size_t)na + 1, 0);
+    L.g_off.assign(1, 0);
+    std::vector<int32_t> mark((size_t)na, -1), slot((size_t)na, 0), cols;
+    std::vector<std::vector<int32_t>> groups;
+    for (int32_t I = 0; I < na; ++I) {
+      cols.clear();
+      for (int32_t m = L.m_off[I]; m < L.m_off[I + 1]; ++m) {
+        const int32_t i = L.mem[m];
+        for (int32_t j = a.off[i]; j < a.off[i + 1]; ++j) {
+          const int32_t J = agg[a.col[j]];
+          if (mark[J] != I) {
+            mark[J] = I;
+            slot[J] = (int32_t)cols.size();
+            cols.push_back(J);
+            if (groups.size() < cols.size()) groups.emplace_back();
+            groups[cols.size() - 1].clear();
+          }
+          groups[slot[J]].push_back(j);
+        }
+      }
+      std::vector<int32_t> order(cols.size());
+      for (size_t k = 0; k < order.size(); ++k) order[k] = (int32_t)k;
+      std::sort(order.begin(), order.end(), [&](int32_t u, int32_t v) { return cols[u] < cols[v]; });
+      for (const int32_t k : order) {
+        std::vector<int32_t> &g = groups[k];
+        std::sort(g.begin(), g.end());
+        double v = 0.0;
+        for (const int32_t j : g) v += a.val[j];
+        c.col.push_back(cols[k]);
+        c.val.push_back(v);
+        L.g_idx.insert(L.g_idx.end(), g.begin(), g.end());
+        L.g_off.push_back((int32_t)L.g_idx.size());
+      }
+      c.off[I + 1] = (int32_t)c.col.size();
+    }
+    L.agg = std::move(agg);
+    lv.push_back(std::move(L));
+    a = std::move(c);
+  }
+}
+
 namespace {
 
 constexpr int AB = 256;

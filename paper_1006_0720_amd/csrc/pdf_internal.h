@@ -160,7 +160,42 @@ bool redist_alloc(RedistBuf &b, int32_t ne, int64_t np, void *(*alloc)(size_t, v
 // elliptic relaxation for wp_ij: per-element L^2 classes and wall normals,
 // Dirichlet flags and normals per node, conjugate-gradient vectors ([9][nn])
 // and scalars
+// Plain-aggregation hierarchy of the elliptic relaxation (k_amg.hip builds
+// the chain on the host from the stiffness matrix over the free masters;
+// k_elliptic.hip forms each level's values every solve).  Level l has n rows
+// (vectors [n][9]) and a CSR pattern; its values, four L2 classes per entry,
+// are sums of the finer level's values (the Galerkin product with the
+// tentative prolongator, whose entries are all 1): coarse entry J sums the
+// fine entries g_idx[g_off[J] .. g_off[J+1]).  Level 0 takes its values from
+// the full matrix's entries g0 and its rows from the free masters fidx.
+struct AggHostLevel {
+  int32_t n = 0;
+  std::vector<int32_t> off, col;     // pattern of this level
+  std::vector<int32_t> agg;          // row -> aggregate (the next level's row); empty on the last
+  std::vector<int32_t> m_off, mem;   // rows of each aggregate
+  std::vector<int32_t> g_off, g_idx; // next level's entries as sums of this level's
+};
+// false if no coarsening is possible; the last level has at most max_last rows
+bool agg_chain(int32_t n, const std::vector<int32_t> &off, const std::vector<int32_t> &col,
+               const std::vector<double> &val, int32_t max_last, std::vector<AggHostLevel> &lv);
+constexpr int ELL_MAXL = 16;
+constexpr int32_t ELL_COARSE_MAX = 512;  // rows of the last level (its sweeps run in one workgroup's LDS)
+struct EllMgLevel {
+  int32_t n = 0, nnz = 0;
+  const int32_t *off = nullptr, *col = nullptr;
+  double4 *val = nullptr, *dinv = nullptr;  // values; inverse l1 row sums per class
+  double *b = nullptr, *x = nullptr, *r = nullptr, *y = nullptr;  // [n][9]
+  const int32_t *agg = nullptr, *m_off = nullptr, *mem = nullptr, *g_off = nullptr, *g_idx = nullptr;
+};
+struct EllMg {
+  int nl = 0;  // 0: Jacobi preconditioning
+  int sweeps = 8;  // l1-Jacobi sweeps on the last level
+  const int32_t *fidx = nullptr, *g0 = nullptr;
+  EllMgLevel lv[ELL_MAXL];
+};
+
 struct EllBuf {
+  EllMg mg;
   double4 *L2 = nullptr;
   double2 *nrm = nullptr, *dnv = nullptr;
   int8_t *dir = nullptr;                        // row role: 0 free master, 1 wall master, 2 not a master
