@@ -579,7 +579,10 @@ __global__ void k_merge(int nn, const int32_t *master, const double *S, int32_t 
     for (int a = 0; a < 8; ++a) {
       const int fld = kQuant[a];
       const double corr = (double)scale[a] * (double)R[(size_t)r * ldr + a];
-      ok[a] = fabs(corr) <= tau * (double)scale[8 + a] * se[a];
+      // taken unless it exceeds the limit; tau = +inf takes every finite
+      // correction (inf * 0 at a node of zero spread is NaN, not a limit)
+      const double lim = tau * (double)scale[8 + a] * se[a];
+      ok[a] = isfinite(corr) && !(fabs(corr) > lim);
       mv[a] = S[(size_t)fld * nn + q] + corr;
       fb += ok[a] ? 0 : 1;
     }

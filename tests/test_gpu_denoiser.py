@@ -145,7 +145,8 @@ def test_merge_zero_network_and_fallback(env):
 def test_merge_calibrated_fallback(env):
     """pdf_denoiser_set_fallback: with factor kappa_q the threshold of
     statistic q is tau * kappa_q * SE_q; a correction of size c is taken where
-    tau * kappa_q * SE_q >= c, per statistic; invalid factors are refused."""
+    tau * kappa_q * SE_q >= c, per statistic; tau = inf takes every
+    correction; invalid factors are refused."""
     torch, L, ctx, w = env
     dn = L.Denoiser(ctx, hidden=32)
     plain = ctx.stats()
@@ -186,6 +187,11 @@ def test_merge_calibrated_fallback(env):
     dn.set_fallback(np.ones(8))
     _, nf1 = dn.denoise(tau=1.0)
     assert nf1 > nf
+    # tau = inf: every finite correction is taken, also at nodes of zero spread
+    out_inf, nf_inf = dn.denoise(tau=np.inf)
+    assert nf_inf == 0
+    for a, fld in enumerate(M.QUANT):
+        assert np.allclose(out_inf[fld] - plain[fld], cs[a], rtol=1e-6, atol=0), fld
     for bad in (np.zeros(8), np.full(8, -1.0), np.full(8, np.inf)):
         with pytest.raises(L.PdfError):
             dn.set_fallback(bad)
