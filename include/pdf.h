@@ -197,7 +197,7 @@ typedef struct pdf_mesh_desc {
  *                pdf_init_mesh from the stiffness matrix over the free master nodes; every
  *                solve sums the matrix entries over pairs of aggregates for the coarser
  *                levels, one l1-Jacobi step before and after each coarse correction, 8
- *                l1-Jacobi sweeps on the last level of at most 512 rows; PDF_E_NUMERIC if it
+ *                l1-Jacobi sweeps on the last level of at most 128 rows; PDF_E_NUMERIC if it
  *                cannot be built)
  *   Cp           stabilization constant of eq:pressure-projection-smooth (the paper: 1e-3)
  *   nu_wall      kinematic viscosity of the log law eq:Ue at PDF_BC_WALLFN edges (> 0 when

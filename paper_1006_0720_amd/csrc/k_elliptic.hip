@@ -337,12 +337,6 @@ __global__ __launch_bounds__(NB) void k_ell_in(MeshDev m, const double *wp, doub
 // consecutive components of a row, so the [n][9] vectors are read coalesced.
 __device__ __forceinline__ double cls4(const double4 &v, int c) { return l2_of(v, ell_class(c)); }
 
-// level 0's values from the full matrix
-__global__ __launch_bounds__(NB) void k_mg_vals0(int32_t nnz, const int32_t *g0, const double4 *av, double4 *val) {
-  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < nnz) val[j] = av[g0[j]];
-}
-
 // the next level's values: sums of this level's (the Galerkin product with the
 // tentative prolongator)
 __global__ __launch_bounds__(NB) void k_mg_vals(int32_t nnzc, const int32_t *g_off, const int32_t *g_idx,
@@ -376,34 +370,6 @@ __global__ __launch_bounds__(NB) void k_mg_dinv(int32_t n, const int32_t *off, c
   dinv[i] = make_double4(1.0 / s.x, 1.0 / s.y, 1.0 / s.z, 1.0 / s.w);
 }
 
-__global__ __launch_bounds__(NB) void k_mg_gather(int32_t n, const int32_t *fidx, const double *rin, double *b,
-                                                  const int *stop) {
-  if (*stop) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 9 * (int64_t)n) return;
-  const int32_t k = (int32_t)(t / 9);
-  b[t] = rin[9 * (size_t)fidx[k] + (t - 9 * (int64_t)k)];
-}
-
-__global__ __launch_bounds__(NB) void k_mg_scatter(int32_t n, const int32_t *fidx, const double *y, double *zout,
-                                                   const int *stop) {
-  if (*stop) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 9 * (int64_t)n) return;
-  const int32_t k = (int32_t)(t / 9);
-  zout[9 * (size_t)fidx[k] + (t - 9 * (int64_t)k)] = y[t];
-}
-
-// x = D^-1 b (one smoothing step from zero)
-__global__ __launch_bounds__(NB) void k_mg_smooth0(int32_t n, const double4 *dinv, const double *b, double *x,
-                                                   const int *stop) {
-  if (*stop) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 9 * (int64_t)n) return;
-  const int32_t i = (int32_t)(t / 9);
-  x[t] = cls4(dinv[i], (int)(t - 9 * (int64_t)i)) * b[t];
-}
-
 // (A x)_t for entry t = (row i, component c)
 __device__ __forceinline__ double mg_row(const int32_t *off, const int32_t *col, const double4 *val,
                                          const double *x, int32_t i, int c) {
@@ -412,27 +378,40 @@ __device__ __forceinline__ double mg_row(const int32_t *off, const int32_t *col,
   return s;
 }
 
-// r = b - A x
-__global__ __launch_bounds__(NB) void k_mg_resid(int32_t n, const int32_t *off, const int32_t *col,
-                                                 const double4 *val, const double *b, const double *x, double *r,
-                                                 const int *stop) {
-  if (*stop) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 9 * (int64_t)n) return;
-  const int32_t i = (int32_t)(t / 9);
-  r[t] = b[t] - mg_row(off, col, val, x, i, (int)(t - 9 * (int64_t)i));
-}
-
-// y = x + D^-1 (b - A x)
-__global__ __launch_bounds__(NB) void k_mg_post(int32_t n, const int32_t *off, const int32_t *col,
-                                                const double4 *val, const double4 *dinv, const double *b,
-                                                const double *x, double *y, const int *stop) {
+// the pre-smoothing step from zero folded into the residual: r = b - A (D^-1 b)
+__global__ __launch_bounds__(NB) void k_mg_pre(int32_t n, const int32_t *off, const int32_t *col,
+                                               const double4 *val, const double4 *dinv, const double *b, double *r,
+                                               const int *stop) {
   if (*stop) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 9 * (int64_t)n) return;
   const int32_t i = (int32_t)(t / 9);
   const int c = (int)(t - 9 * (int64_t)i);
-  y[t] = x[t] + cls4(dinv[i], c) * (b[t] - mg_row(off, col, val, x, i, c));
+  double s = 0.0;
+  for (int32_t j = off[i]; j < off[i + 1]; ++j) {
+    const int32_t q = col[j];
+    s += cls4(val[j], c) * (cls4(dinv[q], c) * b[9 * (size_t)q + c]);
+  }
+  r[t] = b[t] - s;
+}
+
+// the coarse correction folded into the post-smoothing step:
+// x = D^-1 b + T yc, y = x + D^-1 (b - A x)
+__global__ __launch_bounds__(NB) void k_mg_post(int32_t n, const int32_t *off, const int32_t *col,
+                                                const double4 *val, const double4 *dinv, const int32_t *agg,
+                                                const double *yc, const double *b, double *y, const int *stop) {
+  if (*stop) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 9 * (int64_t)n) return;
+  const int32_t i = (int32_t)(t / 9);
+  const int c = (int)(t - 9 * (int64_t)i);
+  double s = 0.0;
+  for (int32_t j = off[i]; j < off[i + 1]; ++j) {
+    const int32_t q = col[j];
+    s += cls4(val[j], c) * (cls4(dinv[q], c) * b[9 * (size_t)q + c] + yc[9 * (size_t)agg[q] + c]);
+  }
+  const double x = cls4(dinv[i], c) * b[t] + yc[9 * (size_t)agg[i] + c];
+  y[t] = x + cls4(dinv[i], c) * (b[t] - s);
 }
 
 // bc = T^T r: the sum over each aggregate's rows
@@ -448,15 +427,6 @@ __global__ __launch_bounds__(NB) void k_mg_restrict(int32_t nc, const int32_t *m
   bc[t] = s;
 }
 
-// x += T yc
-__global__ __launch_bounds__(NB) void k_mg_prolong(int32_t n, const int32_t *agg, const double *yc, double *x,
-                                                   const int *stop) {
-  if (*stop) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 9 * (int64_t)n) return;
-  const int32_t i = (int32_t)(t / 9);
-  x[t] += yc[9 * (size_t)agg[i] + (t - 9 * (int64_t)i)];
-}
 
 // the last level: `sweeps` l1-Jacobi sweeps from zero, in one workgroup,
 // the iterate in LDS (n <= ELL_COARSE_MAX)
@@ -507,35 +477,153 @@ void mg_vcycle(hipStream_t s, const EllMg &g, int l, const int *stop) {
     return;
   }
   const EllMgLevel &C = g.lv[l + 1];
-  hipLaunchKernelGGL(k_mg_smooth0, dim3(g9(L.n)), dim3(NB), 0, s, L.n, L.dinv, L.b, L.x, stop);
-  hipLaunchKernelGGL(k_mg_resid, dim3(g9(L.n)), dim3(NB), 0, s, L.n, L.off, L.col, L.val, L.b, L.x, L.r, stop);
+  hipLaunchKernelGGL(k_mg_pre, dim3(g9(L.n)), dim3(NB), 0, s, L.n, L.off, L.col, L.val, L.dinv, L.b, L.r, stop);
   hipLaunchKernelGGL(k_mg_restrict, dim3(g9(C.n)), dim3(NB), 0, s, C.n, L.m_off, L.mem, L.r, C.b, stop);
   mg_vcycle(s, g, l + 1, stop);
-  hipLaunchKernelGGL(k_mg_prolong, dim3(g9(L.n)), dim3(NB), 0, s, L.n, L.agg, C.y, L.x, stop);
-  hipLaunchKernelGGL(k_mg_post, dim3(g9(L.n)), dim3(NB), 0, s, L.n, L.off, L.col, L.val, L.dinv, L.b, L.x, L.y,
-                     stop);
+  hipLaunchKernelGGL(k_mg_post, dim3(g9(L.n)), dim3(NB), 0, s, L.n, L.off, L.col, L.val, L.dinv, L.agg, C.y, L.b,
+                     L.y, stop);
 }
 
-// zout = V-cycle of rin on the free rows (zout's other rows untouched)
-void mg_apply(hipStream_t s, const EllMg &g, const double *rin, double *zout, const int *stop) {
-  const EllMgLevel &L0 = g.lv[0];
-  hipLaunchKernelGGL(k_mg_gather, dim3(g9(L0.n)), dim3(NB), 0, s, L0.n, g.fidx, rin, L0.b, stop);
-  mg_vcycle(s, g, 0, stop);
-  hipLaunchKernelGGL(k_mg_scatter, dim3(g9(L0.n)), dim3(NB), 0, s, L0.n, g.fidx, L0.y, zout, stop);
+// ---- level 0, on the full matrix and the node-major vectors ----
+// inverse l1 row sums of the free rows over the free columns
+__global__ __launch_bounds__(NB) void k_mg0_dinv(int32_t n0, const int32_t *fidx, const int32_t *lidx,
+                                                 const int32_t *row_off, const int32_t *cols, const double4 *av,
+                                                 double4 *dinv) {
+  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n0) return;
+  const int32_t a = fidx[k];
+  double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
+  for (int32_t j = row_off[a]; j < row_off[a + 1]; ++j) {
+    if (lidx[cols[j]] < 0) continue;
+    const double4 v = av[j];
+    s.x += fabs(v.x);
+    s.y += fabs(v.y);
+    s.z += fabs(v.z);
+    s.w += fabs(v.w);
+  }
+  dinv[k] = make_double4(1.0 / s.x, 1.0 / s.y, 1.0 / s.z, 1.0 / s.w);
 }
 
-// the hierarchy's values for this solve
-void mg_values(hipStream_t s, const EllMg &g, const double4 *av) {
-  const EllMgLevel &L0 = g.lv[0];
-  hipLaunchKernelGGL(k_mg_vals0, dim3((L0.nnz + NB - 1) / NB), dim3(NB), 0, s, L0.nnz, g.g0, av, L0.val);
-  for (int l = 0; l < g.nl; ++l) {
-    const EllMgLevel &L = g.lv[l];
-    if (l + 1 < g.nl) {
-      const EllMgLevel &C = g.lv[l + 1];
-      hipLaunchKernelGGL(k_mg_vals, dim3((C.nnz + NB - 1) / NB), dim3(NB), 0, s, C.nnz, L.g_off, L.g_idx, L.val,
-                         C.val);
+// the pre-smoothing step from zero folded into the residual:
+// r0 = r - A (D^-1 r) on the free rows (r is zero on the other rows)
+__global__ __launch_bounds__(NB) void k_mg0_pre(int32_t n0, const int32_t *fidx, const int32_t *lidx,
+                                                const int32_t *row_off, const int32_t *cols, const double4 *av,
+                                                const double4 *dinv, const double *r, double *r0, const int *stop) {
+  if (*stop) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 9 * (int64_t)n0) return;
+  const int32_t k = (int32_t)(t / 9);
+  const int c = (int)(t - 9 * (int64_t)k);
+  const int32_t a = fidx[k];
+  double s = 0.0;
+  for (int32_t j = row_off[a]; j < row_off[a + 1]; ++j) {
+    const int32_t q = cols[j];
+    const int32_t lq = lidx[q];
+    if (lq < 0) continue;
+    s += cls4(av[j], c) * (cls4(dinv[lq], c) * r[9 * (size_t)q + c]);
+  }
+  r0[t] = r[9 * (size_t)a + c] - s;
+}
+
+// the coarse correction folded into the post-smoothing step:
+// x = D^-1 r + T y1, z = x + D^-1 (r - A x) on the free rows; dot += r.z
+// (per component, block sums added with atomics)
+__global__ __launch_bounds__(NB9) void k_mg0_post(int32_t n0, const int32_t *fidx, const int32_t *lidx,
+                                                  const int32_t *row_off, const int32_t *cols, const double4 *av,
+                                                  const double4 *dinv, const int32_t *agg, const double *y1,
+                                                  const double *r, double *z, double *dot, const int *stop) {
+  if (*stop) return;
+  __shared__ double part[NB9];
+  const int c = threadIdx.x % 9;
+  double acc = 0.0;
+  const int64_t n9 = 9 * (int64_t)n0;
+  for (int64_t t = (int64_t)blockIdx.x * NB9 + threadIdx.x; t < n9; t += (int64_t)gridDim.x * NB9) {
+    const int32_t k = (int32_t)(t / 9);
+    const int32_t a = fidx[k];
+    double s = 0.0;
+    for (int32_t j = row_off[a]; j < row_off[a + 1]; ++j) {
+      const int32_t q = cols[j];
+      const int32_t lq = lidx[q];
+      if (lq < 0) continue;
+      const double xq = cls4(dinv[lq], c) * r[9 * (size_t)q + c] + (y1 ? y1[9 * (size_t)agg[lq] + c] : 0.0);
+      s += cls4(av[j], c) * xq;
     }
-    hipLaunchKernelGGL(k_mg_dinv, dim3((L.n + NB - 1) / NB), dim3(NB), 0, s, L.n, L.off, L.val, L.dinv);
+    const double ra = r[9 * (size_t)a + c];
+    const double xa = cls4(dinv[k], c) * ra + (y1 ? y1[9 * (size_t)agg[k] + c] : 0.0);
+    const double za = xa + cls4(dinv[k], c) * (ra - s);
+    z[9 * (size_t)a + c] = za;
+    acc += ra * za;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < 9) {
+    double sum = 0.0;
+    for (int k = threadIdx.x; k < NB9; k += 9) sum += part[k];
+    atomicAdd(&dot[threadIdx.x], sum);
+  }
+}
+
+// z = V-cycle of r on the free rows (z's other rows untouched); dot += r.z
+void mg_apply(hipStream_t s, const EllMg &g, const EllBuf &b, const MeshDev &m, const double *r, double *z,
+              double *dot, const int *stop) {
+  const EllMgLevel &L0 = g.lv[0];
+  const int64_t n9 = 9 * (int64_t)L0.n;
+  const int64_t gp = (n9 + NB9 - 1) / NB9;
+  const unsigned gpost = (unsigned)(gp < 2048 ? gp : 2048);
+  (void)m;
+  if (g.nl > 1) {
+    const EllMgLevel &C = g.lv[1];
+    hipLaunchKernelGGL(k_mg0_pre, dim3(g9(L0.n)), dim3(NB), 0, s, L0.n, g.fidx, g.lidx, b.row_off, b.cols, b.av,
+                       g.dinv0, r, g.r0, stop);
+    hipLaunchKernelGGL(k_mg_restrict, dim3(g9(C.n)), dim3(NB), 0, s, C.n, L0.m_off, L0.mem, g.r0, C.b, stop);
+    mg_vcycle(s, g, 1, stop);
+    hipLaunchKernelGGL(k_mg0_post, dim3(gpost), dim3(NB9), 0, s, L0.n, g.fidx, g.lidx, b.row_off, b.cols, b.av,
+                       g.dinv0, L0.agg, C.y, r, z, dot, stop);
+  } else {
+    // a single level: two l1-Jacobi steps from zero
+    hipLaunchKernelGGL(k_mg0_post, dim3(gpost), dim3(NB9), 0, s, L0.n, g.fidx, g.lidx, b.row_off, b.cols, b.av,
+                       g.dinv0, (const int32_t *)nullptr, (const double *)nullptr, r, z, dot, stop);
+  }
+}
+
+// the hierarchy's values for this solve: level 0 is the matrix itself
+void mg_values(hipStream_t s, const EllMg &g, const EllBuf &b) {
+  const EllMgLevel &L0 = g.lv[0];
+  hipLaunchKernelGGL(k_mg0_dinv, dim3((L0.n + NB - 1) / NB), dim3(NB), 0, s, L0.n, g.fidx, g.lidx, b.row_off,
+                     b.cols, b.av, g.dinv0);
+  for (int l = 0; l + 1 < g.nl; ++l) {
+    const EllMgLevel &L = g.lv[l];
+    const EllMgLevel &C = g.lv[l + 1];
+    hipLaunchKernelGGL(k_mg_vals, dim3((C.nnz + NB - 1) / NB), dim3(NB), 0, s, C.nnz, L.g_off, L.g_idx,
+                       l == 0 ? (const double4 *)b.av : L.val, C.val);
+    hipLaunchKernelGGL(k_mg_dinv, dim3((C.n + NB - 1) / NB), dim3(NB), 0, s, C.n, C.off, C.val, C.dinv);
+  }
+}
+
+// q = A p on the free rows (free columns only: p is zero on the others),
+// pq += p.q; one thread per (free row, component), so that a row's nine
+// components are read and written together
+__global__ __launch_bounds__(NB9) void k_ell_apply9(int32_t n0, const int32_t *fidx, const int32_t *row_off,
+                                                    const int32_t *cols, const double4 *av, const double *p, double *q,
+                                                    double *pq, const int *stop) {
+  if (*stop) return;
+  __shared__ double part[NB9];
+  const int c = threadIdx.x % 9;
+  double acc = 0.0;
+  const int64_t n9 = 9 * (int64_t)n0;
+  for (int64_t t = (int64_t)blockIdx.x * NB9 + threadIdx.x; t < n9; t += (int64_t)gridDim.x * NB9) {
+    const int32_t a = fidx[t / 9];
+    double y = 0.0;
+    for (int32_t j = row_off[a]; j < row_off[a + 1]; ++j) y += cls4(av[j], c) * p[9 * (size_t)cols[j] + c];
+    q[9 * (size_t)a + c] = y;
+    acc += p[9 * (size_t)a + c] * y;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < 9) {
+    double sum = 0.0;
+    for (int k = threadIdx.x; k < NB9; k += 9) sum += part[k];
+    atomicAdd(&pq[threadIdx.x], sum);
   }
 }
 
@@ -587,22 +675,6 @@ __global__ __launch_bounds__(NB) void k_ell_copy9(int64_t n9, const int8_t *role
   if (i < n9 && role[i / 9] == 0) p[i] = z[i];
 }
 
-// out[c] += sum over the free rows of u_i v_i (component c = i % 9)
-__global__ __launch_bounds__(NB9) void k_ell_dot9(int64_t n9, const int8_t *role, const double *u, const double *v,
-                                                  double *out, const int *stop) {
-  if (*stop) return;
-  __shared__ double part[NB9];
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * NB9 + threadIdx.x; i < n9; i += (int64_t)gridDim.x * NB9)
-    if (role[i / 9] == 0) acc += u[i] * v[i];
-  part[threadIdx.x] = acc;
-  __syncthreads();
-  if (threadIdx.x < 9) {
-    double sum = 0.0;
-    for (int k = threadIdx.x; k < NB9; k += 9) sum += part[k];
-    atomicAdd(&out[threadIdx.x], sum);
-  }
-}
 
 }  // namespace
 
@@ -628,17 +700,17 @@ int launch_ell_solve(hipStream_t s, const MeshDev &m, const ModelDev &md, const 
   hipLaunchKernelGGL(k_ell_in, dim3(gm), dim3(NB), 0, s, m, wp, b.x);
   hipLaunchKernelGGL(k_ell_start, dim3(gm), dim3(NB), 0, s, m, md, S, b.dir, b.dnv, b.x, b.r, b.z, b.p, b.diag);
   const bool mg = b.mg.nl > 0;
+  const int64_t g0p_ = mg ? (9 * (int64_t)b.mg.lv[0].n + NB9 - 1) / NB9 : 1;
+  const unsigned g0p = (unsigned)(g0p_ < 2048 ? g0p_ : 2048);
   const double *rz0 = b.scal, *bb = b.scal + 9;
   if (mg) {
     // the stopping rule measures residuals in the preconditioner's norm:
     // r.M r against b.M b (M the V-cycle)
-    mg_values(s, b.mg, b.av);
+    mg_values(s, b.mg, b);
     hipLaunchKernelGGL(k_ell_resid_mg, dim3(gm), dim3(NB), 0, s, m, f, b.dir, b.row_off, b.cols, b.mv, b.av, b.x,
                        b.r, b.q);
-    mg_apply(s, b.mg, b.q, b.z, b.stop);
-    hipLaunchKernelGGL(k_ell_dot9, dim3(gu), dim3(NB9), 0, s, n9, b.dir, b.q, b.z, b.scal + 9, b.stop);
-    mg_apply(s, b.mg, b.r, b.z, b.stop);
-    hipLaunchKernelGGL(k_ell_dot9, dim3(gu), dim3(NB9), 0, s, n9, b.dir, b.r, b.z, b.scal, b.stop);
+    mg_apply(s, b.mg, b, m, b.q, b.z, b.scal + 9, b.stop);
+    mg_apply(s, b.mg, b, m, b.r, b.z, b.scal, b.stop);
     hipLaunchKernelGGL(k_ell_copy9, dim3(g9), dim3(NB), 0, s, n9, b.dir, b.z, b.p);
   } else {
     hipLaunchKernelGGL(k_ell_resid, dim3(gm), dim3(NB), 0, s, m, f, b.dir, b.row_off, b.cols, b.mv, b.av, b.x, b.r,
@@ -653,14 +725,15 @@ int launch_ell_solve(hipStream_t s, const MeshDev &m, const ModelDev &md, const 
       const double *rz = it == 0 ? rz0 : b.scal + 27 + 18 * (it - 1);
       double *pq = b.scal + 18 + 18 * it;
       double *rzn = b.scal + 27 + 18 * it;
-      hipLaunchKernelGGL(k_ell_apply, dim3(gm), dim3(NB), 0, s, m, b.dir, b.row_off, b.cols, b.av, b.p, b.q, pq,
-                         b.stop);
       if (mg) {
+        hipLaunchKernelGGL(k_ell_apply9, dim3(g0p), dim3(NB9), 0, s, b.mg.lv[0].n, b.mg.fidx, b.row_off, b.cols, b.av,
+                           b.p, b.q, pq, b.stop);
         hipLaunchKernelGGL(k_ell_update_mg, dim3(gu), dim3(NB9), 0, s, n9, b.dir, b.p, b.q, b.x, b.r, rz, pq,
                            b.stop);
-        mg_apply(s, b.mg, b.r, b.z, b.stop);
-        hipLaunchKernelGGL(k_ell_dot9, dim3(gu), dim3(NB9), 0, s, n9, b.dir, b.r, b.z, rzn, b.stop);
+        mg_apply(s, b.mg, b, m, b.r, b.z, rzn, b.stop);
       } else {
+        hipLaunchKernelGGL(k_ell_apply, dim3(gm), dim3(NB), 0, s, m, b.dir, b.row_off, b.cols, b.av, b.p, b.q, pq,
+                           b.stop);
         hipLaunchKernelGGL(k_ell_update, dim3(gu), dim3(NB9), 0, s, n9, b.dir, b.p, b.q, b.diag, b.x, b.r, b.z, rz,
                            pq, rzn, b.stop);
       }

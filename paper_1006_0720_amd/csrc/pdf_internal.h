@@ -179,7 +179,7 @@ struct AggHostLevel {
 bool agg_chain(int32_t n, const std::vector<int32_t> &off, const std::vector<int32_t> &col,
                const std::vector<double> &val, int32_t max_last, std::vector<AggHostLevel> &lv);
 constexpr int ELL_MAXL = 16;
-constexpr int32_t ELL_COARSE_MAX = 512;  // rows of the last level (its sweeps run in one workgroup's LDS)
+constexpr int32_t ELL_COARSE_MAX = 128;  // rows of the last level (its sweeps run in one workgroup's LDS)
 struct EllMgLevel {
   int32_t n = 0, nnz = 0;
   const int32_t *off = nullptr, *col = nullptr;
@@ -187,10 +187,17 @@ struct EllMgLevel {
   double *b = nullptr, *x = nullptr, *r = nullptr, *y = nullptr;  // [n][9]
   const int32_t *agg = nullptr, *m_off = nullptr, *mem = nullptr, *g_off = nullptr, *g_idx = nullptr;
 };
+// Level 0 works on the conjugate gradients' own node-major vectors and the
+// full matrix (row_off, cols, av), restricted to the free rows: lidx maps a
+// node to its free-row index (-1 for wall and identified nodes), fidx back;
+// dinv0 holds level 0's inverse l1 row sums over the free columns, r0 the
+// smoothed residual that is restricted.  Level 0's g_idx index av directly.
 struct EllMg {
   int nl = 0;  // 0: Jacobi preconditioning
   int sweeps = 8;  // l1-Jacobi sweeps on the last level
-  const int32_t *fidx = nullptr, *g0 = nullptr;
+  const int32_t *fidx = nullptr, *lidx = nullptr;
+  double4 *dinv0 = nullptr;
+  double *r0 = nullptr;
   EllMgLevel lv[ELL_MAXL];
 };
 
