@@ -179,71 +179,73 @@ void launch_seed(hipStream_t s, const MeshDev &m, const ModelDev &md, PartDev<T>
 // (eq:frequency-source) and t_m, pre-multiplied by dt where the step uses them.
 // (px, py) is the point where the source-aware t_m measures its distance.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void record_from(const ModelDev &md, const double U[3], double Om, double Phi,
-                                            const double R[6], const double lap[3], const double gp[2],
-                                            const double *W, const double dU[3][2], const double gs[2],
-                                            double dt, double px, double py, T *r) {
-  double k = 0.5 * (R[0] + R[1] + R[2]);
-  if (!(k > md.k_floor)) k = md.k_floor;
-  const double eps = Om * (k + md.nu * md.CT * md.CT * Om);
-  double G[3][3], C0;
+template <typename T, typename C = double>
+__device__ __forceinline__ void record_from(const ModelDev &md, const C U[3], C Om, C Phi, const C R[6],
+                                            const C lap[3], const C gp[2], const C *W, const C dU[3][2],
+                                            const C gs[2], C dt, C px, C py, T *r) {
+  const C k_floor = (C)md.k_floor, nu = (C)md.nu, CT = (C)md.CT, C0m = (C)md.C0, C3 = (C)md.C3, C4 = (C)md.C4,
+          Cw1 = (C)md.Cw1, Cw2 = (C)md.Cw2, Cphi = (C)md.Cphi, Cs = (C)md.Cs, Ct = (C)md.Ct, sx = (C)md.src_x,
+          sy = (C)md.src_y, sr = (C)md.src_r;
+  C k = C(0.5) * (R[0] + R[1] + R[2]);
+  if (!(k > k_floor)) k = k_floor;
+  const C eps = Om * (k + nu * CT * CT * Om);
+  C G[3][3], C0;
   const int sidx[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
   if (md.model == PDF_MODEL_SLM) {
-    C0 = md.C0;
+    C0 = C0m;
     for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) G[i][j] = (i == j) ? -(0.5 + 0.75 * md.C0) * Om : 0.0;
+      for (int j = 0; j < 3; ++j) G[i][j] = (i == j) ? -(C(0.5) + C(0.75) * C0m) * Om : C(0.0);
   } else {
-    double wr = 0.0;
+    C wr = C(0.0);
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
-        const double Wij = W[3 * i + j];
-        G[i][j] = (Wij - ((i == j) ? 0.5 * eps : 0.0)) / k;
+        const C Wij = W[3 * i + j];
+        G[i][j] = (Wij - ((i == j) ? C(0.5) * eps : C(0.0))) / k;
         wr += Wij * R[sidx[i][j]];
       }
-    const double c0 = -2.0 * wr / (3.0 * k * eps);
-    C0 = (c0 > 0.0) ? c0 : 0.0;
+    const C c0 = -C(2.0) * wr / (C(3.0) * k * eps);
+    C0 = (c0 > C(0.0)) ? c0 : C(0.0);
   }
-  double prod = 0.0;
+  C prod = C(0.0);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 2; ++j) prod -= R[sidx[i][j]] * dU[i][j];
-  const double Sw = md.omega_source ? (md.Cw2 - md.Cw1 * prod / eps) : 0.0;
-  double inv_tm;
+  const C Sw = md.omega_source ? (Cw2 - Cw1 * prod / eps) : C(0.0);
+  C inv_tm;
   if (md.tm_mode == PDF_TM_CPHI) {
-    inv_tm = 0.5 * md.Cphi * Om;
+    inv_tm = C(0.5) * Cphi * Om;
   } else {
-    const double ta = k / eps, tb = md.CT * sqrt(md.nu / eps);
-    double tm = ta > tb ? ta : tb;
+    const C ta = k / eps, tb = CT * sqrt(nu / eps);
+    C tm = ta > tb ? ta : tb;
     if (md.tm_mode == PDF_TM_SOURCE) {
       // eq:micromixing-timescale-canyon: the source term C_s (r0^2/eps)^(1/3)
       // + C_t d / U_c drops out where U_c = |<U>| = 0
-      const double dx = px - md.src_x, dy = py - md.src_y;
-      const double d = sqrt(dx * dx + dy * dy);
-      const double uc = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
-      if (uc > 0.0) {
-        const double ts = md.Cs * cbrt(md.src_r * md.src_r / eps) + md.Ct * d / uc;
+      const C dx = px - sx, dy = py - sy;
+      const C d = sqrt(dx * dx + dy * dy);
+      const C uc = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+      if (uc > C(0.0)) {
+        const C ts = Cs * cbrt(sr * sr / eps) + Ct * d / uc;
         if (ts < tm) tm = ts;
       }
     }
-    inv_tm = 1.0 / tm;
+    inv_tm = C(1.0) / tm;
   }
   r[R_U] = (T)U[0];
   r[R_V] = (T)U[1];
   r[R_W] = (T)U[2];
   r[R_OM] = (T)Om;
   r[R_PHI] = (T)Phi;
-  r[R_A0] = (T)((-gp[0] + 2.0 * md.nu * lap[0]) * dt);
-  r[R_A1] = (T)((-gp[1] + 2.0 * md.nu * lap[1]) * dt);
-  r[R_A2] = (T)((2.0 * md.nu * lap[2]) * dt);
+  r[R_A0] = (T)((-gp[0] + C(2.0) * nu * lap[0]) * dt);
+  r[R_A1] = (T)((-gp[1] + C(2.0) * nu * lap[1]) * dt);
+  r[R_A2] = (T)((C(2.0) * nu * lap[2]) * dt);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) r[R_G00 + 3 * i + j] = (T)(G[i][j] * dt);
   r[R_SC0] = (T)sqrt(C0 * eps * dt);
-  const double sv = sqrt(2.0 * md.nu * dt);
+  const C sv = sqrt(C(2.0) * nu * dt);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 2; ++j) r[R_B00 + 2 * i + j] = (T)(sv * dU[i][j]);
-  r[R_WA] = (T)(md.C3 * Om * dt);
+  r[R_WA] = (T)(C3 * Om * dt);
   r[R_WB] = (T)(Sw * Om * dt);
-  r[R_WC] = (T)sqrt(2.0 * md.C3 * md.C4 * Om * Om * dt);
+  r[R_WC] = (T)sqrt(C(2.0) * C3 * C4 * Om * Om * dt);
   r[R_MIX] = (T)(dt * inv_tm);
   r[R_GSX] = (T)gs[0];
   r[R_GSY] = (T)gs[1];
@@ -363,26 +365,31 @@ __device__ __forceinline__ void shape_w(const double lam[3], double w[3]) {
 
 // statistics of a SHAPE record interpolated with weights w (eq:approximation),
 // then the step coefficients as for an element record
+// FP32 state forms these per-particle coefficients in binary32 (the FP64
+// state, and every element record, in binary64): they are rounded to the
+// state's precision anyway, and in binary32 the divisions and square roots
+// are single hardware-assisted sequences
 template <typename T>
 __device__ __forceinline__ void shape_record(const ModelDev &md, const T *rs, const double w[3], double dt,
                                              double px, double py, T *r) {
-#define INTERP(f) \
-  (w[0] * (double)rs[(f)] + w[1] * (double)rs[S_NODE + (f)] + w[2] * (double)rs[2 * S_NODE + (f)])
-  const double U[3] = {INTERP(S_U), INTERP(S_V), INTERP(S_W)};
-  const double Om = INTERP(S_OM), Phi = INTERP(S_PHI);
-  double R[6];
+  using C = T;
+  const C w0 = (C)w[0], w1 = (C)w[1], w2 = (C)w[2];
+#define INTERP(f) (w0 * (C)rs[(f)] + w1 * (C)rs[S_NODE + (f)] + w2 * (C)rs[2 * S_NODE + (f)])
+  const C U[3] = {INTERP(S_U), INTERP(S_V), INTERP(S_W)};
+  const C Om = INTERP(S_OM), Phi = INTERP(S_PHI);
+  C R[6];
   for (int i = 0; i < 6; ++i) R[i] = INTERP(S_R11 + i);
-  const double lap[3] = {INTERP(S_L0), INTERP(S_L1), INTERP(S_L2)};
-  const double gp[2] = {INTERP(S_GP0), INTERP(S_GP0 + 1)};
-  double W[9];
+  const C lap[3] = {INTERP(S_L0), INTERP(S_L1), INTERP(S_L2)};
+  const C gp[2] = {INTERP(S_GP0), INTERP(S_GP0 + 1)};
+  C W[9];
   if (md.model == PDF_MODEL_GLM)
     for (int f = 0; f < 9; ++f) W[f] = INTERP(S_WP00 + f);
 #undef INTERP
-  double dU[3][2];
+  C dU[3][2];
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 2; ++j) dU[i][j] = (double)rs[S_DU + 2 * i + j];
-  const double gs[2] = {(double)rs[S_GS], (double)rs[S_GS + 1]};
-  record_from<T>(md, U, Om, Phi, R, lap, gp, W, dU, gs, dt, px, py, r);
+    for (int j = 0; j < 2; ++j) dU[i][j] = (C)rs[S_DU + 2 * i + j];
+  const C gs[2] = {(C)rs[S_GS], (C)rs[S_GS + 1]};
+  record_from<T, C>(md, U, Om, Phi, R, lap, gp, W, dU, gs, (C)dt, (C)px, (C)py, r);
 }
 
 template <typename T>
