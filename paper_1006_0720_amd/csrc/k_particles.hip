@@ -785,12 +785,14 @@ __device__ __noinline__ double3 wall_function(const ModelDev &md, const double *
   return make_double3(UR * tx + VR * nx, UR * ty + VR * ny, omr);
 }
 
-// Occupancy: the FP32 element-average kernel is held to 3 waves per SIMD
-// (at most 168 VGPRs; the LDS table of 3 copies, 48 KB, lets 3 workgroups
-// share a CU), which hides more of the latency of the walk's dependent loads
-// than the 2 waves its unconstrained register count would allow.
+// Occupancy: the FP32 kernels are held to 3 waves per SIMD (at most 168
+// VGPRs; the LDS table of 3 copies, 48 KB, with the 4 KB geometry window lets
+// 3 workgroups share a CU), which hides more of the latency of the walk's
+// dependent loads than the 2 waves their unconstrained register count would
+// allow; the SHAPE kernel spills some registers for it and is still faster.
+constexpr int GWIN = 32;  // elements of the workgroup's geometry window (4 KB of LDS)
 template <typename T, bool SHAPE>
-constexpr int advance_waves() { return (sizeof(T) == 4 && !SHAPE) ? 3 : 1; }
+constexpr int advance_waves() { return sizeof(T) == 4 ? 3 : 1; }
 
 template <typename T, bool VISC, bool WALLB, bool SHAPE, bool SPARSE>
 __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(const KArgs *__restrict__ ka, PartDev<T> p, int64_t np,
@@ -799,6 +801,7 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
                                                 const double *dtp, double s2nu, const T *__restrict__ cm,
                                                 const double *S, const double *gradp, unsigned long long *cnt) {
   __shared__ std::conditional_t<SHAPE, SumTableW, std::conditional_t<SPARSE, SumTableSparse, SumTable>> tab;
+  __shared__ WalkGeo gwin[SHAPE ? 1 : GWIN];
   const MeshDev &m = ka->m;
   const ModelDev &md = ka->md;
   if (dtp) {  // time step chosen on the device this step
@@ -806,6 +809,19 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
     sdt = sqrt(dt);
   }
   table_init(tab);
+  // the geometry of GWIN consecutive elements from the host of the
+  // workgroup's first particle, staged in LDS: after a reorder the
+  // workgroup's particles sit in a few consecutive elements, and the walk's
+  // first test then reads LDS instead of waiting on the cache
+  int32_t e_lo = 0, n_win = 0;
+  if constexpr (!SHAPE) {
+    const int64_t b0 = (int64_t)blockIdx.x * WG * ppt;
+    e_lo = b0 < np ? ldg(p.e, b0) : 0;
+    n_win = m.ne - e_lo < GWIN ? m.ne - e_lo : GWIN;
+    const uint4 *src = (const uint4 *)(m.wgeo + e_lo);
+    uint4 *dst = (uint4 *)gwin;
+    for (int k = threadIdx.x; k < n_win * (int)(sizeof(WalkGeo) / 16); k += WG) dst[k] = ldg(src, k);
+  }
   __syncthreads();
   uint64_t ca = 0, cb = 0;
   const int64_t base = (int64_t)blockIdx.x * WG * ppt;
@@ -937,7 +953,7 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
     const bool finite_pos = isfinite(x) && isfinite(y);
     for (int it = 0; it < 64 && finite_pos; ++it) {
       C_WALK(1);
-      const WalkGeo g = ldg(m.wgeo, e);
+      const WalkGeo g = (!SHAPE && (uint32_t)(e - e_lo) < (uint32_t)n_win) ? gwin[e - e_lo] : ldg(m.wgeo, e);
       double lam[3];
       edge_lambdas(g, x, y, lam);
       if (lam[0] >= 0.0 && lam[1] >= 0.0 && lam[2] >= 0.0) {
