@@ -514,32 +514,32 @@ pdf_status ell_setup(pdf_ctx *c, const pdf_mesh_desc *mesh) {
       if (!agg_chain(n0, off0, col0, val0, ELL_COARSE_MAX, lv))
         return fail(c, PDF_E_NUMERIC, "the multigrid hierarchy of the elliptic relaxation could not be built");
       EllMg &g = b.mg;
-      g.dinv0 = (double4 *)dalloc(c, (size_t)n0 * sizeof(double4));
-      g.r0 = (double *)dalloc(c, 9 * (size_t)n0 * sizeof(double));
-      bool ok = g.dinv0 && g.r0 && upload(c, fidx, &g.fidx) && upload(c, lidx, &g.lidx);
-      // level 0 is the matrix itself: its coarse values index the full entries
-      std::vector<int32_t> gi0;
-      if (lv.size() > 1) {
-        gi0.resize(lv[0].g_idx.size());
-        for (size_t k = 0; k < gi0.size(); ++k) gi0[k] = g0[lv[0].g_idx[k]];
-      }
+      const size_t c9b = 9 * (size_t)n0 * sizeof(double);
+      g.cx = (double *)dalloc(c, c9b);
+      g.cr = (double *)dalloc(c, c9b);
+      g.cz = (double *)dalloc(c, c9b);
+      g.cp = (double *)dalloc(c, c9b);
+      g.cq = (double *)dalloc(c, c9b);
+      g.cb = (double *)dalloc(c, c9b);
+      bool ok = g.cx && g.cr && g.cz && g.cp && g.cq && g.cb && upload(c, fidx, &g.fidx) && upload(c, g0, &g.g0);
       for (size_t l = 0; l < lv.size() && ok; ++l) {
         const AggHostLevel &H = lv[l];
         EllMgLevel &D = g.lv[l];
         D.n = H.n;
         D.nnz = (int32_t)H.col.size();
-        if (l > 0) {
-          const size_t v9b = 9 * (size_t)H.n * sizeof(double);
-          D.val = (double4 *)dalloc(c, ((size_t)D.nnz + 1) * sizeof(double4));
-          D.dinv = (double4 *)dalloc(c, (size_t)H.n * sizeof(double4));
+        const size_t v9b = 9 * (size_t)H.n * sizeof(double);
+        D.val = (double4 *)dalloc(c, ((size_t)D.nnz + 1) * sizeof(double4));
+        D.dinv = (double4 *)dalloc(c, (size_t)H.n * sizeof(double4));
+        D.r = (double *)dalloc(c, v9b);
+        ok = D.val && D.dinv && D.r && upload(c, H.off, &D.off) && upload(c, H.col, &D.col);
+        if (ok && l > 0) {  // level 0 takes its input and output vectors from the caller
           D.b = (double *)dalloc(c, v9b);
-          D.r = (double *)dalloc(c, v9b);
           D.y = (double *)dalloc(c, v9b);
-          ok = D.val && D.dinv && D.b && D.r && D.y && upload(c, H.off, &D.off) && upload(c, H.col, &D.col);
+          ok = D.b && D.y;
         }
         if (ok && l + 1 < lv.size())
           ok = upload(c, H.agg, &D.agg) && upload(c, H.m_off, &D.m_off) && upload(c, H.mem, &D.mem) &&
-               upload(c, H.g_off, &D.g_off) && upload(c, l == 0 ? gi0 : H.g_idx, &D.g_idx);
+               upload(c, H.g_off, &D.g_off) && upload(c, H.g_idx, &D.g_idx);
       }
       if (!ok) return fail(c, PDF_E_OOM, "multigrid hierarchy of the elliptic relaxation");
       g.nl = (int)lv.size();

@@ -484,146 +484,147 @@ void mg_vcycle(hipStream_t s, const EllMg &g, int l, const int *stop) {
                      L.y, stop);
 }
 
-// ---- level 0, on the full matrix and the node-major vectors ----
-// inverse l1 row sums of the free rows over the free columns
-__global__ __launch_bounds__(NB) void k_mg0_dinv(int32_t n0, const int32_t *fidx, const int32_t *lidx,
-                                                 const int32_t *row_off, const int32_t *cols, const double4 *av,
-                                                 double4 *dinv) {
-  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n0) return;
-  const int32_t a = fidx[k];
-  double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
-  for (int32_t j = row_off[a]; j < row_off[a + 1]; ++j) {
-    if (lidx[cols[j]] < 0) continue;
-    const double4 v = av[j];
-    s.x += fabs(v.x);
-    s.y += fabs(v.y);
-    s.z += fabs(v.z);
-    s.w += fabs(v.w);
-  }
-  dinv[k] = make_double4(1.0 / s.x, 1.0 / s.y, 1.0 / s.z, 1.0 / s.w);
+// ---- the conjugate gradients on compact free-row vectors ([n0][9]) ----
+// level 0 is the free-free block of the matrix, its values gathered from the
+// full matrix every solve; the CG kernels take one thread per (row,
+// component) with block sizes and strides that are multiples of 9, so a
+// thread keeps one component and the dot products add nine block sums
+
+__global__ __launch_bounds__(NB) void k_c_vals0(int32_t nnz, const int32_t *g0, const double4 *av, double4 *val) {
+  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < nnz) val[j] = av[g0[j]];
 }
 
-// the pre-smoothing step from zero folded into the residual:
-// r0 = r - A (D^-1 r) on the free rows (r is zero on the other rows)
-__global__ __launch_bounds__(NB) void k_mg0_pre(int32_t n0, const int32_t *fidx, const int32_t *lidx,
-                                                const int32_t *row_off, const int32_t *cols, const double4 *av,
-                                                const double4 *dinv, const double *r, double *r0, const int *stop) {
-  if (*stop) return;
+// compact residual, right-hand side and iterate from the full vectors
+__global__ __launch_bounds__(NB) void k_c_gather(int32_t n0, const int32_t *fidx, const double *r, const double *q,
+                                                 const double *x, double *cr, double *cb, double *cx) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 9 * (int64_t)n0) return;
   const int32_t k = (int32_t)(t / 9);
-  const int c = (int)(t - 9 * (int64_t)k);
-  const int32_t a = fidx[k];
-  double s = 0.0;
-  for (int32_t j = row_off[a]; j < row_off[a + 1]; ++j) {
-    const int32_t q = cols[j];
-    const int32_t lq = lidx[q];
-    if (lq < 0) continue;
-    s += cls4(av[j], c) * (cls4(dinv[lq], c) * r[9 * (size_t)q + c]);
-  }
-  r0[t] = r[9 * (size_t)a + c] - s;
+  const size_t o = 9 * (size_t)fidx[k] + (size_t)(t - 9 * (int64_t)k);
+  cr[t] = r[o];
+  cb[t] = q[o];
+  cx[t] = x[o];
 }
 
-// the coarse correction folded into the post-smoothing step:
-// x = D^-1 r + T y1, z = x + D^-1 (r - A x) on the free rows; dot += r.z
-// (per component, block sums added with atomics)
-__global__ __launch_bounds__(NB9) void k_mg0_post(int32_t n0, const int32_t *fidx, const int32_t *lidx,
-                                                  const int32_t *row_off, const int32_t *cols, const double4 *av,
-                                                  const double4 *dinv, const int32_t *agg, const double *y1,
-                                                  const double *r, double *z, double *dot, const int *stop) {
-  if (*stop) return;
+__global__ __launch_bounds__(NB) void k_c_scatter(int32_t n0, const int32_t *fidx, const double *cx, double *x) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 9 * (int64_t)n0) return;
+  const int32_t k = (int32_t)(t / 9);
+  x[9 * (size_t)fidx[k] + (size_t)(t - 9 * (int64_t)k)] = cx[t];
+}
+
+// the nine per-component sums of a block of NB9 threads added to out
+__device__ __forceinline__ void add9(double acc, double *out) {
   __shared__ double part[NB9];
-  const int c = threadIdx.x % 9;
-  double acc = 0.0;
-  const int64_t n9 = 9 * (int64_t)n0;
-  for (int64_t t = (int64_t)blockIdx.x * NB9 + threadIdx.x; t < n9; t += (int64_t)gridDim.x * NB9) {
-    const int32_t k = (int32_t)(t / 9);
-    const int32_t a = fidx[k];
-    double s = 0.0;
-    for (int32_t j = row_off[a]; j < row_off[a + 1]; ++j) {
-      const int32_t q = cols[j];
-      const int32_t lq = lidx[q];
-      if (lq < 0) continue;
-      const double xq = cls4(dinv[lq], c) * r[9 * (size_t)q + c] + (y1 ? y1[9 * (size_t)agg[lq] + c] : 0.0);
-      s += cls4(av[j], c) * xq;
-    }
-    const double ra = r[9 * (size_t)a + c];
-    const double xa = cls4(dinv[k], c) * ra + (y1 ? y1[9 * (size_t)agg[k] + c] : 0.0);
-    const double za = xa + cls4(dinv[k], c) * (ra - s);
-    z[9 * (size_t)a + c] = za;
-    acc += ra * za;
-  }
   part[threadIdx.x] = acc;
   __syncthreads();
   if (threadIdx.x < 9) {
     double sum = 0.0;
     for (int k = threadIdx.x; k < NB9; k += 9) sum += part[k];
-    atomicAdd(&dot[threadIdx.x], sum);
+    atomicAdd(&out[threadIdx.x], sum);
   }
 }
 
-// z = V-cycle of r on the free rows (z's other rows untouched); dot += r.z
-void mg_apply(hipStream_t s, const EllMg &g, const EllBuf &b, const MeshDev &m, const double *r, double *z,
-              double *dot, const int *stop) {
+// q = A p, pq += p.q
+__global__ __launch_bounds__(NB9) void k_c_apply(int32_t n0, const int32_t *off, const int32_t *col,
+                                                 const double4 *val, const double *p, double *q, double *pq,
+                                                 const int *stop) {
+  if (*stop) return;
+  const int c = threadIdx.x % 9;
+  double acc = 0.0;
+  const int64_t n9 = 9 * (int64_t)n0;
+  for (int64_t t = (int64_t)blockIdx.x * NB9 + threadIdx.x; t < n9; t += (int64_t)gridDim.x * NB9) {
+    const int32_t i = (int32_t)(t / 9);
+    double y = 0.0;
+    for (int32_t j = off[i]; j < off[i + 1]; ++j) y += cls4(val[j], c) * p[9 * (size_t)col[j] + c];
+    q[t] = y;
+    acc += p[t] * y;
+  }
+  add9(acc, pq);
+}
+
+// x += alpha p, r -= alpha q
+__global__ __launch_bounds__(NB9) void k_c_update(int64_t n9, const double *p, const double *q, double *x, double *r,
+                                                  const double *rz, const double *pq, const int *stop) {
+  if (*stop) return;
+  const int c = threadIdx.x % 9;
+  const double alpha = (pq[c] != 0.0) ? rz[c] / pq[c] : 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * NB9 + threadIdx.x; t < n9; t += (int64_t)gridDim.x * NB9) {
+    x[t] += alpha * p[t];
+    r[t] -= alpha * q[t];
+  }
+}
+
+// p = z + beta p, beta = rzn / rz (rz null: p = z)
+__global__ __launch_bounds__(NB9) void k_c_dir(int64_t n9, const double *z, double *p, const double *rz,
+                                               const double *rzn, const int *stop) {
+  if (*stop) return;
+  const int c = threadIdx.x % 9;
+  const double beta = (rz && rz[c] != 0.0) ? rzn[c] / rz[c] : 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * NB9 + threadIdx.x; t < n9; t += (int64_t)gridDim.x * NB9)
+    p[t] = rz ? z[t] + beta * p[t] : z[t];
+}
+
+// level 0's post-smoothing with the coarse correction folded in (yc null: no
+// coarser level) and the dot product: x = D^-1 b + T yc,
+// y = x + D^-1 (b - A x), dot += b.y
+__global__ __launch_bounds__(NB9) void k_c_post0(int32_t n0, const int32_t *off, const int32_t *col,
+                                                 const double4 *val, const double4 *dinv, const int32_t *agg,
+                                                 const double *yc, const double *b, double *y, double *dot,
+                                                 const int *stop) {
+  if (*stop) return;
+  const int c = threadIdx.x % 9;
+  double acc = 0.0;
+  const int64_t n9 = 9 * (int64_t)n0;
+  for (int64_t t = (int64_t)blockIdx.x * NB9 + threadIdx.x; t < n9; t += (int64_t)gridDim.x * NB9) {
+    const int32_t i = (int32_t)(t / 9);
+    double s = 0.0;
+    for (int32_t j = off[i]; j < off[i + 1]; ++j) {
+      const int32_t q = col[j];
+      const double xq = cls4(dinv[q], c) * b[9 * (size_t)q + c] + (yc ? yc[9 * (size_t)agg[q] + c] : 0.0);
+      s += cls4(val[j], c) * xq;
+    }
+    const double xa = cls4(dinv[i], c) * b[t] + (yc ? yc[9 * (size_t)agg[i] + c] : 0.0);
+    const double ya = xa + cls4(dinv[i], c) * (b[t] - s);
+    y[t] = ya;
+    acc += b[t] * ya;
+  }
+  add9(acc, dot);
+}
+
+// z = V-cycle of r (compact), dot += r.z
+void mg_apply(hipStream_t s, const EllMg &g, const double *r, double *z, double *dot, const int *stop) {
   const EllMgLevel &L0 = g.lv[0];
-  const int64_t n9 = 9 * (int64_t)L0.n;
-  const int64_t gp = (n9 + NB9 - 1) / NB9;
+  const int64_t gp = (9 * (int64_t)L0.n + NB9 - 1) / NB9;
   const unsigned gpost = (unsigned)(gp < 2048 ? gp : 2048);
-  (void)m;
   if (g.nl > 1) {
     const EllMgLevel &C = g.lv[1];
-    hipLaunchKernelGGL(k_mg0_pre, dim3(g9(L0.n)), dim3(NB), 0, s, L0.n, g.fidx, g.lidx, b.row_off, b.cols, b.av,
-                       g.dinv0, r, g.r0, stop);
-    hipLaunchKernelGGL(k_mg_restrict, dim3(g9(C.n)), dim3(NB), 0, s, C.n, L0.m_off, L0.mem, g.r0, C.b, stop);
+    hipLaunchKernelGGL(k_mg_pre, dim3(g9(L0.n)), dim3(NB), 0, s, L0.n, L0.off, L0.col, L0.val, L0.dinv, r, L0.r,
+                       stop);
+    hipLaunchKernelGGL(k_mg_restrict, dim3(g9(C.n)), dim3(NB), 0, s, C.n, L0.m_off, L0.mem, L0.r, C.b, stop);
     mg_vcycle(s, g, 1, stop);
-    hipLaunchKernelGGL(k_mg0_post, dim3(gpost), dim3(NB9), 0, s, L0.n, g.fidx, g.lidx, b.row_off, b.cols, b.av,
-                       g.dinv0, L0.agg, C.y, r, z, dot, stop);
+    hipLaunchKernelGGL(k_c_post0, dim3(gpost), dim3(NB9), 0, s, L0.n, L0.off, L0.col, L0.val, L0.dinv, L0.agg,
+                       (const double *)C.y, r, z, dot, stop);
   } else {
     // a single level: two l1-Jacobi steps from zero
-    hipLaunchKernelGGL(k_mg0_post, dim3(gpost), dim3(NB9), 0, s, L0.n, g.fidx, g.lidx, b.row_off, b.cols, b.av,
-                       g.dinv0, (const int32_t *)nullptr, (const double *)nullptr, r, z, dot, stop);
+    hipLaunchKernelGGL(k_c_post0, dim3(gpost), dim3(NB9), 0, s, L0.n, L0.off, L0.col, L0.val, L0.dinv,
+                       (const int32_t *)nullptr, (const double *)nullptr, r, z, dot, stop);
   }
 }
 
-// the hierarchy's values for this solve: level 0 is the matrix itself
-void mg_values(hipStream_t s, const EllMg &g, const EllBuf &b) {
+// the hierarchy's values for this solve
+void mg_values(hipStream_t s, const EllMg &g, const double4 *av) {
   const EllMgLevel &L0 = g.lv[0];
-  hipLaunchKernelGGL(k_mg0_dinv, dim3((L0.n + NB - 1) / NB), dim3(NB), 0, s, L0.n, g.fidx, g.lidx, b.row_off,
-                     b.cols, b.av, g.dinv0);
-  for (int l = 0; l + 1 < g.nl; ++l) {
+  hipLaunchKernelGGL(k_c_vals0, dim3((L0.nnz + NB - 1) / NB), dim3(NB), 0, s, L0.nnz, g.g0, av, L0.val);
+  for (int l = 0; l < g.nl; ++l) {
     const EllMgLevel &L = g.lv[l];
-    const EllMgLevel &C = g.lv[l + 1];
-    hipLaunchKernelGGL(k_mg_vals, dim3((C.nnz + NB - 1) / NB), dim3(NB), 0, s, C.nnz, L.g_off, L.g_idx,
-                       l == 0 ? (const double4 *)b.av : L.val, C.val);
-    hipLaunchKernelGGL(k_mg_dinv, dim3((C.n + NB - 1) / NB), dim3(NB), 0, s, C.n, C.off, C.val, C.dinv);
-  }
-}
-
-// q = A p on the free rows (free columns only: p is zero on the others),
-// pq += p.q; one thread per (free row, component), so that a row's nine
-// components are read and written together
-__global__ __launch_bounds__(NB9) void k_ell_apply9(int32_t n0, const int32_t *fidx, const int32_t *row_off,
-                                                    const int32_t *cols, const double4 *av, const double *p, double *q,
-                                                    double *pq, const int *stop) {
-  if (*stop) return;
-  __shared__ double part[NB9];
-  const int c = threadIdx.x % 9;
-  double acc = 0.0;
-  const int64_t n9 = 9 * (int64_t)n0;
-  for (int64_t t = (int64_t)blockIdx.x * NB9 + threadIdx.x; t < n9; t += (int64_t)gridDim.x * NB9) {
-    const int32_t a = fidx[t / 9];
-    double y = 0.0;
-    for (int32_t j = row_off[a]; j < row_off[a + 1]; ++j) y += cls4(av[j], c) * p[9 * (size_t)cols[j] + c];
-    q[9 * (size_t)a + c] = y;
-    acc += p[9 * (size_t)a + c] * y;
-  }
-  part[threadIdx.x] = acc;
-  __syncthreads();
-  if (threadIdx.x < 9) {
-    double sum = 0.0;
-    for (int k = threadIdx.x; k < NB9; k += 9) sum += part[k];
-    atomicAdd(&pq[threadIdx.x], sum);
+    if (l + 1 < g.nl) {
+      const EllMgLevel &C = g.lv[l + 1];
+      hipLaunchKernelGGL(k_mg_vals, dim3((C.nnz + NB - 1) / NB), dim3(NB), 0, s, C.nnz, L.g_off, L.g_idx, L.val,
+                         C.val);
+    }
+    hipLaunchKernelGGL(k_mg_dinv, dim3((L.n + NB - 1) / NB), dim3(NB), 0, s, L.n, L.off, L.val, L.dinv);
   }
 }
 
@@ -654,26 +655,7 @@ __global__ __launch_bounds__(NB) void k_ell_resid_mg(MeshDev m, const double *f,
   }
 }
 
-// x += alpha p, r -= alpha q on the free rows (the multigrid iteration: z
-// comes from the V-cycle)
-__global__ __launch_bounds__(NB9) void k_ell_update_mg(int64_t n9, const int8_t *role, const double *p,
-                                                       const double *q, double *x, double *r, const double *rz,
-                                                       const double *pq, const int *stop) {
-  if (*stop) return;
-  const int c = threadIdx.x % 9;
-  const double alpha = (pq[c] != 0.0) ? rz[c] / pq[c] : 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * NB9 + threadIdx.x; i < n9; i += (int64_t)gridDim.x * NB9) {
-    if (role[i / 9] != 0) continue;
-    x[i] += alpha * p[i];
-    r[i] -= alpha * q[i];
-  }
-}
 
-// p = z on the free rows
-__global__ __launch_bounds__(NB) void k_ell_copy9(int64_t n9, const int8_t *role, const double *z, double *p) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n9 && role[i / 9] == 0) p[i] = z[i];
-}
 
 
 }  // namespace
@@ -688,7 +670,7 @@ int launch_ell_solve(hipStream_t s, const MeshDev &m, const ModelDev &md, const 
   const unsigned ge = (unsigned)((m.ne + NB - 1) / NB);
   const unsigned gn = (unsigned)((m.nn + NB - 1) / NB);
   const int64_t n9 = 9 * (int64_t)m.nn;
-  const unsigned g9 = (unsigned)((n9 + NB - 1) / NB);
+  const unsigned gn9 = (unsigned)((n9 + NB - 1) / NB);
   const int64_t gu_ = (n9 + NB9 - 1) / NB9;
   const unsigned gu = (unsigned)(gu_ < 2048 ? gu_ : 2048);
   // scal: [0, 9) rz0, [9, 18) bb, then per iteration k: pq at 18 + 18k, the
@@ -700,18 +682,23 @@ int launch_ell_solve(hipStream_t s, const MeshDev &m, const ModelDev &md, const 
   hipLaunchKernelGGL(k_ell_in, dim3(gm), dim3(NB), 0, s, m, wp, b.x);
   hipLaunchKernelGGL(k_ell_start, dim3(gm), dim3(NB), 0, s, m, md, S, b.dir, b.dnv, b.x, b.r, b.z, b.p, b.diag);
   const bool mg = b.mg.nl > 0;
-  const int64_t g0p_ = mg ? (9 * (int64_t)b.mg.lv[0].n + NB9 - 1) / NB9 : 1;
-  const unsigned g0p = (unsigned)(g0p_ < 2048 ? g0p_ : 2048);
   const double *rz0 = b.scal, *bb = b.scal + 9;
+  const EllMg &g = b.mg;
+  const int32_t n0 = mg ? g.lv[0].n : 0;
+  const int64_t c9 = 9 * (int64_t)n0;
+  const int64_t gc_ = (c9 + NB9 - 1) / NB9;
+  const unsigned gc = (unsigned)(gc_ < 2048 ? (gc_ > 0 ? gc_ : 1) : 2048);
   if (mg) {
     // the stopping rule measures residuals in the preconditioner's norm:
     // r.M r against b.M b (M the V-cycle)
-    mg_values(s, b.mg, b);
+    mg_values(s, g, b.av);
     hipLaunchKernelGGL(k_ell_resid_mg, dim3(gm), dim3(NB), 0, s, m, f, b.dir, b.row_off, b.cols, b.mv, b.av, b.x,
                        b.r, b.q);
-    mg_apply(s, b.mg, b, m, b.q, b.z, b.scal + 9, b.stop);
-    mg_apply(s, b.mg, b, m, b.r, b.z, b.scal, b.stop);
-    hipLaunchKernelGGL(k_ell_copy9, dim3(g9), dim3(NB), 0, s, n9, b.dir, b.z, b.p);
+    hipLaunchKernelGGL(k_c_gather, dim3(g9(n0)), dim3(NB), 0, s, n0, g.fidx, b.r, b.q, b.x, g.cr, g.cb, g.cx);
+    mg_apply(s, g, g.cb, g.cz, b.scal + 9, b.stop);
+    mg_apply(s, g, g.cr, g.cz, b.scal, b.stop);
+    hipLaunchKernelGGL(k_c_dir, dim3(gc), dim3(NB9), 0, s, c9, g.cz, g.cp, (const double *)nullptr,
+                       (const double *)nullptr, b.stop);
   } else {
     hipLaunchKernelGGL(k_ell_resid, dim3(gm), dim3(NB), 0, s, m, f, b.dir, b.row_off, b.cols, b.mv, b.av, b.x, b.r,
                        b.z, b.p, b.diag, b.scal, b.scal + 9);
@@ -726,23 +713,25 @@ int launch_ell_solve(hipStream_t s, const MeshDev &m, const ModelDev &md, const 
       double *pq = b.scal + 18 + 18 * it;
       double *rzn = b.scal + 27 + 18 * it;
       if (mg) {
-        hipLaunchKernelGGL(k_ell_apply9, dim3(g0p), dim3(NB9), 0, s, b.mg.lv[0].n, b.mg.fidx, b.row_off, b.cols, b.av,
-                           b.p, b.q, pq, b.stop);
-        hipLaunchKernelGGL(k_ell_update_mg, dim3(gu), dim3(NB9), 0, s, n9, b.dir, b.p, b.q, b.x, b.r, rz, pq,
-                           b.stop);
-        mg_apply(s, b.mg, b, m, b.r, b.z, rzn, b.stop);
+        const EllMgLevel &L0 = g.lv[0];
+        hipLaunchKernelGGL(k_c_apply, dim3(gc), dim3(NB9), 0, s, n0, L0.off, L0.col, L0.val, g.cp, g.cq, pq, b.stop);
+        hipLaunchKernelGGL(k_c_update, dim3(gc), dim3(NB9), 0, s, c9, g.cp, g.cq, g.cx, g.cr, rz, pq, b.stop);
+        mg_apply(s, g, g.cr, g.cz, rzn, b.stop);
+        hipLaunchKernelGGL(k_ell_check, dim3(1), dim3(64), 0, s, bb, rzn, tol * tol, it + 1, b.stop);
+        hipLaunchKernelGGL(k_c_dir, dim3(gc), dim3(NB9), 0, s, c9, g.cz, g.cp, rz, rzn, b.stop);
       } else {
         hipLaunchKernelGGL(k_ell_apply, dim3(gm), dim3(NB), 0, s, m, b.dir, b.row_off, b.cols, b.av, b.p, b.q, pq,
                            b.stop);
         hipLaunchKernelGGL(k_ell_update, dim3(gu), dim3(NB9), 0, s, n9, b.dir, b.p, b.q, b.diag, b.x, b.r, b.z, rz,
                            pq, rzn, b.stop);
+        hipLaunchKernelGGL(k_ell_check, dim3(1), dim3(64), 0, s, bb, rzn, tol * tol, it + 1, b.stop);
+        hipLaunchKernelGGL(k_ell_dir, dim3(gn9), dim3(NB), 0, s, n9, b.dir, b.z, b.p, rz, rzn, b.stop);
       }
-      hipLaunchKernelGGL(k_ell_check, dim3(1), dim3(64), 0, s, bb, rzn, tol * tol, it + 1, b.stop);
-      hipLaunchKernelGGL(k_ell_dir, dim3(g9), dim3(NB), 0, s, n9, b.dir, b.z, b.p, rz, rzn, b.stop);
     }
     (void)hipMemcpyAsync(&stop_host, b.stop, sizeof(int), hipMemcpyDeviceToHost, s);
     (void)hipStreamSynchronize(s);
   }
+  if (mg) hipLaunchKernelGGL(k_c_scatter, dim3(g9(n0)), dim3(NB), 0, s, n0, g.fidx, g.cx, b.x);
   hipLaunchKernelGGL(k_ell_out, dim3(gn), dim3(NB), 0, s, m, b.x, wp);
   return stop_host > 0 ? stop_host - 1 : it;
 }

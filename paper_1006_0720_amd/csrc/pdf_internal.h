@@ -187,17 +187,15 @@ struct EllMgLevel {
   double *b = nullptr, *x = nullptr, *r = nullptr, *y = nullptr;  // [n][9]
   const int32_t *agg = nullptr, *m_off = nullptr, *mem = nullptr, *g_off = nullptr, *g_idx = nullptr;
 };
-// Level 0 works on the conjugate gradients' own node-major vectors and the
-// full matrix (row_off, cols, av), restricted to the free rows: lidx maps a
-// node to its free-row index (-1 for wall and identified nodes), fidx back;
-// dinv0 holds level 0's inverse l1 row sums over the free columns, r0 the
-// smoothed residual that is restricted.  Level 0's g_idx index av directly.
+// With the multigrid the conjugate gradients run on compact vectors of the
+// free rows ([n0][9], fidx maps them to nodes), and level 0 is the free-free
+// block of the matrix: its pattern over the free rows is built once, its
+// values are the full matrix's entries g0 of every solve.
 struct EllMg {
   int nl = 0;  // 0: Jacobi preconditioning
   int sweeps = 8;  // l1-Jacobi sweeps on the last level
-  const int32_t *fidx = nullptr, *lidx = nullptr;
-  double4 *dinv0 = nullptr;
-  double *r0 = nullptr;
+  const int32_t *fidx = nullptr, *g0 = nullptr;
+  double *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr, *cb = nullptr;
   EllMgLevel lv[ELL_MAXL];
 };
 
