@@ -2,10 +2,12 @@
 // element-wise kernels of a 4-layer MLP (forward, backward, Adam), the nodal
 // feature kernel and the merge with the plain estimator.
 //
-// Matrix cores: v_mfma_f32_16x16x16bf16_1k computes a 16x16 FP32 tile
-// D = A(16x16) B(16x16) + C over one wave.  Operand layout per lane l:
-//   A: row l%16, columns 4*(l/16) .. +3      B: rows 4*(l/16) .. +3, column l%16
+// Matrix cores: gfx950's v_mfma_f32_16x16x32_bf16 computes a 16x16 FP32 tile
+// D = A(16x32) B(32x16) + C over one wave.  Operand layout per lane l:
+//   A: row l%16, columns 8*(l/16) .. +7      B: rows 8*(l/16) .. +7, column l%16
 //   C/D: rows 4*(l/16) .. +3, column l%16
+// A K tail of 16 uses v_mfma_f32_16x16x16bf16_1k (A: columns 4*(l/16) .. +3,
+// B: rows 4*(l/16) .. +3, the same C/D).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,6 +18,7 @@
 namespace pdfk {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // round-to-nearest-even binary32 -> bfloat16 bits
@@ -32,9 +35,9 @@ __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint
 // ---------------------------------------------------------------------------
 // C (MxN, fp32, row-major, ldc) = op(A) op(B) + beta C;  A, B bf16 row-major.
 // op(A)(i,k) = ta ? A[k*lda+i] : A[i*lda+k];  op(B)(k,j) = tb ? B[j*ldb+k] : B[k*ldb+j]
-// Workgroup tile 64x64, four waves of 32x32 (2x2 MFMA tiles), K steps of 16.
+// Workgroup tile 64x64, four waves of 32x32 (2x2 MFMA tiles), K steps of 32.
 // ---------------------------------------------------------------------------
-constexpr int GT = 64, GK = 16;
+constexpr int GT = 64, GK = 32;
 
 __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const uint16_t *__restrict__ A,
                                                    int lda, int ta, const uint16_t *__restrict__ B,
@@ -52,7 +55,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
   const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
   const bool split = gridDim.z > 1;
   for (int k0 = kb; k0 < ke; k0 += GK) {
-    // stage 64x16 of op(A) and 16x64 of op(B) (four elements per thread each)
+    // stage 64x32 of op(A) and 32x64 of op(B) (eight elements per thread each)
     for (int t = tid; t < GT * GK; t += 256) {
       const int r = t / GK, k = t % GK;
       const int gi = i0 + r, gk = k0 + k;
@@ -66,14 +69,14 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
       sB[kb][c] = w;
     }
     __syncthreads();
-    const int kq = 4 * (lane >> 4), rc = lane & 15;
+    const int kq = 8 * (lane >> 4), rc = lane & 15;
     for (int a = 0; a < 2; ++a) {
-      bf16x4 fa;
-      for (int q = 0; q < 4; ++q) fa[q] = (short)sA[wi + 16 * a + rc][kq + q];
+      bf16x8 fa;
+      for (int q = 0; q < 8; ++q) fa[q] = __builtin_bit_cast(__bf16, sA[wi + 16 * a + rc][kq + q]);
       for (int b = 0; b < 2; ++b) {
-        bf16x4 fb;
-        for (int q = 0; q < 4; ++q) fb[q] = (short)sB[kq + q][wj + 16 * b + rc];
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa, fb, acc[a][b], 0, 0, 0);
+        bf16x8 fb;
+        for (int q = 0; q < 8; ++q) fb[q] = __builtin_bit_cast(__bf16, sB[kq + q][wj + 16 * b + rc]);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[a][b], 0, 0, 0);
       }
     }
     __syncthreads();
@@ -157,6 +160,9 @@ __device__ __forceinline__ bf16x4 lds_frag(const uint16_t *p) {
   return r;
 }
 
+// eight bf16 from 16-byte-aligned LDS
+__device__ __forceinline__ bf16x8 lds_frag8(const uint16_t *p) { return __builtin_bit_cast(bf16x8, *(const uint4 *)p); }
+
 // W [K][N] (row-major) -> Wt [Np][K + MLP_PAD] (Np = N rounded up to 16,
 // columns N .. Np-1 zero): the LDS layout of a layer, kept in global memory
 // so that a workgroup stages it with 16-byte copies
@@ -198,11 +204,20 @@ __device__ __forceinline__ void mlp_pass(const uint16_t *in, int K, const uint16
                                          int64_t nrows) {
   const int lane = threadIdx.x & 63;
   const int ldi = K + MLP_PAD;
-  const int kq = 4 * (lane >> 4), rc = lane & 15;
+  const int kq = 4 * (lane >> 4), rc = lane & 15, kq8 = 8 * (lane >> 4);
   f32x4 acc[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) acc[u] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  int k0 = 0;
+  for (; k0 + 32 <= K; k0 += 32) {
+    const bf16x8 fa = lds_frag8(in + rc * ldi + k0 + kq8);
+    bf16x8 fb[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) fb[u] = lds_frag8(Wt + (n0 + 16 * u + rc) * ldi + k0 + kq8);
+#pragma unroll
+    for (int u = 0; u < NT; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[u], fa, acc[u], 0, 0, 0);
+  }
+  if (k0 < K) {  // K a multiple of 16: a tail of 16
     const bf16x4 fa = lds_frag(in + rc * ldi + k0 + kq);
     bf16x4 fb[NT];
 #pragma unroll
