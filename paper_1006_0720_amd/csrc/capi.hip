@@ -15,7 +15,7 @@
 #include <mutex>
 #include <vector>
 
-#include "pdf_internal.h"
+#include "pdf_solvers.h"
 
 using namespace pdfk;
 

@@ -25,7 +25,7 @@
 // conjugate-gradient method.
 #include <hip/hip_runtime.h>
 
-#include "pdf_internal.h"
+#include "pdf_solvers.h"
 
 #include <algorithm>
 #include <cmath>

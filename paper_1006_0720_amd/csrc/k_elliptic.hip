@@ -30,7 +30,7 @@
 // block sums added with atomics.
 #include <hip/hip_runtime.h>
 
-#include "pdf_internal.h"
+#include "pdf_solvers.h"
 
 namespace pdfk {
 

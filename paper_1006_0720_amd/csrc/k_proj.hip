@@ -20,7 +20,7 @@
 // plus the node average of the element gradients of P'.
 #include <hip/hip_runtime.h>
 
-#include "pdf_internal.h"
+#include "pdf_solvers.h"
 
 #include <utility>
 

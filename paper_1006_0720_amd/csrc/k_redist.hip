@@ -17,7 +17,7 @@
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
-#include "pdf_internal.h"
+#include "pdf_solvers.h"
 #include "rng.h"
 
 namespace pdfk {

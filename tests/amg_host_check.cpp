@@ -8,7 +8,7 @@
 // restriction by P^T, the coarse correction, prolongation by P, a damped-Jacobi
 // step; the coarsest level by its dense inverse).  Writes the iteration count,
 // the level sizes and the solution.
-#include "../paper_1006_0720_amd/csrc/pdf_internal.h"
+#include "../paper_1006_0720_amd/csrc/pdf_solvers.h"
 
 #include <cmath>
 #include <cstdio>
