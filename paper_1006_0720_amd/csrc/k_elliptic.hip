@@ -27,7 +27,10 @@
 // four L2 classes row by row (every master node gathers the elements around
 // it, no atomics); the iteration vectors are node-major ([nn][9]) so that a
 // column's nine components are one contiguous read; the dot products are
-// block sums added with atomics.
+// block sums added with atomics.  With the multigrid the iteration runs on
+// compact vectors of the free rows ([n0][9]): the residual of the warm start
+// (with the wall columns' Dirichlet values) is formed on the full rows once,
+// gathered, and the solution scattered back at the end.
 #include <hip/hip_runtime.h>
 
 #include "pdf_solvers.h"
