@@ -394,7 +394,8 @@ pdf_status pdf_denoiser_train_step(pdf_denoiser *dn, const float *x, const float
  * corrected fields; *n_fallback (may be NULL) counts rejected corrections.
  * tau >= 0; tau = +inf (HUGE_VAL) takes every finite correction, also at
  * nodes where the standard error is zero; a non-finite correction is always
- * rejected. */
+ * rejected.  With out on the device and n_fallback NULL the call only queues
+ * the work on the context's stream and returns; otherwise it waits for it. */
 pdf_status pdf_denoise_stats(pdf_denoiser *dn, double tau, double *out, int32_t on_device,
                              uint64_t *n_fallback);
 

@@ -412,6 +412,15 @@ class Denoiser:
             self.ctx._chk(lib.pdf_denoise_stats(self.h, float(tau), _ptr(out), 0, C.byref(nf)))
         return out, nf.value
 
+    def denoise_into(self, out, tau=3.0):
+        """pdf_denoise_stats into a caller-owned device tensor (float64
+        [25, n_nodes]) without the rejection count: queued on the context's
+        stream, the call does not wait for it."""
+        t = self.torch
+        assert out.dtype == t.float64 and out.is_contiguous() and tuple(out.shape) == (NSTAT, self.ctx.n_nodes)
+        self.ctx._chk(lib.pdf_denoise_stats(self.h, float(tau), C.c_void_p(out.data_ptr()), 1, None))
+        return out
+
     def denoise_noalloc(self, out, n_fallback=None, tau=3.0):
         """pdf_denoise_stats_noalloc into caller-owned device tensors: out
         (float64 [25, n_nodes]) and n_fallback (int64 [1] or None)."""

@@ -1689,6 +1689,7 @@ pdf_status pdf_denoise_stats(pdf_denoiser *d, double tau, double *out, int32_t o
   HIPCHK(c, hipMemsetAsync(d->nfall, 0, 8, s));
   launch_merge(s, nn, c->md.master, c->latest, R, PDF_DN_NOUT, d->scale, tau, c->params.C4, res, d->nfall);
   HIPCHK(c, hipGetLastError());
+  if (on_device && !n_fallback) return PDF_OK;  // nothing for the host to wait for
   unsigned long long nf = 0;
   HIPCHK(c, hipMemcpyAsync(&nf, d->nfall, 8, hipMemcpyDeviceToHost, s));
   if (!on_device)

@@ -567,9 +567,9 @@ void launch_features(hipStream_t s, const MeshDev &m, const int32_t *p2p_off, co
 // moments s: s sqrt(2/N), <uv>: sqrt((<uu><vv> + <uv>^2)/N), <omega>: <omega>
 // sqrt(C4/N).  Every other statistic is copied from the plain estimate.
 // Node n = n0 + r takes its network output from row r of R (rows r < cnt).
-__global__ void k_merge(int nn, const int32_t *master, const double *S, int32_t n0, int32_t cnt, const float *R,
-                        int ldr, const float *scale, double tau, double C4, double *out,
-                        unsigned long long *nfall) {
+__global__ void k_merge(int nn, const int32_t *__restrict__ master, const double *__restrict__ S, int32_t n0,
+                        int32_t cnt, const float *__restrict__ R, int ldr, const float *__restrict__ scale,
+                        double tau, double C4, double *__restrict__ out, unsigned long long *nfall) {
   const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t n = n0 + r;
   int fb = 0;

@@ -218,3 +218,19 @@ def test_fused_inference_matches_training_forward(env):
     loss2 = dn.train_step(xt, tt, 0.0)
     assert abs(loss2 - float(((y2 - t) ** 2).mean())) <= 1e-5 * loss2 and abs(loss2 - loss) > 1e-4 * loss
     dn.close()
+
+
+def test_denoise_queued_without_count_matches(env):
+    """pdf_denoise_stats into device memory with no rejection count returns
+    without waiting; after the stream is drained its output equals the
+    counted call's, also over several queued calls."""
+    torch, L, ctx, w = env
+    dn = L.Denoiser(ctx, hidden=64, seed=3)
+    dn.set_norm(np.zeros(48), np.ones(48), np.full(8, 1e-3, np.float32))
+    ref, _ = dn.denoise(tau=3.0, device=True)
+    out = torch.full_like(ref, float("nan"))
+    for _ in range(5):
+        dn.denoise_into(out, tau=3.0)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    dn.close()
