@@ -81,14 +81,18 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def profile_counters(workload):
+def profile_counters(workload, cfg):
     """Committed rocprofv3 counter summary of the particle kernel for this
-    workload, or None when none exists or the kernel source changed since."""
+    workload, or None when none exists, the kernel source changed since, or
+    this run's configuration (particle count, kernel variant) is not the one
+    the counters were taken at."""
     path = os.path.join(ROOT, "profiles", f"k_advance_{workload}_counters.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("source_hash") != source_hash():
+        return None
+    if any(cfg.get(k) != v for k, v in d.get("bench_config", {}).items()):
         return None
     return d
 
@@ -226,6 +230,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="channel_block", choices=sorted(WORKLOADS))
     ap.add_argument("--reorder-every", type=int, default=8)
+    ap.add_argument("--ppe", type=int, default=0,
+                    help="particles per element at seeding (0: the workload's own count)")
     ap.add_argument("--min-ppe", type=int, default=0,
                     help="particle redistribution: minimum particles per element (0: off)")
     ap.add_argument("--stats-mode", default="elem", choices=["elem", "shape"],
@@ -269,7 +275,7 @@ def main():
     from synth import configs as CF
 
     ctor, desc = WORKLOADS[args.workload]
-    w = getattr(CF, ctor)()
+    w = getattr(CF, ctor)(**({"ppe": args.ppe} if args.ppe > 0 else {}))
     shape = args.stats_mode == "shape"
     if shape:
         w.params = dict(w.params, stats_mode=CF.STATS_SHAPE)
@@ -318,7 +324,9 @@ def main():
     bytes_alg, per_p, per_e = kernel_bytes(w, tsize, shape)
     adv_ms = tm["advance"] / args.steps
     achieved = bytes_alg / (adv_ms * 1e-3) / 1e9
-    prof = None if shape else profile_counters(args.workload)
+    prof = None if shape else profile_counters(
+        args.workload, {"n_particles": n_p, "n_elements": w.mesh.n_elems, "stats_mode": args.stats_mode,
+                        "min_ppe": args.min_ppe, "mix": args.mix, "wp": args.wp, "proj": bool(args.proj)})
     traffic = prof["traffic_bytes_per_launch"] if prof else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

@@ -70,7 +70,7 @@ def compare_stats(gpu, ref, rtol, fields=range(25), what=""):
         s = float(np.sqrt((ref[f] ** 2).mean())) + 1e-300
         out[f] = max_rel_err(gpu[f], ref[f], s)
     bad = {f: e for f, e in out.items() if not e <= rtol}
-    assert not bad, f"{what} nodal statistics mismatch (rtol {rtol}): {bad}"
+    assert not bad, f"{what} statistics mismatch (rtol {rtol}): {bad}"
     return out
 
 

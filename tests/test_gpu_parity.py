@@ -62,13 +62,20 @@ def test_seed_parity_fp64(L):
 
 @pytest.mark.parametrize("reorder", [0, 4])
 def test_trajectory_parity_fp64_periodic_square(L, reorder):
-    """Workload 1 at full size: 2048 elements, 102400 particles, 100 steps."""
+    """Workload 1 at full size: 2048 elements, 102400 particles, 100 steps;
+    nodal statistics and the exported element moments."""
     w = CF.periodic_square()
     ctx, o = _pair(L, w, reorder_every=reorder)
     for chunk in range(4):
         ctx.advance(25, w.dt)
         o.run(w.dt, 25)
         _check(ctx, o, w, 1e-12, f"step {25 * (chunk + 1)}")
+        # element moments of the last accumulation (formed on demand after a
+        # step that gathered the node values straight from the sums; the last
+        # chunk ends on a reorder step when reorder = 4)
+        _, el = ctx.stats(elem=True)
+        assert np.array_equal(el[0], o.elem_stats[0])
+        compare_stats(el, o.elem_stats, 1e-12, fields=range(1, 16), what=f"element moments, step {25 * (chunk + 1)}")
     c = ctx.counters()
     oc = o.counter_dict()
     assert c["lost"] == 0 and oc["lost"] == 0
