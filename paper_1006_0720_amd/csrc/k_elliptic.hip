@@ -117,6 +117,8 @@ __device__ __forceinline__ double elem_area(const ElemGeo &g) {
   return 0.5 * ((g.x[1] - g.x[0]) * (g.y[2] - g.y[0]) - (g.x[2] - g.x[0]) * (g.y[1] - g.y[0]));
 }
 
+// class value of a double4 row; only with a class known at compile time (the
+// unrolled per-row loops below), see cls_at for lane-varying classes
 __device__ __forceinline__ double l2_of(const double4 &v, int cls) {
   return cls == 0 ? v.x : (cls == 1 ? v.y : (cls == 2 ? v.z : v.w));
 }
@@ -216,6 +218,7 @@ __global__ __launch_bounds__(NB) void k_ell_resid(MeshDev m, const double *f, co
         const double M = mv[j];
         const double4 v = av[j];
         const double *xq = x + 9 * (size_t)q;
+#pragma unroll
         for (int c = 0; c < 9; ++c) {
           const double A = l2_of(v, ell_class(c));
           b[c] += M * f[(size_t)c * nn + q];
@@ -256,6 +259,7 @@ __global__ __launch_bounds__(NB) void k_ell_apply(MeshDev m, const int8_t *dir, 
         const double4 v = av[j];
         const double *pq_ = p + 9 * (size_t)cols[j];
         const double cl[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
         for (int c = 0; c < 9; ++c) y[c] += cl[ell_class(c)] * pq_[c];
       }
       for (int c = 0; c < 9; ++c) part[c] = p[9 * (size_t)a + c] * y[c];
@@ -338,7 +342,13 @@ __global__ __launch_bounds__(NB) void k_ell_in(MeshDev m, const double *wp, doub
 // ---- plain-aggregation multigrid preconditioner (EllMg) ----
 // One thread per (row, component) on every level: consecutive threads read
 // consecutive components of a row, so the [n][9] vectors are read coalesced.
-__device__ __forceinline__ double cls4(const double4 &v, int c) { return l2_of(v, ell_class(c)); }
+//
+// Kernels whose lanes take different components read a class value by its
+// address, one 8-byte load at element k of the double4 row.  Selecting among
+// the loaded members by a lane-varying class (a chain of conditionals) was
+// compiled into branches that pick a load address, and lanes of class 3 kept
+// the class-1 address: the wrong matrix value, found against a host product.
+__device__ __forceinline__ double cls_at(const double4 *a, size_t i, int k) { return ((const double *)(a + i))[k]; }
 
 // the next level's values: sums of this level's (the Galerkin product with the
 // tentative prolongator)
@@ -373,14 +383,6 @@ __global__ __launch_bounds__(NB) void k_mg_dinv(int32_t n, const int32_t *off, c
   dinv[i] = make_double4(1.0 / s.x, 1.0 / s.y, 1.0 / s.z, 1.0 / s.w);
 }
 
-// (A x)_t for entry t = (row i, component c)
-__device__ __forceinline__ double mg_row(const int32_t *off, const int32_t *col, const double4 *val,
-                                         const double *x, int32_t i, int c) {
-  double s = 0.0;
-  for (int32_t j = off[i]; j < off[i + 1]; ++j) s += cls4(val[j], c) * x[9 * (size_t)col[j] + c];
-  return s;
-}
-
 // the pre-smoothing step from zero folded into the residual: r = b - A (D^-1 b)
 __global__ __launch_bounds__(NB) void k_mg_pre(int32_t n, const int32_t *off, const int32_t *col,
                                                const double4 *val, const double4 *dinv, const double *b, double *r,
@@ -390,10 +392,11 @@ __global__ __launch_bounds__(NB) void k_mg_pre(int32_t n, const int32_t *off, co
   if (t >= 9 * (int64_t)n) return;
   const int32_t i = (int32_t)(t / 9);
   const int c = (int)(t - 9 * (int64_t)i);
+  const int k = ell_class(c);
   double s = 0.0;
   for (int32_t j = off[i]; j < off[i + 1]; ++j) {
     const int32_t q = col[j];
-    s += cls4(val[j], c) * (cls4(dinv[q], c) * b[9 * (size_t)q + c]);
+    s += cls_at(val, j, k) * (cls_at(dinv, q, k) * b[9 * (size_t)q + c]);
   }
   r[t] = b[t] - s;
 }
@@ -408,13 +411,15 @@ __global__ __launch_bounds__(NB) void k_mg_post(int32_t n, const int32_t *off, c
   if (t >= 9 * (int64_t)n) return;
   const int32_t i = (int32_t)(t / 9);
   const int c = (int)(t - 9 * (int64_t)i);
+  const int k = ell_class(c);
   double s = 0.0;
   for (int32_t j = off[i]; j < off[i + 1]; ++j) {
     const int32_t q = col[j];
-    s += cls4(val[j], c) * (cls4(dinv[q], c) * b[9 * (size_t)q + c] + yc[9 * (size_t)agg[q] + c]);
+    s += cls_at(val, j, k) * (cls_at(dinv, q, k) * b[9 * (size_t)q + c] + yc[9 * (size_t)agg[q] + c]);
   }
-  const double x = cls4(dinv[i], c) * b[t] + yc[9 * (size_t)agg[i] + c];
-  y[t] = x + cls4(dinv[i], c) * (b[t] - s);
+  const double di = cls_at(dinv, i, k);
+  const double x = di * b[t] + yc[9 * (size_t)agg[i] + c];
+  y[t] = x + di * (b[t] - s);
 }
 
 // bc = T^T r: the sum over each aggregate's rows
@@ -444,7 +449,7 @@ __global__ __launch_bounds__(NBC) void k_mg_coarse(int32_t n, const int32_t *off
   double nx[CQ];
   for (int32_t t = threadIdx.x; t < n9; t += NBC) {
     const int32_t i = t / 9;
-    xs[t] = cls4(dinv[i], t - 9 * i) * b[t];
+    xs[t] = cls_at(dinv, i, ell_class(t - 9 * i)) * b[t];
   }
   __syncthreads();
   for (int sw = 1; sw < sweeps; ++sw) {
@@ -454,9 +459,10 @@ __global__ __launch_bounds__(NBC) void k_mg_coarse(int32_t n, const int32_t *off
       if (t < n9) {
         const int32_t i = t / 9;
         const int c = t - 9 * i;
+        const int k = ell_class(c);
         double s = 0.0;
-        for (int32_t j = off[i]; j < off[i + 1]; ++j) s += cls4(val[j], c) * xs[9 * col[j] + c];
-        nx[q] = xs[t] + cls4(dinv[i], c) * (b[t] - s);
+        for (int32_t j = off[i]; j < off[i + 1]; ++j) s += cls_at(val, j, k) * xs[9 * col[j] + c];
+        nx[q] = xs[t] + cls_at(dinv, i, k) * (b[t] - s);
       }
     }
     __syncthreads();
@@ -535,12 +541,13 @@ __global__ __launch_bounds__(NB9) void k_c_apply(int32_t n0, const int32_t *off,
                                                  const int *stop) {
   if (*stop) return;
   const int c = threadIdx.x % 9;
+  const int k = ell_class(c);
   double acc = 0.0;
   const int64_t n9 = 9 * (int64_t)n0;
   for (int64_t t = (int64_t)blockIdx.x * NB9 + threadIdx.x; t < n9; t += (int64_t)gridDim.x * NB9) {
     const int32_t i = (int32_t)(t / 9);
     double y = 0.0;
-    for (int32_t j = off[i]; j < off[i + 1]; ++j) y += cls4(val[j], c) * p[9 * (size_t)col[j] + c];
+    for (int32_t j = off[i]; j < off[i + 1]; ++j) y += cls_at(val, j, k) * p[9 * (size_t)col[j] + c];
     q[t] = y;
     acc += p[t] * y;
   }
@@ -578,6 +585,7 @@ __global__ __launch_bounds__(NB9) void k_c_post0(int32_t n0, const int32_t *off,
                                                  const int *stop) {
   if (*stop) return;
   const int c = threadIdx.x % 9;
+  const int k = ell_class(c);
   double acc = 0.0;
   const int64_t n9 = 9 * (int64_t)n0;
   for (int64_t t = (int64_t)blockIdx.x * NB9 + threadIdx.x; t < n9; t += (int64_t)gridDim.x * NB9) {
@@ -585,11 +593,12 @@ __global__ __launch_bounds__(NB9) void k_c_post0(int32_t n0, const int32_t *off,
     double s = 0.0;
     for (int32_t j = off[i]; j < off[i + 1]; ++j) {
       const int32_t q = col[j];
-      const double xq = cls4(dinv[q], c) * b[9 * (size_t)q + c] + (yc ? yc[9 * (size_t)agg[q] + c] : 0.0);
-      s += cls4(val[j], c) * xq;
+      const double xq = cls_at(dinv, q, k) * b[9 * (size_t)q + c] + (yc ? yc[9 * (size_t)agg[q] + c] : 0.0);
+      s += cls_at(val, j, k) * xq;
     }
-    const double xa = cls4(dinv[i], c) * b[t] + (yc ? yc[9 * (size_t)agg[i] + c] : 0.0);
-    const double ya = xa + cls4(dinv[i], c) * (b[t] - s);
+    const double di = cls_at(dinv, i, k);
+    const double xa = di * b[t] + (yc ? yc[9 * (size_t)agg[i] + c] : 0.0);
+    const double ya = xa + di * (b[t] - s);
     y[t] = ya;
     acc += b[t] * ya;
   }
@@ -647,6 +656,7 @@ __global__ __launch_bounds__(NB) void k_ell_resid_mg(MeshDev m, const double *f,
     const double M = mv[j];
     const double4 v = av[j];
     const double *xq = x + 9 * (size_t)qn;
+#pragma unroll
     for (int c = 0; c < 9; ++c) {
       b[c] += M * f[(size_t)c * nn + qn];
       ax[c] += l2_of(v, ell_class(c)) * xq[c];
