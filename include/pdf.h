@@ -372,6 +372,22 @@ pdf_status pdf_denoiser_set_norm(pdf_denoiser *dn, const float *mu48, const floa
  * Each factor positive and finite (PDF_E_INVALID_ARG otherwise). */
 pdf_status pdf_denoiser_set_fallback(pdf_denoiser *dn, const float *kappa8);
 
+/* Save (save != 0) or load (save = 0) a trained denoiser at path, so that a
+ * network trained once (on pairs of low- and high-count runs) can serve later
+ * runs on a mesh.  The file holds an 8-byte tag "pdfdn001", the hidden width
+ * and a flag for a set standardisation (int32 each), the parameter count
+ * (int64), the float32 parameter vector (layout above), the 48 feature means,
+ * the 48 feature scales, the 8 output scales and the 8 fallback factors
+ * (float32), in the host's byte order.  The optimiser state is not kept: a
+ * load resets it, as pdf_denoiser_params does.  Loading needs a denoiser of
+ * the same hidden width (on any mesh) and rejects a file with another tag,
+ * width or parameter count, a short or oversized file, non-positive feature
+ * scales and non-positive or non-finite fallback factors; these and a file
+ * that cannot be opened, read or written are PDF_E_INVALID_ARG with the
+ * reason in pdf_last_error.  The denoiser is unchanged by a failed load.
+ * Waits for the context's stream. */
+pdf_status pdf_denoiser_io(pdf_denoiser *dn, int32_t save, const char *path);
+
 /* Features of nodal statistics [PDF_NSTAT][n_nodes] (device pointer; NULL: the
  * context's latest estimate) into feat [n_nodes][48] (device, float32),
  * standardised when standardized != 0. */

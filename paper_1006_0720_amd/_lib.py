@@ -299,6 +299,7 @@ def _declare_denoiser():
         "pdf_denoiser_params": ([vp, vp, i64, i32], i32),
         "pdf_denoiser_set_norm": ([vp, vp, vp, vp], i32),
         "pdf_denoiser_set_fallback": ([vp, vp], i32),
+        "pdf_denoiser_io": ([vp, i32, C.c_char_p], i32),
         "pdf_denoiser_features": ([vp, vp, vp, i32], i32),
         "pdf_denoiser_forward": ([vp, vp, i32, vp], i32),
         "pdf_denoiser_train_step": ([vp, vp, vp, i32, C.c_float, C.POINTER(C.c_float), vp], i32),
@@ -369,6 +370,19 @@ class Denoiser:
         assert kappa.size == DN_NOUT
         self.ctx._chk(lib.pdf_denoiser_set_fallback(self.h, _ptr(kappa)))
         self.kappa = kappa.copy()
+
+    def save(self, path):
+        """pdf_denoiser_io: write the parameters, standardisation, output
+        scales and fallback factors to path."""
+        self.ctx._chk(lib.pdf_denoiser_io(self.h, 1, os.fsencode(path)))
+
+    def load(self, path):
+        """pdf_denoiser_io: read a file written by save() (same hidden width).
+        The host copies of the standardisation and fallback factors that
+        set_norm and set_fallback keep are then unknown (None)."""
+        self.ctx._chk(lib.pdf_denoiser_io(self.h, 0, os.fsencode(path)))
+        self.norm = None
+        self.kappa = None
 
     def features(self, nodal=None, standardized=False):
         """Features [n_nodes, 48] (torch, device) of nodal statistics (torch

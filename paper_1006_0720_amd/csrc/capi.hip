@@ -1576,6 +1576,66 @@ pdf_status pdf_denoiser_set_fallback(pdf_denoiser *d, const float *kappa8) {
   return PDF_OK;
 }
 
+pdf_status pdf_denoiser_io(pdf_denoiser *d, int32_t save, const char *path) {
+  if (!d || !path) return PDF_E_INVALID_ARG;
+  pdf_ctx *c = d->ctx;
+  static const char TAG[8] = {'p', 'd', 'f', 'd', 'n', '0', '0', '1'};
+  const size_t np = (size_t)d->np;
+  std::vector<float> P(np), norm(2 * PDF_DN_NIN + 2 * PDF_DN_NOUT);  // mu, sig, scales, fallback factors
+  if (save) {
+    HIPCHK(c, hipMemcpyAsync(P.data(), d->P, np * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(norm.data(), d->mu, PDF_DN_NIN * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(norm.data() + PDF_DN_NIN, d->sig, PDF_DN_NIN * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(norm.data() + 2 * PDF_DN_NIN, d->scale, 2 * PDF_DN_NOUT * 4, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    FILE *f = fopen(path, "wb");
+    if (!f) return fail(c, PDF_E_INVALID_ARG, std::string("cannot open for writing: ") + path);
+    const int32_t hdr[2] = {d->H, d->norm_set ? 1 : 0};
+    const int64_t n64 = d->np;
+    bool ok = fwrite(TAG, 1, 8, f) == 8 && fwrite(hdr, 4, 2, f) == 2 && fwrite(&n64, 8, 1, f) == 1 &&
+              fwrite(P.data(), 4, np, f) == np && fwrite(norm.data(), 4, norm.size(), f) == norm.size();
+    ok = (fclose(f) == 0) && ok;
+    if (!ok) return fail(c, PDF_E_INVALID_ARG, std::string("write failed: ") + path);
+    return PDF_OK;
+  }
+  FILE *f = fopen(path, "rb");
+  if (!f) return fail(c, PDF_E_INVALID_ARG, std::string("cannot open for reading: ") + path);
+  char tag[8];
+  int32_t hdr[2];
+  int64_t n64 = -1;
+  bool ok = fread(tag, 1, 8, f) == 8 && memcmp(tag, TAG, 8) == 0;
+  if (!ok) {
+    fclose(f);
+    return fail(c, PDF_E_INVALID_ARG, std::string("not a denoiser file: ") + path);
+  }
+  ok = fread(hdr, 4, 2, f) == 2 && fread(&n64, 8, 1, f) == 1;
+  if (!ok || hdr[0] != d->H || n64 != d->np) {
+    fclose(f);
+    return fail(c, PDF_E_INVALID_ARG, "the file's hidden width or parameter count differs from this denoiser's");
+  }
+  ok = fread(P.data(), 4, np, f) == np && fread(norm.data(), 4, norm.size(), f) == norm.size();
+  char extra;
+  ok = ok && fread(&extra, 1, 1, f) == 0;  // nothing after the last field
+  fclose(f);
+  if (!ok) return fail(c, PDF_E_INVALID_ARG, std::string("truncated or oversized denoiser file: ") + path);
+  for (int i = 0; i < PDF_DN_NIN; ++i)
+    if (!(norm[PDF_DN_NIN + i] > 0.f)) return fail(c, PDF_E_INVALID_ARG, "feature scale must be positive");
+  for (int i = 0; i < PDF_DN_NOUT; ++i) {
+    const float k = norm[2 * PDF_DN_NIN + PDF_DN_NOUT + i];
+    if (!(k > 0.f) || !std::isfinite(k)) return fail(c, PDF_E_INVALID_ARG, "fallback factors must be positive and finite");
+  }
+  const pdf_status st = pdf_denoiser_params(d, P.data(), d->np, 1);
+  if (st != PDF_OK) return st;
+  HIPCHK(c, hipMemcpyAsync(d->mu, norm.data(), PDF_DN_NIN * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(d->sig, norm.data() + PDF_DN_NIN, PDF_DN_NIN * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(d->scale, norm.data() + 2 * PDF_DN_NIN, 2 * PDF_DN_NOUT * 4, hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  d->norm_set = hdr[1] != 0;
+  return PDF_OK;
+}
+
 pdf_status pdf_denoiser_features(pdf_denoiser *d, const double *nodal, float *feat, int32_t standardized) {
   if (!d || !feat) return PDF_E_INVALID_ARG;
   pdf_ctx *c = d->ctx;

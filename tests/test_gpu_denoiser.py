@@ -234,3 +234,54 @@ def test_denoise_queued_without_count_matches(env):
     torch.cuda.synchronize()
     assert torch.equal(out, ref)
     dn.close()
+
+
+def test_denoiser_save_and_load(env, tmp_path):
+    """pdf_denoiser_io: a trained denoiser written to a file and read into a
+    fresh one (another seed) gives the same parameters, the same network
+    outputs and the same denoised statistics and rejection count, bit for
+    bit; files of another width, truncated, carrying trailing bytes or
+    another tag are refused and leave the denoiser as it was."""
+    torch, L, ctx, w = env
+    rng = np.random.default_rng(11)
+    a = L.Denoiser(ctx, hidden=64, seed=5)
+    x = rng.normal(size=(2048, 48)).astype(np.float32)
+    t = rng.normal(size=(2048, 8)).astype(np.float32)
+    xt, tt = _tensors(torch, x, t)
+    for _ in range(3):
+        a.train_step(xt, tt, 1e-3)
+    a.set_norm(rng.normal(size=48).astype(np.float32), rng.uniform(0.5, 2.0, 48).astype(np.float32),
+               np.full(8, 1e-3, np.float32))
+    a.set_fallback(np.array([1.0, 2.0, 3.0, 4.0, 5.0, 6.0, 7.0, 8.0], np.float32))
+    path = tmp_path / "dn.bin"
+    a.save(path)
+    assert path.stat().st_size == 8 + 4 + 4 + 8 + 4 * (a.n_param + 48 + 48 + 8 + 8)
+    b = L.Denoiser(ctx, hidden=64, seed=6)
+    assert not np.array_equal(a.params(), b.params())
+    b.load(path)
+    assert np.array_equal(a.params(), b.params())
+    assert torch.equal(a.forward(xt), b.forward(xt))
+    oa, na = a.denoise(tau=1.0)
+    ob, nb = b.denoise(tau=1.0)
+    assert np.array_equal(oa, ob) and na == nb
+    # every field travelled: b written back out is the same file
+    b.save(tmp_path / "dn_again.bin")
+    assert (tmp_path / "dn_again.bin").read_bytes() == path.read_bytes()
+    # refused files leave the denoiser unchanged
+    keep = b.params()
+    c32 = L.Denoiser(ctx, hidden=32, seed=1)
+    p32 = tmp_path / "dn32.bin"
+    c32.save(p32)
+    raw = path.read_bytes()
+    bad = {"width": p32.read_bytes(), "short": raw[:-4], "long": raw + b"\0", "tag": b"x" + raw[1:]}
+    for name, data in bad.items():
+        f = tmp_path / f"bad_{name}.bin"
+        f.write_bytes(data)
+        with pytest.raises(L.PdfError) as ei:
+            b.load(f)
+        assert ei.value.status == 1, name
+        assert np.array_equal(b.params(), keep), name
+    with pytest.raises(L.PdfError):
+        b.load(tmp_path / "missing.bin")
+    for d in (a, b, c32):
+        d.close()
