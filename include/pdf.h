@@ -309,7 +309,9 @@ pdf_status pdf_num_particles(pdf_ctx *ctx, int64_t *n);
 pdf_status pdf_get_particles(pdf_ctx *ctx, double *state, int32_t *elem, uint32_t *id);
 
 /* Replace the particle state from host memory (same layout; n particles).
- * Values are rounded to the context precision.  Statistics are re-estimated. */
+ * Values are rounded to the context precision.  Statistics are re-estimated.
+ * PDF_E_INVALID_ARG for n < 1 (a context always holds particles once seeded)
+ * or an element index outside [0, n_elems); the state is then unchanged. */
 pdf_status pdf_set_particles(pdf_ctx *ctx, int64_t n, const double *state, const int32_t *elem,
                              const uint32_t *id);
 

@@ -79,6 +79,11 @@ def test_invalid_parameters_and_sizes(L):
     bad_elem[0] = w.mesh.n_elems
     st, msg = _status(L, lambda: ctx.set_particles(state, bad_elem, pid))
     assert st == 1 and "element" in msg
+    # an empty particle set is refused and the context keeps its particles
+    st, _ = _status(L, lambda: ctx.set_particles(state[:, :0], elem[:0], pid[:0]))
+    assert st == 1
+    assert ctx.num_particles() == elem.size
+    assert np.array_equal(ctx.particles()[0], state)
     st, _ = _status(L, lambda: L.Denoiser(ctx, hidden=40))
     assert st == 1
     ctx.close()
