@@ -786,11 +786,18 @@ __device__ __noinline__ double3 wall_function(const ModelDev &md, const double *
 }
 
 // Occupancy: the FP32 kernels are held to 3 waves per SIMD (at most 168
-// VGPRs; the LDS table of 3 copies, 48 KB, with the 4 KB geometry window lets
-// 3 workgroups share a CU), which hides more of the latency of the walk's
+// VGPRs; the LDS table of 3 copies, 48.5 KB, with the geometry window lets 3
+// workgroups share a CU), which hides more of the latency of the walk's
 // dependent loads than the 2 waves their unconstrained register count would
 // allow; the SHAPE kernel spills some registers for it and is still faster.
-constexpr int GWIN = 32;  // elements of the workgroup's geometry window (4 KB of LDS)
+// The window takes the rest of the LDS that three workgroups may hold: 53760
+// bytes each (measured on gfx950: a workgroup of 53888 bytes leaves room for
+// two only, and the kernel then runs 23 % slower).
+constexpr int GWIN = 41;  // elements of the workgroup's geometry window (5.1 KB of LDS)
+constexpr size_t LDS_3WG = 53760;
+static_assert(sizeof(SumTable) + GWIN * sizeof(WalkGeo) <= LDS_3WG &&
+                  sizeof(SumTableSparse) + GWIN * sizeof(WalkGeo) <= LDS_3WG,
+              "the particle kernel's LDS must leave room for three workgroups per CU");
 template <typename T, bool SHAPE>
 constexpr int advance_waves() { return sizeof(T) == 4 ? 3 : 1; }
 
