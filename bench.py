@@ -166,13 +166,15 @@ def denoise_study(mode, out_path=""):
       bench     the default line's bounded study: the street-canyon mesh
                 (~200k triangles), statistics fed back with the particle
                 redistribution keeping 3 per element, 10 vs 200 particles per
-                element, 16 training pairs, 4 held-out sources x 4 reference
-                runs
+                element, 16 training pairs, 16000 Adam steps, 4 held-out
+                sources x 4 reference runs, plain runs at 20, 40, 80 and 160
+                per element
       full      the same with 64 training pairs (4 x 4 = 16 held-out runs)
       quick     a 20k-triangle canyon, for tests
       c5        the 1M-triangle channel with a floor block, 10 vs 100 per
                 element, fed back with redistribution, the scalar line at a
-                different x in each run
+                different x in each run; 32 training pairs, 16000 Adam
+                steps, plain runs at 20, 40, 80, 160, 200 and 240 per element
     A '-frozen' suffix freezes the model coefficients instead of feeding the
     statistics back."""
     import numpy as np
@@ -186,8 +188,9 @@ def denoise_study(mode, out_path=""):
     base = dict(frozen=frozen, min_ppe=0 if frozen else 3)
     if mode == "c5":
         mesh = M.channel_block(1_000_000, 0.15, 0)
-        kw = dict(n_train=16, n_test=3, n_ref=3, steps_spin=100, n_snap=5, every=10, train_steps=4000,
-                  batch=8192, ppe_low=10, ppe_high=100, eval_ppes=(20, 40), source_box=(1.0, 4.0, 0.5, 1.5, 0.05))
+        kw = dict(n_train=32, n_test=3, n_ref=3, steps_spin=100, n_snap=5, every=10, train_steps=16000,
+                  batch=8192, ppe_low=10, ppe_high=100, eval_ppes=(20, 40, 80, 160, 200, 240),
+                  source_box=(1.0, 4.0, 0.5, 1.5, 0.05))
 
         def make(ppe, seed, src):
             w = CF.channel_block(mesh=mesh, ppe=ppe, seed=seed)
@@ -201,7 +204,7 @@ def denoise_study(mode, out_path=""):
         else:
             mesh = M.canyon(200_000, 0.15, 0)
             kw = dict(n_train=64 if mode == "full" else 16, n_test=4, n_ref=4, steps_spin=100, n_snap=5,
-                      every=10, train_steps=4000, batch=8192, eval_ppes=(20, 40, 80))
+                      every=10, train_steps=16000, batch=8192, eval_ppes=(20, 40, 80, 160))
 
         def make(ppe, seed, src):
             return CF.canyon(mesh=mesh, ppe=ppe, seed=seed, src=src)
