@@ -242,7 +242,10 @@ typedef struct pdf_seed_desc {
  * elements of their gradients as a sum over its ring (formed on the device;
  * PDF_E_DEVICE if that fails).  precision is PDF_FP64 or PDF_FP32;
  * hip_stream is a hipStream_t (NULL: the null stream); alloc may be NULL.
- * On success *out owns all device memory until pdf_destroy. */
+ * On success *out owns all device memory until pdf_destroy.  On failure *out
+ * is NULL when no context was formed (invalid arguments, no current device);
+ * otherwise it holds the failed context so that pdf_last_error gives the
+ * reason, and the caller destroys it. */
 pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *params,
                          int32_t precision, const pdf_allocator *alloc, void *hip_stream,
                          pdf_ctx **out);

@@ -1015,7 +1015,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   if (!ok || !c->stats_a || !c->stats_b || !c->wp || !c->gradp || !c->rec || !c->sums || !c->emom ||
       !c->offs || !c->cursor || !c->blocksums || !c->cnt || !c->cfl) {
     c->err = "device allocation or upload failed";
-    pdf_destroy(c);
+    *out = c;  // the caller reads the message, then destroys
     return PDF_E_OOM;
   }
   c->stats_cur = c->stats_a;
@@ -1032,7 +1032,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
       hipMemsetAsync(gw_bad, 0, sizeof(unsigned long long), s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
     c->err = "device initialisation failed";
-    pdf_destroy(c);
+    *out = c;  // the caller reads the message, then destroys
     return PDF_E_DEVICE;
   }
   {  // the gradient weights over the rings
@@ -1042,7 +1042,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
         hipMemcpyAsync(&bad, gw_bad, sizeof(bad), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess || bad) {
       c->err = bad ? "mesh set-up: an element node outside its master's ring" : "mesh set-up: gradient weights failed";
-      pdf_destroy(c);
+      *out = c;  // the caller reads the message, then destroys
       return PDF_E_DEVICE;
     }
   }
@@ -1083,14 +1083,14 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   if (params->model == PDF_MODEL_GLM && params->wp_source == PDF_WP_ELLIPTIC) {
     const pdf_status es = ell_setup(c, mesh);
     if (es != PDF_OK) {
-      pdf_destroy(c);
+      *out = c;  // the caller reads the message, then destroys
       return es;
     }
   }
   if (params->proj) {
     const pdf_status ps = proj_setup(c, mesh);
     if (ps != PDF_OK) {
-      pdf_destroy(c);
+      *out = c;  // the caller reads the message, then destroys
       return ps;
     }
   }
@@ -1101,7 +1101,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   if (!c->dka || hipMemcpyAsync(c->dka, &hka, sizeof(KArgs), hipMemcpyHostToDevice, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
     c->err = "device allocation or upload failed";
-    pdf_destroy(c);
+    *out = c;  // the caller reads the message, then destroys
     return PDF_E_OOM;
   }
   *out = c;
