@@ -82,6 +82,12 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
                           "(run __graft_entry__.build() or python -m paper_1006_0720_amd.build)")
+    # torch first: it loads the HIP runtime it ships, and the library then
+    # binds to that same runtime, the one that owns the memory and streams it
+    # is handed.  Loaded first, the library would pull in the system runtime
+    # under a name torch's own libraries do not match, torch would load its
+    # copy beside it, and the library's first HIP call would fail.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     sig = {

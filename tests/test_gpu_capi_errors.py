@@ -141,3 +141,22 @@ def test_zero_mean_frequency(L):
     assert np.array_equal(el, o.elem) and np.all(np.isfinite(st)) and np.all(st[5] == 0.0)
     compare_state(st, o.state, w.mesh, 1e-12, "zero frequency", elem=o.elem)
     ctx.close()
+
+
+def test_context_as_the_first_gpu_action_of_a_process(L):
+    """A fresh process whose first GPU action is creating a context (the
+    binding imported before torch has touched the GPU): the library must
+    share torch's HIP runtime, or its first HIP call fails."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("from paper_1006_0720_amd.runner import workload_context\n"
+            "from synth import configs as CF\n"
+            "ctx = workload_context(CF.periodic_square(n=4, ppe=2))\n"
+            "print('particles', ctx.num_particles())\n"
+            "ctx.close()\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=180)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "particles 64" in r.stdout
