@@ -8,7 +8,12 @@ derivatives (plus the periodic reorder).  Inputs are resident in HBM before the
 timed region; the timed region is exactly K calls' worth of steps bracketed by
 device synchronisation.
 
-Prints one JSON line (see the design doc for the roofline accounting).
+Prints one JSON line.  Its roofline object prices the dominant kernel,
+k_advance: algorithmic bytes per launch (68 B per particle and 384 B per
+element in FP32) over the launch time measured with HIP events on the
+context's stream, against the 8 TB/s HBM peak, with the HBM traffic of the
+committed rocprofv3 counters when the kernel source and configuration match
+the ones they were taken at.
 """
 from __future__ import annotations
 
@@ -268,8 +273,8 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the particle hot path is built and measured on a "
-              "single MI355X; multi-GPU sharding (spatial domain decomposition) is described in "
-              "DESIGN.md but not built.", file=sys.stderr)
+              "single MI355X; multi-GPU sharding (spatial domain decomposition) is not built.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

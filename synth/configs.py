@@ -7,8 +7,8 @@ the elliptic-relaxation tensor), a time step and a step count.  These are
 inputs only: no step of the particle method is computed here.
 
 Model constants are those of the paper's constant tables (Ch.4 tab:fd-constants,
-Ch.5 tab:constants); the workload-specific values follow the benchmark
-definitions restated in the design doc.
+Ch.5 tab:constants); the workload-specific values (meshes, particle counts,
+time steps, sources) are stated in each workload's constructor below.
 """
 from __future__ import annotations
 
