@@ -196,9 +196,9 @@ typedef struct pdf_mesh_desc {
  *                V-cycle of a plain-aggregation multigrid hierarchy (aggregates built once by
  *                pdf_init_mesh from the stiffness matrix over the free master nodes; every
  *                solve sums the matrix entries over pairs of aggregates for the coarser
- *                levels, one l1-Jacobi step before and after each coarse correction, 8
- *                l1-Jacobi sweeps on the last level of at most 128 rows; PDF_E_NUMERIC if it
- *                cannot be built)
+ *                levels, one Jacobi step on the diagonal a_ii + (1/2) sum_{j!=i} |a_ij|
+ *                before and after each coarse correction, 8 such sweeps on the last level
+ *                of at most 128 rows; PDF_E_NUMERIC if it cannot be built)
  *   Cp           stabilization constant of eq:pressure-projection-smooth (the paper: 1e-3)
  *   nu_wall      kinematic viscosity of the log law eq:Ue at PDF_BC_WALLFN edges (> 0 when
  *                the mesh has such edges).  A particle reflected at such an edge gets the

@@ -9,8 +9,9 @@
 // the matrix of every solve: level 0 copies the free-free block of M + L2 K,
 // each coarser level sums the finer entries over pairs of aggregates (the
 // Galerkin product with the tentative prolongator), and every level smooths
-// with one l1-Jacobi step before and after the coarse correction; the last
-// level takes a fixed number of l1-Jacobi sweeps.  The V-cycle is a fixed
+// with one Jacobi step before and after the coarse correction, its diagonal
+// the l1 row sum with the off-diagonal part halved (k_mg_dinv); the last
+// level takes a fixed number of such sweeps.  The V-cycle is a fixed
 // symmetric positive definite operator, so the iteration stays a conjugate-
 // gradient method and converges to the same solution, in several times fewer
 // iterations on graded meshes.
@@ -367,20 +368,34 @@ __global__ __launch_bounds__(NB) void k_mg_vals(int32_t nnzc, const int32_t *g_o
   vc[J] = s;
 }
 
-// inverse l1 row sums per class (the l1-Jacobi smoother: convergent for any
-// symmetric positive definite matrix, no spectral estimate needed)
-__global__ __launch_bounds__(NB) void k_mg_dinv(int32_t n, const int32_t *off, const double4 *val, double4 *dinv) {
+// the smoother's diagonal per class: d_i = a_ii + (1/2) sum_{j != i} |a_ij|
+// (l1-Jacobi with the off-diagonal sum halved).  For a symmetric matrix with
+// a positive diagonal, 2 D - A then has the diagonal a_ii + sum_{j != i}
+// |a_ij| and is diagonally dominant, so the smoothing step converges in the
+// energy norm and the V-cycle stays symmetric positive definite, with no
+// spectral estimate; with the full l1 sum (weight 1 instead of 1/2) the
+// step is damped more and the conjugate gradients take 12-16 % more
+// iterations (23.8 against 20.6 per solve on the 1M-triangle graded channel,
+// 27 against 24 on a 5913-node channel).  A row without a positive diagonal
+// entry keeps the full l1 sum.
+__device__ __forceinline__ double half_l1(double diag, double l1) {
+  return diag > 0.0 ? 0.5 * (diag + l1) : l1;
+}
+__global__ __launch_bounds__(NB) void k_mg_dinv(int32_t n, const int32_t *off, const int32_t *col, const double4 *val,
+                                                double4 *dinv) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
+  double4 s = make_double4(0.0, 0.0, 0.0, 0.0), dg = make_double4(0.0, 0.0, 0.0, 0.0);
   for (int32_t j = off[i]; j < off[i + 1]; ++j) {
     const double4 v = val[j];
     s.x += fabs(v.x);
     s.y += fabs(v.y);
     s.z += fabs(v.z);
     s.w += fabs(v.w);
+    if (col[j] == i) dg = v;
   }
-  dinv[i] = make_double4(1.0 / s.x, 1.0 / s.y, 1.0 / s.z, 1.0 / s.w);
+  dinv[i] = make_double4(1.0 / half_l1(dg.x, s.x), 1.0 / half_l1(dg.y, s.y), 1.0 / half_l1(dg.z, s.z),
+                         1.0 / half_l1(dg.w, s.w));
 }
 
 // the pre-smoothing step from zero folded into the residual: r = b - A (D^-1 b)
@@ -436,7 +451,7 @@ __global__ __launch_bounds__(NB) void k_mg_restrict(int32_t nc, const int32_t *m
 }
 
 
-// the last level: `sweeps` l1-Jacobi sweeps from zero, in one workgroup,
+// the last level: `sweeps` smoothing sweeps from zero, in one workgroup,
 // the iterate in LDS (n <= ELL_COARSE_MAX)
 constexpr int NBC = 1024;
 constexpr int CQ = (9 * ELL_COARSE_MAX + NBC - 1) / NBC;
@@ -619,7 +634,7 @@ void mg_apply(hipStream_t s, const EllMg &g, const double *r, double *z, double 
     hipLaunchKernelGGL(k_c_post0, dim3(gpost), dim3(NB9), 0, s, L0.n, L0.off, L0.col, L0.val, L0.dinv, L0.agg,
                        (const double *)C.y, r, z, dot, stop);
   } else {
-    // a single level: two l1-Jacobi steps from zero
+    // a single level: two smoothing steps from zero
     hipLaunchKernelGGL(k_c_post0, dim3(gpost), dim3(NB9), 0, s, L0.n, L0.off, L0.col, L0.val, L0.dinv,
                        (const int32_t *)nullptr, (const double *)nullptr, r, z, dot, stop);
   }
@@ -636,7 +651,7 @@ void mg_values(hipStream_t s, const EllMg &g, const double4 *av) {
       hipLaunchKernelGGL(k_mg_vals, dim3((C.nnz + NB - 1) / NB), dim3(NB), 0, s, C.nnz, L.g_off, L.g_idx, L.val,
                          C.val);
     }
-    hipLaunchKernelGGL(k_mg_dinv, dim3((L.n + NB - 1) / NB), dim3(NB), 0, s, L.n, L.off, L.val, L.dinv);
+    hipLaunchKernelGGL(k_mg_dinv, dim3((L.n + NB - 1) / NB), dim3(NB), 0, s, L.n, L.off, L.col, L.val, L.dinv);
   }
 }
 

@@ -48,7 +48,7 @@ constexpr int32_t ELL_COARSE_MAX = 128;  // rows of the last level (its sweeps r
 struct EllMgLevel {
   int32_t n = 0, nnz = 0;
   const int32_t *off = nullptr, *col = nullptr;
-  double4 *val = nullptr, *dinv = nullptr;  // values; inverse l1 row sums per class
+  double4 *val = nullptr, *dinv = nullptr;  // values; inverse smoother diagonal per class
   double *b = nullptr, *x = nullptr, *r = nullptr, *y = nullptr;  // [n][9]
   const int32_t *agg = nullptr, *m_off = nullptr, *mem = nullptr, *g_off = nullptr, *g_idx = nullptr;
 };
@@ -58,7 +58,7 @@ struct EllMgLevel {
 // values are the full matrix's entries g0 of every solve.
 struct EllMg {
   int nl = 0;  // 0: Jacobi preconditioning
-  int sweeps = 8;  // l1-Jacobi sweeps on the last level
+  int sweeps = 8;  // smoothing sweeps on the last level
   const int32_t *fidx = nullptr, *g0 = nullptr;
   double *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr, *cb = nullptr;
   EllMgLevel lv[ELL_MAXL];
