@@ -619,10 +619,10 @@ __device__ __forceinline__ void table_flush(SumTableW &t, double *nsums) {
 // scatter of one particle at (x, y) in element e to the element's three nodes
 template <typename T>
 __device__ __forceinline__ void scatter_shape(SumTableW &t, const MeshDev &m, double *nsums, const T *rec,
-                                              int32_t e, double x, double y, T u, T v, T w, T om, T psi) {
-  const WalkGeo g = ldg(m.wgeo, e);
-  double lam[3], wt[3];
-  edge_lambdas(g, x, y, lam);
+                                              int32_t e, double x, double y, T u, T v, T w, T om, T psi,
+                                              double l0 = -1.0, double l1 = 0.0, double l2 = 0.0) {
+  double lam[3] = {l0, l1, l2}, wt[3];
+  if (l0 < 0.0) edge_lambdas(ldg(m.wgeo, e), x, y, lam);
   shape_w(lam, wt);
   const T *rs = rec + (size_t)e * NRECS;
 #pragma unroll
@@ -956,6 +956,7 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
     int32_t e = e0, found = -1, nrefl = 0;
     int32_t fwb = 0, fwn = -1;  // wall segments near the host found by the walk
     double shx = 0.0, shy = 0.0;
+    double lf0 = -1.0, lf1 = 0.0, lf2 = 0.0;  // SHAPE: the host's area coordinates from the walk
     // a non-finite position cannot be located: the particle is lost at once
     const bool finite_pos = isfinite(x) && isfinite(y);
     for (int it = 0; it < 64 && finite_pos; ++it) {
@@ -967,6 +968,11 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
         found = e;
         fwb = g.wb;
         fwn = g.wn;
+        if constexpr (SHAPE) {
+          lf0 = lam[0];
+          lf1 = lam[1];
+          lf2 = lam[2];
+        }
         break;
       }
       int k = 0;
@@ -1134,7 +1140,7 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
     p.psi[i] = psin;
     p.e[i] = found;
     if constexpr (SHAPE)
-      scatter_shape<T>(tab, m, sums, rec, found, x, y, un0, un1, un2, omn, psin);
+      scatter_shape<T>(tab, m, sums, rec, found, x, y, un0, un1, un2, omn, psin, lf0, lf1, lf2);
     else {
       // reloaded rather than kept from the start of the step: holding them
       // across the walk costs register spills
