@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "liboracle.so")
 NSTAT = 25
 CNT_NAMES = ["walk_steps", "fallback", "brute", "lost", "reflect", "periodic", "noslip_b",
-             "omega_clamp", "gamma_fail", "empty_node", "redist"]
+             "omega_clamp", "gamma_fail", "empty_node", "redist", "outflow"]
 
 
 def build(force=False):
@@ -83,13 +83,13 @@ class _Params(C.Structure):
                                          "cond_nu", "cond_nv", "cond_nw", "cond_min")] + \
                [(n, C.c_double) for n in ("C0", "C1", "C2", "C3", "C4", "CT", "CL", "Ceta", "Cv",
                                           "gamma5", "Cw1", "Cw2", "Cphi", "nu", "k_floor",
-                                          "src_x", "src_y", "src_r", "Cs", "Ct", "nu_wall")]
+                                          "src_x", "src_y", "src_r", "Cs", "Ct", "nu_wall", "inflow_u")]
 
 
 # parameters that older parameter sets may lack: IEM, 5x5x5 bins, at least 2
 # particles per subgroup, the constants of tab:constants
 _DEFAULTS = dict(stats_mode=0, min_ppe=0, mix_model=0, cond_nu=5, cond_nv=5, cond_nw=5, cond_min=2,
-                 Cs=0.02, Ct=0.7, nu_wall=0.0)
+                 Cs=0.02, Ct=0.7, nu_wall=0.0, inflow_u=0.0)
 
 
 class _Seed(C.Structure):

@@ -244,7 +244,7 @@ or_mesh *or_mesh_new(int32_t nn, int32_t ne, int32_t nb, const double *xy, const
   /* node -> wall edges (slip and no-slip) ending at the node, ascending */
   m->nwall_off = (int32_t *)calloc((size_t)nn + 1, sizeof(int32_t));
   for (int32_t b = 0; b < nb; ++b) {
-    if (bt[b] == OR_BC_PERIODIC) continue;
+    if (bt[b] == OR_BC_PERIODIC || bt[b] == OR_BC_OUTFLOW) continue;
     int32_t e = be[b], k = bl[b];
     m->nwall_off[en[3 * e + (k + 1) % 3] + 1]++;
     m->nwall_off[en[3 * e + (k + 2) % 3] + 1]++;
@@ -253,7 +253,7 @@ or_mesh *or_mesh_new(int32_t nn, int32_t ne, int32_t nb, const double *xy, const
   m->nwall = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m->nwall_off[nn] + 1));
   fill = (int32_t *)dup(m->nwall_off, sizeof(int32_t) * (size_t)nn);
   for (int32_t b = 0; b < nb; ++b) {
-    if (bt[b] == OR_BC_PERIODIC) continue;
+    if (bt[b] == OR_BC_PERIODIC || bt[b] == OR_BC_OUTFLOW) continue;
     int32_t e = be[b], k = bl[b];
     m->nwall[fill[en[3 * e + (k + 1) % 3]]++] = b;
     m->nwall[fill[en[3 * e + (k + 2) % 3]]++] = b;
@@ -1080,6 +1080,7 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
     double psin = psi - dt * r->inv_tm * (psi - (cm ? cm[i] : r->Phi));
     /* tracking: next best element walk with boundary conditions */
     int32_t e = e0, found = -1, nrefl = 0;
+    int reloc = 0; /* left through an outflow edge */
     double shx = 0.0, shy = 0.0;
     /* a non-finite position cannot be located: the particle is lost at once */
     int finite_pos = isfinite(x) && isfinite(y);
@@ -1100,13 +1101,18 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
         continue;
       }
       int32_t b = -(nb + 1);
-      if (m->bt[b] == OR_BC_PERIODIC) {
+      if (m->bt[b] == OR_BC_PERIODIC || m->bt[b] == OR_BC_OUTFLOW) {
         x = st(p, x + m->bs[2 * b]);
         y = st(p, y + m->bs[2 * b + 1]);
         shx += m->bs[2 * b];
         shy += m->bs[2 * b + 1];
         e = m->be[m->bp[b]];
-        if (cnt) cnt[OR_CNT_PERIODIC]++;
+        if (m->bt[b] == OR_BC_OUTFLOW) {
+          reloc = 1;
+          if (cnt) cnt[OR_CNT_OUTFLOW]++;
+        } else if (cnt) {
+          cnt[OR_CNT_PERIODIC]++;
+        }
         continue;
       }
       double xa, ya, xb, yb;
@@ -1193,6 +1199,12 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
         y = y0;
         found = e0;
       }
+    }
+    /* relocated at the inflow: the velocity of the incoming flow */
+    if (reloc) {
+      un[0] = p->inflow_u;
+      un[1] = 0.0;
+      un[2] = 0.0;
     }
     /* no-slip trajectory (b): eq:fw and eq:exp-wall-condition */
     if (p->wall_b && p->nu > 0.0 && nrefl == 0) {

@@ -22,6 +22,13 @@
 #define OR_BC_SLIP 2
 #define OR_BC_NOSLIP 3
 #define OR_BC_WALLFN 4 /* wall treated by the wall functions of eq:wall-normal-velocity to eq:wall-omega */
+/* outflow edge, paired with an inflow edge (of type OR_BC_PERIODIC): a
+ * particle leaving through it is relocated at the inflow with its
+ * cross-stream position kept (the pair's translation) and its velocity set to
+ * (inflow_u, 0, 0) (Ch.6, cylinder flow, Sec. Results: its boundary
+ * conditions); the other properties are kept.  Leaving through the inflow
+ * edge is periodic. */
+#define OR_BC_OUTFLOW 5
 
 typedef struct or_params {
   int32_t model;        /* 0 = simplified Langevin (eq:wall-GandC), 1 = generalized Langevin (eq:GandC) */
@@ -43,6 +50,7 @@ typedef struct or_params {
   double src_x, src_y, src_r;
   double Cs, Ct;        /* constants of eq:micromixing-timescale-canyon */
   double nu_wall;       /* kinematic viscosity of the log law eq:Ue (wall-function walls) */
+  double inflow_u;      /* streamwise velocity given to particles relocated at the inflow */
 } or_params;
 
 typedef struct or_seedspec {
@@ -60,7 +68,7 @@ typedef struct or_mesh or_mesh;
 /* counters (index) */
 enum { OR_CNT_WALK_STEPS = 0, OR_CNT_FALLBACK, OR_CNT_BRUTE, OR_CNT_LOST, OR_CNT_REFLECT,
        OR_CNT_PERIODIC, OR_CNT_NOSLIP_B, OR_CNT_OMEGA_CLAMP, OR_CNT_GAMMA_FAIL, OR_CNT_EMPTY_NODE,
-       OR_CNT_REDIST, OR_CNT_N };
+       OR_CNT_REDIST, OR_CNT_OUTFLOW, OR_CNT_N };
 
 #ifdef __cplusplus
 extern "C" {

@@ -83,14 +83,14 @@ def node_gradient(mesh, f):
     return out[:, mesh.node_master]
 
 
-BC_PERIODIC, BC_WALLFN = 1, 4
+BC_PERIODIC, BC_WALLFN, BC_OUTFLOW = 1, 4, 5
 
 
 def wall_edges(mesh):
-    """Every non-periodic boundary edge: its end nodes a, b (local nodes k+1
+    """Every wall edge (not periodic, not outflow): its end nodes a, b (local nodes k+1
     and k+2 of its element, so the domain lies on its left), its element, its
     outward unit normal and its length, as arrays."""
-    keep = np.flatnonzero(mesh.bedge_type != BC_PERIODIC)
+    keep = np.flatnonzero((mesh.bedge_type != BC_PERIODIC) & (mesh.bedge_type != BC_OUTFLOW))
     e = mesh.bedge_elem[keep]
     k = mesh.bedge_local[keep]
     a = mesh.elem_nodes[e, (k + 1) % 3]

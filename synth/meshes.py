@@ -23,6 +23,7 @@ BC_PERIODIC = 1
 BC_SLIP = 2
 BC_NOSLIP = 3
 BC_WALLFN = 4   # wall treated by wall functions
+BC_OUTFLOW = 5  # outflow edge paired with a periodic (inflow) edge: particles leaving are relocated
 
 
 @dataclass
@@ -429,3 +430,24 @@ def box(nx=16, ny=16, Lx=1.0, Ly=1.0, jitter=0.0, seed=0, bc=BC_SLIP, diag="same
     return _finish(xy, quads, used, rng, jitter, diag, fixed,
                    lambda m, nrm: np.full(m.shape[0], bc, np.int32), (0.0, 0.0),
                    f"box_{nx}x{ny}", {"Lx": Lx, "Ly": Ly})
+
+
+def with_outflow(mesh):
+    """A copy of a streamwise-periodic mesh whose periodic edges at the
+    largest x become outflow edges: particles leaving there are relocated at
+    the inflow (the edges at the smallest x, which stay periodic, so that
+    leaving upstream is periodic) with a reset velocity.  The nodes stay
+    identified across the pair."""
+    from dataclasses import replace
+
+    bt = mesh.bedge_type.copy()
+    e, k = mesh.bedge_elem, mesh.bedge_local
+    a = mesh.elem_nodes[e, (k + 1) % 3]
+    b = mesh.elem_nodes[e, (k + 2) % 3]
+    mid_x = 0.5 * (mesh.node_xy[a, 0] + mesh.node_xy[b, 0])
+    xmax = mesh.node_xy[:, 0].max()
+    hi = (bt == BC_PERIODIC) & (np.abs(mid_x - xmax) < 1e-9 * max(1.0, abs(xmax)))
+    assert hi.any() and (bt[mesh.bedge_partner[hi]] == BC_PERIODIC).all()
+    bt[hi] = BC_OUTFLOW
+    return replace(mesh, bedge_type=bt, name=mesh.name + "_outflow")
+
