@@ -235,7 +235,16 @@ class Oracle:
         self.estimate()
         return self
 
+    def _c_layout(self):
+        # the C routines take raw pointers to [7][n] state and [n] arrays:
+        # arrays handed in from elsewhere (an id-sorted copy, say, which numpy
+        # lays out column-major) are brought to that layout first
+        self.state = np.ascontiguousarray(self.state, np.float64)
+        self.elem = np.ascontiguousarray(self.elem, np.int32)
+        self.id = np.ascontiguousarray(self.id, np.uint32)
+
     def estimate(self, into_stats=True):
+        self._c_layout()
         m = self.mesh
         out = np.zeros((NSTAT, m.n_nodes))
         el = np.zeros((16, m.n_elems))
@@ -263,6 +272,7 @@ class Oracle:
     def step(self, dt, mask=None):
         """One step: element records from the current nodal statistics, advance,
         then re-estimate (fed back unless params['frozen'])."""
+        self._c_layout()
         m = self.mesh
         st = np.ascontiguousarray(self.stats)
         if self.params["model"] == 1:
@@ -324,6 +334,7 @@ class Oracle:
 
     def cond_means(self):
         """<phi|V> of every particle from the current state (App. B binning)."""
+        self._c_layout()
         cm = np.empty(self.state.shape[1])
         st = np.ascontiguousarray(self.state, np.float64)
         lib().or_cond_means(self.om.h, C.byref(self.cp), st.shape[1], _p(st, C.c_double),
