@@ -51,7 +51,16 @@ typedef enum pdf_status {
 } pdf_status;
 
 enum { PDF_FP64 = 0, PDF_FP32 = 1 };                          /* particle-state precision */
-enum { PDF_BC_PERIODIC = 1, PDF_BC_SLIP = 2, PDF_BC_NOSLIP = 3, PDF_BC_WALLFN = 4 }; /* boundary-edge types */
+/* boundary-edge types.  PDF_BC_OUTFLOW: an outflow edge paired (bedge_partner,
+ * bedge_shift) with an inflow edge of type PDF_BC_PERIODIC; a particle leaving
+ * through it is relocated at the inflow with its cross-stream position kept
+ * (the pair's translation) and its velocity set to (inflow_u, 0, 0) (Ch.6,
+ * cylinder flow, Sec. Results: its boundary conditions) as it crosses, so
+ * that a wall condition later in the same step's walk acts on that velocity;
+ * its frequency and scalar are kept, and leaving through the inflow edge is
+ * periodic.  The
+ * nodes of the pair stay identified through node_master. */
+enum { PDF_BC_PERIODIC = 1, PDF_BC_SLIP = 2, PDF_BC_NOSLIP = 3, PDF_BC_WALLFN = 4, PDF_BC_OUTFLOW = 5 };
 enum { PDF_MODEL_SLM = 0, PDF_MODEL_GLM = 1 };                /* eq:wall-GandC / eq:GandC */
 enum { PDF_WP_INPUT = 0, PDF_WP_LOCAL = 1, PDF_WP_ELLIPTIC = 2 };                  /* source of the tensor wp_ij (GLM) */
 enum { PDF_TM_CPHI = 0, PDF_TM_KEPS = 1, PDF_TM_SOURCE = 2 }; /* micromixing time scale */
@@ -72,7 +81,8 @@ enum {
   PDF_CNT_GAMMA_FAIL = 8, PDF_CNT_EMPTY_NODE = 9, PDF_CNT_NONFINITE = 10, PDF_CNT_STEPS = 11,
   PDF_CNT_REDIST = 12, /* particles moved by the redistribution */
   PDF_CNT_ELL_ITERS = 13, /* conjugate-gradient iterations of the elliptic relaxation */
-  PDF_CNT_PROJ_ITERS = 14 /* conjugate-gradient iterations of the pressure projection */
+  PDF_CNT_PROJ_ITERS = 14, /* conjugate-gradient iterations of the pressure projection */
+  PDF_CNT_OUTFLOW = 15     /* particles relocated at the inflow (PDF_BC_OUTFLOW) */
 };
 
 /* Device allocator hook.  alloc returns device memory of at least `bytes`
@@ -219,6 +229,7 @@ typedef struct pdf_model_params {
   int32_t ell_precond;
   double C0, C1, C2, C3, C4, CT, CL, Ceta, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
   double src_x, src_y, src_r, Cs, Ct, nu_wall, ell_tol, Cp, proj_tol;
+  double inflow_u;  /* streamwise velocity of particles relocated at the inflow (PDF_BC_OUTFLOW) */
 } pdf_model_params;
 
 /* Initial particle population (Ch.3, Sec. Particle-number control): ppe

@@ -1080,7 +1080,6 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
     double psin = psi - dt * r->inv_tm * (psi - (cm ? cm[i] : r->Phi));
     /* tracking: next best element walk with boundary conditions */
     int32_t e = e0, found = -1, nrefl = 0;
-    int reloc = 0; /* left through an outflow edge */
     double shx = 0.0, shy = 0.0;
     /* a non-finite position cannot be located: the particle is lost at once */
     int finite_pos = isfinite(x) && isfinite(y);
@@ -1108,7 +1107,11 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
         shy += m->bs[2 * b + 1];
         e = m->be[m->bp[b]];
         if (m->bt[b] == OR_BC_OUTFLOW) {
-          reloc = 1;
+          /* relocated at the inflow with the velocity of the incoming flow;
+           * a later wall condition of the same walk acts on it */
+          un[0] = p->inflow_u;
+          un[1] = 0.0;
+          un[2] = 0.0;
           if (cnt) cnt[OR_CNT_OUTFLOW]++;
         } else if (cnt) {
           cnt[OR_CNT_PERIODIC]++;
@@ -1199,12 +1202,6 @@ int32_t or_step(const or_mesh *m, const or_params *p, const double *stats, const
         y = y0;
         found = e0;
       }
-    }
-    /* relocated at the inflow: the velocity of the incoming flow */
-    if (reloc) {
-      un[0] = p->inflow_u;
-      un[1] = 0.0;
-      un[2] = 0.0;
     }
     /* no-slip trajectory (b): eq:fw and eq:exp-wall-condition */
     if (p->wall_b && p->nu > 0.0 && nrefl == 0) {

@@ -26,8 +26,9 @@
  * particle leaving through it is relocated at the inflow with its
  * cross-stream position kept (the pair's translation) and its velocity set to
  * (inflow_u, 0, 0) (Ch.6, cylinder flow, Sec. Results: its boundary
- * conditions); the other properties are kept.  Leaving through the inflow
- * edge is periodic. */
+ * conditions) when it crosses, so that a wall condition later in the same
+ * walk acts on that velocity; the other properties are kept.  Leaving through
+ * the inflow edge is periodic. */
 #define OR_BC_OUTFLOW 5
 
 typedef struct or_params {

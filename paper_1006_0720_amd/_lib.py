@@ -24,7 +24,7 @@ NELEMSTAT = 16
 NCOUNTERS = 16
 COUNTER_NAMES = ["walk_steps", "fallback", "brute", "lost", "reflect", "periodic", "noslip_b",
                  "omega_clamp", "gamma_fail", "empty_node", "nonfinite", "steps", "redist", "ell_iters",
-                 "proj_iters"]
+                 "proj_iters", "outflow"]
 STATUS = {0: "PDF_OK", 1: "PDF_E_INVALID_ARG", 2: "PDF_E_BAD_MESH", 3: "PDF_E_OOM",
           4: "PDF_E_DEVICE", 5: "PDF_E_STATE", 6: "PDF_E_LOST_PARTICLE", 7: "PDF_E_NUMERIC"}
 
@@ -51,7 +51,7 @@ class ModelParams(C.Structure):
                [(n, C.c_double) for n in ("C0", "C1", "C2", "C3", "C4", "CT", "CL", "Ceta", "Cv",
                                           "gamma5", "Cw1", "Cw2", "Cphi", "nu", "k_floor",
                                           "src_x", "src_y", "src_r", "Cs", "Ct", "nu_wall", "ell_tol", "Cp",
-                                          "proj_tol")]
+                                          "proj_tol", "inflow_u")]
 
 
 # fields a parameter set may omit: ELEM statistics, no redistribution, IEM,
@@ -61,7 +61,7 @@ class ModelParams(C.Structure):
 # and the multigrid preconditioners of the projection and the elliptic relaxation
 PARAM_DEFAULTS = dict(stats_mode=0, min_ppe=0, mix_model=0, cond_nu=5, cond_nv=5, cond_nw=5,
                       cond_min=2, Cs=0.02, Ct=0.7, nu_wall=0.0, ell_maxit=500, ell_tol=1e-12, proj=0,
-                      proj_maxit=2000, proj_precond=1, ell_precond=1, Cp=1e-3, proj_tol=1e-12)
+                      proj_maxit=2000, proj_precond=1, ell_precond=1, Cp=1e-3, proj_tol=1e-12, inflow_u=0.0)
 
 
 class SeedDesc(C.Structure):

@@ -330,7 +330,7 @@ pdf_status proj_setup(pdf_ctx *c, const pdf_mesh_desc *mesh) {
     std::vector<int4> we;
     std::vector<double4> wg;
     for (int32_t bi = 0; bi < mesh->n_bedges; ++bi) {
-      if (mesh->bedge_type[bi] == PDF_BC_PERIODIC) continue;
+      if (mesh->bedge_type[bi] == PDF_BC_PERIODIC || mesh->bedge_type[bi] == PDF_BC_OUTFLOW) continue;
       const int32_t e = mesh->bedge_elem[bi], k = mesh->bedge_local[bi];
       const int32_t na = en[3 * e + (k + 1) % 3], nb = en[3 * e + (k + 2) % 3];
       const double dx = xy[2 * nb] - xy[2 * na], dy = xy[2 * nb + 1] - xy[2 * na + 1];
@@ -704,6 +704,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   // need the viscosity of the log law
   bool has_wallfn = false;
   for (int32_t b = 0; b < mesh->n_bedges; ++b) has_wallfn |= mesh->bedge_type[b] == PDF_BC_WALLFN;
+  if (!std::isfinite(params->inflow_u)) return PDF_E_INVALID_ARG;
   if (has_wallfn && (params->nu != 0.0 || !(params->nu_wall > 0.0) || !std::isfinite(params->nu_wall)))
     return PDF_E_INVALID_ARG;
   if (params->mix_model != PDF_MIX_IEM && params->mix_model != PDF_MIX_IECM) return PDF_E_INVALID_ARG;
@@ -786,14 +787,18 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
     }
   for (int32_t b = 0; b < nb; ++b) {
     const int32_t t = mesh->bedge_type[b];
-    if (t != PDF_BC_PERIODIC && t != PDF_BC_SLIP && t != PDF_BC_NOSLIP && t != PDF_BC_WALLFN)
+    if (t != PDF_BC_PERIODIC && t != PDF_BC_SLIP && t != PDF_BC_NOSLIP && t != PDF_BC_WALLFN &&
+        t != PDF_BC_OUTFLOW)
       return bad("unknown boundary type at edge " + std::to_string(b));
     const int32_t e = mesh->bedge_elem[b], k = mesh->bedge_local[b];
     if (e < 0 || e >= ne || k < 0 || k > 2 || nbr[3 * e + k] != -(b + 1))
       return bad("boundary edge " + std::to_string(b) + " does not match elem_nbr");
-    if (t == PDF_BC_PERIODIC) {
+    if (t == PDF_BC_PERIODIC || t == PDF_BC_OUTFLOW) {
+      // a periodic edge pairs with a periodic or an outflow edge, an outflow
+      // edge with a periodic (inflow) edge
       const int32_t p = mesh->bedge_partner[b];
-      if (p < 0 || p >= nb || mesh->bedge_partner[p] != b || mesh->bedge_type[p] != PDF_BC_PERIODIC)
+      if (p < 0 || p >= nb || mesh->bedge_partner[p] != b ||
+          !(mesh->bedge_type[p] == PDF_BC_PERIODIC || (t == PDF_BC_PERIODIC && mesh->bedge_type[p] == PDF_BC_OUTFLOW)))
         return bad("periodic partner not mutual at edge " + std::to_string(b));
     }
   }
@@ -886,7 +891,7 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   {
     std::vector<std::vector<int32_t>> l(nn);
     for (int32_t b = 0; b < nb; ++b) {
-      if (mesh->bedge_type[b] == PDF_BC_PERIODIC) continue;
+      if (mesh->bedge_type[b] == PDF_BC_PERIODIC || mesh->bedge_type[b] == PDF_BC_OUTFLOW) continue;
       const int32_t e = mesh->bedge_elem[b], k = mesh->bedge_local[b];
       l[en[3 * e + (k + 1) % 3]].push_back(b);
       l[en[3 * e + (k + 2) % 3]].push_back(b);
@@ -1076,8 +1081,10 @@ pdf_status pdf_init_mesh(const pdf_mesh_desc *mesh, const pdf_model_params *para
   md.cond_nv = params->cond_nv;
   md.cond_nw = params->cond_nw;
   md.cond_min = params->cond_min;
-  md.pad = 0;
+  md.outflow = 0;
+  for (int32_t b = 0; b < nb; ++b) md.outflow |= mesh->bedge_type[b] == PDF_BC_OUTFLOW ? 1 : 0;
   md.nu_wall = params->nu_wall;
+  md.inflow_u = params->inflow_u;
   md.CL = params->CL;
   md.Ceta = params->Ceta;
   if (params->model == PDF_MODEL_GLM && params->wp_source == PDF_WP_ELLIPTIC) {

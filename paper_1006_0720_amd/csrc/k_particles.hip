@@ -741,7 +741,8 @@ __device__ __forceinline__ void noslip(const ModelDev &md, const T *r, double nx
 // ---------------------------------------------------------------------------
 // event counters of one thread, packed 16 bits each in ca (walk steps, periodic
 // crossings, reflections, trajectory-(b) conditions) and 8 bits each in cb
-// (fall-backs, brute-force searches, lost, omega folds, gamma failures, non-finite)
+// (fall-backs, brute-force searches, lost, omega folds, gamma failures, non-finite,
+// outflow relocations)
 #define C_WALK(v) (ca += (uint64_t)(v))
 #define C_PER(v) (ca += (uint64_t)(v) << 16)
 #define C_REFL(v) (ca += (uint64_t)(v) << 32)
@@ -752,6 +753,7 @@ __device__ __forceinline__ void noslip(const ModelDev &md, const T *r, double nx
 #define C_CLAMP(v) (cb += (uint64_t)(v) << 24)
 #define C_GFAIL(v) (cb += (uint64_t)(v) << 32)
 #define C_NAN(v) (cb += (uint64_t)(v) << 40)
+#define C_OUT(v) (cb += (uint64_t)(v) << 48)
 
 // Wall-function condition (eq:wall-normal-velocity, eq:particle-wallcondition-wf
 // with eq:alpha, eq:hatu, eq:Ue and eq:friction-velocity; eq:wall-omega) for a
@@ -801,7 +803,7 @@ static_assert(sizeof(SumTable) + GWIN * sizeof(WalkGeo) <= LDS_3WG &&
 template <typename T, bool SHAPE>
 constexpr int advance_waves() { return sizeof(T) == 4 ? 3 : 1; }
 
-template <typename T, bool VISC, bool WALLB, bool SHAPE, bool SPARSE>
+template <typename T, bool VISC, bool WALLB, bool SHAPE, bool SPARSE, bool OUTF>
 __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(const KArgs *__restrict__ ka, PartDev<T> p, int64_t np,
                                                 int ppt, const T *__restrict__ rec, double *sums, uint32_t k0,
                                                 uint32_t k1, uint32_t step, double dt, double sdt,
@@ -985,14 +987,25 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
       }
       const int32_t b = -(nb + 1);
       const int32_t bt = ldg(m.btype, b);
-      if (bt == PDF_BC_PERIODIC) {
+      if (bt == PDF_BC_PERIODIC || (OUTF && bt == PDF_BC_OUTFLOW)) {
+        // periodic, or an outflow edge: the same translation to the paired
+        // (inflow) edge, and there the velocity of the incoming flow (Ch.6,
+        // cylinder flow, Sec. Results: its boundary conditions), on which
+        // any later wall condition of the walk then acts
         const double sx = ldg(m.bshift, 2 * b), sy = ldg(m.bshift, 2 * b + 1);
         x = stor<T>(x + sx);
         y = stor<T>(y + sy);
         shx += sx;
         shy += sy;
         e = ldg(m.belem, ldg(m.bpart, b));
-        C_PER(1);
+        if (OUTF && bt == PDF_BC_OUTFLOW) {
+          un0 = (T)md.inflow_u;
+          un1 = (T)0;
+          un2 = (T)0;
+          C_OUT(1);
+        } else {
+          C_PER(1);
+        }
         continue;
       }
       // a boundary edge: the element's vertices and node numbers
@@ -1160,9 +1173,10 @@ __global__ __launch_bounds__(WG, (advance_waves<T, SHAPE>())) void k_advance(con
   wave_count(&cnt[PDF_CNT_OMEGA_CLAMP], (int)((cb >> 24) & 0xFF));
   wave_count(&cnt[PDF_CNT_GAMMA_FAIL], (int)((cb >> 32) & 0xFF));
   wave_count(&cnt[PDF_CNT_NONFINITE], (int)((cb >> 40) & 0xFF));
+  if constexpr (OUTF) wave_count(&cnt[PDF_CNT_OUTFLOW], (int)((cb >> 48) & 0xFF));
 }
 
-template <typename T, bool SHAPE, bool SPARSE>
+template <typename T, bool SHAPE, bool SPARSE, bool OUTF>
 void launch_advance_k(hipStream_t s, const KArgs *dka, const ModelDev &md, PartDev<T> p, int64_t np, int ppt,
                       const T *rec, double *sums, uint64_t seed, uint32_t step, double dt, const double *dtp,
                       const T *cm, const double *S, const double *gradp, unsigned long long *cnt) {
@@ -1172,13 +1186,13 @@ void launch_advance_k(hipStream_t s, const KArgs *dka, const ModelDev &md, PartD
   const double sdt = sqrt(dt), s2nu = sqrt(2.0 * md.nu);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   if (visc && wallb)
-    hipLaunchKernelGGL((k_advance<T, true, true, SHAPE, SPARSE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt,
+    hipLaunchKernelGGL((k_advance<T, true, true, SHAPE, SPARSE, OUTF>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt,
                        rec, sums, k0, k1, step, dt, sdt, dtp, s2nu, cm, S, gradp, cnt);
   else if (visc)
-    hipLaunchKernelGGL((k_advance<T, true, false, SHAPE, SPARSE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt,
+    hipLaunchKernelGGL((k_advance<T, true, false, SHAPE, SPARSE, OUTF>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt,
                        rec, sums, k0, k1, step, dt, sdt, dtp, s2nu, cm, S, gradp, cnt);
   else
-    hipLaunchKernelGGL((k_advance<T, false, false, SHAPE, SPARSE>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt,
+    hipLaunchKernelGGL((k_advance<T, false, false, SHAPE, SPARSE, OUTF>), dim3(grid), dim3(WG), 0, s, dka, p, np, ppt,
                        rec, sums, k0, k1, step, dt, sdt, dtp, s2nu, cm, S, gradp, cnt);
 }
 
@@ -1189,13 +1203,24 @@ void launch_advance_m(hipStream_t s, const KArgs *dka, const ModelDev &md, PartD
                       unsigned long long *cnt) {
   if constexpr (!SHAPE) {
     if (np < SPARSE_PPE * (int64_t)ne) {  // few particles per element: the sparse table
-      launch_advance_k<T, false, true>(s, dka, md, p, np, pick_ppt(np, ne, CHUNK_ELEMS_SPARSE), rec, sums, seed,
-                                       step, dt, dtp, cm, S, gradp, cnt);
+      if (md.outflow)
+        launch_advance_k<T, false, true, true>(s, dka, md, p, np, pick_ppt(np, ne, CHUNK_ELEMS_SPARSE), rec, sums,
+                                               seed, step, dt, dtp, cm, S, gradp, cnt);
+      else
+        launch_advance_k<T, false, true, false>(s, dka, md, p, np, pick_ppt(np, ne, CHUNK_ELEMS_SPARSE), rec, sums,
+                                                seed, step, dt, dtp, cm, S, gradp, cnt);
       return;
     }
   }
-  launch_advance_k<T, SHAPE, false>(s, dka, md, p, np, pick_ppt(np, ne), rec, sums, seed, step, dt, dtp, cm, S,
-                                    gradp, cnt);
+  // the outflow relocation lives in its own kernel variant: its code in the
+  // walk changes the register allocation of the whole kernel (8 more bytes
+  // of spills, 1.5 % slower), which meshes without outflow edges do not pay
+  if (md.outflow)
+    launch_advance_k<T, SHAPE, false, true>(s, dka, md, p, np, pick_ppt(np, ne), rec, sums, seed, step, dt, dtp, cm,
+                                            S, gradp, cnt);
+  else
+    launch_advance_k<T, SHAPE, false, false>(s, dka, md, p, np, pick_ppt(np, ne), rec, sums, seed, step, dt, dtp,
+                                             cm, S, gradp, cnt);
 }
 
 template <typename T>

@@ -118,9 +118,11 @@ struct PartDev {
 
 struct ModelDev {
   int32_t model, wp_source, omega_source, tm_mode, wall_b, stats_mode;
-  int32_t mix_model, cond_nu, cond_nv, cond_nw, cond_min, pad;
+  int32_t mix_model, cond_nu, cond_nv, cond_nw, cond_min;
+  int32_t outflow;  // 1: the mesh has PDF_BC_OUTFLOW edges (the particle kernel's variant with them)
   double C0, C1, C2, C3, C4, CT, Cv, gamma5, Cw1, Cw2, Cphi, nu, k_floor;
   double src_x, src_y, src_r, Cs, Ct, nu_wall;
+  double inflow_u;  // velocity of particles relocated at the inflow (PDF_BC_OUTFLOW)
   double CL, Ceta;  // eq:L
 };
 
