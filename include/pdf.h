@@ -222,7 +222,10 @@ typedef struct pdf_mesh_desc {
  *                that vertex's distance to the edge's line.  Wall functions replace the
  *                viscous terms of the particle equations (eq:Lagrangian-position-wf,
  *                eq:Lagrangian-model-wf): a mesh with PDF_BC_WALLFN edges needs nu = 0
- *                (PDF_E_INVALID_ARG otherwise). */
+ *                (PDF_E_INVALID_ARG otherwise).
+ *   inflow_u     streamwise velocity given to particles relocated at the inflow when they
+ *                leave through a PDF_BC_OUTFLOW edge (finite; PDF_E_INVALID_ARG otherwise;
+ *                unused without such edges) */
 typedef struct pdf_model_params {
   int32_t model, wp_source, omega_source, tm_mode, frozen, wall_b, reorder_every, stats_mode;
   int32_t min_ppe, mix_model, cond_nu, cond_nv, cond_nw, cond_min, ell_maxit, proj, proj_maxit, proj_precond;
