@@ -100,6 +100,10 @@ __device__ __forceinline__ Passes plan_passes(const ModelDev &md, int32_t n) {
 }
 
 __device__ __forceinline__ int32_t gstart(int64_t g, int64_t n, int64_t P) { return (int32_t)((g * n + P - 1) / P); }
+// the same in 32 bits for the LDS paths (n <= CAP_M): every level keeps at
+// least one particle per group, so P <= n and g * n + P stays below 2^19
+__device__ __forceinline__ int32_t gstart32(uint32_t g, uint32_t n, uint32_t P) { return (int32_t)((g * n + P - 1) / P); }
+__device__ __forceinline__ int32_t group_of32(uint32_t q, uint32_t n, uint32_t P) { return (int32_t)(P * q / n); }
 
 // barrier of the NT threads that share one element's LDS: a whole workgroup,
 // or (NT = 64) one wave, whose LDS accesses complete in issue order
@@ -248,39 +252,40 @@ struct CondLds {
   T ku[CAP], kv[CAP], kw[CAP], psi[CAP];  // by slot (the element's list order)
   uint32_t id[CAP];
   int32_t idx[CAP];
-  // by position, two buffers: the sort key (FP32: the 32-bit key over the id
-  // in one word; FP64: the 64-bit key, the id apart) and the slot
-  uint64_t k[2][CAP];
-  uint32_t ki[sizeof(T) == 8 ? 2 : 1][sizeof(T) == 8 ? CAP : 1];
-  uint16_t s[2][CAP];
+  // by position: the sort key (FP32: the 32-bit key over the id in one word;
+  // FP64: the 64-bit key, the id apart) and the slot, rewritten in place by
+  // every pass once all of its ranks are counted
+  uint64_t k[CAP];
+  uint32_t ki[sizeof(T) == 8 ? CAP : 1];
+  uint16_t s[CAP];
 };
 
 template <typename T, int CAP>
-__device__ __forceinline__ void set_key(CondLds<T, CAP> &L, int buf, int pos, int slot, int dir) {
+__device__ __forceinline__ void set_key(CondLds<T, CAP> &L, int pos, int slot, int dir) {
   if constexpr (sizeof(T) == 4) {
     const uint64_t kk = dir < 0 ? 0 : ordkey(dir == 0 ? L.ku[slot] : (dir == 1 ? L.kv[slot] : L.kw[slot]));
-    L.k[buf][pos] = (kk << 32) | L.id[slot];
+    L.k[pos] = (kk << 32) | L.id[slot];
   } else {
-    L.k[buf][pos] = dir < 0 ? 0 : ordkey(dir == 0 ? L.ku[slot] : (dir == 1 ? L.kv[slot] : L.kw[slot]));
-    L.ki[buf][pos] = L.id[slot];
+    L.k[pos] = dir < 0 ? 0 : ordkey(dir == 0 ? L.ku[slot] : (dir == 1 ? L.kv[slot] : L.kw[slot]));
+    L.ki[pos] = L.id[slot];
   }
 }
 
 // rank of position q within its group [s0, s1) in (key, id, position) order
 template <typename T, int CAP>
-__device__ __forceinline__ int32_t rank_in(const CondLds<T, CAP> &L, int cur, int32_t s0, int32_t s1, int32_t q) {
-  const uint64_t mk = L.k[cur][q];
+__device__ __forceinline__ int32_t rank_in(const CondLds<T, CAP> &L, int32_t s0, int32_t s1, int32_t q) {
+  const uint64_t mk = L.k[q];
   int32_t rank = 0;
   if constexpr (sizeof(T) == 4) {
     // (key, id) in one word, unique while the ids are
 #pragma unroll 8
-    for (int32_t r = s0; r < s1; ++r) rank += L.k[cur][r] < mk;
+    for (int32_t r = s0; r < s1; ++r) rank += L.k[r] < mk;
   } else {
-    const uint32_t mi = L.ki[cur][q];
+    const uint32_t mi = L.ki[q];
 #pragma unroll 8
     for (int32_t r = s0; r < s1; ++r) {
-      const uint64_t k = L.k[cur][r];
-      const uint32_t id = L.ki[cur][r];
+      const uint64_t k = L.k[r];
+      const uint32_t id = L.ki[r];
       rank += (k < mk) | ((k == mk) & ((id < mi) | ((id == mi) & (r < q))));
     }
   }
@@ -290,25 +295,25 @@ __device__ __forceinline__ int32_t rank_in(const CondLds<T, CAP> &L, int cur, in
 // the first division (one group): each thread ranks its QP positions in one
 // sweep over all n keys, read once per sweep
 template <typename T, int CAP, int NT>
-__device__ __forceinline__ void rank_all(const CondLds<T, CAP> &L, int cur, int32_t n, int32_t rank[], int t) {
+__device__ __forceinline__ void rank_all(const CondLds<T, CAP> &L, int32_t n, int32_t rank[], int t) {
   constexpr int QP = CAP / NT;
   uint64_t mk[QP];
   uint32_t mi[QP];
 #pragma unroll
   for (int j = 0; j < QP; ++j) {
     const int32_t q = t + j * NT;
-    mk[j] = q < n ? L.k[cur][q] : 0;
-    if constexpr (sizeof(T) == 8) mi[j] = q < n ? L.ki[cur][q] : 0;
+    mk[j] = q < n ? L.k[q] : 0;
+    if constexpr (sizeof(T) == 8) mi[j] = q < n ? L.ki[q] : 0;
     rank[j] = 0;
   }
 #pragma unroll 4
   for (int32_t r = 0; r < n; ++r) {
-    const uint64_t k = L.k[cur][r];
+    const uint64_t k = L.k[r];
     if constexpr (sizeof(T) == 4) {
 #pragma unroll
       for (int j = 0; j < QP; ++j) rank[j] += k < mk[j];
     } else {
-      const uint32_t id = L.ki[cur][r];
+      const uint32_t id = L.ki[r];
 #pragma unroll
       for (int j = 0; j < QP; ++j)
         rank[j] += (k < mk[j]) | ((k == mk[j]) & ((id < mi[j]) | ((id == mi[j]) & (r < t + j * NT))));
@@ -322,69 +327,96 @@ template <typename T, int CAP, int NT>
 __device__ void cond_element(CondLds<T, CAP> &L, const ModelDev &md, const PartDev<T> &p, int32_t n, int32_t base,
                              const int32_t *list, T *cm, int t) {
   constexpr int QP = CAP / NT;
-  for (int q = t; q < n; q += NT) {
-    const int32_t i = list[base + q];
-    L.idx[q] = i;
-    L.id[q] = p.id[i];
-    L.ku[q] = p.u[i];
-    L.kv[q] = p.v[i];
-    L.kw[q] = p.w[i];
-    L.psi[q] = p.psi[i];
+  {
+    // every list entry of the thread first, then every particle load, so that
+    // the gather waits on two rounds of global loads rather than two per entry
+    int32_t gi[QP];
+#pragma unroll
+    for (int j = 0; j < QP; ++j) {
+      const int32_t q = t + j * NT;
+      gi[j] = q < n ? list[base + q] : 0;
+    }
+    uint32_t vid[QP];
+    T vu[QP], vv[QP], vw[QP], vp[QP];
+#pragma unroll
+    for (int j = 0; j < QP; ++j) {
+      if (t + j * NT >= n) continue;
+      const int32_t i = gi[j];
+      vid[j] = p.id[i];
+      vu[j] = p.u[i];
+      vv[j] = p.v[i];
+      vw[j] = p.w[i];
+      vp[j] = p.psi[i];
+    }
+#pragma unroll
+    for (int j = 0; j < QP; ++j) {
+      const int32_t q = t + j * NT;
+      if (q >= n) continue;
+      L.idx[q] = gi[j];
+      L.id[q] = vid[j];
+      L.ku[q] = vu[j];
+      L.kv[q] = vv[j];
+      L.kw[q] = vw[j];
+      L.psi[q] = vp[j];
+    }
   }
   grp_sync<NT>();
   const Passes ps = plan_passes(md, n);
   for (int q = t; q < n; q += NT) {
-    L.s[0][q] = (uint16_t)q;
-    set_key(L, 0, q, q, ps.dir[0]);
+    L.s[q] = (uint16_t)q;
+    set_key(L, q, q, ps.dir[0]);
   }
   grp_sync<NT>();
-  int cur = 0;
   int32_t nc = 1;
   for (int pass = 0; pass < ps.n_pass; ++pass) {
     const bool more = pass + 1 < ps.n_pass;
     const int nextdir = more ? pick3(ps.dir, pass + 1) : 0;
     // FP32 ranks are strict-order counts, a permutation only while the ids are
-    // unique: the target positions first get a valid slot so that repeated
-    // ids can only give wrong bins, never an index outside the element
-    if constexpr (sizeof(T) == 4) {
-      for (int q = t; q < n; q += NT) L.s[1 - cur][q] = 0;
-      grp_sync<NT>();
-    }
+    // unique; a rank stays below the end of its group, and a position that no
+    // rank hits keeps its slot of the last pass, so repeated ids can only give
+    // wrong bins, never an index outside the element
     int32_t rank[QP];
     if (nc == 1) {
-      rank_all<T, CAP, NT>(L, cur, n, rank, t);
+      rank_all<T, CAP, NT>(L, n, rank, t);
     } else {
 #pragma unroll
       for (int j = 0; j < QP; ++j) {
         const int32_t q = t + j * NT;
         rank[j] = 0;
         if (q < n) {
-          const int32_t g = (int32_t)((int64_t)nc * q / n);
-          rank[j] = gstart(g, n, nc) + rank_in(L, cur, gstart(g, n, nc), gstart(g + 1, n, nc), q);
+          const int32_t g = group_of32(q, n, nc);
+          const int32_t s0 = gstart32(g, n, nc);
+          rank[j] = s0 + rank_in(L, s0, gstart32(g + 1, n, nc), q);
         }
       }
     }
+    // every rank is counted and every slot read before the order is rewritten
+    int sl[QP];
+#pragma unroll
+    for (int j = 0; j < QP; ++j) {
+      const int32_t q = t + j * NT;
+      sl[j] = q < n ? L.s[q] : 0;
+    }
+    grp_sync<NT>();
 #pragma unroll
     for (int j = 0; j < QP; ++j) {
       const int32_t q = t + j * NT;
       if (q < n) {
         const int np_ = rank[j];  // the group start is 0 for the single group
-        const int sl = L.s[cur][q];
-        L.s[1 - cur][np_] = (uint16_t)sl;
-        if (more) set_key(L, 1 - cur, np_, sl, nextdir);
+        L.s[np_] = (uint16_t)sl[j];
+        if (more) set_key(L, np_, sl[j], nextdir);
       }
     }
     grp_sync<NT>();
-    cur = 1 - cur;
     nc = pick3(ps.groups, pass);
   }
   // bin means (App. B), each bin summed in the order of its positions
   for (int32_t b = t; b < nc; b += NT) {
-    const int32_t s0 = gstart(b, n, nc), s1 = gstart(b + 1, n, nc);
+    const int32_t s0 = gstart32(b, n, nc), s1 = gstart32(b + 1, n, nc);
     double sum = 0.0;
-    for (int32_t r = s0; r < s1; ++r) sum += (double)L.psi[L.s[cur][r]];
+    for (int32_t r = s0; r < s1; ++r) sum += (double)L.psi[L.s[r]];
     const T mean = (T)(sum / (double)(s1 - s0));
-    for (int32_t r = s0; r < s1; ++r) cm[L.idx[L.s[cur][r]]] = mean;
+    for (int32_t r = s0; r < s1; ++r) cm[L.idx[L.s[r]]] = mean;
   }
 }
 
@@ -397,9 +429,12 @@ __global__ __launch_bounds__(64 * SW) void k_cond_small(int32_t ne, ModelDev md,
                                                         const int32_t *off, const int32_t *list, int32_t *mid,
                                                         int32_t *big, int32_t *counters, T *cm) {
   __shared__ CondLds<T, CAP_S> L[SW];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wave number through readfirstlane: it makes the element and all that
+  // follows from it (counts, group bounds, loop trips) wave-uniform to the
+  // compiler, which then keeps them in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   for (int32_t e = blockIdx.x * SW + w; e < ne; e += gridDim.x * SW) {
-    const int32_t n = cnt[e];
+    const int32_t n = cnt[e], first = off[e];  // both loads in flight together
     if (n == 0) continue;
     if (n > CAP_S) {
       if (lane == 0) {
@@ -410,7 +445,7 @@ __global__ __launch_bounds__(64 * SW) void k_cond_small(int32_t ne, ModelDev md,
       }
       continue;
     }
-    cond_element<T, CAP_S, 64>(L[w], md, p, n, off[e], list, cm, lane);
+    cond_element<T, CAP_S, 64>(L[w], md, p, n, first, list, cm, lane);
     grp_sync<64>();  // before the wave's next element overwrites its LDS
   }
 }
