@@ -174,9 +174,14 @@ __global__ __launch_bounds__(TT) void k_cond_count(int64_t np, int32_t ne, const
   }
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * TT * TP;
+  int32_t pe_[TP];  // every element number loaded before the first atomic
+#pragma unroll
   for (int j = 0; j < TP; ++j) {
     const int64_t i = base + (int64_t)j * TT + t;
-    const int32_t e = i < np ? pe[i] : -1;
+    pe_[j] = i < np ? pe[i] : -1;
+  }
+  for (int j = 0; j < TP; ++j) {
+    const int32_t e = pe_[j];
     const bool valid = e >= 0 && e < ne;
     int hl, len;
     wave_runs(e, valid, hl, len);
@@ -206,10 +211,16 @@ __global__ __launch_bounds__(TT) void k_cond_fill(int64_t np, int32_t ne, const 
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * TT * TP;
   int32_t pe_[TP], slot[TP], rank[TP];
+  // every element number loaded before the first atomic, so that the loads
+  // overlap instead of waiting one by one
 #pragma unroll
   for (int j = 0; j < TP; ++j) {
     const int64_t i = base + (int64_t)j * TT + t;
-    const int32_t e = i < np ? pe[i] : -1;
+    pe_[j] = i < np ? pe[i] : -1;
+  }
+#pragma unroll
+  for (int j = 0; j < TP; ++j) {
+    const int32_t e = pe_[j];
     const bool valid = e >= 0 && e < ne;
     int hl, len;
     wave_runs(e, valid, hl, len);
@@ -230,16 +241,28 @@ __global__ __launch_bounds__(TT) void k_cond_fill(int64_t np, int32_t ne, const 
     const int32_t k = hk[s];
     if (k >= 0) hb[s] = atomicAdd(&cursor[k], hc[s]);
   }
-  __syncthreads();
+  // the element offsets, all loaded before the first store
+  int32_t o0[TP], o1[TP];
 #pragma unroll
   for (int j = 0; j < TP; ++j) {
-    const int32_t e = pe_[j];
-    if (e < 0) continue;
-    const int64_t i = base + (int64_t)j * TT + t;
-    const int32_t pos = slot[j] >= 0 ? hb[slot[j]] + rank[j] : rank[j];
-    if (pos >= off[e + 1] - off[e]) continue;  // counts that disagree with the elements stay in bounds
-    list[off[e] + pos] = (int32_t)i;
+    o0[j] = pe_[j] >= 0 ? off[pe_[j]] : 0;
+    o1[j] = pe_[j] >= 0 ? off[pe_[j] + 1] : 0;
   }
+  __syncthreads();
+  // every destination before the first store (a store between the loads and
+  // their use makes the compiler wait for all memory operations)
+  int32_t dst[TP];
+#pragma unroll
+  for (int j = 0; j < TP; ++j) {
+    dst[j] = -1;
+    if (pe_[j] < 0) continue;
+    const int32_t pos = slot[j] >= 0 ? hb[slot[j]] + rank[j] : rank[j];
+    if (pos < o1[j] - o0[j]) dst[j] = o0[j] + pos;  // counts that disagree with the elements stay in bounds
+  }
+  __builtin_amdgcn_sched_barrier(0);  // keeps the stores after every destination
+#pragma unroll
+  for (int j = 0; j < TP; ++j)
+    if (dst[j] >= 0) list[dst[j]] = (int32_t)(base + (int64_t)j * TT + t);
 }
 
 // ---- sort and divide in LDS: one element of at most CAP particles per
@@ -249,7 +272,13 @@ constexpr int32_t SMALL_GRID = 1 << 30;  // workgroups of k_cond_small at most
 
 template <typename T, int CAP>
 struct CondLds {
-  T ku[CAP], kv[CAP], kw[CAP], psi[CAP];  // by slot (the element's list order)
+  // by slot (the element's list order); the U keys' space also holds the
+  // bucket counts and starts of the first division by buckets
+  union {
+    T ku[CAP];
+    int32_t kh[CAP * sizeof(T) / 4];
+  };
+  T kv[CAP], kw[CAP], psi[CAP];
   uint32_t id[CAP];
   int32_t idx[CAP];
   // by position: the sort key (FP32: the 32-bit key over the id in one word;
@@ -293,10 +322,9 @@ __device__ __forceinline__ int32_t rank_in(const CondLds<T, CAP> &L, int32_t s0,
 }
 
 // the first division (one group): each thread ranks its QP positions in one
-// sweep over all n keys, read once per sweep
-template <typename T, int CAP, int NT>
+// sweep over all n keys, read once per sweep (QP * NT >= n)
+template <typename T, int CAP, int NT, int QP>
 __device__ __forceinline__ void rank_all(const CondLds<T, CAP> &L, int32_t n, int32_t rank[], int t) {
-  constexpr int QP = CAP / NT;
   uint64_t mk[QP];
   uint32_t mi[QP];
 #pragma unroll
@@ -319,6 +347,87 @@ __device__ __forceinline__ void rank_all(const CondLds<T, CAP> &L, int32_t n, in
         rank[j] += (k < mk[j]) | ((k == mk[j]) & ((id < mi[j]) | ((id == mi[j]) & (r < t + j * NT))));
     }
   }
+}
+
+// the first division by velocity buckets (FP32, one wave per element, first
+// level by U): a map that never decreases with U spreads the keys over NB
+// buckets, so every key of a lower bucket is smaller and equal velocities share
+// a bucket; a position's rank is the start of its bucket plus its rank among
+// that bucket's keys, the same (key, id) rank as the full sweep.  Returns false
+// with LDS untouched, for the full sweep, when a velocity is not finite.
+constexpr int NB = 64;
+template <int CAP>
+__device__ __forceinline__ bool rank_buckets(CondLds<float, CAP> &L, int32_t n, int32_t rank[], int lane) {
+  constexpr int QP = CAP / 64;
+  static_assert(CAP >= 2 * NB, "the bucket counts and starts fit the U keys' space");
+  float u[QP];
+  uint64_t mk[QP];
+  float lo = INFINITY, hi = -INFINITY;
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < QP; ++j) {
+    const int32_t q = lane + j * 64;
+    u[j] = 0.0f;
+    mk[j] = 0;
+    if (q < n) {
+      u[j] = L.ku[q];  // the first pass still has the list order
+      mk[j] = L.k[q];
+      bad |= !__builtin_isfinite(u[j]);
+      lo = fminf(lo, u[j]);
+      hi = fmaxf(hi, u[j]);
+    }
+  }
+  if (__ballot(bad) != 0) return false;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    lo = fminf(lo, __shfl_xor(lo, m, 64));
+    hi = fmaxf(hi, __shfl_xor(hi, m, 64));
+  }
+  // zero spread, or one too narrow or too wide for a finite scale: one bucket
+  float scale = (float)NB / (hi - lo);
+  if (!(scale <= __FLT_MAX__)) scale = 0.0f;
+  int32_t *cnt = L.kh, *start = L.kh + NB;
+  grp_sync<64>();  // every lane holds its U values before their space is reused
+  cnt[lane] = 0;
+  grp_sync<64>();
+  int32_t b[QP], c[QP];
+#pragma unroll
+  for (int j = 0; j < QP; ++j) {
+    b[j] = 0;
+    c[j] = 0;
+    if (lane + j * 64 < n) {
+      // (u - lo) and the product are correctly rounded, so they never decrease with u
+      const int32_t bb = scale > 0.0f ? (int32_t)((u[j] - lo) * scale) : 0;
+      b[j] = bb < NB - 1 ? bb : NB - 1;
+      c[j] = atomicAdd(&cnt[b[j]], 1);
+    }
+  }
+  grp_sync<64>();
+  const int32_t mine = cnt[lane];
+  int32_t incl = mine;
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    const int32_t o = __shfl_up(incl, m, 64);
+    if (lane >= m) incl += o;
+  }
+  start[lane] = incl - mine;
+  grp_sync<64>();
+  // the keys in bucket order over the sweep's key array, then the ranks
+#pragma unroll
+  for (int j = 0; j < QP; ++j)
+    if (lane + j * 64 < n) L.k[start[b[j]] + c[j]] = mk[j];
+  grp_sync<64>();
+#pragma unroll
+  for (int j = 0; j < QP; ++j) {
+    rank[j] = 0;
+    if (lane + j * 64 < n) {
+      const int32_t s0 = start[b[j]], s1 = s0 + cnt[b[j]];
+      int32_t r = 0;
+      for (int32_t k = s0; k < s1; ++k) r += L.k[k] < mk[j];
+      rank[j] = s0 + r;
+    }
+  }
+  return true;
 }
 
 // sort and divide the n <= CAP particles of one element (list[base, base+n))
@@ -376,9 +485,21 @@ __device__ void cond_element(CondLds<T, CAP> &L, const ModelDev &md, const PartD
     // rank hits keeps its slot of the last pass, so repeated ids can only give
     // wrong bins, never an index outside the element
     int32_t rank[QP];
-    if (nc == 1) {
-      rank_all<T, CAP, NT>(L, n, rank, t);
-    } else {
+    bool ranked = false;
+    if constexpr (sizeof(T) == 4 && NT == 64) {
+      if (nc == 1 && ps.dir[0] == 0) ranked = rank_buckets<CAP>(L, n, rank, t);
+    }
+    if (!ranked && nc == 1) {
+      // one position per thread when the element allows (n is uniform over the
+      // threads of the element)
+      if (QP > 1 && n <= NT) {
+        rank_all<T, CAP, NT, 1>(L, n, rank, t);
+#pragma unroll
+        for (int j = 1; j < QP; ++j) rank[j] = 0;
+      } else {
+        rank_all<T, CAP, NT, QP>(L, n, rank, t);
+      }
+    } else if (!ranked) {
 #pragma unroll
       for (int j = 0; j < QP; ++j) {
         const int32_t q = t + j * NT;

@@ -148,6 +148,44 @@ def test_iecm_fp32_one_step(L, n, ppe):
     ctx.close()
 
 
+def test_iecm_fp32_velocity_ties(L):
+    """FP32 one step with exact ties planted in every element: U copied from
+    one particle to the next (ties broken by id), a whole velocity copied, U
+    of -0 and +0 side by side (equal keys), with a strong mixing rate so that
+    a particle put in a wrong bin shows in its scalar.  About 100 per element
+    runs the first division by velocity buckets on the one-wave path."""
+    w = _square(8, 100, Cphi=10.0)
+    w.precision = "f32"
+    ctx, o = _pair(w)
+    st, el, pid = ctx.particles()
+    st = np.array(st, dtype=np.float64, order="C")
+    order = np.argsort(el, kind="stable")
+    first = np.flatnonzero(np.r_[True, np.diff(el[order]) != 0])
+    assert np.diff(np.r_[first, el.size]).min() >= 8
+
+    def at(k):  # the k-th particle of every element
+        return order[first + k]
+
+    st[2, at(1)] = st[2, at(0)]
+    st[2:5, at(3)] = st[2:5, at(2)]
+    st[2, at(4)] = -0.0
+    st[2, at(5)] = 0.0
+    st[2, at(6)] = -0.0
+    ctx.set_particles(st, el, pid)
+    st0, el0, pid0 = ctx.particles()
+    assert np.array_equal(pid0, pid)
+    assert np.signbit(st0[2, at(4)]).all() and not np.signbit(st0[2, at(5)]).any()
+    o.state, o.elem, o.id = st0, el0, pid0
+    o.set_stats(ctx.stats())
+    ctx.advance(1, w.dt)
+    o.step(w.dt)
+    st1, el1, _ = ctx.particles()
+    assert np.abs(st1[6] - st0[6]).max() > 1e-3  # mixing moved the scalar
+    compare_elements(el1, st1, o.elem, o.state, w.mesh, "iecm fp32 ties", fp32=True)
+    compare_state(st1, o.state, w.mesh, 1e-5, "iecm fp32 ties", elem=o.elem)
+    ctx.close()
+
+
 def test_iecm_invalid_parameters(L):
     from synth import meshes as M
 
