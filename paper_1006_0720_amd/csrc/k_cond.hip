@@ -268,7 +268,10 @@ __global__ __launch_bounds__(TT) void k_cond_fill(int64_t np, int32_t ne, const 
 // ---- sort and divide in LDS: one element of at most CAP particles per
 // 64-thread workgroup ----
 constexpr int CAP_S = 128, CAP_M = 512;
-constexpr int32_t SMALL_GRID = 1 << 30;  // workgroups of k_cond_small at most
+// elements per wave of k_cond_small: with 1 to 4 the step times agree within
+// 1.5 % at 100M particles, 2 the fastest; longer runs per wave leave a long
+// last round of workgroups (the chip holds about 1800 at once) and lose
+constexpr int32_t SMALL_PER_WAVE = 2;
 
 template <typename T, int CAP>
 struct CondLds {
@@ -318,6 +321,20 @@ __device__ __forceinline__ int32_t rank_in(const CondLds<T, CAP> &L, int32_t s0,
       rank += (k < mk) | ((k == mk) & ((id < mi) | ((id == mi) & (r < q))));
     }
   }
+  return rank;
+}
+
+// FP32 rank of key mk within the group [s0, s0 + len), where every group of the
+// division has lmin (uniform over the threads) or lmin + 1 members: the first
+// lmin members in a loop the threads share, the possible extra one after it
+template <int CAP>
+__device__ __forceinline__ int32_t rank_in_even(const CondLds<float, CAP> &L, int32_t s0, int32_t len, int32_t lmin,
+                                                uint64_t mk) {
+  const uint64_t *kp = L.k + s0;
+  int32_t rank = 0;
+#pragma unroll 4
+  for (int32_t r = 0; r < lmin; ++r) rank += kp[r] < mk;
+  if (len > lmin) rank += kp[lmin] < mk;
   return rank;
 }
 
@@ -430,45 +447,60 @@ __device__ __forceinline__ bool rank_buckets(CondLds<float, CAP> &L, int32_t n, 
   return true;
 }
 
-// sort and divide the n <= CAP particles of one element (list[base, base+n))
-// with NT threads (t = 0..NT-1), and write every particle's bin mean
-template <typename T, int CAP, int NT>
-__device__ void cond_element(CondLds<T, CAP> &L, const ModelDev &md, const PartDev<T> &p, int32_t n, int32_t base,
-                             const int32_t *list, T *cm, int t) {
-  constexpr int QP = CAP / NT;
-  {
-    // every list entry of the thread first, then every particle load, so that
-    // the gather waits on two rounds of global loads rather than two per entry
-    int32_t gi[QP];
+// one element's particles as a thread holds them between their loads and LDS
+template <typename T, int QP>
+struct Held {
+  int32_t gi[QP];  // particle indices (the list entries)
+  uint32_t id[QP];
+  T u[QP], v[QP], w[QP], psi[QP];
+};
+
+// the list entries of the n > 0 particles of an element (list[base, base+n)).
+// Every load is unconditional, a thread past the end reading the last entry
+// again: loads under a per-thread branch would each wait for the ones before
+template <typename T, int QP, int NT>
+__device__ __forceinline__ void load_list(Held<T, QP> &h, const int32_t *list, int32_t base, int32_t n, int t) {
 #pragma unroll
-    for (int j = 0; j < QP; ++j) {
-      const int32_t q = t + j * NT;
-      gi[j] = q < n ? list[base + q] : 0;
-    }
-    uint32_t vid[QP];
-    T vu[QP], vv[QP], vw[QP], vp[QP];
-#pragma unroll
-    for (int j = 0; j < QP; ++j) {
-      if (t + j * NT >= n) continue;
-      const int32_t i = gi[j];
-      vid[j] = p.id[i];
-      vu[j] = p.u[i];
-      vv[j] = p.v[i];
-      vw[j] = p.w[i];
-      vp[j] = p.psi[i];
-    }
-#pragma unroll
-    for (int j = 0; j < QP; ++j) {
-      const int32_t q = t + j * NT;
-      if (q >= n) continue;
-      L.idx[q] = gi[j];
-      L.id[q] = vid[j];
-      L.ku[q] = vu[j];
-      L.kv[q] = vv[j];
-      L.kw[q] = vw[j];
-      L.psi[q] = vp[j];
-    }
+  for (int j = 0; j < QP; ++j) {
+    const int32_t q = t + j * NT;
+    h.gi[j] = list[base + (q < n ? q : n - 1)];
   }
+}
+
+// the particles of the list entries held (after load_list with n > 0)
+template <typename T, int QP, int NT>
+__device__ __forceinline__ void load_particles(Held<T, QP> &h, const PartDev<T> &p) {
+#pragma unroll
+  for (int j = 0; j < QP; ++j) {
+    const int32_t i = h.gi[j];
+    h.id[j] = p.id[i];
+    h.u[j] = p.u[i];
+    h.v[j] = p.v[i];
+    h.w[j] = p.w[i];
+    h.psi[j] = p.psi[i];
+  }
+}
+
+template <typename T, int CAP, int QP, int NT>
+__device__ __forceinline__ void store_held(CondLds<T, CAP> &L, const Held<T, QP> &h, int32_t n, int t) {
+#pragma unroll
+  for (int j = 0; j < QP; ++j) {
+    const int32_t q = t + j * NT;
+    if (q >= n) continue;
+    L.idx[q] = h.gi[j];
+    L.id[q] = h.id[j];
+    L.ku[q] = h.u[j];
+    L.kv[q] = h.v[j];
+    L.kw[q] = h.w[j];
+    L.psi[q] = h.psi[j];
+  }
+}
+
+// sort and divide the n <= CAP particles of one element, staged in LDS by
+// store_held, with NT threads (t = 0..NT-1), and write every particle's bin mean
+template <typename T, int CAP, int NT>
+__device__ void cond_solve(CondLds<T, CAP> &L, const ModelDev &md, int32_t n, T *cm, int t) {
+  constexpr int QP = CAP / NT;
   grp_sync<NT>();
   const Passes ps = plan_passes(md, n);
   for (int q = t; q < n; q += NT) {
@@ -500,14 +532,18 @@ __device__ void cond_element(CondLds<T, CAP> &L, const ModelDev &md, const PartD
         rank_all<T, CAP, NT, QP>(L, n, rank, t);
       }
     } else if (!ranked) {
+      const int32_t lmin = n / nc;  // the groups hold lmin or lmin + 1 members
 #pragma unroll
       for (int j = 0; j < QP; ++j) {
         const int32_t q = t + j * NT;
         rank[j] = 0;
         if (q < n) {
           const int32_t g = group_of32(q, n, nc);
-          const int32_t s0 = gstart32(g, n, nc);
-          rank[j] = s0 + rank_in(L, s0, gstart32(g + 1, n, nc), q);
+          const int32_t s0 = gstart32(g, n, nc), s1 = gstart32(g + 1, n, nc);
+          if constexpr (sizeof(T) == 4)
+            rank[j] = s0 + rank_in_even(L, s0, s1 - s0, lmin, L.k[q]);
+          else
+            rank[j] = s0 + rank_in(L, s0, s1, q);
         }
       }
     }
@@ -541,6 +577,20 @@ __device__ void cond_element(CondLds<T, CAP> &L, const ModelDev &md, const PartD
   }
 }
 
+// one element from its list: every list entry of the thread first, then every
+// particle load, so that the gather waits on two rounds of global loads
+template <typename T, int CAP, int NT>
+__device__ void cond_element(CondLds<T, CAP> &L, const ModelDev &md, const PartDev<T> &p, int32_t n, int32_t base,
+                             const int32_t *list, T *cm, int t) {
+  constexpr int QP = CAP / NT;
+  if (n <= 0) return;
+  Held<T, QP> h;
+  load_list<T, QP, NT>(h, list, base, n, t);
+  load_particles<T, QP, NT>(h, p);
+  store_held<T, CAP, QP, NT>(L, h, n, t);
+  cond_solve<T, CAP, NT>(L, md, n, cm, t);
+}
+
 // every element: those of at most CAP_S particles here, one per wave at a
 // time (SW waves per workgroup, each with its own LDS), the others listed for
 // the mid-size and large-element kernels
@@ -554,20 +604,51 @@ __global__ __launch_bounds__(64 * SW) void k_cond_small(int32_t ne, ModelDev md,
   // follows from it (counts, group bounds, loop trips) wave-uniform to the
   // compiler, which then keeps them in scalar registers
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  for (int32_t e = blockIdx.x * SW + w; e < ne; e += gridDim.x * SW) {
-    const int32_t n = cnt[e], first = off[e];  // both loads in flight together
-    if (n == 0) continue;
-    if (n > CAP_S) {
-      if (lane == 0) {
-        if (n > CAP_M)
-          big[atomicAdd(&counters[0], 1)] = e;
-        else
-          mid[atomicAdd(&counters[1], 1)] = e;
-      }
-      continue;
+  constexpr int QP = CAP_S / 64;
+  const int64_t stride = (int64_t)gridDim.x * SW;
+  // a software pipeline over the wave's elements e, e + stride, ...: the
+  // particle loads of one element go out together with the list entries of
+  // the next and the counts of the one after, so that each element waits on
+  // one round of global loads
+  auto counts = [&](int64_t x, int32_t &nx, int32_t &fx) {
+    nx = 0;
+    fx = 0;
+    if (x < ne) {
+      nx = cnt[x];
+      fx = off[x];
     }
-    cond_element<T, CAP_S, 64>(L[w], md, p, n, first, list, cm, lane);
-    grp_sync<64>();  // before the wave's next element overwrites its LDS
+  };
+  int64_t e = (int64_t)blockIdx.x * SW + w;
+  int32_t n, first, n1, first1;
+  counts(e, n, first);
+  counts(e + stride, n1, first1);
+  Held<T, QP> h;
+  if (n > 0 && n <= CAP_S) load_list<T, QP, 64>(h, list, first, n, lane);
+  while (e < ne) {
+    const int32_t m = n <= CAP_S ? n : 0;  // the particles sorted here
+    if (m > 0) load_particles<T, QP, 64>(h, p);
+    Held<T, QP> h1;
+    if (n1 > 0 && n1 <= CAP_S) load_list<T, QP, 64>(h1, list, first1, n1, lane);
+    int32_t n2, first2;
+    counts(e + 2 * stride, n2, first2);
+    if (n > CAP_S && lane == 0) {
+      if (n > CAP_M)
+        big[atomicAdd(&counters[0], 1)] = (int32_t)e;
+      else
+        mid[atomicAdd(&counters[1], 1)] = (int32_t)e;
+    }
+    if (m > 0) {
+      store_held<T, CAP_S, QP, 64>(L[w], h, m, lane);
+      cond_solve<T, CAP_S, 64>(L[w], md, m, cm, lane);
+      grp_sync<64>();  // before the wave's next element overwrites its LDS
+    }
+    e += stride;
+    n = n1;
+    first = first1;
+    n1 = n2;
+    first1 = first2;
+#pragma unroll
+    for (int j = 0; j < QP; ++j) h.gi[j] = h1.gi[j];
   }
 }
 
@@ -702,8 +783,8 @@ hipError_t launch_cond_means(hipStream_t s, const ModelDev &md, const CondBuf &b
   (void)hipMemsetAsync(b.nbig, 0, 8, s);
   hipLaunchKernelGGL(k_cond_fill, dim3(gt), dim3(TT), 0, s, np, ne, p.e, b.off, b.cursor, b.list);
   T *cm = (T *)b.cm;
-  const int32_t gs = (ne + SW - 1) / SW;
-  hipLaunchKernelGGL(k_cond_small<T>, dim3((unsigned)(gs < SMALL_GRID ? gs : SMALL_GRID)), dim3(64 * SW), 0, s, ne,
+  const int32_t gs = (int32_t)(((int64_t)ne + SW * SMALL_PER_WAVE - 1) / (SW * SMALL_PER_WAVE));
+  hipLaunchKernelGGL(k_cond_small<T>, dim3((unsigned)gs), dim3(64 * SW), 0, s, ne,
                      md, p, b.cnt, b.off, b.list, b.mid, b.big, b.nbig, cm);
   hipLaunchKernelGGL(k_cond_mid<T>, dim3((unsigned)(ne < 65536 ? ne : 65536)), dim3(256), 0, s, md, p, b.cnt, b.off,
                      b.list, b.mid, b.nbig, cm);
