@@ -212,11 +212,19 @@ __global__ __launch_bounds__(TT) void k_cond_fill(int64_t np, int32_t ne, const 
   const int64_t base = (int64_t)blockIdx.x * TT * TP;
   int32_t pe_[TP], slot[TP], rank[TP];
   // every element number loaded before the first atomic, so that the loads
-  // overlap instead of waiting one by one
+  // overlap instead of waiting one by one, and the elements' offsets right
+  // after them, in flight during the ranking
 #pragma unroll
   for (int j = 0; j < TP; ++j) {
     const int64_t i = base + (int64_t)j * TT + t;
     pe_[j] = i < np ? pe[i] : -1;
+  }
+  int32_t o0[TP], o1[TP];
+#pragma unroll
+  for (int j = 0; j < TP; ++j) {
+    const int32_t ec = pe_[j] >= 0 && pe_[j] < ne ? pe_[j] : 0;  // unconditional loads, in bounds
+    o0[j] = off[ec];
+    o1[j] = off[ec + 1];
   }
 #pragma unroll
   for (int j = 0; j < TP; ++j) {
@@ -240,13 +248,6 @@ __global__ __launch_bounds__(TT) void k_cond_fill(int64_t np, int32_t ne, const 
   for (int s = t; s < HS; s += TT) {
     const int32_t k = hk[s];
     if (k >= 0) hb[s] = atomicAdd(&cursor[k], hc[s]);
-  }
-  // the element offsets, all loaded before the first store
-  int32_t o0[TP], o1[TP];
-#pragma unroll
-  for (int j = 0; j < TP; ++j) {
-    o0[j] = pe_[j] >= 0 ? off[pe_[j]] : 0;
-    o1[j] = pe_[j] >= 0 ? off[pe_[j] + 1] : 0;
   }
   __syncthreads();
   // every destination before the first store (a store between the loads and
